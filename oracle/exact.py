@@ -1,0 +1,107 @@
+"""Exact discrete space-time solutions (oracle).
+
+The space-time system of Sec. 3 (eq. (par1)-(par2)), written with the test
+index first, is
+
+    (Dt kron Mx + Mt kron Kx) vec(U) = vec(F1 F2^T),
+
+and by the vec identity of Sec. 4 ((D kron A) vec X = vec(A X D^T), columns
+stacked) it is the generalized Sylvester equation of eq. (Sylv_Heat):
+
+    Kx U Mt^T + Mx U Dt^T = F1 F2^T,   U in R^{Nh x Nt},  U[:, l-1] = u(t^l).
+
+The system is block lower bidiagonal in time with SPD diagonal blocks
+Mt[l,l] Kx + Dt[l,l] Mx, so its solution is unique.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def vec(X: np.ndarray) -> np.ndarray:
+    """Stack the columns of X (Sec. 4)."""
+    return np.asarray(X).reshape(-1, order="F")
+
+
+def unvec(x: np.ndarray, nrows: int) -> np.ndarray:
+    return np.asarray(x).reshape(nrows, -1, order="F")
+
+
+def kron_system(Kx, Mx, Dt, Mt) -> sp.csc_matrix:
+    """The assembled space-time matrix Dt kron Mx + Mt kron Kx (eq. (par1))."""
+    Dt = sp.csr_matrix(Dt)
+    Mt = sp.csr_matrix(Mt)
+    return (sp.kron(Dt, Mx) + sp.kron(Mt, Kx)).tocsc()
+
+
+def kron_solve(Kx, Mx, Dt, Mt, F1, F2) -> np.ndarray:
+    """Sparse-direct solve of the assembled Kronecker system (tiny sizes only)."""
+    B = kron_system(Kx, Mx, Dt, Mt)
+    f = vec(np.asarray(F1) @ np.asarray(F2).T)
+    return unvec(spla.spsolve(B, f), Kx.shape[0])
+
+
+def crank_nicolson(Kx, Mx, Dt, Mt, F1, F2, steps: int | None = None) -> np.ndarray:
+    """Time stepping of the space-time system, one interval at a time.
+
+    Row l of the block-bidiagonal system reads
+        (Mt[l,l] Kx + Dt[l,l] Mx) u^l = F[:, l] - (Mt[l,l-1] Kx + Dt[l,l-1] Mx) u^{l-1},
+    u^0 = 0.  With the uniform hat/indicator pair this is the Crank-Nicolson
+    scheme with the exact-integral load (Sec. 3, final remark of the heat
+    paragraph).  A factorisation is reused while the step matrix is unchanged.
+    ``steps`` limits the march to the first ``steps`` intervals.
+    """
+    F1 = np.asarray(F1)
+    F2 = np.asarray(F2)
+    nt = F2.shape[0] if steps is None else min(steps, F2.shape[0])
+    nh = Kx.shape[0]
+    U = np.zeros((nh, nt))
+    prev = np.zeros(nh)
+    key, lu = None, None
+    for l in range(nt):
+        d, m = Dt[l, l], Mt[l, l]
+        if key != (d, m):
+            lu = spla.splu((m * Kx + d * Mx).tocsc())
+            key = (d, m)
+        rhs = F1 @ F2[l]
+        if l > 0:
+            rhs = rhs - (Mt[l, l - 1] * (Kx @ prev) + Dt[l, l - 1] * (Mx @ prev))
+        prev = lu.solve(rhs)
+        U[:, l] = prev
+    return U
+
+
+def modal_solve_1d(n: int, mu: float, Dt, Mt, F1, F2) -> np.ndarray:
+    """Exact solve for uniform 1-D P1 by sine-mode diagonalisation.
+
+    Kx and Mx are symmetric tridiagonal Toeplitz, so both are diagonalised by
+    q_m = sin(m pi x_j): Kx q_m = kappa_m q_m, Mx q_m = nu_m q_m with
+    kappa_m = (2 mu / h)(1 - cos m pi h), nu_m = (h/3)(2 + cos m pi h).
+    Writing U = sum_m q_m w_m^T and projecting on q_m gives the Nt x Nt
+    lower-bidiagonal systems (nu_m Dt + kappa_m Mt) w_m = F2 (F1^T q_m)/|q_m|^2.
+    """
+    h = 1.0 / (n + 1)
+    j = np.arange(1, n + 1)
+    U = np.zeros((n, F2.shape[0]))
+    for m in range(1, n + 1):
+        q = np.sin(m * np.pi * j * h)
+        kappa = 2.0 * mu / h * (1.0 - np.cos(m * np.pi * h))
+        nu = h / 3.0 * (2.0 + np.cos(m * np.pi * h))
+        rhs = np.asarray(F2) @ (np.asarray(F1).T @ q) / (q @ q)
+        w = np.linalg.solve(nu * np.asarray(Dt) + kappa * np.asarray(Mt), rhs)
+        U += np.outer(q, w)
+    return U
+
+
+def sylvester_residual(Kx, Mx, Dt, Mt, F1, F2, U) -> float:
+    """Relative Frobenius residual of eq. (Sylv_Heat) for a full U."""
+    F = np.asarray(F1) @ np.asarray(F2).T
+    R = F - (Kx @ (U @ np.asarray(Mt).T) + Mx @ (U @ np.asarray(Dt).T))
+    return float(np.linalg.norm(R) / np.linalg.norm(F))
+
+
+def relative_error(A: np.ndarray, B: np.ndarray) -> float:
+    """||A - B||_F / ||B||_F on nodal coefficients."""
+    return float(np.linalg.norm(A - B) / np.linalg.norm(B))
