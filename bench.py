@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the space-time heat solver on one MI355X.
+
+One step = one complete FP64 extended-Krylov Galerkin solve (start block,
+expansions with inner CG, block Gram-Schmidt, reduced eigensolve and time
+sweep, projected residual, exact-residual confirmation) of the 2-D heat
+problem on the unit square: P1 on a 511 x 511 interior grid (Nh = 261121),
+Nt = 1024 steps on (0, 1], rank-2 right-hand side (Gaussian-bump fields in
+space, trigonometric series in time), relative Sylvester residual 1e-10.
+Inputs are resident in device memory before the timed region; every timed
+step re-solves from scratch on the same problem object.
+
+Prints one JSON line.  ``value`` is space-time degrees of freedom (Nh * Nt)
+per second of wall time.  ``roofline`` reports the dominant kernel (the fused
+CG iteration) against the 8 TB/s HBM peak, from HIP events around its
+launches inside the timed steps.  ``cpu_baseline`` times the CPU oracle's
+Crank-Nicolson stepper on the first time steps of the same problem; those
+columns also gate the result (relative error <= 1e-8).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "space-time dof/s at rel. error 1e-8; % HBM roofline; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_iter_2d_n511_traffic.json")
+CG_SOURCE = os.path.join(ROOT, "paper_1912_10082_amd", "csrc", "stencil_cg.hip")
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _kernel_hash() -> str:
+    with open(CG_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def _traffic(bytes_per_launch_alg):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != _kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, U_gpu_cols, sample_steps):
+    """Oracle Crank-Nicolson on the first `sample_steps` intervals (1 core)."""
+    import numpy as np
+
+    from oracle import exact, fem
+    import workloads as wl
+
+    K, M = fem.spatial_operators(w.dim, w.n[0], w.mu)
+    Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+    t0 = time.perf_counter()
+    U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2, steps=sample_steps)
+    secs = time.perf_counter() - t0
+    err = float(np.linalg.norm(U_gpu_cols - U) / np.linalg.norm(U))
+    return secs, err
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=511, help="interior nodes per direction")
+    ap.add_argument("--nt", type=int, default=1024)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--sample-steps", type=int, default=48,
+                    help="Crank-Nicolson steps of the CPU baseline / error gate")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the solver has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1912_10082_amd as sts
+    import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = wl.heat_2d_bumps(n=args.n, nt=args.nt, p=2, seed=2)
+    t = wl.time_grid(w.nt, w.T)
+    dd, ds, md, ms = sts.time_matrices(t)
+    F1 = torch.from_numpy(np.asarray(w.F1)).cuda()
+    F2 = torch.from_numpy(np.asarray(w.F2)).cuda()
+    torch.cuda.synchronize()
+    prob = sts.Problem(2, w.n[0], w.mu, (dd, ds), (md, ms), F1, F2)
+    opts = dict(tol=args.tol, restart=1, max_outer=150)
+    for i in range(args.warmup):
+        info = prob.solve(**opts)
+        _log(f"warmup {i}: {info['status']} outer={info['outer_its']} k={info['k']} "
+             f"{info['seconds']:.3f}s")
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        info = prob.solve(profile=1, **opts)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        infos.append(info)
+        _log(f"step {i}: {info['status']} outer={info['outer_its']} k={info['k']} "
+             f"res_true={info['res_true']:.2e} {lat[-1]:.3f}s")
+    total = sum(lat)
+    dof = w.nh * w.nt
+    value = dof * args.steps / total
+    last = infos[-1]
+    cg_secs = sum(i["cg_kernel_seconds"] for i in infos)
+    cg_launches = sum(i["cg_launches"] for i in infos)
+    cg_bytes = 48.0 * w.nh * sum(i["cg_col_iters"] for i in infos)
+    achieved = cg_bytes / cg_secs / 1e9 if cg_secs > 0 else None
+    bytes_per_launch = cg_bytes / max(cg_launches, 1)
+    roofline = {
+        "kernel": "cg_iter_kernel<2> (fused single-reduction CG iteration, 2-D)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": _traffic(bytes_per_launch),
+        "alg_bytes_per_launch": bytes_per_launch,
+        "avg_launch_us": 1e6 * cg_secs / max(cg_launches, 1),
+        "launches_per_step": cg_launches / args.steps,
+        "cg_time_share": cg_secs / total,
+    }
+    gate = last["status"] == "STS_OK" and last["res_true"] <= args.tol
+    V, Y = prob.factors(device=True)
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        S = min(args.sample_steps, w.nt)
+        U_cols = (V @ Y[:, :S]).cpu().numpy()
+        cores = 1
+        secs, err = cpu_baseline(w, U_cols, S)
+        gate = gate and err <= 1e-8
+        cpu = {"value": w.nh * S / secs, "unit": "dof/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {S} of {w.nt} Crank-Nicolson steps of the same {w.n[0]}^2 x "
+                         f"{w.nt} problem (SuperLU factorisation once + {S} solves, "
+                         f"{secs:.1f} s, single-threaded SciPy)",
+               "seconds": secs}
+    lat_ms = sorted(1e3 * x for x in lat)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "dof/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"heat2d_p1_courant_{w.n[0]}x{w.n[0]}_nt{w.nt}_rank2_tol{args.tol:g}",
+                   "nh": w.nh, "nt": w.nt, "p": 2, "tol": args.tol, "seed": 2},
+        "latency_ms": {"p50": lat_ms[len(lat_ms) // 2],
+                       "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
+        "gate_passed": bool(gate),
+        "rel_error_vs_oracle_sample": err,
+        "res_true": last["res_true"],
+        "outer_its": last["outer_its"],
+        "k": last["k"],
+        "inner_its_K": last["inner_its_K"],
+        "inner_its_M": last["inner_its_M"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    prob.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,249 @@
+/*
+ * sts.h -- space-time Sylvester solver for the heat equation on one MI355X.
+ *
+ * Solves the space-time Petrov-Galerkin system of the heat equation
+ * (hat functions in time for trial, indicators in time for test, P1/Q1
+ * elements in space; Sec. 3 of Henning, Palitta, Simoncini, Urban,
+ * "Matrix oriented reduction of space-time Petrov-Galerkin variational
+ * problems", eq. (par1)-(par2)) in its matrix form, the generalized
+ * Sylvester equation of Sec. 4, eq. (Sylv_Heat):
+ *
+ *     Kx U Mt^T + Mx U Dt^T = F1 F2^T,      U in R^{Nh x Nt},
+ *
+ * where Kx = mu * stiffness, Mx = mass (Nh x Nh, SPD), Dt[l,k] =
+ * (d/dt sigma^k, tau^l), Mt[l,k] = (sigma^k, tau^l) (Nt x Nt, lower
+ * bidiagonal, indexed [test l, trial k]) and F1 (Nh x P), F2 (Nt x P) are the
+ * factors of the low-rank load (Sec. 3, eq. (EIM)).  Column l-1 of U holds the
+ * nodal values at time t^l; u(t^0) = 0 is not stored.
+ *
+ * The solver is the Galerkin projection of Sec. 4: the spatial space is grown
+ * as an extended Krylov space (rational Krylov with the poles 0 and infinity)
+ * in the operator Mx^{-1} Kx started from Mx^{-1} F1; the basis V is
+ * orthonormal in the Mx inner product; the reduced equation
+ * (V^T Kx V) Y Mt^T + (V^T Mx V) Y Dt^T = (V^T F1) F2^T is solved by
+ * diagonalising the reduced spatial pencil and sweeping the bidiagonal time
+ * recurrence per eigencomponent; the residual is monitored in projected form
+ * and confirmed by the exact residual before success is reported.  The result
+ * is returned as the factors V (Nh x k) and Y (k x Nt), U ~= V Y.
+ *
+ * Conventions (all entry points)
+ *   - Column-major storage, leading dimensions in elements, FP64 throughout.
+ *   - Grid nodes are the interior nodes of a uniform grid on the unit
+ *     interval / square / cube, numbered lexicographically with x fastest.
+ *   - Pointers marked "device" must be device memory of the current HIP
+ *     device; "host" means host memory; "mem" arguments select between them
+ *     (STS_MEM_HOST / STS_MEM_DEVICE).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is ordered on that stream.  Calls marked
+ *     "synchronous" wait for their own work before returning.
+ *   - Every function returns an sts_status; none throws or aborts.  On error
+ *     sts_last_error() returns a description (thread-local, valid until the
+ *     next call on the same thread).
+ *   - The library allocates its own device memory with hipMalloc and frees it
+ *     in sts_destroy (or before returning, for the step-level calls).  It
+ *     never frees caller memory.
+ */
+#ifndef STS_H
+#define STS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STS_OK = 0,
+  STS_E_INVALID = 1,       /* bad argument: sizes, strides, NULL, non-finite data */
+  STS_E_NOMEM = 2,         /* device allocation failed or exceeds the memory budget */
+  STS_E_DEVICE = 3,        /* a HIP runtime call failed */
+  STS_E_NOT_CONVERGED = 4, /* max_outer reached; factors of the last iterate stay fetchable */
+  STS_E_NUMERIC = 5,       /* breakdown: CG curvature <= 0, NaN/Inf, basis lost orthogonality */
+  STS_E_STATE = 6          /* call out of order (e.g. get_factors before solve) */
+} sts_status;
+
+typedef enum { STS_MEM_HOST = 0, STS_MEM_DEVICE = 1 } sts_mem;
+
+/* Spatial discretisation (Sec. 3: conforming X_h; P1 elements).
+ *   STS_FE_P1_1D       (0,1), P1 hats: Kx = (mu/h) tridiag(-1,2,-1),
+ *                      Mx = (h/6) tridiag(1,4,1).
+ *   STS_FE_P1_2D       unit square, P1 on the uniform Courant triangulation
+ *                      (squares cut along the SW-NE diagonal): Kx = mu *
+ *                      5-point (4; -1), Mx = (h^2/12)(6; 1 at E,W,N,S,NE,SW).
+ *   STS_FE_Q1_3D_7PT   unit cube, trilinear elements: consistent Q1 mass
+ *                      (27-point, the tensor product of 1-D P1 masses) and the
+ *                      Q1 stiffness with lumped transverse mass (7-point,
+ *                      mu h (6; -1 on faces)).
+ * n[d] = interior nodes in direction d (n[d] = 1 for unused directions),
+ * h = 1/(n[d]+1) (the grid must be isotropic: equal n[d] for used d). */
+typedef enum { STS_FE_P1_1D = 1, STS_FE_P1_2D = 2, STS_FE_Q1_3D_7PT = 3 } sts_fe_kind;
+
+typedef struct {
+  int32_t kind;   /* sts_fe_kind */
+  int32_t pad_;
+  int64_t n[3];   /* interior nodes per direction */
+  double mu;      /* diffusion coefficient (> 0) */
+} sts_space;
+
+/* Which spatial operator a step-level call applies. */
+typedef enum { STS_OP_K = 0, STS_OP_M = 1 } sts_op;
+
+/* Lower-bidiagonal Nt x Nt time matrix: diag[l] = A[l,l] (length nt),
+ * sub[l] = A[l+1,l] (length nt-1).  Host pointers. */
+typedef struct {
+  const double* diag;
+  const double* sub;
+} sts_bidiag;
+
+typedef struct {
+  double tol;               /* relative Frobenius residual target (Sec. 5 uses 1e-8); default 1e-8 */
+  int32_t max_outer;        /* max extended-Krylov blocks; default 200 */
+  int32_t check_every;      /* 0 = adaptive residual checks, n > 0 = every n blocks; default 0 */
+  double inner_rtol;        /* CG relative residual target; default 1e-12 */
+  int32_t inner_maxit;      /* CG iteration cap per solve; default 200000 */
+  int32_t verify_true;      /* 1 = confirm convergence with the exact residual; default 1 */
+  double defl_tol;          /* drop a new column whose Mx-norm falls below this fraction; default 1e-10 */
+  int64_t mem_budget;       /* bytes of device memory the problem may hold; 0 = unlimited */
+  int32_t restart;          /* 1 = discard the current basis and solve from scratch; default 0 */
+  int32_t profile;          /* 1 = time the CG iteration kernels with HIP events; default 0 */
+} sts_opts;
+
+typedef struct {
+  int32_t outer_its;        /* blocks added after the start block */
+  int32_t checks;           /* reduced solves performed */
+  int64_t k;                /* basis size of the returned factors (mu_mem of Sec. 5, Table 1) */
+  int64_t rank;             /* numerical rank of V Y (singular values > 1e-12 sigma_1) */
+  int64_t inner_its_K;      /* CG iterations on Kx, summed over columns and solves */
+  int64_t inner_its_M;      /* CG iterations on Mx, summed over columns and solves */
+  double res_cheap;         /* last projected residual estimate (relative Frobenius) */
+  double res_true;          /* exact relative residual of the returned factors, or -1 */
+  double orth_err;          /* max |V^T Mx V - I| over the reduced matrix */
+  double seconds;           /* wall time of sts_solve */
+  double alg_bytes;         /* algorithmic HBM bytes moved by the kernels (model) */
+  int32_t breakdown;        /* 1 = the space became invariant (exact solution) */
+  int32_t pad_;
+  /* filled when opts.profile = 1 (CG iteration kernels only, this call) */
+  double cg_kernel_seconds; /* summed HIP-event time of the launches */
+  int64_t cg_launches;      /* iteration-kernel launches */
+  int64_t cg_col_iters;     /* column-iterations performed (each streams 48 bytes per node) */
+} sts_info;
+
+typedef struct sts_problem sts_problem;
+
+/* Fill *o with the defaults listed in sts_opts. */
+void sts_default_opts(sts_opts* o);
+
+/* Time matrices of the hat/indicator pair (Sec. 3, eq. (par1)) on the nodes
+ * t[0..nt] (host, strictly increasing): Dt diag = 1, sub = -1; Mt diag =
+ * sub = (t[l+1]-t[l])/2 on row l.  Outputs are host arrays (nt and nt-1). */
+sts_status sts_time_matrices(int64_t nt, const double* t, double* dt_diag, double* dt_sub,
+                             double* mt_diag, double* mt_sub);
+
+/* Create a problem.  Copies F1 (Nh x p, ld ldf1) and F2 (nt x p, ld ldf2) from
+ * `mem` into library memory; the caller keeps its arrays.  Dt, Mt are host
+ * bidiagonals.  Errors: STS_E_INVALID for nt < 2, p < 1 or p > 4, ld < rows,
+ * non-positive diagonals of Dt or Mt, non-finite data or an unsupported space;
+ * STS_E_NOMEM / STS_E_DEVICE on allocation or copy failure.  Synchronous. */
+sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bidiag* Mt,
+                      int64_t nt, int32_t p, const double* F1, int64_t ldf1,
+                      const double* F2, int64_t ldf2, int32_t mem, void* stream,
+                      sts_problem** out);
+
+/* Solve to opts->tol (NULL = defaults).  Fills *info if non-NULL.  May be
+ * called again on the same problem with a tighter tolerance: the space is
+ * extended from where the previous call stopped.  Returns STS_OK,
+ * STS_E_NOT_CONVERGED (factors of the last iterate are kept), STS_E_NUMERIC
+ * or STS_E_NOMEM.  Synchronous. */
+sts_status sts_solve(sts_problem* prob, const sts_opts* opts, sts_info* info);
+
+/* Number of columns of V (rows of Y) of the current solution. */
+sts_status sts_rank(const sts_problem* prob, int64_t* k);
+
+/* Copy the factors into caller buffers: V (Nh x k, ld ldv >= Nh) and
+ * Y (k x nt, ld ldy >= k), either may be NULL.  STS_E_STATE before a
+ * successful or not-converged solve.  Synchronous. */
+sts_status sts_get_factors(const sts_problem* prob, double* V, int64_t ldv, double* Y,
+                           int64_t ldy, int32_t mem, void* stream);
+
+/* Exact relative residual ||F1 F2^T - Kx V Y Mt^T - Mx V Y Dt^T||_F / ||F1 F2^T||_F
+ * of the current factors (Sec. 4, residual R_m).  Synchronous. */
+sts_status sts_true_residual(sts_problem* prob, double* res);
+
+/* Numerical rank of the current solution V Y (Sec. 5 reports rank(U)): the
+ * number of singular values of V Y in the Mx norm (those of Y, V being
+ * Mx-orthonormal) above 1e-8 times the largest.  Synchronous. */
+sts_status sts_numerical_rank(sts_problem* prob, int64_t* rank);
+
+/* Free everything the problem holds.  NULL-safe. */
+void sts_destroy(sts_problem* prob);
+
+/* Description of the last error on this thread ("" if none). */
+const char* sts_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Step-level entry points (each runs one step of the solver's path on
+ * caller-provided device buffers; used for parity checks).  All pointers are
+ * device pointers; scratch is allocated and freed inside the call; all are
+ * synchronous.
+ * ------------------------------------------------------------------------ */
+
+/* Y[:, c] = A X[:, c] for c < ncols, A = Kx or Mx of `space` (matrix-free
+ * stencil SpMM; Sec. 3 spatial matrices).  X: Nh x ncols (ldx), Y: Nh x ncols
+ * (ldy); X and Y must not overlap.  ncols <= 16. */
+sts_status sts_apply_op(const sts_space* space, int32_t op, const double* X, int64_t ldx,
+                        double* Y, int64_t ldy, int32_t ncols, void* stream);
+
+/* Conjugate gradients on A X[:, c] = B[:, c] with A = Kx or Mx per column
+ * (ops[c]), X0 = 0, stopping when ||r|| <= rtol ||b|| or after maxit
+ * iterations.  iters (host, length ncols, may be NULL) receives the
+ * iteration count of each column.  ncols <= 8.  Returns STS_E_NUMERIC on a
+ * non-positive curvature and STS_E_NOT_CONVERGED if a column hits maxit. */
+sts_status sts_cg(const sts_space* space, const int32_t* ops, const double* B, int64_t ldb,
+                  double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                  int32_t* iters, void* stream);
+
+/* Block Gram-Schmidt in the Mx inner product: orthogonalise the ncols columns
+ * of W (in place, Nh x ncols, ldw) against V (Nh x k, Mx-orthonormal, with
+ * MV = Mx V given) twice (CGS2), then orthonormalise them by two Cholesky-QR
+ * passes, dropping columns whose Mx-norm fell below defl_tol of their norm on
+ * entry.  The kept, orthonormal columns are packed to the front of W, and
+ * MW (Nh x ncols, ldw) receives Mx times them.  *kept (host) is the number of
+ * kept columns and keep_idx (host, length ncols, may be NULL) their original
+ * indices.  ncols <= 8. */
+sts_status sts_m_orthonormalize(const sts_space* space, const double* V, const double* MV,
+                                int64_t ldv, int64_t k, double* W, double* MW, int64_t ldw,
+                                int32_t ncols, double defl_tol, int32_t* kept,
+                                int32_t* keep_idx, void* stream);
+
+/* The contraction of block Gram-Schmidt, C (m x n, ldc) = A^T B, for a tall
+ * A (rows x m, lda) and a thin B (rows x n, ldb), n <= 16; FP64 matrix cores. */
+sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double* C, int64_t ldc, void* stream);
+
+/* The basis update of block Gram-Schmidt, W (rows x n, ldw) -= A (rows x m,
+ * lda) C (m x n, ldc), n <= 16; FP64 matrix cores. */
+sts_status sts_basis_update(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
+                            const double* C, int64_t ldc, double* W, int64_t ldw, void* stream);
+
+/* Eigendecomposition of a symmetric k x k matrix A (lda): A Q = Q diag(lam),
+ * Q^T Q = I, by Householder tridiagonalisation and implicit QL.  lam: k,
+ * Q: k x k (ldq).  For the reduced pencil (Km, Mm) of an Mx-orthonormal basis
+ * Mm = I up to rounding, so this diagonalises the pencil (Sec. 4, reduced
+ * equation). */
+sts_status sts_sym_eig(int64_t k, const double* A, int64_t lda, double* lam, double* Q,
+                       int64_t ldq, void* stream);
+
+/* Reduced time sweep: Y = Q Z where each row z_i solves the lower-bidiagonal
+ * recurrence (Dt + lam_i Mt) z_i = (Q^T beta F2^T)[i, :] (Sec. 4 reduced
+ * equation after diagonalising the spatial pencil).  lam: k, Q: k x k (ldq),
+ * beta: k x p (ldb), F2: nt x p (ldf), Dt/Mt host bidiagonals, Y: k x nt (ldy). */
+sts_status sts_time_sweep(int64_t k, int64_t nt, int32_t p, const double* lam, const double* Q,
+                          int64_t ldq, const double* beta, int64_t ldb, const double* F2,
+                          int64_t ldf, const sts_bidiag* Dt, const sts_bidiag* Mt, double* Y,
+                          int64_t ldy, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STS_H */

@@ -1,0 +1,13 @@
+"""Space-time Petrov-Galerkin heat solver for MI355X (gfx950).
+
+Solves Kx U Mt^T + Mx U Dt^T = F1 F2^T -- the matrix form of the space-time
+Petrov-Galerkin discretisation of the heat equation -- by Galerkin projection
+onto an extended Krylov space, returning low-rank factors U ~= V Y.  All
+computation runs in the HIP library ``libsts.so`` behind the C ABI of
+``include/sts.h``; ``binding`` is its ctypes marshalling layer.
+"""
+from .binding import (  # noqa: F401
+    EXPORTED, STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT, STS_OP_K, STS_OP_M, Problem,
+    STSError, apply_op, basis_update, cg, default_opts, gram, load, m_orthonormalize, make_space,
+    sym_eig, time_matrices, time_sweep,
+)

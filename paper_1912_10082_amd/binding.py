@@ -1,0 +1,388 @@
+"""ctypes binding of the C ABI in include/sts.h (argument marshalling only).
+
+Every computation runs in ``libsts.so``; this module only converts arguments:
+NumPy arrays are passed as host memory, PyTorch CUDA tensors as device memory
+(column-major, float64), and PyTorch supplies device allocations and the
+current stream.  If the library cannot be loaded the calls raise; there is no
+other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsts.so")
+
+STS_OK, STS_E_INVALID, STS_E_NOMEM, STS_E_DEVICE, STS_E_NOT_CONVERGED, STS_E_NUMERIC, STS_E_STATE = range(7)
+STATUS_NAMES = {0: "STS_OK", 1: "STS_E_INVALID", 2: "STS_E_NOMEM", 3: "STS_E_DEVICE",
+                4: "STS_E_NOT_CONVERGED", 5: "STS_E_NUMERIC", 6: "STS_E_STATE"}
+STS_MEM_HOST, STS_MEM_DEVICE = 0, 1
+STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT = 1, 2, 3
+STS_OP_K, STS_OP_M = 0, 1
+
+
+class STSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Space(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("n", C.c_int64 * 3), ("mu", C.c_double)]
+
+
+class Bidiag(C.Structure):
+    _fields_ = [("diag", C.POINTER(C.c_double)), ("sub", C.POINTER(C.c_double))]
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
+                ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32), ("verify_true", C.c_int32),
+                ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
+                ("profile", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("outer_its", C.c_int32), ("checks", C.c_int32), ("k", C.c_int64),
+                ("rank", C.c_int64), ("inner_its_K", C.c_int64), ("inner_its_M", C.c_int64),
+                ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
+                ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
+                ("pad_", C.c_int32), ("cg_kernel_seconds", C.c_double), ("cg_launches", C.c_int64),
+                ("cg_col_iters", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I64, _I32, _F64 = C.c_int64, C.c_int32, C.c_double
+
+_SIGS = {
+    "sts_default_opts": (None, [C.POINTER(Opts)]),
+    "sts_last_error": (C.c_char_p, []),
+    "sts_time_matrices": (C.c_int, [_I64, _D, _D, _D, _D, _D]),
+    "sts_create": (C.c_int, [C.POINTER(Space), C.POINTER(Bidiag), C.POINTER(Bidiag), _I64, _I32,
+                             _P, _I64, _P, _I64, _I32, _P, C.POINTER(_P)]),
+    "sts_solve": (C.c_int, [_P, C.POINTER(Opts), C.POINTER(Info)]),
+    "sts_rank": (C.c_int, [_P, C.POINTER(_I64)]),
+    "sts_get_factors": (C.c_int, [_P, _P, _I64, _P, _I64, _I32, _P]),
+    "sts_true_residual": (C.c_int, [_P, _D]),
+    "sts_numerical_rank": (C.c_int, [_P, C.POINTER(_I64)]),
+    "sts_destroy": (None, [_P]),
+    "sts_apply_op": (C.c_int, [C.POINTER(Space), _I32, _P, _I64, _P, _I64, _I32, _P]),
+    "sts_cg": (C.c_int, [C.POINTER(Space), C.POINTER(_I32), _P, _I64, _P, _I64, _I32, _F64, _I32,
+                         C.POINTER(_I32), _P]),
+    "sts_m_orthonormalize": (C.c_int, [C.POINTER(Space), _P, _P, _I64, _I64, _P, _P, _I64, _I32,
+                                       _F64, C.POINTER(_I32), C.POINTER(_I32), _P]),
+    "sts_gram": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "sts_basis_update": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "sts_sym_eig": (C.c_int, [_I64, _P, _I64, _P, _P, _I64, _P]),
+    "sts_time_sweep": (C.c_int, [_I64, _I64, _I32, _P, _P, _I64, _P, _I64, _P, _I64,
+                                 C.POINTER(Bidiag), C.POINTER(Bidiag), _P, _I64, _P]),
+}
+
+EXPORTED = tuple(_SIGS)
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libsts.so (building it first if it is absent) and declare signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            from . import build as _build
+            _build.build()
+        lib = C.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _check(code: int):
+    if code != STS_OK:
+        raise STSError(code, load().sts_last_error().decode())
+
+
+# ----------------------------------------------------------------------------
+# array marshalling
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _host_colmajor(a) -> np.ndarray:
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    return np.asfortranarray(a)
+
+
+def dev_colmajor(t):
+    """A float64 CUDA tensor viewed as a column-major matrix -> (tensor, ptr, ld).
+
+    Returns a (possibly copied) tensor whose memory is column-major, so that
+    t[i, j] lives at ptr + (i + j * ld) * 8.
+    """
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 CUDA tensor")
+    if t.dim() == 1:
+        t = t[:, None]
+    if t.stride(0) != 1 or (t.shape[1] > 1 and t.stride(1) < t.shape[0]):
+        t = t.t().contiguous().t()
+    ld = t.stride(1) if t.shape[1] > 1 else max(t.shape[0], 1)
+    return t, C.c_void_p(t.data_ptr()), int(ld)
+
+
+def dev_empty(rows: int, cols: int, device="cuda"):
+    """Uninitialised column-major float64 CUDA matrix (rows x cols)."""
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=torch.float64, device=device).t()
+
+
+def dev_zeros(rows: int, cols: int, device="cuda"):
+    torch = _torch()
+    return torch.zeros((cols, rows), dtype=torch.float64, device=device).t()
+
+
+def make_space(dim: int, n: int, mu: float = 1.0) -> Space:
+    s = Space()
+    s.kind = {1: STS_FE_P1_1D, 2: STS_FE_P1_2D, 3: STS_FE_Q1_3D_7PT}[dim]
+    for d in range(3):
+        s.n[d] = n if d < dim else 1
+    s.mu = mu
+    return s
+
+
+def _bidiag(diag: np.ndarray, sub: np.ndarray):
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    sub = np.ascontiguousarray(sub, dtype=np.float64)
+    b = Bidiag(diag.ctypes.data_as(_D), sub.ctypes.data_as(_D))
+    return b, (diag, sub)
+
+
+# ----------------------------------------------------------------------------
+# API
+# ----------------------------------------------------------------------------
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().sts_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def time_matrices(t):
+    """(Dt diag, Dt sub, Mt diag, Mt sub) of the hat/indicator pair on nodes t."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    nt = len(t) - 1
+    out = [np.empty(nt), np.empty(max(nt - 1, 1)), np.empty(nt), np.empty(max(nt - 1, 1))]
+    _check(load().sts_time_matrices(nt, t.ctypes.data_as(_D), *[a.ctypes.data_as(_D) for a in out]))
+    return out[0], out[1][: nt - 1], out[2], out[3][: nt - 1]
+
+
+class Problem:
+    """A space-time heat problem held by the library (sts_create / sts_destroy).
+
+    F1 (Nh x P) and F2 (Nt x P) may be NumPy arrays (copied from host memory)
+    or float64 CUDA tensors (copied on the device).  ``dt``/``mt`` are the
+    (diag, sub) pairs of the lower-bidiagonal time matrices.
+    """
+
+    def __init__(self, dim: int, n: int, mu: float, dt, mt, F1, F2, stream=None):
+        lib = load()
+        self._lib = lib
+        self.space = make_space(dim, n, mu)
+        self._Dt, self._keep_dt = _bidiag(*dt)
+        self._Mt, self._keep_mt = _bidiag(*mt)
+        self.nt = len(self._keep_dt[0])
+        self.device_inputs = _is_torch(F1)
+        if self.device_inputs:
+            self._stream = _stream_handle(stream)
+            f1, p1, ld1 = dev_colmajor(F1)
+            f2, p2, ld2 = dev_colmajor(F2)
+            self._keep_f = (f1, f2)
+            mem = STS_MEM_DEVICE
+        else:
+            self._stream = C.c_void_p(0) if stream is None else _stream_handle(stream)
+            f1, f2 = _host_colmajor(F1), _host_colmajor(F2)
+            p1, ld1 = C.c_void_p(f1.ctypes.data), f1.shape[0]
+            p2, ld2 = C.c_void_p(f2.ctypes.data), f2.shape[0]
+            self._keep_f = (f1, f2)
+            mem = STS_MEM_HOST
+        self.p = int(f1.shape[1])
+        self.nh = int(f1.shape[0])
+        h = C.c_void_p()
+        _check(lib.sts_create(C.byref(self.space), C.byref(self._Dt), C.byref(self._Mt), self.nt,
+                              self.p, p1, ld1, p2, ld2, mem, self._stream, C.byref(h)))
+        self._h = h
+
+    def solve(self, **opts) -> dict:
+        o = default_opts(**opts)
+        info = Info()
+        code = self._lib.sts_solve(self._h, C.byref(o), C.byref(info))
+        d = info.as_dict()
+        d["status"] = STATUS_NAMES.get(code, code)
+        if code not in (STS_OK, STS_E_NOT_CONVERGED):
+            _check(code)
+        d["error"] = self._lib.sts_last_error().decode() if code != STS_OK else ""
+        return d
+
+    def rank(self) -> int:
+        k = C.c_int64()
+        _check(self._lib.sts_rank(self._h, C.byref(k)))
+        return int(k.value)
+
+    def factors(self, device: bool = False):
+        """(V, Y): NumPy arrays, or CUDA tensors if device=True."""
+        k = self.rank()
+        if device:
+            V, Y = dev_empty(self.nh, k), dev_empty(k, self.nt)
+            _check(self._lib.sts_get_factors(self._h, C.c_void_p(V.data_ptr()), max(self.nh, 1),
+                                             C.c_void_p(Y.data_ptr()), max(k, 1), STS_MEM_DEVICE,
+                                             self._stream))
+            return V, Y
+        V = np.zeros((self.nh, k), order="F")
+        Y = np.zeros((k, self.nt), order="F")
+        _check(self._lib.sts_get_factors(self._h, C.c_void_p(V.ctypes.data), max(self.nh, 1),
+                                         C.c_void_p(Y.ctypes.data), max(k, 1), STS_MEM_HOST,
+                                         self._stream))
+        return V, Y
+
+    def true_residual(self) -> float:
+        r = C.c_double()
+        _check(self._lib.sts_true_residual(self._h, C.byref(r)))
+        return r.value
+
+    def numerical_rank(self) -> int:
+        r = C.c_int64()
+        _check(self._lib.sts_numerical_rank(self._h, C.byref(r)))
+        return int(r.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sts_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---- step-level calls (device tensors) ----
+
+def apply_op(space: Space, op: int, X):
+    X, px, ldx = dev_colmajor(X)
+    Y = dev_empty(X.shape[0], X.shape[1])
+    _check(load().sts_apply_op(C.byref(space), op, px, ldx, C.c_void_p(Y.data_ptr()),
+                               max(Y.shape[0], 1), X.shape[1], _stream_handle()))
+    return Y
+
+
+def cg(space: Space, ops, B, rtol: float = 1e-12, maxit: int = 200000, check: bool = True):
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_zeros(B.shape[0], B.shape[1])
+    ops_a = (C.c_int32 * len(ops))(*ops)
+    its = (C.c_int32 * len(ops))()
+    code = load().sts_cg(C.byref(space), ops_a, pb, ldb, C.c_void_p(X.data_ptr()), X.shape[0],
+                         B.shape[1], rtol, maxit, its, _stream_handle())
+    if check:
+        _check(code)
+    return X, list(its), code
+
+
+def m_orthonormalize(space: Space, V, MV, W, defl_tol: float = 1e-10):
+    torch = _torch()
+    W, pw, ldw = dev_colmajor(W.clone())
+    MW = dev_empty(W.shape[0], W.shape[1])
+    if V is None or V.shape[1] == 0:
+        pv = pmv = C.c_void_p(0)
+        ldv, k = max(W.shape[0], 1), 0
+    else:
+        V, pv, ldv = dev_colmajor(V)
+        MV, pmv, ldmv = dev_colmajor(MV)
+        assert ldmv == ldv
+        k = V.shape[1]
+    kept = C.c_int32()
+    idx = (C.c_int32 * W.shape[1])()
+    _check(load().sts_m_orthonormalize(C.byref(space), pv, pmv, ldv, k, pw,
+                                       C.c_void_p(MW.data_ptr()), ldw, W.shape[1], defl_tol,
+                                       C.byref(kept), idx, _stream_handle()))
+    kv = kept.value
+    return W[:, :kv], MW[:, :kv], [idx[j] for j in range(kv)]
+
+
+def gram(A, B):
+    A, pa, lda = dev_colmajor(A)
+    B, pb, ldb = dev_colmajor(B)
+    Cm = dev_empty(A.shape[1], B.shape[1])
+    _check(load().sts_gram(A.shape[0], A.shape[1], B.shape[1], pa, lda, pb, ldb,
+                           C.c_void_p(Cm.data_ptr()), A.shape[1], _stream_handle()))
+    return Cm
+
+
+def basis_update(A, Cm, W):
+    A, pa, lda = dev_colmajor(A)
+    Cm, pc, ldc = dev_colmajor(Cm)
+    W, pw, ldw = dev_colmajor(W.clone())
+    _check(load().sts_basis_update(A.shape[0], A.shape[1], W.shape[1], pa, lda, pc, ldc, pw, ldw,
+                                   _stream_handle()))
+    return W
+
+
+def sym_eig(A):
+    A, pa, lda = dev_colmajor(A)
+    k = A.shape[0]
+    lam = dev_empty(k, 1)
+    Q = dev_empty(k, k)
+    _check(load().sts_sym_eig(k, pa, lda, C.c_void_p(lam.data_ptr()), C.c_void_p(Q.data_ptr()), k,
+                              _stream_handle()))
+    return lam[:, 0], Q
+
+
+def time_sweep(lam, Q, beta, F2, dt, mt):
+    lam, pl, _ = dev_colmajor(lam)
+    Q, pq, ldq = dev_colmajor(Q)
+    beta, pb, ldb = dev_colmajor(beta)
+    F2, pf, ldf = dev_colmajor(F2)
+    k, nt, p = Q.shape[0], F2.shape[0], F2.shape[1]
+    Dt, kd = _bidiag(*dt)
+    Mt, km = _bidiag(*mt)
+    Y = dev_empty(k, nt)
+    _check(load().sts_time_sweep(k, nt, p, pl, pq, ldq, pb, ldb, pf, ldf, C.byref(Dt), C.byref(Mt),
+                                 C.c_void_p(Y.data_ptr()), k, _stream_handle()))
+    return Y

@@ -1,0 +1,463 @@
+// Dense kernels of the projection step, FP64 on the CDNA4 matrix cores.
+//
+// The block Gram-Schmidt of the extended Krylov basis contracts the tall
+// basis V (Nh x k) with a thin block W (Nh x <= 16): C = V^T W and W -= V C.
+// Both are HBM-bound (about one flop per byte); the matrix cores are used
+// for the contraction itself through v_mfma_f64_16x16x4f64.  With lane l
+// supplying a = X[l % 16][l / 16] and b = Y[l / 16][l % 16], element q of lane
+// l's accumulator is (X Y)[l % 16][4 (l / 16) + q] (measured on gfx950: rows of
+// the product follow the lane within a 16-lane group, columns follow the group
+// and the accumulator element).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sts_internal.h"
+
+namespace sts {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+constexpr int kRowsPerChunk = 1024;   // rows of one gemm_tn work-group
+
+int64_t tn_chunks(int64_t rows) { return (rows + kRowsPerChunk - 1) / kRowsPerChunk; }
+
+// partial[chunk][i][j] (16-padded m x 16) of A^T B over the chunk's rows.
+__global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t rows, int m, int n, const double* A,
+                                                      int64_t lda, const double* B, int64_t ldb,
+                                                      double* partial, int m16) {
+  __shared__ double acc_s[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int tile = blockIdx.x;            // 16 columns of A
+  const int64_t chunk = blockIdx.y;
+  const int j0 = tile * 16;
+  const int64_t r_begin = chunk * kRowsPerChunk + (int64_t)wv * (kRowsPerChunk / 4);
+  const int64_t r_end = min(r_begin + kRowsPerChunk / 4, rows);
+  const bool acol = (j0 + i) < m;
+  const bool bcol = i < n;
+  const double* Ap = A + (int64_t)(j0 + i) * lda;
+  const double* Bp = B + (int64_t)i * ldb;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r_begin; r < r_end; r += 16) {
+    double av[4], bv[4];
+    const int64_t rr = r + 4 * g;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool ok = (rr + s) < r_end;
+      av[s] = (ok && acol) ? Ap[rr + s] : 0.0;
+      bv[s] = (ok && bcol) ? Bp[rr + s] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = mfma(av[s], bv[s], acc);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc_s[wv][(4 * q + g) * 16 + i] = acc[q];
+  __syncthreads();
+  const int t = threadIdx.x;   // (row, col) = (t / 16, t % 16) of the 16x16 block
+  const double v = (acc_s[0][t] + acc_s[1][t]) + (acc_s[2][t] + acc_s[3][t]);
+  partial[(chunk * m16 + j0 + t / 16) * 16 + (t % 16)] = v;
+}
+
+__global__ void gemm_tn_reduce(int m, int n, int64_t nchunks, int m16, const double* partial,
+                               double* C, int64_t ldc) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int i = idx % m, j = idx / m;
+  double s = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) s += partial[(c * m16 + i) * 16 + j];
+  C[i + (int64_t)j * ldc] = s;
+}
+
+// W (rows x n) -= A (rows x m) C (m x n); each wave owns 16 rows.
+__global__ __launch_bounds__(256) void gemm_nn_sub_kernel(int64_t rows, int m, int n,
+                                                          const double* A, int64_t lda,
+                                                          const double* C, int64_t ldc, double* W,
+                                                          int64_t ldw) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+  if (r0 >= rows) return;
+  const bool rok = (r0 + i) < rows;
+  const bool cok = i < n;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += 4) {
+    const int kk = k0 + g;
+    const double a = (rok && kk < m) ? A[(r0 + i) + (int64_t)kk * lda] : 0.0;
+    const double b = (cok && kk < m) ? C[kk + (int64_t)i * ldc] : 0.0;
+    acc = mfma(a, b, acc);
+  }
+  if (cok) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = r0 + 4 * q + g;
+      if (row < rows) W[row + (int64_t)i * ldw] -= acc[q];
+    }
+  }
+}
+
+// D (m x n) = A (m x kk) B (kk x n); each wave one 16x16 tile.
+__global__ __launch_bounds__(256) void gemm_nn_kernel(int m, int n, int kk, const double* A,
+                                                      int64_t lda, const double* B, int64_t ldb,
+                                                      double* D, int64_t ldd) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int tiles_m = (m + 15) / 16;
+  const int tile = blockIdx.x * 4 + wv;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  if (tn * 16 >= n) return;
+  const int r0 = tm * 16, c0 = tn * 16;
+  const bool rok = (r0 + i) < m;
+  const bool cok = (c0 + i) < n;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kk; k0 += 4) {
+    const int k = k0 + g;
+    const double a = (rok && k < kk) ? A[(r0 + i) + (int64_t)k * lda] : 0.0;
+    const double b = (cok && k < kk) ? B[k + (int64_t)(c0 + i) * ldb] : 0.0;
+    acc = mfma(a, b, acc);
+  }
+  if (cok) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = r0 + 4 * q + g;
+      if (row < m) D[row + (int64_t)(c0 + i) * ldd] = acc[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// || [A_0 A_1 A_2] B ||_F^2 with B given transposed (BT: n x mtot).
+// Work-group tile: 64 rows x 256 columns; wave w owns columns [64 w, 64 w + 64).
+// ---------------------------------------------------------------------------
+struct ResArgs {
+  int64_t rows;
+  int n;
+  int nseg;
+  const double* A[3];
+  int64_t lda[3];
+  int m[3];
+  int mtot;
+  const double* BT;
+  int64_t ldbt;
+  double* partial;
+  unsigned* counter;
+  double* out;
+};
+
+__device__ __forceinline__ double seg_load(const ResArgs& a, int64_t row, int k) {
+  int s = 0, base = 0;
+  while (s < a.nseg - 1 && k >= base + a.m[s]) {
+    base += a.m[s];
+    ++s;
+  }
+  return a.A[s][row + (int64_t)(k - base) * a.lda[s]];
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(ResArgs a) {
+  __shared__ double red[4];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 256 + wv * 64;
+  d4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < a.mtot; k0 += 4) {
+    const int k = k0 + g;
+    double av[4], bv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int64_t row = r0 + 16 * x + i;
+      av[x] = (row < a.rows && k < a.mtot) ? seg_load(a, row, k) : 0.0;
+      const int col = c0 + 16 * x + i;
+      bv[x] = (col < a.n && k < a.mtot) ? a.BT[col + (int64_t)k * a.ldbt] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x], bv[y], acc[x][y]);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += acc[x][y][q] * acc[x][y][q];
+  s = wave_sum(s);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  const int nblk = gridDim.x * gridDim.y;
+  const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+  if (threadIdx.x == 0) {
+    a.partial[bid] = (red[0] + red[1]) + (red[2] + red[3]);
+    __threadfence();
+    const unsigned prev = atomicAdd(a.counter, 1u);
+    last = prev == (unsigned)(nblk - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) t += a.partial[b];
+  t = wave_sum(t);
+  __syncthreads();
+  if (lane == 0) red[wv] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *a.out = (red[0] + red[1]) + (red[2] + red[3]);
+    atomicExch(a.counter, 0u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// Cholesky-based column selection on a b x b Gram matrix (one thread).
+// A column is dropped if its norm^2 G[c][c] is below defl_v^2 norm0[c] (it was
+// already in the span of the basis it was orthogonalised against; G[c][c] is
+// a directly computed norm, so this test is accurate to rounding), or if its
+// remainder after the earlier kept columns of the block falls below
+// defl_b^2 G[c][c] (a Gram-based test, resolvable only to about sqrt(eps)).
+__global__ void chol_deflate_kernel(int b, const double* G, int64_t ldg, const double* norm0,
+                                    double defl_v, double defl_b, double* Rinv, CholInfo* info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double L[16][16];
+  int idx[16];
+  int kept = 0;
+  for (int c = 0; c < b; ++c) {
+    double v[16];
+    const double gcc = G[c + c * ldg];
+    if (!(gcc == gcc) || !(gcc > 0.0)) continue;
+    if (norm0 && !(gcc > defl_v * defl_v * norm0[c])) continue;
+    double d = gcc;
+    for (int j = 0; j < kept; ++j) {
+      double s = G[c + idx[j] * ldg];
+      for (int q = 0; q < j; ++q) s -= v[q] * L[j][q];
+      v[j] = s / L[j][j];
+      d -= v[j] * v[j];
+    }
+    if (!(d > defl_b * defl_b * gcc) || !(d == d)) continue;
+    for (int j = 0; j < kept; ++j) L[kept][j] = v[j];
+    L[kept][kept] = sqrt(d);
+    idx[kept] = c;
+    ++kept;
+  }
+  // R = L^T (upper); Rinv by back substitution, column by column.
+  for (int j = 0; j < b; ++j)
+    for (int i = 0; i < b; ++i) Rinv[i + j * b] = 0.0;
+  for (int j = 0; j < kept; ++j) {
+    // solve R x = e_j, R[i][q] = L[q][i]
+    double x[16];
+    for (int i = kept - 1; i >= 0; --i) {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int q = i + 1; q < kept; ++q) s -= L[q][i] * x[q];
+      x[i] = s / L[i][i];
+    }
+    for (int i = 0; i < kept; ++i) Rinv[i + j * b] = (i <= j) ? x[i] : 0.0;
+  }
+  info->kept = kept;
+  for (int j = 0; j < 16; ++j) info->idx[j] = j < kept ? idx[j] : -1;
+  info->ok = 1;
+}
+
+__global__ void apply_rinv_kernel(int64_t rows, int b, const CholInfo* info, const double* Rinv,
+                                  double* W, double* MW, int64_t ldw) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int kept = info->kept;
+  double w[16], mw[16];
+  for (int j = 0; j < kept; ++j) {
+    const int c = info->idx[j];
+    w[j] = W[r + c * ldw];
+    mw[j] = MW ? MW[r + c * ldw] : 0.0;
+  }
+  for (int j = 0; j < kept; ++j) {
+    double s = 0.0, t = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      const double q = Rinv[i + j * b];
+      s += w[i] * q;
+      t += mw[i] * q;
+    }
+    W[r + j * ldw] = s;
+    if (MW) MW[r + j * ldw] = t;
+  }
+}
+
+__global__ void copy_cols_kernel(int64_t rows, int ncols, const double* src, int64_t lds,
+                                 double* dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ncols) return;
+  const int64_t r = idx % rows, c = idx / rows;
+  dst[r + c * ldd] = src[r + c * lds];
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) p[idx] = v;
+}
+
+__global__ void sumsq_kernel(int64_t rows, int ncols, const double* A, int64_t lda,
+                             double* partial, unsigned* counter, double* out) {
+  __shared__ double red[4];
+  __shared__ int last;
+  const int64_t total = rows * ncols;
+  double s = 0.0;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * 256) {
+    const double v = A[(idx % rows) + (idx / rows) * lda];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double t = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += 256) t += partial[b];
+  t = wave_sum(t);
+  __syncthreads();
+  if (lane == 0) red[wv] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *out = (red[0] + red[1]) + (red[2] + red[3]);
+    atomicExch(counter, 0u);
+  }
+}
+
+}  // namespace
+
+int64_t gemm_tn_partial_size(int64_t rows, int m) {
+  return tn_chunks(rows) * (int64_t)(((m + 15) / 16) * 16) * 16;
+}
+
+void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const double* B,
+             int64_t ldb, double* C, int64_t ldc, double* partial, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  STS_REQUIRE(n <= 16, STS_E_INVALID, "gemm_tn: n > 16");
+  const int m16 = ((m + 15) / 16) * 16;
+  const int64_t nch = tn_chunks(rows);
+  if (rows <= 0) {
+    fill_kernel<<<1, 256, 0, st>>>(partial, (int64_t)m16 * 16, 0.0);
+  } else {
+    dim3 grid(m16 / 16, (unsigned)nch);
+    gemm_tn_kernel<<<grid, 256, 0, st>>>(rows, m, n, A, lda, B, ldb, partial, m16);
+  }
+  STS_HIP(hipGetLastError());
+  gemm_tn_reduce<<<(m * n + 255) / 256, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C,
+                                                      ldc);
+  STS_HIP(hipGetLastError());
+}
+
+void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const double* C,
+                 int64_t ldc, double* W, int64_t ldw, hipStream_t st) {
+  if (m <= 0 || n <= 0 || rows <= 0) return;
+  STS_REQUIRE(n <= 16, STS_E_INVALID, "gemm_nn_sub: n > 16");
+  const int64_t blocks = (rows + 63) / 64;
+  gemm_nn_sub_kernel<<<(unsigned)blocks, 256, 0, st>>>(rows, m, n, A, lda, C, ldc, W, ldw);
+  STS_HIP(hipGetLastError());
+}
+
+void gemm_nn(int m, int n, int kk, const double* A, int64_t lda, const double* B, int64_t ldb,
+             double* D, int64_t ldd, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  if (kk <= 0) {
+    for (int j = 0; j < n; ++j) fill(D + (int64_t)j * ldd, m, 0.0, st);
+    return;
+  }
+  const int tiles = ((m + 15) / 16) * ((n + 15) / 16);
+  gemm_nn_kernel<<<(tiles + 3) / 4, 256, 0, st>>>(m, n, kk, A, lda, B, ldb, D, ldd);
+  STS_HIP(hipGetLastError());
+}
+
+int64_t residual_norm2_partial_size(int64_t rows, int n) {
+  return ((rows + 63) / 64) * ((n + 255) / 256);
+}
+
+void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double* BT,
+                    int64_t ldbt, double* out, double* partial, unsigned* counter,
+                    hipStream_t st) {
+  STS_REQUIRE(nseg >= 1 && nseg <= 3, STS_E_INVALID, "residual_norm2: 1..3 segments");
+  ResArgs a{};
+  a.rows = rows;
+  a.n = n;
+  a.nseg = nseg;
+  a.mtot = 0;
+  for (int s = 0; s < nseg; ++s) {
+    a.A[s] = segs[s].A;
+    a.lda[s] = segs[s].lda;
+    a.m[s] = segs[s].m;
+    a.mtot += segs[s].m;
+  }
+  a.BT = BT;
+  a.ldbt = ldbt;
+  a.partial = partial;
+  a.counter = counter;
+  a.out = out;
+  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((n + 255) / 256));
+  residual_kernel<<<grid, 256, 0, st>>>(a);
+  STS_HIP(hipGetLastError());
+}
+
+void chol_deflate(int b, const double* G, int64_t ldg, const double* norm0, double defl_v,
+                  double defl_b, double* Rinv, CholInfo* info, hipStream_t st) {
+  STS_REQUIRE(b >= 0 && b <= 16, STS_E_INVALID, "chol_deflate: b > 16");
+  chol_deflate_kernel<<<1, 64, 0, st>>>(b, G, ldg, norm0, defl_v, defl_b, Rinv, info);
+  STS_HIP(hipGetLastError());
+}
+
+void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, double* W,
+                double* MW, int64_t ldw, double* /*tmp*/, hipStream_t st) {
+  if (rows <= 0 || b <= 0) return;
+  apply_rinv_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(rows, b, info, Rinv, W, MW,
+                                                                     ldw);
+  STS_HIP(hipGetLastError());
+}
+
+void copy_cols(int64_t rows, int ncols, const double* src, int64_t lds, double* dst, int64_t ldd,
+               hipStream_t st) {
+  const int64_t n = rows * ncols;
+  if (n <= 0) return;
+  copy_cols_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(rows, ncols, src, lds, dst, ldd);
+  STS_HIP(hipGetLastError());
+}
+
+void fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+  STS_HIP(hipGetLastError());
+}
+
+void sumsq(int64_t rows, int ncols, const double* A, int64_t lda, double* out, double* partial,
+           unsigned* counter, hipStream_t st) {
+  const int64_t total = rows * ncols;
+  int blocks = (int)std::min<int64_t>((total + 255) / 256, 1024);
+  if (blocks < 1) blocks = 1;
+  sumsq_kernel<<<blocks, 256, 0, st>>>(rows, ncols, A, lda, partial, counter, out);
+  STS_HIP(hipGetLastError());
+}
+
+}  // namespace sts

@@ -1,0 +1,1194 @@
+// Host driver and C ABI of the space-time Sylvester solver.
+//
+// Galerkin projection (Sec. 4) onto an extended Krylov space in the operator
+// A = Mx^{-1} Kx started from Mx^{-1} F1 (the rational Krylov space of Sec. 4
+// with the poles 0 and infinity):
+//   V_1     = orth_M([Mx^{-1} F1, Kx^{-1} F1])
+//   V_{j+1} = orth_M([Mx^{-1} Kx V_j^+, Kx^{-1} Mx V_j^-])   against V_1..V_j
+// (V_j^+ / V_j^- are the block's columns descended from the positive /
+// negative powers).  Because Mx^{-1} F1 lies in the space and V is
+// Mx-orthonormal, F1 = Mx V beta with beta = V^T F1, and the Arnoldi-type
+// relation A V_m = V_{m+1} T gives the residual of the Galerkin solution in
+// closed form: R = -(Mx V_new)(tau Y Mt^T) with tau = V_new^T Kx V_m, so
+// ||R||_F = ||L^T tau Y Mt^T||_F where L L^T = (Mx V_new)^T (Mx V_new).  This
+// projected residual is monitored; success is confirmed with the exact
+// residual ||F1 F2^T - (Kx V) Y Mt^T - (Mx V) Y Dt^T||_F, evaluated without
+// forming the Nh x Nt product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sts_internal.h"
+
+namespace sts {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// spatial operators
+// ---------------------------------------------------------------------------
+
+void validate_space(const sts_space* s) {
+  STS_REQUIRE(s != nullptr, STS_E_INVALID, "space is NULL");
+  STS_REQUIRE(s->kind == STS_FE_P1_1D || s->kind == STS_FE_P1_2D || s->kind == STS_FE_Q1_3D_7PT,
+              STS_E_INVALID, "unsupported space kind");
+  STS_REQUIRE(std::isfinite(s->mu) && s->mu > 0.0, STS_E_INVALID, "mu must be finite and > 0");
+  const int dim = s->kind;
+  for (int d = 0; d < 3; ++d) {
+    if (d < dim) {
+      STS_REQUIRE(s->n[d] >= 1 && s->n[d] <= (int64_t)1 << 30, STS_E_INVALID,
+                  "grid size out of range");
+      STS_REQUIRE(s->n[d] == s->n[0], STS_E_INVALID, "grid must be isotropic (equal n[d])");
+    } else {
+      STS_REQUIRE(s->n[d] == 1 || s->n[d] == 0, STS_E_INVALID, "unused directions need n[d] = 1");
+    }
+  }
+  int64_t nh = 1;
+  for (int d = 0; d < dim; ++d) nh *= s->n[d];
+  STS_REQUIRE(nh <= ((int64_t)1 << 34), STS_E_INVALID, "too many grid nodes");
+}
+
+Grid make_grid(const sts_space& s) {
+  Grid g;
+  g.dim = s.kind;
+  g.nx = (int)s.n[0];
+  g.ny = g.dim >= 2 ? (int)s.n[1] : 1;
+  g.nz = g.dim >= 3 ? (int)s.n[2] : 1;
+  g.nh = (int64_t)g.nx * g.ny * g.nz;
+  return g;
+}
+
+static inline int sidx(int dx, int dy, int dz) { return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); }
+
+Stencil make_stencil(const sts_space& s, int op) {
+  Stencil st{};
+  const Grid g = make_grid(s);
+  st.dim = g.dim;
+  st.nx = g.nx;
+  st.ny = g.ny;
+  st.nz = g.nz;
+  const double h = 1.0 / (double)(s.n[0] + 1);
+  const double mu = s.mu;
+  if (s.kind == STS_FE_P1_1D) {
+    if (op == STS_OP_K) {
+      st.c[sidx(-1, 0, 0)] = -mu / h;
+      st.c[sidx(0, 0, 0)] = 2.0 * mu / h;
+      st.c[sidx(1, 0, 0)] = -mu / h;
+    } else {
+      st.c[sidx(-1, 0, 0)] = h / 6.0;
+      st.c[sidx(0, 0, 0)] = 4.0 * h / 6.0;
+      st.c[sidx(1, 0, 0)] = h / 6.0;
+    }
+  } else if (s.kind == STS_FE_P1_2D) {
+    if (op == STS_OP_K) {
+      st.c[sidx(0, 0, 0)] = 4.0 * mu;
+      st.c[sidx(1, 0, 0)] = st.c[sidx(-1, 0, 0)] = -mu;
+      st.c[sidx(0, 1, 0)] = st.c[sidx(0, -1, 0)] = -mu;
+    } else {
+      const double w = h * h / 12.0;
+      st.c[sidx(0, 0, 0)] = 6.0 * w;
+      st.c[sidx(1, 0, 0)] = st.c[sidx(-1, 0, 0)] = w;
+      st.c[sidx(0, 1, 0)] = st.c[sidx(0, -1, 0)] = w;
+      st.c[sidx(1, 1, 0)] = st.c[sidx(-1, -1, 0)] = w;
+    }
+  } else {
+    if (op == STS_OP_K) {
+      st.c[sidx(0, 0, 0)] = 6.0 * mu * h;
+      st.c[sidx(1, 0, 0)] = st.c[sidx(-1, 0, 0)] = -mu * h;
+      st.c[sidx(0, 1, 0)] = st.c[sidx(0, -1, 0)] = -mu * h;
+      st.c[sidx(0, 0, 1)] = st.c[sidx(0, 0, -1)] = -mu * h;
+    } else {
+      const double w1[3] = {1.0, 4.0, 1.0};
+      const double sc = (h / 6.0) * (h / 6.0) * (h / 6.0);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx)
+            st.c[sidx(dx, dy, dz)] = sc * w1[dx + 1] * w1[dy + 1] * w1[dz + 1];
+    }
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{STS_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+  }
+  double* d() const { return static_cast<double*>(p); }
+};
+
+static inline int64_t pad_ld(int64_t n) { return ((n + 31) / 32) * 32; }
+
+// Scratch of the step-level calls: freed when the call returns.
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  T* get(size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 8));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{STS_E_NOMEM, "hipMalloc failed in step-level call"};
+    }
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// block Gram-Schmidt in the Mx inner product
+// ---------------------------------------------------------------------------
+
+int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
+                         const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
+                         int64_t ldw, int ncols, double defl, const OrthScratch& s, int* idx,
+                         hipStream_t st) {
+  const int64_t nh = g.nh;
+  int opsM[16];
+  for (int c = 0; c < 16; ++c) opsM[c] = STS_OP_M;
+  auto cgs = [&](int nc) {
+    if (k <= 0) return;
+    gemm_tn(nh, (int)k, nc, MV, ldv, W, ldw, s.C, s.ldc, s.part, st);   // C = V^T Mx W
+    gemm_nn_sub(nh, (int)k, nc, V, ldv, s.C, s.ldc, W, ldw, st);        // W -= V C
+  };
+  auto fetch_info = [&]() {
+    STS_HIP(hipMemcpyAsync(s.host, s.info, sizeof(CholInfo), hipMemcpyDeviceToHost, st));
+    STS_HIP(hipStreamSynchronize(st));
+    return *s.host;
+  };
+  // Mx-norms on entry: the reference for "already in the span of V"
+  stencil_apply(g, K, M, opsM, ncols, W, ldw, MW, ldw, st);
+  gemm_tn(nh, ncols, ncols, W, ldw, MW, ldw, s.G, 16, s.part, st);
+  copy_cols(1, ncols, s.G, 17, s.norm0, 1, st);
+  // classical Gram-Schmidt against V, twice
+  cgs(ncols);
+  cgs(ncols);
+  // Cholesky-QR of the block with deflation
+  stencil_apply(g, K, M, opsM, ncols, W, ldw, MW, ldw, st);
+  gemm_tn(nh, ncols, ncols, W, ldw, MW, ldw, s.G, 16, s.part, st);
+  chol_deflate(ncols, s.G, 16, s.norm0, defl, kBlockDefl, s.Rinv, s.info, st);
+  apply_rinv(nh, ncols, s.info, s.Rinv, W, nullptr, ldw, nullptr, st);
+  CholInfo h = fetch_info();
+  const int kept = h.kept;
+  for (int j = 0; j < kept; ++j) idx[j] = h.idx[j];
+  if (kept == 0) return 0;
+  // A small pivot above amplifies rounding along V and within the block:
+  // one more pass against V and a second Cholesky-QR restore both.
+  cgs(kept);
+  stencil_apply(g, K, M, opsM, kept, W, ldw, MW, ldw, st);
+  gemm_tn(nh, kept, kept, W, ldw, MW, ldw, s.G, 16, s.part, st);
+  chol_deflate(kept, s.G, 16, nullptr, 0.0, kBlockDefl, s.Rinv, s.info, st);
+  apply_rinv(nh, kept, s.info, s.Rinv, W, nullptr, ldw, nullptr, st);
+  h = fetch_info();
+  STS_REQUIRE(h.kept == kept, STS_E_NUMERIC, "block lost rank in the second Cholesky-QR pass");
+  stencil_apply(g, K, M, opsM, kept, W, ldw, MW, ldw, st);   // exact Mx image
+  return kept;
+}
+
+// ---------------------------------------------------------------------------
+// CG batch runner (shared by the solver and sts_cg)
+// ---------------------------------------------------------------------------
+
+struct CGRunner {
+  Grid g;
+  Stencil K, M;
+  CGWork w;
+  CGScal* host_scal = nullptr;   // pinned, 2 * kMaxCols
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // optional event timing of the iteration kernels
+  bool profile = false;
+  std::vector<hipEvent_t> tev;   // pairs (start, end) per chunk, reused
+  double prof_seconds = 0.0;
+  int64_t prof_launches = 0, prof_col_iters = 0;
+
+  ~CGRunner() {
+    for (auto e : tev) (void)hipEventDestroy(e);
+  }
+
+  // Solve A_c x_c = b_c for c < ncols; x_c written to w.x + c * w.ld.
+  // Returns per-column iteration counts and flags in `out` (host).
+  void run(const int* ops, int ncols, const double* const* b, double rtol, int maxit,
+           CGScal* out, hipStream_t st) {
+    CGScal init[kMaxCols];
+    for (int c = 0; c < kMaxCols; ++c) {
+      init[c] = CGScal{};
+      init[c].rtol2 = rtol * rtol;
+      init[c].maxit = maxit;
+      init[c].active = c < ncols ? 1 : 0;
+    }
+    std::memcpy(host_scal, init, sizeof(init));
+    // initial state into slot 0, read by the set-up (launch 0) and launch 1
+    STS_HIP(hipMemcpyAsync(w.scal, host_scal, sizeof(init), hipMemcpyHostToDevice, st));
+    for (int c = 0; c < ncols; ++c) w.b[c] = b[c];
+    cg_setup(g, K, M, ops, ncols, w, st);
+    int64_t launches = 0;   // iteration launches so far (launch index = launches)
+    int slot = 0, chunk = 8;
+    bool pending = false;
+    size_t nchunk = 0;
+    for (;;) {
+      if (profile) {
+        if (tev.size() < 2 * (nchunk + 1)) {
+          for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            STS_HIP(hipEventCreate(&e));
+            tev.push_back(e);
+          }
+        }
+        STS_HIP(hipEventRecord(tev[2 * nchunk], st));
+      }
+      for (int i = 0; i < chunk; ++i) {
+        ++launches;
+        cg_iterate(g, K, M, ops, ncols, w, (int)(launches & 1), st);
+      }
+      if (profile) {
+        STS_HIP(hipEventRecord(tev[2 * nchunk + 1], st));
+        prof_launches += chunk;
+        ++nchunk;
+      }
+      // state written by the last launch of the chunk
+      STS_HIP(hipMemcpyAsync(host_scal + slot * kMaxCols, w.scal + (launches & 1) * kMaxCols,
+                             sizeof(CGScal) * kMaxCols, hipMemcpyDeviceToHost, st));
+      STS_HIP(hipEventRecord(ev[slot], st));
+      if (pending) {
+        const int other = slot ^ 1;
+        STS_HIP(hipEventSynchronize(ev[other]));
+        bool any = false;
+        for (int c = 0; c < ncols; ++c) any |= host_scal[other * kMaxCols + c].active != 0;
+        if (!any) break;
+      }
+      pending = true;
+      slot ^= 1;
+      chunk = std::min(chunk * 2, 256);
+    }
+    // the chunk in flight found nothing to do; its copy holds the same state
+    STS_HIP(hipEventSynchronize(ev[slot]));
+    std::memcpy(out, host_scal + slot * kMaxCols, sizeof(CGScal) * kMaxCols);
+    if (profile) {
+      for (size_t q = 0; q < nchunk; ++q) {
+        float ms = 0.0f;
+        STS_HIP(hipEventElapsedTime(&ms, tev[2 * q], tev[2 * q + 1]));
+        prof_seconds += 1e-3 * ms;
+      }
+      for (int c = 0; c < ncols; ++c) prof_col_iters += out[c].iters;
+    }
+  }
+};
+
+}  // namespace sts
+
+using namespace sts;
+
+// ---------------------------------------------------------------------------
+// the problem object
+// ---------------------------------------------------------------------------
+
+struct sts_problem {
+  sts_space space{};
+  Grid grid{};
+  Stencil K{}, M{};
+  int64_t nh = 0, nt = 0, ldv = 0;
+  int p = 0;
+  hipStream_t stream = nullptr;
+  double fnorm = 0.0;
+
+  std::vector<double> h_td, h_ts, h_md, h_ms;
+  DevBuf F1, F2, tdv;   // tdv: d (nt) | e (nt) | m (nt) | n (nt)
+
+  // basis and reduced matrices
+  int64_t kcap = 0;
+  int64_t k = 0;          // columns in V (including a pending new block)
+  int64_t k_sol = 0;      // columns of the current Galerkin solution
+  int64_t blk_start = 0, blk_size = 0;
+  std::vector<int> tags;  // 0: positive power, 1: negative power
+  DevBuf V, MV, KV, Kred, Mred, beta;
+
+  // CG
+  DevBuf cg_r, cg_p, cg_scal, cg_part, counters;
+  CGRunner cg;
+
+  // small scratch
+  DevBuf gram, tn_part, rinv, cinfo, norm0, smallv, Lb, T1, okflag;
+  // reduced solve
+  DevBuf lam, Q, eig_a, eig_tau, eig_e, eig_meta, qb, Z, Y;
+  // residual
+  DevBuf BT, res_part;
+  double* pinned = nullptr;   // 64 doubles
+  bool solved = false;
+  int64_t inner_K = 0, inner_M = 0;
+  double alg_bytes = 0.0;
+  int checks = 0;
+  double last_cheap = -1.0;
+
+  unsigned* counter(int i) const { return static_cast<unsigned*>(counters.p) + i; }
+
+  ~sts_problem() {
+    if (cg.host_scal) (void)hipHostFree(cg.host_scal);
+    if (pinned) (void)hipHostFree(pinned);
+    for (auto& e : cg.ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+void ensure_capacity(sts_problem* P, int64_t need, int64_t budget) {
+  if (need <= P->kcap) return;
+  const int64_t kc = need;
+  const int64_t ld = P->ldv;
+  const int64_t nt = P->nt;
+  const int64_t bytes = 3 * ld * kc * 8 + 2 * kc * kc * 8 + kc * P->p * 8 +   // V MV KV Kred Mred beta
+                        kc * kc * 8 * 2 + kc * 8 * 3 + 2 * kc * nt * 8 +       // Q eig_a, vectors, Z Y
+                        nt * (P->p + 2 * kc) * 8;                              // BT
+  STS_REQUIRE(budget <= 0 || bytes <= budget, STS_E_NOMEM,
+              "basis of " + std::to_string(kc) + " columns needs " + std::to_string(bytes) +
+                  " bytes, above the memory budget");
+  hipStream_t st = P->stream;
+  auto grow = [&](DevBuf& b, size_t nbytes, size_t keep) {
+    DevBuf nb;
+    nb.alloc(nbytes);
+    if (keep && b.p) STS_HIP(hipMemcpyAsync(nb.p, b.p, keep, hipMemcpyDeviceToDevice, st));
+    STS_HIP(hipStreamSynchronize(st));
+    std::swap(b.p, nb.p);
+    std::swap(b.bytes, nb.bytes);
+  };
+  const int64_t old = P->kcap;
+  grow(P->V, ld * kc * 8, ld * old * 8);
+  grow(P->MV, ld * kc * 8, ld * old * 8);
+  grow(P->KV, ld * kc * 8, ld * old * 8);
+  // reduced matrices change leading dimension: copy column by column
+  auto grow_sq = [&](DevBuf& b) {
+    DevBuf nb;
+    nb.alloc(kc * kc * 8);
+    fill(nb.d(), kc * kc, 0.0, st);
+    if (old && b.p) copy_cols(old, (int)old, b.d(), old, nb.d(), kc, st);
+    STS_HIP(hipStreamSynchronize(st));
+    std::swap(b.p, nb.p);
+    std::swap(b.bytes, nb.bytes);
+  };
+  grow_sq(P->Kred);
+  grow_sq(P->Mred);
+  {
+    DevBuf nb;
+    nb.alloc(kc * P->p * 8);
+    if (old && P->beta.p) copy_cols(old, P->p, P->beta.d(), old, nb.d(), kc, st);
+    STS_HIP(hipStreamSynchronize(st));
+    std::swap(P->beta.p, nb.p);
+    std::swap(P->beta.bytes, nb.bytes);
+  }
+  P->lam.alloc(kc * 8);
+  P->Q.alloc(kc * kc * 8);
+  P->eig_a.alloc(kc * kc * 8);
+  P->eig_tau.alloc(kc * 8);
+  P->eig_e.alloc(kc * 8);
+  P->eig_meta.alloc(64);
+  P->qb.alloc(kc * 4 * 8);
+  P->Z.alloc(kc * nt * 8);
+  P->Y.alloc(kc * nt * 8);
+  P->BT.alloc(nt * (P->p + 2 * kc) * 8);
+  P->tn_part.alloc(gemm_tn_partial_size(P->nh, (int)kc) * 8);
+  P->kcap = kc;
+}
+
+TimeOps time_ops(const sts_problem* P) {
+  const double* b = P->tdv.d();
+  return TimeOps{b, b + P->nt, b + 2 * P->nt, b + 3 * P->nt};
+}
+
+// Copy a few device doubles to the host (synchronising the stream).
+void fetch(sts_problem* P, const double* src, int n, double* dst) {
+  STS_HIP(hipMemcpyAsync(P->pinned, src, n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  STS_HIP(hipStreamSynchronize(P->stream));
+  std::memcpy(dst, P->pinned, n * sizeof(double));
+}
+
+// Orthonormalise the ncols columns at V[:, k..k+ncols) against V[:, 0..k) in
+// the Mx inner product (CGS2, then two Cholesky-QR passes with deflation),
+// pack the kept ones at V[:, k..), fill MV, KV, the reduced matrices and beta.
+// Returns the number of kept columns; keep_idx receives their source indices.
+int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
+  hipStream_t st = P->stream;
+  const int64_t nh = P->nh, ld = P->ldv, k = P->k;
+  double* W = P->V.d() + k * ld;
+  double* MW = P->MV.d() + k * ld;
+  OrthScratch s;
+  s.part = P->tn_part.d();
+  s.G = P->gram.d();
+  s.C = P->smallv.d();
+  s.ldc = P->kcap;
+  s.norm0 = P->norm0.d();
+  s.Rinv = P->rinv.d();
+  s.info = static_cast<CholInfo*>(P->cinfo.p);
+  s.host = reinterpret_cast<CholInfo*>(P->pinned);
+  const int kept = orthonormalize_block(P->grid, P->K, P->M, P->V.d(), P->MV.d(), ld, k, W, MW,
+                                        ld, ncols, defl, s, keep_idx, st);
+  P->alg_bytes += 6.0 * 8.0 * nh * k + 8.0 * 16.0 * nh * ncols;
+  if (kept == 0) return 0;
+  // Kx image of the new columns
+  int opsK[16];
+  for (int c = 0; c < 16; ++c) opsK[c] = STS_OP_K;
+  double* KW = P->KV.d() + k * ld;
+  stencil_apply(P->grid, P->K, P->M, opsK, kept, W, ld, KW, ld, st);
+  // reduced matrices: new columns and their mirror rows
+  const int64_t kn = k + kept, kc = P->kcap;
+  gemm_tn(nh, (int)kn, kept, P->V.d(), ld, KW, ld, P->Kred.d() + k * kc, kc, P->tn_part.d(), st);
+  gemm_tn(nh, (int)kn, kept, P->V.d(), ld, MW, ld, P->Mred.d() + k * kc, kc, P->tn_part.d(), st);
+  mirror((int)k, kept, P->Kred.d() + k * kc, kc, P->Kred.d() + k, kc, st);
+  mirror((int)k, kept, P->Mred.d() + k * kc, kc, P->Mred.d() + k, kc, st);
+  gemm_tn(nh, kept, P->p, W, ld, P->F1.d(), ld, P->beta.d() + k, kc, P->tn_part.d(), st);
+  P->alg_bytes += 2.0 * 8.0 * nh * kn + 4.0 * 16.0 * nh * kept;
+  return kept;
+}
+
+// Reduced solve on the first ks columns and projected residual with the block
+// V[:, ks..ks+b).  Returns the relative projected residual (b = 0 -> 0).
+double reduced_solve(sts_problem* P, int64_t ks, int64_t b) {
+  hipStream_t st = P->stream;
+  const int64_t kc = P->kcap, nt = P->nt;
+  EigWork ew{};
+  ew.a = P->eig_a.d();
+  ew.tau = P->eig_tau.d();
+  ew.e = P->eig_e.d();
+  ew.meta = static_cast<int*>(P->eig_meta.p);
+  sym_eig((int)ks, P->Kred.d(), kc, P->lam.d(), P->Q.d(), kc, ew, st);
+  gemm_tn(ks, (int)ks, P->p, P->Q.d(), kc, P->beta.d(), kc, P->qb.d(), kc, P->tn_part.d(), st);
+  time_sweep((int)ks, (int)nt, P->p, P->lam.d(), P->qb.d(), kc, P->F2.d(), nt, time_ops(P),
+             P->Z.d(), kc, st);
+  gemm_nn((int)ks, (int)nt, (int)ks, P->Q.d(), kc, P->Z.d(), kc, P->Y.d(), kc, st);
+  double res2 = 0.0;
+  if (b > 0) {
+    // tau = Kred[ks:ks+b, 0:ks]; T1 = tau Y
+    gemm_nn((int)b, (int)nt, (int)ks, P->Kred.d() + ks, kc, P->Y.d(), kc, P->T1.d(), 16, st);
+    double* MWn = P->MV.d() + ks * P->ldv;
+    gemm_tn(P->nh, (int)b, (int)b, MWn, P->ldv, MWn, P->ldv, P->gram.d(), 16, P->tn_part.d(), st);
+    chol_lower((int)b, P->gram.d(), 16, P->Lb.d(), 16, static_cast<int*>(P->okflag.p), st);
+    const TimeOps t = time_ops(P);
+    cheap_residual((int)b, (int)nt, P->T1.d(), 16, P->Lb.d(), 16, t.m, t.n, P->smallv.d(),
+                   P->res_part.d(), P->counter(0), st);
+    P->alg_bytes += 8.0 * P->nh * b;
+  }
+  int status = 0;
+  STS_HIP(hipMemcpyAsync(P->pinned, P->eig_meta.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  STS_HIP(hipStreamSynchronize(st));
+  std::memcpy(&status, P->pinned, sizeof(int));
+  STS_REQUIRE(status == 0, STS_E_NUMERIC, "reduced eigensolver did not converge");
+  if (b > 0) fetch(P, P->smallv.d(), 1, &res2);
+  ++P->checks;
+  return std::sqrt(std::max(res2, 0.0)) / P->fnorm;
+}
+
+double true_residual(sts_problem* P) {
+  hipStream_t st = P->stream;
+  const int64_t ks = P->k_sol, nt = P->nt, p = P->p;
+  double* BT = P->BT.d();
+  const int64_t ldbt = nt;
+  copy_cols(nt, (int)p, P->F2.d(), nt, BT, ldbt, st);
+  const TimeOps t = time_ops(P);
+  bidiag_right((int)ks, (int)nt, P->Y.d(), P->kcap, t.m, t.n, -1.0, BT + p * ldbt, ldbt, st);
+  bidiag_right((int)ks, (int)nt, P->Y.d(), P->kcap, t.d, t.e, -1.0, BT + (p + ks) * ldbt, ldbt,
+               st);
+  Seg segs[3] = {{P->F1.d(), P->ldv, (int)p}, {P->KV.d(), P->ldv, (int)ks},
+                 {P->MV.d(), P->ldv, (int)ks}};
+  const int nseg = ks > 0 ? 3 : 1;
+  residual_norm2(P->nh, (int)nt, segs, nseg, BT, ldbt, P->smallv.d(), P->res_part.d(),
+                 P->counter(1), st);
+  double r2 = 0.0;
+  fetch(P, P->smallv.d(), 1, &r2);
+  P->alg_bytes += 8.0 * P->nh * (p + 2 * ks) * ((nt + 255) / 256);
+  return std::sqrt(std::max(r2, 0.0)) / P->fnorm;
+}
+
+void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const* b,
+                  const sts_opts& o) {
+  CGScal out[kMaxCols];
+  P->cg.w.x = P->V.d() + P->k * P->ldv;
+  P->cg.w.ld = P->ldv;
+  P->cg.run(ops, ncols, b, o.inner_rtol, o.inner_maxit, out, P->stream);
+  for (int c = 0; c < ncols; ++c) {
+    STS_REQUIRE(out[c].flag != 3, STS_E_NUMERIC,
+                "inner CG broke down (non-positive curvature or non-finite value)");
+    STS_REQUIRE(out[c].flag != 2, STS_E_NUMERIC, "inner CG reached its iteration cap");
+    if (ops[c] == STS_OP_K) P->inner_K += out[c].iters;
+    else P->inner_M += out[c].iters;
+    P->alg_bytes += (48.0 * out[c].iters + 32.0) * P->nh;
+  }
+}
+
+int64_t numerical_rank(sts_problem* P) {
+  // V is Mx-orthonormal, so the singular values of V Y in the Mx norm are those
+  // of Y: eigenvalues of Y Y^T (reuses the eigen workspace; Kred untouched).
+  hipStream_t st = P->stream;
+  const int64_t ks = P->k_sol, nt = P->nt, kc = P->kcap;
+  if (ks == 0) return 0;
+  transpose((int)ks, (int)nt, P->Y.d(), kc, P->Z.d(), nt, st);   // Z <- Y^T (nt x ks)
+  DevBuf gy;
+  gy.alloc(ks * ks * 8);
+  gemm_nn((int)ks, (int)ks, (int)nt, P->Y.d(), kc, P->Z.d(), nt, gy.d(), ks, st);
+  EigWork ew{};
+  ew.a = P->eig_a.d();
+  ew.tau = P->eig_tau.d();
+  ew.e = P->eig_e.d();
+  ew.meta = static_cast<int*>(P->eig_meta.p);
+  DevBuf qtmp;
+  qtmp.alloc(ks * ks * 8);
+  DevBuf ltmp;
+  ltmp.alloc(ks * 8);
+  sym_eig((int)ks, gy.d(), ks, ltmp.d(), qtmp.d(), ks, ew, st);
+  std::vector<double> ev(ks);
+  STS_HIP(hipMemcpyAsync(ev.data(), ltmp.p, ks * 8, hipMemcpyDeviceToHost, st));
+  STS_HIP(hipStreamSynchronize(st));
+  double mx = 0.0;
+  for (double v : ev) mx = std::max(mx, v);
+  int64_t r = 0;
+  for (double v : ev)
+    if (v > 1e-16 * mx) ++r;   // sigma_i > 1e-8 sigma_1
+  // Y was overwritten only in Z (scratch): the solution stays in P->Y.
+  return r;
+}
+
+double orth_error(sts_problem* P) {
+  const int64_t ks = P->k_sol, kc = P->kcap;
+  if (ks == 0) return 0.0;
+  std::vector<double> m(kc * ks);
+  STS_HIP(hipMemcpyAsync(m.data(), P->Mred.p, kc * ks * 8, hipMemcpyDeviceToHost, P->stream));
+  STS_HIP(hipStreamSynchronize(P->stream));
+  double e = 0.0;
+  for (int64_t j = 0; j < ks; ++j)
+    for (int64_t i = 0; i < ks; ++i) e = std::max(e, std::fabs(m[i + j * kc] - (i == j ? 1.0 : 0.0)));
+  return e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+namespace {
+sts_status run_guarded(const std::function<void()>& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return STS_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return STS_E_NOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return STS_E_DEVICE;
+  }
+}
+
+void check_finite(const double* h, int64_t rows, int64_t cols, int64_t ld, const char* what) {
+  for (int64_t j = 0; j < cols; ++j)
+    for (int64_t i = 0; i < rows; ++i)
+      STS_REQUIRE(std::isfinite(h[i + j * ld]), STS_E_INVALID, std::string(what) + " is not finite");
+}
+}  // namespace
+
+extern "C" {
+
+void sts_default_opts(sts_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->max_outer = 200;
+  o->check_every = 0;
+  o->inner_rtol = 1e-12;
+  o->inner_maxit = 200000;
+  o->verify_true = 1;
+  o->defl_tol = 1e-10;
+  o->mem_budget = 0;
+  o->restart = 0;
+  o->profile = 0;
+}
+
+const char* sts_last_error(void) { return g_last_error.c_str(); }
+
+sts_status sts_time_matrices(int64_t nt, const double* t, double* dd, double* ds, double* md,
+                             double* ms) {
+  return run_guarded([&] {
+    STS_REQUIRE(nt >= 1 && t && dd && md && (nt == 1 || (ds && ms)), STS_E_INVALID,
+                "sts_time_matrices: bad arguments");
+    for (int64_t l = 0; l < nt; ++l)
+      STS_REQUIRE(std::isfinite(t[l]) && std::isfinite(t[l + 1]) && t[l + 1] > t[l],
+                  STS_E_INVALID, "time nodes must be finite and strictly increasing");
+    // On I^l the hat sigma^l rises from 0 to 1 and sigma^{l-1} falls from 1 to 0:
+    // (d/dt sigma^l, tau^l) = 1, (d/dt sigma^{l-1}, tau^l) = -1, and both hats
+    // integrate to |I^l| / 2 over I^l.
+    for (int64_t l = 0; l < nt; ++l) {
+      const double len = t[l + 1] - t[l];
+      dd[l] = 1.0;
+      md[l] = 0.5 * len;
+      if (l > 0) {
+        ds[l - 1] = -1.0;
+        ms[l - 1] = 0.5 * len;
+      }
+    }
+  });
+}
+
+sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bidiag* Mt,
+                      int64_t nt, int32_t p, const double* F1, int64_t ldf1, const double* F2,
+                      int64_t ldf2, int32_t mem, void* stream, sts_problem** out) {
+  return run_guarded([&] {
+    STS_REQUIRE(out != nullptr, STS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    validate_space(space);
+    STS_REQUIRE(Dt && Mt && Dt->diag && Mt->diag, STS_E_INVALID, "time matrices are NULL");
+    STS_REQUIRE(nt >= 2, STS_E_INVALID, "nt must be >= 2");
+    STS_REQUIRE(Dt->sub && Mt->sub, STS_E_INVALID, "time sub-diagonals are NULL");
+    STS_REQUIRE(p >= 1 && p <= 4, STS_E_INVALID, "p must be in 1..4");
+    STS_REQUIRE(F1 && F2, STS_E_INVALID, "F1 / F2 is NULL");
+    STS_REQUIRE(mem == STS_MEM_HOST || mem == STS_MEM_DEVICE, STS_E_INVALID, "bad mem kind");
+    const Grid g = make_grid(*space);
+    STS_REQUIRE(ldf1 >= g.nh && ldf2 >= nt, STS_E_INVALID, "leading dimension too small");
+    for (int64_t l = 0; l < nt; ++l) {
+      STS_REQUIRE(std::isfinite(Dt->diag[l]) && Dt->diag[l] > 0.0 && std::isfinite(Mt->diag[l]) &&
+                      Mt->diag[l] > 0.0,
+                  STS_E_INVALID, "time matrices need positive, finite diagonals");
+      if (l + 1 < nt)
+        STS_REQUIRE(std::isfinite(Dt->sub[l]) && std::isfinite(Mt->sub[l]), STS_E_INVALID,
+                    "time sub-diagonals must be finite");
+    }
+    if (mem == STS_MEM_HOST) {
+      check_finite(F1, g.nh, p, ldf1, "F1");
+      check_finite(F2, nt, p, ldf2, "F2");
+    }
+    auto P = std::make_unique<sts_problem>();
+    P->space = *space;
+    P->grid = g;
+    P->K = make_stencil(*space, STS_OP_K);
+    P->M = make_stencil(*space, STS_OP_M);
+    P->nh = g.nh;
+    P->nt = nt;
+    P->p = p;
+    P->ldv = pad_ld(g.nh);
+    P->stream = static_cast<hipStream_t>(stream);
+    hipStream_t st = P->stream;
+    P->h_td.assign(Dt->diag, Dt->diag + nt);
+    P->h_ts.assign(Dt->sub, Dt->sub + nt - 1);
+    P->h_md.assign(Mt->diag, Mt->diag + nt);
+    P->h_ms.assign(Mt->sub, Mt->sub + nt - 1);
+    // inputs
+    P->F1.alloc(P->ldv * p * 8);
+    P->F2.alloc(nt * p * 8);
+    if (mem == STS_MEM_HOST) {
+      STS_HIP(hipMemcpy2DAsync(P->F1.p, P->ldv * 8, F1, ldf1 * 8, g.nh * 8, p,
+                               hipMemcpyHostToDevice, st));
+      STS_HIP(hipMemcpy2DAsync(P->F2.p, nt * 8, F2, ldf2 * 8, nt * 8, p, hipMemcpyHostToDevice, st));
+    } else {
+      copy_cols(g.nh, p, F1, ldf1, P->F1.d(), P->ldv, st);
+      copy_cols(nt, p, F2, ldf2, P->F2.d(), nt, st);
+    }
+    std::vector<double> tv(4 * nt, 0.0);
+    for (int64_t l = 0; l < nt; ++l) {
+      tv[l] = P->h_td[l];
+      tv[2 * nt + l] = P->h_md[l];
+      if (l + 1 < nt) {
+        tv[nt + l] = P->h_ts[l];
+        tv[3 * nt + l] = P->h_ms[l];
+      }
+    }
+    P->tdv.alloc(4 * nt * 8);
+    STS_HIP(hipMemcpyAsync(P->tdv.p, tv.data(), 4 * nt * 8, hipMemcpyHostToDevice, st));
+    // CG work
+    const int tiles = cg_tiles(g);
+    P->cg_r.alloc(P->ldv * kMaxCols * 8);
+    P->cg_p.alloc(P->ldv * kMaxCols * 8);
+    P->cg_scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
+    P->cg_part.alloc((size_t)2 * 2 * kMaxCols * tiles * 8);
+    P->counters.alloc(64);
+    STS_HIP(hipMemsetAsync(P->counters.p, 0, 64, st));
+    P->cg.g = g;
+    P->cg.K = P->K;
+    P->cg.M = P->M;
+    P->cg.w.r = P->cg_r.d();
+    P->cg.w.p = P->cg_p.d();
+    P->cg.w.scal = static_cast<CGScal*>(P->cg_scal.p);
+    P->cg.w.partials = P->cg_part.d();
+    P->cg.w.max_tiles = tiles;
+    STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->cg.host_scal),
+                          sizeof(CGScal) * 2 * kMaxCols, hipHostMallocDefault));
+    STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->pinned), 64 * 8, hipHostMallocDefault));
+    STS_HIP(hipEventCreateWithFlags(&P->cg.ev[0], hipEventDisableTiming));
+    STS_HIP(hipEventCreateWithFlags(&P->cg.ev[1], hipEventDisableTiming));
+    // small scratch
+    P->gram.alloc(16 * 16 * 8);
+    P->rinv.alloc(16 * 16 * 8);
+    P->cinfo.alloc(sizeof(CholInfo));
+    P->norm0.alloc(16 * 8);
+    P->Lb.alloc(16 * 16 * 8);
+    P->T1.alloc(16 * nt * 8);
+    P->okflag.alloc(16);
+    P->res_part.alloc(std::max<int64_t>(residual_norm2_partial_size(g.nh, (int)nt), 4096) * 8);
+    // ||F1 F2^T||_F^2 = trace((F1^T F1)(F2^T F2))
+    P->tn_part.alloc(gemm_tn_partial_size(std::max<int64_t>(g.nh, nt), 16) * 8);
+    double* G1 = P->gram.d();
+    double* G2 = P->rinv.d();
+    gemm_tn(g.nh, p, p, P->F1.d(), P->ldv, P->F1.d(), P->ldv, G1, 16, P->tn_part.d(), st);
+    gemm_tn(nt, p, p, P->F2.d(), nt, P->F2.d(), nt, G2, 16, P->tn_part.d(), st);
+    double h1[256], h2[256];
+    STS_HIP(hipMemcpyAsync(h1, G1, 256 * 8, hipMemcpyDeviceToHost, st));
+    STS_HIP(hipMemcpyAsync(h2, G2, 256 * 8, hipMemcpyDeviceToHost, st));
+    STS_HIP(hipStreamSynchronize(st));
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) tr += h1[i + 16 * j] * h2[j + 16 * i];
+    P->fnorm = std::sqrt(std::max(tr, 0.0));
+    STS_REQUIRE(std::isfinite(P->fnorm), STS_E_INVALID, "F1 or F2 is not finite");
+    *out = P.release();
+  });
+}
+
+sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
+  return run_guarded([&] {
+    STS_REQUIRE(P != nullptr, STS_E_INVALID, "problem is NULL");
+    sts_opts o;
+    sts_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    STS_REQUIRE(o.tol > 0.0 && o.max_outer >= 1 && o.inner_rtol > 0.0 && o.inner_maxit >= 1 &&
+                    o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0,
+                STS_E_INVALID, "invalid options");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = P->stream;
+    const int p = P->p;
+    const int b2 = 2 * p;
+    if (o.restart) {
+      P->k = P->k_sol = P->blk_start = P->blk_size = 0;
+      P->tags.clear();
+      P->solved = false;
+      P->inner_K = P->inner_M = 0;
+      P->alg_bytes = 0.0;
+      P->checks = 0;
+    }
+    P->cg.profile = o.profile != 0;
+    P->cg.prof_seconds = 0.0;
+    P->cg.prof_launches = P->cg.prof_col_iters = 0;
+    ensure_capacity(P, P->k + (int64_t)b2 * (o.max_outer + 2), o.mem_budget);
+    if (!P->smallv.p) P->smallv.alloc(std::max<int64_t>(P->kcap * 16, 4096) * 8);
+    if (P->smallv.bytes < (size_t)P->kcap * 16 * 8) P->smallv.alloc(P->kcap * 16 * 8);
+    sts_status result = STS_E_NOT_CONVERGED;
+    bool breakdown = false;
+    double cheap = -1.0, truer = -1.0;
+    int outer = 0;
+    if (P->fnorm == 0.0) {
+      // zero right-hand side: U = 0
+      P->k_sol = 0;
+      P->solved = true;
+      result = STS_OK;
+      cheap = truer = 0.0;
+    } else {
+      if (P->k == 0) {
+        // start block [Mx^{-1} F1, Kx^{-1} F1]
+        int ops[kMaxCols];
+        const double* b[kMaxCols];
+        for (int c = 0; c < p; ++c) {
+          ops[c] = STS_OP_M;
+          ops[p + c] = STS_OP_K;
+          b[c] = b[p + c] = P->F1.d() + c * P->ldv;
+        }
+        run_cg_block(P, ops, b2, b, o);
+        int idx[16];
+        const int kept = append_block(P, b2, o.defl_tol, idx);
+        P->blk_start = 0;
+        P->blk_size = kept;
+        P->tags.clear();
+        for (int j = 0; j < kept; ++j) P->tags.push_back(idx[j] < p ? 0 : 1);
+        P->k = kept;
+        P->k_sol = 0;
+        STS_REQUIRE(kept > 0, STS_E_NUMERIC, "start block vanished although F is non-zero");
+      }
+      int next_check = 1;
+      int last_check_outer = -1;
+      double last_check_res = -1.0;
+      for (outer = 1; outer <= o.max_outer; ++outer) {
+        // expand with the last block
+        const int64_t bs = P->blk_start, bsz = P->blk_size;
+        int ops[kMaxCols];
+        const double* b[kMaxCols];
+        int n = 0;
+        for (int64_t j = 0; j < bsz; ++j) {
+          const int tag = P->tags[bs + j];
+          ops[n] = tag == 0 ? STS_OP_M : STS_OP_K;
+          // positive power: Mx^{-1} (Kx v); negative power: Kx^{-1} (Mx v)
+          b[n] = (tag == 0 ? P->KV.d() : P->MV.d()) + (bs + j) * P->ldv;
+          ++n;
+        }
+        std::vector<int> src_tag(n);
+        for (int j = 0; j < n; ++j) src_tag[j] = P->tags[bs + j];
+        run_cg_block(P, ops, n, b, o);
+        int idx[16];
+        const int64_t kprev = P->k;
+        const int kept = append_block(P, n, o.defl_tol, idx);
+        for (int j = 0; j < kept; ++j) P->tags.push_back(src_tag[idx[j]]);
+        P->blk_start = kprev;
+        P->blk_size = kept;
+        P->k = kprev + kept;
+        if (kept == 0) {
+          // the space is invariant under A and A^{-1}: the Galerkin solution is exact
+          breakdown = true;
+          P->k_sol = kprev;
+          cheap = reduced_solve(P, kprev, 0);
+          result = STS_OK;
+          break;
+        }
+        const bool due = o.check_every > 0 ? (outer % o.check_every == 0 || outer == o.max_outer)
+                                           : (outer >= next_check || outer == o.max_outer);
+        if (!due) continue;
+        P->k_sol = kprev;
+        cheap = reduced_solve(P, kprev, kept);
+        P->last_cheap = cheap;
+        if (cheap <= o.tol) {
+          if (!o.verify_true) {
+            result = STS_OK;
+            break;
+          }
+          truer = true_residual(P);
+          if (truer <= o.tol) {
+            result = STS_OK;
+            break;
+          }
+        }
+        // schedule the next check from the observed convergence rate
+        if (o.check_every == 0) {
+          int step = 1;
+          if (last_check_res > 0.0 && cheap > 0.0 && cheap < last_check_res && cheap > o.tol) {
+            const double rate =
+                std::pow(cheap / last_check_res, 1.0 / std::max(1, outer - last_check_outer));
+            const double need = std::log(o.tol / cheap) / std::log(rate);
+            step = std::max(1, std::min(20, (int)std::floor(0.75 * need)));
+          }
+          last_check_outer = outer;
+          last_check_res = cheap;
+          next_check = outer + step;
+        }
+      }
+      if (outer > o.max_outer) outer = o.max_outer;
+      P->solved = true;
+    }
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->outer_its = outer;
+      info->checks = P->checks;
+      info->k = P->k_sol;
+      info->inner_its_K = P->inner_K;
+      info->inner_its_M = P->inner_M;
+      info->res_cheap = cheap;
+      info->breakdown = breakdown ? 1 : 0;
+      if (truer < 0.0 && o.verify_true && P->k_sol > 0) truer = true_residual(P);
+      info->res_true = truer;
+      info->orth_err = orth_error(P);
+      info->rank = -1;
+      info->alg_bytes = P->alg_bytes;
+      info->cg_kernel_seconds = P->cg.prof_seconds;
+      info->cg_launches = P->cg.prof_launches;
+      info->cg_col_iters = P->cg.prof_col_iters;
+    }
+    STS_HIP(hipStreamSynchronize(st));
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) info->seconds = secs;
+    if (result != STS_OK)
+      throw Error{result, "max_outer reached before the residual met tol (last projected residual " +
+                              std::to_string(cheap) + ")"};
+  });
+}
+
+sts_status sts_rank(const sts_problem* P, int64_t* k) {
+  return run_guarded([&] {
+    STS_REQUIRE(P && k, STS_E_INVALID, "NULL argument");
+    *k = P->solved ? P->k_sol : 0;
+  });
+}
+
+sts_status sts_get_factors(const sts_problem* Pc, double* V, int64_t ldv, double* Y, int64_t ldy,
+                           int32_t mem, void* stream) {
+  return run_guarded([&] {
+    STS_REQUIRE(Pc != nullptr, STS_E_INVALID, "problem is NULL");
+    STS_REQUIRE(Pc->solved, STS_E_STATE, "no solution yet: call sts_solve first");
+    STS_REQUIRE(mem == STS_MEM_HOST || mem == STS_MEM_DEVICE, STS_E_INVALID, "bad mem kind");
+    sts_problem* P = const_cast<sts_problem*>(Pc);
+    const int64_t ks = P->k_sol;
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : P->stream;
+    if (st != P->stream) STS_HIP(hipStreamSynchronize(P->stream));
+    const hipMemcpyKind kind = mem == STS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (V && ks > 0) {
+      STS_REQUIRE(ldv >= P->nh, STS_E_INVALID, "ldv < Nh");
+      STS_HIP(hipMemcpy2DAsync(V, ldv * 8, P->V.p, P->ldv * 8, P->nh * 8, ks, kind, st));
+    }
+    if (Y && ks > 0) {
+      STS_REQUIRE(ldy >= ks, STS_E_INVALID, "ldy < k");
+      STS_HIP(hipMemcpy2DAsync(Y, ldy * 8, P->Y.p, P->kcap * 8, ks * 8, P->nt, kind, st));
+    }
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_true_residual(sts_problem* P, double* res) {
+  return run_guarded([&] {
+    STS_REQUIRE(P && res, STS_E_INVALID, "NULL argument");
+    STS_REQUIRE(P->solved, STS_E_STATE, "no solution yet");
+    *res = (P->fnorm == 0.0) ? 0.0 : true_residual(P);
+  });
+}
+
+sts_status sts_numerical_rank(sts_problem* P, int64_t* rank) {
+  return run_guarded([&] {
+    STS_REQUIRE(P && rank, STS_E_INVALID, "NULL argument");
+    STS_REQUIRE(P->solved, STS_E_STATE, "no solution yet");
+    *rank = numerical_rank(P);
+  });
+}
+
+void sts_destroy(sts_problem* P) {
+  if (!P) return;
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  delete P;
+}
+
+// ---------------------------------------------------------------------------
+// step-level entry points
+// ---------------------------------------------------------------------------
+
+sts_status sts_apply_op(const sts_space* space, int32_t op, const double* X, int64_t ldx,
+                        double* Y, int64_t ldy, int32_t ncols, void* stream) {
+  return run_guarded([&] {
+    validate_space(space);
+    const Grid g = make_grid(*space);
+    STS_REQUIRE(op == STS_OP_K || op == STS_OP_M, STS_E_INVALID, "bad op");
+    STS_REQUIRE(ncols >= 0 && ncols <= 16, STS_E_INVALID, "ncols out of range");
+    STS_REQUIRE(ncols == 0 || (X && Y && ldx >= g.nh && ldy >= g.nh), STS_E_INVALID,
+                "bad buffers / leading dimensions");
+    const Stencil K = make_stencil(*space, STS_OP_K), M = make_stencil(*space, STS_OP_M);
+    int ops[16];
+    for (int c = 0; c < 16; ++c) ops[c] = op;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    stencil_apply(g, K, M, ops, ncols, X, ldx, Y, ldy, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_cg(const sts_space* space, const int32_t* ops_in, const double* B, int64_t ldb,
+                  double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                  int32_t* iters, void* stream) {
+  sts_status bad = STS_OK;
+  sts_status s = run_guarded([&] {
+    validate_space(space);
+    const Grid g = make_grid(*space);
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(ops_in && B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(rtol > 0.0 && maxit >= 1, STS_E_INVALID, "bad rtol / maxit");
+    int ops[kMaxCols];
+    for (int c = 0; c < ncols; ++c) {
+      STS_REQUIRE(ops_in[c] == STS_OP_K || ops_in[c] == STS_OP_M, STS_E_INVALID, "bad op");
+      ops[c] = ops_in[c];
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    const int64_t ld = pad_ld(g.nh);
+    const int tiles = cg_tiles(g);
+    CGRunner r;
+    r.g = g;
+    r.K = make_stencil(*space, STS_OP_K);
+    r.M = make_stencil(*space, STS_OP_M);
+    r.w.x = X;
+    r.w.ld = ldx;
+    r.w.r = sc.get<double>(ld * ncols);
+    r.w.p = sc.get<double>(ld * ncols);
+    // x, r, p share one leading dimension in the kernels: stage x if needed
+    double* xs = X;
+    if (ldx != ld) {
+      xs = sc.get<double>(ld * ncols);
+      r.w.x = xs;
+    }
+    r.w.ld = ld;
+    r.w.scal = sc.get<CGScal>(2 * kMaxCols);
+    r.w.partials = sc.get<double>((size_t)2 * 2 * kMaxCols * tiles);
+    r.w.max_tiles = tiles;
+    STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&r.host_scal), sizeof(CGScal) * 2 * kMaxCols,
+                          hipHostMallocDefault));
+    STS_HIP(hipEventCreateWithFlags(&r.ev[0], hipEventDisableTiming));
+    STS_HIP(hipEventCreateWithFlags(&r.ev[1], hipEventDisableTiming));
+    struct Cleanup {
+      CGRunner& r;
+      ~Cleanup() {
+        if (r.host_scal) (void)hipHostFree(r.host_scal);
+        for (auto& e : r.ev)
+          if (e) (void)hipEventDestroy(e);
+      }
+    } cleanup{r};
+    const double* bcols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
+    CGScal out[kMaxCols];
+    r.run(ops, ncols, bcols, rtol, maxit, out, st);
+    if (xs != X) copy_cols(g.nh, ncols, xs, ld, X, ldx, st);
+    STS_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < ncols; ++c) {
+      if (iters) iters[c] = out[c].iters;
+      if (out[c].flag == 3) bad = STS_E_NUMERIC;
+      else if (out[c].flag == 2 && bad == STS_OK) bad = STS_E_NOT_CONVERGED;
+    }
+  });
+  if (s == STS_OK && bad != STS_OK) {
+    set_error(bad == STS_E_NUMERIC ? "CG breakdown" : "CG reached maxit");
+    return bad;
+  }
+  return s;
+}
+
+sts_status sts_m_orthonormalize(const sts_space* space, const double* V, const double* MV,
+                                int64_t ldv, int64_t k, double* W, double* MW, int64_t ldw,
+                                int32_t ncols, double defl_tol, int32_t* kept,
+                                int32_t* keep_idx, void* stream) {
+  return run_guarded([&] {
+    validate_space(space);
+    const Grid g = make_grid(*space);
+    STS_REQUIRE(ncols >= 1 && ncols <= 16, STS_E_INVALID, "ncols must be 1..16");
+    STS_REQUIRE(k >= 0 && (k == 0 || (V && MV && ldv >= g.nh)), STS_E_INVALID, "bad basis");
+    STS_REQUIRE(W && MW && ldw >= g.nh && kept, STS_E_INVALID, "bad block buffers");
+    STS_REQUIRE(defl_tol >= 0.0 && defl_tol < 1.0, STS_E_INVALID, "bad defl_tol");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Stencil K = make_stencil(*space, STS_OP_K), M = make_stencil(*space, STS_OP_M);
+    Scratch sc;
+    const int64_t nh = g.nh;
+    OrthScratch s;
+    s.part = sc.get<double>(gemm_tn_partial_size(nh, (int)std::max<int64_t>(k, 16)));
+    s.G = sc.get<double>(256);
+    s.ldc = std::max<int64_t>(k, 1);
+    s.C = sc.get<double>(s.ldc * 16);
+    s.norm0 = sc.get<double>(16);
+    s.Rinv = sc.get<double>(256);
+    s.info = sc.get<CholInfo>(1);
+    CholInfo hbuf;
+    s.host = &hbuf;
+    int idx[16];
+    const int nk = orthonormalize_block(g, K, M, V, MV, ldv, k, W, MW, ldw, ncols, defl_tol, s,
+                                        idx, st);
+    STS_HIP(hipStreamSynchronize(st));
+    *kept = nk;
+    if (keep_idx)
+      for (int j = 0; j < ncols; ++j) keep_idx[j] = j < nk ? idx[j] : -1;
+  });
+}
+
+sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double* C, int64_t ldc, void* stream) {
+  return run_guarded([&] {
+    STS_REQUIRE(rows >= 0 && m >= 1 && n >= 1 && n <= 16, STS_E_INVALID, "bad sizes");
+    STS_REQUIRE(A && B && C && lda >= rows && ldb >= rows && ldc >= m, STS_E_INVALID,
+                "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    double* part = sc.get<double>(gemm_tn_partial_size(std::max<int64_t>(rows, 1), m));
+    gemm_tn(rows, m, n, A, lda, B, ldb, C, ldc, part, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_basis_update(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
+                            const double* C, int64_t ldc, double* W, int64_t ldw, void* stream) {
+  return run_guarded([&] {
+    STS_REQUIRE(rows >= 0 && m >= 1 && n >= 1 && n <= 16, STS_E_INVALID, "bad sizes");
+    STS_REQUIRE(A && C && W && lda >= rows && ldc >= m && ldw >= rows, STS_E_INVALID,
+                "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    gemm_nn_sub(rows, m, n, A, lda, C, ldc, W, ldw, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_sym_eig(int64_t k, const double* A, int64_t lda, double* lam, double* Q,
+                       int64_t ldq, void* stream) {
+  return run_guarded([&] {
+    STS_REQUIRE(k >= 1 && k <= 2048, STS_E_INVALID, "k must be 1..2048");
+    STS_REQUIRE(A && lam && Q && lda >= k && ldq >= k, STS_E_INVALID, "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    EigWork w{};
+    w.a = sc.get<double>(k * k);
+    w.tau = sc.get<double>(k);
+    w.e = sc.get<double>(k);
+    w.meta = sc.get<int>(16);
+    sym_eig((int)k, A, lda, lam, Q, ldq, w, st);
+    int status = 0;
+    STS_HIP(hipMemcpyAsync(&status, w.meta, sizeof(int), hipMemcpyDeviceToHost, st));
+    STS_HIP(hipStreamSynchronize(st));
+    STS_REQUIRE(status == 0, STS_E_NUMERIC, "QL iteration did not converge");
+  });
+}
+
+sts_status sts_time_sweep(int64_t k, int64_t nt, int32_t p, const double* lam, const double* Q,
+                          int64_t ldq, const double* beta, int64_t ldb, const double* F2,
+                          int64_t ldf, const sts_bidiag* Dt, const sts_bidiag* Mt, double* Y,
+                          int64_t ldy, void* stream) {
+  return run_guarded([&] {
+    STS_REQUIRE(k >= 1 && nt >= 1 && p >= 1 && p <= 4, STS_E_INVALID, "bad sizes");
+    STS_REQUIRE(lam && Q && beta && F2 && Y && ldq >= k && ldb >= k && ldf >= nt && ldy >= k,
+                STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(Dt && Mt && Dt->diag && Mt->diag && (nt == 1 || (Dt->sub && Mt->sub)),
+                STS_E_INVALID, "bad time matrices");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    std::vector<double> tv(4 * nt, 0.0);
+    for (int64_t l = 0; l < nt; ++l) {
+      tv[l] = Dt->diag[l];
+      tv[2 * nt + l] = Mt->diag[l];
+      if (l + 1 < nt) {
+        tv[nt + l] = Dt->sub[l];
+        tv[3 * nt + l] = Mt->sub[l];
+      }
+    }
+    double* td = sc.get<double>(4 * nt);
+    STS_HIP(hipMemcpyAsync(td, tv.data(), 4 * nt * 8, hipMemcpyHostToDevice, st));
+    double* qb = sc.get<double>(k * p);
+    double* Z = sc.get<double>(k * nt);
+    double* part = sc.get<double>(gemm_tn_partial_size(k, (int)k));
+    gemm_tn(k, (int)k, p, Q, ldq, beta, ldb, qb, k, part, st);
+    time_sweep((int)k, (int)nt, p, lam, qb, k, F2, ldf, TimeOps{td, td + nt, td + 2 * nt, td + 3 * nt},
+               Z, k, st);
+    gemm_nn((int)k, (int)nt, (int)k, Q, ldq, Z, k, Y, ldy, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+}  // extern "C"

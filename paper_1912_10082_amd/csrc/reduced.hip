@@ -1,0 +1,524 @@
+// The reduced (projected) problem of the Galerkin method.
+//
+// With an Mx-orthonormal basis V the reduced spatial pencil is (Km, I) up to
+// rounding, Km = V^T Kx V.  Its eigendecomposition Km Q = Q diag(lam) turns
+// the reduced Sylvester equation Km Y Mt^T + Y Dt^T = beta F2^T into k
+// independent lower-bidiagonal recurrences in time, one per eigencomponent:
+//   (Dt + lam_i Mt) z_i = (Q^T beta F2^T)[i, :],   Y = Q Z.
+//
+// sym_eig: one work-group reduces Km to tridiagonal form with Householder
+// reflectors, accumulates them into Q, then runs implicit-shift QL on the
+// tridiagonal.  The QL scalar recurrence is inherently sequential; it runs in
+// one lane of wave 0 and publishes each sweep's plane rotations in LDS while
+// the other 15 waves apply the previous sweep's rotations to the rows of Q.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sts_internal.h"
+
+namespace sts {
+
+namespace {
+
+constexpr int kEigThreads = 1024;
+constexpr int kEigMaxK = 2048;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sum over 1024 threads (16 waves), fixed order; result broadcast.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < kEigThreads / 64; ++i) t += red[i];
+  return t;
+}
+
+struct EigArgs {
+  int k;
+  const double* A;
+  int64_t lda;
+  double* lam;
+  double* Q;
+  int64_t ldq;
+  double* a;      // k x k working copy
+  double* tau;
+  double* e;
+  int* status;
+};
+
+__global__ __launch_bounds__(kEigThreads) void sym_eig_kernel(EigArgs g) {
+  __shared__ double v[kEigMaxK];
+  __shared__ double w[kEigMaxK];
+  __shared__ double red[kEigThreads / 64];
+  __shared__ double rc[2][kEigMaxK];     // rotation cosines (double-buffered sweeps)
+  __shared__ double rs[2][kEigMaxK];     // rotation sines
+  __shared__ int sweep_hi[2], sweep_cnt[2];
+  __shared__ int done_flag;
+
+  const int k = g.k;
+  const int tid = threadIdx.x;
+  double* a = g.a;
+  const int64_t lda = k;
+
+  // working copy (symmetrised)
+  for (int64_t idx = tid; idx < (int64_t)k * k; idx += kEigThreads) {
+    const int i = idx % k, j = idx / k;
+    a[idx] = 0.5 * (g.A[i + j * g.lda] + g.A[j + i * g.lda]);
+  }
+  __syncthreads();
+
+  // ---- Householder tridiagonalisation (lower), reflectors kept in a ----
+  for (int j = 0; j + 2 < k; ++j) {
+    const int n2 = k - j - 1;                   // trailing size
+    double* col = a + (j + 1) + (int64_t)j * lda;
+    double sig = 0.0;
+    for (int i = 1 + tid; i < n2; i += kEigThreads) sig += col[i] * col[i];
+    sig = block_sum(sig, red);
+    const double alpha = col[0];
+    double tau = 0.0, beta = alpha, scale = 0.0;
+    if (sig > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sig);
+      beta = alpha <= 0.0 ? nrm : -nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    for (int i = tid; i < n2; i += kEigThreads) v[i] = (i == 0) ? 1.0 : col[i] * scale;
+    __syncthreads();
+    if (tid == 0) {
+      g.tau[j] = tau;
+      g.e[j] = beta;
+    }
+    if (tau != 0.0) {
+      // p = tau * A22 v  (A22 symmetric, full storage), four partial sums per row
+      double* A22 = a + (j + 1) + (int64_t)(j + 1) * lda;
+      for (int base = 0; base < n2; base += kEigThreads / 4) {
+        const int i = base + (tid & (kEigThreads / 4 - 1));
+        const int part = tid / (kEigThreads / 4);
+        double s = 0.0;
+        if (i < n2) {
+          const int c0 = (n2 * part) / 4, c1 = (n2 * (part + 1)) / 4;
+          for (int c = c0; c < c1; ++c) s += A22[i + (int64_t)c * lda] * v[c];
+        }
+        __syncthreads();
+        rc[0][tid] = s;
+        __syncthreads();
+        if (part == 0 && i < n2) {
+          const int q = tid & (kEigThreads / 4 - 1);
+          w[i] = tau * ((rc[0][q] + rc[0][q + 256]) + (rc[0][q + 512] + rc[0][q + 768]));
+        }
+        __syncthreads();
+      }
+      // w <- p - (tau/2)(p.v) v
+      double pv = 0.0;
+      for (int i = tid; i < n2; i += kEigThreads) pv += w[i] * v[i];
+      pv = block_sum(pv, red);
+      const double kk = -0.5 * tau * pv;
+      __syncthreads();
+      for (int i = tid; i < n2; i += kEigThreads) w[i] += kk * v[i];
+      __syncthreads();
+      // A22 -= v w^T + w v^T
+      for (int64_t idx = tid; idx < (int64_t)n2 * n2; idx += kEigThreads) {
+        const int i = idx % n2, c = idx / n2;
+        A22[i + (int64_t)c * lda] -= v[i] * w[c] + w[i] * v[c];
+      }
+    }
+    // keep the reflector (v[0] = 1 implicit) below the diagonal
+    for (int i = 1 + tid; i < n2; i += kEigThreads) col[i] = v[i];
+    __syncthreads();
+  }
+  // diagonal and last sub-diagonal
+  for (int i = tid; i < k; i += kEigThreads) g.lam[i] = a[i + (int64_t)i * lda];
+  if (tid == 0) {
+    if (k >= 2) g.e[k - 2] = a[(k - 1) + (int64_t)(k - 2) * lda];
+    g.e[k - 1] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- accumulate Q = H_0 H_1 ... H_{k-3} (backward) ----
+  double* Q = g.Q;
+  const int64_t ldq = g.ldq;
+  for (int64_t idx = tid; idx < (int64_t)k * k; idx += kEigThreads) {
+    const int i = idx % k, j = idx / k;
+    Q[i + j * ldq] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = k - 3; j >= 0; --j) {
+    const double tau = g.tau[j];
+    if (tau == 0.0) continue;
+    const int n2 = k - j - 1;
+    const double* col = a + (j + 1) + (int64_t)j * lda;
+    for (int i = tid; i < n2; i += kEigThreads) v[i] = (i == 0) ? 1.0 : col[i];
+    __syncthreads();
+    double* Q22 = Q + (j + 1) + (int64_t)(j + 1) * ldq;
+    // u_c = tau * sum_i v_i Q22[i, c]  (one wave per column)
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int c = wv; c < n2; c += kEigThreads / 64) {
+      double s = 0.0;
+      for (int i = lane; i < n2; i += 64) s += v[i] * Q22[i + (int64_t)c * ldq];
+      s = wave_sum(s);
+      if (lane == 0) w[c] = tau * s;
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < (int64_t)n2 * n2; idx += kEigThreads) {
+      const int i = idx % n2, c = idx / n2;
+      Q22[i + (int64_t)c * ldq] -= v[i] * w[c];
+    }
+    __syncthreads();
+  }
+
+  // ---- implicit QL on (d = lam, e), rotations applied to Q's columns ----
+  // d, e in LDS (v, w reused); wave 0 lane 0 produces sweeps, waves 1.. apply.
+  double* d = v;
+  double* e = w;
+  for (int i = tid; i < k; i += kEigThreads) {
+    d[i] = g.lam[i];
+    e[i] = g.e[i];
+  }
+  if (tid == 0) {
+    done_flag = 0;
+    sweep_cnt[0] = sweep_cnt[1] = 0;
+  }
+  __syncthreads();
+  const int wv = tid >> 6;
+  int l = 0, iter = 0, failed = 0;
+  int buf = 0;
+  const double eps = 1.1102230246251565e-16;
+  for (;;) {
+    if (wv == 0) {
+      if (tid == 0) {
+        // find the next sweep: advance l past converged eigenvalues
+        int produced = 0;
+        while (!produced && l < k) {
+          int m = l;
+          for (; m < k - 1; ++m) {
+            const double dd = fabs(d[m]) + fabs(d[m + 1]);
+            if (fabs(e[m]) <= eps * dd) break;
+          }
+          if (m == l) {
+            ++l;
+            iter = 0;
+            continue;
+          }
+          if (++iter > 60) {
+            failed = 1;
+            l = k;
+            break;
+          }
+          double gg = (d[l + 1] - d[l]) / (2.0 * e[l]);
+          double r = sqrt(gg * gg + 1.0);
+          gg = d[m] - d[l] + e[l] / (gg + (gg >= 0.0 ? r : -r));
+          double s = 1.0, c = 1.0, p = 0.0;
+          int cnt = 0;
+          bool zero_r = false;
+          for (int i = m - 1; i >= l; --i) {
+            const double f = s * e[i], b = c * e[i];
+            r = sqrt(f * f + gg * gg);
+            e[i + 1] = r;
+            if (r == 0.0) {
+              d[i + 1] -= p;
+              e[m] = 0.0;
+              zero_r = true;
+              break;
+            }
+            const double rinv = 1.0 / r;
+            s = f * rinv;
+            c = gg * rinv;
+            gg = d[i + 1] - p;
+            r = (d[i] - gg) * s + 2.0 * c * b;
+            p = s * r;
+            d[i + 1] = gg + p;
+            gg = c * r - b;
+            rc[buf][cnt] = c;
+            rs[buf][cnt] = s;
+            ++cnt;
+          }
+          if (!zero_r) {
+            d[l] -= p;
+            e[l] = gg;
+            e[m] = 0.0;
+          }
+          sweep_hi[buf] = m - 1;
+          sweep_cnt[buf] = cnt;
+          produced = 1;
+        }
+        if (!produced) {
+          sweep_cnt[buf] = 0;
+          done_flag = 1;
+        }
+      }
+    } else {
+      // apply the sweep in the other buffer to the rows of Q
+      const int ob = buf ^ 1;
+      const int cnt = sweep_cnt[ob];
+      if (cnt > 0) {
+        const int hi = sweep_hi[ob];
+        for (int row = tid - 64; row < k; row += kEigThreads - 64) {
+          double* qr = Q + row;
+          double cur = qr[(int64_t)(hi + 1) * ldq];
+          int i = hi;
+          int t = 0;
+          while (t < cnt) {
+            // batch of up to 8 independent loads ahead of the rotations
+            double nx[8];
+            const int nb = min(8, cnt - t);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (u < nb) nx[u] = qr[(int64_t)(i - u) * ldq];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (u < nb) {
+                const double c = rc[ob][t + u], s = rs[ob][t + u];
+                const double av = nx[u];
+                qr[(int64_t)(i - u + 1) * ldq] = s * av + c * cur;
+                cur = c * av - s * cur;
+              }
+            i -= nb;
+            t += nb;
+          }
+          qr[(int64_t)(i + 1) * ldq] = cur;
+        }
+      }
+    }
+    __syncthreads();
+    const int finished = done_flag;
+    if (tid == 0) {
+      sweep_cnt[buf ^ 1] = 0;     // consumed
+    }
+    __syncthreads();
+    if (finished) break;
+    buf ^= 1;
+  }
+  for (int i = tid; i < k; i += kEigThreads) g.lam[i] = d[i];
+  if (tid == 0) *g.status = failed ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// time sweep
+// ---------------------------------------------------------------------------
+struct SweepArgs {
+  int k, nt, p;
+  const double* lam;
+  const double* qb;
+  int64_t ldqb;
+  const double* F2;
+  int64_t ldf;
+  TimeOps t;
+  double* Z;
+  int64_t ldz;
+};
+
+constexpr int kSweepChunk = 256;
+
+__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+  __shared__ double f2[4][kSweepChunk];
+  __shared__ double dd[kSweepChunk], de[kSweepChunk], dm[kSweepChunk], dn[kSweepChunk];
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const bool act = i < a.k;
+  const double lam = act ? a.lam[i] : 0.0;
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = 0; p < a.p; ++p) q[p] = act ? a.qb[i + p * a.ldqb] : 0.0;
+  double z = 0.0;
+  for (int l0 = 0; l0 < a.nt; l0 += kSweepChunk) {
+    const int len = min(kSweepChunk, a.nt - l0);
+    __syncthreads();
+    for (int u = threadIdx.x; u < len; u += 64) {
+      const int l = l0 + u;
+      for (int p = 0; p < a.p; ++p) f2[p][u] = a.F2[l + p * a.ldf];
+      dd[u] = a.t.d[l];
+      dm[u] = a.t.m[l];
+      de[u] = l > 0 ? a.t.e[l - 1] : 0.0;
+      dn[u] = l > 0 ? a.t.n[l - 1] : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      for (int u = 0; u < len; ++u) {
+        double gl = 0.0;
+        for (int p = 0; p < a.p; ++p) gl += q[p] * f2[p][u];
+        z = (gl - (de[u] + lam * dn[u]) * z) / (dd[u] + lam * dm[u]);
+        a.Z[i + (int64_t)(l0 + u) * a.ldz] = z;
+      }
+    }
+  }
+}
+
+// out (nt x k, ldo) = scale * T A^T for A (k x nt) and lower-bidiagonal T:
+// out[l, i] = scale (td[l] A[i, l] + ts[l-1] A[i, l-1]).
+__global__ void bidiag_right_kernel(int k, int nt, const double* A, int64_t lda, const double* td,
+                                    const double* ts, double scale, double* out, int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)k * nt) return;
+  const int l = idx % nt, i = idx / nt;
+  double v = td[l] * A[i + (int64_t)l * lda];
+  if (l > 0) v += ts[l - 1] * A[i + (int64_t)(l - 1) * lda];
+  out[l + (int64_t)i * ldo] = scale * v;
+}
+
+__global__ void transpose_kernel(int m, int n, const double* A, int64_t lda, double* B,
+                                 int64_t ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int j = idx % n, i = idx / n;
+  B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
+}
+
+__global__ void chol_lower_kernel(int b, const double* G, int64_t ldg, double* L, int64_t ldl,
+                                  int* ok) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int good = 1;
+  for (int j = 0; j < b; ++j)
+    for (int i = 0; i < b; ++i) L[i + j * ldl] = 0.0;
+  for (int j = 0; j < b; ++j) {
+    double d = G[j + j * ldg];
+    for (int q = 0; q < j; ++q) d -= L[j + q * ldl] * L[j + q * ldl];
+    if (!(d > 0.0)) {
+      good = 0;
+      d = 0.0;
+    }
+    const double ljj = sqrt(d);
+    L[j + j * ldl] = ljj;
+    for (int i = j + 1; i < b; ++i) {
+      double s = G[i + j * ldg];
+      for (int q = 0; q < j; ++q) s -= L[i + q * ldl] * L[j + q * ldl];
+      L[i + j * ldl] = ljj > 0.0 ? s / ljj : 0.0;
+    }
+  }
+  *ok = good;
+}
+
+// dst[c, r] = src[r, c] for r < m, c < n (dst is n x m, ldd)
+__global__ void mirror_kernel(int m, int n, const double* src, int64_t lds, double* dst,
+                              int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int r = idx % m, c = idx / m;
+  dst[c + (int64_t)r * ldd] = src[r + (int64_t)c * lds];
+}
+
+// ||L^T (m_l T1[:, l] + n_{l-1} T1[:, l-1])||^2 summed over l.
+__global__ __launch_bounds__(256) void cheap_res_kernel(int b, int nt, const double* T1,
+                                                        int64_t ldt, const double* L, int64_t ldl,
+                                                        const double* md, const double* ms,
+                                                        double* partial, unsigned* counter,
+                                                        double* out) {
+  __shared__ double red[4];
+  __shared__ int last;
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (l < nt) {
+    double vv[16];
+    for (int r = 0; r < b; ++r) {
+      double x = md[l] * T1[r + (int64_t)l * ldt];
+      if (l > 0) x += ms[l - 1] * T1[r + (int64_t)(l - 1) * ldt];
+      vv[r] = x;
+    }
+    for (int c = 0; c < b; ++c) {   // (L^T v)_c = sum_{r >= c} L[r, c] v_r
+      double u = 0.0;
+      for (int r = c; r < b; ++r) u += L[r + c * ldl] * vv[r];
+      s += u * u;
+    }
+  }
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double t = 0.0;
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += 256) t += partial[q];
+  t = wave_sum(t);
+  __syncthreads();
+  if (lane == 0) red[wv] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *out = (red[0] + red[1]) + (red[2] + red[3]);
+    atomicExch(counter, 0u);
+  }
+}
+
+}  // namespace
+
+void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_t ldq,
+             const EigWork& w, hipStream_t st) {
+  STS_REQUIRE(k >= 1 && k <= kEigMaxK, STS_E_INVALID, "sym_eig: order out of range");
+  EigArgs g{};
+  g.k = k;
+  g.A = A;
+  g.lda = lda;
+  g.lam = lam;
+  g.Q = Q;
+  g.ldq = ldq;
+  g.a = w.a;
+  g.tau = w.tau;
+  g.e = w.e;
+  g.status = w.meta;
+  sym_eig_kernel<<<1, kEigThreads, 0, st>>>(g);
+  STS_HIP(hipGetLastError());
+}
+
+void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64_t ldqb,
+                const double* F2, int64_t ldf, const TimeOps& t, double* Z, int64_t ldz,
+                hipStream_t st) {
+  if (k <= 0 || nt <= 0) return;
+  STS_REQUIRE(p >= 1 && p <= 4, STS_E_INVALID, "time_sweep: 1 <= p <= 4");
+  SweepArgs a{k, nt, p, lam, qb, ldqb, F2, ldf, t, Z, ldz};
+  sweep_kernel<<<(k + 63) / 64, 64, 0, st>>>(a);
+  STS_HIP(hipGetLastError());
+}
+
+void bidiag_right(int k, int nt, const double* A, int64_t lda, const double* td, const double* ts,
+                  double scale, double* out, int64_t ldo, hipStream_t st) {
+  const int64_t n = (int64_t)k * nt;
+  if (n <= 0) return;
+  bidiag_right_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(k, nt, A, lda, td, ts, scale,
+                                                                    out, ldo);
+  STS_HIP(hipGetLastError());
+}
+
+void transpose(int m, int n, const double* A, int64_t lda, double* B, int64_t ldb,
+               hipStream_t st) {
+  const int64_t cnt = (int64_t)m * n;
+  if (cnt <= 0) return;
+  transpose_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(m, n, A, lda, B, ldb);
+  STS_HIP(hipGetLastError());
+}
+
+void chol_lower(int b, const double* G, int64_t ldg, double* L, int64_t ldl, int* ok,
+                hipStream_t st) {
+  chol_lower_kernel<<<1, 64, 0, st>>>(b, G, ldg, L, ldl, ok);
+  STS_HIP(hipGetLastError());
+}
+
+void mirror(int m, int n, const double* src, int64_t lds, double* dst, int64_t ldd,
+            hipStream_t st) {
+  const int64_t cnt = (int64_t)m * n;
+  if (cnt <= 0) return;
+  mirror_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(m, n, src, lds, dst, ldd);
+  STS_HIP(hipGetLastError());
+}
+
+void cheap_residual(int b, int nt, const double* T1, int64_t ldt, const double* L, int64_t ldl,
+                    const double* md, const double* ms, double* out, double* partial,
+                    unsigned* counter, hipStream_t st) {
+  STS_REQUIRE(b >= 1 && b <= 16, STS_E_INVALID, "cheap_residual: 1 <= b <= 16");
+  const int blocks = (nt + 255) / 256;
+  cheap_res_kernel<<<blocks, 256, 0, st>>>(b, nt, T1, ldt, L, ldl, md, ms, partial, counter, out);
+  STS_HIP(hipGetLastError());
+}
+
+}  // namespace sts

@@ -1,0 +1,559 @@
+// Matrix-free spatial operators and the inner conjugate-gradient solver.
+//
+// Kx and Mx of the P1 / Q1 discretisations on uniform grids are constant-
+// coefficient stencils (Sec. 3, spatial matrices), so "SpMM" here streams the
+// vectors and never reads a matrix.
+//
+// The CG iteration is a single-reduction variant: with w = A r kept implicit,
+//   beta_i  = gamma_i / gamma_{i-1},
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   gamma_i = (r_i, r_i), delta_i = (A r_i, r_i),
+// where the denominator equals (p_i, A p_i) because r_i is orthogonal to
+// r_{i-1} and (r_i, A p_{i-1}) = -gamma_i / alpha_{i-1}.  One launch performs
+//   p <- r + beta p;  s = A p;  x <- x + alpha p;  r <- r - alpha s;
+//   partial sums of gamma' = (r, r) and delta' = (A r, r)
+// for a tile: r and p are staged with a two-point halo in LDS, p and then
+// r - alpha A p are recomputed on the halo, so neither s nor A r is stored.
+// Per grid point and column a launch reads r, p, x and writes them back
+// (48 bytes).
+//
+// Reduction without a serial tail: every work-group of launch k first sums
+// the per-tile partials written by launch k-1 (in one fixed order, so all
+// groups obtain bitwise identical scalars) while its own tile loads are in
+// flight, derives alpha and beta, and work-group 0 records the new state.
+// State and partials are double-buffered by launch parity, so no fence,
+// atomic or grid barrier is needed: the kernel boundary orders them.
+#include <hip/hip_runtime.h>
+
+#include "sts_internal.h"
+
+namespace sts {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int DIM>
+struct TileShape;
+template <>
+struct TileShape<1> { static constexpr int X = 1024, Y = 1, Z = 1; };
+template <>
+struct TileShape<2> { static constexpr int X = 64, Y = 16, Z = 1; };
+template <>
+struct TileShape<3> { static constexpr int X = 32, Y = 8, Z = 4; };
+
+struct Coefs {
+  double k[27];
+  double m[27];
+};
+
+struct IterArgs {
+  int nx, ny, nz;
+  int ntx, nty, ntz;      // tiles per direction
+  int ncols;
+  int parity;             // launch index & 1
+  int ops[kMaxCols];
+  double* x;
+  double* r;
+  double* p;
+  int64_t ld;
+  CGScal* scal;           // 2 slots of kMaxCols
+  double* partials;       // 2 slots of kMaxCols * max_tiles * 2
+  int max_tiles;
+  Coefs cf;
+};
+
+struct SetupArgs {
+  IterArgs it;
+  const double* b[kMaxCols];
+};
+
+// Work items lin = tile * ncols + column.  Block ids are handed to the 8 XCDs
+// round-robin; the remap gives each XCD one contiguous range of work items,
+// i.e. a contiguous band of tiles for every column, so halo reads mostly hit
+// the XCD's own L2 and the XCDs stay balanced when some columns have stopped.
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int q = n >> 3, rem = n & 7;
+  const int x = bid & 7, j = bid >> 3;
+  return x * q + min(x, rem) + j;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+template <int DIM>
+__device__ __forceinline__ void tile_origin(const IterArgs& a, int t, int& x0, int& y0, int& z0) {
+  using T = TileShape<DIM>;
+  const int tx = t % a.ntx;
+  const int rest = t / a.ntx;
+  x0 = tx * T::X;
+  y0 = (rest % a.nty) * T::Y;
+  z0 = (rest / a.nty) * T::Z;
+}
+
+// Apply a stencil at LDS point (ix, iy, iz) of an array laid out RX x RY x RZ.
+template <int DIM, int RX, int RY>
+__device__ __forceinline__ double apply_lds(const double* c, const double* s, int ix, int iy,
+                                            int iz) {
+  double acc = 0.0;
+  const int zlo = DIM >= 3 ? -1 : 0, zhi = DIM >= 3 ? 1 : 0;
+  const int ylo = DIM >= 2 ? -1 : 0, yhi = DIM >= 2 ? 1 : 0;
+#pragma unroll
+  for (int dz = zlo; dz <= zhi; ++dz)
+#pragma unroll
+    for (int dy = ylo; dy <= yhi; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const double cc = c[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
+        if (cc != 0.0) acc += cc * s[((iz + dz) * RY + (iy + dy)) * RX + (ix + dx)];
+      }
+  return acc;
+}
+
+// Sum of (g, d) over the block in a fixed order; valid in thread 0.
+__device__ __forceinline__ void block_sum2(double& g, double& d, double* red) {
+  g = wave_sum(g);
+  d = wave_sum(d);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[2 * wv] = g;
+    red[2 * wv + 1] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    g = (red[0] + red[2]) + (red[4] + red[6]);
+    d = (red[1] + red[3]) + (red[5] + red[7]);
+  }
+}
+
+// Reduce the previous launch's partials of every active column and take the
+// CG decisions.  Results in shared arrays; work-group 0 also records them.
+__device__ void step_scalars(const IterArgs& a, int ntiles, bool writer, double (*red)[4],
+                             double* s_alpha, double* s_beta, int* s_go) {
+  const CGScal* prev = a.scal + (a.parity ^ 1) * kMaxCols;
+  CGScal* next = a.scal + a.parity * kMaxCols;
+  const double* pin = a.partials + (size_t)(a.parity ^ 1) * kMaxCols * a.max_tiles * 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = 0; c < a.ncols; ++c) {
+    double g = 0.0, d = 0.0;
+    if (prev[c].active) {
+      const double* pp = pin + (size_t)c * a.max_tiles * 2;
+      for (int t = threadIdx.x; t < ntiles; t += kThreads) {
+        g += pp[2 * t];
+        d += pp[2 * t + 1];
+      }
+    }
+    g = wave_sum(g);
+    d = wave_sum(d);
+    if (lane == 0) {
+      red[2 * c][wv] = g;
+      red[2 * c + 1][wv] = d;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < a.ncols; ++c) {
+      CGScal s = prev[c];
+      int go = 0;
+      double al = 0.0, be = 0.0;
+      if (s.active) {
+        const double g = (red[2 * c][0] + red[2 * c][1]) + (red[2 * c][2] + red[2 * c][3]);
+        const double d = (red[2 * c + 1][0] + red[2 * c + 1][1]) +
+                         (red[2 * c + 1][2] + red[2 * c + 1][3]);
+        if (!finite(g) || !finite(d)) {
+          s.active = 0;
+          s.flag = 3;
+        } else if (s.iters == 0) {
+          s.gamma0 = g;
+          if (g == 0.0) {
+            s.active = 0;
+            s.flag = 1;
+          } else if (!(d > 0.0)) {
+            s.active = 0;
+            s.flag = 3;
+          } else {
+            al = g / d;
+            go = 1;
+          }
+        } else if (g <= s.rtol2 * s.gamma0) {
+          s.active = 0;
+          s.flag = 1;
+        } else if (s.iters >= s.maxit) {
+          s.active = 0;
+          s.flag = 2;
+        } else {
+          be = g / s.gamma;
+          const double den = d - be * g / s.alpha;
+          if (!(den > 0.0)) {
+            s.active = 0;
+            s.flag = 3;
+          } else {
+            al = g / den;
+            go = 1;
+          }
+        }
+        s.gamma = g;
+        if (go) {
+          s.alpha = al;
+          s.iters += 1;
+        }
+      }
+      s_go[c] = go;
+      s_alpha[c] = al;
+      s_beta[c] = be;
+      if (writer) next[c] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void cg_iter_kernel(IterArgs a) {
+  using T = TileShape<DIM>;
+  constexpr int H = 2;
+  constexpr int RX = T::X + 2 * H;
+  constexpr int RY = DIM >= 2 ? T::Y + 2 * H : 1;
+  constexpr int RZ = DIM >= 3 ? T::Z + 2 * H : 1;
+  constexpr int NR = RX * RY * RZ;
+  constexpr int LR = (NR + kThreads - 1) / kThreads;
+  constexpr int SX = T::X + 2, SY = DIM >= 2 ? T::Y + 2 : 1, SZ = DIM >= 3 ? T::Z + 2 : 1;
+  constexpr int NS = SX * SY * SZ;
+  constexpr int NI = T::X * T::Y * T::Z;
+  constexpr int LI = (NI + kThreads - 1) / kThreads;
+  constexpr int OY = DIM >= 2 ? 1 : 0, OZ = DIM >= 3 ? 1 : 0;   // S-region offset in R
+  constexpr int IY = DIM >= 2 ? 2 : 0, IZ = DIM >= 3 ? 2 : 0;   // interior offset in R
+
+  __shared__ double rs[NR];
+  __shared__ double ps[NR];
+  __shared__ double red[2 * kMaxCols][4];
+  __shared__ double s_alpha[kMaxCols], s_beta[kMaxCols];
+  __shared__ int s_go[kMaxCols];
+
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int lin = xcd_remap(blockIdx.x, a.ncols * ntiles);
+  const int t = lin / a.ncols, c = lin % a.ncols;
+  const bool writer = blockIdx.x == 0;
+  const bool mine = a.scal[(a.parity ^ 1) * kMaxCols + c].active != 0;
+  if (!mine && !writer) return;
+
+  int x0, y0, z0;
+  tile_origin<DIM>(a, t, x0, y0, z0);
+  double* xg = a.x + (size_t)c * a.ld;
+  double* rg = a.r + (size_t)c * a.ld;
+  double* pg = a.p + (size_t)c * a.ld;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t sxy = (size_t)nx * ny;
+
+  // issue every global load of the tile before waiting on the scalars
+  double rr[LR], pv[LR], xv[LI];
+  if (mine) {
+#pragma unroll
+    for (int u = 0; u < LR; ++u) {
+      const int i = threadIdx.x + u * kThreads;
+      rr[u] = 0.0;
+      pv[u] = 0.0;
+      if (i < NR) {
+        const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+        const int gx = x0 - H + lx;
+        const int gy = DIM >= 2 ? y0 - H + ly : 0;
+        const int gz = DIM >= 3 ? z0 - H + lz : 0;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+          const size_t gi = (size_t)gz * sxy + (size_t)gy * nx + gx;
+          rr[u] = rg[gi];
+          pv[u] = pg[gi];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < LI; ++u) {
+      const int i = threadIdx.x + u * kThreads;
+      xv[u] = 0.0;
+      if (i < NI) {
+        const int gx = x0 + i % T::X, gy = y0 + (i / T::X) % T::Y, gz = z0 + i / (T::X * T::Y);
+        if (gx < nx && gy < ny && gz < nz) xv[u] = xg[(size_t)gz * sxy + (size_t)gy * nx + gx];
+      }
+    }
+  }
+
+  step_scalars(a, ntiles, writer, red, s_alpha, s_beta, s_go);
+  if (!mine || !s_go[c]) return;
+  const double alpha = s_alpha[c];
+  const double beta = s_beta[c];
+  const double* cf = a.ops[c] ? a.cf.m : a.cf.k;
+
+  // stage 1: r and p <- r + beta p on the tile plus a two-point halo
+#pragma unroll
+  for (int u = 0; u < LR; ++u) {
+    const int i = threadIdx.x + u * kThreads;
+    if (i < NR) {
+      rs[i] = rr[u];
+      ps[i] = rr[u] + beta * pv[u];
+    }
+  }
+  __syncthreads();
+
+  // stage 2: on the tile plus a one-point halo, r <- r - alpha A p (zero outside)
+  for (int i = threadIdx.x; i < NS; i += kThreads) {
+    const int sx = i % SX, sy = (i / SX) % SY, sz = i / (SX * SY);
+    const int ix = sx + 1, iy = sy + OY, iz = sz + OZ;
+    const int gx = x0 - 1 + sx;
+    const int gy = DIM >= 2 ? y0 - 1 + sy : 0;
+    const int gz = DIM >= 3 ? z0 - 1 + sz : 0;
+    const double s = apply_lds<DIM, RX, RY>(cf, ps, ix, iy, iz);
+    const int q = (iz * RY + iy) * RX + ix;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    rs[q] = in ? rs[q] - alpha * s : 0.0;
+  }
+  __syncthreads();
+
+  // stage 3: interior -- gamma', delta' partials; write x, r, p
+  double gsum = 0.0, dsum = 0.0;
+#pragma unroll
+  for (int u = 0; u < LI; ++u) {
+    const int i = threadIdx.x + u * kThreads;
+    if (i < NI) {
+      const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
+      const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
+      if (gx < nx && gy < ny && gz < nz) {
+        const int ix = ux + 2, iy = uy + IY, iz = uz + IZ;
+        const int q = (iz * RY + iy) * RX + ix;
+        const double w = apply_lds<DIM, RX, RY>(cf, rs, ix, iy, iz);
+        const double rn = rs[q];
+        const double pn = ps[q];
+        gsum += rn * rn;
+        dsum += w * rn;
+        const size_t gi = (size_t)gz * sxy + (size_t)gy * nx + gx;
+        xg[gi] = xv[u] + alpha * pn;
+        rg[gi] = rn;
+        pg[gi] = pn;
+      }
+    }
+  }
+  __syncthreads();   // red[] reuse
+  block_sum2(gsum, dsum, &red[0][0]);
+  if (threadIdx.x == 0) {
+    double* po = a.partials + ((size_t)a.parity * kMaxCols * a.max_tiles + (size_t)c * a.max_tiles +
+                               t) * 2;
+    po[0] = gsum;
+    po[1] = dsum;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void cg_setup_kernel(SetupArgs sa) {
+  using T = TileShape<DIM>;
+  const IterArgs& a = sa.it;
+  constexpr int H = 1;
+  constexpr int RX = T::X + 2 * H;
+  constexpr int RY = DIM >= 2 ? T::Y + 2 * H : 1;
+  constexpr int RZ = DIM >= 3 ? T::Z + 2 * H : 1;
+  constexpr int NR = RX * RY * RZ;
+  constexpr int NI = T::X * T::Y * T::Z;
+  constexpr int IY = DIM >= 2 ? 1 : 0, IZ = DIM >= 3 ? 1 : 0;
+
+  __shared__ double bs[NR];
+  __shared__ double red[8];
+
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int lin = xcd_remap(blockIdx.x, a.ncols * ntiles);
+  const int t = lin / a.ncols, c = lin % a.ncols;
+  if (!a.scal[c].active) return;     // the host wrote the initial state to slot 0
+  int x0, y0, z0;
+  tile_origin<DIM>(a, t, x0, y0, z0);
+  const double* cf = a.ops[c] ? a.cf.m : a.cf.k;
+  const double* bg = sa.b[c];
+  double* xg = a.x + (size_t)c * a.ld;
+  double* rg = a.r + (size_t)c * a.ld;
+  double* pg = a.p + (size_t)c * a.ld;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t sxy = (size_t)nx * ny;
+
+  for (int i = threadIdx.x; i < NR; i += kThreads) {
+    const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+    const int gx = x0 - H + lx;
+    const int gy = DIM >= 2 ? y0 - H + ly : 0;
+    const int gz = DIM >= 3 ? z0 - H + lz : 0;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+      v = bg[(size_t)gz * sxy + (size_t)gy * nx + gx];
+    bs[i] = v;
+  }
+  __syncthreads();
+  double gsum = 0.0, dsum = 0.0;
+  for (int i = threadIdx.x; i < NI; i += kThreads) {
+    const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
+    const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
+    if (gx < nx && gy < ny && gz < nz) {
+      const int ix = ux + 1, iy = uy + IY, iz = uz + IZ;
+      const double bv = bs[(iz * RY + iy) * RX + ix];
+      const double w = apply_lds<DIM, RX, RY>(cf, bs, ix, iy, iz);
+      gsum += bv * bv;
+      dsum += w * bv;
+      const size_t gi = (size_t)gz * sxy + (size_t)gy * nx + gx;
+      xg[gi] = 0.0;
+      rg[gi] = bv;
+      pg[gi] = 0.0;
+    }
+  }
+  block_sum2(gsum, dsum, red);
+  if (threadIdx.x == 0) {
+    double* po = a.partials + ((size_t)c * a.max_tiles + t) * 2;   // slot 0
+    po[0] = gsum;
+    po[1] = dsum;
+  }
+}
+
+struct ApplyArgs {
+  int nx, ny, nz, ntx, nty, ntz, ncols;
+  int ops[16];
+  const double* X;
+  int64_t ldx;
+  double* Y;
+  int64_t ldy;
+  Coefs cf;
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
+  using T = TileShape<DIM>;
+  constexpr int H = 1;
+  constexpr int RX = T::X + 2 * H;
+  constexpr int RY = DIM >= 2 ? T::Y + 2 * H : 1;
+  constexpr int RZ = DIM >= 3 ? T::Z + 2 * H : 1;
+  constexpr int NR = RX * RY * RZ;
+  constexpr int NI = T::X * T::Y * T::Z;
+  constexpr int IY = DIM >= 2 ? 1 : 0, IZ = DIM >= 3 ? 1 : 0;
+  __shared__ double xs[NR];
+
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int lin = xcd_remap(blockIdx.x, ntiles * a.ncols);
+  const int t = lin / a.ncols, c = lin % a.ncols;
+  const int tx = t % a.ntx, ty = (t / a.ntx) % a.nty, tz = t / (a.ntx * a.nty);
+  const int x0 = tx * T::X, y0 = ty * T::Y, z0 = tz * T::Z;
+  const double* cf = a.ops[c] ? a.cf.m : a.cf.k;
+  const double* xg = a.X + (size_t)c * a.ldx;
+  double* yg = a.Y + (size_t)c * a.ldy;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t sxy = (size_t)nx * ny;
+  for (int i = threadIdx.x; i < NR; i += kThreads) {
+    const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+    const int gx = x0 - H + lx;
+    const int gy = DIM >= 2 ? y0 - H + ly : 0;
+    const int gz = DIM >= 3 ? z0 - H + lz : 0;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+      v = xg[(size_t)gz * sxy + (size_t)gy * nx + gx];
+    xs[i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NI; i += kThreads) {
+    const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
+    const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
+    if (gx < nx && gy < ny && gz < nz)
+      yg[(size_t)gz * sxy + (size_t)gy * nx + gx] =
+          apply_lds<DIM, RX, RY>(cf, xs, ux + 1, uy + IY, uz + IZ);
+  }
+}
+
+template <int DIM>
+void tiles_of(const Grid& g, int& ntx, int& nty, int& ntz) {
+  using T = TileShape<DIM>;
+  ntx = (g.nx + T::X - 1) / T::X;
+  nty = (g.ny + T::Y - 1) / T::Y;
+  ntz = (g.nz + T::Z - 1) / T::Z;
+}
+
+void tiles_any(const Grid& g, int& ntx, int& nty, int& ntz) {
+  if (g.dim == 1) tiles_of<1>(g, ntx, nty, ntz);
+  else if (g.dim == 2) tiles_of<2>(g, ntx, nty, ntz);
+  else tiles_of<3>(g, ntx, nty, ntz);
+}
+
+IterArgs make_iter_args(const Grid& g, const Stencil& K, const Stencil& M, const int* ops,
+                        int ncols, const CGWork& w, int parity) {
+  IterArgs a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  tiles_any(g, a.ntx, a.nty, a.ntz);
+  a.ncols = ncols;
+  a.parity = parity;
+  for (int c = 0; c < ncols; ++c) a.ops[c] = ops[c];
+  a.x = w.x;
+  a.r = w.r;
+  a.p = w.p;
+  a.ld = w.ld;
+  a.scal = w.scal;
+  a.partials = w.partials;
+  a.max_tiles = w.max_tiles;
+  for (int i = 0; i < 27; ++i) {
+    a.cf.k[i] = K.c[i];
+    a.cf.m[i] = M.c[i];
+  }
+  return a;
+}
+
+}  // namespace
+
+int cg_tiles(const Grid& g) {
+  int a, b, c;
+  tiles_any(g, a, b, c);
+  return a * b * c;
+}
+
+void cg_setup(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+              const CGWork& w, hipStream_t st) {
+  STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "cg_setup: 1..8 columns");
+  STS_REQUIRE(cg_tiles(g) <= w.max_tiles, STS_E_INVALID, "cg_setup: partial buffer too small");
+  SetupArgs sa;
+  sa.it = make_iter_args(g, K, M, ops, ncols, w, 0);
+  for (int c = 0; c < kMaxCols; ++c) sa.b[c] = c < ncols ? w.b[c] : nullptr;
+  const int blocks = cg_tiles(g) * ncols;
+  if (g.dim == 1) cg_setup_kernel<1><<<blocks, kThreads, 0, st>>>(sa);
+  else if (g.dim == 2) cg_setup_kernel<2><<<blocks, kThreads, 0, st>>>(sa);
+  else cg_setup_kernel<3><<<blocks, kThreads, 0, st>>>(sa);
+  STS_HIP(hipGetLastError());
+}
+
+void cg_iterate(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+                const CGWork& w, int parity, hipStream_t st) {
+  IterArgs a = make_iter_args(g, K, M, ops, ncols, w, parity & 1);
+  const int blocks = cg_tiles(g) * ncols;
+  if (g.dim == 1) cg_iter_kernel<1><<<blocks, kThreads, 0, st>>>(a);
+  else if (g.dim == 2) cg_iter_kernel<2><<<blocks, kThreads, 0, st>>>(a);
+  else cg_iter_kernel<3><<<blocks, kThreads, 0, st>>>(a);
+  STS_HIP(hipGetLastError());
+}
+
+void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+                   const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t st) {
+  if (ncols <= 0) return;
+  STS_REQUIRE(ncols <= 16, STS_E_INVALID, "stencil_apply: at most 16 columns");
+  ApplyArgs a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  tiles_any(g, a.ntx, a.nty, a.ntz);
+  a.ncols = ncols;
+  for (int c = 0; c < ncols; ++c) a.ops[c] = ops[c];
+  a.X = X;
+  a.ldx = ldx;
+  a.Y = Y;
+  a.ldy = ldy;
+  for (int i = 0; i < 27; ++i) {
+    a.cf.k[i] = K.c[i];
+    a.cf.m[i] = M.c[i];
+  }
+  const int blocks = a.ntx * a.nty * a.ntz * ncols;
+  if (g.dim == 1) apply_kernel<1><<<blocks, kThreads, 0, st>>>(a);
+  else if (g.dim == 2) apply_kernel<2><<<blocks, kThreads, 0, st>>>(a);
+  else apply_kernel<3><<<blocks, kThreads, 0, st>>>(a);
+  STS_HIP(hipGetLastError());
+}
+
+}  // namespace sts

@@ -1,0 +1,231 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/sts.h"
+
+namespace sts {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+void set_error(const std::string& msg);
+
+struct Error {
+  sts_status code;
+  std::string msg;
+};
+
+#define STS_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::sts::Error{STS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define STS_REQUIRE(cond, code, msg)                      \
+  do {                                                    \
+    if (!(cond)) throw ::sts::Error{(code), (msg)};       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// spatial operators as constant-coefficient stencils
+// ---------------------------------------------------------------------------
+
+// A constant-coefficient stencil on an nx x ny x nz box of interior nodes
+// (x fastest) with zero Dirichlet values outside.  c[(dz+1)*9 + (dy+1)*3 +
+// (dx+1)] multiplies the neighbour at offset (dx, dy, dz).
+struct Stencil {
+  int dim;
+  int nx, ny, nz;
+  double c[27];
+};
+
+struct Grid {
+  int dim;
+  int nx, ny, nz;
+  int64_t nh;
+};
+
+// Kx (op = STS_OP_K) or Mx (STS_OP_M) of a space descriptor (validated).
+Stencil make_stencil(const sts_space& s, int op);
+Grid make_grid(const sts_space& s);
+void validate_space(const sts_space* s);
+
+// ---------------------------------------------------------------------------
+// CG state shared by host and device
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxCols = 8;     // columns in one CG batch (2P, P <= 4)
+
+// Per-column CG state.  Iteration i of a column uses gamma_i = (r_i, r_i) and
+// delta_i = (A r_i, r_i) of the residual entering it, plus alpha_{i-1} and
+// gamma_{i-1} kept here; `iters` counts completed iterations.
+struct CGScal {
+  double alpha;   // alpha of the last completed iteration
+  double gamma;   // gamma of the residual that entered it
+  double gamma0;  // (b, b)
+  double rtol2;   // stop when gamma_i <= rtol2 * gamma0
+  int active;     // 1 while the column iterates
+  int iters;      // completed iterations
+  int maxit;
+  int flag;       // 0 running, 1 converged, 2 hit maxit, 3 breakdown / non-finite
+};
+
+// The state and the per-tile partial sums are double-buffered by launch
+// parity: launch k reads slot (k-1) & 1 and writes slot k & 1.
+struct CGWork {
+  // device buffers, column-major nh x ncols with leading dimension ld
+  double* x;
+  double* r;
+  double* p;
+  int64_t ld;
+  CGScal* scal;         // device, 2 * kMaxCols entries (two slots)
+  double* partials;     // device, 2 slots * kMaxCols * max_tiles * 2
+  int max_tiles;
+  const double* b[kMaxCols];   // right-hand-side columns (set-up only)
+};
+
+// Set-up: r = b, p = 0, x = 0, partials of (b, b) and (A b, b) into slot 0.
+// The host has written the initial state to slot 0 (iters = 0).
+void cg_setup(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+              const CGWork& w, hipStream_t st);
+// One CG iteration for all active columns; `parity` = launch index & 1
+// (the set-up is launch 0).  Cheap no-op once every column has stopped.
+void cg_iterate(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+                const CGWork& w, int parity, hipStream_t st);
+int cg_tiles(const Grid& g);
+
+// Y[:, c] = A_c X[:, c], A_c = ops[c] ? M : K (ncols <= 16)
+void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+                   const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// dense tall-skinny kernels (FP64 MFMA)
+// ---------------------------------------------------------------------------
+
+// C (m x n, ldc) = A^T B with A: rows x m (lda), B: rows x n (ldb), n <= 16.
+// partial: device scratch of gemm_tn_partial_size(rows, m) doubles.
+void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const double* B,
+             int64_t ldb, double* C, int64_t ldc, double* partial, hipStream_t st);
+int64_t gemm_tn_partial_size(int64_t rows, int m);
+
+// W (rows x n, ldw) -= A (rows x m, lda) C (m x n, ldc), n <= 16.
+void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const double* C,
+                 int64_t ldc, double* W, int64_t ldw, hipStream_t st);
+
+// D (m x n, ldd) = A (m x kk, lda) B (kk x n, ldb), small/medium sizes.
+void gemm_nn(int m, int n, int kk, const double* A, int64_t lda, const double* B, int64_t ldb,
+             double* D, int64_t ldd, hipStream_t st);
+
+// ||[A_0 A_1 A_2] B||_F^2 without forming the product: A_s rows x m_s (lda_s),
+// B (m_0+m_1+m_2) x n (ldb).  Result written to *out (device).
+struct Seg {
+  const double* A;
+  int64_t lda;
+  int m;
+};
+void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double* B, int64_t ldb,
+                    double* out, double* partial, unsigned* counter, hipStream_t st);
+int64_t residual_norm2_partial_size(int64_t rows, int n);
+
+// ---------------------------------------------------------------------------
+// small dense helpers (one work-group)
+// ---------------------------------------------------------------------------
+
+// Cholesky-QR step on the b x b Gram G (ldg) of a block: keeps, in order,
+// the columns whose norm is at least defl_v times norm0[c] (skipped if norm0 is
+// NULL) and whose part independent of the earlier kept columns is at least
+// defl_b of their norm; writes R^{-1} of the kept block (upper triangular,
+// b x b, ld b) and the kept count / indices to `info`.
+struct CholInfo {
+  int kept;
+  int idx[16];
+  int ok;
+};
+void chol_deflate(int b, const double* G, int64_t ldg, const double* norm0, double defl_v,
+                  double defl_b, double* Rinv, CholInfo* info, hipStream_t st);
+// Smallest block-internal independence the Gram-based test can resolve.
+constexpr double kBlockDefl = 1e-7;
+
+// Orthonormalise W (nh x ncols, ldw) against V (nh x k, Mx-orthonormal,
+// MV = Mx V, ld ldv) and within itself in the Mx inner product: CGS2 against V,
+// Cholesky-QR with deflation, one more CGS pass against V and a second
+// Cholesky-QR.  Kept columns are packed to the front of W, MW = Mx W.
+// Returns the kept count; idx[j] = source column of kept column j.
+struct OrthScratch {
+  double* part;   // gemm_tn partial, gemm_tn_partial_size(nh, max(k, 16))
+  double* G;      // 256
+  double* C;      // max(k, 1) * 16 (ld ldc)
+  int64_t ldc;
+  double* norm0;  // 16
+  double* Rinv;   // 256
+  CholInfo* info; // device
+  CholInfo* host; // pinned host copy
+};
+int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
+                         const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
+                         int64_t ldw, int ncols, double defl, const OrthScratch& s, int* idx,
+                         hipStream_t st);
+// W[:, 0:kept] = W[:, idx] * Rinv (kept x kept upper triangular), also for MW.
+void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, double* W,
+                double* MW, int64_t ldw, double* tmp, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// reduced problem
+// ---------------------------------------------------------------------------
+
+struct EigWork {
+  double* a;      // k x k working copy (ld k)
+  double* tau;    // k
+  double* e;      // k
+  double* rot;    // 2 * rot_cap (c, s) pairs
+  int* sweeps;    // 3 * sweep_cap (l, m, offset)
+  int* meta;      // [nsweeps, nrot, status]
+  int64_t rot_cap;
+  int sweep_cap;
+};
+void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_t ldq,
+             const EigWork& w, hipStream_t st);
+
+struct TimeOps {
+  const double* d;   // Dt diagonal (nt)
+  const double* e;   // Dt sub-diagonal (nt-1, e[l] = Dt[l+1, l])
+  const double* m;   // Mt diagonal
+  const double* n;   // Mt sub-diagonal
+};
+// Z (k x nt, ldz): (Dt + lam_i Mt) z_i = G_i with G = qb F2^T, qb = Q^T beta (k x p).
+void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64_t ldqb,
+                const double* F2, int64_t ldf, const TimeOps& t, double* Z, int64_t ldz,
+                hipStream_t st);
+// out (nt x k, ldo) = scale * T A^T for A (k x nt) and a lower-bidiagonal T
+// (diag td, sub ts): out[l, i] = scale (td[l] A[i, l] + ts[l-1] A[i, l-1]).
+void bidiag_right(int k, int nt, const double* A, int64_t lda, const double* td, const double* ts,
+                  double scale, double* out, int64_t ldo, hipStream_t st);
+// ||L^T (T1 Mt^T)||_F^2 for T1 (b x nt), L (b x b lower, ldl); result to *out.
+void cheap_residual(int b, int nt, const double* T1, int64_t ldt, const double* L, int64_t ldl,
+                    const double* md, const double* ms, double* out, double* partial,
+                    unsigned* counter, hipStream_t st);
+
+// B (n x m, ldb) = A^T for A (m x n, lda).
+void transpose(int m, int n, const double* A, int64_t lda, double* B, int64_t ldb, hipStream_t st);
+// Lower Cholesky factor of a b x b SPD matrix (one thread); *ok = 0 if not SPD.
+void chol_lower(int b, const double* G, int64_t ldg, double* L, int64_t ldl, int* ok,
+                hipStream_t st);
+// dst[c, r] = src[r, c] for the m x n block src (fills the mirror of a symmetric block).
+void mirror(int m, int n, const double* src, int64_t lds, double* dst, int64_t ldd, hipStream_t st);
+
+// Copy / fill helpers.
+void copy_cols(int64_t rows, int ncols, const double* src, int64_t lds, double* dst, int64_t ldd,
+               hipStream_t st);
+void fill(double* p, int64_t n, double v, hipStream_t st);
+// sum of squares of a column-major block (deterministic), result to *out.
+void sumsq(int64_t rows, int ncols, const double* A, int64_t lda, double* out, double* partial,
+           unsigned* counter, hipStream_t st);
+
+}  // namespace sts

@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and host-side validation rejects bad arguments."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1912_10082_amd as sts
+from paper_1912_10082_amd import binding as b
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sts.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sts_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = b.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(b.EXPORTED), set(names) ^ set(b.EXPORTED)
+
+
+def test_default_opts():
+    o = b.default_opts()
+    assert o.tol == 1e-8 and o.max_outer == 200 and o.inner_rtol == 1e-12 and o.verify_true == 1
+
+
+def test_time_matrices_match_oracle_quadrature():
+    from oracle import fem
+    t = np.cumsum(np.r_[0.0, np.random.default_rng(3).uniform(0.1, 1.0, 9)])
+    dd, ds, md, ms = sts.time_matrices(t)
+    Dt, Mt = fem.time_matrices(t)
+    ref = fem.bidiagonals(Dt, Mt)
+    for got, want in zip((dd, ds, md, ms), ref):
+        np.testing.assert_allclose(got, want, rtol=1e-15, atol=1e-16)
+
+
+def test_time_matrices_reject_bad_nodes():
+    with pytest.raises(b.STSError) as e:
+        sts.time_matrices(np.array([0.0, 0.5, 0.5, 1.0]))
+    assert e.value.code == b.STS_E_INVALID
+
+
+def _create(space, nt=8, p=1, dt=None, mt=None, F1=None, F2=None):
+    lib = b.load()
+    nh = 49                                  # the 7 x 7 grid of the tests below
+    dd = np.ones(nt) if dt is None else dt[0]
+    ds = -np.ones(nt - 1) if dt is None else dt[1]
+    md = np.full(nt, 0.5 / nt) if mt is None else mt[0]
+    ms = np.full(nt - 1, 0.5 / nt) if mt is None else mt[1]
+    D, kd = b._bidiag(dd, ds)
+    M, km = b._bidiag(md, ms)
+    F1 = np.ones((nh, p), order="F") if F1 is None else F1
+    F2 = np.ones((nt, p), order="F") if F2 is None else F2
+    h = C.c_void_p()
+    code = lib.sts_create(C.byref(space), C.byref(D), C.byref(M), nt, p,
+                          C.c_void_p(F1.ctypes.data), F1.shape[0], C.c_void_p(F2.ctypes.data),
+                          F2.shape[0], b.STS_MEM_HOST, None, C.byref(h))
+    return code, lib.sts_last_error().decode(), h
+
+
+@pytest.mark.parametrize("case", ["kind", "mu", "aniso", "nt", "p", "diag", "nan"])
+def test_create_rejects_invalid_arguments(case):
+    space = b.make_space(2, 7)
+    kw = {}
+    if case == "kind":
+        space.kind = 9
+    elif case == "mu":
+        space.mu = -1.0
+    elif case == "aniso":
+        space.n[1] = 5
+    elif case == "nt":
+        kw = dict(nt=1, dt=(np.ones(1), np.zeros(0)), mt=(np.ones(1), np.zeros(0)))
+    elif case == "p":
+        kw = dict(p=5)
+    elif case == "diag":
+        kw = dict(mt=(np.r_[0.1, 0.0, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1], np.ones(7)))
+    elif case == "nan":
+        F1 = np.ones((49, 1), order="F")
+        F1[3] = np.nan
+        kw = dict(F1=F1)
+    code, msg, h = _create(space, **kw)
+    assert code == b.STS_E_INVALID, (code, msg)
+    assert msg and not h.value
+
+
+def test_destroy_null_and_state_errors():
+    lib = b.load()
+    lib.sts_destroy(None)
+    k = C.c_int64()
+    assert lib.sts_rank(None, C.byref(k)) == b.STS_E_INVALID
+    assert lib.sts_get_factors(None, None, 1, None, 1, 0, None) == b.STS_E_INVALID
+    assert lib.sts_last_error().decode() != ""
+
+
+def test_package_has_no_cpu_fallback():
+    """The product package never imports the oracle and has no CPU solver."""
+    pkg = os.path.join(ROOT, "paper_1912_10082_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            for banned in ("import oracle", "from oracle", "import scipy", "from scipy"):
+                assert banned not in src, (fn, banned)

@@ -1,0 +1,271 @@
+"""GPU parity of every step of the HIP path against the CPU oracle.
+
+All calls go through the C ABI (ctypes binding).  Inputs come from the seeded
+generators in ``workloads``; expected values from ``oracle``.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import paper_1912_10082_amd as sts
+import workloads as wl
+from oracle import exact, fem, projection
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    sts.load()
+
+
+def dev(a):
+    return torch.from_numpy(np.asfortranarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---------------------------------------------------------------- a1: operators
+
+@pytest.mark.parametrize("dim,n", [(1, 127), (1, 1), (1, 3000), (2, 1), (2, 31), (2, 100),
+                                   (2, 129), (3, 7), (3, 33)])
+def test_apply_op_matches_assembled_matrices(dim, n):
+    rng = np.random.default_rng(100 + n)
+    K, M = fem.spatial_operators(dim, n, 0.7)
+    X = rng.normal(size=(K.shape[0], 3))
+    space = sts.make_space(dim, n, 0.7)
+    for op, A in ((sts.STS_OP_K, K), (sts.STS_OP_M, M)):
+        Y = host(sts.apply_op(space, op, dev(X)))
+        ref = A @ X
+        np.testing.assert_allclose(Y, ref, rtol=1e-13, atol=1e-15 * abs(ref).max())
+
+
+# ---------------------------------------------------------------- a3: inner CG
+
+@pytest.mark.parametrize("dim,n", [(1, 127), (2, 63), (2, 100), (3, 15)])
+def test_cg_matches_sparse_direct(dim, n):
+    rng = np.random.default_rng(7 + n)
+    K, M = fem.spatial_operators(dim, n, 1.0)
+    B = rng.normal(size=(K.shape[0], 3))
+    ops = [sts.STS_OP_K, sts.STS_OP_M, sts.STS_OP_K]
+    X, its, _ = sts.cg(sts.make_space(dim, n), ops, dev(B), rtol=1e-12)
+    X = host(X)
+    for c, op in enumerate(ops):
+        A = K if op == sts.STS_OP_K else M
+        x_ref = spla.spsolve(A.tocsc(), B[:, c])
+        assert rel(X[:, c], x_ref) < 1e-8, (c, rel(X[:, c], x_ref))
+        assert np.linalg.norm(B[:, c] - A @ X[:, c]) <= 1e-10 * np.linalg.norm(B[:, c])
+    assert its[1] < its[0]          # the mass matrix is well conditioned
+
+
+def test_cg_zero_rhs_and_iteration_cap():
+    space = sts.make_space(2, 31)
+    B = np.zeros((31 * 31, 2))
+    B[:, 1] = 1.0
+    X, its, code = sts.cg(space, [0, 0], dev(B), rtol=1e-12, maxit=5, check=False)
+    assert its[0] == 0 and np.all(host(X)[:, 0] == 0.0)
+    assert code == 4                                   # STS_E_NOT_CONVERGED (maxit)
+
+
+def test_cg_is_bitwise_deterministic():
+    rng = np.random.default_rng(3)
+    B = dev(rng.normal(size=(127 * 127, 2)))
+    space = sts.make_space(2, 127)
+    X1, _, _ = sts.cg(space, [0, 1], B)
+    X2, _, _ = sts.cg(space, [0, 1], B)
+    assert torch.equal(X1, X2)
+
+
+# ---------------------------------------------------------------- a4: Gram-Schmidt
+
+@pytest.mark.parametrize("rows,m,n", [(1000, 37, 5), (4099, 16, 16), (17, 3, 1), (70000, 130, 8)])
+def test_gram_and_update_match_numpy(rows, m, n):
+    rng = np.random.default_rng(rows + m)
+    A, B, Cm = rng.normal(size=(rows, m)), rng.normal(size=(rows, n)), rng.normal(size=(m, n))
+    G = host(sts.gram(dev(A), dev(B)))
+    np.testing.assert_allclose(G, A.T @ B, rtol=1e-12, atol=1e-12 * math.sqrt(rows))
+    W = host(sts.basis_update(dev(A), dev(Cm), dev(B)))
+    np.testing.assert_allclose(W, B - A @ Cm, rtol=1e-12, atol=1e-12 * math.sqrt(m))
+
+
+def test_m_orthonormalize_properties():
+    n = 63
+    K, M = fem.spatial_operators(2, n)
+    rng = np.random.default_rng(5)
+    V0, _ = projection.m_orthonormalize(rng.normal(size=(n * n, 9)), np.zeros((n * n, 0)), M)
+    W = rng.normal(size=(n * n, 6))
+    W[:, 2] = V0 @ rng.normal(size=9)              # already in the space: must be dropped
+    W[:, 4] = W[:, 0] - 2.0 * W[:, 1]               # dependent on earlier columns: dropped
+    space = sts.make_space(2, n)
+    Vn, MVn, idx = sts.m_orthonormalize(space, dev(V0), dev(M @ V0), dev(W))
+    Vn, MVn = host(Vn), host(MVn)
+    assert idx == [0, 1, 3, 5]
+    np.testing.assert_allclose(Vn.T @ (M @ Vn), np.eye(4), atol=1e-12)
+    assert abs(V0.T @ (M @ Vn)).max() < 1e-12
+    np.testing.assert_allclose(MVn, M @ Vn, rtol=1e-12, atol=1e-16)
+    Vall = np.hstack([V0, Vn])
+    coef = Vall.T @ (M @ W)                         # M-orthogonal projection onto span(Vall)
+    assert rel(Vall @ coef, W) < 1e-11
+
+
+# ---------------------------------------------------------------- a6: reduced eigensolve
+
+@pytest.mark.parametrize("k", [1, 2, 5, 40, 211])
+def test_sym_eig_matches_lapack(k):
+    Km, _ = wl.random_spd_pencil(k, seed=k)
+    lam, Q = sts.sym_eig(dev(Km))
+    lam, Q = host(lam), host(Q)
+    ref = sla.eigvalsh(Km)
+    np.testing.assert_allclose(np.sort(lam), ref, rtol=1e-11, atol=1e-12 * ref.max())
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-12)
+    assert np.linalg.norm(Km @ Q - Q * lam) <= 1e-12 * np.linalg.norm(Km) * math.sqrt(k)
+
+
+def test_sym_eig_repeated_and_clustered():
+    k = 30
+    rng = np.random.default_rng(1)
+    Qr, _ = np.linalg.qr(rng.normal(size=(k, k)))
+    lam0 = np.r_[np.full(10, 2.0), 2.0 + 1e-12 * np.arange(10), np.logspace(1, 6, 10)]
+    A = (Qr * lam0) @ Qr.T
+    lam, Q = sts.sym_eig(dev(A))
+    lam, Q = host(lam), host(Q)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-12)
+    assert np.linalg.norm(A @ Q - Q * lam) <= 1e-12 * np.linalg.norm(A) * math.sqrt(k)
+
+
+# ---------------------------------------------------------------- a7: time sweep
+
+@pytest.mark.parametrize("k,nt,p", [(1, 2, 1), (40, 64, 3), (130, 300, 4)])
+def test_time_sweep_matches_block_substitution(k, nt, p):
+    Km, _, beta, F2 = wl.random_reduced_problem(k, nt, p, seed=k + nt)
+    t = np.cumsum(np.r_[0.0, np.random.default_rng(k).uniform(0.5, 1.5, nt)]) / nt
+    Dt, Mt = fem.time_matrices(t)
+    lam, Q = sla.eigh(Km)
+    dd, ds, md, ms = fem.bidiagonals(Dt, Mt)
+    Y = host(sts.time_sweep(dev(lam), dev(Q), dev(beta), dev(F2), (dd, ds), (md, ms)))
+    ref = projection.galerkin_reduced_solve(Km, np.eye(k), Dt, Mt, beta, F2)
+    assert rel(Y, ref) < 1e-10
+
+
+# ---------------------------------------------------------------- whole path
+
+def _solve(w, device_inputs=True, **opts):
+    t = wl.time_grid(w.nt, w.T)
+    dd, ds, md, ms = sts.time_matrices(t)
+    F1 = dev(w.F1) if device_inputs else w.F1
+    F2 = dev(w.F2) if device_inputs else w.F2
+    prob = sts.Problem(w.dim, w.n[0], w.mu, (dd, ds), (md, ms), F1, F2)
+    info = prob.solve(**opts)
+    V, Y = prob.factors()
+    return prob, info, V, Y
+
+
+def _oracle(w, steps=None):
+    K, M = fem.spatial_operators(w.dim, w.n[0], w.mu)
+    Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+    return K, M, Dt, Mt, exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2, steps=steps)
+
+
+def test_c1_heat1d_sine_rank_one():
+    w = wl.heat_1d_sine()
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    K, M, Dt, Mt, U = _oracle(w)
+    Uk = exact.kron_solve(K, M, Dt, Mt, w.F1, w.F2)
+    assert info["status"] == "STS_OK" and info["breakdown"] == 1 and info["k"] == 1, info
+    assert info["orth_err"] <= 1e-13
+    assert rel(V @ Y, Uk) <= 1e-10 and rel(V @ Y, U) <= 1e-10
+    assert prob.numerical_rank() == 1
+    prob.close()
+
+
+@pytest.mark.parametrize("n,nt,p,seed", [(31, 64, 2, 2), (63, 128, 1, 4), (65, 33, 4, 5),
+                                         (100, 16, 3, 6)])
+def test_2d_solve_matches_crank_nicolson(n, nt, p, seed):
+    w = wl.heat_2d_bumps(n=n, nt=nt, p=p, seed=seed)
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    K, M, Dt, Mt, U = _oracle(w)
+    assert info["status"] == "STS_OK", info
+    assert info["res_true"] <= 1e-10
+    assert exact.sylvester_residual(K, M, Dt, Mt, w.F1, w.F2, V @ Y) <= 1.5e-10
+    assert rel(V @ Y, U) <= 1e-8, rel(V @ Y, U)
+    np.testing.assert_allclose(V.T @ (M @ V), np.eye(V.shape[1]), atol=1e-11)
+    prob.close()
+
+
+def test_1d_and_3d_solves():
+    for w in (wl.heat_1d_sine(nx=255, nt=64, seed=8), wl.heat_3d_separable(n=15, nt=32, p=4, seed=3)):
+        if w.dim == 1:      # a generic rank-one load, not an eigenvector
+            w.F1 = np.asfortranarray(np.random.default_rng(1).normal(size=(255, 1)) / 256)
+        prob, info, V, Y = _solve(w, tol=1e-10)
+        K, M, Dt, Mt, U = _oracle(w)
+        assert info["status"] == "STS_OK", info
+        assert rel(V @ Y, U) <= 1e-8, (w.name, rel(V @ Y, U))
+        prob.close()
+
+
+def test_host_and_device_inputs_agree_bitwise():
+    w = wl.heat_2d_bumps(n=47, nt=40, p=2, seed=9)
+    _, i1, V1, Y1 = _solve(w, device_inputs=True, tol=1e-9)
+    _, i2, V2, Y2 = _solve(w, device_inputs=False, tol=1e-9)
+    assert i1["k"] == i2["k"]
+    assert np.array_equal(V1, V2) and np.array_equal(Y1, Y2)
+
+
+def test_outer_iterations_independent_of_nt():
+    """The all-at-once solver's work does not grow with Nt (Sec. 5, Example 1)."""
+    its = []
+    for nt in (128, 1024):
+        w = wl.heat_2d_bumps(n=63, nt=nt, p=2, seed=11)
+        _, info, _, _ = _solve(w, tol=1e-10, check_every=1)
+        its.append(info["outer_its"])
+    assert abs(its[0] - its[1]) <= 2, its
+
+
+def test_zero_and_rank_deficient_rhs():
+    w = wl.heat_2d_bumps(n=31, nt=16, p=2, seed=12)
+    w.F1 = np.asfortranarray(np.column_stack([w.F1[:, 0], 3.0 * w.F1[:, 0]]))
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    K, M, Dt, Mt, U = _oracle(w)
+    assert info["status"] == "STS_OK" and rel(V @ Y, U) <= 1e-8, info
+    assert info["orth_err"] <= 1e-12
+    np.testing.assert_allclose(V.T @ (M @ V), np.eye(V.shape[1]), atol=1e-12)
+    w.F1 = np.zeros_like(w.F1)
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    assert info["status"] == "STS_OK" and info["k"] == 0 and V.shape[1] == 0
+
+
+def test_not_converged_keeps_factors_and_warm_continues():
+    w = wl.heat_2d_bumps(n=63, nt=32, p=2, seed=13)
+    prob, info, V, Y = _solve(w, tol=1e-12, max_outer=3)
+    assert info["status"] == "STS_E_NOT_CONVERGED" and V.shape[1] > 0
+    info2 = prob.solve(tol=1e-10)
+    assert info2["status"] == "STS_OK"
+    V, Y = prob.factors()
+    *_, U = _oracle(w)
+    assert rel(V @ Y, U) <= 1e-8
+
+
+def test_full_size_2d_bump_problem_properties():
+    """511^2 x 1024, rank 2: exact residual and sampled columns against the oracle."""
+    w = wl.heat_2d_bumps()
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    assert info["status"] == "STS_OK", info
+    assert info["res_true"] <= 1e-10
+    K, M, Dt, Mt, U = _oracle(w, steps=12)
+    assert rel(V @ Y[:, :12], U) <= 1e-8
+    np.testing.assert_allclose(V.T @ (M @ V), np.eye(V.shape[1]), atol=1e-11)
+    prob.close()
