@@ -126,6 +126,7 @@ typedef struct {
   double cg_kernel_seconds; /* summed HIP-event time of the launches */
   int64_t cg_launches;      /* iteration-kernel launches */
   int64_t cg_col_iters;     /* column-iterations performed (each streams 48 bytes per node) */
+  int64_t cg_poll_restarts; /* times a polled CG state was stale and iterations resumed */
 } sts_info;
 
 typedef struct sts_problem sts_problem;

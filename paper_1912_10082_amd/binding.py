@@ -52,7 +52,7 @@ class Info(C.Structure):
                 ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
                 ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
                 ("pad_", C.c_int32), ("cg_kernel_seconds", C.c_double), ("cg_launches", C.c_int64),
-                ("cg_col_iters", C.c_int64)]
+                ("cg_col_iters", C.c_int64), ("cg_poll_restarts", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}

@@ -237,6 +237,7 @@ struct CGRunner {
   std::vector<hipEvent_t> tev;   // pairs (start, end) per chunk, reused
   double prof_seconds = 0.0;
   int64_t prof_launches = 0, prof_col_iters = 0;
+  int64_t poll_restarts = 0;
 
   ~CGRunner() {
     for (auto e : tev) (void)hipEventDestroy(e);
@@ -246,60 +247,70 @@ struct CGRunner {
   // Returns per-column iteration counts and flags in `out` (host).
   void run(const int* ops, int ncols, const double* const* b, double rtol, int maxit,
            CGScal* out, hipStream_t st) {
-    CGScal init[kMaxCols];
-    for (int c = 0; c < kMaxCols; ++c) {
-      init[c] = CGScal{};
-      init[c].rtol2 = rtol * rtol;
-      init[c].maxit = maxit;
-      init[c].active = c < ncols ? 1 : 0;
-    }
-    std::memcpy(host_scal, init, sizeof(init));
-    // initial state into slot 0, read by the set-up (launch 0) and launch 1
-    STS_HIP(hipMemcpyAsync(w.scal, host_scal, sizeof(init), hipMemcpyHostToDevice, st));
+    // initial state (read by the set-up, launch 0, and by launch 1)
+    cg_init_state(w, ncols, rtol, maxit, st);
     for (int c = 0; c < ncols; ++c) w.b[c] = b[c];
     cg_setup(g, K, M, ops, ncols, w, st);
+    for (int q = 0; q < 2 * kMaxCols; ++q) {
+      host_scal[q] = CGScal{};
+      host_scal[q].active = 1;   // never read as "stopped" before a copy lands
+    }
     int64_t launches = 0;   // iteration launches so far (launch index = launches)
+    int cols[kMaxCols], nl = ncols;
+    for (int c = 0; c < ncols; ++c) cols[c] = c;
     int slot = 0, chunk = 8;
-    bool pending = false;
     size_t nchunk = 0;
     for (;;) {
-      if (profile) {
-        if (tev.size() < 2 * (nchunk + 1)) {
-          for (int q = 0; q < 2; ++q) {
-            hipEvent_t e;
-            STS_HIP(hipEventCreate(&e));
-            tev.push_back(e);
+      bool pending = false;
+      for (;;) {
+        if (profile) {
+          if (tev.size() < 2 * (nchunk + 1)) {
+            for (int q = 0; q < 2; ++q) {
+              hipEvent_t e;
+              STS_HIP(hipEventCreate(&e));
+              tev.push_back(e);
+            }
           }
+          STS_HIP(hipEventRecord(tev[2 * nchunk], st));
         }
-        STS_HIP(hipEventRecord(tev[2 * nchunk], st));
+        for (int i = 0; i < chunk; ++i) {
+          ++launches;
+          cg_iterate(g, K, M, ops, ncols, w, (int)(launches & 1), cols, nl, st);
+        }
+        if (profile) {
+          STS_HIP(hipEventRecord(tev[2 * nchunk + 1], st));
+          prof_launches += chunk;
+          ++nchunk;
+        }
+        // state written by the last launch of the chunk
+        STS_HIP(hipMemcpyAsync(host_scal + slot * kMaxCols, w.scal + (launches & 1) * kMaxCols,
+                               sizeof(CGScal) * kMaxCols, hipMemcpyDeviceToHost, st));
+        STS_HIP(hipEventRecord(ev[slot], st));
+        if (pending) {
+          const int other = slot ^ 1;
+          STS_HIP(hipEventSynchronize(ev[other]));
+          int n2 = 0;
+          for (int c = 0; c < ncols; ++c)
+            if (host_scal[other * kMaxCols + c].active) cols[n2++] = c;
+          if (n2 == 0) break;
+          nl = n2;
+        }
+        pending = true;
+        slot ^= 1;
+        chunk = std::min(chunk * 2, 256);
       }
-      for (int i = 0; i < chunk; ++i) {
-        ++launches;
-        cg_iterate(g, K, M, ops, ncols, w, (int)(launches & 1), st);
-      }
-      if (profile) {
-        STS_HIP(hipEventRecord(tev[2 * nchunk + 1], st));
-        prof_launches += chunk;
-        ++nchunk;
-      }
-      // state written by the last launch of the chunk
-      STS_HIP(hipMemcpyAsync(host_scal + slot * kMaxCols, w.scal + (launches & 1) * kMaxCols,
-                             sizeof(CGScal) * kMaxCols, hipMemcpyDeviceToHost, st));
-      STS_HIP(hipEventRecord(ev[slot], st));
-      if (pending) {
-        const int other = slot ^ 1;
-        STS_HIP(hipEventSynchronize(ev[other]));
-        bool any = false;
-        for (int c = 0; c < ncols; ++c) any |= host_scal[other * kMaxCols + c].active != 0;
-        if (!any) break;
-      }
-      pending = true;
-      slot ^= 1;
-      chunk = std::min(chunk * 2, 256);
+      // confirm with a fully synchronised read of the newest state
+      STS_HIP(hipStreamSynchronize(st));
+      STS_HIP(hipMemcpy(out, w.scal + (launches & 1) * kMaxCols, sizeof(CGScal) * kMaxCols,
+                        hipMemcpyDeviceToHost));
+      int n2 = 0;
+      for (int c = 0; c < ncols; ++c)
+        if (out[c].active) cols[n2++] = c;
+      if (n2 == 0) break;
+      ++poll_restarts;   // the polled copy was not current: keep iterating
+      nl = n2;
+      chunk = 8;
     }
-    // the chunk in flight found nothing to do; its copy holds the same state
-    STS_HIP(hipEventSynchronize(ev[slot]));
-    std::memcpy(out, host_scal + slot * kMaxCols, sizeof(CGScal) * kMaxCols);
     if (profile) {
       for (size_t q = 0; q < nchunk; ++q) {
         float ms = 0.0f;
@@ -733,8 +744,8 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     STS_HIP(hipMemcpyAsync(P->tdv.p, tv.data(), 4 * nt * 8, hipMemcpyHostToDevice, st));
     // CG work
     const int tiles = cg_tiles(g);
-    P->cg_r.alloc(P->ldv * kMaxCols * 8);
-    P->cg_p.alloc(P->ldv * kMaxCols * 8);
+    P->cg_r.alloc(2 * P->ldv * kMaxCols * 8);
+    P->cg_p.alloc(2 * P->ldv * kMaxCols * 8);
     P->cg_scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
     P->cg_part.alloc((size_t)2 * 2 * kMaxCols * tiles * 8);
     P->counters.alloc(64);
@@ -742,8 +753,10 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     P->cg.g = g;
     P->cg.K = P->K;
     P->cg.M = P->M;
-    P->cg.w.r = P->cg_r.d();
-    P->cg.w.p = P->cg_p.d();
+    P->cg.w.r[0] = P->cg_r.d();
+    P->cg.w.r[1] = P->cg_r.d() + P->ldv * kMaxCols;
+    P->cg.w.p[0] = P->cg_p.d();
+    P->cg.w.p[1] = P->cg_p.d() + P->ldv * kMaxCols;
     P->cg.w.scal = static_cast<CGScal*>(P->cg_scal.p);
     P->cg.w.partials = P->cg_part.d();
     P->cg.w.max_tiles = tiles;
@@ -923,6 +936,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       info->cg_kernel_seconds = P->cg.prof_seconds;
       info->cg_launches = P->cg.prof_launches;
       info->cg_col_iters = P->cg.prof_col_iters;
+      info->cg_poll_restarts = P->cg.poll_restarts;
     }
     STS_HIP(hipStreamSynchronize(st));
     const double secs =
@@ -1033,8 +1047,10 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops_in, const double* B
     r.M = make_stencil(*space, STS_OP_M);
     r.w.x = X;
     r.w.ld = ldx;
-    r.w.r = sc.get<double>(ld * ncols);
-    r.w.p = sc.get<double>(ld * ncols);
+    r.w.r[0] = sc.get<double>(ld * ncols);
+    r.w.r[1] = sc.get<double>(ld * ncols);
+    r.w.p[0] = sc.get<double>(ld * ncols);
+    r.w.p[1] = sc.get<double>(ld * ncols);
     // x, r, p share one leading dimension in the kernels: stage x if needed
     double* xs = X;
     if (ldx != ld) {

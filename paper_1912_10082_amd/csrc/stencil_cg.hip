@@ -15,7 +15,10 @@
 // for a tile: r and p are staged with a two-point halo in LDS, p and then
 // r - alpha A p are recomputed on the halo, so neither s nor A r is stored.
 // Per grid point and column a launch reads r, p, x and writes them back
-// (48 bytes).
+// (48 bytes).  r and p are read on a halo that neighbouring work-groups own,
+// so each launch writes them to the other buffer of a pair (ping-pong by
+// launch parity); x is only touched on the tile itself and is updated in
+// place.
 //
 // Reduction without a serial tail: every work-group of launch k first sums
 // the per-tile partials written by launch k-1 (in one fixed order, so all
@@ -33,14 +36,19 @@ namespace {
 
 constexpr int kThreads = 256;
 
+template <int TX, int TY, int TZ>
+struct Tile {
+  static constexpr int X = TX, Y = TY, Z = TZ;
+};
+// default tile per dimension
 template <int DIM>
 struct TileShape;
 template <>
-struct TileShape<1> { static constexpr int X = 1024, Y = 1, Z = 1; };
+struct TileShape<1> : Tile<1024, 1, 1> {};
 template <>
-struct TileShape<2> { static constexpr int X = 64, Y = 16, Z = 1; };
+struct TileShape<2> : Tile<64, 16, 1> {};
 template <>
-struct TileShape<3> { static constexpr int X = 32, Y = 8, Z = 4; };
+struct TileShape<3> : Tile<32, 8, 4> {};
 
 struct Coefs {
   double k[27];
@@ -50,12 +58,14 @@ struct Coefs {
 struct IterArgs {
   int nx, ny, nz;
   int ntx, nty, ntz;      // tiles per direction
-  int ncols;
+  int ncols;              // columns of the batch (state entries)
   int parity;             // launch index & 1
+  int nlaunch;            // columns this launch works on (host's view of the active set)
+  int cols[kMaxCols];
   int ops[kMaxCols];
   double* x;
-  double* r;
-  double* p;
+  double* r[2];           // r and p are ping-ponged by launch parity: launch k reads
+  double* p[2];           // buffer (k-1) & 1 (tile plus halo) and writes buffer k & 1
   int64_t ld;
   CGScal* scal;           // 2 slots of kMaxCols
   double* partials;       // 2 slots of kMaxCols * max_tiles * 2
@@ -86,9 +96,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
-template <int DIM>
+
+template <class T>
 __device__ __forceinline__ void tile_origin(const IterArgs& a, int t, int& x0, int& y0, int& z0) {
-  using T = TileShape<DIM>;
   const int tx = t % a.ntx;
   const int rest = t / a.ntx;
   x0 = tx * T::X;
@@ -96,26 +106,45 @@ __device__ __forceinline__ void tile_origin(const IterArgs& a, int t, int& x0, i
   z0 = (rest / a.nty) * T::Z;
 }
 
-// Apply a stencil at LDS point (ix, iy, iz) of an array laid out RX x RY x RZ.
-template <int DIM, int RX, int RY>
+// Sparsity patterns of the stencils, bit (dz+1)*9 + (dy+1)*3 + (dx+1) per
+// neighbour offset; fixed per discretisation so that the stencil loops have
+// no run-time branches.
+constexpr unsigned kMask1D = (1u << 12) | (1u << 13) | (1u << 14);
+constexpr unsigned kMask2DK = (1u << 10) | (1u << 12) | (1u << 13) | (1u << 14) | (1u << 16);
+constexpr unsigned kMask2DM = kMask2DK | (1u << 9) | (1u << 17);   // + SW, NE (Courant diagonal)
+constexpr unsigned kMask3DK = kMask2DK | (1u << 4) | (1u << 22);
+constexpr unsigned kMask3DM = 0x7FFFFFFu;
+
+template <int DIM>
+struct Masks;
+template <>
+struct Masks<1> { static constexpr unsigned K = kMask1D, M = kMask1D; };
+template <>
+struct Masks<2> { static constexpr unsigned K = kMask2DK, M = kMask2DM; };
+template <>
+struct Masks<3> { static constexpr unsigned K = kMask3DK, M = kMask3DM; };
+
+// Apply the stencil with pattern MASK at LDS point (ix, iy, iz) of an array
+// laid out RX x RY x RZ.
+template <unsigned MASK, int RX, int RY>
 __device__ __forceinline__ double apply_lds(const double* c, const double* s, int ix, int iy,
                                             int iz) {
   double acc = 0.0;
-  const int zlo = DIM >= 3 ? -1 : 0, zhi = DIM >= 3 ? 1 : 0;
-  const int ylo = DIM >= 2 ? -1 : 0, yhi = DIM >= 2 ? 1 : 0;
 #pragma unroll
-  for (int dz = zlo; dz <= zhi; ++dz)
+  for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-    for (int dy = ylo; dy <= yhi; ++dy)
+    for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const double cc = c[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
-        if (cc != 0.0) acc += cc * s[((iz + dz) * RY + (iy + dy)) * RX + (ix + dx)];
+        const int bit = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        if ((MASK >> bit) & 1u)
+          acc += c[bit] * s[((iz + dz) * RY + (iy + dy)) * RX + (ix + dx)];
       }
   return acc;
 }
 
-// Sum of (g, d) over the block in a fixed order; valid in thread 0.
+// Sum of (g, d) over a block of NT threads in a fixed order; valid in thread 0.
+template <int NT = kThreads>
 __device__ __forceinline__ void block_sum2(double& g, double& d, double* red) {
   g = wave_sum(g);
   d = wave_sum(d);
@@ -126,135 +155,276 @@ __device__ __forceinline__ void block_sum2(double& g, double& d, double* red) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    g = (red[0] + red[2]) + (red[4] + red[6]);
-    d = (red[1] + red[3]) + (red[5] + red[7]);
+    g = 0.0;
+    d = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      g += red[2 * w];
+      d += red[2 * w + 1];
+    }
   }
 }
 
-// Reduce the previous launch's partials of every active column and take the
-// CG decisions.  Results in shared arrays; work-group 0 also records them.
-__device__ void step_scalars(const IterArgs& a, int ntiles, bool writer, double (*red)[4],
-                             double* s_alpha, double* s_beta, int* s_go) {
-  const CGScal* prev = a.scal + (a.parity ^ 1) * kMaxCols;
-  CGScal* next = a.scal + a.parity * kMaxCols;
+// Per-thread share of the previous launch's partials, loaded before the tile
+// so that its latency overlaps the tile loads (a wait on a later load would
+// also wait on every earlier one).  One tile per thread for the first
+// kPreCols launched columns is held in registers; further tiles and columns
+// are summed in a loop after the tile loads.  Columns outside the launch list
+// have already stopped (the host drops a column only after seeing it stop).
+constexpr int kPreCols = 4;
+
+struct Pre {
+  double g[kPreCols];
+  double d[kPreCols];
+  CGScal prev;            // state of launched column threadIdx.x
+};
+
+template <int NT>
+__device__ __forceinline__ void pre_load(const IterArgs& a, int ntiles, Pre& P) {
+  const double* pin = a.partials + (size_t)(a.parity ^ 1) * kMaxCols * a.max_tiles * 2;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kPreCols; ++j) {
+    P.g[j] = 0.0;
+    P.d[j] = 0.0;
+    if (j < a.nlaunch && t < ntiles) {
+      const double* pp = pin + ((size_t)a.cols[j] * a.max_tiles + t) * 2;
+      P.g[j] = pp[0];
+      P.d[j] = pp[1];
+    }
+  }
+  if ((int)threadIdx.x < a.nlaunch)
+    P.prev = a.scal[(a.parity ^ 1) * kMaxCols + a.cols[threadIdx.x]];
+}
+
+// Sum the partials (fixed order), take the CG decisions (thread j for launch
+// slot j) and, in work-group 0, record the new state of every column.
+template <int NT>
+__device__ void step_scalars(const IterArgs& a, int ntiles, bool writer, const Pre& P,
+                             double (*red)[NT / 64], double* s_alpha, double* s_beta, int* s_go) {
   const double* pin = a.partials + (size_t)(a.parity ^ 1) * kMaxCols * a.max_tiles * 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int c = 0; c < a.ncols; ++c) {
+#pragma unroll
+  for (int j = 0; j < kMaxCols; ++j) {
+    if (j >= a.nlaunch) break;
     double g = 0.0, d = 0.0;
-    if (prev[c].active) {
-      const double* pp = pin + (size_t)c * a.max_tiles * 2;
-      for (int t = threadIdx.x; t < ntiles; t += kThreads) {
-        g += pp[2 * t];
-        d += pp[2 * t + 1];
-      }
+    int t0 = threadIdx.x;
+    if (j < kPreCols) {
+      g = P.g[j];
+      d = P.d[j];
+      t0 += NT;
+    }
+    const double* pc = pin + (size_t)a.cols[j] * a.max_tiles * 2;
+    for (int t = t0; t < ntiles; t += NT) {
+      g += pc[2 * t];
+      d += pc[2 * t + 1];
     }
     g = wave_sum(g);
     d = wave_sum(d);
     if (lane == 0) {
-      red[2 * c][wv] = g;
-      red[2 * c + 1][wv] = d;
+      red[2 * j][wv] = g;
+      red[2 * j + 1][wv] = d;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < a.ncols; ++c) {
-      CGScal s = prev[c];
-      int go = 0;
-      double al = 0.0, be = 0.0;
-      if (s.active) {
-        const double g = (red[2 * c][0] + red[2 * c][1]) + (red[2 * c][2] + red[2 * c][3]);
-        const double d = (red[2 * c + 1][0] + red[2 * c + 1][1]) +
-                         (red[2 * c + 1][2] + red[2 * c + 1][3]);
-        if (!finite(g) || !finite(d)) {
-          s.active = 0;
-          s.flag = 3;
-        } else if (s.iters == 0) {
-          s.gamma0 = g;
-          if (g == 0.0) {
-            s.active = 0;
-            s.flag = 1;
-          } else if (!(d > 0.0)) {
-            s.active = 0;
-            s.flag = 3;
-          } else {
-            al = g / d;
-            go = 1;
-          }
-        } else if (g <= s.rtol2 * s.gamma0) {
+  const int j = threadIdx.x;
+  if (j < a.nlaunch) {
+    CGScal s = P.prev;
+    int go = 0;
+    double al = 0.0, be = 0.0;
+    if (s.active) {
+      double g = 0.0, d = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) {
+        g += red[2 * j][w];
+        d += red[2 * j + 1][w];
+      }
+      if (!finite(g) || !finite(d)) {
+        s.active = 0;
+        s.flag = 3;
+      } else if (s.iters == 0) {
+        s.gamma0 = g;
+        if (g == 0.0) {
           s.active = 0;
           s.flag = 1;
-        } else if (s.iters >= s.maxit) {
+        } else if (!(d > 0.0)) {
           s.active = 0;
-          s.flag = 2;
+          s.flag = 3;
         } else {
-          be = g / s.gamma;
-          const double den = d - be * g / s.alpha;
-          if (!(den > 0.0)) {
-            s.active = 0;
-            s.flag = 3;
-          } else {
-            al = g / den;
-            go = 1;
-          }
+          al = g / d;
+          go = 1;
         }
-        s.gamma = g;
-        if (go) {
-          s.alpha = al;
-          s.iters += 1;
+      } else if (g <= s.rtol2 * s.gamma0) {
+        s.active = 0;
+        s.flag = 1;
+      } else if (s.iters >= s.maxit) {
+        s.active = 0;
+        s.flag = 2;
+      } else {
+        be = g / s.gamma;
+        const double den = d - be * g / s.alpha;
+        if (!(den > 0.0)) {
+          s.active = 0;
+          s.flag = 3;
+        } else {
+          al = g / den;
+          go = 1;
         }
       }
-      s_go[c] = go;
-      s_alpha[c] = al;
-      s_beta[c] = be;
-      if (writer) next[c] = s;
+      s.gamma = g;
+      if (go) {
+        s.alpha = al;
+        s.iters += 1;
+      }
     }
+    s_go[j] = go;
+    s_alpha[j] = al;
+    s_beta[j] = be;
+    if (writer) a.scal[a.parity * kMaxCols + a.cols[j]] = s;
+  }
+  if (writer && j < a.ncols) {
+    bool launched = false;
+    for (int q = 0; q < a.nlaunch; ++q) launched |= a.cols[q] == j;
+    if (!launched) a.scal[a.parity * kMaxCols + j] = a.scal[(a.parity ^ 1) * kMaxCols + j];
   }
   __syncthreads();
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kThreads) void cg_iter_kernel(IterArgs a) {
-  using T = TileShape<DIM>;
+// Stages of one CG iteration on one tile, given the loaded r, p (tile plus
+// two-point halo) and x (tile) in registers.
+template <int DIM, class T, int NT, unsigned MASK, int LR, int LI>
+__device__ __forceinline__ void cg_tile_stages(const IterArgs& a, const double* cf, int c, int t,
+                                               int x0, int y0, int z0, double alpha, double beta,
+                                               const double (&rr)[LR], const double (&pv)[LR],
+                                               const double (&xv)[LI], double* rs, double* ps,
+                                               double* red) {
   constexpr int H = 2;
   constexpr int RX = T::X + 2 * H;
   constexpr int RY = DIM >= 2 ? T::Y + 2 * H : 1;
   constexpr int RZ = DIM >= 3 ? T::Z + 2 * H : 1;
   constexpr int NR = RX * RY * RZ;
-  constexpr int LR = (NR + kThreads - 1) / kThreads;
   constexpr int SX = T::X + 2, SY = DIM >= 2 ? T::Y + 2 : 1, SZ = DIM >= 3 ? T::Z + 2 : 1;
   constexpr int NS = SX * SY * SZ;
+  constexpr int LS = (NS + NT - 1) / NT;
   constexpr int NI = T::X * T::Y * T::Z;
-  constexpr int LI = (NI + kThreads - 1) / kThreads;
   constexpr int OY = DIM >= 2 ? 1 : 0, OZ = DIM >= 3 ? 1 : 0;   // S-region offset in R
   constexpr int IY = DIM >= 2 ? 2 : 0, IZ = DIM >= 3 ? 2 : 0;   // interior offset in R
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t sxy = (size_t)nx * ny;
+  double* xg = a.x + (size_t)c * a.ld;
+  double* rg = a.r[a.parity] + (size_t)c * a.ld;
+  double* pg = a.p[a.parity] + (size_t)c * a.ld;
+
+  // stage 1: r and p <- r + beta p on the tile plus a two-point halo
+#pragma unroll
+  for (int u = 0; u < LR; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < NR) {
+      rs[i] = rr[u];
+      ps[i] = rr[u] + beta * pv[u];
+    }
+  }
+  __syncthreads();
+
+  // stage 2: on the tile plus a one-point halo, r <- r - alpha A p (zero outside);
+  // all reads of this stage come from ps, so its iterations are independent
+  double sv[LS];
+#pragma unroll
+  for (int u = 0; u < LS; ++u) {
+    const int i = threadIdx.x + u * NT;
+    sv[u] = 0.0;
+    if (i < NS) {
+      const int sx = i % SX, sy = (i / SX) % SY, sz = i / (SX * SY);
+      sv[u] = apply_lds<MASK, RX, RY>(cf, ps, sx + 1, sy + OY, sz + OZ);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < LS; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < NS) {
+      const int sx = i % SX, sy = (i / SX) % SY, sz = i / (SX * SY);
+      const int gx = x0 - 1 + sx;
+      const int gy = DIM >= 2 ? y0 - 1 + sy : 0;
+      const int gz = DIM >= 3 ? z0 - 1 + sz : 0;
+      const int q = ((sz + OZ) * RY + (sy + OY)) * RX + (sx + 1);
+      const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+      rs[q] = in ? rs[q] - alpha * sv[u] : 0.0;
+    }
+  }
+  __syncthreads();
+
+  // stage 3: interior -- gamma', delta' partials; write x, r, p
+  double gsum = 0.0, dsum = 0.0;
+#pragma unroll
+  for (int u = 0; u < LI; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < NI) {
+      const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
+      const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
+      if (gx < nx && gy < ny && gz < nz) {
+        const int ix = ux + 2, iy = uy + IY, iz = uz + IZ;
+        const int q = (iz * RY + iy) * RX + ix;
+        const double w = apply_lds<MASK, RX, RY>(cf, rs, ix, iy, iz);
+        const double rn = rs[q];
+        const double pn = ps[q];
+        gsum += rn * rn;
+        dsum += w * rn;
+        const size_t gi = (size_t)gz * sxy + (size_t)gy * nx + gx;
+        xg[gi] = xv[u] + alpha * pn;
+        rg[gi] = rn;
+        pg[gi] = pn;
+      }
+    }
+  }
+  __syncthreads();   // red[] reuse
+  block_sum2<NT>(gsum, dsum, red);
+  if (threadIdx.x == 0) {
+    double* po = a.partials + ((size_t)a.parity * kMaxCols * a.max_tiles + (size_t)c * a.max_tiles +
+                               t) * 2;
+    po[0] = gsum;
+    po[1] = dsum;
+  }
+}
+
+template <int DIM, class T = TileShape<DIM>, int NT = kThreads>
+__global__ __launch_bounds__(NT) void cg_iter_kernel(IterArgs a) {
+  constexpr int H = 2;
+  constexpr int RX = T::X + 2 * H;
+  constexpr int RY = DIM >= 2 ? T::Y + 2 * H : 1;
+  constexpr int RZ = DIM >= 3 ? T::Z + 2 * H : 1;
+  constexpr int NR = RX * RY * RZ;
+  constexpr int LR = (NR + NT - 1) / NT;
+  constexpr int NI = T::X * T::Y * T::Z;
+  constexpr int LI = (NI + NT - 1) / NT;
 
   __shared__ double rs[NR];
   __shared__ double ps[NR];
-  __shared__ double red[2 * kMaxCols][4];
+  __shared__ double red[2 * kMaxCols][NT / 64];
   __shared__ double s_alpha[kMaxCols], s_beta[kMaxCols];
   __shared__ int s_go[kMaxCols];
 
   const int ntiles = a.ntx * a.nty * a.ntz;
-  const int lin = xcd_remap(blockIdx.x, a.ncols * ntiles);
-  const int t = lin / a.ncols, c = lin % a.ncols;
+  const int lin = xcd_remap(blockIdx.x, a.nlaunch * ntiles);
+  const int t = lin / a.nlaunch, jb = lin % a.nlaunch, c = a.cols[jb];
   const bool writer = blockIdx.x == 0;
-  const bool mine = a.scal[(a.parity ^ 1) * kMaxCols + c].active != 0;
-  if (!mine && !writer) return;
+
+  Pre pre;
+  pre_load<NT>(a, ntiles, pre);
 
   int x0, y0, z0;
-  tile_origin<DIM>(a, t, x0, y0, z0);
-  double* xg = a.x + (size_t)c * a.ld;
-  double* rg = a.r + (size_t)c * a.ld;
-  double* pg = a.p + (size_t)c * a.ld;
+  tile_origin<T>(a, t, x0, y0, z0);
+  const double* xg = a.x + (size_t)c * a.ld;
+  const double* rg = a.r[a.parity ^ 1] + (size_t)c * a.ld;
+  const double* pg = a.p[a.parity ^ 1] + (size_t)c * a.ld;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t sxy = (size_t)nx * ny;
 
   // issue every global load of the tile before waiting on the scalars
   double rr[LR], pv[LR], xv[LI];
-  if (mine) {
+  {
 #pragma unroll
     for (int u = 0; u < LR; ++u) {
-      const int i = threadIdx.x + u * kThreads;
+      const int i = threadIdx.x + u * NT;
       rr[u] = 0.0;
       pv[u] = 0.0;
       if (i < NR) {
@@ -271,7 +441,7 @@ __global__ __launch_bounds__(kThreads) void cg_iter_kernel(IterArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < LI; ++u) {
-      const int i = threadIdx.x + u * kThreads;
+      const int i = threadIdx.x + u * NT;
       xv[u] = 0.0;
       if (i < NI) {
         const int gx = x0 + i % T::X, gy = y0 + (i / T::X) % T::Y, gz = z0 + i / (T::X * T::Y);
@@ -280,73 +450,20 @@ __global__ __launch_bounds__(kThreads) void cg_iter_kernel(IterArgs a) {
     }
   }
 
-  step_scalars(a, ntiles, writer, red, s_alpha, s_beta, s_go);
-  if (!mine || !s_go[c]) return;
-  const double alpha = s_alpha[c];
-  const double beta = s_beta[c];
-  const double* cf = a.ops[c] ? a.cf.m : a.cf.k;
-
-  // stage 1: r and p <- r + beta p on the tile plus a two-point halo
-#pragma unroll
-  for (int u = 0; u < LR; ++u) {
-    const int i = threadIdx.x + u * kThreads;
-    if (i < NR) {
-      rs[i] = rr[u];
-      ps[i] = rr[u] + beta * pv[u];
-    }
-  }
-  __syncthreads();
-
-  // stage 2: on the tile plus a one-point halo, r <- r - alpha A p (zero outside)
-  for (int i = threadIdx.x; i < NS; i += kThreads) {
-    const int sx = i % SX, sy = (i / SX) % SY, sz = i / (SX * SY);
-    const int ix = sx + 1, iy = sy + OY, iz = sz + OZ;
-    const int gx = x0 - 1 + sx;
-    const int gy = DIM >= 2 ? y0 - 1 + sy : 0;
-    const int gz = DIM >= 3 ? z0 - 1 + sz : 0;
-    const double s = apply_lds<DIM, RX, RY>(cf, ps, ix, iy, iz);
-    const int q = (iz * RY + iy) * RX + ix;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-    rs[q] = in ? rs[q] - alpha * s : 0.0;
-  }
-  __syncthreads();
-
-  // stage 3: interior -- gamma', delta' partials; write x, r, p
-  double gsum = 0.0, dsum = 0.0;
-#pragma unroll
-  for (int u = 0; u < LI; ++u) {
-    const int i = threadIdx.x + u * kThreads;
-    if (i < NI) {
-      const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
-      const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
-      if (gx < nx && gy < ny && gz < nz) {
-        const int ix = ux + 2, iy = uy + IY, iz = uz + IZ;
-        const int q = (iz * RY + iy) * RX + ix;
-        const double w = apply_lds<DIM, RX, RY>(cf, rs, ix, iy, iz);
-        const double rn = rs[q];
-        const double pn = ps[q];
-        gsum += rn * rn;
-        dsum += w * rn;
-        const size_t gi = (size_t)gz * sxy + (size_t)gy * nx + gx;
-        xg[gi] = xv[u] + alpha * pn;
-        rg[gi] = rn;
-        pg[gi] = pn;
-      }
-    }
-  }
-  __syncthreads();   // red[] reuse
-  block_sum2(gsum, dsum, &red[0][0]);
-  if (threadIdx.x == 0) {
-    double* po = a.partials + ((size_t)a.parity * kMaxCols * a.max_tiles + (size_t)c * a.max_tiles +
-                               t) * 2;
-    po[0] = gsum;
-    po[1] = dsum;
-  }
+  step_scalars<NT>(a, ntiles, writer, pre, red, s_alpha, s_beta, s_go);
+  if (!s_go[jb]) return;
+  const double alpha = s_alpha[jb];
+  const double beta = s_beta[jb];
+  if (a.ops[c])
+    cg_tile_stages<DIM, T, NT, Masks<DIM>::M>(a, a.cf.m, c, t, x0, y0, z0, alpha, beta, rr, pv, xv,
+                                               rs, ps, &red[0][0]);
+  else
+    cg_tile_stages<DIM, T, NT, Masks<DIM>::K>(a, a.cf.k, c, t, x0, y0, z0, alpha, beta, rr, pv, xv,
+                                               rs, ps, &red[0][0]);
 }
 
-template <int DIM>
+template <int DIM, class T = TileShape<DIM>>
 __global__ __launch_bounds__(kThreads) void cg_setup_kernel(SetupArgs sa) {
-  using T = TileShape<DIM>;
   const IterArgs& a = sa.it;
   constexpr int H = 1;
   constexpr int RX = T::X + 2 * H;
@@ -364,12 +481,12 @@ __global__ __launch_bounds__(kThreads) void cg_setup_kernel(SetupArgs sa) {
   const int t = lin / a.ncols, c = lin % a.ncols;
   if (!a.scal[c].active) return;     // the host wrote the initial state to slot 0
   int x0, y0, z0;
-  tile_origin<DIM>(a, t, x0, y0, z0);
+  tile_origin<T>(a, t, x0, y0, z0);
   const double* cf = a.ops[c] ? a.cf.m : a.cf.k;
   const double* bg = sa.b[c];
   double* xg = a.x + (size_t)c * a.ld;
-  double* rg = a.r + (size_t)c * a.ld;
-  double* pg = a.p + (size_t)c * a.ld;
+  double* rg = a.r[0] + (size_t)c * a.ld;     // the set-up is launch 0
+  double* pg = a.p[0] + (size_t)c * a.ld;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t sxy = (size_t)nx * ny;
 
@@ -391,7 +508,8 @@ __global__ __launch_bounds__(kThreads) void cg_setup_kernel(SetupArgs sa) {
     if (gx < nx && gy < ny && gz < nz) {
       const int ix = ux + 1, iy = uy + IY, iz = uz + IZ;
       const double bv = bs[(iz * RY + iy) * RX + ix];
-      const double w = apply_lds<DIM, RX, RY>(cf, bs, ix, iy, iz);
+      const double w = a.ops[c] ? apply_lds<Masks<DIM>::M, RX, RY>(cf, bs, ix, iy, iz)
+                                : apply_lds<Masks<DIM>::K, RX, RY>(cf, bs, ix, iy, iz);
       gsum += bv * bv;
       dsum += w * bv;
       const size_t gi = (size_t)gz * sxy + (size_t)gy * nx + gx;
@@ -406,6 +524,17 @@ __global__ __launch_bounds__(kThreads) void cg_setup_kernel(SetupArgs sa) {
     po[0] = gsum;
     po[1] = dsum;
   }
+}
+
+__global__ void cg_init_state_kernel(CGScal* scal, int ncols, double rtol2, int maxit) {
+  const int c = threadIdx.x;
+  if (c >= kMaxCols) return;
+  CGScal s{};
+  s.rtol2 = rtol2;
+  s.maxit = maxit;
+  s.active = c < ncols ? 1 : 0;
+  scal[c] = s;                  // slot 0
+  scal[kMaxCols + c] = s;       // slot 1 (never read before it is written)
 }
 
 struct ApplyArgs {
@@ -456,7 +585,8 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
     const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
     if (gx < nx && gy < ny && gz < nz)
       yg[(size_t)gz * sxy + (size_t)gy * nx + gx] =
-          apply_lds<DIM, RX, RY>(cf, xs, ux + 1, uy + IY, uz + IZ);
+          a.ops[c] ? apply_lds<Masks<DIM>::M, RX, RY>(cf, xs, ux + 1, uy + IY, uz + IZ)
+                   : apply_lds<Masks<DIM>::K, RX, RY>(cf, xs, ux + 1, uy + IY, uz + IZ);
   }
 }
 
@@ -477,6 +607,8 @@ void tiles_any(const Grid& g, int& ntx, int& nty, int& ntz) {
 IterArgs make_iter_args(const Grid& g, const Stencil& K, const Stencil& M, const int* ops,
                         int ncols, const CGWork& w, int parity) {
   IterArgs a{};
+  a.nlaunch = ncols;
+  for (int c = 0; c < kMaxCols; ++c) a.cols[c] = c < ncols ? c : 0;
   a.nx = g.nx;
   a.ny = g.ny;
   a.nz = g.nz;
@@ -485,8 +617,10 @@ IterArgs make_iter_args(const Grid& g, const Stencil& K, const Stencil& M, const
   a.parity = parity;
   for (int c = 0; c < ncols; ++c) a.ops[c] = ops[c];
   a.x = w.x;
-  a.r = w.r;
-  a.p = w.p;
+  a.r[0] = w.r[0];
+  a.r[1] = w.r[1];
+  a.p[0] = w.p[0];
+  a.p[1] = w.p[1];
   a.ld = w.ld;
   a.scal = w.scal;
   a.partials = w.partials;
@@ -498,6 +632,16 @@ IterArgs make_iter_args(const Grid& g, const Stencil& K, const Stencil& M, const
   return a;
 }
 
+// The kernels only visit the offsets of their dimension's patterns.
+void check_patterns(const Grid& g, const Stencil& K, const Stencil& M) {
+  const unsigned mk = g.dim == 1 ? kMask1D : g.dim == 2 ? kMask2DK : kMask3DK;
+  const unsigned mm = g.dim == 1 ? kMask1D : g.dim == 2 ? kMask2DM : kMask3DM;
+  for (int b = 0; b < 27; ++b) {
+    STS_REQUIRE(((mk >> b) & 1u) || K.c[b] == 0.0, STS_E_INVALID, "stiffness stencil pattern");
+    STS_REQUIRE(((mm >> b) & 1u) || M.c[b] == 0.0, STS_E_INVALID, "mass stencil pattern");
+  }
+}
+
 }  // namespace
 
 int cg_tiles(const Grid& g) {
@@ -506,10 +650,16 @@ int cg_tiles(const Grid& g) {
   return a * b * c;
 }
 
+void cg_init_state(const CGWork& w, int ncols, double rtol, int maxit, hipStream_t st) {
+  cg_init_state_kernel<<<1, 64, 0, st>>>(w.scal, ncols, rtol * rtol, maxit);
+  STS_HIP(hipGetLastError());
+}
+
 void cg_setup(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
               const CGWork& w, hipStream_t st) {
   STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "cg_setup: 1..8 columns");
   STS_REQUIRE(cg_tiles(g) <= w.max_tiles, STS_E_INVALID, "cg_setup: partial buffer too small");
+  check_patterns(g, K, M);
   SetupArgs sa;
   sa.it = make_iter_args(g, K, M, ops, ncols, w, 0);
   for (int c = 0; c < kMaxCols; ++c) sa.b[c] = c < ncols ? w.b[c] : nullptr;
@@ -521,9 +671,15 @@ void cg_setup(const Grid& g, const Stencil& K, const Stencil& M, const int* ops,
 }
 
 void cg_iterate(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
-                const CGWork& w, int parity, hipStream_t st) {
+                const CGWork& w, int parity, const int* cols, int nlaunch, hipStream_t st) {
+  STS_REQUIRE(nlaunch >= 1 && nlaunch <= ncols, STS_E_INVALID, "cg_iterate: bad launch list");
   IterArgs a = make_iter_args(g, K, M, ops, ncols, w, parity & 1);
-  const int blocks = cg_tiles(g) * ncols;
+  a.nlaunch = nlaunch;
+  for (int j = 0; j < nlaunch; ++j) {
+    STS_REQUIRE(cols[j] >= 0 && cols[j] < ncols, STS_E_INVALID, "cg_iterate: bad column");
+    a.cols[j] = cols[j];
+  }
+  const int blocks = cg_tiles(g) * nlaunch;
   if (g.dim == 1) cg_iter_kernel<1><<<blocks, kThreads, 0, st>>>(a);
   else if (g.dim == 2) cg_iter_kernel<2><<<blocks, kThreads, 0, st>>>(a);
   else cg_iter_kernel<3><<<blocks, kThreads, 0, st>>>(a);
@@ -534,6 +690,7 @@ void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int*
                    const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t st) {
   if (ncols <= 0) return;
   STS_REQUIRE(ncols <= 16, STS_E_INVALID, "stencil_apply: at most 16 columns");
+  check_patterns(g, K, M);
   ApplyArgs a{};
   a.nx = g.nx;
   a.ny = g.ny;

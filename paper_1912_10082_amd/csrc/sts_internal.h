@@ -80,10 +80,11 @@ struct CGScal {
 // The state and the per-tile partial sums are double-buffered by launch
 // parity: launch k reads slot (k-1) & 1 and writes slot k & 1.
 struct CGWork {
-  // device buffers, column-major nh x ncols with leading dimension ld
+  // device buffers, column-major nh x ncols with leading dimension ld; r and
+  // p are pairs (launch k reads buffer (k-1) & 1, writes buffer k & 1)
   double* x;
-  double* r;
-  double* p;
+  double* r[2];
+  double* p[2];
   int64_t ld;
   CGScal* scal;         // device, 2 * kMaxCols entries (two slots)
   double* partials;     // device, 2 slots * kMaxCols * max_tiles * 2
@@ -91,14 +92,19 @@ struct CGWork {
   const double* b[kMaxCols];   // right-hand-side columns (set-up only)
 };
 
+// Initial state of a CG batch (both slots): columns c < ncols active.
+void cg_init_state(const CGWork& w, int ncols, double rtol, int maxit, hipStream_t st);
 // Set-up: r = b, p = 0, x = 0, partials of (b, b) and (A b, b) into slot 0.
-// The host has written the initial state to slot 0 (iters = 0).
+// cg_init_state has written the initial state.
 void cg_setup(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
               const CGWork& w, hipStream_t st);
-// One CG iteration for all active columns; `parity` = launch index & 1
-// (the set-up is launch 0).  Cheap no-op once every column has stopped.
+// One CG iteration; `parity` = launch index & 1 (the set-up is launch 0).
+// Work-groups are launched for the columns in cols[0..nlaunch) (the host's
+// possibly stale view of the active ones); every launch updates the state of
+// all ncols columns, and a launched column that has stopped costs one tile
+// load per work-group.
 void cg_iterate(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
-                const CGWork& w, int parity, hipStream_t st);
+                const CGWork& w, int parity, const int* cols, int nlaunch, hipStream_t st);
 int cg_tiles(const Grid& g);
 
 // Y[:, c] = A_c X[:, c], A_c = ops[c] ? M : K (ncols <= 16)
