@@ -71,14 +71,19 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t rows, int m, int n
   partial[(chunk * m16 + j0 + t / 16) * 16 + (t % 16)] = v;
 }
 
-__global__ void gemm_tn_reduce(int m, int n, int64_t nchunks, int m16, const double* partial,
-                               double* C, int64_t ldc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per output element: lanes take chunks lane, lane + 64, ... and the
+// lane sums are combined in a fixed order.
+__global__ __launch_bounds__(256) void gemm_tn_reduce(int m, int n, int64_t nchunks, int m16,
+                                                      const double* partial, double* C,
+                                                      int64_t ldc) {
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (idx >= m * n) return;
   const int i = idx % m, j = idx / m;
   double s = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) s += partial[(c * m16 + i) * 16 + j];
-  C[i + (int64_t)j * ldc] = s;
+  for (int64_t c = lane; c < nchunks; c += 64) s += partial[(c * m16 + i) * 16 + j];
+  s = wave_sum(s);
+  if (lane == 0) C[i + (int64_t)j * ldc] = s;
 }
 
 // W (rows x n) -= A (rows x m) C (m x n); each wave owns 16 rows.
@@ -367,8 +372,7 @@ void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const dou
     gemm_tn_kernel<<<grid, 256, 0, st>>>(rows, m, n, A, lda, B, ldb, partial, m16);
   }
   STS_HIP(hipGetLastError());
-  gemm_tn_reduce<<<(m * n + 255) / 256, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C,
-                                                      ldc);
+  gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C, ldc);
   STS_HIP(hipGetLastError());
 }
 

@@ -854,6 +854,9 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       int next_check = 1;
       int last_check_outer = -1;
       double last_check_res = -1.0;
+      // exact / projected residual, learned from exact checks (inexact inner
+      // solves make the projected value read low)
+      double ratio = 1.0;
       for (outer = 1; outer <= o.max_outer; ++outer) {
         // expand with the last block
         const int64_t bs = P->blk_start, bsz = P->blk_size;
@@ -891,7 +894,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
         P->k_sol = kprev;
         cheap = reduced_solve(P, kprev, kept);
         P->last_cheap = cheap;
-        if (cheap <= o.tol) {
+        if (ratio * cheap <= o.tol) {
           if (!o.verify_true) {
             result = STS_OK;
             break;
@@ -901,15 +904,18 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
             result = STS_OK;
             break;
           }
+          if (cheap > 0.0) ratio = std::max(ratio, truer / cheap);
         }
-        // schedule the next check from the observed convergence rate
+        // schedule the next check from the observed convergence rate: aim at
+        // the step before the predicted crossing of tol / ratio
         if (o.check_every == 0) {
           int step = 1;
-          if (last_check_res > 0.0 && cheap > 0.0 && cheap < last_check_res && cheap > o.tol) {
+          const double target = o.tol / ratio;
+          if (last_check_res > 0.0 && cheap > 0.0 && cheap < last_check_res && cheap > target) {
             const double rate =
                 std::pow(cheap / last_check_res, 1.0 / std::max(1, outer - last_check_outer));
-            const double need = std::log(o.tol / cheap) / std::log(rate);
-            step = std::max(1, std::min(20, (int)std::floor(0.75 * need)));
+            const double need = std::log(target / cheap) / std::log(rate);
+            step = std::max(1, std::min(20, (int)std::floor(need) - 1));
           }
           last_check_outer = outer;
           last_check_res = cheap;
