@@ -106,6 +106,10 @@ typedef struct {
   int64_t mem_budget;       /* bytes of device memory the problem may hold; 0 = unlimited */
   int32_t restart;          /* 1 = discard the current basis and solve from scratch; default 0 */
   int32_t profile;          /* 1 = time the CG iteration kernels with HIP events; default 0 */
+  int32_t inner_precond;    /* Kx solves: 1 = CG preconditioned by one geometric multigrid
+                               V-cycle where the grid allows it (2-D, n halving to <= 63),
+                               else plain CG; 0 = plain CG always; default 1 */
+  int32_t pad_;
 } sts_opts;
 
 typedef struct {
@@ -127,6 +131,11 @@ typedef struct {
   int64_t cg_launches;      /* iteration-kernel launches */
   int64_t cg_col_iters;     /* column-iterations performed (each streams 48 bytes per node) */
   int64_t cg_poll_restarts; /* times a polled CG state was stale and iterations resumed */
+  /* filled when opts.profile = 1 (multigrid-preconditioned CG, this call) */
+  double mg_kernel_seconds; /* summed HIP-event time of the PCG iterations */
+  int64_t mg_iterations;    /* PCG iterations launched (V-cycle + two PCG launches each) */
+  int64_t mg_col_iters;     /* column-iterations performed */
+  double mg_bytes_per_node; /* algorithmic bytes per fine node of one column-iteration */
 } sts_info;
 
 typedef struct sts_problem sts_problem;
@@ -202,6 +211,27 @@ sts_status sts_apply_op(const sts_space* space, int32_t op, const double* X, int
 sts_status sts_cg(const sts_space* space, const int32_t* ops, const double* B, int64_t ldb,
                   double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
                   int32_t* iters, void* stream);
+
+/* Kx X[:, c] = B[:, c] for c < ncols by conjugate gradients preconditioned
+ * with one geometric multigrid V-cycle (the inner Kx^{-1} applications of
+ * the extended Krylov space, Sec. 4; the preconditioner is this library's
+ * choice, not the paper's).  X0 = 0; stops when ||r|| <= rtol ||b|| or after
+ * maxit iterations.  Only for STS_FE_P1_2D spaces whose n halves, n ->
+ * (n-1)/2, down to at most 63 (e.g. 511, 255, 127, or any n <= 63); else
+ * STS_E_INVALID.  B: Nh x ncols (ldb), X: Nh x ncols (ldx), device.  iters
+ * (host, may be NULL) as for sts_cg.  ncols <= 8.  Same errors as sts_cg. */
+sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, double* X,
+                      int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
+                      void* stream);
+
+/* The preconditioner of sts_pcg_mg: Z[:, c] = Bmg R[:, c], one V-cycle from
+ * zero (two damped-Jacobi sweeps, weight 0.8, before and after each coarse
+ * correction; P1 interpolation and its transpose between the nested meshes;
+ * the single-node level solved exactly).  Bmg is symmetric positive definite.
+ * Same spaces as sts_pcg_mg.  R: Nh x ncols (ldr), Z: Nh x ncols (ldz),
+ * device, ncols <= 8. */
+sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,
+                         int64_t ldz, int32_t ncols, void* stream);
 
 /* Block Gram-Schmidt in the Mx inner product: orthogonalise the ncols columns
  * of W (in place, Nh x ncols, ldw) against V (Nh x k, Mx-orthonormal, with

@@ -43,7 +43,7 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32), ("verify_true", C.c_int32),
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("inner_precond", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -52,7 +52,9 @@ class Info(C.Structure):
                 ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
                 ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
                 ("pad_", C.c_int32), ("cg_kernel_seconds", C.c_double), ("cg_launches", C.c_int64),
-                ("cg_col_iters", C.c_int64), ("cg_poll_restarts", C.c_int64)]
+                ("cg_col_iters", C.c_int64), ("cg_poll_restarts", C.c_int64),
+                ("mg_kernel_seconds", C.c_double), ("mg_iterations", C.c_int64),
+                ("mg_col_iters", C.c_int64), ("mg_bytes_per_node", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
@@ -77,6 +79,9 @@ _SIGS = {
     "sts_apply_op": (C.c_int, [C.POINTER(Space), _I32, _P, _I64, _P, _I64, _I32, _P]),
     "sts_cg": (C.c_int, [C.POINTER(Space), C.POINTER(_I32), _P, _I64, _P, _I64, _I32, _F64, _I32,
                          C.POINTER(_I32), _P]),
+    "sts_pcg_mg": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64, _I32,
+                             C.POINTER(_I32), _P]),
+    "sts_mg_vcycle": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _P]),
     "sts_m_orthonormalize": (C.c_int, [C.POINTER(Space), _P, _P, _I64, _I64, _P, _P, _I64, _I32,
                                        _F64, C.POINTER(_I32), C.POINTER(_I32), _P]),
     "sts_gram": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
@@ -323,6 +328,27 @@ def cg(space: Space, ops, B, rtol: float = 1e-12, maxit: int = 200000, check: bo
     if check:
         _check(code)
     return X, list(its), code
+
+
+def pcg_mg(space: Space, B, rtol: float = 1e-12, maxit: int = 1000, check: bool = True):
+    """Kx X = B by multigrid-preconditioned CG (2-D P1 spaces whose n halves)."""
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_zeros(B.shape[0], B.shape[1])
+    its = (C.c_int32 * B.shape[1])()
+    code = load().sts_pcg_mg(C.byref(space), pb, ldb, C.c_void_p(X.data_ptr()), X.shape[0],
+                             B.shape[1], rtol, maxit, its, _stream_handle())
+    if check:
+        _check(code)
+    return X, list(its), code
+
+
+def mg_vcycle(space: Space, R):
+    """Z = Bmg R, one multigrid V-cycle (the preconditioner of pcg_mg)."""
+    R, pr, ldr = dev_colmajor(R)
+    Z = dev_empty(R.shape[0], R.shape[1])
+    _check(load().sts_mg_vcycle(C.byref(space), pr, ldr, C.c_void_p(Z.data_ptr()),
+                                max(Z.shape[0], 1), R.shape[1], _stream_handle()))
+    return Z
 
 
 def m_orthonormalize(space: Space, V, MV, W, defl_tol: float = 1e-10):

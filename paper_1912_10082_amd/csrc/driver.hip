@@ -223,44 +223,63 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
 }
 
 // ---------------------------------------------------------------------------
-// CG batch runner (shared by the solver and sts_cg)
+// Iteration loop with asynchronous polling (plain CG and multigrid PCG)
 // ---------------------------------------------------------------------------
 
-struct CGRunner {
-  Grid g;
-  Stencil K, M;
-  CGWork w;
+// Launches iterations in chunks until every column has stopped.  After each
+// chunk the newest state slot is copied to pinned memory behind an event.
+// Pipelined: the next chunk is queued before the host waits for the copy of
+// the previous one (the GPU never idles; suits long runs of short launches).
+// Not pipelined: the host waits for the chunk it just queued (suits short
+// runs whose length is known well in advance).
+struct PollLoop {
   CGScal* host_scal = nullptr;   // pinned, 2 * kMaxCols
   hipEvent_t ev[2] = {nullptr, nullptr};
-  // optional event timing of the iteration kernels
   bool profile = false;
-  std::vector<hipEvent_t> tev;   // pairs (start, end) per chunk, reused
+  std::vector<hipEvent_t> tev;   // (start, end) per chunk, reused
   double prof_seconds = 0.0;
-  int64_t prof_launches = 0, prof_col_iters = 0;
+  int64_t prof_iters = 0, prof_col_iters = 0;
   int64_t poll_restarts = 0;
 
-  ~CGRunner() {
+  PollLoop() = default;
+  PollLoop(const PollLoop&) = delete;
+  PollLoop& operator=(const PollLoop&) = delete;
+  ~PollLoop() {
+    if (host_scal) (void)hipHostFree(host_scal);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
     for (auto e : tev) (void)hipEventDestroy(e);
   }
+  void init() {
+    if (host_scal) return;
+    STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_scal), sizeof(CGScal) * 2 * kMaxCols,
+                          hipHostMallocDefault));
+    STS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    STS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  }
+  void reset_profile(bool on) {
+    profile = on;
+    prof_seconds = 0.0;
+    prof_iters = prof_col_iters = 0;
+  }
 
-  // Solve A_c x_c = b_c for c < ncols; x_c written to w.x + c * w.ld.
-  // Returns per-column iteration counts and flags in `out` (host).
-  void run(const int* ops, int ncols, const double* const* b, double rtol, int maxit,
-           CGScal* out, hipStream_t st) {
-    // initial state (read by the set-up, launch 0, and by launch 1)
-    cg_init_state(w, ncols, rtol, maxit, st);
-    for (int c = 0; c < ncols; ++c) w.b[c] = b[c];
-    cg_setup(g, K, M, ops, ncols, w, st);
+  // iterate(parity, cols, nl) queues one iteration writing state slot
+  // `parity`; the set-up has initialised both slots.  Iteration i (from 1)
+  // has parity i & 1.  Final states of columns < ncols go to out.
+  template <class F>
+  void run(F&& iterate, const CGScal* dev_scal, int ncols, int chunk, int chunk_cap,
+           bool pipelined, CGScal* out, hipStream_t st) {
     for (int q = 0; q < 2 * kMaxCols; ++q) {
       host_scal[q] = CGScal{};
       host_scal[q].active = 1;   // never read as "stopped" before a copy lands
     }
-    int64_t launches = 0;   // iteration launches so far (launch index = launches)
-    int cols[kMaxCols], nl = ncols;
-    for (int c = 0; c < ncols; ++c) cols[c] = c;
-    int slot = 0, chunk = 8;
+    int64_t iters = 0;
+    int cols[kMaxCols], nl = 0;
+    for (int c = 0; c < ncols; ++c) cols[nl++] = c;
+    int slot = 0;
     size_t nchunk = 0;
-    for (;;) {
+    bool done = false;
+    while (!done) {
       bool pending = false;
       for (;;) {
         if (profile) {
@@ -274,34 +293,45 @@ struct CGRunner {
           STS_HIP(hipEventRecord(tev[2 * nchunk], st));
         }
         for (int i = 0; i < chunk; ++i) {
-          ++launches;
-          cg_iterate(g, K, M, ops, ncols, w, (int)(launches & 1), cols, nl, st);
+          ++iters;
+          iterate((int)(iters & 1), cols, nl);
         }
         if (profile) {
           STS_HIP(hipEventRecord(tev[2 * nchunk + 1], st));
-          prof_launches += chunk;
+          prof_iters += chunk;
           ++nchunk;
         }
-        // state written by the last launch of the chunk
-        STS_HIP(hipMemcpyAsync(host_scal + slot * kMaxCols, w.scal + (launches & 1) * kMaxCols,
+        // state written by the last iteration of the chunk
+        STS_HIP(hipMemcpyAsync(host_scal + slot * kMaxCols, dev_scal + (iters & 1) * kMaxCols,
                                sizeof(CGScal) * kMaxCols, hipMemcpyDeviceToHost, st));
         STS_HIP(hipEventRecord(ev[slot], st));
-        if (pending) {
-          const int other = slot ^ 1;
-          STS_HIP(hipEventSynchronize(ev[other]));
-          int n2 = 0;
-          for (int c = 0; c < ncols; ++c)
-            if (host_scal[other * kMaxCols + c].active) cols[n2++] = c;
-          if (n2 == 0) break;
-          nl = n2;
+        if (pipelined && !pending) {
+          pending = true;
+          slot ^= 1;
+          chunk = std::min(chunk * 2, chunk_cap);
+          continue;
         }
-        pending = true;
+        const int look = pipelined ? slot ^ 1 : slot;
+        STS_HIP(hipEventSynchronize(ev[look]));
+        int n2 = 0;
+        for (int c = 0; c < ncols; ++c)
+          if (host_scal[look * kMaxCols + c].active) cols[n2++] = c;
+        if (n2 == 0) {
+          if (!pipelined) {
+            // the copy followed every queued iteration: it is the final state
+            for (int c = 0; c < ncols; ++c) out[c] = host_scal[look * kMaxCols + c];
+            done = true;
+          }
+          break;
+        }
+        nl = n2;
         slot ^= 1;
-        chunk = std::min(chunk * 2, 256);
+        chunk = pipelined ? std::min(chunk * 2, chunk_cap) : chunk_cap;
       }
+      if (done) break;
       // confirm with a fully synchronised read of the newest state
       STS_HIP(hipStreamSynchronize(st));
-      STS_HIP(hipMemcpy(out, w.scal + (launches & 1) * kMaxCols, sizeof(CGScal) * kMaxCols,
+      STS_HIP(hipMemcpy(out, dev_scal + (iters & 1) * kMaxCols, sizeof(CGScal) * kMaxCols,
                         hipMemcpyDeviceToHost));
       int n2 = 0;
       for (int c = 0; c < ncols; ++c)
@@ -309,7 +339,7 @@ struct CGRunner {
       if (n2 == 0) break;
       ++poll_restarts;   // the polled copy was not current: keep iterating
       nl = n2;
-      chunk = 8;
+      chunk = pipelined ? 8 : chunk_cap;
     }
     if (profile) {
       for (size_t q = 0; q < nchunk; ++q) {
@@ -319,6 +349,105 @@ struct CGRunner {
       }
       for (int c = 0; c < ncols; ++c) prof_col_iters += out[c].iters;
     }
+  }
+};
+
+// Plain CG on a batch of columns (Kx or Mx per column).
+struct CGRunner {
+  Grid g;
+  Stencil K, M;
+  CGWork w;
+  PollLoop poll;
+
+  // Solve A_c x_c = b_c for c < ncols; x_c written to w.x + c * w.ld.
+  void run(const int* ops, int ncols, const double* const* b, double rtol, int maxit,
+           CGScal* out, hipStream_t st) {
+    // initial state (read by the set-up, launch 0, and by launch 1)
+    cg_init_state(w, ncols, rtol, maxit, st);
+    for (int c = 0; c < ncols; ++c) w.b[c] = b[c];
+    cg_setup(g, K, M, ops, ncols, w, st);
+    poll.run([&](int parity, const int* cols, int nl) {
+               cg_iterate(g, K, M, ops, ncols, w, parity, cols, nl, st);
+             },
+             w.scal, ncols, 8, 256, true, out, st);
+  }
+};
+
+// Multigrid-preconditioned CG on Kx columns, with its level buffers.
+struct MGRunner {
+  MGWork w{};
+  PollLoop poll;
+  DevBuf levels, vecs, scal, parts;
+  int expect = 12;   // iterations the last run needed (first chunk length)
+
+  // Allocate for the plan; x / ldx are set per run.
+  void setup(const MGPlan& plan) {
+    w.plan = plan;
+    int64_t tot = 0;
+    for (int l = 1; l <= plan.nlev; ++l) {
+      w.ld[l] = pad_ld((int64_t)plan.n[l] * plan.n[l]);
+      tot += 2 * w.ld[l] * kMaxCols;
+    }
+    w.ld[0] = pad_ld((int64_t)plan.n[0] * plan.n[0]);
+    levels.alloc(std::max<int64_t>(tot, 1) * 8);
+    vecs.alloc(5 * w.ld[0] * kMaxCols * 8);
+    double* q = levels.d();
+    for (int l = 1; l <= plan.nlev; ++l) {
+      w.b[l] = q;
+      w.e[l] = q + w.ld[l] * kMaxCols;
+      q += 2 * w.ld[l] * kMaxCols;
+    }
+    double* v = vecs.d();
+    w.b[0] = v;
+    w.e[0] = v + 1 * w.ld[0] * kMaxCols;
+    w.p[0] = v + 2 * w.ld[0] * kMaxCols;
+    w.p[1] = v + 3 * w.ld[0] * kMaxCols;
+    w.q = v + 4 * w.ld[0] * kMaxCols;
+    if (plan.nlev == 0) {
+      // the coarse kernel works on the finest level directly
+      w.b[0] = v;
+    }
+    w.max_tiles = mg_max_tiles(plan);
+    scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
+    w.scal = static_cast<CGScal*>(scal.p);
+    parts.alloc((size_t)(3 * w.max_tiles + 1) * kMaxCols * 8);
+    w.part_rr = parts.d();
+    w.part_rz = w.part_rr + (size_t)w.max_tiles * kMaxCols;
+    w.part_pq = w.part_rz + (size_t)w.max_tiles * kMaxCols;
+    w.alpha = w.part_pq + (size_t)w.max_tiles * kMaxCols;
+    poll.init();
+  }
+
+  // Algorithmic bytes of one column-iteration per fine node: each level's
+  // down reads b_l and writes b_{l+1}, its up reads b_l and e_{l+1} and
+  // writes e_l, the coarse launch reads b_L and writes e_L, A reads z, p and
+  // writes p, q, B reads x, p, r, q and writes x, r.
+  double bytes_per_node() const {
+    const double n0 = (double)w.plan.n[0] * w.plan.n[0];
+    double b = 80.0 * n0;
+    for (int l = 0; l < w.plan.nlev; ++l) {
+      const double nf = (double)w.plan.n[l] * w.plan.n[l];
+      const double nc = (double)w.plan.n[l + 1] * w.plan.n[l + 1];
+      b += 8.0 * (nf + nc) + 8.0 * (2.0 * nf + nc);
+    }
+    const double nL = (double)w.plan.n[w.plan.nlev] * w.plan.n[w.plan.nlev];
+    b += 16.0 * nL;
+    return b / n0;
+  }
+
+  // K x_c = b_c for c < ncols, x_c at x + c * ldx.
+  void run(double* x, int64_t ldx, int ncols, const double* const* b, double rtol, int maxit,
+           CGScal* out, hipStream_t st) {
+    w.x = x;
+    w.ldx = ldx;
+    int cols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) cols[c] = c;
+    pcg_setup(w, b, cols, ncols, ncols, rtol, maxit, st);
+    poll.run([&](int parity, const int* cl, int nl) { pcg_iterate(w, parity, cl, nl, ncols, st); },
+             w.scal, ncols, std::max(1, std::min(expect, maxit + 1)), 2, false, out, st);
+    int most = 0;
+    for (int c = 0; c < ncols; ++c) most = std::max(most, out[c].iters);
+    expect = most + 1;   // the iteration after the last update detects convergence
   }
 };
 
@@ -353,6 +482,10 @@ struct sts_problem {
   // CG
   DevBuf cg_r, cg_p, cg_scal, cg_part, counters;
   CGRunner cg;
+  // multigrid-preconditioned CG for Kx (allocated on first use)
+  bool mg_ok = false;
+  MGPlan mg_plan_{};
+  std::unique_ptr<MGRunner> mg;
 
   // small scratch
   DevBuf gram, tn_part, rinv, cinfo, norm0, smallv, Lb, T1, okflag;
@@ -370,10 +503,7 @@ struct sts_problem {
   unsigned* counter(int i) const { return static_cast<unsigned*>(counters.p) + i; }
 
   ~sts_problem() {
-    if (cg.host_scal) (void)hipHostFree(cg.host_scal);
     if (pinned) (void)hipHostFree(pinned);
-    for (auto& e : cg.ev)
-      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -545,19 +675,63 @@ double true_residual(sts_problem* P) {
   return std::sqrt(std::max(r2, 0.0)) / P->fnorm;
 }
 
+void check_inner(const CGScal& s) {
+  STS_REQUIRE(s.flag != 3, STS_E_NUMERIC,
+              "inner CG broke down (non-positive curvature or non-finite value)");
+  STS_REQUIRE(s.flag != 2, STS_E_NUMERIC, "inner CG reached its iteration cap");
+}
+
+// Inner solves of one block: x_j = A_j^{-1} b_j written to the next columns
+// of V.  With the multigrid preconditioner the Mx columns are solved first
+// (plain CG) and the Kx columns after them (preconditioned CG); perm[j] is the
+// source column of result column j.  Otherwise all columns go through plain
+// CG in their order.
 void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const* b,
-                  const sts_opts& o) {
-  CGScal out[kMaxCols];
-  P->cg.w.x = P->V.d() + P->k * P->ldv;
-  P->cg.w.ld = P->ldv;
-  P->cg.run(ops, ncols, b, o.inner_rtol, o.inner_maxit, out, P->stream);
-  for (int c = 0; c < ncols; ++c) {
-    STS_REQUIRE(out[c].flag != 3, STS_E_NUMERIC,
-                "inner CG broke down (non-positive curvature or non-finite value)");
-    STS_REQUIRE(out[c].flag != 2, STS_E_NUMERIC, "inner CG reached its iteration cap");
-    if (ops[c] == STS_OP_K) P->inner_K += out[c].iters;
-    else P->inner_M += out[c].iters;
-    P->alg_bytes += (48.0 * out[c].iters + 32.0) * P->nh;
+                  const sts_opts& o, int* perm) {
+  for (int c = 0; c < ncols; ++c) perm[c] = c;
+  double* x0 = P->V.d() + P->k * P->ldv;
+  const bool use_mg = o.inner_precond != 0 && P->mg_ok;
+  int nm = 0, nk = 0;
+  if (use_mg) {
+    for (int c = 0; c < ncols; ++c)
+      if (ops[c] == STS_OP_M) perm[nm++] = c;
+    for (int c = 0; c < ncols; ++c)
+      if (ops[c] == STS_OP_K) perm[nm + nk++] = c;
+  }
+  if (!use_mg || nm > 0) {
+    const int n = use_mg ? nm : ncols;
+    int ops2[kMaxCols];
+    const double* b2[kMaxCols];
+    for (int j = 0; j < n; ++j) {
+      ops2[j] = ops[perm[j]];
+      b2[j] = b[perm[j]];
+    }
+    CGScal out[kMaxCols];
+    P->cg.w.x = x0;
+    P->cg.w.ld = P->ldv;
+    P->cg.run(ops2, n, b2, o.inner_rtol, o.inner_maxit, out, P->stream);
+    for (int j = 0; j < n; ++j) {
+      check_inner(out[j]);
+      if (ops2[j] == STS_OP_K) P->inner_K += out[j].iters;
+      else P->inner_M += out[j].iters;
+      P->alg_bytes += (48.0 * out[j].iters + 32.0) * P->nh;
+    }
+  }
+  if (use_mg && nk > 0) {
+    if (!P->mg) {
+      P->mg = std::make_unique<MGRunner>();
+      P->mg->setup(P->mg_plan_);
+    }
+    const double* b2[kMaxCols];
+    for (int j = 0; j < nk; ++j) b2[j] = b[perm[nm + j]];
+    CGScal out[kMaxCols];
+    P->mg->run(x0 + nm * P->ldv, P->ldv, nk, b2, o.inner_rtol, o.inner_maxit, out, P->stream);
+    const double bpn = P->mg->bytes_per_node();
+    for (int j = 0; j < nk; ++j) {
+      check_inner(out[j]);
+      P->inner_K += out[j].iters;
+      P->alg_bytes += (bpn * (out[j].iters + 1) + 40.0) * P->nh;
+    }
   }
 }
 
@@ -636,6 +810,28 @@ void check_finite(const double* h, int64_t rows, int64_t cols, int64_t ld, const
 }
 }  // namespace
 
+namespace {
+// Multigrid plan of a space (STS_E_INVALID if the grid does not allow one).
+MGPlan require_mg(const sts_space* space, Grid* g) {
+  validate_space(space);
+  *g = make_grid(*space);
+  MGPlan plan{};
+  STS_REQUIRE(mg_plan(*g, make_stencil(*space, STS_OP_K), &plan), STS_E_INVALID,
+              "multigrid needs a 2-D P1 space whose n halves, n -> (n-1)/2, down to <= 63");
+  return plan;
+}
+
+sts_status cg_status(const CGScal* out, int ncols, int32_t* iters) {
+  sts_status bad = STS_OK;
+  for (int c = 0; c < ncols; ++c) {
+    if (iters) iters[c] = out[c].iters;
+    if (out[c].flag == 3) bad = STS_E_NUMERIC;
+    else if (out[c].flag == 2 && bad == STS_OK) bad = STS_E_NOT_CONVERGED;
+  }
+  return bad;
+}
+}  // namespace
+
 extern "C" {
 
 void sts_default_opts(sts_opts* o) {
@@ -651,6 +847,7 @@ void sts_default_opts(sts_opts* o) {
   o->mem_budget = 0;
   o->restart = 0;
   o->profile = 0;
+  o->inner_precond = 1;
 }
 
 const char* sts_last_error(void) { return g_last_error.c_str(); }
@@ -760,11 +957,9 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     P->cg.w.scal = static_cast<CGScal*>(P->cg_scal.p);
     P->cg.w.partials = P->cg_part.d();
     P->cg.w.max_tiles = tiles;
-    STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->cg.host_scal),
-                          sizeof(CGScal) * 2 * kMaxCols, hipHostMallocDefault));
+    P->cg.poll.init();
     STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->pinned), 64 * 8, hipHostMallocDefault));
-    STS_HIP(hipEventCreateWithFlags(&P->cg.ev[0], hipEventDisableTiming));
-    STS_HIP(hipEventCreateWithFlags(&P->cg.ev[1], hipEventDisableTiming));
+    P->mg_ok = mg_plan(g, P->K, &P->mg_plan_);
     // small scratch
     P->gram.alloc(16 * 16 * 8);
     P->rinv.alloc(16 * 16 * 8);
@@ -814,9 +1009,8 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       P->alg_bytes = 0.0;
       P->checks = 0;
     }
-    P->cg.profile = o.profile != 0;
-    P->cg.prof_seconds = 0.0;
-    P->cg.prof_launches = P->cg.prof_col_iters = 0;
+    P->cg.poll.reset_profile(o.profile != 0);
+    if (P->mg) P->mg->poll.reset_profile(o.profile != 0);
     ensure_capacity(P, P->k + (int64_t)b2 * (o.max_outer + 2), o.mem_budget);
     if (!P->smallv.p) P->smallv.alloc(std::max<int64_t>(P->kcap * 16, 4096) * 8);
     if (P->smallv.bytes < (size_t)P->kcap * 16 * 8) P->smallv.alloc(P->kcap * 16 * 8);
@@ -840,13 +1034,14 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
           ops[p + c] = STS_OP_K;
           b[c] = b[p + c] = P->F1.d() + c * P->ldv;
         }
-        run_cg_block(P, ops, b2, b, o);
+        int perm[kMaxCols];
+        run_cg_block(P, ops, b2, b, o, perm);
         int idx[16];
         const int kept = append_block(P, b2, o.defl_tol, idx);
         P->blk_start = 0;
         P->blk_size = kept;
         P->tags.clear();
-        for (int j = 0; j < kept; ++j) P->tags.push_back(idx[j] < p ? 0 : 1);
+        for (int j = 0; j < kept; ++j) P->tags.push_back(perm[idx[j]] < p ? 0 : 1);
         P->k = kept;
         P->k_sol = 0;
         STS_REQUIRE(kept > 0, STS_E_NUMERIC, "start block vanished although F is non-zero");
@@ -870,9 +1065,10 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
           b[n] = (tag == 0 ? P->KV.d() : P->MV.d()) + (bs + j) * P->ldv;
           ++n;
         }
+        int perm[kMaxCols];
+        run_cg_block(P, ops, n, b, o, perm);
         std::vector<int> src_tag(n);
-        for (int j = 0; j < n; ++j) src_tag[j] = P->tags[bs + j];
-        run_cg_block(P, ops, n, b, o);
+        for (int j = 0; j < n; ++j) src_tag[j] = P->tags[bs + perm[j]];
         int idx[16];
         const int64_t kprev = P->k;
         const int kept = append_block(P, n, o.defl_tol, idx);
@@ -939,10 +1135,16 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       info->orth_err = orth_error(P);
       info->rank = -1;
       info->alg_bytes = P->alg_bytes;
-      info->cg_kernel_seconds = P->cg.prof_seconds;
-      info->cg_launches = P->cg.prof_launches;
-      info->cg_col_iters = P->cg.prof_col_iters;
-      info->cg_poll_restarts = P->cg.poll_restarts;
+      info->cg_kernel_seconds = P->cg.poll.prof_seconds;
+      info->cg_launches = P->cg.poll.prof_iters;
+      info->cg_col_iters = P->cg.poll.prof_col_iters;
+      info->cg_poll_restarts = P->cg.poll.poll_restarts;
+      if (P->mg) {
+        info->mg_kernel_seconds = P->mg->poll.prof_seconds;
+        info->mg_iterations = P->mg->poll.prof_iters;
+        info->mg_col_iters = P->mg->poll.prof_col_iters;
+        info->mg_bytes_per_node = P->mg->bytes_per_node();
+      }
     }
     STS_HIP(hipStreamSynchronize(st));
     const double secs =
@@ -1067,18 +1269,7 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops_in, const double* B
     r.w.scal = sc.get<CGScal>(2 * kMaxCols);
     r.w.partials = sc.get<double>((size_t)2 * 2 * kMaxCols * tiles);
     r.w.max_tiles = tiles;
-    STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&r.host_scal), sizeof(CGScal) * 2 * kMaxCols,
-                          hipHostMallocDefault));
-    STS_HIP(hipEventCreateWithFlags(&r.ev[0], hipEventDisableTiming));
-    STS_HIP(hipEventCreateWithFlags(&r.ev[1], hipEventDisableTiming));
-    struct Cleanup {
-      CGRunner& r;
-      ~Cleanup() {
-        if (r.host_scal) (void)hipHostFree(r.host_scal);
-        for (auto& e : r.ev)
-          if (e) (void)hipEventDestroy(e);
-      }
-    } cleanup{r};
+    r.poll.init();
     const double* bcols[kMaxCols];
     for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
     CGScal out[kMaxCols];
@@ -1096,6 +1287,53 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops_in, const double* B
     return bad;
   }
   return s;
+}
+
+sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, double* X,
+                      int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
+                      void* stream) {
+  sts_status bad = STS_OK;
+  sts_status s = run_guarded([&] {
+    Grid g;
+    const MGPlan plan = require_mg(space, &g);
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(rtol > 0.0 && maxit >= 1, STS_E_INVALID, "bad rtol / maxit");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MGRunner r;
+    r.setup(plan);
+    const double* bcols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
+    CGScal out[kMaxCols];
+    r.run(X, ldx, ncols, bcols, rtol, maxit, out, st);
+    STS_HIP(hipStreamSynchronize(st));
+    bad = cg_status(out, ncols, iters);
+  });
+  if (s == STS_OK && bad != STS_OK) {
+    set_error(bad == STS_E_NUMERIC ? "preconditioned CG breakdown"
+                                   : "preconditioned CG reached maxit");
+    return bad;
+  }
+  return s;
+}
+
+sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,
+                         int64_t ldz, int32_t ncols, void* stream) {
+  return run_guarded([&] {
+    Grid g;
+    const MGPlan plan = require_mg(space, &g);
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(R && Z && ldr >= g.nh && ldz >= g.nh, STS_E_INVALID, "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MGRunner r;
+    r.setup(plan);
+    copy_cols(g.nh, ncols, R, ldr, r.w.b[0], r.w.ld[0], st);
+    int cols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) cols[c] = c;
+    mg_vcycle(r.w, nullptr, cols, ncols, false, st);
+    copy_cols(g.nh, ncols, r.w.e[0], r.w.ld[0], Z, ldz, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
 }
 
 sts_status sts_m_orthonormalize(const sts_space* space, const double* V, const double* MV,

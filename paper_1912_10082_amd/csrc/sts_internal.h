@@ -75,6 +75,7 @@ struct CGScal {
   int iters;      // completed iterations
   int maxit;
   int flag;       // 0 running, 1 converged, 2 hit maxit, 3 breakdown / non-finite
+  double rho;     // preconditioned CG: (r, z) of the current direction
 };
 
 // The state and the per-tile partial sums are double-buffered by launch
@@ -110,6 +111,53 @@ int cg_tiles(const Grid& g);
 // Y[:, c] = A_c X[:, c], A_c = ops[c] ? M : K (ncols <= 16)
 void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
                    const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// multigrid-preconditioned CG for the 2-D P1 stiffness
+// ---------------------------------------------------------------------------
+
+constexpr int kMGMaxLevels = 12;
+constexpr int kMGCoarseMax = 63;   // levels up to this size run in one work-group
+
+struct MGPlan {
+  int nlev;                  // tiled levels 0..nlev-1; level nlev has <= kMGCoarseMax nodes
+  int n[kMGMaxLevels + 1];   // nodes per direction, n[l+1] = (n[l] - 1) / 2
+  double mu;                 // Kx = mu (4; -1, -1, -1, -1)
+};
+// True (and *plan filled) if Kx is the 2-D five-point P1 stiffness on a square
+// grid that halves, n -> (n-1)/2, down to at most kMGCoarseMax nodes.
+bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan);
+// Partial-sum slots per column the PCG kernels need.
+int mg_max_tiles(const MGPlan& p);
+
+struct MGWork {
+  MGPlan plan;
+  double* b[kMGMaxLevels + 1];   // right-hand side per level; b[0] is the PCG residual r
+  double* e[kMGMaxLevels + 1];   // V-cycle result per level; e[0] is z
+  int64_t ld[kMGMaxLevels + 1];  // column stride per level
+  double* x;                     // solution columns (x + c * ldx)
+  int64_t ldx;
+  double* p[2];                  // search directions (stride ld[0]), by parity
+  double* q;                     // K p
+  CGScal* scal;                  // 2 slots of kMaxCols
+  double* part_rr;               // kMaxCols * max_tiles each
+  double* part_rz;
+  double* part_pq;
+  double* alpha;                 // kMaxCols
+  int max_tiles;
+};
+// e[0][:, c] = B b[0][:, c] (one V-cycle) for the columns cols[0..nlaunch);
+// columns whose state in `act` (may be null) is inactive are skipped; with
+// `partials` the per-tile (b, e) sums go to part_rz.
+void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
+               hipStream_t st);
+// PCG set-up for K x_c = b[j] (c = cols[j]): x = 0, r = b, state slots of
+// columns c < ncols (active if launched).
+void pcg_setup(const MGWork& w, const double* const* b, const int* cols, int nlaunch, int ncols,
+               double rtol, int maxit, hipStream_t st);
+// One PCG iteration (V-cycle, A, B) writing state slot `parity`.
+void pcg_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
+                 hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // dense tall-skinny kernels (FP64 MFMA)

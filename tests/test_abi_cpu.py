@@ -31,6 +31,7 @@ def test_header_symbols_exported():
 def test_default_opts():
     o = b.default_opts()
     assert o.tol == 1e-8 and o.max_outer == 200 and o.inner_rtol == 1e-12 and o.verify_true == 1
+    assert o.inner_precond == 1
 
 
 def test_time_matrices_match_oracle_quadrature():
@@ -99,6 +100,23 @@ def test_destroy_null_and_state_errors():
     assert lib.sts_rank(None, C.byref(k)) == b.STS_E_INVALID
     assert lib.sts_get_factors(None, None, 1, None, 1, 0, None) == b.STS_E_INVALID
     assert lib.sts_last_error().decode() != ""
+
+
+def test_multigrid_entry_points_reject_unsupported_grids():
+    """Argument checks of the multigrid calls run before any device work."""
+    lib = b.load()
+    for dim, n in ((2, 100), (2, 129), (2, 510), (1, 127), (3, 15)):
+        s = sts.make_space(dim, n)
+        nh = n ** dim
+        assert lib.sts_pcg_mg(C.byref(s), None, nh, None, nh, 1, 1e-12, 10, None,
+                              None) == b.STS_E_INVALID
+        assert "multigrid" in lib.sts_last_error().decode()
+        assert lib.sts_mg_vcycle(C.byref(s), None, nh, None, nh, 1, None) == b.STS_E_INVALID
+    s = sts.make_space(2, 511)
+    assert lib.sts_pcg_mg(C.byref(s), None, 511 ** 2, None, 511 ** 2, 1, 1e-12, 10, None,
+                          None) == b.STS_E_INVALID
+    assert "bad buffers" in lib.sts_last_error().decode()
+    assert lib.sts_mg_vcycle(C.byref(s), None, 511 ** 2, None, 511 ** 2, 9, None) == b.STS_E_INVALID
 
 
 def test_package_has_no_cpu_fallback():

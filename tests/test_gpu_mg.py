@@ -1,0 +1,141 @@
+"""GPU parity of the multigrid-preconditioned inner solver.
+
+The V-cycle is compared entry by entry with the reference of
+``tests/mg_reference.py``; the preconditioned CG solves with the oracle's
+sparse direct solve; whole solves with the preconditioner on and off with the
+oracle's Crank-Nicolson solution.  All calls go through the C ABI.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import mg_reference as mgr
+import paper_1912_10082_amd as sts
+import workloads as wl
+from oracle import exact, fem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    sts.load()
+
+
+def dev(a):
+    return torch.from_numpy(np.asfortranarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# Sizes: the coarse kernel alone (1 .. 63, even tops), one tiled level with a
+# coarse grid that is an exact multiple of the tile in x (65 -> 32) or in y
+# (97 -> 48), ragged tiles (81 -> 40, 125 -> 62, 127 -> 63), and two and
+# three tiled levels (255, 511).
+VC_SIZES = [1, 2, 3, 31, 62, 63, 65, 81, 97, 125, 127, 255, 511]
+
+
+@pytest.mark.parametrize("n", VC_SIZES)
+def test_vcycle_matches_reference(n):
+    mu = 0.25 + 0.1 * (n % 7)
+    rng = np.random.default_rng(200 + n)
+    R = rng.normal(size=(n * n, 3))
+    R[:, 2] = 0.0                                   # a zero column stays zero
+    Z = host(sts.mg_vcycle(sts.make_space(2, n, mu), dev(R)))
+    Zr = mgr.vcycle(R, n, mu)
+    scale = abs(Zr).max()
+    np.testing.assert_allclose(Z, Zr, rtol=0, atol=1e-13 * scale)
+    assert np.all(Z[:, 2] == 0.0)
+
+
+def test_vcycle_symmetric_and_below_the_inverse():
+    n, mu = 127, 1.3
+    rng = np.random.default_rng(5)
+    R = rng.normal(size=(n * n, 4))
+    Z = host(sts.mg_vcycle(sts.make_space(2, n, mu), dev(R)))
+    G = R.T @ Z
+    np.testing.assert_allclose(G, G.T, rtol=1e-12, atol=1e-14 * abs(G).max())
+    K = fem.spatial_operators(2, n, mu)[0].tocsc()
+    X = spla.spsolve(K, R)
+    for j in range(4):
+        assert 0.0 < R[:, j] @ Z[:, j] <= R[:, j] @ X[:, j] * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("n,ncols", [(1, 1), (31, 2), (65, 3), (127, 8), (255, 4), (511, 2)])
+def test_pcg_matches_sparse_direct(n, ncols):
+    mu = 0.7
+    rng = np.random.default_rng(300 + n)
+    B = rng.normal(size=(n * n, ncols))
+    X, its, _ = sts.pcg_mg(sts.make_space(2, n, mu), dev(B), rtol=1e-12)
+    X = host(X)
+    K = fem.spatial_operators(2, n, mu)[0].tocsc()
+    for c in range(ncols):
+        assert np.linalg.norm(B[:, c] - K @ X[:, c]) <= 1e-12 * np.linalg.norm(B[:, c])
+        x_ref = spla.spsolve(K, B[:, c])
+        assert rel(X[:, c], x_ref) < 1e-9, (c, rel(X[:, c], x_ref))
+    # mesh-independent convergence where every level halves (unpreconditioned
+    # CG needs ~1900 at n = 511); 65 -> 32 ends on a level that does not halve
+    # and is only smoothed, which costs iterations but stays correct
+    assert max(its) <= (40 if n == 65 else 16), its
+
+
+def test_pcg_zero_rhs_iteration_cap_and_bad_grids():
+    space = sts.make_space(2, 63)
+    B = np.zeros((63 * 63, 2))
+    B[:, 1] = np.random.default_rng(1).normal(size=63 * 63)
+    X, its, code = sts.pcg_mg(space, dev(B), rtol=1e-14, maxit=3, check=False)
+    assert its[0] == 0 and np.all(host(X)[:, 0] == 0.0)
+    assert its[1] == 3 and code == 4                   # STS_E_NOT_CONVERGED (maxit)
+    for bad in (sts.make_space(2, 100), sts.make_space(2, 129), sts.make_space(1, 127),
+                sts.make_space(3, 15)):
+        nh = int(np.prod([bad.n[d] for d in range(3)]))
+        with pytest.raises(sts.STSError) as e:
+            sts.pcg_mg(bad, dev(np.ones((nh, 1))))
+        assert e.value.code == 1
+
+
+def test_pcg_is_bitwise_deterministic():
+    rng = np.random.default_rng(3)
+    B = dev(rng.normal(size=(255 * 255, 3)))
+    space = sts.make_space(2, 255)
+    X1, i1, _ = sts.pcg_mg(space, B)
+    X2, i2, _ = sts.pcg_mg(space, B)
+    assert i1 == i2 and torch.equal(X1, X2)
+
+
+def _solve(w, **opts):
+    t = wl.time_grid(w.nt, w.T)
+    dd, ds, md, ms = sts.time_matrices(t)
+    prob = sts.Problem(w.dim, w.n[0], w.mu, (dd, ds), (md, ms), dev(w.F1), dev(w.F2))
+    info = prob.solve(**opts)
+    V, Y = prob.factors()
+    prob.close()
+    return info, V, Y
+
+
+@pytest.mark.parametrize("n,nt,p,seed", [(63, 64, 2, 21), (127, 40, 3, 22), (97, 17, 1, 23)])
+def test_solve_with_and_without_multigrid_match_crank_nicolson(n, nt, p, seed):
+    w = wl.heat_2d_bumps(n=n, nt=nt, p=p, seed=seed)
+    K, M = fem.spatial_operators(2, n, w.mu)
+    Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+    U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
+    res = {}
+    for pre in (0, 1):
+        info, V, Y = _solve(w, tol=1e-10, inner_precond=pre)
+        assert info["status"] == "STS_OK", info
+        assert info["res_true"] <= 1e-10
+        assert rel(V @ Y, U) <= 1e-8, (pre, rel(V @ Y, U))
+        res[pre] = info
+    # the preconditioned run needs far fewer inner iterations on Kx
+    assert res[1]["inner_its_K"] * 4 < res[0]["inner_its_K"], (res[0], res[1])
