@@ -99,7 +99,7 @@ typedef struct {
   double tol;               /* relative Frobenius residual target (Sec. 5 uses 1e-8); default 1e-8 */
   int32_t max_outer;        /* max extended-Krylov blocks; default 200 */
   int32_t check_every;      /* 0 = adaptive residual checks, n > 0 = every n blocks; default 0 */
-  double inner_rtol;        /* CG relative residual target; default 1e-12 */
+  double inner_rtol;        /* CG relative residual target; default 1e-13 */
   int32_t inner_maxit;      /* CG iteration cap per solve; default 200000 */
   int32_t verify_true;      /* 1 = confirm convergence with the exact residual; default 1 */
   double defl_tol;          /* drop a new column whose Mx-norm falls below this fraction; default 1e-10 */

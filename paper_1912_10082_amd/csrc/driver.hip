@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -358,6 +360,10 @@ struct CGRunner {
   Stencil K, M;
   CGWork w;
   PollLoop poll;
+  // iterations the last batch of each kind needed (0 = none yet): batches
+  // with only Mx columns converge in a nearly fixed count, so the first chunk
+  // is sized from it and the host waits once instead of doubling chunks
+  int expect[2] = {0, 0};
 
   // Solve A_c x_c = b_c for c < ncols; x_c written to w.x + c * w.ld.
   void run(const int* ops, int ncols, const double* const* b, double rtol, int maxit,
@@ -366,10 +372,20 @@ struct CGRunner {
     cg_init_state(w, ncols, rtol, maxit, st);
     for (int c = 0; c < ncols; ++c) w.b[c] = b[c];
     cg_setup(g, K, M, ops, ncols, w, st);
-    poll.run([&](int parity, const int* cols, int nl) {
-               cg_iterate(g, K, M, ops, ncols, w, parity, cols, nl, st);
-             },
-             w.scal, ncols, 8, 256, true, out, st);
+    int kind = 0;   // 1 if any column is Kx
+    for (int c = 0; c < ncols; ++c) kind |= ops[c] == STS_OP_K ? 1 : 0;
+    auto iterate = [&](int parity, const int* cols, int nl) {
+      cg_iterate(g, K, M, ops, ncols, w, parity, cols, nl, st);
+    };
+    const int ex = expect[kind];
+    if (ex > 0)
+      poll.run(iterate, w.scal, ncols, std::min(ex, maxit + 1), std::max(2, ex / 16), false, out,
+               st);
+    else
+      poll.run(iterate, w.scal, ncols, 8, 256, true, out, st);
+    int most = 0;
+    for (int c = 0; c < ncols; ++c) most = std::max(most, out[c].iters);
+    expect[kind] = most + 1;   // the launch after the last update detects convergence
   }
 };
 
@@ -840,7 +856,7 @@ void sts_default_opts(sts_opts* o) {
   o->tol = 1e-8;
   o->max_outer = 200;
   o->check_every = 0;
-  o->inner_rtol = 1e-12;
+  o->inner_rtol = 1e-13;
   o->inner_maxit = 200000;
   o->verify_true = 1;
   o->defl_tol = 1e-10;
@@ -1014,6 +1030,9 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     ensure_capacity(P, P->k + (int64_t)b2 * (o.max_outer + 2), o.mem_budget);
     if (!P->smallv.p) P->smallv.alloc(std::max<int64_t>(P->kcap * 16, 4096) * 8);
     if (P->smallv.bytes < (size_t)P->kcap * 16 * 8) P->smallv.alloc(P->kcap * 16 * 8);
+    // STS_TRACE=1: one line per residual check on stderr
+    const char* tr = std::getenv("STS_TRACE");
+    const bool trace = tr && tr[0] == '1';
     sts_status result = STS_E_NOT_CONVERGED;
     bool breakdown = false;
     double cheap = -1.0, truer = -1.0;
@@ -1090,28 +1109,35 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
         P->k_sol = kprev;
         cheap = reduced_solve(P, kprev, kept);
         P->last_cheap = cheap;
+        if (trace)
+          std::fprintf(stderr, "sts: outer %d k %lld projected residual %.3e (x %.2f)\n", outer,
+                       (long long)kprev, cheap, ratio);
         if (ratio * cheap <= o.tol) {
           if (!o.verify_true) {
             result = STS_OK;
             break;
           }
           truer = true_residual(P);
+          if (trace) std::fprintf(stderr, "sts: outer %d exact residual %.3e\n", outer, truer);
           if (truer <= o.tol) {
             result = STS_OK;
             break;
           }
           if (cheap > 0.0) ratio = std::max(ratio, truer / cheap);
         }
-        // schedule the next check from the observed convergence rate: aim at
-        // the step before the predicted crossing of tol / ratio
+        // schedule the next check from the observed convergence rate and the
+        // predicted crossing of tol / ratio
         if (o.check_every == 0) {
           int step = 1;
           const double target = o.tol / ratio;
           if (last_check_res > 0.0 && cheap > 0.0 && cheap < last_check_res && cheap > target) {
             const double rate =
                 std::pow(cheap / last_check_res, 1.0 / std::max(1, outer - last_check_outer));
+            // an extra block is far cheaper than an extra check (eigensolve
+            // of the reduced pencil, possibly an exact residual): aim at the
+            // predicted crossing, not before it
             const double need = std::log(target / cheap) / std::log(rate);
-            step = std::max(1, std::min(20, (int)std::floor(need) - 1));
+            step = std::max(1, std::min(24, (int)std::ceil(need)));
           }
           last_check_outer = outer;
           last_check_res = cheap;

@@ -30,7 +30,7 @@ def test_header_symbols_exported():
 
 def test_default_opts():
     o = b.default_opts()
-    assert o.tol == 1e-8 and o.max_outer == 200 and o.inner_rtol == 1e-12 and o.verify_true == 1
+    assert o.tol == 1e-8 and o.max_outer == 200 and o.inner_rtol == 1e-13 and o.verify_true == 1
     assert o.inner_precond == 1
 
 
