@@ -35,8 +35,10 @@ constexpr int kRowsPerChunk = 1024;   // rows of one gemm_tn work-group
 int64_t tn_chunks(int64_t rows) { return (rows + kRowsPerChunk - 1) / kRowsPerChunk; }
 
 // partial[chunk][i][j] (16-padded m x 16) of A^T B over the chunk's rows.
+// Columns j < n1 of B come from B1, the rest from B2 (same leading dimension).
 __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t rows, int m, int n, const double* A,
-                                                      int64_t lda, const double* B, int64_t ldb,
+                                                      int64_t lda, const double* B1,
+                                                      const double* B2, int n1, int64_t ldb,
                                                       double* partial, int m16) {
   __shared__ double acc_s[4][256];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t rows, int m, int n
   const bool acol = (j0 + i) < m;
   const bool bcol = i < n;
   const double* Ap = A + (int64_t)(j0 + i) * lda;
-  const double* Bp = B + (int64_t)i * ldb;
+  const double* Bp = i < n1 ? B1 + (int64_t)i * ldb : B2 + (int64_t)(i - n1) * ldb;
   d4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int64_t r = r_begin; r < r_end; r += 16) {
     double av[4], bv[4];
@@ -72,10 +74,11 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t rows, int m, int n
 }
 
 // One wave per output element: lanes take chunks lane, lane + 64, ... and the
-// lane sums are combined in a fixed order.
+// lane sums are combined in a fixed order.  Columns j < n1 go to C1, the rest
+// to C2.
 __global__ __launch_bounds__(256) void gemm_tn_reduce(int m, int n, int64_t nchunks, int m16,
-                                                      const double* partial, double* C,
-                                                      int64_t ldc) {
+                                                      const double* partial, double* C1,
+                                                      double* C2, int n1, int64_t ldc) {
   const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (idx >= m * n) return;
@@ -83,7 +86,10 @@ __global__ __launch_bounds__(256) void gemm_tn_reduce(int m, int n, int64_t nchu
   double s = 0.0;
   for (int64_t c = lane; c < nchunks; c += 64) s += partial[(c * m16 + i) * 16 + j];
   s = wave_sum(s);
-  if (lane == 0) C[i + (int64_t)j * ldc] = s;
+  if (lane == 0) {
+    if (j < n1) C1[i + (int64_t)j * ldc] = s;
+    else C2[i + (int64_t)(j - n1) * ldc] = s;
+  }
 }
 
 // W (rows x n) -= A (rows x m) C (m x n); each wave owns 16 rows.
@@ -114,9 +120,13 @@ __global__ __launch_bounds__(256) void gemm_nn_sub_kernel(int64_t rows, int m, i
 }
 
 // D (m x n) = A (m x kk) B (kk x n); each wave one 16x16 tile.
-__global__ __launch_bounds__(256) void gemm_nn_kernel(int m, int n, int kk, const double* A,
-                                                      int64_t lda, const double* B, int64_t ldb,
-                                                      double* D, int64_t ldd) {
+// D = alpha op(A) B + beta D with op(A) = A (m x kk) or A^T (A: kk x m); one
+// wave per 16 x 16 tile of D.
+template <bool TA>
+__global__ __launch_bounds__(256) void gemm_small_kernel(int m, int n, int kk, double alpha,
+                                                         const double* A, int64_t lda,
+                                                         const double* B, int64_t ldb,
+                                                         double beta, double* D, int64_t ldd) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int tiles_m = (m + 15) / 16;
@@ -129,7 +139,8 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int m, int n, int kk, cons
   d4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < kk; k0 += 4) {
     const int k = k0 + g;
-    const double a = (rok && k < kk) ? A[(r0 + i) + (int64_t)k * lda] : 0.0;
+    double a = 0.0;
+    if (rok && k < kk) a = TA ? A[k + (int64_t)(r0 + i) * lda] : A[(r0 + i) + (int64_t)k * lda];
     const double b = (cok && k < kk) ? B[k + (int64_t)(c0 + i) * ldb] : 0.0;
     acc = mfma(a, b, acc);
   }
@@ -137,7 +148,10 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int m, int n, int kk, cons
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = r0 + 4 * q + g;
-      if (row < m) D[row + (int64_t)(c0 + i) * ldd] = acc[q];
+      if (row < m) {
+        double* d = D + row + (int64_t)(c0 + i) * ldd;
+        *d = beta == 0.0 ? alpha * acc[q] : alpha * acc[q] + beta * *d;
+      }
     }
   }
 }
@@ -246,6 +260,7 @@ __global__ void chol_deflate_kernel(int b, const double* G, int64_t ldg, const d
   double L[16][16];
   int idx[16];
   int kept = 0;
+  double rmin = 1.0;
   for (int c = 0; c < b; ++c) {
     double v[16];
     const double gcc = G[c + c * ldg];
@@ -259,6 +274,7 @@ __global__ void chol_deflate_kernel(int b, const double* G, int64_t ldg, const d
       d -= v[j] * v[j];
     }
     if (!(d > defl_b * defl_b * gcc) || !(d == d)) continue;
+    rmin = fmin(rmin, sqrt(d / gcc));
     for (int j = 0; j < kept; ++j) L[kept][j] = v[j];
     L[kept][kept] = sqrt(d);
     idx[kept] = c;
@@ -278,6 +294,7 @@ __global__ void chol_deflate_kernel(int b, const double* G, int64_t ldg, const d
     for (int i = 0; i < kept; ++i) Rinv[i + j * b] = (i <= j) ? x[i] : 0.0;
   }
   info->kept = kept;
+  info->rmin = rmin;
   for (int j = 0; j < 16; ++j) info->idx[j] = j < kept ? idx[j] : -1;
   info->ok = 1;
 }
@@ -311,6 +328,11 @@ __global__ void copy_cols_kernel(int64_t rows, int ncols, const double* src, int
   if (idx >= rows * ncols) return;
   const int64_t r = idx % rows, c = idx / rows;
   dst[r + c * ldd] = src[r + c * lds];
+}
+
+__global__ void scale_kernel(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v == 0.0 ? 0.0 : v * p[i];
 }
 
 __global__ void fill_kernel(double* p, int64_t n, double v) {
@@ -359,21 +381,29 @@ int64_t gemm_tn_partial_size(int64_t rows, int m) {
   return tn_chunks(rows) * (int64_t)(((m + 15) / 16) * 16) * 16;
 }
 
-void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const double* B,
-             int64_t ldb, double* C, int64_t ldc, double* partial, hipStream_t st) {
+void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
+              const double* B1, const double* B2, int64_t ldb, double* C1, double* C2,
+              int64_t ldc, double* partial, hipStream_t st) {
+  const int n = n1 + n2;
   if (m <= 0 || n <= 0) return;
-  STS_REQUIRE(n <= 16, STS_E_INVALID, "gemm_tn: n > 16");
+  STS_REQUIRE(n <= 16 && n1 >= 0 && n2 >= 0, STS_E_INVALID, "gemm_tn: n > 16");
   const int m16 = ((m + 15) / 16) * 16;
   const int64_t nch = tn_chunks(rows);
   if (rows <= 0) {
     fill_kernel<<<1, 256, 0, st>>>(partial, (int64_t)m16 * 16, 0.0);
   } else {
     dim3 grid(m16 / 16, (unsigned)nch);
-    gemm_tn_kernel<<<grid, 256, 0, st>>>(rows, m, n, A, lda, B, ldb, partial, m16);
+    gemm_tn_kernel<<<grid, 256, 0, st>>>(rows, m, n, A, lda, B1, B2, n1, ldb, partial, m16);
   }
   STS_HIP(hipGetLastError());
-  gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C, ldc);
+  gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C1,
+                                                  C2, n1, ldc);
   STS_HIP(hipGetLastError());
+}
+
+void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const double* B,
+             int64_t ldb, double* C, int64_t ldc, double* partial, hipStream_t st) {
+  gemm_tn2(rows, m, n, 0, A, lda, B, B, ldb, C, C, ldc, partial, st);
 }
 
 void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const double* C,
@@ -385,16 +415,29 @@ void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const
   STS_HIP(hipGetLastError());
 }
 
-void gemm_nn(int m, int n, int kk, const double* A, int64_t lda, const double* B, int64_t ldb,
-             double* D, int64_t ldd, hipStream_t st) {
+void gemm_small(bool transA, int m, int n, int kk, double alpha, const double* A, int64_t lda,
+                const double* B, int64_t ldb, double beta, double* D, int64_t ldd,
+                hipStream_t st) {
   if (m <= 0 || n <= 0) return;
   if (kk <= 0) {
-    for (int j = 0; j < n; ++j) fill(D + (int64_t)j * ldd, m, 0.0, st);
+    if (beta != 1.0)
+      for (int j = 0; j < n; ++j) scale_kernel<<<(m + 255) / 256, 256, 0, st>>>(D + (int64_t)j * ldd, m, beta);
+    STS_HIP(hipGetLastError());
     return;
   }
   const int tiles = ((m + 15) / 16) * ((n + 15) / 16);
-  gemm_nn_kernel<<<(tiles + 3) / 4, 256, 0, st>>>(m, n, kk, A, lda, B, ldb, D, ldd);
+  if (transA)
+    gemm_small_kernel<true><<<(tiles + 3) / 4, 256, 0, st>>>(m, n, kk, alpha, A, lda, B, ldb,
+                                                             beta, D, ldd);
+  else
+    gemm_small_kernel<false><<<(tiles + 3) / 4, 256, 0, st>>>(m, n, kk, alpha, A, lda, B, ldb,
+                                                              beta, D, ldd);
   STS_HIP(hipGetLastError());
+}
+
+void gemm_nn(int m, int n, int kk, const double* A, int64_t lda, const double* B, int64_t ldb,
+             double* D, int64_t ldd, hipStream_t st) {
+  gemm_small(false, m, n, kk, 1.0, A, lda, B, ldb, 0.0, D, ldd, st);
 }
 
 int64_t residual_norm2_partial_size(int64_t rows, int n) {

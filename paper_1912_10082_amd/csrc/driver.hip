@@ -178,15 +178,21 @@ struct Scratch {
 // block Gram-Schmidt in the Mx inner product
 // ---------------------------------------------------------------------------
 
+// Below this independence ratio of the block the Cholesky-QR step amplifies
+// the O(eps) components along V left by CGS2 beyond 1e-14.
+constexpr double kThirdPassRatio = 1e-2;
+
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
-                         int64_t ldw, int ncols, double defl, const OrthScratch& s, int* idx,
+                         int64_t ldw, int ncols, double defl, OrthScratch& s, int* idx,
                          hipStream_t st) {
   const int64_t nh = g.nh;
   int opsM[16];
   for (int c = 0; c < 16; ++c) opsM[c] = STS_OP_M;
+  s.cgs_passes = 0;
   auto cgs = [&](int nc) {
     if (k <= 0) return;
+    ++s.cgs_passes;
     gemm_tn(nh, (int)k, nc, MV, ldv, W, ldw, s.C, s.ldc, s.part, st);   // C = V^T Mx W
     gemm_nn_sub(nh, (int)k, nc, V, ldv, s.C, s.ldc, W, ldw, st);        // W -= V C
   };
@@ -211,9 +217,10 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
   const int kept = h.kept;
   for (int j = 0; j < kept; ++j) idx[j] = h.idx[j];
   if (kept == 0) return 0;
-  // A small pivot above amplifies rounding along V and within the block:
-  // one more pass against V and a second Cholesky-QR restore both.
-  cgs(kept);
+  // A small pivot above amplifies the rounding left along V (by 1 / rmin)
+  // and within the block: then one more pass against V restores the
+  // former; a second Cholesky-QR always restores the latter.
+  if (h.rmin < kThirdPassRatio) cgs(kept);
   stencil_apply(g, K, M, opsM, kept, W, ldw, MW, ldw, st);
   gemm_tn(nh, kept, kept, W, ldw, MW, ldw, s.G, 16, s.part, st);
   chol_deflate(kept, s.G, 16, nullptr, 0.0, kBlockDefl, s.Rinv, s.info, st);
@@ -506,7 +513,7 @@ struct sts_problem {
   // small scratch
   DevBuf gram, tn_part, rinv, cinfo, norm0, smallv, Lb, T1, okflag;
   // reduced solve
-  DevBuf lam, Q, eig_a, eig_tau, eig_e, eig_meta, qb, Z, Y;
+  DevBuf lam, Q, eig_a, eig_tau, eig_e, eig_meta, qb, Z, Y, RB;
   // residual
   DevBuf BT, res_part;
   double* pinned = nullptr;   // 64 doubles
@@ -531,7 +538,7 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t budget) {
   const int64_t ld = P->ldv;
   const int64_t nt = P->nt;
   const int64_t bytes = 3 * ld * kc * 8 + 2 * kc * kc * 8 + kc * P->p * 8 +   // V MV KV Kred Mred beta
-                        kc * kc * 8 * 2 + kc * 8 * 3 + 2 * kc * nt * 8 +       // Q eig_a, vectors, Z Y
+                        kc * kc * 8 * 2 + kc * 8 * 3 + 3 * kc * nt * 8 +       // Q eig_a, vectors, Z Y RB
                         nt * (P->p + 2 * kc) * 8;                              // BT
   STS_REQUIRE(budget <= 0 || bytes <= budget, STS_E_NOMEM,
               "basis of " + std::to_string(kc) + " columns needs " + std::to_string(bytes) +
@@ -578,6 +585,7 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t budget) {
   P->qb.alloc(kc * 4 * 8);
   P->Z.alloc(kc * nt * 8);
   P->Y.alloc(kc * nt * 8);
+  P->RB.alloc(kc * nt * 8);
   P->BT.alloc(nt * (P->p + 2 * kc) * 8);
   P->tn_part.alloc(gemm_tn_partial_size(P->nh, (int)kc) * 8);
   P->kcap = kc;
@@ -615,7 +623,7 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
   s.host = reinterpret_cast<CholInfo*>(P->pinned);
   const int kept = orthonormalize_block(P->grid, P->K, P->M, P->V.d(), P->MV.d(), ld, k, W, MW,
                                         ld, ncols, defl, s, keep_idx, st);
-  P->alg_bytes += 6.0 * 8.0 * nh * k + 8.0 * 16.0 * nh * ncols;
+  P->alg_bytes += 2.0 * s.cgs_passes * 8.0 * nh * k + 8.0 * 16.0 * nh * ncols;
   if (kept == 0) return 0;
   // Kx image of the new columns
   int opsK[16];
@@ -624,12 +632,13 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
   stencil_apply(P->grid, P->K, P->M, opsK, kept, W, ld, KW, ld, st);
   // reduced matrices: new columns and their mirror rows
   const int64_t kn = k + kept, kc = P->kcap;
-  gemm_tn(nh, (int)kn, kept, P->V.d(), ld, KW, ld, P->Kred.d() + k * kc, kc, P->tn_part.d(), st);
-  gemm_tn(nh, (int)kn, kept, P->V.d(), ld, MW, ld, P->Mred.d() + k * kc, kc, P->tn_part.d(), st);
+  // one pass over V for both: [Kred Mred](:, new) = V^T [Kx W, Mx W]
+  gemm_tn2(nh, (int)kn, kept, kept, P->V.d(), ld, KW, MW, ld, P->Kred.d() + k * kc,
+           P->Mred.d() + k * kc, kc, P->tn_part.d(), st);
   mirror((int)k, kept, P->Kred.d() + k * kc, kc, P->Kred.d() + k, kc, st);
   mirror((int)k, kept, P->Mred.d() + k * kc, kc, P->Mred.d() + k, kc, st);
   gemm_tn(nh, kept, P->p, W, ld, P->F1.d(), ld, P->beta.d() + k, kc, P->tn_part.d(), st);
-  P->alg_bytes += 2.0 * 8.0 * nh * kn + 4.0 * 16.0 * nh * kept;
+  P->alg_bytes += 8.0 * nh * kn + 4.0 * 16.0 * nh * kept;
   return kept;
 }
 
@@ -648,6 +657,20 @@ double reduced_solve(sts_problem* P, int64_t ks, int64_t b) {
   time_sweep((int)ks, (int)nt, P->p, P->lam.d(), P->qb.d(), kc, P->F2.d(), nt, time_ops(P),
              P->Z.d(), kc, st);
   gemm_nn((int)ks, (int)nt, (int)ks, P->Q.d(), kc, P->Z.d(), kc, P->Y.d(), kc, st);
+  // One step of iterative refinement with the same eigendecomposition: its
+  // backward error eps ||Km|| is large against the smallest eigenvalues,
+  // which carry the smooth part of the solution.
+  {
+    const TimeOps t = time_ops(P);
+    double* KY = P->RB.d();
+    gemm_nn((int)ks, (int)nt, (int)ks, P->Kred.d(), kc, P->Y.d(), kc, KY, kc, st);
+    reduced_residual((int)ks, (int)nt, P->p, P->beta.d(), kc, P->F2.d(), nt, KY, P->Y.d(), kc,
+                     t, P->Z.d(), kc, st);
+    gemm_small(true, (int)ks, (int)nt, (int)ks, 1.0, P->Q.d(), kc, P->Z.d(), kc, 0.0, KY, kc, st);
+    time_sweep_full((int)ks, (int)nt, P->lam.d(), KY, kc, t, P->Z.d(), kc, st);
+    gemm_small(false, (int)ks, (int)nt, (int)ks, 1.0, P->Q.d(), kc, P->Z.d(), kc, 1.0, P->Y.d(),
+               kc, st);
+  }
   double res2 = 0.0;
   if (b > 0) {
     // tau = Kred[ks:ks+b, 0:ks]; T1 = tau Y

@@ -315,6 +315,8 @@ struct SweepArgs {
   TimeOps t;
   double* Z;
   int64_t ldz;
+  const double* G;   // if set: full right-hand side G (k x nt, ldg) instead of qb F2^T
+  int64_t ldg;
 };
 
 constexpr int kSweepChunk = 256;
@@ -343,7 +345,9 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     if (act) {
       for (int u = 0; u < len; ++u) {
         double gl = 0.0;
-        for (int p = 0; p < a.p; ++p) gl += q[p] * f2[p][u];
+        if (a.G) gl = a.G[i + (int64_t)(l0 + u) * a.ldg];
+        else
+          for (int p = 0; p < a.p; ++p) gl += q[p] * f2[p][u];
         z = (gl - (de[u] + lam * dn[u]) * z) / (dd[u] + lam * dm[u]);
         a.Z[i + (int64_t)(l0 + u) * a.ldz] = z;
       }
@@ -353,6 +357,23 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
 
 // out (nt x k, ldo) = scale * T A^T for A (k x nt) and lower-bidiagonal T:
 // out[l, i] = scale (td[l] A[i, l] + ts[l-1] A[i, l-1]).
+// R = beta F2^T - KY Mt^T - Y Dt^T (k x nt), KY = Km Y.  Row l of a
+// lower-bidiagonal time matrix T has T[l, l] and T[l, l-1].
+__global__ void reduced_residual_kernel(int k, int nt, int p, const double* beta, int64_t ldb,
+                                        const double* F2, int64_t ldf, const double* KY,
+                                        const double* Y, int64_t ldy, TimeOps t, double* R,
+                                        int64_t ldr) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)k * nt) return;
+  const int i = idx % k, l = idx / k;
+  double f = 0.0;
+  for (int q = 0; q < p; ++q) f += beta[i + (int64_t)q * ldb] * F2[l + (int64_t)q * ldf];
+  const int64_t c = i + (int64_t)l * ldy;
+  double v = f - t.m[l] * KY[c] - t.d[l] * Y[c];
+  if (l > 0) v -= t.n[l - 1] * KY[c - ldy] + t.e[l - 1] * Y[c - ldy];
+  R[i + (int64_t)l * ldr] = v;
+}
+
 __global__ void bidiag_right_kernel(int k, int nt, const double* A, int64_t lda, const double* td,
                                     const double* ts, double scale, double* out, int64_t ldo) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -476,8 +497,26 @@ void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64
                 hipStream_t st) {
   if (k <= 0 || nt <= 0) return;
   STS_REQUIRE(p >= 1 && p <= 4, STS_E_INVALID, "time_sweep: 1 <= p <= 4");
-  SweepArgs a{k, nt, p, lam, qb, ldqb, F2, ldf, t, Z, ldz};
+  SweepArgs a{k, nt, p, lam, qb, ldqb, F2, ldf, t, Z, ldz, nullptr, 0};
   sweep_kernel<<<(k + 63) / 64, 64, 0, st>>>(a);
+  STS_HIP(hipGetLastError());
+}
+
+void time_sweep_full(int k, int nt, const double* lam, const double* G, int64_t ldg,
+                     const TimeOps& t, double* Z, int64_t ldz, hipStream_t st) {
+  if (k <= 0 || nt <= 0) return;
+  SweepArgs a{k, nt, 0, lam, nullptr, 0, nullptr, 0, t, Z, ldz, G, ldg};
+  sweep_kernel<<<(k + 63) / 64, 64, 0, st>>>(a);
+  STS_HIP(hipGetLastError());
+}
+
+void reduced_residual(int k, int nt, int p, const double* beta, int64_t ldb, const double* F2,
+                      int64_t ldf, const double* KY, const double* Y, int64_t ldy,
+                      const TimeOps& t, double* R, int64_t ldr, hipStream_t st) {
+  if (k <= 0 || nt <= 0) return;
+  const int64_t n = (int64_t)k * nt;
+  reduced_residual_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(k, nt, p, beta, ldb, F2,
+                                                                       ldf, KY, Y, ldy, t, R, ldr);
   STS_HIP(hipGetLastError());
 }
 

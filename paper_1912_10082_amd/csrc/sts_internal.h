@@ -169,9 +169,21 @@ void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const dou
              int64_t ldb, double* C, int64_t ldc, double* partial, hipStream_t st);
 int64_t gemm_tn_partial_size(int64_t rows, int m);
 
+// [C1 C2] = A^T [B1 B2]: B1 rows x n1, B2 rows x n2 (common ldb), n1 + n2 <= 16;
+// C1 (m x n1) and C2 (m x n2) share ldc.  One pass over A.
+void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
+              const double* B1, const double* B2, int64_t ldb, double* C1, double* C2,
+              int64_t ldc, double* partial, hipStream_t st);
+
 // W (rows x n, ldw) -= A (rows x m, lda) C (m x n, ldc), n <= 16.
 void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const double* C,
                  int64_t ldc, double* W, int64_t ldw, hipStream_t st);
+
+// D (m x n, ldd) = alpha op(A) B + beta D, op(A) = A (m x kk) or A^T (A kk x m);
+// small/medium sizes.
+void gemm_small(bool transA, int m, int n, int kk, double alpha, const double* A, int64_t lda,
+                const double* B, int64_t ldb, double beta, double* D, int64_t ldd,
+                hipStream_t st);
 
 // D (m x n, ldd) = A (m x kk, lda) B (kk x n, ldb), small/medium sizes.
 void gemm_nn(int m, int n, int kk, const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -201,6 +213,7 @@ struct CholInfo {
   int kept;
   int idx[16];
   int ok;
+  double rmin;   // smallest independence ratio sqrt(d_j / G_jj) of a kept column
 };
 void chol_deflate(int b, const double* G, int64_t ldg, const double* norm0, double defl_v,
                   double defl_b, double* Rinv, CholInfo* info, hipStream_t st);
@@ -221,10 +234,11 @@ struct OrthScratch {
   double* Rinv;   // 256
   CholInfo* info; // device
   CholInfo* host; // pinned host copy
+  int cgs_passes; // out: Gram-Schmidt passes made against V (2 or 3)
 };
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
-                         int64_t ldw, int ncols, double defl, const OrthScratch& s, int* idx,
+                         int64_t ldw, int ncols, double defl, OrthScratch& s, int* idx,
                          hipStream_t st);
 // W[:, 0:kept] = W[:, idx] * Rinv (kept x kept upper triangular), also for MW.
 void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, double* W,
@@ -257,6 +271,14 @@ struct TimeOps {
 void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64_t ldqb,
                 const double* F2, int64_t ldf, const TimeOps& t, double* Z, int64_t ldz,
                 hipStream_t st);
+// The same recurrences for a full right-hand side G (k x nt, ldg).
+void time_sweep_full(int k, int nt, const double* lam, const double* G, int64_t ldg,
+                     const TimeOps& t, double* Z, int64_t ldz, hipStream_t st);
+// R (k x nt, ldr) = beta F2^T - KY Mt^T - Y Dt^T with KY = Km Y (both ldy):
+// the residual of the reduced equation.
+void reduced_residual(int k, int nt, int p, const double* beta, int64_t ldb, const double* F2,
+                      int64_t ldf, const double* KY, const double* Y, int64_t ldy,
+                      const TimeOps& t, double* R, int64_t ldr, hipStream_t st);
 // out (nt x k, ldo) = scale * T A^T for A (k x nt) and a lower-bidiagonal T
 // (diag td, sub ts): out[l, i] = scale (td[l] A[i, l] + ts[l-1] A[i, l-1]).
 void bidiag_right(int k, int nt, const double* A, int64_t lda, const double* td, const double* ts,
