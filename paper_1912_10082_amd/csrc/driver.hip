@@ -513,7 +513,7 @@ struct sts_problem {
   // small scratch
   DevBuf gram, tn_part, rinv, cinfo, norm0, smallv, Lb, T1, okflag;
   // reduced solve
-  DevBuf lam, Q, eig_a, eig_tau, eig_e, eig_meta, qb, Z, Y, RB;
+  DevBuf lam, Q, eig_work, eig_meta, qb, Z, Y, RB;
   // residual
   DevBuf BT, res_part;
   double* pinned = nullptr;   // 64 doubles
@@ -538,7 +538,8 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t budget) {
   const int64_t ld = P->ldv;
   const int64_t nt = P->nt;
   const int64_t bytes = 3 * ld * kc * 8 + 2 * kc * kc * 8 + kc * P->p * 8 +   // V MV KV Kred Mred beta
-                        kc * kc * 8 * 2 + kc * 8 * 3 + 3 * kc * nt * 8 +       // Q eig_a, vectors, Z Y RB
+                        kc * kc * 8 + eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8 +
+                        kc * 8 * 3 + 3 * kc * nt * 8 +                         // Q, eigen work, Z Y RB
                         nt * (P->p + 2 * kc) * 8;                              // BT
   STS_REQUIRE(budget <= 0 || bytes <= budget, STS_E_NOMEM,
               "basis of " + std::to_string(kc) + " columns needs " + std::to_string(bytes) +
@@ -578,9 +579,7 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t budget) {
   }
   P->lam.alloc(kc * 8);
   P->Q.alloc(kc * kc * 8);
-  P->eig_a.alloc(kc * kc * 8);
-  P->eig_tau.alloc(kc * 8);
-  P->eig_e.alloc(kc * 8);
+  P->eig_work.alloc(eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8);
   P->eig_meta.alloc(64);
   P->qb.alloc(kc * 4 * 8);
   P->Z.alloc(kc * nt * 8);
@@ -648,10 +647,8 @@ double reduced_solve(sts_problem* P, int64_t ks, int64_t b) {
   hipStream_t st = P->stream;
   const int64_t kc = P->kcap, nt = P->nt;
   EigWork ew{};
-  ew.a = P->eig_a.d();
-  ew.tau = P->eig_tau.d();
-  ew.e = P->eig_e.d();
-  ew.meta = static_cast<int*>(P->eig_meta.p);
+  ew.base = P->eig_work.d();
+  ew.status = static_cast<int*>(P->eig_meta.p);
   sym_eig((int)ks, P->Kred.d(), kc, P->lam.d(), P->Q.d(), kc, ew, st);
   gemm_tn(ks, (int)ks, P->p, P->Q.d(), kc, P->beta.d(), kc, P->qb.d(), kc, P->tn_part.d(), st);
   time_sweep((int)ks, (int)nt, P->p, P->lam.d(), P->qb.d(), kc, P->F2.d(), nt, time_ops(P),
@@ -687,7 +684,7 @@ double reduced_solve(sts_problem* P, int64_t ks, int64_t b) {
   STS_HIP(hipMemcpyAsync(P->pinned, P->eig_meta.p, sizeof(int), hipMemcpyDeviceToHost, st));
   STS_HIP(hipStreamSynchronize(st));
   std::memcpy(&status, P->pinned, sizeof(int));
-  STS_REQUIRE(status == 0, STS_E_NUMERIC, "reduced eigensolver did not converge");
+  STS_REQUIRE(status == 0, STS_E_NUMERIC, "reduced matrix is not finite");
   if (b > 0) fetch(P, P->smallv.d(), 1, &res2);
   ++P->checks;
   return std::sqrt(std::max(res2, 0.0)) / P->fnorm;
@@ -785,10 +782,8 @@ int64_t numerical_rank(sts_problem* P) {
   gy.alloc(ks * ks * 8);
   gemm_nn((int)ks, (int)ks, (int)nt, P->Y.d(), kc, P->Z.d(), nt, gy.d(), ks, st);
   EigWork ew{};
-  ew.a = P->eig_a.d();
-  ew.tau = P->eig_tau.d();
-  ew.e = P->eig_e.d();
-  ew.meta = static_cast<int*>(P->eig_meta.p);
+  ew.base = P->eig_work.d();
+  ew.status = static_cast<int*>(P->eig_meta.p);
   DevBuf qtmp;
   qtmp.alloc(ks * ks * 8);
   DevBuf ltmp;
@@ -1454,15 +1449,13 @@ sts_status sts_sym_eig(int64_t k, const double* A, int64_t lda, double* lam, dou
     hipStream_t st = static_cast<hipStream_t>(stream);
     Scratch sc;
     EigWork w{};
-    w.a = sc.get<double>(k * k);
-    w.tau = sc.get<double>(k);
-    w.e = sc.get<double>(k);
-    w.meta = sc.get<int>(16);
+    w.base = sc.get<double>(eig_work_doubles((int)k));
+    w.status = sc.get<int>(16);
     sym_eig((int)k, A, lda, lam, Q, ldq, w, st);
     int status = 0;
-    STS_HIP(hipMemcpyAsync(&status, w.meta, sizeof(int), hipMemcpyDeviceToHost, st));
+    STS_HIP(hipMemcpyAsync(&status, w.status, sizeof(int), hipMemcpyDeviceToHost, st));
     STS_HIP(hipStreamSynchronize(st));
-    STS_REQUIRE(status == 0, STS_E_NUMERIC, "QL iteration did not converge");
+    STS_REQUIRE(status == 0, STS_E_NUMERIC, "matrix is not finite");
   });
 }
 

@@ -6,11 +6,8 @@
 // independent lower-bidiagonal recurrences in time, one per eigencomponent:
 //   (Dt + lam_i Mt) z_i = (Q^T beta F2^T)[i, :],   Y = Q Z.
 //
-// sym_eig: one work-group reduces Km to tridiagonal form with Householder
-// reflectors, accumulates them into Q, then runs implicit-shift QL on the
-// tridiagonal.  The QL scalar recurrence is inherently sequential; it runs in
-// one lane of wave 0 and publishes each sweep's plane rotations in LDS while
-// the other 15 waves apply the previous sweep's rotations to the rows of Q.
+// This file holds the time sweep, the reduced residual and the small dense
+// helpers; the eigendecomposition itself is in eig.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -21,285 +18,10 @@ namespace sts {
 
 namespace {
 
-constexpr int kEigThreads = 1024;
-constexpr int kEigMaxK = 2048;
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-// Block sum over 1024 threads (16 waves), fixed order; result broadcast.
-__device__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wv] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < kEigThreads / 64; ++i) t += red[i];
-  return t;
-}
-
-struct EigArgs {
-  int k;
-  const double* A;
-  int64_t lda;
-  double* lam;
-  double* Q;
-  int64_t ldq;
-  double* a;      // k x k working copy
-  double* tau;
-  double* e;
-  int* status;
-};
-
-__global__ __launch_bounds__(kEigThreads) void sym_eig_kernel(EigArgs g) {
-  __shared__ double v[kEigMaxK];
-  __shared__ double w[kEigMaxK];
-  __shared__ double red[kEigThreads / 64];
-  __shared__ double rc[2][kEigMaxK];     // rotation cosines (double-buffered sweeps)
-  __shared__ double rs[2][kEigMaxK];     // rotation sines
-  __shared__ int sweep_hi[2], sweep_cnt[2];
-  __shared__ int done_flag;
-
-  const int k = g.k;
-  const int tid = threadIdx.x;
-  double* a = g.a;
-  const int64_t lda = k;
-
-  // working copy (symmetrised)
-  for (int64_t idx = tid; idx < (int64_t)k * k; idx += kEigThreads) {
-    const int i = idx % k, j = idx / k;
-    a[idx] = 0.5 * (g.A[i + j * g.lda] + g.A[j + i * g.lda]);
-  }
-  __syncthreads();
-
-  // ---- Householder tridiagonalisation (lower), reflectors kept in a ----
-  for (int j = 0; j + 2 < k; ++j) {
-    const int n2 = k - j - 1;                   // trailing size
-    double* col = a + (j + 1) + (int64_t)j * lda;
-    double sig = 0.0;
-    for (int i = 1 + tid; i < n2; i += kEigThreads) sig += col[i] * col[i];
-    sig = block_sum(sig, red);
-    const double alpha = col[0];
-    double tau = 0.0, beta = alpha, scale = 0.0;
-    if (sig > 0.0) {
-      const double nrm = sqrt(alpha * alpha + sig);
-      beta = alpha <= 0.0 ? nrm : -nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();
-    for (int i = tid; i < n2; i += kEigThreads) v[i] = (i == 0) ? 1.0 : col[i] * scale;
-    __syncthreads();
-    if (tid == 0) {
-      g.tau[j] = tau;
-      g.e[j] = beta;
-    }
-    if (tau != 0.0) {
-      // p = tau * A22 v  (A22 symmetric, full storage), four partial sums per row
-      double* A22 = a + (j + 1) + (int64_t)(j + 1) * lda;
-      for (int base = 0; base < n2; base += kEigThreads / 4) {
-        const int i = base + (tid & (kEigThreads / 4 - 1));
-        const int part = tid / (kEigThreads / 4);
-        double s = 0.0;
-        if (i < n2) {
-          const int c0 = (n2 * part) / 4, c1 = (n2 * (part + 1)) / 4;
-          for (int c = c0; c < c1; ++c) s += A22[i + (int64_t)c * lda] * v[c];
-        }
-        __syncthreads();
-        rc[0][tid] = s;
-        __syncthreads();
-        if (part == 0 && i < n2) {
-          const int q = tid & (kEigThreads / 4 - 1);
-          w[i] = tau * ((rc[0][q] + rc[0][q + 256]) + (rc[0][q + 512] + rc[0][q + 768]));
-        }
-        __syncthreads();
-      }
-      // w <- p - (tau/2)(p.v) v
-      double pv = 0.0;
-      for (int i = tid; i < n2; i += kEigThreads) pv += w[i] * v[i];
-      pv = block_sum(pv, red);
-      const double kk = -0.5 * tau * pv;
-      __syncthreads();
-      for (int i = tid; i < n2; i += kEigThreads) w[i] += kk * v[i];
-      __syncthreads();
-      // A22 -= v w^T + w v^T
-      for (int64_t idx = tid; idx < (int64_t)n2 * n2; idx += kEigThreads) {
-        const int i = idx % n2, c = idx / n2;
-        A22[i + (int64_t)c * lda] -= v[i] * w[c] + w[i] * v[c];
-      }
-    }
-    // keep the reflector (v[0] = 1 implicit) below the diagonal
-    for (int i = 1 + tid; i < n2; i += kEigThreads) col[i] = v[i];
-    __syncthreads();
-  }
-  // diagonal and last sub-diagonal
-  for (int i = tid; i < k; i += kEigThreads) g.lam[i] = a[i + (int64_t)i * lda];
-  if (tid == 0) {
-    if (k >= 2) g.e[k - 2] = a[(k - 1) + (int64_t)(k - 2) * lda];
-    g.e[k - 1] = 0.0;
-  }
-  __syncthreads();
-
-  // ---- accumulate Q = H_0 H_1 ... H_{k-3} (backward) ----
-  double* Q = g.Q;
-  const int64_t ldq = g.ldq;
-  for (int64_t idx = tid; idx < (int64_t)k * k; idx += kEigThreads) {
-    const int i = idx % k, j = idx / k;
-    Q[i + j * ldq] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = k - 3; j >= 0; --j) {
-    const double tau = g.tau[j];
-    if (tau == 0.0) continue;
-    const int n2 = k - j - 1;
-    const double* col = a + (j + 1) + (int64_t)j * lda;
-    for (int i = tid; i < n2; i += kEigThreads) v[i] = (i == 0) ? 1.0 : col[i];
-    __syncthreads();
-    double* Q22 = Q + (j + 1) + (int64_t)(j + 1) * ldq;
-    // u_c = tau * sum_i v_i Q22[i, c]  (one wave per column)
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int c = wv; c < n2; c += kEigThreads / 64) {
-      double s = 0.0;
-      for (int i = lane; i < n2; i += 64) s += v[i] * Q22[i + (int64_t)c * ldq];
-      s = wave_sum(s);
-      if (lane == 0) w[c] = tau * s;
-    }
-    __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)n2 * n2; idx += kEigThreads) {
-      const int i = idx % n2, c = idx / n2;
-      Q22[i + (int64_t)c * ldq] -= v[i] * w[c];
-    }
-    __syncthreads();
-  }
-
-  // ---- implicit QL on (d = lam, e), rotations applied to Q's columns ----
-  // d, e in LDS (v, w reused); wave 0 lane 0 produces sweeps, waves 1.. apply.
-  double* d = v;
-  double* e = w;
-  for (int i = tid; i < k; i += kEigThreads) {
-    d[i] = g.lam[i];
-    e[i] = g.e[i];
-  }
-  if (tid == 0) {
-    done_flag = 0;
-    sweep_cnt[0] = sweep_cnt[1] = 0;
-  }
-  __syncthreads();
-  const int wv = tid >> 6;
-  int l = 0, iter = 0, failed = 0;
-  int buf = 0;
-  const double eps = 1.1102230246251565e-16;
-  for (;;) {
-    if (wv == 0) {
-      if (tid == 0) {
-        // find the next sweep: advance l past converged eigenvalues
-        int produced = 0;
-        while (!produced && l < k) {
-          int m = l;
-          for (; m < k - 1; ++m) {
-            const double dd = fabs(d[m]) + fabs(d[m + 1]);
-            if (fabs(e[m]) <= eps * dd) break;
-          }
-          if (m == l) {
-            ++l;
-            iter = 0;
-            continue;
-          }
-          if (++iter > 60) {
-            failed = 1;
-            l = k;
-            break;
-          }
-          double gg = (d[l + 1] - d[l]) / (2.0 * e[l]);
-          double r = sqrt(gg * gg + 1.0);
-          gg = d[m] - d[l] + e[l] / (gg + (gg >= 0.0 ? r : -r));
-          double s = 1.0, c = 1.0, p = 0.0;
-          int cnt = 0;
-          bool zero_r = false;
-          for (int i = m - 1; i >= l; --i) {
-            const double f = s * e[i], b = c * e[i];
-            r = sqrt(f * f + gg * gg);
-            e[i + 1] = r;
-            if (r == 0.0) {
-              d[i + 1] -= p;
-              e[m] = 0.0;
-              zero_r = true;
-              break;
-            }
-            const double rinv = 1.0 / r;
-            s = f * rinv;
-            c = gg * rinv;
-            gg = d[i + 1] - p;
-            r = (d[i] - gg) * s + 2.0 * c * b;
-            p = s * r;
-            d[i + 1] = gg + p;
-            gg = c * r - b;
-            rc[buf][cnt] = c;
-            rs[buf][cnt] = s;
-            ++cnt;
-          }
-          if (!zero_r) {
-            d[l] -= p;
-            e[l] = gg;
-            e[m] = 0.0;
-          }
-          sweep_hi[buf] = m - 1;
-          sweep_cnt[buf] = cnt;
-          produced = 1;
-        }
-        if (!produced) {
-          sweep_cnt[buf] = 0;
-          done_flag = 1;
-        }
-      }
-    } else {
-      // apply the sweep in the other buffer to the rows of Q
-      const int ob = buf ^ 1;
-      const int cnt = sweep_cnt[ob];
-      if (cnt > 0) {
-        const int hi = sweep_hi[ob];
-        for (int row = tid - 64; row < k; row += kEigThreads - 64) {
-          double* qr = Q + row;
-          double cur = qr[(int64_t)(hi + 1) * ldq];
-          int i = hi;
-          int t = 0;
-          while (t < cnt) {
-            // batch of up to 8 independent loads ahead of the rotations
-            double nx[8];
-            const int nb = min(8, cnt - t);
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (u < nb) nx[u] = qr[(int64_t)(i - u) * ldq];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (u < nb) {
-                const double c = rc[ob][t + u], s = rs[ob][t + u];
-                const double av = nx[u];
-                qr[(int64_t)(i - u + 1) * ldq] = s * av + c * cur;
-                cur = c * av - s * cur;
-              }
-            i -= nb;
-            t += nb;
-          }
-          qr[(int64_t)(i + 1) * ldq] = cur;
-        }
-      }
-    }
-    __syncthreads();
-    const int finished = done_flag;
-    if (tid == 0) {
-      sweep_cnt[buf ^ 1] = 0;     // consumed
-    }
-    __syncthreads();
-    if (finished) break;
-    buf ^= 1;
-  }
-  for (int i = tid; i < k; i += kEigThreads) g.lam[i] = d[i];
-  if (tid == 0) *g.status = failed ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -474,23 +196,6 @@ __global__ __launch_bounds__(256) void cheap_res_kernel(int b, int nt, const dou
 
 }  // namespace
 
-void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_t ldq,
-             const EigWork& w, hipStream_t st) {
-  STS_REQUIRE(k >= 1 && k <= kEigMaxK, STS_E_INVALID, "sym_eig: order out of range");
-  EigArgs g{};
-  g.k = k;
-  g.A = A;
-  g.lda = lda;
-  g.lam = lam;
-  g.Q = Q;
-  g.ldq = ldq;
-  g.a = w.a;
-  g.tau = w.tau;
-  g.e = w.e;
-  g.status = w.meta;
-  sym_eig_kernel<<<1, kEigThreads, 0, st>>>(g);
-  STS_HIP(hipGetLastError());
-}
 
 void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64_t ldqb,
                 const double* F2, int64_t ldf, const TimeOps& t, double* Z, int64_t ldz,

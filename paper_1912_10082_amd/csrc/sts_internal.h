@@ -248,16 +248,17 @@ void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, d
 // reduced problem
 // ---------------------------------------------------------------------------
 
+constexpr int kEigMaxK = 2048;   // largest order of sym_eig
+constexpr int kEigNB = 16;       // panel width of the tridiagonalisation
+
 struct EigWork {
-  double* a;      // k x k working copy (ld k)
-  double* tau;    // k
-  double* e;      // k
-  double* rot;    // 2 * rot_cap (c, s) pairs
-  int* sweeps;    // 3 * sweep_cap (l, m, offset)
-  int* meta;      // [nsweeps, nrot, status]
-  int64_t rot_cap;
-  int sweep_cap;
+  double* base;   // eig_work_doubles(k) doubles of device scratch
+  int* status;    // device: 0, or 1 if the input was not finite
 };
+int64_t eig_work_doubles(int k);
+// Km Q = Q diag(lam) for a symmetric k x k matrix (ascending eigenvalues,
+// orthonormal Q): Householder tridiagonalisation, multisection, inverse
+// iteration, Rayleigh-Ritz correction, back-transformation.
 void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_t ldq,
              const EigWork& w, hipStream_t st);
 
