@@ -38,6 +38,7 @@ constexpr int kSect = 4;             // threads per eigenvalue in the multisecti
 constexpr double kEps = 1.1102230246251565e-16;
 constexpr double kClusterTol = 1e-8;
 constexpr int kInvIters = 3;
+constexpr int kLdsPanelMaxK = 480;   // orders whose tridiagonalisation panel fits in LDS
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -73,17 +74,32 @@ struct TriArgs {
   double* bounds;   // gl, gu, tnorm, pivmin
 };
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: lane l = i + 16 g supplies a = X[i][g] and
+// b = Y[g][i]; element q of the accumulator is (X Y)[4 q + g][i].
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// LP: the panel's reflectors V and images W live in LDS (orders up to
+// kLdsPanelMaxK), else in global scratch.
+template <bool LP>
 __global__ __launch_bounds__(kTT) void tridiag_kernel(TriArgs g) {
-  __shared__ double v[kEigMaxK];
-  __shared__ double y[kEigMaxK];
+  constexpr int VK = LP ? kLdsPanelMaxK : kEigMaxK;
+  __shared__ double v[VK];
+  __shared__ double y[VK];
+  __shared__ double cj[VK];
   __shared__ double part[kTT];
   __shared__ double red[kTT / 64];
   __shared__ double t12[2 * kEigNB];
+  __shared__ double panel[LP ? 2 * kLdsPanelMaxK * kEigNB : 1];
   const int k = g.k;
   const int tid = threadIdx.x;
   double* a = g.a;
-  double* vp = g.vp;
-  double* wp = g.wp;
+  double* vp = LP ? panel : g.vp;
+  double* wp = LP ? panel + kLdsPanelMaxK * kEigNB : g.wp;
+  const int ldp = LP ? kLdsPanelMaxK : k;
 
   double fin = 0.0;
   for (int64_t idx = tid; idx < (int64_t)k * k; idx += kTT) {
@@ -102,20 +118,18 @@ __global__ __launch_bounds__(kTT) void tridiag_kernel(TriArgs g) {
       const int j = j0 + jj;
       const int n2 = k - j - 1;
       double* col = a + (int64_t)j * k;
-      // column j, rows j..k-1, with the panel's earlier reflectors applied
+      // column j (rows j..k-1) with the panel's earlier reflectors applied,
+      // and the squared norm below row j+1
+      double sq = 0.0;
       for (int i = j + tid; i < k; i += kTT) {
         double s = col[i];
         for (int q = 0; q < jj; ++q)
-          s -= vp[i + (int64_t)q * k] * wp[j + (int64_t)q * k] +
-               wp[i + (int64_t)q * k] * vp[j + (int64_t)q * k];
-        col[i] = s;
+          s -= vp[i + q * ldp] * wp[j + q * ldp] + wp[i + q * ldp] * vp[j + q * ldp];
+        cj[i] = s;
+        if (i >= j + 2) sq += s * s;
       }
-      __syncthreads();
-      // reflector for x = col[j+1 .. k-1]
-      double sig = 0.0;
-      for (int i = j + 2 + tid; i < k; i += kTT) sig += col[i] * col[i];
-      sig = block_sum(sig, red);
-      const double alpha = col[j + 1];
+      const double sig = block_sum(sq, red);
+      const double alpha = cj[j + 1];
       double tau = 0.0, beta = alpha, scale = 0.0;
       if (sig > 0.0) {
         const double nrm = sqrt(alpha * alpha + sig);
@@ -123,21 +137,36 @@ __global__ __launch_bounds__(kTT) void tridiag_kernel(TriArgs g) {
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      for (int i = tid; i < n2; i += kTT) v[i] = (i == 0) ? 1.0 : col[j + 1 + i] * scale;
+      // reflector v (v_0 = 1), kept below the sub-diagonal of column j
+      for (int i = tid; i < n2; i += kTT) {
+        const double vi = (i == 0) ? 1.0 : cj[j + 1 + i] * scale;
+        v[i] = vi;
+        if (i > 0) col[j + 1 + i] = vi;
+      }
       if (tid == 0) {
-        g.d[j] = col[j];
+        g.d[j] = cj[j];
         g.e[j] = beta;
         g.tau[j] = tau;
       }
       __syncthreads();
-      for (int i = 1 + tid; i < n2; i += kTT) col[j + 1 + i] = v[i];
       if (tau == 0.0) {
         for (int i = tid; i < n2; i += kTT) {
-          vp[j + 1 + i + (int64_t)jj * k] = 0.0;
-          wp[j + 1 + i + (int64_t)jj * k] = 0.0;
+          vp[j + 1 + i + jj * ldp] = 0.0;
+          wp[j + 1 + i + jj * ldp] = 0.0;
         }
         __syncthreads();
         continue;
+      }
+      // t1 = W_p^T v, t2 = V_p^T v over rows j+1..k-1 (one wave per product)
+      {
+        const int wv = tid >> 6, lane = tid & 63;
+        for (int q = wv; q < 2 * jj; q += kTT / 64) {
+          const double* src = (q < jj ? wp : vp) + (q % jj) * ldp + (j + 1);
+          double s = 0.0;
+          for (int i = lane; i < n2; i += 64) s += src[i] * v[i];
+          s = wave_sum(s);
+          if (lane == 0) t12[q] = s;
+        }
       }
       // y = A22 v, A22 = a[j+1.., j+1..] as of the panel start
       const double* A22 = a + (j + 1) + (int64_t)(j + 1) * k;
@@ -157,23 +186,12 @@ __global__ __launch_bounds__(kTT) void tridiag_kernel(TriArgs g) {
         }
         __syncthreads();
       }
-      // t1 = W_p^T v, t2 = V_p^T v over rows j+1..k-1 (one wave per product)
-      {
-        const int wv = tid >> 6, lane = tid & 63;
-        for (int q = wv; q < 2 * jj; q += kTT / 64) {
-          const double* src = (q < jj ? wp : vp) + (int64_t)(q % jj) * k + (j + 1);
-          double s = 0.0;
-          for (int i = lane; i < n2; i += 64) s += src[i] * v[i];
-          s = wave_sum(s);
-          if (lane == 0) t12[q] = s;
-        }
-      }
-      __syncthreads();
+      // p = tau (y - V_p t1 - W_p t2); w = p - (tau / 2)(p . v) v
       double pv = 0.0;
       for (int i = tid; i < n2; i += kTT) {
         double s = y[i];
         for (int q = 0; q < jj; ++q)
-          s -= vp[j + 1 + i + (int64_t)q * k] * t12[q] + wp[j + 1 + i + (int64_t)q * k] * t12[jj + q];
+          s -= vp[j + 1 + i + q * ldp] * t12[q] + wp[j + 1 + i + q * ldp] * t12[jj + q];
         s *= tau;
         y[i] = s;
         pv += s * v[i];
@@ -181,21 +199,35 @@ __global__ __launch_bounds__(kTT) void tridiag_kernel(TriArgs g) {
       pv = block_sum(pv, red);
       const double kk = -0.5 * tau * pv;
       for (int i = tid; i < n2; i += kTT) {
-        vp[j + 1 + i + (int64_t)jj * k] = v[i];
-        wp[j + 1 + i + (int64_t)jj * k] = y[i] + kk * v[i];
+        vp[j + 1 + i + jj * ldp] = v[i];
+        wp[j + 1 + i + jj * ldp] = y[i] + kk * v[i];
       }
       __syncthreads();
     }
-    // trailing update: A[t0.., t0..] -= V W^T + W V^T
+    // trailing update A[t0.., t0..] -= [V W] [W V]^T on the matrix cores,
+    // one 16 x 16 tile per wave at a time
     const int t0 = j0 + jb;
     const int nt2 = k - t0;
-    for (int64_t idx = tid; idx < (int64_t)nt2 * nt2; idx += kTT) {
-      const int r = t0 + idx % nt2, c = t0 + idx / nt2;
-      double s = a[r + (int64_t)c * k];
-      for (int q = 0; q < jb; ++q)
-        s -= vp[r + (int64_t)q * k] * wp[c + (int64_t)q * k] +
-             wp[r + (int64_t)q * k] * vp[c + (int64_t)q * k];
-      a[r + (int64_t)c * k] = s;
+    const int tiles = (nt2 + 15) / 16;
+    const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
+    for (int tt = wv; tt < tiles * tiles; tt += kTT / 64) {
+      const int r0 = t0 + (tt % tiles) * 16, c0 = t0 + (tt / tiles) * 16;
+      const int r = r0 + li, c = c0 + li;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < 2 * jb; k0 += 4) {
+        const int q = k0 + lg;
+        double xa = 0.0, yb = 0.0;
+        if (q < 2 * jb) {
+          if (r < k) xa = q < jb ? vp[r + q * ldp] : wp[r + (q - jb) * ldp];
+          if (c < k) yb = q < jb ? wp[c + q * ldp] : vp[c + (q - jb) * ldp];
+        }
+        acc = mfma(xa, yb, acc);
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int rr = r0 + 4 * qq + lg;
+        if (rr < k && c < k) a[rr + (int64_t)c * k] -= acc[qq];
+      }
     }
     __syncthreads();
   }
@@ -523,7 +555,8 @@ void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_
   double* lu = p;
 
   TriArgs t{k, A, lda, w.status, a, d, e, tau, vp, wp, bounds};
-  tridiag_kernel<<<1, kTT, 0, st>>>(t);
+  if (k <= kLdsPanelMaxK) tridiag_kernel<true><<<1, kTT, 0, st>>>(t);
+  else tridiag_kernel<false><<<1, kTT, 0, st>>>(t);
   STS_HIP(hipGetLastError());
   const int nthreads = k * kSect;
   bisect_kernel<<<(nthreads + 255) / 256, 256, 0, st>>>(k, d, e, bounds, lam);

@@ -124,7 +124,7 @@ def test_m_orthonormalize_properties():
 
 # ---------------------------------------------------------------- a6: reduced eigensolve
 
-@pytest.mark.parametrize("k", [1, 2, 5, 40, 211])
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 17, 40, 211, 497])
 def test_sym_eig_matches_lapack(k):
     Km, _ = wl.random_spd_pencil(k, seed=k)
     lam, Q = sts.sym_eig(dev(Km))
