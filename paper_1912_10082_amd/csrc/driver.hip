@@ -400,7 +400,7 @@ struct CGRunner {
 struct MGRunner {
   MGWork w{};
   PollLoop poll;
-  DevBuf levels, vecs, scal, parts;
+  DevBuf levels, vecs, scal, parts, dst;
   int expect = 12;   // iterations the last run needed (first chunk length)
 
   // Allocate for the plan; x / ldx are set per run.
@@ -426,10 +426,6 @@ struct MGRunner {
     w.p[0] = v + 2 * w.ld[0] * kMaxCols;
     w.p[1] = v + 3 * w.ld[0] * kMaxCols;
     w.q = v + 4 * w.ld[0] * kMaxCols;
-    if (plan.nlev == 0) {
-      // the coarse kernel works on the finest level directly
-      w.b[0] = v;
-    }
     w.max_tiles = mg_max_tiles(plan);
     scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
     w.scal = static_cast<CGScal*>(scal.p);
@@ -438,6 +434,12 @@ struct MGRunner {
     w.part_rz = w.part_rr + (size_t)w.max_tiles * kMaxCols;
     w.part_pq = w.part_rz + (size_t)w.max_tiles * kMaxCols;
     w.alpha = w.part_pq + (size_t)w.max_tiles * kMaxCols;
+    const int m = plan.exact;
+    std::vector<double> tab((size_t)m * (m + 1));
+    mg_dst_table(m, tab.data());
+    dst.alloc(tab.size() * 8);
+    STS_HIP(hipMemcpy(dst.p, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
+    w.dst = dst.d();
     poll.init();
   }
 

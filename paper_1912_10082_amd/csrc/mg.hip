@@ -1,30 +1,41 @@
 // Multigrid-preconditioned conjugate gradients for the 2-D P1 stiffness.
 //
 // The inner solves with Kx (the negative powers of the extended Krylov space,
-// Sec. 4) dominate the solver, and unpreconditioned CG needs O(1/h) iterations
-// for them.  On the uniform Courant triangulation the P1 spaces of the meshes
-// h, 2h, 4h, ... are nested: the prolongation P is P1 interpolation (coarse
-// values at coincident nodes, the mean of the two end points at midpoints of
-// horizontal, vertical and SW-NE edges) and the Galerkin coarse operator
-// P^T Kx P is again mu (4; -1, -1, -1, -1) on the coarse mesh.  The
-// preconditioner is one symmetric V-cycle started from zero: two damped-Jacobi
-// sweeps (u += c (b - K u), c = omega / (4 mu)) before and after each coarse
-// correction, restriction P^T, and the levels with at most kCoarseMax nodes
-// per direction handled by one work-group in LDS, down to one node solved
-// exactly.  Pre- and post-smoothing are adjoint, so the V-cycle is a fixed
-// symmetric positive definite operator and the outer iteration is ordinary
-// preconditioned CG.
+// Sec. 4) dominate the solver, and unpreconditioned CG needs O(1/h)
+// iterations for them.  On the uniform Courant triangulation the P1 spaces of
+// the meshes h, 2h, 4h, ... are nested: the prolongation P is P1
+// interpolation (coarse values at coincident nodes, the mean of the two end
+// points at midpoints of horizontal, vertical and SW-NE edges) and the
+// Galerkin coarse operator P^T Kx P is again mu (4; -1, -1, -1, -1) on the
+// coarse mesh.
 //
-// Launches per PCG iteration: per tiled level a "down" (two sweeps from zero,
-// residual, restriction -- recomputed on LDS halos, only the restricted
-// right-hand side is stored) and an "up" (pre-smoothed values recomputed from
-// the level's right-hand side, interpolated correction, two sweeps), one
+// The preconditioner is one V-cycle started from zero:
+//  - smoothing: kNu steps of Chebyshev iteration on D^{-1} Kx (D = 4 mu)
+//    for the interval [1/2, 2] of its spectrum, before and after each coarse
+//    correction (the same polynomial both times, so the two are adjoint);
+//  - restriction P^T of the residual, prolongation P of the correction;
+//  - levels above kMGCoarseMax nodes per direction run as tiled launches; the
+//    coarsest level (at most kMGCoarseMax) is solved exactly in one
+//    work-group per column by the fast sine transform: with
+//    T = tridiag(-1, 2, -1) = S diag(l) S (S the orthonormal, symmetric DST-I
+//    matrix), Kx U = mu (T U + U T) for the nodal array U, so
+//    U = S [(S B S) / (mu (l_y + l_x))] S -- four small GEMMs on the matrix
+//    cores.
+// The V-cycle is a fixed symmetric positive definite operator, so the outer
+// iteration is ordinary preconditioned CG.
+//
+// Launches per PCG iteration: per tiled level a "down" (smoothing from
+// zero, residual, restriction -- recomputed on LDS halos, only the restricted
+// right-hand side is stored) and an "up" (pre-smoothed values recomputed
+// from the level's right-hand side, interpolated correction, smoothing), one
 // coarse launch, and two PCG launches: A {beta from (r, z); p = z + beta p;
 // q = K p; (p, q)} and B {alpha = rho / (p, q); x += alpha p; r -= alpha q;
-// (r, r)}.  Global sums are per-tile partials that every work-group of the
-// consuming launch adds in the same fixed order, so all of them take the same
-// decision without atomics or a grid barrier.
+// (r, r)}.  Global sums are per-tile partials that the consuming work-groups
+// add in the same fixed order, so they all take the same decision without
+// atomics or a grid barrier.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 #include "sts_internal.h"
 
@@ -35,12 +46,8 @@ namespace {
 constexpr int kT = 256;          // threads per work-group of the level and PCG kernels
 constexpr int CX = 32, CY = 8;   // coarse nodes per level-kernel tile (fine footprint 64 x 16)
 constexpr int TX = 64, TY = 16;  // fine nodes per PCG-kernel tile
-constexpr double kOmega = 0.8;   // damped-Jacobi weight (smoothing factor 0.6 for this stencil)
+constexpr int kNu = kMGNu;       // smoothing steps
 constexpr int kCT = 1024;        // threads of the coarse kernel
-constexpr int kCoarseStore = 5760;                              // >= sum (n+2)^2, n = 63, 31, ..., 1
-constexpr int kCoarseTmp = (kMGCoarseMax + 2) * (kMGCoarseMax + 2);
-constexpr int kCoarseLevels = 8;
-constexpr int kBottomSweeps = 20;   // a coarsest level that does not halve (even n > 1)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -89,6 +96,64 @@ __device__ __forceinline__ double interp(const double* ec, int CW, int cox, int 
   return 0.5 * (c[0] + c[CW + 1]);            // SW-NE diagonal edge
 }
 
+// Chebyshev smoothing coefficients: d_0 = c_0 r_0 / D and, for k >= 1,
+// d_k = a_k d_{k-1} + c_k r_k / D with r_k = b - K u_k; u_{k+1} = u_k + d_k.
+struct Smooth {
+  double a[kNu];
+  double c[kNu];
+};
+
+// An LDS region of W x H fine nodes with global origin (ox, oy) on an n x n
+// grid; `shrink` excludes a band at the region's edge (where neighbours are
+// missing), nodes outside the domain are excluded (they stay zero).
+template <int W, int H>
+struct Region {
+  int ox, oy, n;
+  __device__ __forceinline__ bool inside(int i, int shrink) const {
+    const int lx = i % W, ly = i / W;
+    const int gx = ox + lx, gy = oy + ly;
+    return lx >= shrink && lx < W - shrink && ly >= shrink && ly < H - shrink && gx >= 0 &&
+           gx < n && gy >= 0 && gy < n;
+  }
+};
+
+// One smoothing step with ping-pong buffers: d = a d + c (b - K u) / D and
+// u' = u + d on the nodes at least `shrink` inside the region; one barrier.
+template <int W, int H>
+__device__ __forceinline__ void cheb_step(const Region<W, H>& R, int shrink, double ak, double ck,
+                                          double inv_d, const double* bs, const double* u,
+                                          double* un, double* ds, double mu) {
+  for (int i = threadIdx.x; i < W * H; i += kT) {
+    if (R.inside(i, shrink)) {
+      const double d = ak * ds[i] + ck * inv_d * (bs[i] - k5(u, i, W, mu));
+      ds[i] = d;
+      un[i] = u[i] + d;
+    }
+  }
+  __syncthreads();
+}
+
+// kNu steps from u = 0; step k on shrink k.  Returns the buffer index of u,
+// which is valid on shrink kNu - 1.
+template <int W, int H>
+__device__ __forceinline__ int presmooth(const Region<W, H>& R, const Smooth& sm, double inv_d,
+                                         const double* bs, double (*us)[W * H], double* ds,
+                                         double mu) {
+  for (int i = threadIdx.x; i < W * H; i += kT) {
+    const double v = R.inside(i, 0) ? sm.c[0] * inv_d * bs[i] : 0.0;
+    ds[i] = v;
+    us[0][i] = v;
+    us[1][i] = v;   // keeps zeros outside the domain in both buffers
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k = 1; k < kNu; ++k) {
+    cheb_step<W, H>(R, k, sm.a[k], sm.c[k], inv_d, bs, us[cur], us[cur ^ 1], ds, mu);
+    cur ^= 1;
+  }
+  return cur;
+}
+
 struct LevelArgs {
   int nf, nc;          // fine / coarse nodes per direction (nf = 2 nc + 1)
   int64_t ldf, ldc;    // column strides
@@ -101,71 +166,66 @@ struct LevelArgs {
   int cols[kMaxCols];
   const CGScal* st;    // per-column activity, may be null (all active)
   double mu;
+  Smooth sm;
   double* part;        // up: per-tile (b, e), may be null
   int max_tiles;
 };
 
 // ---------------------------------------------------------------------------
-// down: u2 = two sweeps from zero = c (2 b - c K b); res = b - K u2;
-// b_c = P^T res at the tile's coarse nodes.  Fine region of the tile:
-// [2 cx0 - 2, 2 cx0 + 2 CX + 4) in x (likewise y).
+// down: u = smoothing from zero; res = b - K u; b_c = P^T res at the tile's
+// coarse nodes.  Fine region [2 cx0 - kNu, 2 cx0 + 2 CX + kNu] per direction.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
-  constexpr int W = 2 * CX + 6, H = 2 * CY + 6;
+  constexpr int W = 2 * CX + 1 + 2 * kNu, H = 2 * CY + 1 + 2 * kNu;
   __shared__ double bs[W * H];
-  __shared__ double us[W * H];
+  __shared__ double us[2][W * H];
+  __shared__ double ds[W * H];
   const int ntiles = a.ntx * a.nty;
   const int lin = xcd_remap(blockIdx.x, a.nlaunch * ntiles);
   const int t = lin / a.nlaunch, col = a.cols[lin % a.nlaunch];
   if (a.st && !a.st[col].active) return;
   const int cx0 = (t % a.ntx) * CX, cy0 = (t / a.ntx) * CY;
   const int nf = a.nf, nc = a.nc;
-  const int ox = 2 * cx0 - 2, oy = 2 * cy0 - 2;
-  const double mu = a.mu, cw = kOmega / (4.0 * mu);
+  const Region<W, H> R{2 * cx0 - kNu, 2 * cy0 - kNu, nf};
+  const double mu = a.mu, inv_d = 1.0 / (4.0 * mu);
   const double* bf = a.bf + (size_t)col * a.ldf;
   for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int gx = ox + i % W, gy = oy + i / W;
+    const int gx = R.ox + i % W, gy = R.oy + i / W;
     bs[i] = (gx >= 0 && gx < nf && gy >= 0 && gy < nf) ? bf[(size_t)gy * nf + gx] : 0.0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int lx = i % W, ly = i / W, gx = ox + lx, gy = oy + ly;
-    double v = 0.0;
-    if (lx >= 1 && lx < W - 1 && ly >= 1 && ly < H - 1 && gx >= 0 && gx < nf && gy >= 0 &&
-        gy < nf)
-      v = cw * (2.0 * bs[i] - cw * k5(bs, i, W, mu));
-    us[i] = v;
-  }
-  __syncthreads();
-  // residual, in place over b (each entry reads only its own b)
+  const int cur = presmooth<W, H>(R, a.sm, inv_d, bs, us, ds, mu);
+  // residual on shrink kNu into ds
   for (int i = threadIdx.x; i < W * H; i += kT) {
     const int lx = i % W, ly = i / W;
-    if (lx >= 2 && lx < W - 2 && ly >= 2 && ly < H - 2) bs[i] -= k5(us, i, W, mu);
+    if (lx >= kNu && lx < W - kNu && ly >= kNu && ly < H - kNu)
+      ds[i] = bs[i] - k5(us[cur], i, W, mu);
   }
   __syncthreads();
   double* bc = a.bc + (size_t)col * a.ldc;
   for (int i = threadIdx.x; i < CX * CY; i += kT) {
     const int I = cx0 + i % CX, J = cy0 + i / CX;
     if (I < nc && J < nc) {
-      const int q = (2 * (J - cy0) + 3) * W + (2 * (I - cx0) + 3);
+      const int q = (2 * (J - cy0) + 1 + kNu) * W + (2 * (I - cx0) + 1 + kNu);
       bc[(size_t)J * nc + I] =
-          bs[q] + 0.5 * ((bs[q - 1] + bs[q + 1]) + (bs[q - W] + bs[q + W]) +
-                         (bs[q - W - 1] + bs[q + W + 1]));
+          ds[q] + 0.5 * ((ds[q - 1] + ds[q + 1]) + (ds[q - W] + ds[q + W]) +
+                         (ds[q - W - 1] + ds[q + W + 1]));
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// up: u = u2 + P e_c; two sweeps; e on the tile's fine nodes
-// [2 cx0, x1) x [2 cy0, y1) (the last tile in a direction runs to nf).
-// Fine region [2 cx0 - 3, 2 cx0 + 2 CX + 4), coarse [cx0 - 2, cx0 + CX + 2).
+// up: u = pre-smoothed u (recomputed) + P e_c; smoothing; e on the tile's
+// fine nodes [2 cx0, x1) x [2 cy0, y1) (the last tile in a direction runs to
+// nf).  Fine region [2 cx0 - (2 kNu - 1), ...), coarse [cx0 - kNu, ...).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
-  constexpr int W = 2 * CX + 7, H = 2 * CY + 7;
-  constexpr int EW = CX + 4, EH = CY + 4;
+  constexpr int HL = 2 * kNu - 1;
+  constexpr int W = 2 * CX + 1 + 2 * HL, H = 2 * CY + 1 + 2 * HL;
+  constexpr int EW = CX + 2 * kNu, EH = CY + 2 * kNu;
   __shared__ double bs[W * H];
-  __shared__ double us[W * H];
-  __shared__ double vs[W * H];
+  __shared__ double us[2][W * H];
+  __shared__ double ds[W * H];
   __shared__ double es[EW * EH];
   __shared__ double red[kT / 64];
   const int ntiles = a.ntx * a.nty;
@@ -174,13 +234,13 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   if (a.st && !a.st[col].active) return;
   const int cx0 = (t % a.ntx) * CX, cy0 = (t / a.ntx) * CY;
   const int nf = a.nf, nc = a.nc;
-  const int ox = 2 * cx0 - 3, oy = 2 * cy0 - 3;
-  const int cox = cx0 - 2, coy = cy0 - 2;
-  const double mu = a.mu, cw = kOmega / (4.0 * mu);
+  const Region<W, H> R{2 * cx0 - HL, 2 * cy0 - HL, nf};
+  const int cox = cx0 - kNu, coy = cy0 - kNu;
+  const double mu = a.mu, inv_d = 1.0 / (4.0 * mu);
   const double* bf = a.bf + (size_t)col * a.ldf;
   const double* ecg = a.ec + (size_t)col * a.ldc;
   for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int gx = ox + i % W, gy = oy + i / W;
+    const int gx = R.ox + i % W, gy = R.oy + i / W;
     bs[i] = (gx >= 0 && gx < nf && gy >= 0 && gy < nf) ? bf[(size_t)gy * nf + gx] : 0.0;
   }
   for (int i = threadIdx.x; i < EW * EH; i += kT) {
@@ -188,33 +248,32 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
     es[i] = (I >= 0 && I < nc && J >= 0 && J < nc) ? ecg[(size_t)J * nc + I] : 0.0;
   }
   __syncthreads();
+  int cur = presmooth<W, H>(R, a.sm, inv_d, bs, us, ds, mu);
   for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int lx = i % W, ly = i / W, gx = ox + lx, gy = oy + ly;
-    double v = 0.0;
-    if (lx >= 1 && lx < W - 1 && ly >= 1 && ly < H - 1 && gx >= 0 && gx < nf && gy >= 0 &&
-        gy < nf)
-      v = cw * (2.0 * bs[i] - cw * k5(bs, i, W, mu)) + interp(es, EW, cox, coy, gx, gy);
-    us[i] = v;
+    if (R.inside(i, kNu - 1)) {
+      const int gx = R.ox + i % W, gy = R.oy + i / W;
+      us[cur][i] += interp(es, EW, cox, coy, gx, gy);
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int lx = i % W, ly = i / W, gx = ox + lx, gy = oy + ly;
-    double v = 0.0;
-    if (lx >= 2 && lx < W - 2 && ly >= 2 && ly < H - 2 && gx >= 0 && gx < nf && gy >= 0 &&
-        gy < nf)
-      v = us[i] + cw * (bs[i] - k5(us, i, W, mu));
-    vs[i] = v;
+  // post-smoothing; the last step's new values are needed on the owned nodes only
+  for (int k = 0; k + 1 < kNu; ++k) {
+    cheb_step<W, H>(R, kNu + k, k == 0 ? 0.0 : a.sm.a[k], a.sm.c[k], inv_d, bs, us[cur],
+                    us[cur ^ 1], ds, mu);
+    cur ^= 1;
   }
-  __syncthreads();
   const int x1 = (cx0 + CX >= nc) ? nf : 2 * (cx0 + CX);
   const int y1 = (cy0 + CY >= nc) ? nf : 2 * (cy0 + CY);
   const int ow = x1 - 2 * cx0, oh = y1 - 2 * cy0;
+  const double ak = kNu == 1 ? 0.0 : a.sm.a[kNu - 1], ck = a.sm.c[kNu - 1];
+  const double* u = us[cur];
   double* ef = a.ef + (size_t)col * a.ldf;
   double part = 0.0;
   for (int i = threadIdx.x; i < ow * oh; i += kT) {
     const int gx = 2 * cx0 + i % ow, gy = 2 * cy0 + i / ow;
-    const int q = (gy - oy) * W + (gx - ox);
-    const double e = vs[q] + cw * (bs[q] - k5(vs, q, W, mu));
+    const int q = (gy - R.oy) * W + (gx - R.ox);
+    const double d = ak * ds[q] + ck * inv_d * (bs[q] - k5(u, q, W, mu));
+    const double e = u[q] + d;
     ef[(size_t)gy * nf + gx] = e;
     part += bs[q] * e;
   }
@@ -225,14 +284,26 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// coarse levels (n <= kMGCoarseMax): the rest of the V-cycle in one
-// work-group per column.  Each level is an (n+2)^2 LDS array with a zero frame.
+// coarse level (n <= kMGCoarseMax): exact solve by the sine transform, four
+// 64 x 64 GEMMs on the matrix cores in LDS, one work-group per column
 // ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: lane l = i + 16 g supplies a = X[i][g] and
+// b = Y[g][i]; element q of the accumulator is (X Y)[4 q + g][i].
+__device__ __forceinline__ d4 mfma(double x, double y, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+
+constexpr int kE = 64;        // padded order of the exact solve
+constexpr int kEL = kE + 1;   // LDS row stride (odd: no bank conflicts along columns)
+
 struct CoarseArgs {
-  int n;
+  int n;               // order of the coarse level (<= kMGCoarseMax)
   int64_t ld;
   const double* b;
   double* e;
+  const double* dst;   // n x n sine-transform matrix S (row-major, symmetric), then l (n)
   double mu;
   int nlaunch;
   int cols[kMaxCols];
@@ -241,128 +312,63 @@ struct CoarseArgs {
   int max_tiles;
 };
 
-// out = u + c (b - K u) on the interior of an n x n level (row width W = n+2),
-// zero on the frame.
-__device__ __forceinline__ void jacobi_full(double* out, const double* u, const double* b, int n,
-                                            double mu, double cw) {
-  const int W = n + 2;
-  for (int i = threadIdx.x; i < W * W; i += kCT) {
-    const int x = i % W, y = i / W;
-    out[i] = (x >= 1 && x <= n && y >= 1 && y <= n) ? u[i] + cw * (b[i] - k5(u, i, W, mu)) : 0.0;
+// C = A B for 64 x 64 LDS matrices (row stride kEL); with `scale`, C[y][x]
+// is divided by mu (l_y + l_x) (zero outside the n x n block).  One 16 x 16
+// tile per wave.
+__device__ __forceinline__ void lds_gemm(const double* A, const double* B, double* C, bool scale,
+                                         const double* l, double mu, int n) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int r0 = (wv & 3) * 16, c0 = (wv >> 2) * 16;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kE; k0 += 4)
+    acc = mfma(A[(r0 + i) * kEL + k0 + g], B[(k0 + g) * kEL + c0 + i], acc);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int y = r0 + 4 * q + g, x = c0 + i;
+    double v = acc[q];
+    if (scale) v = (y < n && x < n) ? v / (mu * (l[y] + l[x])) : 0.0;
+    C[y * kEL + x] = v;
   }
 }
 
 __global__ __launch_bounds__(kCT) void mg_coarse_kernel(CoarseArgs a) {
-  __shared__ double B[kCoarseStore];
-  __shared__ double U[kCoarseStore];
-  __shared__ double T[kCoarseTmp];
+  __shared__ double S[kE * kEL];
+  __shared__ double X[kE * kEL];
+  __shared__ double T[kE * kEL];
+  __shared__ double l[kE];
   __shared__ double red[kCT / 64];
-  __shared__ int nl[kCoarseLevels], off[kCoarseLevels], nlev;
   const int col = a.cols[blockIdx.x];
   if (a.st && !a.st[col].active) return;
-  const double mu = a.mu, cw = kOmega / (4.0 * mu);
-  if (threadIdx.x == 0) {
-    int L = 0, tot = 0;
-    for (int n = a.n;;) {
-      nl[L] = n;
-      off[L] = tot;
-      tot += (n + 2) * (n + 2);
-      ++L;
-      if (n <= 1 || (n & 1) == 0 || L == kCoarseLevels) break;
-      n = (n - 1) / 2;
-    }
-    nlev = L;
+  const int n = a.n;
+  const double* bg = a.b + (size_t)col * a.ld;
+  double* eg = a.e + (size_t)col * a.ld;
+  for (int i = threadIdx.x; i < kE * kE; i += kCT) {
+    const int y = i / kE, x = i % kE;
+    const bool in = y < n && x < n;
+    S[y * kEL + x] = in ? a.dst[y * n + x] : 0.0;
+    X[y * kEL + x] = in ? bg[y * n + x] : 0.0;
   }
-  for (int i = threadIdx.x; i < kCoarseStore; i += kCT) {
-    B[i] = 0.0;
-    U[i] = 0.0;
-  }
+  if (threadIdx.x < kE) l[threadIdx.x] = threadIdx.x < n ? a.dst[n * n + threadIdx.x] : 0.0;
   __syncthreads();
-  const int L = nlev;
-  {
-    const int n = nl[0], W = n + 2;
-    const double* bg = a.b + (size_t)col * a.ld;
-    for (int i = threadIdx.x; i < n * n; i += kCT)
-      B[off[0] + (i / n + 1) * W + (i % n + 1)] = bg[i];
-  }
+  lds_gemm(S, X, T, false, l, a.mu, n);   // T = S B
   __syncthreads();
-  // descent: two sweeps from zero, residual, restriction
-  for (int m = 0; m + 1 < L; ++m) {
-    const int n = nl[m], W = n + 2;
-    const double* b = B + off[m];
-    double* u = U + off[m];
-    for (int i = threadIdx.x; i < W * W; i += kCT) {
-      const int x = i % W, y = i / W;
-      T[i] = (x >= 1 && x <= n && y >= 1 && y <= n) ? cw * b[i] : 0.0;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < W * W; i += kCT) {
-      const int x = i % W, y = i / W;
-      if (x >= 1 && x <= n && y >= 1 && y <= n) u[i] = T[i] + cw * (b[i] - k5(T, i, W, mu));
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < W * W; i += kCT) {
-      const int x = i % W, y = i / W;
-      T[i] = (x >= 1 && x <= n && y >= 1 && y <= n) ? b[i] - k5(u, i, W, mu) : 0.0;
-    }
-    __syncthreads();
-    const int nc = nl[m + 1], Wc = nc + 2;
-    double* bc = B + off[m + 1];
-    for (int i = threadIdx.x; i < nc * nc; i += kCT) {
-      const int I = i % nc, J = i / nc;
-      const int q = (2 * J + 2) * W + (2 * I + 2);   // fine (2I+1, 2J+1), padded
-      bc[(J + 1) * Wc + (I + 1)] = T[q] + 0.5 * ((T[q - 1] + T[q + 1]) + (T[q - W] + T[q + W]) +
-                                                 (T[q - W - 1] + T[q + W + 1]));
-    }
-    __syncthreads();
+  lds_gemm(T, S, X, true, l, a.mu, n);    // X = (T S) ./ (mu (l_y + l_x))
+  __syncthreads();
+  lds_gemm(S, X, T, false, l, a.mu, n);   // T = S X
+  __syncthreads();
+  lds_gemm(T, S, X, false, l, a.mu, n);   // X = T S
+  __syncthreads();
+  double part = 0.0;
+  for (int i = threadIdx.x; i < n * n; i += kCT) {
+    const double v = X[(i / n) * kEL + i % n];
+    eg[i] = v;
+    part += bg[i] * v;
   }
-  // coarsest level
-  {
-    const int m = L - 1, n = nl[m];
-    const double* b = B + off[m];
-    double* u = U + off[m];
-    if (n == 1) {
-      if (threadIdx.x == 0) u[4] = b[4] / (4.0 * mu);
-    } else {
-      for (int s = 0; s < kBottomSweeps / 2; ++s) {
-        jacobi_full(T, u, b, n, mu, cw);
-        __syncthreads();
-        jacobi_full(u, T, b, n, mu, cw);
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-  }
-  // ascent: interpolate the correction, two sweeps
-  for (int m = L - 2; m >= 0; --m) {
-    const int n = nl[m], W = n + 2;
-    const int Wc = nl[m + 1] + 2;
-    const double* b = B + off[m];
-    double* u = U + off[m];
-    const double* ec = U + off[m + 1];
-    for (int i = threadIdx.x; i < n * n; i += kCT) {
-      const int x = i % n, y = i / n;
-      u[(y + 1) * W + (x + 1)] += interp(ec, Wc, -1, -1, x, y);
-    }
-    __syncthreads();
-    jacobi_full(T, u, b, n, mu, cw);
-    __syncthreads();
-    jacobi_full(u, T, b, n, mu, cw);
-    __syncthreads();
-  }
-  {
-    const int n = nl[0], W = n + 2;
-    double* eg = a.e + (size_t)col * a.ld;
-    double part = 0.0;
-    for (int i = threadIdx.x; i < n * n; i += kCT) {
-      const int q = off[0] + (i / n + 1) * W + (i % n + 1);
-      eg[i] = U[q];
-      part += B[q] * U[q];
-    }
-    if (a.part) {
-      part = block_sum<kCT>(part, red);
-      if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles] = part;
-    }
+  if (a.part) {
+    part = block_sum<kCT>(part, red);
+    if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles] = part;
   }
 }
 
@@ -395,77 +401,75 @@ struct PCGArgs {
   const double* b[kMaxCols];   // set-up only
 };
 
-__device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
-  double s = 0.0;
-  for (int t = threadIdx.x; t < n; t += kT) s += p[t];
-  return block_sum<kT>(s, red);
-}
-
-// A: stopping test and beta from (r, r) and (r, z); p = z + beta p; q = K p; (p, q).
+// A: stopping test and beta from (r, r) and (r, z) of this work-group's
+// column; p = z + beta p; q = K p; (p, q).  Tile 0 of each column writes its
+// state; work-group 0 carries over the state of columns not launched.
 __global__ __launch_bounds__(kT) void pcg_a_kernel(PCGArgs a) {
   constexpr int RW = TX + 2, RH = TY + 2;
   __shared__ double ps[RW * RH];
-  __shared__ double red[kT / 64];
-  __shared__ double s_beta[kMaxCols];
-  __shared__ int s_go[kMaxCols];
+  __shared__ double red[2][kT / 64];
   const int ntiles = a.ntx * a.nty;
   const int lin = xcd_remap(blockIdx.x, a.nlaunch * ntiles);
-  const int t = lin / a.nlaunch, jb = lin % a.nlaunch, col = a.cols[jb];
-  const bool writer = blockIdx.x == 0;
-  for (int j = 0; j < a.nlaunch; ++j) {
-    const int c = a.cols[j];
-    CGScal s = a.prev[c];
-    int go = 0;
-    double beta = 0.0;
-    if (s.active) {
-      const double rr = sum_partials(a.part_rr + (size_t)c * a.max_tiles, ntiles, red);
-      const double rz = sum_partials(a.part_rz + (size_t)c * a.max_tiles, a.rz_tiles, red);
-      const int done = s.iters;
-      if (done > 0 && !(a.alpha[c] > 0.0)) {
-        s.active = 0;
-        s.flag = 3;   // (p, K p) was not positive or not finite
-      } else if (!__builtin_isfinite(rr) || !__builtin_isfinite(rz)) {
-        s.active = 0;
-        s.flag = 3;
-      } else if (done == 0 && rr == 0.0) {
-        s.gamma0 = 0.0;
-        s.active = 0;
-        s.flag = 1;   // b = 0: x = 0
-      } else if (done > 0 && rr <= s.rtol2 * s.gamma0) {
-        s.active = 0;
-        s.flag = 1;
-      } else if (done >= s.maxit) {
-        s.active = 0;
-        s.flag = 2;
-      } else if (!(rz > 0.0)) {
-        s.active = 0;
-        s.flag = 3;   // the preconditioner lost definiteness in rounding
-      } else {
-        if (done == 0) s.gamma0 = rr;
-        beta = done == 0 ? 0.0 : rz / s.rho;
-        s.rho = rz;
-        s.iters = done + 1;
-        go = 1;
-      }
-      s.gamma = rr;
-    }
-    if (threadIdx.x == 0) {
-      s_go[j] = go;
-      s_beta[j] = beta;
-      if (writer) a.next[c] = s;
-    }
-  }
-  if (writer) {
-    // columns outside the launch list keep their state
+  const int t = lin / a.nlaunch, col = a.cols[lin % a.nlaunch];
+  if (blockIdx.x == 0) {
     for (int c = threadIdx.x; c < a.ncols; c += kT) {
       bool launched = false;
       for (int j = 0; j < a.nlaunch; ++j) launched |= a.cols[j] == c;
       if (!launched) a.next[c] = a.prev[c];
     }
   }
+  CGScal s = a.prev[col];
+  if (!s.active) {
+    if (t == 0 && threadIdx.x == 0) a.next[col] = s;
+    return;
+  }
+  // (r, r) and (r, z) in one pass over the partials
+  double rr = 0.0, rz = 0.0;
+  const double* prr = a.part_rr + (size_t)col * a.max_tiles;
+  const double* prz = a.part_rz + (size_t)col * a.max_tiles;
+  for (int u = threadIdx.x; u < ntiles; u += kT) rr += prr[u];
+  for (int u = threadIdx.x; u < a.rz_tiles; u += kT) rz += prz[u];
+  rr = wave_sum(rr);
+  rz = wave_sum(rz);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = rr;
+    red[1][threadIdx.x >> 6] = rz;
+  }
   __syncthreads();
-  if (!s_go[jb]) return;
-  const double beta = s_beta[jb];
+  rr = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+  rz = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  int go = 0;
+  double beta = 0.0;
+  const int done = s.iters;
+  if (done > 0 && !(a.alpha[col] > 0.0)) {
+    s.active = 0;
+    s.flag = 3;   // (p, K p) was not positive or not finite
+  } else if (!__builtin_isfinite(rr) || !__builtin_isfinite(rz)) {
+    s.active = 0;
+    s.flag = 3;
+  } else if (done == 0 && rr == 0.0) {
+    s.gamma0 = 0.0;
+    s.active = 0;
+    s.flag = 1;   // b = 0: x = 0
+  } else if (done > 0 && rr <= s.rtol2 * s.gamma0) {
+    s.active = 0;
+    s.flag = 1;
+  } else if (done >= s.maxit) {
+    s.active = 0;
+    s.flag = 2;
+  } else if (!(rz > 0.0)) {
+    s.active = 0;
+    s.flag = 3;   // the preconditioner lost definiteness in rounding
+  } else {
+    if (done == 0) s.gamma0 = rr;
+    beta = done == 0 ? 0.0 : rz / s.rho;
+    s.rho = rz;
+    s.iters = done + 1;
+    go = 1;
+  }
+  s.gamma = rr;
+  if (t == 0 && threadIdx.x == 0) a.next[col] = s;
+  if (!go) return;
   const int n = a.n;
   const int x0 = (t % a.ntx) * TX, y0 = (t / a.ntx) * TY;
   const double* zg = a.z + (size_t)col * a.ld;
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(kT) void pcg_a_kernel(PCGArgs a) {
       part += pv * qv;
     }
   }
-  part = block_sum<kT>(part, red);
+  part = block_sum<kT>(part, red[0]);
   if (threadIdx.x == 0) a.part_pq[(size_t)col * a.max_tiles + t] = part;
 }
 
@@ -507,7 +511,10 @@ __global__ __launch_bounds__(kT) void pcg_b_kernel(PCGArgs a) {
   const int t = lin / a.nlaunch, col = a.cols[lin % a.nlaunch];
   const CGScal s = a.next[col];   // written by this iteration's A
   if (!s.active) return;
-  const double pq = sum_partials(a.part_pq + (size_t)col * a.max_tiles, ntiles, red);
+  double pq = 0.0;
+  const double* ppq = a.part_pq + (size_t)col * a.max_tiles;
+  for (int u = threadIdx.x; u < ntiles; u += kT) pq += ppq[u];
+  pq = block_sum<kT>(pq, red);
   const bool ok = pq > 0.0 && __builtin_isfinite(pq);
   const double alpha = ok ? s.rho / pq : 0.0;
   if (t == 0 && threadIdx.x == 0) a.alpha[col] = alpha;
@@ -575,6 +582,24 @@ __global__ __launch_bounds__(kT) void pcg_setup_kernel(PCGArgs a, double rtol2, 
 
 int tiles_of(int n, int tx, int ty) { return ((n + tx - 1) / tx) * ((n + ty - 1) / ty); }
 
+// Chebyshev coefficients for [1/2, 2] (the upper three quarters of the
+// spectrum of D^{-1} Kx, which lies in (0, 2)).
+Smooth smooth_coefficients() {
+  const double lo = 0.5, hi = 2.0;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  Smooth s{};
+  double rho = 1.0 / sigma;
+  s.a[0] = 0.0;
+  s.c[0] = 1.0 / theta;
+  for (int k = 1; k < kNu; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    s.a[k] = rho1 * rho;
+    s.c[k] = 2.0 * rho1 / delta;
+    rho = rho1;
+  }
+  return s;
+}
+
 PCGArgs pcg_args(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols) {
   PCGArgs a{};
   a.n = w.plan.n[0];
@@ -631,6 +656,7 @@ bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan) {
     p.n[++L] = n;
   }
   p.nlev = L;
+  p.exact = n;
   *plan = p;
   return true;
 }
@@ -641,10 +667,24 @@ int mg_max_tiles(const MGPlan& p) {
   return std::max(t, 1);
 }
 
+void mg_dst_table(int m, double* out) {
+  // S[y][x] = sqrt(2 / (m + 1)) sin(pi (y + 1)(x + 1) / (m + 1)); l_y = 2 - 2 cos(pi (y + 1) / (m + 1))
+  const double pi = 3.14159265358979323846;
+  const double s = std::sqrt(2.0 / (m + 1));
+  for (int y = 0; y < m; ++y)
+    for (int x = 0; x < m; ++x) {
+      // reduce the angle's integer multiple modulo 2 (m + 1) before the sine
+      const long long num = (long long)(y + 1) * (x + 1) % (2LL * (m + 1));
+      out[y * m + x] = s * std::sin(pi * (double)num / (m + 1));
+    }
+  for (int y = 0; y < m; ++y) out[m * m + y] = 2.0 - 2.0 * std::cos(pi * (y + 1) / (m + 1));
+}
+
 void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
                hipStream_t st) {
   const MGPlan& p = w.plan;
   const int L = p.nlev;
+  const Smooth sm = smooth_coefficients();
   for (int l = 0; l < L; ++l) {
     LevelArgs a{};
     a.nf = p.n[l];
@@ -659,6 +699,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
     a.st = act;
     a.mu = p.mu;
+    a.sm = sm;
     mg_down_kernel<<<a.ntx * a.nty * nlaunch, kT, 0, st>>>(a);
     STS_HIP(hipGetLastError());
   }
@@ -668,6 +709,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     c.ld = w.ld[L];
     c.b = w.b[L];
     c.e = w.e[L];
+    c.dst = w.dst;
     c.mu = p.mu;
     c.nlaunch = nlaunch;
     for (int j = 0; j < nlaunch; ++j) c.cols[j] = cols[j];
@@ -692,6 +734,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
     a.st = act;
     a.mu = p.mu;
+    a.sm = sm;
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
     a.max_tiles = w.max_tiles;
     mg_up_kernel<<<a.ntx * a.nty * nlaunch, kT, 0, st>>>(a);
@@ -701,8 +744,8 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
 
 void pcg_setup(const MGWork& w, const double* const* b, const int* cols, int nlaunch, int ncols,
                double rtol, int maxit, hipStream_t st) {
-  // state slot 1 is "previous" for the first iteration (parity 0)
-  PCGArgs a = pcg_args(w, 1, cols, nlaunch, ncols);
+  // state slot 0 is "previous" for the first iteration (parity 1)
+  PCGArgs a = pcg_args(w, 0, cols, nlaunch, ncols);
   for (int j = 0; j < nlaunch; ++j) a.b[j] = b[j];
   pcg_setup_kernel<<<a.ntx * a.nty * nlaunch, kT, 0, st>>>(a, rtol * rtol, maxit);
   STS_HIP(hipGetLastError());

@@ -117,13 +117,18 @@ void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int*
 // ---------------------------------------------------------------------------
 
 constexpr int kMGMaxLevels = 12;
-constexpr int kMGCoarseMax = 63;   // levels up to this size run in one work-group
+constexpr int kMGCoarseMax = 63;   // the coarsest level (at most this size) is solved exactly
+constexpr int kMGNu = 3;           // Chebyshev smoothing steps before and after
 
 struct MGPlan {
   int nlev;                  // tiled levels 0..nlev-1; level nlev has <= kMGCoarseMax nodes
   int n[kMGMaxLevels + 1];   // nodes per direction, n[l+1] = (n[l] - 1) / 2
+  int exact;                 // size of the exactly solved coarsest level (= n[nlev])
   double mu;                 // Kx = mu (4; -1, -1, -1, -1)
 };
+// The m x m sine-transform matrix (row-major) followed by the m eigenvalues
+// 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.
+void mg_dst_table(int m, double* out);
 // True (and *plan filled) if Kx is the 2-D five-point P1 stiffness on a square
 // grid that halves, n -> (n-1)/2, down to at most kMGCoarseMax nodes.
 bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan);
@@ -145,6 +150,7 @@ struct MGWork {
   double* part_pq;
   double* alpha;                 // kMaxCols
   int max_tiles;
+  const double* dst;             // device copy of mg_dst_table(plan.exact)
 };
 // e[0][:, c] = B b[0][:, c] (one V-cycle) for the columns cols[0..nlaunch);
 // columns whose state in `act` (may be null) is inactive are skipped; with

@@ -9,21 +9,30 @@ evaluating coarse P1 hat functions at fine nodes, and a recursive V-cycle --
 so that the GPU V-cycle can be compared entry by entry.
 
 V-cycle on level n (interior nodes per direction), right-hand side b:
-  n == 1           exact solve;
-  n even, n > 1    20 damped-Jacobi sweeps from zero (the level does not halve);
-  otherwise        two damped-Jacobi sweeps from zero (weight 0.8), restriction
-                   of the residual by P^T to n_c = (n - 1) / 2, recursive
-                   V-cycle there, correction u += P e_c, two more sweeps.
+  n <= 63             exact solve (larger levels must be odd);
+  otherwise           three Chebyshev smoothing steps from zero, restriction of
+                      the residual by P^T to n_c = (n - 1) / 2, recursive
+                      V-cycle there, correction u += P e_c, three more
+                      Chebyshev steps on the residual equation.
+Chebyshev smoothing targets [1/2, 2] of the spectrum of D^{-1} Kx (D its
+diagonal, 4 mu): with theta, delta the centre and half-width of the interval
+and sigma = theta / delta, the textbook three-term recurrence
+  d_0 = r_0 / (theta D),  rho_0 = 1 / sigma,
+  rho_k = 1 / (2 sigma - rho_{k-1}),
+  d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) D^{-1} r_k,
+  u_{k+1} = u_k + d_k,  r_k = b - Kx u_k.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from oracle import fem
 
-OMEGA = 0.8
-BOTTOM_SWEEPS = 20
+CHEB_STEPS = 3
+CHEB_INTERVAL = (0.5, 2.0)
+EXACT_MAX = 63
 
 
 def hat(xi, eta):
@@ -58,28 +67,36 @@ def stiffness(n: int, mu: float) -> sp.csr_matrix:
     return fem.spatial_operators(2, n, mu)[0].tocsr()
 
 
+def chebyshev(K, b, u, steps=CHEB_STEPS):
+    """`steps` Chebyshev steps on K u = b from u (see the module docstring)."""
+    lo, hi = CHEB_INTERVAL
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    dinv = 1.0 / K.diagonal()
+    if b.ndim == 2:
+        dinv = dinv[:, None]
+    rho = 1.0 / sigma
+    d = dinv * (b - K @ u) / theta
+    u = u + d
+    for _ in range(steps - 1):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * dinv * (b - K @ u)
+        u = u + d
+        rho = rho_new
+    return u
+
+
 def vcycle(b: np.ndarray, n: int, mu: float) -> np.ndarray:
     """One V-cycle from zero applied to b (length n^2, or n^2 x m)."""
     K = stiffness(n, mu)
-    c = OMEGA / K.diagonal()
-    if b.ndim == 2:
-        c = c[:, None]
-    if n == 1:
-        return b / K.diagonal()[0]
-    if n % 2 == 0:
-        u = np.zeros_like(b)
-        for _ in range(BOTTOM_SWEEPS):
-            u = u + c * (b - K @ u)
-        return u
-    u = np.zeros_like(b)
-    for _ in range(2):
-        u = u + c * (b - K @ u)
+    if n <= EXACT_MAX:
+        return spla.spsolve(K.tocsc(), b).reshape(b.shape)
+    assert n % 2 == 1, "levels above 63 must halve"
+    u = chebyshev(K, b, np.zeros_like(b))
     nc = (n - 1) // 2
     P = prolongation(nc)
     u = u + P @ vcycle(P.T @ (b - K @ u), nc, mu)
-    for _ in range(2):
-        u = u + c * (b - K @ u)
-    return u
+    return chebyshev(K, b, u)
 
 
 def supported(n: int) -> bool:

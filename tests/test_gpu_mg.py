@@ -39,11 +39,12 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-# Sizes: the coarse kernel alone (1 .. 63, even tops), one tiled level with a
-# coarse grid that is an exact multiple of the tile in x (65 -> 32) or in y
-# (97 -> 48), ragged tiles (81 -> 40, 125 -> 62, 127 -> 63), and two and
-# three tiled levels (255, 511).
-VC_SIZES = [1, 2, 3, 31, 62, 63, 65, 81, 97, 125, 127, 255, 511]
+# Sizes: exact solves alone (1 .. 31, even 62), one level in LDS above an
+# exact solve (33, 63), one tiled level with a coarse grid that is an exact
+# multiple of the tile in x (65 -> 32) or in y (97 -> 48), ragged tiles
+# (81 -> 40, 125 -> 62, 127 -> 63 -> 31), and two and three tiled levels
+# (255, 511).
+VC_SIZES = [1, 2, 3, 31, 33, 62, 63, 65, 81, 97, 125, 127, 255, 511]
 
 
 @pytest.mark.parametrize("n", VC_SIZES)
@@ -84,19 +85,21 @@ def test_pcg_matches_sparse_direct(n, ncols):
         assert np.linalg.norm(B[:, c] - K @ X[:, c]) <= 1e-12 * np.linalg.norm(B[:, c])
         x_ref = spla.spsolve(K, B[:, c])
         assert rel(X[:, c], x_ref) < 1e-9, (c, rel(X[:, c], x_ref))
-    # mesh-independent convergence where every level halves (unpreconditioned
-    # CG needs ~1900 at n = 511); 65 -> 32 ends on a level that does not halve
-    # and is only smoothed, which costs iterations but stays correct
-    assert max(its) <= (40 if n == 65 else 16), its
+    # mesh-independent convergence (unpreconditioned CG needs ~1900 at n = 511)
+    assert max(its) <= 13, its
 
 
 def test_pcg_zero_rhs_iteration_cap_and_bad_grids():
-    space = sts.make_space(2, 63)
-    B = np.zeros((63 * 63, 2))
-    B[:, 1] = np.random.default_rng(1).normal(size=63 * 63)
+    space = sts.make_space(2, 127)
+    B = np.zeros((127 * 127, 2))
+    B[:, 1] = np.random.default_rng(1).normal(size=127 * 127)
     X, its, code = sts.pcg_mg(space, dev(B), rtol=1e-14, maxit=3, check=False)
     assert its[0] == 0 and np.all(host(X)[:, 0] == 0.0)
     assert its[1] == 3 and code == 4                   # STS_E_NOT_CONVERGED (maxit)
+    # n <= 63: the V-cycle is the exact inverse, one iteration
+    B = np.random.default_rng(2).normal(size=(63 * 63, 1))
+    X, its, _ = sts.pcg_mg(sts.make_space(2, 63), dev(B), rtol=1e-12)
+    assert its[0] == 1
     for bad in (sts.make_space(2, 100), sts.make_space(2, 129), sts.make_space(1, 127),
                 sts.make_space(3, 15)):
         nh = int(np.prod([bad.n[d] for d in range(3)]))
