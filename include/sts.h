@@ -106,9 +106,10 @@ typedef struct {
   int64_t mem_budget;       /* bytes of device memory the problem may hold; 0 = unlimited */
   int32_t restart;          /* 1 = discard the current basis and solve from scratch; default 0 */
   int32_t profile;          /* 1 = time the CG iteration kernels with HIP events; default 0 */
-  int32_t inner_precond;    /* Kx solves: 1 = CG preconditioned by one geometric multigrid
-                               V-cycle where the grid allows it (2-D, n halving to <= 63),
-                               else plain CG; 0 = plain CG always; default 1 */
+  int32_t inner_precond;    /* 1 = fast inner solvers where the space allows them (2-D P1,
+                               n halving to <= 63): Kx by CG preconditioned with one
+                               geometric multigrid V-cycle, Mx by Chebyshev iteration;
+                               0 = plain CG for both; default 1 */
   int32_t pad_;
 } sts_opts;
 
@@ -223,6 +224,17 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops, const double* B, i
 sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, double* X,
                       int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
                       void* stream);
+
+/* Mx X[:, c] = B[:, c] for c < ncols by Chebyshev iteration (the Mx^{-1}
+ * applications of the extended Krylov space, Sec. 4; the solver is this
+ * library's choice).  For the 2-D P1 mass matrix the spectrum of
+ * diag(Mx)^{-1} Mx lies in [1/2, 2], so k steps guarantee
+ * ||r|| <= 2 (1/3)^k ||b||; k is the smallest count meeting rtol (at most
+ * 64) and is written to iters (host, may be NULL).  Only STS_FE_P1_2D spaces
+ * (else STS_E_INVALID).  B, X: Nh x ncols (ldb, ldx), device, ncols <= 8. */
+sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, double* X,
+                          int64_t ldx, int32_t ncols, double rtol, int32_t* iters,
+                          void* stream);
 
 /* The preconditioner of sts_pcg_mg: Z[:, c] = Bmg R[:, c], one V-cycle from
  * zero (two damped-Jacobi sweeps, weight 0.8, before and after each coarse

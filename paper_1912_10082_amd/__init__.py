@@ -9,5 +9,5 @@ computation runs in the HIP library ``libsts.so`` behind the C ABI of
 from .binding import (  # noqa: F401
     EXPORTED, STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT, STS_OP_K, STS_OP_M, Problem,
     STSError, apply_op, basis_update, cg, default_opts, gram, load, m_orthonormalize, make_space,
-    mg_vcycle, pcg_mg, sym_eig, time_matrices, time_sweep,
+    mass_solve, mg_vcycle, pcg_mg, sym_eig, time_matrices, time_sweep,
 )

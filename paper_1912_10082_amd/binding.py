@@ -82,6 +82,8 @@ _SIGS = {
     "sts_pcg_mg": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64, _I32,
                              C.POINTER(_I32), _P]),
     "sts_mg_vcycle": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _P]),
+    "sts_mass_solve": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64,
+                                 C.POINTER(_I32), _P]),
     "sts_m_orthonormalize": (C.c_int, [C.POINTER(Space), _P, _P, _I64, _I64, _P, _P, _I64, _I32,
                                        _F64, C.POINTER(_I32), C.POINTER(_I32), _P]),
     "sts_gram": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
@@ -340,6 +342,16 @@ def pcg_mg(space: Space, B, rtol: float = 1e-12, maxit: int = 1000, check: bool 
     if check:
         _check(code)
     return X, list(its), code
+
+
+def mass_solve(space: Space, B, rtol: float = 1e-13):
+    """Mx X = B by Chebyshev iteration (2-D P1); returns (X, iterations)."""
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_zeros(B.shape[0], B.shape[1])
+    its = (C.c_int32 * B.shape[1])()
+    _check(load().sts_mass_solve(C.byref(space), pb, ldb, C.c_void_p(X.data_ptr()), X.shape[0],
+                                 B.shape[1], rtol, its, _stream_handle()))
+    return X, its[0]
 
 
 def mg_vcycle(space: Space, R):

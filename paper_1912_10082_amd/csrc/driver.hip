@@ -509,6 +509,7 @@ struct sts_problem {
   CGRunner cg;
   // multigrid-preconditioned CG for Kx (allocated on first use)
   bool mg_ok = false;
+  bool mass_cheb = false;   // Mx solves by Chebyshev iteration
   MGPlan mg_plan_{};
   std::unique_ptr<MGRunner> mg;
 
@@ -736,7 +737,18 @@ void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const
     for (int c = 0; c < ncols; ++c)
       if (ops[c] == STS_OP_K) perm[nm + nk++] = c;
   }
-  if (!use_mg || nm > 0) {
+  if (use_mg && nm > 0 && P->mass_cheb) {
+    // Mx columns: Chebyshev iteration with the analytic spectral bounds
+    const double* b2[kMaxCols];
+    for (int j = 0; j < nm; ++j) b2[j] = b[perm[j]];
+    const int its = mass_cheb_iters(o.inner_rtol);
+    double* xb[2] = {P->cg.w.r[0], P->cg.w.r[1]};
+    double* db[2] = {P->cg.w.p[0], P->cg.w.p[1]};
+    mass_cheb_solve(P->grid, P->M, nm, b2, x0, P->ldv, xb, db, P->ldv, its, P->stream);
+    P->inner_M += (int64_t)its * nm;
+    const int launches = (its + kMassSteps - 1) / kMassSteps;
+    P->alg_bytes += 40.0 * launches * P->nh * nm;
+  } else if (!use_mg || nm > 0) {
     const int n = use_mg ? nm : ncols;
     int ops2[kMaxCols];
     const double* b2[kMaxCols];
@@ -996,6 +1008,7 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     P->cg.poll.init();
     STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->pinned), 64 * 8, hipHostMallocDefault));
     P->mg_ok = mg_plan(g, P->K, &P->mg_plan_);
+    P->mass_cheb = mass_cheb_supported(g, P->M);
     // small scratch
     P->gram.alloc(16 * 16 * 8);
     P->rinv.alloc(16 * 16 * 8);
@@ -1361,6 +1374,33 @@ sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, doub
     return bad;
   }
   return s;
+}
+
+sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, double* X,
+                          int64_t ldx, int32_t ncols, double rtol, int32_t* iters,
+                          void* stream) {
+  return run_guarded([&] {
+    validate_space(space);
+    const Grid g = make_grid(*space);
+    const Stencil M = make_stencil(*space, STS_OP_M);
+    STS_REQUIRE(mass_cheb_supported(g, M), STS_E_INVALID,
+                "Chebyshev mass solve needs a 2-D P1 space");
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(rtol > 0.0 && rtol < 1.0, STS_E_INVALID, "rtol must be in (0, 1)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    const int64_t ld = pad_ld(g.nh);
+    double* xb[2] = {sc.get<double>(ld * ncols), sc.get<double>(ld * ncols)};
+    double* db[2] = {sc.get<double>(ld * ncols), sc.get<double>(ld * ncols)};
+    const double* bc[kMaxCols];
+    for (int c = 0; c < ncols; ++c) bc[c] = B + c * ldb;
+    const int its = mass_cheb_iters(rtol);
+    mass_cheb_solve(g, M, ncols, bc, X, ldx, xb, db, ld, its, st);
+    STS_HIP(hipStreamSynchronize(st));
+    if (iters)
+      for (int c = 0; c < ncols; ++c) iters[c] = its;
+  });
 }
 
 sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,

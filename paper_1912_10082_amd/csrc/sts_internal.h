@@ -166,6 +166,23 @@ void pcg_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int 
                  hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// Mx solves by Chebyshev iteration (2-D P1 mass matrix)
+// ---------------------------------------------------------------------------
+
+constexpr int kMassSteps = 6;       // Chebyshev steps fused per launch (= LDS halo)
+constexpr int kMassMaxIters = 64;
+
+// Steps for ||r|| <= rtol ||b|| (the bound 2 (1/3)^k).
+int mass_cheb_iters(double rtol);
+// True if Mx is the 2-D P1 mass stencil w (6; 1 at E, W, N, S, NE, SW).
+bool mass_cheb_supported(const Grid& g, const Stencil& M);
+// x[:, c] = Mx^{-1} b[c] for c < ncols after `iters` steps; xbuf / dbuf: two
+// state buffers each (stride ld, kMaxCols columns).
+void mass_cheb_solve(const Grid& g, const Stencil& M, int ncols, const double* const* b,
+                     double* x, int64_t ldx, double* xbuf[2], double* dbuf[2], int64_t ld,
+                     int iters, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // dense tall-skinny kernels (FP64 MFMA)
 // ---------------------------------------------------------------------------
 

@@ -5,6 +5,8 @@ The V-cycle is compared entry by entry with the reference of
 sparse direct solve; whole solves with the preconditioner on and off with the
 oracle's Crank-Nicolson solution.  All calls go through the C ABI.
 """
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -115,6 +117,35 @@ def test_pcg_is_bitwise_deterministic():
     X1, i1, _ = sts.pcg_mg(space, B)
     X2, i2, _ = sts.pcg_mg(space, B)
     assert i1 == i2 and torch.equal(X1, X2)
+
+
+@pytest.mark.parametrize("n,ncols", [(1, 1), (2, 2), (31, 3), (64, 2), (100, 8), (511, 2)])
+def test_mass_chebyshev_matches_sparse_direct(n, ncols):
+    mu = 0.9
+    rng = np.random.default_rng(400 + n)
+    B = rng.normal(size=(n * n, ncols))
+    if ncols > 1:
+        B[:, 0] = 0.0
+    X, its = sts.mass_solve(sts.make_space(2, n, mu), dev(B), rtol=1e-13)
+    X = host(X)
+    assert its == math.ceil(math.log(0.5e-13) / math.log(1.0 / 3.0))
+    M = fem.spatial_operators(2, n, mu)[1].tocsc()
+    for c in range(ncols):
+        nb = np.linalg.norm(B[:, c])
+        if nb == 0.0:
+            assert np.all(X[:, c] == 0.0)
+            continue
+        # the Chebyshev bound 2 (1/3)^k, with rounding slack
+        assert np.linalg.norm(B[:, c] - M @ X[:, c]) <= 2e-13 * nb
+        assert rel(X[:, c], spla.spsolve(M, B[:, c])) < 1e-12
+
+
+def test_mass_chebyshev_rejects_other_spaces():
+    for bad in (sts.make_space(1, 127), sts.make_space(3, 15)):
+        nh = int(np.prod([bad.n[d] for d in range(3)]))
+        with pytest.raises(sts.STSError) as e:
+            sts.mass_solve(bad, dev(np.ones((nh, 1))))
+        assert e.value.code == 1
 
 
 def _solve(w, **opts):

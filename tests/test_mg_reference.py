@@ -95,3 +95,14 @@ def test_pcg_iterations_do_not_grow_with_refinement():
 def test_supported_grids():
     assert all(mgr.supported(n) for n in (1, 2, 31, 62, 63, 65, 97, 125, 127, 255, 511, 1023))
     assert not any(mgr.supported(n) for n in (64, 100, 129, 256, 510))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 31])
+def test_mass_spectrum_inside_the_chebyshev_interval(n):
+    """The Chebyshev Mx solve relies on spec(diag(Mx)^{-1} Mx) within [1/2, 2]
+    (the range of the mass stencil's symbol), checked on the assembled matrix."""
+    from oracle import fem
+    M = fem.spatial_operators(2, n, 1.0)[1].toarray()
+    d = np.diag(M)
+    ev = np.linalg.eigvalsh(M / np.sqrt(np.outer(d, d)))
+    assert ev.min() >= 0.5 - 1e-12 and ev.max() <= 2.0 + 1e-12, (ev.min(), ev.max())
