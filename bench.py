@@ -2,8 +2,9 @@
 """Benchmark of the space-time heat solver on one MI355X.
 
 One step = one complete FP64 extended-Krylov Galerkin solve (start block,
-expansions with inner CG, block Gram-Schmidt, reduced eigensolve and time
-sweep, projected residual, exact-residual confirmation) of the 2-D heat
+expansions with the inner Kx / Mx solves, block Gram-Schmidt, reduced
+eigensolve and time sweep, projected residual, exact-residual confirmation)
+of the 2-D heat
 problem on the unit square: P1 on a 511 x 511 interior grid (Nh = 261121),
 Nt = 1024 steps on (0, 1], rank-2 right-hand side (Gaussian-bump fields in
 space, trigonometric series in time), relative Sylvester residual 1e-10.
@@ -11,9 +12,10 @@ Inputs are resident in device memory before the timed region; every timed
 step re-solves from scratch on the same problem object.
 
 Prints one JSON line.  ``value`` is space-time degrees of freedom (Nh * Nt)
-per second of wall time.  ``roofline`` reports the dominant kernel (the fused
-CG iteration) against the 8 TB/s HBM peak, from HIP events around its
-launches inside the timed steps.  ``cpu_baseline`` times the CPU oracle's
+per second of wall time.  ``roofline`` reports the kernel with the largest
+measured time against its bound (8 TB/s HBM, or 78.6 TFLOP/s FP64 matrix
+cores for the residual contraction), from HIP events attached to every launch
+inside the timed steps; ``kernels`` lists all timed kernels.  ``cpu_baseline`` times the CPU oracle's
 Crank-Nicolson stepper on the first time steps of the same problem; those
 columns also gate the result (relative error <= 1e-8).
 """
@@ -31,30 +33,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "space-time dof/s at rel. error 1e-8; % HBM roofline; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_iter_2d_n511_traffic.json")
-CG_SOURCE = os.path.join(ROOT, "paper_1912_10082_amd", "csrc", "stencil_cg.hip")
+FP64_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_2d_n511.json")
+CSRC = os.path.join(ROOT, "paper_1912_10082_amd", "csrc")
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _kernel_hash() -> str:
-    with open(CG_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def _sources_hash() -> str:
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, fn), "rb") as fh:
+            h.update(fn.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def _traffic(bytes_per_launch_alg):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def _traffic(kernel, alg_bytes_per_launch):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs,
+    if they were taken on the current kernel sources; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256_16") != _kernel_hash():
+    if d.get("sources_sha256_16") != _sources_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(w, U_gpu_cols, sample_steps):
@@ -76,14 +83,18 @@ def cpu_baseline(w, U_gpu_cols, sample_steps):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=511, help="interior nodes per direction")
     ap.add_argument("--nt", type=int, default=1024)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--sample-steps", type=int, default=48,
                     help="Crank-Nicolson steps of the CPU baseline / error gate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the profiled solves (no roofline / kernels table)")
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="extra solves with per-dispatch events for the kernel table")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -114,34 +125,60 @@ def main() -> int:
     lat, infos = [], []
     for i in range(args.steps):
         t0 = time.perf_counter()
-        info = prob.solve(profile=1, **opts)
+        info = prob.solve(**opts)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
         infos.append(info)
-        _log(f"step {i}: {info['status']} outer={info['outer_its']} k={info['k']} "
-             f"res_true={info['res_true']:.2e} {lat[-1]:.3f}s")
+        if i < 3 or i == args.steps - 1:
+            _log(f"step {i}: {info['status']} outer={info['outer_its']} k={info['k']} "
+                 f"res_true={info['res_true']:.2e} {lat[-1]:.3f}s")
+    # Kernel durations: the same solve again with a start/stop event attached
+    # to every dispatch.  The events widen the gaps between launches (so
+    # these solves are not timed), not the kernels' own durations.
+    ksum = {}
+    prof_steps = 0 if args.no_profile else args.profile_steps
+    for i in range(prof_steps):
+        prob.solve(profile=1, **opts)
+        torch.cuda.synchronize()
+        for name, (sec, n, by) in prob.kernel_profile().items():
+            a = ksum.setdefault(name, [0.0, 0, 0.0])
+            a[0] += sec
+            a[1] += n
+            a[2] += by
     total = sum(lat)
     dof = w.nh * w.nt
     value = dof * args.steps / total
     last = infos[-1]
-    cg_secs = sum(i["cg_kernel_seconds"] for i in infos)
-    cg_launches = sum(i["cg_launches"] for i in infos)
-    cg_bytes = 48.0 * w.nh * sum(i["cg_col_iters"] for i in infos)
-    achieved = cg_bytes / cg_secs / 1e9 if cg_secs > 0 else None
-    bytes_per_launch = cg_bytes / max(cg_launches, 1)
-    roofline = {
-        "kernel": "cg_iter_kernel<2> (fused single-reduction CG iteration, 2-D)",
-        "bound": "hbm",
-        "achieved": round(achieved, 1) if achieved else None,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": _traffic(bytes_per_launch),
-        "alg_bytes_per_launch": bytes_per_launch,
-        "avg_launch_us": 1e6 * cg_secs / max(cg_launches, 1),
-        "launches_per_step": cg_launches / args.steps,
-        "cg_time_share": cg_secs / total,
-    }
+    roofline = None
+    kernels = None
+    if ksum:
+        # dominant kernel by measured time; its algorithmic bytes (or flops) per
+        # launch over its average launch duration
+        ktot = sum(v[0] for v in ksum.values())
+        name, (sec, n, by) = max(ksum.items(), key=lambda kv: kv[1][0])
+        kernels = {k: {"ms_per_solve": 1e3 * v[0] / prof_steps,
+                       "launches_per_solve": v[1] / prof_steps, "kernel_time_share": v[0] / ktot,
+                       "GB_per_s": (v[2] / v[0] / 1e9) if v[0] > 0 and v[2] > 0 else None}
+                   for k, v in sorted(ksum.items(), key=lambda kv: -kv[1][0]) if v[1] > 0}
+        avg_us = 1e6 * sec / max(n, 1)
+        common = {"avg_launch_us": avg_us, "launches_per_solve": n / prof_steps,
+                  "kernel_time_share": sec / ktot,
+                  "measured": f"HIP events on every dispatch of {prof_steps} more solves "
+                              "of the same workload after the timed steps"}
+        if name == "residual":
+            # ||[F1, Kx V, Mx V] B||: 2 Nh (p + 2k) Nt flops per launch on the FP64 matrix cores
+            flops = 2.0 * w.nh * (2 + 2 * last["k"]) * w.nt
+            achieved = flops / (sec / max(n, 1)) / 1e12
+            roofline = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 2),
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None, **common}
+        else:
+            achieved = by / sec / 1e9
+            roofline = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": _traffic(name, by / max(n, 1)),
+                        "alg_bytes_per_launch": by / max(n, 1), **common}
     gate = last["status"] == "STS_OK" and last["res_true"] <= args.tol
     V, Y = prob.factors(device=True)
     cpu = None
@@ -183,6 +220,7 @@ def main() -> int:
         "inner_its_K": last["inner_its_K"],
         "inner_its_M": last["inner_its_M"],
         "roofline": roofline,
+        "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -105,7 +105,8 @@ typedef struct {
   double defl_tol;          /* drop a new column whose Mx-norm falls below this fraction; default 1e-10 */
   int64_t mem_budget;       /* bytes of device memory the problem may hold; 0 = unlimited */
   int32_t restart;          /* 1 = discard the current basis and solve from scratch; default 0 */
-  int32_t profile;          /* 1 = time the CG iteration kernels with HIP events; default 0 */
+  int32_t profile;          /* 1 = time the main kernels with HIP events (sts_kernel_profile);
+                               default 0 */
   int32_t inner_precond;    /* 1 = fast inner solvers where the space allows them (2-D P1,
                                n halving to <= 63): Kx by CG preconditioned with one
                                geometric multigrid V-cycle, Mx by Chebyshev iteration;
@@ -127,17 +128,29 @@ typedef struct {
   double alg_bytes;         /* algorithmic HBM bytes moved by the kernels (model) */
   int32_t breakdown;        /* 1 = the space became invariant (exact solution) */
   int32_t pad_;
-  /* filled when opts.profile = 1 (CG iteration kernels only, this call) */
-  double cg_kernel_seconds; /* summed HIP-event time of the launches */
-  int64_t cg_launches;      /* iteration-kernel launches */
-  int64_t cg_col_iters;     /* column-iterations performed (each streams 48 bytes per node) */
   int64_t cg_poll_restarts; /* times a polled CG state was stale and iterations resumed */
-  /* filled when opts.profile = 1 (multigrid-preconditioned CG, this call) */
-  double mg_kernel_seconds; /* summed HIP-event time of the PCG iterations */
-  int64_t mg_iterations;    /* PCG iterations launched (V-cycle + two PCG launches each) */
-  int64_t mg_col_iters;     /* column-iterations performed */
-  double mg_bytes_per_node; /* algorithmic bytes per fine node of one column-iteration */
 } sts_info;
+
+/* Kernels timed by sts_kernel_profile. */
+typedef enum {
+  STS_K_CG_ITER = 0,        /* plain CG iteration (stencil SpMM + vector updates) */
+  STS_K_MG_DOWN = 1,        /* multigrid: smoothing, residual, restriction */
+  STS_K_MG_UP = 2,          /* multigrid: prolongation and smoothing */
+  STS_K_MG_COARSE = 3,      /* multigrid: exact coarsest-level solve */
+  STS_K_PCG_A = 4,          /* preconditioned CG: direction and K p */
+  STS_K_PCG_B = 5,          /* preconditioned CG: x and r updates */
+  STS_K_MASS_CHEB = 6,      /* Chebyshev steps of an Mx solve */
+  STS_K_GRAM = 7,           /* Gram contraction V^T W (matrix cores) */
+  STS_K_BASIS_UPDATE = 8,   /* W -= V C (matrix cores) */
+  STS_K_RESIDUAL = 9,       /* exact residual norm (matrix cores) */
+  STS_K_TRIDIAG = 10,       /* reduced eigensolve: tridiagonalisation */
+  STS_K_BISECT = 11,        /* reduced eigensolve: eigenvalues */
+  STS_K_INVITER = 12,       /* reduced eigensolve: eigenvectors of T */
+  STS_K_BACKTRANSFORM = 13, /* reduced eigensolve: back-transformation */
+  STS_K_SWEEP = 14,         /* time sweep */
+  STS_K_STENCIL = 15,       /* stencil SpMM Kx V, Mx V */
+  STS_K_COUNT = 16
+} sts_kernel;
 
 typedef struct sts_problem sts_problem;
 
@@ -184,6 +197,18 @@ sts_status sts_true_residual(sts_problem* prob, double* res);
  * number of singular values of V Y in the Mx norm (those of Y, V being
  * Mx-orthonormal) above 1e-8 times the largest.  Synchronous. */
 sts_status sts_numerical_rank(sts_problem* prob, int64_t* rank);
+
+/* Kernel timing of the last sts_solve made with opts.profile = 1: summed
+ * event time (seconds) of the launches of `kernel` (sts_kernel), their count
+ * and their algorithmic bytes (the data the operation must read and write
+ * once, in the model stated beside each kernel in the sources).  Outputs are
+ * host pointers, each may be NULL.  STS_E_STATE if that solve did not
+ * profile.  Synchronous (waits for the events). */
+sts_status sts_kernel_profile(sts_problem* prob, int32_t kernel, double* seconds,
+                              int64_t* launches, double* alg_bytes);
+
+/* Short name of an sts_kernel ("" if out of range). */
+const char* sts_kernel_name(int32_t kernel);
 
 /* Free everything the problem holds.  NULL-safe. */
 void sts_destroy(sts_problem* prob);

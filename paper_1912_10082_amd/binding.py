@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "STS_OK", 1: "STS_E_INVALID", 2: "STS_E_NOMEM", 3: "STS_E_DEV
 STS_MEM_HOST, STS_MEM_DEVICE = 0, 1
 STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT = 1, 2, 3
 STS_OP_K, STS_OP_M = 0, 1
+STS_K_COUNT = 16
 
 
 class STSError(RuntimeError):
@@ -51,10 +52,7 @@ class Info(C.Structure):
                 ("rank", C.c_int64), ("inner_its_K", C.c_int64), ("inner_its_M", C.c_int64),
                 ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
                 ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
-                ("pad_", C.c_int32), ("cg_kernel_seconds", C.c_double), ("cg_launches", C.c_int64),
-                ("cg_col_iters", C.c_int64), ("cg_poll_restarts", C.c_int64),
-                ("mg_kernel_seconds", C.c_double), ("mg_iterations", C.c_int64),
-                ("mg_col_iters", C.c_int64), ("mg_bytes_per_node", C.c_double)]
+                ("pad_", C.c_int32), ("cg_poll_restarts", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
@@ -76,6 +74,8 @@ _SIGS = {
     "sts_true_residual": (C.c_int, [_P, _D]),
     "sts_numerical_rank": (C.c_int, [_P, C.POINTER(_I64)]),
     "sts_destroy": (None, [_P]),
+    "sts_kernel_profile": (C.c_int, [_P, _I32, C.POINTER(_F64), C.POINTER(_I64), C.POINTER(_F64)]),
+    "sts_kernel_name": (C.c_char_p, [_I32]),
     "sts_apply_op": (C.c_int, [C.POINTER(Space), _I32, _P, _I64, _P, _I64, _I32, _P]),
     "sts_cg": (C.c_int, [C.POINTER(Space), C.POINTER(_I32), _P, _I64, _P, _I64, _I32, _F64, _I32,
                          C.POINTER(_I32), _P]),
@@ -260,6 +260,15 @@ class Problem:
             _check(code)
         d["error"] = self._lib.sts_last_error().decode() if code != STS_OK else ""
         return d
+
+    def kernel_profile(self) -> dict:
+        """{name: (seconds, launches, algorithmic bytes)} of the last profiled solve."""
+        out = {}
+        for k in range(STS_K_COUNT):
+            sec, n, by = C.c_double(), C.c_int64(), C.c_double()
+            _check(self._lib.sts_kernel_profile(self._h, k, C.byref(sec), C.byref(n), C.byref(by)))
+            out[self._lib.sts_kernel_name(k).decode()] = (sec.value, n.value, by.value)
+        return out
 
     def rank(self) -> int:
         k = C.c_int64()

@@ -393,7 +393,8 @@ void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
     fill_kernel<<<1, 256, 0, st>>>(partial, (int64_t)m16 * 16, 0.0);
   } else {
     dim3 grid(m16 / 16, (unsigned)nch);
-    gemm_tn_kernel<<<grid, 256, 0, st>>>(rows, m, n, A, lda, B1, B2, n1, ldb, partial, m16);
+    launch(STS_K_GRAM, 8.0 * (double)rows * (m + n), gemm_tn_kernel, grid, dim3(256), 0, st, rows,
+           m, n, A, lda, B1, B2, n1, ldb, partial, m16);
   }
   STS_HIP(hipGetLastError());
   gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C1,
@@ -411,7 +412,8 @@ void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const
   if (m <= 0 || n <= 0 || rows <= 0) return;
   STS_REQUIRE(n <= 16, STS_E_INVALID, "gemm_nn_sub: n > 16");
   const int64_t blocks = (rows + 63) / 64;
-  gemm_nn_sub_kernel<<<(unsigned)blocks, 256, 0, st>>>(rows, m, n, A, lda, C, ldc, W, ldw);
+  launch(STS_K_BASIS_UPDATE, 8.0 * (double)rows * (m + 2 * n), gemm_nn_sub_kernel,
+         dim3((unsigned)blocks), dim3(256), 0, st, rows, m, n, A, lda, C, ldc, W, ldw);
   STS_HIP(hipGetLastError());
 }
 
@@ -465,7 +467,8 @@ void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double
   a.counter = counter;
   a.out = out;
   dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((n + 255) / 256));
-  residual_kernel<<<grid, 256, 0, st>>>(a);
+  launch(STS_K_RESIDUAL, 8.0 * ((double)rows * a.mtot + (double)n * a.mtot), residual_kernel, grid,
+         dim3(256), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

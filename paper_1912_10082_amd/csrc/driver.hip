@@ -38,6 +38,51 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+thread_local Profiler* g_profiler = nullptr;
+
+Profiler* active_profiler() { return g_profiler; }
+void set_active_profiler(Profiler* p) { g_profiler = p; }
+
+Profiler::~Profiler() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+void Profiler::reset() {
+  ids.clear();
+  bytes.clear();
+  collected = false;
+}
+
+void Profiler::next(int kid, double b, hipEvent_t* s, hipEvent_t* e) {
+  const size_t i = ids.size();
+  while (pool.size() < 2 * (i + 1)) {
+    hipEvent_t ev;
+    STS_HIP(hipEventCreate(&ev));
+    pool.push_back(ev);
+  }
+  *s = pool[2 * i];
+  *e = pool[2 * i + 1];
+  ids.push_back(kid);
+  bytes.push_back(b);
+}
+
+void Profiler::collect() {
+  if (collected) return;
+  for (int k = 0; k < STS_K_COUNT; ++k) {
+    sec[k] = byt[k] = 0.0;
+    cnt[k] = 0;
+  }
+  for (size_t i = 0; i < ids.size(); ++i) {
+    STS_HIP(hipEventSynchronize(pool[2 * i + 1]));
+    float ms = 0.0f;
+    STS_HIP(hipEventElapsedTime(&ms, pool[2 * i], pool[2 * i + 1]));
+    sec[ids[i]] += 1e-3 * ms;
+    cnt[ids[i]] += 1;
+    byt[ids[i]] += bytes[i];
+  }
+  collected = true;
+}
+
 // ---------------------------------------------------------------------------
 // spatial operators
 // ---------------------------------------------------------------------------
@@ -244,10 +289,6 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
 struct PollLoop {
   CGScal* host_scal = nullptr;   // pinned, 2 * kMaxCols
   hipEvent_t ev[2] = {nullptr, nullptr};
-  bool profile = false;
-  std::vector<hipEvent_t> tev;   // (start, end) per chunk, reused
-  double prof_seconds = 0.0;
-  int64_t prof_iters = 0, prof_col_iters = 0;
   int64_t poll_restarts = 0;
 
   PollLoop() = default;
@@ -257,7 +298,6 @@ struct PollLoop {
     if (host_scal) (void)hipHostFree(host_scal);
     for (auto e : ev)
       if (e) (void)hipEventDestroy(e);
-    for (auto e : tev) (void)hipEventDestroy(e);
   }
   void init() {
     if (host_scal) return;
@@ -265,11 +305,6 @@ struct PollLoop {
                           hipHostMallocDefault));
     STS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     STS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  }
-  void reset_profile(bool on) {
-    profile = on;
-    prof_seconds = 0.0;
-    prof_iters = prof_col_iters = 0;
   }
 
   // iterate(parity, cols, nl) queues one iteration writing state slot
@@ -286,29 +321,13 @@ struct PollLoop {
     int cols[kMaxCols], nl = 0;
     for (int c = 0; c < ncols; ++c) cols[nl++] = c;
     int slot = 0;
-    size_t nchunk = 0;
     bool done = false;
     while (!done) {
       bool pending = false;
       for (;;) {
-        if (profile) {
-          if (tev.size() < 2 * (nchunk + 1)) {
-            for (int q = 0; q < 2; ++q) {
-              hipEvent_t e;
-              STS_HIP(hipEventCreate(&e));
-              tev.push_back(e);
-            }
-          }
-          STS_HIP(hipEventRecord(tev[2 * nchunk], st));
-        }
         for (int i = 0; i < chunk; ++i) {
           ++iters;
           iterate((int)(iters & 1), cols, nl);
-        }
-        if (profile) {
-          STS_HIP(hipEventRecord(tev[2 * nchunk + 1], st));
-          prof_iters += chunk;
-          ++nchunk;
         }
         // state written by the last iteration of the chunk
         STS_HIP(hipMemcpyAsync(host_scal + slot * kMaxCols, dev_scal + (iters & 1) * kMaxCols,
@@ -349,14 +368,6 @@ struct PollLoop {
       ++poll_restarts;   // the polled copy was not current: keep iterating
       nl = n2;
       chunk = pipelined ? 8 : chunk_cap;
-    }
-    if (profile) {
-      for (size_t q = 0; q < nchunk; ++q) {
-        float ms = 0.0f;
-        STS_HIP(hipEventElapsedTime(&ms, tev[2 * q], tev[2 * q + 1]));
-        prof_seconds += 1e-3 * ms;
-      }
-      for (int c = 0; c < ncols; ++c) prof_col_iters += out[c].iters;
     }
   }
 };
@@ -512,6 +523,9 @@ struct sts_problem {
   bool mass_cheb = false;   // Mx solves by Chebyshev iteration
   MGPlan mg_plan_{};
   std::unique_ptr<MGRunner> mg;
+  // kernel timing of the last profiled solve
+  Profiler prof;
+  bool profiled = false;
 
   // small scratch
   DevBuf gram, tn_part, rinv, cinfo, norm0, smallv, Lb, T1, okflag;
@@ -1058,8 +1072,13 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       P->alg_bytes = 0.0;
       P->checks = 0;
     }
-    P->cg.poll.reset_profile(o.profile != 0);
-    if (P->mg) P->mg->poll.reset_profile(o.profile != 0);
+    // kernel timing for sts_kernel_profile, active until this call returns
+    struct ProfGuard {
+      explicit ProfGuard(Profiler* p) { set_active_profiler(p); }
+      ~ProfGuard() { set_active_profiler(nullptr); }
+    } prof_guard(o.profile ? &P->prof : nullptr);
+    if (o.profile) P->prof.reset();
+    P->profiled = o.profile != 0;
     ensure_capacity(P, P->k + (int64_t)b2 * (o.max_outer + 2), o.mem_budget);
     if (!P->smallv.p) P->smallv.alloc(std::max<int64_t>(P->kcap * 16, 4096) * 8);
     if (P->smallv.bytes < (size_t)P->kcap * 16 * 8) P->smallv.alloc(P->kcap * 16 * 8);
@@ -1194,16 +1213,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       info->orth_err = orth_error(P);
       info->rank = -1;
       info->alg_bytes = P->alg_bytes;
-      info->cg_kernel_seconds = P->cg.poll.prof_seconds;
-      info->cg_launches = P->cg.poll.prof_iters;
-      info->cg_col_iters = P->cg.poll.prof_col_iters;
       info->cg_poll_restarts = P->cg.poll.poll_restarts;
-      if (P->mg) {
-        info->mg_kernel_seconds = P->mg->poll.prof_seconds;
-        info->mg_iterations = P->mg->poll.prof_iters;
-        info->mg_col_iters = P->mg->poll.prof_col_iters;
-        info->mg_bytes_per_node = P->mg->bytes_per_node();
-      }
     }
     STS_HIP(hipStreamSynchronize(st));
     const double secs =
@@ -1259,6 +1269,27 @@ sts_status sts_numerical_rank(sts_problem* P, int64_t* rank) {
     STS_REQUIRE(P->solved, STS_E_STATE, "no solution yet");
     *rank = numerical_rank(P);
   });
+}
+
+sts_status sts_kernel_profile(sts_problem* P, int32_t kernel, double* seconds,
+                              int64_t* launches, double* alg_bytes) {
+  return run_guarded([&] {
+    STS_REQUIRE(P != nullptr, STS_E_INVALID, "problem is NULL");
+    STS_REQUIRE(kernel >= 0 && kernel < STS_K_COUNT, STS_E_INVALID, "unknown kernel");
+    STS_REQUIRE(P->profiled, STS_E_STATE, "the last solve was not profiled");
+    P->prof.collect();
+    if (seconds) *seconds = P->prof.sec[kernel];
+    if (launches) *launches = P->prof.cnt[kernel];
+    if (alg_bytes) *alg_bytes = P->prof.byt[kernel];
+  });
+}
+
+const char* sts_kernel_name(int32_t kernel) {
+  static const char* names[STS_K_COUNT] = {
+      "cg_iter",   "mg_down",  "mg_up",   "mg_coarse",     "pcg_a", "pcg_b",
+      "mass_cheb", "gram",     "basis_update", "residual", "tridiag", "bisect",
+      "inviter",   "backtransform", "sweep", "stencil"};
+  return (kernel >= 0 && kernel < STS_K_COUNT) ? names[kernel] : "";
 }
 
 void sts_destroy(sts_problem* P) {

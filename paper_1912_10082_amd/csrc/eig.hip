@@ -555,14 +555,18 @@ void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_
   double* lu = p;
 
   TriArgs t{k, A, lda, w.status, a, d, e, tau, vp, wp, bounds};
-  if (k <= kLdsPanelMaxK) tridiag_kernel<true><<<1, kTT, 0, st>>>(t);
-  else tridiag_kernel<false><<<1, kTT, 0, st>>>(t);
+  const double kk8 = 8.0 * (double)k * k;
+  if (k <= kLdsPanelMaxK)
+    launch(STS_K_TRIDIAG, kk8, tridiag_kernel<true>, dim3(1), dim3(kTT), 0, st, t);
+  else
+    launch(STS_K_TRIDIAG, kk8, tridiag_kernel<false>, dim3(1), dim3(kTT), 0, st, t);
   STS_HIP(hipGetLastError());
   const int nthreads = k * kSect;
-  bisect_kernel<<<(nthreads + 255) / 256, 256, 0, st>>>(k, d, e, bounds, lam);
+  launch(STS_K_BISECT, 24.0 * k, bisect_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, st, k,
+         d, e, bounds, lam);
   STS_HIP(hipGetLastError());
   InvArgs iv{k, d, e, lam, bounds, z, lu};
-  inviter_kernel<<<(k + 63) / 64, 64, 0, st>>>(iv);
+  launch(STS_K_INVITER, kk8, inviter_kernel, dim3((k + 63) / 64), dim3(64), 0, st, iv);
   STS_HIP(hipGetLastError());
   // two Newton-Schulz steps Z <- Z (3 I - Z^T Z) / 2 (ping-pong z / B)
   const unsigned nb = (unsigned)((kk + 255) / 256);
@@ -581,8 +585,8 @@ void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_
   STS_HIP(hipGetLastError());
   rayleigh_kernel<<<(k + 3) / 4, 256, 0, st>>>(k, zc, tzc, lam);
   STS_HIP(hipGetLastError());
-  backtransform_kernel<<<(k + 3) / 4, 256, 4 * (size_t)k * sizeof(double), st>>>(k, a, tau, zc, Q,
-                                                                                 ldq);
+  launch(STS_K_BACKTRANSFORM, 2.0 * kk8, backtransform_kernel, dim3((k + 3) / 4), dim3(256),
+         (unsigned)(4 * (size_t)k * sizeof(double)), st, k, a, tau, zc, Q, ldq);
   STS_HIP(hipGetLastError());
 }
 

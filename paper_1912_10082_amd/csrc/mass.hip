@@ -178,7 +178,9 @@ void mass_cheb_solve(const Grid& g, const Stencil& M, int ncols, const double* c
     a.xout = last ? x : xbuf[l & 1];
     a.ldx = last ? ldx : ld;
     a.dout = last ? nullptr : dbuf[l & 1];
-    mass_cheb_kernel<<<blocks, kT, 0, st>>>(a);
+    // read b (and x, d after the first launch), write x (and d before the last)
+    const double per = 8.0 + (k0 == 0 ? 0.0 : 16.0) + 8.0 + (last ? 0.0 : 8.0);
+    launch(STS_K_MASS_CHEB, per * g.nh * ncols, mass_cheb_kernel, dim3(blocks), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
     k0 += steps;
   }

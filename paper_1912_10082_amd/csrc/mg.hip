@@ -700,7 +700,8 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.st = act;
     a.mu = p.mu;
     a.sm = sm;
-    mg_down_kernel<<<a.ntx * a.nty * nlaunch, kT, 0, st>>>(a);
+    launch(STS_K_MG_DOWN, 8.0 * ((double)a.nf * a.nf + (double)a.nc * a.nc) * nlaunch,
+           mg_down_kernel, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
   }
   {
@@ -716,7 +717,8 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     c.st = act;
     c.part = (partials && L == 0) ? w.part_rz : nullptr;
     c.max_tiles = w.max_tiles;
-    mg_coarse_kernel<<<nlaunch, kCT, 0, st>>>(c);
+    launch(STS_K_MG_COARSE, 16.0 * c.n * c.n * nlaunch, mg_coarse_kernel, dim3(nlaunch), dim3(kCT),
+           0, st, c);
     STS_HIP(hipGetLastError());
   }
   for (int l = L - 1; l >= 0; --l) {
@@ -737,7 +739,8 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.sm = sm;
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
     a.max_tiles = w.max_tiles;
-    mg_up_kernel<<<a.ntx * a.nty * nlaunch, kT, 0, st>>>(a);
+    launch(STS_K_MG_UP, 8.0 * (2.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch, mg_up_kernel,
+           dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
   }
 }
@@ -756,9 +759,10 @@ void pcg_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int 
   mg_vcycle(w, w.scal + (parity ^ 1) * kMaxCols, cols, nlaunch, true, st);
   const PCGArgs a = pcg_args(w, parity, cols, nlaunch, ncols);
   const int blocks = a.ntx * a.nty * nlaunch;
-  pcg_a_kernel<<<blocks, kT, 0, st>>>(a);
+  const double nn = (double)a.n * a.n * nlaunch;
+  launch(STS_K_PCG_A, 32.0 * nn, pcg_a_kernel, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
-  pcg_b_kernel<<<blocks, kT, 0, st>>>(a);
+  launch(STS_K_PCG_B, 48.0 * nn, pcg_b_kernel, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

@@ -203,7 +203,7 @@ void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64
   if (k <= 0 || nt <= 0) return;
   STS_REQUIRE(p >= 1 && p <= 4, STS_E_INVALID, "time_sweep: 1 <= p <= 4");
   SweepArgs a{k, nt, p, lam, qb, ldqb, F2, ldf, t, Z, ldz, nullptr, 0};
-  sweep_kernel<<<(k + 63) / 64, 64, 0, st>>>(a);
+  launch(STS_K_SWEEP, 8.0 * (double)k * nt, sweep_kernel, dim3((k + 63) / 64), dim3(64), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 
@@ -211,7 +211,7 @@ void time_sweep_full(int k, int nt, const double* lam, const double* G, int64_t 
                      const TimeOps& t, double* Z, int64_t ldz, hipStream_t st) {
   if (k <= 0 || nt <= 0) return;
   SweepArgs a{k, nt, 0, lam, nullptr, 0, nullptr, 0, t, Z, ldz, G, ldg};
-  sweep_kernel<<<(k + 63) / 64, 64, 0, st>>>(a);
+  launch(STS_K_SWEEP, 8.0 * (double)k * nt, sweep_kernel, dim3((k + 63) / 64), dim3(64), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

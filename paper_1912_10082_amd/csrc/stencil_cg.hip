@@ -680,9 +680,11 @@ void cg_iterate(const Grid& g, const Stencil& K, const Stencil& M, const int* op
     a.cols[j] = cols[j];
   }
   const int blocks = cg_tiles(g) * nlaunch;
-  if (g.dim == 1) cg_iter_kernel<1><<<blocks, kThreads, 0, st>>>(a);
-  else if (g.dim == 2) cg_iter_kernel<2><<<blocks, kThreads, 0, st>>>(a);
-  else cg_iter_kernel<3><<<blocks, kThreads, 0, st>>>(a);
+  const double by = 48.0 * (double)g.nh * nlaunch;
+  if (g.dim == 1) launch(STS_K_CG_ITER, by, cg_iter_kernel<1>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else if (g.dim == 2)
+    launch(STS_K_CG_ITER, by, cg_iter_kernel<2>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else launch(STS_K_CG_ITER, by, cg_iter_kernel<3>, dim3(blocks), dim3(kThreads), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 
@@ -707,9 +709,11 @@ void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int*
     a.cf.m[i] = M.c[i];
   }
   const int blocks = a.ntx * a.nty * a.ntz * ncols;
-  if (g.dim == 1) apply_kernel<1><<<blocks, kThreads, 0, st>>>(a);
-  else if (g.dim == 2) apply_kernel<2><<<blocks, kThreads, 0, st>>>(a);
-  else apply_kernel<3><<<blocks, kThreads, 0, st>>>(a);
+  const double by = 16.0 * (double)g.nh * ncols;
+  if (g.dim == 1) launch(STS_K_STENCIL, by, apply_kernel<1>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else if (g.dim == 2)
+    launch(STS_K_STENCIL, by, apply_kernel<2>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else launch(STS_K_STENCIL, by, apply_kernel<3>, dim3(blocks), dim3(kThreads), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

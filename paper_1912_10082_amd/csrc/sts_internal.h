@@ -1,10 +1,14 @@
 // Internal declarations shared by the HIP kernels and the host driver.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
 
 #include "../../include/sts.h"
 
@@ -32,6 +36,54 @@ struct Error {
   do {                                                    \
     if (!(cond)) throw ::sts::Error{(code), (msg)};       \
   } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel profiling (opts.profile = 1)
+// ---------------------------------------------------------------------------
+
+// Per-launch start/stop events attached to the dispatches themselves
+// (hipExtLaunchKernel), with the algorithmic bytes of each launch; the
+// elapsed times are read only when asked for, after the timed work.
+struct Profiler {
+  std::vector<hipEvent_t> pool;   // start / stop pairs
+  std::vector<int> ids;
+  std::vector<double> bytes;
+  double sec[STS_K_COUNT] = {};
+  int64_t cnt[STS_K_COUNT] = {};
+  double byt[STS_K_COUNT] = {};
+  bool collected = false;
+  Profiler() = default;
+  Profiler(const Profiler&) = delete;
+  Profiler& operator=(const Profiler&) = delete;
+  ~Profiler();
+  void reset();
+  void next(int kid, double b, hipEvent_t* s, hipEvent_t* e);
+  void collect();
+};
+// The profiler of the calling thread's current solve, or null.
+Profiler* active_profiler();
+void set_active_profiler(Profiler* p);
+
+template <std::size_t... I, typename Tup>
+inline void arg_ptrs(Tup& t, void** out, std::index_sequence<I...>) {
+  ((out[I] = static_cast<void*>(&std::get<I>(t))), ...);
+}
+
+// Launch a kernel; under an active profiler with start/stop events.
+template <typename... KArgs, typename... Args>
+inline void launch(int kid, double bytes, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                   unsigned shmem, hipStream_t st, Args&&... args) {
+  static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+  std::tuple<KArgs...> tup(std::forward<Args>(args)...);
+  void* ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+  arg_ptrs(tup, ptrs, std::index_sequence_for<KArgs...>{});
+  hipEvent_t s = nullptr, e = nullptr;
+  if (Profiler* p = active_profiler()) p->next(kid, bytes, &s, &e);
+  hipError_t err = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs,
+                                      shmem, st, s, e, 0);
+  if (err != hipSuccess)
+    throw Error{STS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(err)};
+}
 
 // ---------------------------------------------------------------------------
 // spatial operators as constant-coefficient stencils
