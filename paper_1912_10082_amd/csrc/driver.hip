@@ -422,6 +422,8 @@ struct MGRunner {
       w.ld[l] = pad_ld((int64_t)plan.n[l] * plan.n[l]);
       tot += 2 * w.ld[l] * kMaxCols;
     }
+    const bool big = plan.exact > kMGCoarseMax;
+    if (big) tot += 2 * w.ld[plan.nlev] * kMaxCols;
     w.ld[0] = pad_ld((int64_t)plan.n[0] * plan.n[0]);
     levels.alloc(std::max<int64_t>(tot, 1) * 8);
     vecs.alloc(5 * w.ld[0] * kMaxCols * 8);
@@ -430,6 +432,10 @@ struct MGRunner {
       w.b[l] = q;
       w.e[l] = q + w.ld[l] * kMaxCols;
       q += 2 * w.ld[l] * kMaxCols;
+    }
+    if (big) {
+      w.t1 = q;
+      w.t2 = q + w.ld[plan.nlev] * kMaxCols;
     }
     double* v = vecs.d();
     w.b[0] = v;

@@ -14,13 +14,15 @@
 //    for the interval [1/2, 2] of its spectrum, before and after each coarse
 //    correction (the same polynomial both times, so the two are adjoint);
 //  - restriction P^T of the residual, prolongation P of the correction;
-//  - levels above kMGCoarseMax nodes per direction run as tiled launches; the
-//    coarsest level (at most kMGCoarseMax) is solved exactly in one
-//    work-group per column by the fast sine transform: with
-//    T = tridiag(-1, 2, -1) = S diag(l) S (S the orthonormal, symmetric DST-I
-//    matrix), Kx U = mu (T U + U T) for the nodal array U, so
-//    U = S [(S B S) / (mu (l_y + l_x))] S -- four small GEMMs on the matrix
-//    cores.
+//  - the fine levels run as tiled launches; the coarsest level is solved
+//    exactly by the fast sine transform: with T = tridiag(-1, 2, -1) =
+//    S diag(l) S (S the orthonormal, symmetric DST-I matrix),
+//    Kx U = mu (T U + U T) for the nodal array U, so
+//    U = S [(S B S) / (mu (l_y + l_x))] S -- four GEMMs on the matrix cores,
+//    in one work-group per column up to kMGCoarseMax nodes per direction,
+//    over many work-groups up to kMGExactMax.  Grids above kMGCoarseMax keep
+//    at least one smoothed level, grids above kMGExactMax halve until the
+//    coarsest level fits.
 // The V-cycle is a fixed symmetric positive definite operator, so the outer
 // iteration is ordinary preconditioned CG.
 //
@@ -320,14 +322,18 @@ __device__ __forceinline__ void lds_gemm(const double* A, const double* B, doubl
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int r0 = (wv & 3) * 16, c0 = (wv >> 2) * 16;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int k0 = 0; k0 < kE; k0 += 4)
-    acc = mfma(A[(r0 + i) * kEL + k0 + g], B[(k0 + g) * kEL + c0 + i], acc);
+  d4 acc[4] = {};
+#pragma unroll
+  for (int k0 = 0; k0 < kE; k0 += 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[j] = mfma(A[(r0 + i) * kEL + k0 + 4 * j + g], B[(k0 + 4 * j + g) * kEL + c0 + i], acc[j]);
+  }
+  const d4 sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int y = r0 + 4 * q + g, x = c0 + i;
-    double v = acc[q];
+    double v = sum[q];
     if (scale) v = (y < n && x < n) ? v / (mu * (l[y] + l[x])) : 0.0;
     C[y * kEL + x] = v;
   }
@@ -369,6 +375,97 @@ __global__ __launch_bounds__(kCT) void mg_coarse_kernel(CoarseArgs a) {
   if (a.part) {
     part = block_sum<kCT>(part, red);
     if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles] = part;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coarse level of order 64..kMGExactMax: the same exact solve as four
+// row-major m x m GEMMs, C = A B (optionally divided by mu (l_r + l_c)), over
+// many work-groups.  A work-group owns a 32 x 32 tile of C: it stages the
+// 32-row strip of A and the 32-column strip of B (the whole inner dimension)
+// in LDS with coalesced loads, then its four waves each accumulate one
+// 16 x 16 quarter on the matrix cores.
+// ---------------------------------------------------------------------------
+constexpr int kBT = 32;                  // output tile
+constexpr int kAS = kMGExactMax + 2;     // LDS row stride of the A strip (k index, odd)
+constexpr int kBS = kBT + 1;             // LDS row stride of the B strip (column index)
+
+struct DstGemmArgs {
+  int m;
+  int nlaunch;
+  int cols[kMaxCols];
+  const double* A;     // shared (a_ld = 0) or per column
+  int64_t a_ld;        // column stride of A (0: shared)
+  const double* B;
+  int64_t b_ld;
+  double* C;
+  int64_t c_ld;
+  const double* l;     // eigenvalues if the product is scaled, else null
+  double mu;
+  const CGScal* st;
+};
+
+__global__ __launch_bounds__(256) void dst_gemm_kernel(DstGemmArgs a) {
+  __shared__ double As[kBT * kAS];
+  __shared__ double Bs[(kMGExactMax + 1) * kBS];
+  const int m = a.m;
+  const int nt = (m + kBT - 1) / kBT;
+  const int r0 = (blockIdx.x % nt) * kBT, c0 = (blockIdx.x / nt) * kBT;
+  const int col = a.cols[blockIdx.y];
+  if (a.st && !a.st[col].active) return;
+  const double* A = a.A + (size_t)col * a.a_ld;
+  const double* B = a.B + (size_t)col * a.b_ld;
+  double* C = a.C + (size_t)col * a.c_ld;
+  // stage the strips: all loads of a thread are issued before any LDS store
+  // (the inner dimension is padded to kMGExactMax + 1 = 256 with zeros)
+  constexpr int KP = kMGExactMax + 1;
+  constexpr int NA = kBT * KP / 256, NB = KP * kBT / 256;
+  double va[NA], vb[NB];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int ii = threadIdx.x + u * 256;
+    const int r = ii / KP, k = ii % KP;
+    va[u] = (r0 + r < m && k < m) ? A[(size_t)(r0 + r) * m + k] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int ii = threadIdx.x + u * 256;
+    const int k = ii / kBT, c = ii % kBT;
+    vb[u] = (k < m && c0 + c < m) ? B[(size_t)k * m + c0 + c] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int ii = threadIdx.x + u * 256;
+    As[(ii / KP) * kAS + ii % KP] = va[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int ii = threadIdx.x + u * 256;
+    Bs[(ii / kBT) * kBS + ii % kBT] = vb[u];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int tr = (wv & 1) * 16, tc = (wv >> 1) * 16;
+  // four independent accumulators: the FP64 MFMA result latency is long
+  d4 acc[4] = {};
+  const int kp = (m + 15) & ~15;
+  for (int k0 = 0; k0 < kp; k0 += 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[j] = mfma(As[(tr + i) * kAS + k0 + 4 * j + g], Bs[(k0 + 4 * j + g) * kBS + tc + i],
+                    acc[j]);
+  }
+  const d4 sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  const int c = c0 + tc + i;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + tr + 4 * q + g;
+    if (r < m && c < m) {
+      double v = sum[q];
+      if (a.l) v /= a.mu * (a.l[r] + a.l[c]);
+      C[(size_t)r * m + c] = v;
+    }
   }
 }
 
@@ -650,7 +747,9 @@ bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan) {
   p.mu = mu;
   int L = 0, n = g.nx;
   p.n[0] = n;
-  while (n > kMGCoarseMax) {
+  // halve while above kMGExactMax, and at least once above kMGCoarseMax, so
+  // that every grid larger than kMGCoarseMax keeps a smoothed fine level
+  while (n > kMGExactMax || (L == 0 && n > kMGCoarseMax)) {
     if ((n & 1) == 0 || L + 1 >= kMGMaxLevels) return false;   // does not halve
     n = (n - 1) / 2;
     p.n[++L] = n;
@@ -704,7 +803,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
            mg_down_kernel, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
   }
-  {
+  if (p.n[L] <= kMGCoarseMax) {
     CoarseArgs c{};
     c.n = p.n[L];
     c.ld = w.ld[L];
@@ -719,7 +818,36 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     c.max_tiles = w.max_tiles;
     launch(STS_K_MG_COARSE, 16.0 * c.n * c.n * nlaunch, mg_coarse_kernel, dim3(nlaunch), dim3(kCT),
            0, st, c);
-    STS_HIP(hipGetLastError());
+  } else {
+    // e_L = S (S b_L S ./ (mu (l_r + l_c))) S, four GEMMs (L >= 1 here)
+    const int m = p.n[L];
+    const double* S = w.dst;
+    const double* lv = w.dst + (size_t)m * m;
+    DstGemmArgs g{};
+    g.m = m;
+    g.nlaunch = nlaunch;
+    for (int j = 0; j < nlaunch; ++j) g.cols[j] = cols[j];
+    g.mu = p.mu;
+    g.st = act;
+    const int nt = (m + kBT - 1) / kBT;
+    const dim3 grid(nt * nt, nlaunch);
+    const double by = 8.0 * 3.0 * (double)m * m * nlaunch;
+    auto gemm = [&](const double* A, int64_t ald, const double* B, int64_t bld, double* C,
+                    int64_t cld, const double* l) {
+      g.A = A;
+      g.a_ld = ald;
+      g.B = B;
+      g.b_ld = bld;
+      g.C = C;
+      g.c_ld = cld;
+      g.l = l;
+      launch(STS_K_MG_COARSE, by, dst_gemm_kernel, grid, dim3(256), 0, st, g);
+    };
+    const int64_t ld = w.ld[L];
+    gemm(S, 0, w.b[L], ld, w.t1, ld, nullptr);    // T = S B
+    gemm(w.t1, ld, S, 0, w.t2, ld, lv);           // X = (T S) ./ (mu (l_r + l_c))
+    gemm(S, 0, w.t2, ld, w.t1, ld, nullptr);      // T = S X
+    gemm(w.t1, ld, S, 0, w.e[L], ld, nullptr);    // e = T S
   }
   for (int l = L - 1; l >= 0; --l) {
     LevelArgs a{};

@@ -169,7 +169,8 @@ void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int*
 // ---------------------------------------------------------------------------
 
 constexpr int kMGMaxLevels = 12;
-constexpr int kMGCoarseMax = 63;   // the coarsest level (at most this size) is solved exactly
+constexpr int kMGCoarseMax = 63;   // coarsest levels up to this size: one work-group per column
+constexpr int kMGExactMax = 255;   // largest exactly solved (coarsest) level
 constexpr int kMGNu = 3;           // Chebyshev smoothing steps before and after
 
 struct MGPlan {
@@ -203,6 +204,8 @@ struct MGWork {
   double* alpha;                 // kMaxCols
   int max_tiles;
   const double* dst;             // device copy of mg_dst_table(plan.exact)
+  double* t1;                    // coarsest-level temporaries above kMGCoarseMax
+  double* t2;                    //   (stride ld[nlev], kMaxCols columns)
 };
 // e[0][:, c] = B b[0][:, c] (one V-cycle) for the columns cols[0..nlaunch);
 // columns whose state in `act` (may be null) is inactive are skipped; with

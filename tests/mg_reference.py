@@ -9,9 +9,10 @@ evaluating coarse P1 hat functions at fine nodes, and a recursive V-cycle --
 so that the GPU V-cycle can be compared entry by entry.
 
 V-cycle on level n (interior nodes per direction), right-hand side b:
-  n <= 63             exact solve (larger levels must be odd);
+  exact solve         on the finest level if n <= 63, on a coarser level if
+                      n <= 255;
   otherwise           three Chebyshev smoothing steps from zero, restriction of
-                      the residual by P^T to n_c = (n - 1) / 2, recursive
+                      the residual by P^T to n_c = (n - 1) / 2 (n must be odd),
                       V-cycle there, correction u += P e_c, three more
                       Chebyshev steps on the residual equation.
 Chebyshev smoothing targets [1/2, 2] of the spectrum of D^{-1} Kx (D its
@@ -32,7 +33,8 @@ from oracle import fem
 
 CHEB_STEPS = 3
 CHEB_INTERVAL = (0.5, 2.0)
-EXACT_MAX = 63
+EXACT_FINEST = 63     # finest level solved exactly up to this size
+EXACT_COARSE = 255    # coarser levels solved exactly up to this size
 
 
 def hat(xi, eta):
@@ -86,23 +88,26 @@ def chebyshev(K, b, u, steps=CHEB_STEPS):
     return u
 
 
-def vcycle(b: np.ndarray, n: int, mu: float) -> np.ndarray:
+def vcycle(b: np.ndarray, n: int, mu: float, finest: bool = True) -> np.ndarray:
     """One V-cycle from zero applied to b (length n^2, or n^2 x m)."""
     K = stiffness(n, mu)
-    if n <= EXACT_MAX:
+    if n <= (EXACT_FINEST if finest else EXACT_COARSE):
         return spla.spsolve(K.tocsc(), b).reshape(b.shape)
-    assert n % 2 == 1, "levels above 63 must halve"
+    assert n % 2 == 1, "levels that do not fit the exact solve must halve"
     u = chebyshev(K, b, np.zeros_like(b))
     nc = (n - 1) // 2
     P = prolongation(nc)
-    u = u + P @ vcycle(P.T @ (b - K @ u), nc, mu)
+    u = u + P @ vcycle(P.T @ (b - K @ u), nc, mu, finest=False)
     return chebyshev(K, b, u)
 
 
 def supported(n: int) -> bool:
-    """Grids the library's multigrid accepts: n halves down to at most 63."""
-    while n > 63:
+    """Grids the library's multigrid accepts: n <= 63, or n odd halving (odd at
+    each step) down to at most 255."""
+    first = True
+    while n > EXACT_COARSE or (first and n > EXACT_FINEST):
         if n % 2 == 0:
             return False
         n = (n - 1) // 2
+        first = False
     return n >= 1

@@ -105,7 +105,7 @@ def test_destroy_null_and_state_errors():
 def test_multigrid_entry_points_reject_unsupported_grids():
     """Argument checks of the multigrid calls run before any device work."""
     lib = b.load()
-    for dim, n in ((2, 100), (2, 129), (2, 510), (1, 127), (3, 15)):
+    for dim, n in ((2, 100), (2, 130), (2, 510), (1, 127), (3, 15)):
         s = sts.make_space(dim, n)
         nh = n ** dim
         assert lib.sts_pcg_mg(C.byref(s), None, nh, None, nh, 1, 1e-12, 10, None,

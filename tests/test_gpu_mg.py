@@ -41,12 +41,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-# Sizes: exact solves alone (1 .. 31, even 62), one level in LDS above an
-# exact solve (33, 63), one tiled level with a coarse grid that is an exact
-# multiple of the tile in x (65 -> 32) or in y (97 -> 48), ragged tiles
-# (81 -> 40, 125 -> 62, 127 -> 63 -> 31), and two and three tiled levels
-# (255, 511).
-VC_SIZES = [1, 2, 3, 31, 33, 62, 63, 65, 81, 97, 125, 127, 255, 511]
+# Sizes: exact solves in one work-group alone (1 .. 63, even 62), one tiled
+# level above a one-work-group exact solve with a coarse grid that is an
+# exact multiple of the tile in x (65 -> 32) or in y (97 -> 48) or ragged
+# (81 -> 40, 125 -> 62, 127 -> 63), one tiled level above the many-work-group
+# exact solve (129 -> 64, 255 -> 127, 511 -> 255), and two tiled levels
+# (1023 -> 511 -> 255).
+VC_SIZES = [1, 2, 3, 31, 33, 62, 63, 65, 81, 97, 125, 127, 129, 255, 511, 1023]
 
 
 @pytest.mark.parametrize("n", VC_SIZES)
@@ -58,7 +59,10 @@ def test_vcycle_matches_reference(n):
     Z = host(sts.mg_vcycle(sts.make_space(2, n, mu), dev(R)))
     Zr = mgr.vcycle(R, n, mu)
     scale = abs(Zr).max()
-    np.testing.assert_allclose(Z, Zr, rtol=0, atol=1e-13 * scale)
+    # the reference's sparse LU on the 255^2 coarse grid is accurate to about
+    # kappa eps (kappa ~ 3e4); two smoothed levels above it amplify that
+    tol = 1e-13 if n < 1023 else 1e-11
+    np.testing.assert_allclose(Z, Zr, rtol=0, atol=tol * scale)
     assert np.all(Z[:, 2] == 0.0)
 
 
@@ -102,7 +106,7 @@ def test_pcg_zero_rhs_iteration_cap_and_bad_grids():
     B = np.random.default_rng(2).normal(size=(63 * 63, 1))
     X, its, _ = sts.pcg_mg(sts.make_space(2, 63), dev(B), rtol=1e-12)
     assert its[0] == 1
-    for bad in (sts.make_space(2, 100), sts.make_space(2, 129), sts.make_space(1, 127),
+    for bad in (sts.make_space(2, 100), sts.make_space(2, 130), sts.make_space(1, 127),
                 sts.make_space(3, 15)):
         nh = int(np.prod([bad.n[d] for d in range(3)]))
         with pytest.raises(sts.STSError) as e:

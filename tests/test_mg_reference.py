@@ -93,8 +93,9 @@ def test_pcg_iterations_do_not_grow_with_refinement():
 
 
 def test_supported_grids():
-    assert all(mgr.supported(n) for n in (1, 2, 31, 62, 63, 65, 97, 125, 127, 255, 511, 1023))
-    assert not any(mgr.supported(n) for n in (64, 100, 129, 256, 510))
+    assert all(mgr.supported(n) for n in (1, 2, 31, 62, 63, 65, 97, 125, 127, 129, 255, 511,
+                                          1023, 2047))
+    assert not any(mgr.supported(n) for n in (64, 100, 130, 256, 510, 1022))
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 16, 31])
