@@ -3,11 +3,11 @@
 // The block Gram-Schmidt of the extended Krylov basis contracts the tall
 // basis V (Nh x k) with a thin block W (Nh x <= 16): C = V^T W and W -= V C.
 // Both are HBM-bound (about one flop per byte); the matrix cores are used
-// for the contraction itself through v_mfma_f64_16x16x4f64.  With lane l
-// supplying a = X[l % 16][l / 16] and b = Y[l / 16][l % 16], element q of lane
-// l's accumulator is (X Y)[l % 16][4 (l / 16) + q] (measured on gfx950: rows of
-// the product follow the lane within a 16-lane group, columns follow the group
-// and the accumulator element).
+// for the contraction itself through v_mfma_f64_16x16x4f64.  With lane
+// l = i + 16 g supplying a = X[i][g] and b = Y[g][i], element q of lane l's
+// accumulator is (X Y)[4 q + g][i] (measured on gfx950: columns of the product
+// follow the lane within a 16-lane group, rows follow the group and the
+// accumulator element).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,47 +30,133 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-constexpr int kRowsPerChunk = 1024;   // rows of one gemm_tn work-group
+// Work split of C = A^T B: a work-group takes T consecutive 16-column tiles
+// of A (one accumulator each, so a wave runs T independent MFMA chains and
+// loads each B value once for all of them) over NW * rpw consecutive rows,
+// NW waves taking rpw rows each.  At most kMaxChunks row chunks keep the
+// cross-chunk reduction to a few loads per lane.
+constexpr int kMaxChunks = 256;
 
-int64_t tn_chunks(int64_t rows) { return (rows + kRowsPerChunk - 1) / kRowsPerChunk; }
+struct TnPlan {
+  int T, NW, rpw;
+  int64_t nch;
+  int groups;
+};
 
-// partial[chunk][i][j] (16-padded m x 16) of A^T B over the chunk's rows.
+TnPlan tn_plan(int64_t rows, int m) {
+  TnPlan p{};
+  const int tiles = (m + 15) / 16;
+  p.T = tiles >= 4 ? 4 : (tiles >= 2 ? 2 : 1);
+  p.NW = p.T == 1 ? 16 : 4;
+  p.groups = (tiles + p.T - 1) / p.T;
+  // about 512 work-groups in all, at least 64 rows per wave
+  const int64_t target = std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, 512 / p.groups));
+  const int64_t per = (std::max<int64_t>(rows, 1) + p.NW * target - 1) / (p.NW * target);
+  p.rpw = (int)std::max<int64_t>(64, (per + 15) / 16 * 16);
+  p.nch = std::max<int64_t>(1, (rows + (int64_t)p.NW * p.rpw - 1) / ((int64_t)p.NW * p.rpw));
+  return p;
+}
+
+// partial[chunk][c][j] (c < m16, j < 16) of A^T B over the chunk's rows.
 // Columns j < n1 of B come from B1, the rest from B2 (same leading dimension).
-__global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t rows, int m, int n, const double* A,
-                                                      int64_t lda, const double* B1,
-                                                      const double* B2, int n1, int64_t ldb,
-                                                      double* partial, int m16) {
-  __shared__ double acc_s[4][256];
+// Lane (i, g) of a wave feeds rows r + 4 g .. r + 4 g + 3 of column i of each
+// tile to the four MFMAs of a 16-row step; VEC reads them as two 16-byte
+// loads (columns 16-byte aligned, even leading dimensions).
+template <int T, int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW) void gemm_tn_kernel(int64_t rows, int m, int n,
+                                                          const double* A, int64_t lda,
+                                                          const double* B1, const double* B2,
+                                                          int n1, int64_t ldb, double* partial,
+                                                          int m16, int rpw) {
+  __shared__ double red[NW - 1][T][256];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
-  const int tile = blockIdx.x;            // 16 columns of A
+  const int c0 = blockIdx.x * 16 * T;
   const int64_t chunk = blockIdx.y;
-  const int j0 = tile * 16;
-  const int64_t r_begin = chunk * kRowsPerChunk + (int64_t)wv * (kRowsPerChunk / 4);
-  const int64_t r_end = min(r_begin + kRowsPerChunk / 4, rows);
-  const bool acol = (j0 + i) < m;
-  const bool bcol = i < n;
-  const double* Ap = A + (int64_t)(j0 + i) * lda;
-  const double* Bp = i < n1 ? B1 + (int64_t)i * ldb : B2 + (int64_t)(i - n1) * ldb;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r = r_begin; r < r_end; r += 16) {
-    double av[4], bv[4];
-    const int64_t rr = r + 4 * g;
+  const int64_t rb = (chunk * NW + wv) * (int64_t)rpw;
+  const int64_t re = min(rb + rpw, rows);
+  const double* Ap[T];
+  bool aok[T];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const bool ok = (rr + s) < r_end;
-      av[s] = (ok && acol) ? Ap[rr + s] : 0.0;
-      bv[s] = (ok && bcol) ? Bp[rr + s] : 0.0;
+  for (int t = 0; t < T; ++t) {
+    const int col = c0 + 16 * t + i;
+    aok[t] = col < m;
+    Ap[t] = A + (int64_t)(aok[t] ? col : 0) * lda;
+  }
+  const bool bok = i < n;
+  const double* Bp = !bok ? B1 : (i < n1 ? B1 + (int64_t)i * ldb : B2 + (int64_t)(i - n1) * ldb);
+  d4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  int64_t r = rb;
+  for (; r + 16 <= re; r += 16) {
+    const int64_t rr = r + 4 * g;
+    double av[T][4], bv[4];
+    if (VEC) {
+      const double2 b0 = bok ? *(const double2*)(Bp + rr) : double2{0.0, 0.0};
+      const double2 b1 = bok ? *(const double2*)(Bp + rr + 2) : double2{0.0, 0.0};
+      bv[0] = b0.x;
+      bv[1] = b0.y;
+      bv[2] = b1.x;
+      bv[3] = b1.y;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const double2 a0 = aok[t] ? *(const double2*)(Ap[t] + rr) : double2{0.0, 0.0};
+        const double2 a1 = aok[t] ? *(const double2*)(Ap[t] + rr + 2) : double2{0.0, 0.0};
+        av[t][0] = a0.x;
+        av[t][1] = a0.y;
+        av[t][2] = a1.x;
+        av[t][3] = a1.y;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bv[s] = bok ? Bp[rr + s] : 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) av[t][s] = aok[t] ? Ap[t][rr + s] : 0.0;
+      }
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = mfma(av[s], bv[s], acc);
-  }
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc_s[wv][(4 * q + g) * 16 + i] = acc[q];
+      for (int t = 0; t < T; ++t) acc[t] = mfma(av[t][s], bv[s], acc[t]);
+  }
+  if (r < re) {   // ragged end of the wave's rows
+    const int64_t rr = r + 4 * g;
+    double av[T][4], bv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool ok = rr + s < re;
+      bv[s] = (ok && bok) ? Bp[rr + s] : 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) av[t][s] = (ok && aok[t]) ? Ap[t][rr + s] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma(av[t][s], bv[s], acc[t]);
+  }
+  // element q of a lane's accumulator is (tile row 4 q + g, column i)
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wv - 1][t][(4 * q + g) * 16 + i] = acc[t][q];
+  }
   __syncthreads();
-  const int t = threadIdx.x;   // (row, col) = (t / 16, t % 16) of the 16x16 block
-  const double v = (acc_s[0][t] + acc_s[1][t]) + (acc_s[2][t] + acc_s[3][t]);
-  partial[(chunk * m16 + j0 + t / 16) * 16 + (t % 16)] = v;
+  if (wv != 0) return;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    if (c0 + 16 * t >= m16) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = (4 * q + g) * 16 + i;
+      double v = acc[t][q];
+#pragma unroll
+      for (int w = 0; w < NW - 1; ++w) v += red[w][t][e];
+      partial[(chunk * m16 + c0 + 16 * t + 4 * q + g) * 16 + i] = v;
+    }
+  }
 }
 
 // One wave per output element: lanes take chunks lane, lane + 64, ... and the
@@ -378,8 +464,26 @@ __global__ void sumsq_kernel(int64_t rows, int ncols, const double* A, int64_t l
 }  // namespace
 
 int64_t gemm_tn_partial_size(int64_t rows, int m) {
-  return tn_chunks(rows) * (int64_t)(((m + 15) / 16) * 16) * 16;
+  // every plan has at most min(kMaxChunks, ceil(rows / 256)) chunks
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, (rows + 255) / 256));
+  return nch * (int64_t)(((m + 15) / 16) * 16) * 16;
 }
+
+template <int T, int NW>
+static void launch_tn(bool vec, const TnPlan& p, int64_t rows, int m, int n, const double* A,
+                      int64_t lda, const double* B1, const double* B2, int n1, int64_t ldb,
+                      double* partial, int m16, hipStream_t st) {
+  const dim3 grid((unsigned)p.groups, (unsigned)p.nch);
+  const double bytes = 8.0 * (double)rows * (m + n);
+  if (vec)
+    launch(STS_K_GRAM, bytes, gemm_tn_kernel<T, NW, true>, grid, dim3(64 * NW), 0, st, rows, m, n,
+           A, lda, B1, B2, n1, ldb, partial, m16, p.rpw);
+  else
+    launch(STS_K_GRAM, bytes, gemm_tn_kernel<T, NW, false>, grid, dim3(64 * NW), 0, st, rows, m,
+           n, A, lda, B1, B2, n1, ldb, partial, m16, p.rpw);
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
               const double* B1, const double* B2, int64_t ldb, double* C1, double* C2,
@@ -388,16 +492,21 @@ void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
   if (m <= 0 || n <= 0) return;
   STS_REQUIRE(n <= 16 && n1 >= 0 && n2 >= 0, STS_E_INVALID, "gemm_tn: n > 16");
   const int m16 = ((m + 15) / 16) * 16;
-  const int64_t nch = tn_chunks(rows);
+  const TnPlan p = tn_plan(rows, m);
   if (rows <= 0) {
     fill_kernel<<<1, 256, 0, st>>>(partial, (int64_t)m16 * 16, 0.0);
   } else {
-    dim3 grid(m16 / 16, (unsigned)nch);
-    launch(STS_K_GRAM, 8.0 * (double)rows * (m + n), gemm_tn_kernel, grid, dim3(256), 0, st, rows,
-           m, n, A, lda, B1, B2, n1, ldb, partial, m16);
+    const bool vec = aligned16(A) && aligned16(B1) && (n2 == 0 || aligned16(B2)) &&
+                     lda % 2 == 0 && ldb % 2 == 0;
+    if (p.T == 4)
+      launch_tn<4, 4>(vec, p, rows, m, n, A, lda, B1, B2, n1, ldb, partial, m16, st);
+    else if (p.T == 2)
+      launch_tn<2, 4>(vec, p, rows, m, n, A, lda, B1, B2, n1, ldb, partial, m16, st);
+    else
+      launch_tn<1, 16>(vec, p, rows, m, n, A, lda, B1, B2, n1, ldb, partial, m16, st);
   }
   STS_HIP(hipGetLastError());
-  gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : nch, m16, partial, C1,
+  gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : p.nch, m16, partial, C1,
                                                   C2, n1, ldc);
   STS_HIP(hipGetLastError());
 }

@@ -92,7 +92,10 @@ def test_cg_is_bitwise_deterministic():
 
 # ---------------------------------------------------------------- a4: Gram-Schmidt
 
-@pytest.mark.parametrize("rows,m,n", [(1000, 37, 5), (4099, 16, 16), (17, 3, 1), (70000, 130, 8)])
+# Covers one, two and four 16-column tiles per work-group, odd leading
+# dimensions (8-byte loads) and even ones (16-byte loads), ragged row chunks.
+@pytest.mark.parametrize("rows,m,n", [(1000, 37, 5), (4099, 16, 16), (17, 3, 1), (70000, 130, 8),
+                                      (100003, 240, 8), (100000, 68, 16), (261121, 4, 4)])
 def test_gram_and_update_match_numpy(rows, m, n):
     rng = np.random.default_rng(rows + m)
     A, B, Cm = rng.normal(size=(rows, m)), rng.normal(size=(rows, n)), rng.normal(size=(m, n))
