@@ -244,7 +244,10 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(int m, int n, int kk, d
 
 // ---------------------------------------------------------------------------
 // || [A_0 A_1 A_2] B ||_F^2 with B given transposed (BT: n x mtot).
-// Work-group tile: 64 rows x 256 columns; wave w owns columns [64 w, 64 w + 64).
+// Work-group tile: 64 rows x 256 columns; wave w owns columns [64 w, 64 w + 64)
+// as 4 x 4 independent 16 x 16 MFMA accumulators.  Each segment A_s is swept
+// on its own (its k-steps never straddle two segments) and the loads of the
+// next k-step are issued before the MFMAs of the current one.
 // ---------------------------------------------------------------------------
 struct ResArgs {
   int64_t rows;
@@ -253,7 +256,6 @@ struct ResArgs {
   const double* A[3];
   int64_t lda[3];
   int m[3];
-  int mtot;
   const double* BT;
   int64_t ldbt;
   double* partial;
@@ -261,41 +263,72 @@ struct ResArgs {
   double* out;
 };
 
-__device__ __forceinline__ double seg_load(const ResArgs& a, int64_t row, int k) {
-  int s = 0, base = 0;
-  while (s < a.nseg - 1 && k >= base + a.m[s]) {
-    base += a.m[s];
-    ++s;
-  }
-  return a.A[s][row + (int64_t)(k - base) * a.lda[s]];
-}
-
-__global__ __launch_bounds__(256) void residual_kernel(ResArgs a) {
+// VEC: row tiles 0 / 1 take the even / odd rows of r0 .. r0 + 31 and tiles
+// 2 / 3 those of r0 + 32 .. r0 + 63, so one 16-byte load feeds two tiles
+// (segments 16-byte aligned with even leading dimensions).  The sum of
+// squares does not depend on which rows a tile holds.
+// Two work-groups per CU (the register budget this allows keeps all sixteen
+// accumulators and the prefetched operands resident) measured 1.4x faster
+// than the compiler's default budget.
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void residual_kernel(ResArgs a) {
   __shared__ double red[4];
   __shared__ int last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   const int c0 = blockIdx.y * 256 + wv * 64;
+  const bool full = r0 + 64 <= a.rows;
   d4 acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < a.mtot; k0 += 4) {
-    const int k = k0 + g;
-    double av[4], bv[4];
+  int kb = 0;   // first row of BT of the segment
+  for (int s = 0; s < a.nseg; ++s) {
+    const double* A = a.A[s];
+    const int64_t lda = a.lda[s];
+    const int m = a.m[s];
+    auto load = [&](int k0, double* av, double* bv) {
+      const int kk = k0 + g;
+      const bool kok = kk < m;
+      const double* bt = a.BT + (int64_t)(kb + (kok ? kk : 0)) * a.ldbt;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int64_t row = r0 + 16 * x + i;
-      av[x] = (row < a.rows && k < a.mtot) ? seg_load(a, row, k) : 0.0;
-      const int col = c0 + 16 * x + i;
-      bv[x] = (col < a.n && k < a.mtot) ? a.BT[col + (int64_t)k * a.ldbt] : 0.0;
+      for (int y = 0; y < 4; ++y) {
+        const int col = c0 + 16 * y + i;
+        bv[y] = (kok && col < a.n) ? bt[col] : 0.0;
+      }
+      const double* ap = A + (int64_t)(kok ? kk : 0) * lda;
+      if (VEC && full) {
+        const double2 lo = kok ? *(const double2*)(ap + r0 + 2 * i) : double2{0.0, 0.0};
+        const double2 hi = kok ? *(const double2*)(ap + r0 + 32 + 2 * i) : double2{0.0, 0.0};
+        av[0] = lo.x;
+        av[1] = lo.y;
+        av[2] = hi.x;
+        av[3] = hi.y;
+      } else {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int64_t row = VEC ? r0 + 32 * (x >> 1) + 2 * i + (x & 1) : r0 + 16 * x + i;
+          av[x] = (kok && row < a.rows) ? ap[row] : 0.0;
+        }
+      }
+    };
+    double av[4], bv[4], an[4], bn[4];
+    load(0, av, bv);
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      if (k0 + 4 < m) load(k0 + 4, an, bn);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x], bv[y], acc[x][y]);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        av[x] = an[x];
+        bv[x] = bn[x];
+      }
     }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = mfma(av[x], bv[y], acc[x][y]);
+    kb += m;
   }
   double s = 0.0;
 #pragma unroll
@@ -563,12 +596,14 @@ void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double
   a.rows = rows;
   a.n = n;
   a.nseg = nseg;
-  a.mtot = 0;
+  int mtot = 0;
+  bool vec = true;
   for (int s = 0; s < nseg; ++s) {
     a.A[s] = segs[s].A;
     a.lda[s] = segs[s].lda;
     a.m[s] = segs[s].m;
-    a.mtot += segs[s].m;
+    mtot += segs[s].m;
+    vec = vec && aligned16(segs[s].A) && segs[s].lda % 2 == 0;
   }
   a.BT = BT;
   a.ldbt = ldbt;
@@ -576,8 +611,11 @@ void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double
   a.counter = counter;
   a.out = out;
   dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((n + 255) / 256));
-  launch(STS_K_RESIDUAL, 8.0 * ((double)rows * a.mtot + (double)n * a.mtot), residual_kernel, grid,
-         dim3(256), 0, st, a);
+  const double bytes = 8.0 * ((double)rows * mtot + (double)n * mtot);
+  if (vec)
+    launch(STS_K_RESIDUAL, bytes, residual_kernel<true>, grid, dim3(256), 0, st, a);
+  else
+    launch(STS_K_RESIDUAL, bytes, residual_kernel<false>, grid, dim3(256), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

@@ -209,6 +209,23 @@ def test_2d_solve_matches_crank_nicolson(n, nt, p, seed):
     prob.close()
 
 
+@pytest.mark.parametrize("n,nt,p,outer", [(65, 300, 3, 2), (31, 17, 1, 1), (100, 513, 2, 4)])
+def test_true_residual_matches_oracle(n, nt, p, outer):
+    """a8: the exact Sylvester residual of an unconverged iterate, large
+    enough that rounding in either computation is far below the tolerance.
+    Row counts not a multiple of 64 and Nt not a multiple of 256 give ragged
+    work-group tiles in both directions."""
+    w = wl.heat_2d_bumps(n=n, nt=nt, p=p, seed=40 + n)
+    prob, info, V, Y = _solve(w, tol=1e-14, max_outer=outer)
+    assert info["status"] == "STS_E_NOT_CONVERGED", info
+    K, M = fem.spatial_operators(2, n, w.mu)
+    Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+    r = exact.sylvester_residual(K, M, Dt, Mt, w.F1, w.F2, V @ Y)
+    assert r > 1e-9
+    assert abs(prob.true_residual() - r) <= 1e-9 * r, (prob.true_residual(), r)
+    prob.close()
+
+
 def test_1d_and_3d_solves():
     for w in (wl.heat_1d_sine(nx=255, nt=64, seed=8), wl.heat_3d_separable(n=15, nt=32, p=4, seed=3)):
         if w.dim == 1:      # a generic rank-one load, not an eigenvector
