@@ -373,51 +373,63 @@ __global__ __launch_bounds__(256, 2) void residual_kernel(ResArgs a) {
 // a directly computed norm, so this test is accurate to rounding), or if its
 // remainder after the earlier kept columns of the block falls below
 // defl_b^2 G[c][c] (a Gram-based test, resolvable only to about sqrt(eps)).
-__global__ void chol_deflate_kernel(int b, const double* G, int64_t ldg, const double* norm0,
-                                    double defl_v, double defl_b, double* Rinv, CholInfo* info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double L[16][16];
-  int idx[16];
-  int kept = 0;
-  double rmin = 1.0;
-  for (int c = 0; c < b; ++c) {
-    double v[16];
-    const double gcc = G[c + c * ldg];
-    if (!(gcc == gcc) || !(gcc > 0.0)) continue;
-    if (norm0 && !(gcc > defl_v * defl_v * norm0[c])) continue;
-    double d = gcc;
-    for (int j = 0; j < kept; ++j) {
-      double s = G[c + idx[j] * ldg];
-      for (int q = 0; q < j; ++q) s -= v[q] * L[j][q];
-      v[j] = s / L[j][j];
-      d -= v[j] * v[j];
+// The factorisation runs on one thread with every array in LDS (private
+// arrays indexed at run time would live in scratch memory); the columns of
+// R^{-1} are then solved in parallel, one thread per column.
+__global__ __launch_bounds__(64) void chol_deflate_kernel(int b, const double* G, int64_t ldg,
+                                                          const double* norm0, double defl_v,
+                                                          double defl_b, double* Rinv,
+                                                          CholInfo* info) {
+  __shared__ double Gs[16][17];
+  __shared__ double L[16][17];
+  __shared__ double X[16][17];
+  __shared__ double v[16];
+  __shared__ int kept_s;
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += blockDim.x) Gs[e % b][e / b] = G[e % b + (e / b) * ldg];
+  __syncthreads();
+  if (t == 0) {
+    int idx[16];
+    int kept = 0;
+    double rmin = 1.0;
+    for (int c = 0; c < b; ++c) {
+      const double gcc = Gs[c][c];
+      if (!(gcc == gcc) || !(gcc > 0.0)) continue;
+      if (norm0 && !(gcc > defl_v * defl_v * norm0[c])) continue;
+      double d = gcc;
+      for (int j = 0; j < kept; ++j) {
+        double sj = Gs[c][idx[j]];
+        for (int q = 0; q < j; ++q) sj -= v[q] * L[j][q];
+        v[j] = sj / L[j][j];
+        d -= v[j] * v[j];
+      }
+      if (!(d > defl_b * defl_b * gcc) || !(d == d)) continue;
+      rmin = fmin(rmin, sqrt(d / gcc));
+      for (int j = 0; j < kept; ++j) L[kept][j] = v[j];
+      L[kept][kept] = sqrt(d);
+      idx[kept] = c;
+      ++kept;
     }
-    if (!(d > defl_b * defl_b * gcc) || !(d == d)) continue;
-    rmin = fmin(rmin, sqrt(d / gcc));
-    for (int j = 0; j < kept; ++j) L[kept][j] = v[j];
-    L[kept][kept] = sqrt(d);
-    idx[kept] = c;
-    ++kept;
+    kept_s = kept;
+    info->kept = kept;
+    info->rmin = rmin;
+    for (int j = 0; j < 16; ++j) info->idx[j] = j < kept ? idx[j] : -1;
+    info->ok = 1;
   }
-  // R = L^T (upper); Rinv by back substitution, column by column.
-  for (int j = 0; j < b; ++j)
-    for (int i = 0; i < b; ++i) Rinv[i + j * b] = 0.0;
-  for (int j = 0; j < kept; ++j) {
-    // solve R x = e_j, R[i][q] = L[q][i]
-    double x[16];
+  __syncthreads();
+  const int kept = kept_s;
+  // R = L^T (upper); thread j solves R x = e_j and writes column j of R^{-1}
+  const int j = t;
+  if (j < kept) {
     for (int i = kept - 1; i >= 0; --i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int q = i + 1; q < kept; ++q) s -= L[q][i] * x[q];
-      x[i] = s / L[i][i];
+      double sx = (i == j) ? 1.0 : 0.0;
+      for (int q = i + 1; q < kept; ++q) sx -= L[q][i] * X[q][j];
+      X[i][j] = sx / L[i][i];
     }
-    for (int i = 0; i < kept; ++i) Rinv[i + j * b] = (i <= j) ? x[i] : 0.0;
   }
-  info->kept = kept;
-  info->rmin = rmin;
-  for (int j = 0; j < 16; ++j) info->idx[j] = j < kept ? idx[j] : -1;
-  info->ok = 1;
+  if (j < b)
+    for (int i = 0; i < b; ++i) Rinv[i + j * b] = (j < kept && i <= j) ? X[i][j] : 0.0;
 }
-
 __global__ void apply_rinv_kernel(int64_t rows, int b, const CholInfo* info, const double* Rinv,
                                   double* W, double* MW, int64_t ldw) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

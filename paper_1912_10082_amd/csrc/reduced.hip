@@ -41,38 +41,72 @@ struct SweepArgs {
   int64_t ldg;
 };
 
-constexpr int kSweepChunk = 256;
+// Row l of (Dt + lam Mt) z = g reads d_l z_l + c_l z_{l-1} = g_l, i.e. the
+// first-order linear recurrence z_l = a_l z_{l-1} + b_l with a_l = -c_l / d_l,
+// b_l = g_l / d_l (|a_l| < 1 for the Crank-Nicolson pencil, lam > 0).  A
+// work-group takes kSweepI eigencomponents and cuts the time axis into
+// kSweepC chunks, one thread per (component, chunk):
+//   1. each thread runs its chunk from z = 0, stores that particular solution
+//      and keeps the chunk's product of a_l;
+//   2. one thread per component carries the values entering each chunk
+//      across the kSweepC chunks;
+//   3. each thread adds (running product of a_l) x (value entering its chunk).
+// The dependent chain is nt / kSweepC + kSweepC steps instead of nt.
+constexpr int kSweepI = 16;
+constexpr int kSweepC = 16;
 
-__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
-  __shared__ double f2[4][kSweepChunk];
-  __shared__ double dd[kSweepChunk], de[kSweepChunk], dm[kSweepChunk], dn[kSweepChunk];
-  const int i = blockIdx.x * 64 + threadIdx.x;
+__global__ __launch_bounds__(kSweepI * kSweepC) void sweep_kernel(SweepArgs a) {
+  __shared__ double yend[kSweepC][kSweepI], prod[kSweepC][kSweepI], zin[kSweepC][kSweepI];
+  const int il = threadIdx.x % kSweepI, c = threadIdx.x / kSweepI;
+  const int i = blockIdx.x * kSweepI + il;
   const bool act = i < a.k;
   const double lam = act ? a.lam[i] : 0.0;
   double q[4] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < a.p; ++p) q[p] = act ? a.qb[i + p * a.ldqb] : 0.0;
-  double z = 0.0;
-  for (int l0 = 0; l0 < a.nt; l0 += kSweepChunk) {
-    const int len = min(kSweepChunk, a.nt - l0);
-    __syncthreads();
-    for (int u = threadIdx.x; u < len; u += 64) {
-      const int l = l0 + u;
-      for (int p = 0; p < a.p; ++p) f2[p][u] = a.F2[l + p * a.ldf];
-      dd[u] = a.t.d[l];
-      dm[u] = a.t.m[l];
-      de[u] = l > 0 ? a.t.e[l - 1] : 0.0;
-      dn[u] = l > 0 ? a.t.n[l - 1] : 0.0;
+  const int len = (a.nt + kSweepC - 1) / kSweepC;
+  const int l0 = c * len, l1 = min(a.nt, l0 + len);
+  double* Zi = a.Z + (act ? i : 0);
+  auto coef = [&](int l, double& al, double& bl) {
+    double g = 0.0;
+    if (a.G) g = a.G[i + (int64_t)l * a.ldg];
+    else
+      for (int p = 0; p < a.p; ++p) g += q[p] * a.F2[l + p * a.ldf];
+    const double d = a.t.d[l] + lam * a.t.m[l];
+    const double cl = l > 0 ? a.t.e[l - 1] + lam * a.t.n[l - 1] : 0.0;
+    al = -cl / d;
+    bl = g / d;
+  };
+  double y = 0.0, pr = 1.0;
+  if (act) {
+#pragma unroll 4
+    for (int l = l0; l < l1; ++l) {
+      double al, bl;
+      coef(l, al, bl);
+      y = al * y + bl;
+      pr *= al;
+      Zi[(int64_t)l * a.ldz] = y;
     }
-    __syncthreads();
-    if (act) {
-      for (int u = 0; u < len; ++u) {
-        double gl = 0.0;
-        if (a.G) gl = a.G[i + (int64_t)(l0 + u) * a.ldg];
-        else
-          for (int p = 0; p < a.p; ++p) gl += q[p] * f2[p][u];
-        z = (gl - (de[u] + lam * dn[u]) * z) / (dd[u] + lam * dm[u]);
-        a.Z[i + (int64_t)(l0 + u) * a.ldz] = z;
-      }
+  }
+  yend[c][il] = y;
+  prod[c][il] = pr;
+  __syncthreads();
+  if (c == 0) {
+    double z = 0.0;
+    for (int u = 0; u < kSweepC; ++u) {
+      zin[u][il] = z;
+      z = yend[u][il] + prod[u][il] * z;
+    }
+  }
+  __syncthreads();
+  const double z0 = zin[c][il];
+  if (act && z0 != 0.0) {
+    double cum = 1.0;
+#pragma unroll 4
+    for (int l = l0; l < l1; ++l) {
+      double al, bl;
+      coef(l, al, bl);
+      cum *= al;
+      Zi[(int64_t)l * a.ldz] += cum * z0;
     }
   }
 }
@@ -203,7 +237,8 @@ void time_sweep(int k, int nt, int p, const double* lam, const double* qb, int64
   if (k <= 0 || nt <= 0) return;
   STS_REQUIRE(p >= 1 && p <= 4, STS_E_INVALID, "time_sweep: 1 <= p <= 4");
   SweepArgs a{k, nt, p, lam, qb, ldqb, F2, ldf, t, Z, ldz, nullptr, 0};
-  launch(STS_K_SWEEP, 8.0 * (double)k * nt, sweep_kernel, dim3((k + 63) / 64), dim3(64), 0, st, a);
+  launch(STS_K_SWEEP, 8.0 * (double)k * nt, sweep_kernel, dim3((k + kSweepI - 1) / kSweepI),
+         dim3(kSweepI * kSweepC), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 
@@ -211,7 +246,8 @@ void time_sweep_full(int k, int nt, const double* lam, const double* G, int64_t 
                      const TimeOps& t, double* Z, int64_t ldz, hipStream_t st) {
   if (k <= 0 || nt <= 0) return;
   SweepArgs a{k, nt, 0, lam, nullptr, 0, nullptr, 0, t, Z, ldz, G, ldg};
-  launch(STS_K_SWEEP, 8.0 * (double)k * nt, sweep_kernel, dim3((k + 63) / 64), dim3(64), 0, st, a);
+  launch(STS_K_SWEEP, 8.0 * (double)k * nt, sweep_kernel, dim3((k + kSweepI - 1) / kSweepI),
+         dim3(kSweepI * kSweepC), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

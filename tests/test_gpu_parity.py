@@ -152,7 +152,10 @@ def test_sym_eig_repeated_and_clustered():
 
 # ---------------------------------------------------------------- a7: time sweep
 
-@pytest.mark.parametrize("k,nt,p", [(1, 2, 1), (40, 64, 3), (130, 300, 4)])
+# nt below, at and far above the number of time chunks per component (16);
+# component counts that leave a work-group partly idle
+@pytest.mark.parametrize("k,nt,p", [(1, 2, 1), (40, 64, 3), (130, 300, 4), (17, 5, 2),
+                                    (33, 1024, 2)])
 def test_time_sweep_matches_block_substitution(k, nt, p):
     Km, _, beta, F2 = wl.random_reduced_problem(k, nt, p, seed=k + nt)
     t = np.cumsum(np.r_[0.0, np.random.default_rng(k).uniform(0.5, 1.5, nt)]) / nt
