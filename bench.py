@@ -14,8 +14,9 @@ step re-solves from scratch on the same problem object.
 Prints one JSON line.  ``value`` is space-time degrees of freedom (Nh * Nt)
 per second of wall time.  ``roofline`` reports the kernel with the largest
 measured time against its bound (8 TB/s HBM, or 78.6 TFLOP/s FP64 matrix
-cores for the residual contraction), from HIP events attached to every launch
-inside the timed steps; ``kernels`` lists all timed kernels.  ``cpu_baseline`` times the CPU oracle's
+cores for the exact-residual contraction and the coarse-grid sine-transform
+GEMMs), from HIP events attached to every launch of extra solves of the same
+workload; ``kernels`` lists all timed kernels.  ``cpu_baseline`` times the CPU oracle's
 Crank-Nicolson stepper on the first time steps of the same problem; those
 columns also gate the result (relative error <= 1e-8).
 """
@@ -51,9 +52,25 @@ def _sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel, alg_bytes_per_launch):
-    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs,
-    if they were taken on the current kernel sources; else None."""
+# profiler kernel ids of the library -> HIP kernel names in rocprofv3 output
+HIP_KERNELS = {
+    "mg_coarse": ["dst_gemm_kernel", "mg_coarse_kernel"],
+    "gram": ["gemm_tn_kernel"],
+    "residual": ["residual_kernel"],
+    "basis_update": ["gemm_nn_sub_kernel"],
+    "mg_up": ["mg_up_kernel"],
+    "mg_down": ["mg_down_kernel"],
+    "mass_cheb": ["mass_cheb_kernel"],
+    "pcg_a": ["pcg_a_kernel"],
+    "pcg_b": ["pcg_b_kernel"],
+    "stencil": ["apply_kernel"],
+}
+
+
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel factor), if
+    they were taken on the current kernel sources; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
@@ -61,7 +78,86 @@ def _traffic(kernel, alg_bytes_per_launch):
         return None
     if d.get("sources_sha256_16") != _sources_hash():
         return None
-    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    ks = d.get("kernels", {})
+    for name in HIP_KERNELS.get(kernel, [kernel]):
+        if name in ks:
+            return ks[name].get("hbm_bytes_per_launch")
+    return None
+
+
+def _coarse_order(n):
+    """Order of the exactly solved coarsest multigrid level of an n x n grid:
+    halve (n -> (n - 1) / 2) while n > 255, and at least once if n > 63."""
+    first = True
+    while n > 255 or (first and n > 63):
+        n = (n - 1) // 2
+        first = False
+    return n
+
+
+def calibrate_copy(mib):
+    """A plain device-to-device copy of `mib` MiB, 10 times (one dispatch
+    each): the reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read_per_dispatch": n * 8,
+                      "bytes_written_per_dispatch": n * 8}), flush=True)
+    return 0
+
+
+def _pmc_per_kernel(path, counter):
+    """Mean value of `counter` per dispatch, by kernel name, from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    import re
+
+    acc = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") != counter:
+                continue
+            full = re.sub(r"\(anonymous namespace\)::", "", r["Kernel_Name"])
+            name = full.split("(")[0].split("<")[0].split("::")[-1].replace("void ", "").strip()
+            a = acc.setdefault(name, [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+    return {k: v[0] / v[1] for k, v in acc.items()}
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, out):
+    """Write the per-kernel HBM traffic file from two counter runs of the
+    benchmark (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) and the same two runs
+    of calibrate_copy."""
+    fetch = _pmc_per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _pmc_per_kernel(write_csv, "WRITE_SIZE")
+    cf = _pmc_per_kernel(copy_fetch_csv, "FETCH_SIZE")
+    cw = _pmc_per_kernel(copy_write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    # the copy kernel is the one dispatch whose counters are near its size
+    f_copy = max(cf.values()) / copy_kib
+    w_copy = max(cw.values()) / copy_kib
+    kernels = {}
+    for k in sorted(set(fetch) | set(write)):
+        fb = 1024.0 * fetch.get(k, 0.0) / f_copy
+        wb = 1024.0 * write.get(k, 0.0) / w_copy
+        kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                      "hbm_bytes_per_launch": fb + wb}
+    d = {"sources_sha256_16": _sources_hash(),
+         "copy_calibration": {"copy_mib": copy_mib, "fetch_factor": f_copy,
+                              "write_factor": w_copy},
+         "kernels": kernels}
+    with open(out, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    print(f"wrote {out}: fetch factor {f_copy:.4f}, write factor {w_copy:.4f}, "
+          f"{len(kernels)} kernels", flush=True)
+    return 0
 
 
 def cpu_baseline(w, U_gpu_cols, sample_steps):
@@ -95,7 +191,17 @@ def main() -> int:
                     help="skip the profiled solves (no roofline / kernels table)")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="extra solves with per-dispatch events for the kernel table")
+    ap.add_argument("--calibrate-copy", type=int, metavar="MIB", default=0,
+                    help="only run a plain MIB-MiB device copy (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=5,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "MIB"),
+                    help="only write the HBM traffic file from rocprofv3 counter runs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        f, wr, cf, cw, mib = args.summarize_pmc
+        return summarize_pmc(f, wr, cf, cw, int(mib), TRAFFIC_FILE)
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the solver has no multi-GPU path", file=sys.stderr)
@@ -165,19 +271,28 @@ def main() -> int:
                   "kernel_time_share": sec / ktot,
                   "measured": f"HIP events on every dispatch of {prof_steps} more solves "
                               "of the same workload after the timed steps"}
+        flops = None
         if name == "residual":
             # ||[F1, Kx V, Mx V] B||: 2 Nh (p + 2k) Nt flops per launch on the FP64 matrix cores
-            flops = 2.0 * w.nh * (2 + 2 * last["k"]) * w.nt
-            achieved = flops / (sec / max(n, 1)) / 1e12
+            flops = 2.0 * w.nh * (2 + 2 * last["k"]) * w.nt * n
+        elif name == "mg_coarse":
+            # exact coarse solve as m x m GEMMs on the matrix cores (operands
+            # L2-resident, 2 m^3 flops per 24 m^2 algorithmic bytes per column)
+            m = _coarse_order(w.n[0])
+            flops = by * m / 12.0
+        if flops is not None:
+            achieved = flops / sec / 1e12
             roofline = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 2),
                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None, **common}
+                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                        "traffic": _traffic(name),
+                        "alg_flops_per_launch": flops / max(n, 1), **common}
         else:
             achieved = by / sec / 1e9
             roofline = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": _traffic(name, by / max(n, 1)),
+                        "traffic": _traffic(name),
                         "alg_bytes_per_launch": by / max(n, 1), **common}
     gate = last["status"] == "STS_OK" and last["res_true"] <= args.tol
     V, Y = prob.factors(device=True)
