@@ -157,4 +157,91 @@ def extended_krylov_galerkin(Kx, Mx, Dt, Mt, F1, F2, tol: float = 1e-10,
         block = list(range(V.shape[1], V.shape[1] + Wn.shape[1]))
         block_tags = [new_tags[c] for c in kept]
         V = np.column_stack([V, Wn])
-    return ProjectionResult(V, Y, max_outer, history, breakdown)
+    # not converged: the factors of the last reduced solve
+    return ProjectionResult(V[:, :Y.shape[0]], Y, max_outer, history, breakdown)
+
+
+# ---------------------------------------------------------------------------
+# Rational Krylov space with adaptive shifts (Sec. 4, rational Krylov paragraph)
+# ---------------------------------------------------------------------------
+#
+# Sec. 4 proposes RK_m = range([F1, (A_h - s_2 M_h)^{-1} M_h F1, ...]) with
+# shifts chosen adaptively while the space grows, citing the survey of
+# Simoncini for the rule.  In operator form this is the rational Krylov space
+# of A = Mx^{-1} Kx with poles -s_j (s_j = -sigma_j > 0 for the SPD pencil),
+# so each shifted direction solves (Kx + s Mx) w = Mx v.  Read with the same
+# start block as the extended Krylov space ([Mx^{-1} F1, Kx^{-1} F1]: poles
+# infinity and 0) and grown block by block (each new block is the shifted
+# solve applied to the last one; for distinct shifts this spans the same
+# space as the printed partial-fraction form).  The adaptive rule is the
+# greedy one of Druskin and Simoncini (2011) for real spectra: with Ritz
+# values theta_i of the current projected pencil, earlier shifts s_l and the
+# spectral interval [a, b] of A,
+#     s_next = argmax_{s in [a, b]}  prod_l |s - s_l| / prod_i |s + theta_i|,
+# i.e. the point of the mirrored spectrum where the current rational function
+# is largest in modulus.  The interval is the range of the Ritz values seen
+# so far (widened as they move), the maximum is taken over a fine logarithmic
+# grid of the interval.
+
+def adaptive_shift(ritz, shifts, a: float, b: float, grid: int = 4001) -> float:
+    """Next shift by the greedy rule above (log-spaced grid of [a, b], a > 0).
+
+    The objective is evaluated in logarithms; its maximiser over the grid is
+    returned (the first one if several tie)."""
+    ritz = np.asarray(ritz, dtype=float)
+    shifts = np.asarray(shifts, dtype=float)
+    s = np.exp(np.linspace(np.log(a), np.log(b), grid))
+    logf = np.zeros_like(s)
+    for sl in shifts:
+        logf += np.log(np.abs(s - sl) + 1e-300)
+    for th in ritz:
+        logf -= np.log(np.abs(s + th))
+    return float(s[int(np.argmax(logf))])
+
+
+def rational_krylov_galerkin(Kx, Mx, Dt, Mt, F1, F2, tol: float = 1e-10, max_outer: int = 200,
+                             defl: float = 1e-10, shifts=None) -> ProjectionResult:
+    """Grow the rational Krylov space until the Galerkin residual is <= tol.
+
+    ``shifts``: an explicit list of shifts s_2, s_3, ... (used in order), or
+    None for the adaptive rule.  Inner solves are sparse-direct.  The result's
+    history holds (k, residual, shift) per step."""
+    F1 = np.asarray(F1, dtype=float)
+    F2 = np.asarray(F2, dtype=float)
+    luK = spla.splu(Kx.tocsc())
+    luM = spla.splu(Mx.tocsc())
+    X = np.column_stack([luM.solve(F1), luK.solve(F1)])
+    V, kept = m_orthonormalize(X, np.zeros((Kx.shape[0], 0)), Mx, defl)
+    block = list(range(V.shape[1]))
+    used, history = [], []
+    lo, hi = np.inf, 0.0
+    Y = None
+    breakdown = False
+    for outer in range(1, max_outer + 1):
+        Km = V.T @ (Kx @ V)
+        Mm = V.T @ (Mx @ V)
+        beta = V.T @ F1
+        Y = galerkin_reduced_solve(Km, Mm, Dt, Mt, beta, F2)
+        res = galerkin_residual(Kx, Mx, Dt, Mt, F1, F2, V, Y)
+        history.append((V.shape[1], res, used[-1] if used else None))
+        if res <= tol or breakdown:
+            return ProjectionResult(V, Y, outer, history, breakdown)
+        theta = sla.eigh(Km, Mm, eigvals_only=True)
+        lo, hi = min(lo, theta.min()), max(hi, theta.max())
+        if shifts is not None:
+            if len(used) >= len(shifts):
+                break
+            s = float(shifts[len(used)])
+        else:
+            s = adaptive_shift(theta, used, lo, hi)
+        used.append(s)
+        lu = spla.splu((Kx + s * Mx).tocsc())
+        W = np.column_stack([lu.solve(Mx @ V[:, c]) for c in block])
+        Wn, kept = m_orthonormalize(W, V, Mx, defl)
+        if Wn.shape[1] == 0:
+            breakdown = True
+            continue
+        block = list(range(V.shape[1], V.shape[1] + Wn.shape[1]))
+        V = np.column_stack([V, Wn])
+    # not converged: the factors of the last reduced solve
+    return ProjectionResult(V[:, :Y.shape[0]], Y, len(history), history, breakdown)
