@@ -176,6 +176,223 @@ def cpu_baseline(w, U_gpu_cols, sample_steps):
     return secs, err
 
 
+def bench_batch(args) -> int:
+    """256 independent 2-D problems of uneven size (grid side 63 / 127 / 255,
+    Nt 128..1024, rank 1..3, mu log-uniform in [0.1, 10]) solved to a relative
+    residual of 1e-9 through the batch executor, with the worker count picked
+    by the autotuner; the same batch with one worker is the sequential
+    reference.  One step = one pass over the whole batch."""
+    import numpy as np
+    import torch
+
+    import paper_1912_10082_amd as sts
+    import workloads as wl
+    from oracle import exact, fem
+    from paper_1912_10082_amd import autotune
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    batch = wl.batch_2d_uneven(count=args.batch_count)
+    probs = []
+    for w in batch:
+        dd, ds, md, ms = sts.time_matrices(wl.time_grid(w.nt, w.T))
+        probs.append(sts.Problem(2, w.n[0], w.mu, (dd, ds), (md, ms),
+                                 torch.from_numpy(np.asarray(w.F1)).cuda(),
+                                 torch.from_numpy(np.asarray(w.F2)).cuda()))
+    torch.cuda.synchronize()
+    opts = dict(tol=1e-9, max_outer=80, restart=1)
+    t0 = time.perf_counter()
+    best, timings = autotune.tune_workers(probs, probe=32, **opts)
+    _log(f"autotune {time.perf_counter() - t0:.1f}s: {timings} -> {best} workers")
+    dof = sum(w.nh * w.nt for w in batch)
+    res = {}
+    for workers in (best, 1):
+        with sts.Pool(workers) as pool:
+            for i in range(args.warmup):
+                pool.solve(probs, **opts)
+            lat = []
+            for i in range(args.steps):
+                t0 = time.perf_counter()
+                infos = pool.solve(probs, **opts)
+                lat.append(time.perf_counter() - t0)
+            _log(f"{workers} workers: {[round(x, 3) for x in lat]} s per batch")
+        res[workers] = (sum(lat) / len(lat), infos)
+        if workers == best == 1:
+            break
+    t_best, infos = res[best]
+    ok = all(d["status"] == "STS_OK" for d in infos)
+    # oracle check on the smaller problems (Crank-Nicolson, CPU)
+    errs = []
+    for w, pr in zip(batch, probs):
+        if w.n[0] == 63 and w.nt <= 256 and len(errs) < 8:
+            V, Y = pr.factors()
+            K, M = fem.spatial_operators(2, w.n[0], w.mu)
+            Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+            U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
+            errs.append(float(np.linalg.norm(V @ Y - U) / np.linalg.norm(U)))
+    gate = ok and bool(errs) and max(errs) <= 1e-8
+    t_one = res[1][0]
+    out = {
+        "metric": "batched space-time dof/s (256 independent uneven 2-D problems)",
+        "value": dof / t_best, "unit": "dof/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_best, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch2d_uneven_{len(batch)}", "count": len(batch),
+                   "sides": [63, 127, 255], "nt": [128, 256, 512, 1024], "p": [1, 2, 3],
+                   "tol": opts["tol"], "workers": best},
+        "solves_per_s": len(batch) / t_best,
+        "one_worker": {"ms_per_step": 1e3 * t_one, "value": dof / t_one},
+        "speedup_vs_one_worker": t_one / t_best,
+        "autotune_probe_seconds": timings,
+        "gate_passed": gate, "max_rel_error_sampled": max(errs) if errs else None,
+        "errors_sampled": len(errs),
+        "outer_its_total": sum(d["outer_its"] for d in infos),
+    }
+    print(json.dumps(out), flush=True)
+    for pr in probs:
+        pr.close()
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Poisson arrivals (rate --serve-rate, seed 5) over --serve-seconds of
+    requests drawn by workloads.serving_mix (45% 1-D, 45% 2-D, 10% 3-D; Nt
+    log-uniform in [128, 2048]; P in 1..4; mu log-uniform in [0.1, 10]),
+    served by --serve-workers workers under a 64 GiB footprint budget.
+    Reports completed solves/s, p50/p99 latency (submission to factors ready)
+    and queueing delay; re-solves every 20th request alone to check that its
+    factors are bitwise those it got in the mix, and checks the sampled
+    requests of modest size against the oracle's Crank-Nicolson solution."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1912_10082_amd as sts
+    import workloads as wl
+    from oracle import exact, fem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0 / args.serve_rate, size=int(args.serve_rate * args.serve_seconds * 2) + 10)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < args.serve_seconds]
+    shapes = wl.serving_mix(len(arrivals), seed=5)
+    _log(f"serve: {len(arrivals)} requests over {args.serve_seconds:.0f} s; generating inputs")
+    reqs = []
+    for sh in shapes:
+        w = wl.make_request_workload(*sh)
+        dd, ds, md, ms = sts.time_matrices(wl.time_grid(w.nt, w.T))
+        reqs.append((w, (dd, ds), (md, ms)))
+    opts = dict(tol=1e-9, max_outer=100)
+    budget = 200 << 30
+    sample = set(range(0, len(reqs), 20))
+    results = [None] * len(reqs)
+    kept = {}
+    with sts.Server(workers=args.serve_workers, mem_budget=budget) as server:
+        # warm-up: one request of each dimension (first-use allocations, code loading)
+        for d in (1, 2, 3):
+            j = next(i for i, sh in enumerate(shapes) if sh[0] == d)
+            w, dt, mt = reqs[j]
+            t = server.submit(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2, **opts)
+            server.wait(t)
+            server.release(t)
+        tickets = [None] * len(reqs)
+        done_submit = threading.Event()
+
+        def submitter():
+            t0 = time.perf_counter()
+            for i, (w, dt, mt) in enumerate(reqs):
+                delay = arrivals[i] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = server.submit(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2, **opts)
+            done_submit.set()
+
+        t_start = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        last_log = t_start
+        # collect in completion order (a finished request's memory is
+        # released at once, whatever is still running before it)
+        pending, nxt, ndone = [], 0, 0
+        while ndone < len(reqs):
+            while nxt < len(reqs) and tickets[nxt] is not None:
+                pending.append(nxt)
+                nxt += 1
+            still = []
+            for i in pending:
+                try:
+                    res, prob = server.wait(tickets[i], timeout=0.0)
+                except sts.STSError:
+                    still.append(i)
+                    continue
+                results[i] = res
+                if i in sample and prob is not None:
+                    kept[i] = prob.factors()
+                server.release(tickets[i])
+                ndone += 1
+            pending = still
+            time.sleep(0.001)
+            if time.perf_counter() - last_log > 10:
+                last_log = time.perf_counter()
+                _log(f"serve: {ndone}/{len(reqs)} done, {server.stats()}")
+        th.join()
+        t_end = time.perf_counter()
+        stats = server.stats()
+    wall = t_end - t_start
+    ok = [r["status"] == "STS_OK" for r in results]
+    lat = sorted(r["latency_seconds"] for r in results)
+    qd = sorted(r["queued_seconds"] for r in results)
+    pct = lambda a, q: a[min(len(a) - 1, int(q * len(a)))]
+    # alone-vs-mixed and oracle checks on the sample
+    equal, errs = 0, []
+    for i, (V, Y) in kept.items():
+        w, dt, mt = reqs[i]
+        with sts.Problem(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2) as pr:
+            pr.solve(**opts)
+            Va, Ya = pr.factors()
+        equal += int(np.array_equal(V, Va) and np.array_equal(Y, Ya))
+        if w.nh * w.nt <= 4e6:
+            K, M = fem.spatial_operators(w.dim, w.n[0], w.mu)
+            Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+            U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
+            errs.append(float(np.linalg.norm(V @ Y - U) / np.linalg.norm(U)))
+    by_dim = {}
+    for (w, _, _), r in zip(reqs, results):
+        by_dim.setdefault(w.dim, []).append(r["latency_seconds"])
+    dof = sum(w.nh * w.nt for (w, _, _), k in zip(reqs, ok) if k)
+    failed = {}
+    for (w, _, _), r in zip(reqs, results):
+        if r["status"] != "STS_OK":
+            key = f"{w.dim}d:{r['status']}"
+            failed.setdefault(key, []).append(f"n{w.n[0]}_nt{w.nt}_p{w.p}_res{r['res_true']:.1e}")
+    gate = all(ok) and equal == len(kept) and (not errs or max(errs) <= 1e-8)
+    out = {
+        "metric": "served solves/s and p50/p99 latency (Poisson arrivals, mixed 1-D/2-D/3-D)",
+        "value": sum(ok) / wall, "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 3, "ms_per_step": 1e3 * wall / max(len(reqs), 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serve_mix_45_45_10", "rate_per_s": args.serve_rate,
+                   "window_s": args.serve_seconds, "workers": args.serve_workers,
+                   "mem_budget_bytes": budget, "tol": opts["tol"]},
+        "latency_ms": {"p50": 1e3 * pct(lat, 0.5), "p99": 1e3 * pct(lat, 0.99)},
+        "queued_ms": {"p50": 1e3 * pct(qd, 0.5), "p99": 1e3 * pct(qd, 0.99)},
+        "latency_p50_ms_by_dim": {str(d): 1e3 * sorted(v)[len(v) // 2] for d, v in by_dim.items()},
+        "requests": len(reqs), "completed_ok": sum(ok), "wall_s": wall,
+        "space_time_dof_per_s": dof / wall,
+        "mem_peak_bytes": stats["mem_peak"],
+        "alone_vs_mixed_bitwise_equal": f"{equal}/{len(kept)}",
+        "failed": {k: v[:6] for k, v in failed.items()},
+        "failed_count": {k: len(v) for k, v in failed.items()},
+        "oracle_checked": len(errs), "max_rel_error_sampled": max(errs) if errs else None,
+        "gate_passed": gate,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +408,14 @@ def main() -> int:
                     help="skip the profiled solves (no roofline / kernels table)")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="extra solves with per-dispatch events for the kernel table")
+    ap.add_argument("--workload", choices=("heat2d", "batch2d", "serve"), default="heat2d",
+                    help="heat2d: the 511^2 x 1024 solve (default); batch2d: 256 uneven "
+                         "2-D problems through the batch executor; serve: Poisson arrivals "
+                         "of mixed 1-D / 2-D / 3-D requests through the request server")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window")
+    ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, metavar="MIB", default=0,
                     help="only run a plain MIB-MiB device copy (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=5,
@@ -202,6 +427,10 @@ def main() -> int:
         return summarize_pmc(f, wr, cf, cw, int(mib), TRAFFIC_FILE)
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
+    if args.gpus == 1 and args.workload == "batch2d":
+        return bench_batch(args)
+    if args.gpus == 1 and args.workload == "serve":
+        return bench_serve(args)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the solver has no multi-GPU path", file=sys.stderr)

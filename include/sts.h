@@ -107,18 +107,24 @@ typedef struct {
   int32_t restart;          /* 1 = discard the current basis and solve from scratch; default 0 */
   int32_t profile;          /* 1 = time the main kernels with HIP events (sts_kernel_profile);
                                default 0 */
-  int32_t inner_precond;    /* 1 = fast inner solvers where the space allows them (2-D P1,
-                               n halving to <= 63): Kx by CG preconditioned with one
-                               geometric multigrid V-cycle, Mx by Chebyshev iteration;
-                               0 = plain CG for both; default 1 */
-  int32_t pad_;
+  int32_t inner_precond;    /* 1 = fast inner solvers where the space allows them: 1-D P1,
+                               Kx and Mx by a direct tridiagonal solve; 2-D P1 with n <= 63
+                               or n odd halving, n -> (n-1)/2, down to <= 255: Kx by CG
+                               preconditioned with one geometric multigrid V-cycle, Mx by
+                               Chebyshev iteration; 0 = plain CG for both; default 1 */
+  int32_t rational;         /* projection space: 0 = extended Krylov (poles 0 and infinity);
+                               1 = rational Krylov with adaptive shifts (Sec. 4): after the
+                               extended start block, each step applies (Kx + s Mx)^{-1} Mx to
+                               the last block, s chosen by the greedy rule of
+                               sts_adaptive_shift from the Ritz values; convergence is
+                               checked on the exact residual; default 0 */
 } sts_opts;
 
 typedef struct {
   int32_t outer_its;        /* blocks added after the start block */
   int32_t checks;           /* reduced solves performed */
   int64_t k;                /* basis size of the returned factors (mu_mem of Sec. 5, Table 1) */
-  int64_t rank;             /* numerical rank of V Y (singular values > 1e-12 sigma_1) */
+  int64_t rank;             /* numerical rank of V Y (singular values > 1e-8 sigma_1) */
   int64_t inner_its_K;      /* CG iterations on Kx, summed over columns and solves */
   int64_t inner_its_M;      /* CG iterations on Mx, summed over columns and solves */
   double res_cheap;         /* last projected residual estimate (relative Frobenius) */
@@ -127,7 +133,7 @@ typedef struct {
   double seconds;           /* wall time of sts_solve */
   double alg_bytes;         /* algorithmic HBM bytes moved by the kernels (model) */
   int32_t breakdown;        /* 1 = the space became invariant (exact solution) */
-  int32_t pad_;
+  int32_t shifts;           /* shifted solves of a rational Krylov space (0 otherwise) */
   int64_t cg_poll_restarts; /* times a polled CG state was stale and iterations resumed */
 } sts_info;
 
@@ -149,7 +155,8 @@ typedef enum {
   STS_K_BACKTRANSFORM = 13, /* reduced eigensolve: back-transformation */
   STS_K_SWEEP = 14,         /* time sweep */
   STS_K_STENCIL = 15,       /* stencil SpMM Kx V, Mx V */
-  STS_K_COUNT = 16
+  STS_K_TRIDIAG_SOLVE = 16, /* direct tridiagonal inner solve (1-D) */
+  STS_K_COUNT = 17
 } sts_kernel;
 
 typedef struct sts_problem sts_problem;
@@ -242,9 +249,9 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops, const double* B, i
  * with one geometric multigrid V-cycle (the inner Kx^{-1} applications of
  * the extended Krylov space, Sec. 4; the preconditioner is this library's
  * choice, not the paper's).  X0 = 0; stops when ||r|| <= rtol ||b|| or after
- * maxit iterations.  Only for STS_FE_P1_2D spaces whose n halves, n ->
- * (n-1)/2, down to at most 63 (e.g. 511, 255, 127, or any n <= 63); else
- * STS_E_INVALID.  B: Nh x ncols (ldb), X: Nh x ncols (ldx), device.  iters
+ * maxit iterations.  Only for STS_FE_P1_2D spaces with n <= 63, or n odd
+ * halving, n -> (n-1)/2 (odd at every step), at least once and down to at
+ * most 255 (e.g. 1023, 511, 255, 127, 95); else STS_E_INVALID.  B: Nh x ncols (ldb), X: Nh x ncols (ldx), device.  iters
  * (host, may be NULL) as for sts_cg.  ncols <= 8.  Same errors as sts_cg. */
 sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, double* X,
                       int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
@@ -262,13 +269,41 @@ sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, 
                           void* stream);
 
 /* The preconditioner of sts_pcg_mg: Z[:, c] = Bmg R[:, c], one V-cycle from
- * zero (two damped-Jacobi sweeps, weight 0.8, before and after each coarse
- * correction; P1 interpolation and its transpose between the nested meshes;
- * the single-node level solved exactly).  Bmg is symmetric positive definite.
+ * zero (three Chebyshev smoothing steps for the interval [1/2, 2] of the
+ * spectrum of diag(Kx)^{-1} Kx before and after each coarse correction; P1
+ * interpolation and its transpose between the nested meshes; the coarsest
+ * level solved exactly by the discrete sine transform).  Bmg is symmetric
+ * positive definite.
  * Same spaces as sts_pcg_mg.  R: Nh x ncols (ldr), Z: Nh x ncols (ldz),
  * device, ncols <= 8. */
 sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,
                          int64_t ldz, int32_t ncols, void* stream);
+
+/* Direct solves A X[:, c] = B[:, c], A = Kx or Mx per column (ops[c]), for a
+ * 1-D P1 space (STS_FE_P1_1D; else STS_E_INVALID): both matrices of Sec. 3
+ * are constant-coefficient symmetric tridiagonal, solved by elimination
+ * without pivoting (the inner solves of the extended Krylov space, Sec. 4).
+ * B, X: Nh x ncols (ldb, ldx), device, must not overlap; ncols <= 8. */
+sts_status sts_tridiag_solve(const sts_space* space, const int32_t* ops, const double* B,
+                             int64_t ldb, double* X, int64_t ldx, int32_t ncols, void* stream);
+
+/* The adaptive shift rule of the rational Krylov space (Sec. 4 leaves the
+ * rule to the literature it cites; this is the greedy choice of Druskin and
+ * Simoncini for real spectra): the maximiser, over `grid` logarithmically
+ * spaced points of [a, b] (end points included), of
+ *     prod_l |s - shifts[l]| / prod_i |s + ritz[i]|,
+ * evaluated in logarithms.  Host arrays; *s receives the shift.  Errors:
+ * STS_E_INVALID unless 0 < a <= b and grid >= 2. */
+sts_status sts_adaptive_shift(const double* ritz, int32_t k, const double* shifts, int32_t m,
+                              double a, double b, int32_t grid, double* s);
+
+/* (Kx + shift Mx) X[:, c] = B[:, c] (shift >= 0) as the rational Krylov steps
+ * solve them: 1-D P1 spaces directly (elimination), other spaces by CG to
+ * relative residual rtol (at most maxit iterations; iters as for sts_cg).
+ * B, X: Nh x ncols (ldb, ldx), device; ncols <= 8. */
+sts_status sts_shifted_solve(const sts_space* space, double shift, const double* B, int64_t ldb,
+                             double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                             int32_t* iters, void* stream);
 
 /* Block Gram-Schmidt in the Mx inner product: orthogonalise the ncols columns
  * of W (in place, Nh x ncols, ldw) against V (Nh x k, Mx-orthonormal, with
@@ -294,7 +329,8 @@ sts_status sts_basis_update(int64_t rows, int32_t m, int32_t n, const double* A,
                             const double* C, int64_t ldc, double* W, int64_t ldw, void* stream);
 
 /* Eigendecomposition of a symmetric k x k matrix A (lda): A Q = Q diag(lam),
- * Q^T Q = I, by Householder tridiagonalisation and implicit QL.  lam: k,
+ * Q^T Q = I, by Householder tridiagonalisation, bisection, inverse iteration
+ * and Newton-Schulz orthogonalisation.  lam: k,
  * Q: k x k (ldq).  For the reduced pencil (Km, Mm) of an Mx-orthonormal basis
  * Mm = I up to rounding, so this diagonalises the pencil (Sec. 4, reduced
  * equation). */
@@ -309,6 +345,125 @@ sts_status sts_time_sweep(int64_t k, int64_t nt, int32_t p, const double* lam, c
                           int64_t ldq, const double* beta, int64_t ldb, const double* F2,
                           int64_t ldf, const sts_bidiag* Dt, const sts_bidiag* Mt, double* Y,
                           int64_t ldy, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Many independent problems on one GPU.
+ *
+ * Each problem of a batch is the method of Sec. 4 applied to its own data;
+ * the pool only schedules whole solves.  A pool owns `workers` host threads'
+ * worth of HIP streams (non-blocking, default priority) on the device that
+ * is current at creation.  sts_pool_solve runs sts_solve on every problem,
+ * up to `workers` at a time, taking the problems in order of decreasing
+ * estimated cost (grid size, columns, time steps).  While a problem is being
+ * solved it is bound to its worker's stream; before and after, the work on
+ * its own stream is waited for, so the caller may queue work on that stream
+ * before the call and use the factors after it.  Factors are bitwise those of
+ * solving each problem alone.
+ * ------------------------------------------------------------------------ */
+typedef struct sts_pool sts_pool;
+
+/* workers: 1..64.  Errors: STS_E_INVALID, STS_E_DEVICE (stream creation). */
+sts_status sts_pool_create(int32_t workers, sts_pool** out);
+
+/* Number of workers of the pool. */
+sts_status sts_pool_workers(const sts_pool* pool, int32_t* workers);
+
+/* Solve probs[0..n).  opts: nopts = 0 (defaults for all), 1 (opts[0] for all)
+ * or n (opts[i] for problem i).  infos (n entries) and status (n entries)
+ * may be NULL.  A problem may appear only once; problems must not be used by
+ * other threads during the call.  Returns STS_OK if every solve returned
+ * STS_OK, else the status of the lowest-index failing problem (the others
+ * still run to completion; status[] holds each one's result, and
+ * sts_last_error names the failing problem).  Synchronous. */
+sts_status sts_pool_solve(sts_pool* pool, int32_t n, sts_problem* const* probs,
+                          const sts_opts* opts, int32_t nopts, sts_info* infos,
+                          sts_status* status);
+
+/* Destroy the pool (NULL-safe).  Must not overlap an sts_pool_solve. */
+void sts_pool_destroy(sts_pool* pool);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request queue in front of the solver.
+ *
+ * A request is one problem of Sec. 2-4 (space, time matrices, low-rank load,
+ * options).  sts_server_submit copies its host inputs and returns a ticket at
+ * once.  `workers` worker threads, each with its own non-blocking HIP stream
+ * on the device current at creation, take requests first come, first served.
+ * A request is admitted only when its device-memory footprint (sts_footprint)
+ * fits in mem_budget next to the requests admitted and not yet released; a
+ * request that could never fit is refused at submission (STS_E_NOMEM).  A
+ * finished request keeps its problem (basis and factors) in device memory
+ * until sts_server_release.  Factors are bitwise those of the same request
+ * solved alone.
+ * ------------------------------------------------------------------------ */
+typedef struct sts_server sts_server;
+
+typedef struct {
+  sts_space space;
+  int64_t nt;               /* time steps */
+  int32_t p;                /* rank of the load, 1..4 */
+  int32_t pad_;
+  const double* dt_diag;    /* host: Dt diagonal (nt) and sub-diagonal (nt-1) */
+  const double* dt_sub;
+  const double* mt_diag;    /* host: Mt diagonal (nt) and sub-diagonal (nt-1) */
+  const double* mt_sub;
+  const double* F1;         /* host: Nh x p, leading dimension ldf1 */
+  int64_t ldf1;
+  const double* F2;         /* host: nt x p, leading dimension ldf2 */
+  int64_t ldf2;
+  sts_opts opts;            /* solve options (start from sts_default_opts) */
+} sts_request;
+
+typedef struct {
+  int32_t status;           /* sts_status of the request's create and solve */
+  int32_t pad_;
+  double queued_seconds;    /* submission -> admission */
+  double latency_seconds;   /* submission -> factors ready in device memory */
+  int64_t footprint;        /* device bytes reserved for the request */
+  sts_info info;            /* of the solve */
+} sts_result;
+
+typedef struct {
+  int64_t submitted, completed, released;
+  int64_t queued, running;
+  int64_t mem_in_use, mem_peak, mem_budget;   /* bytes of footprint */
+} sts_server_stats;
+
+/* Device bytes a problem of this shape holds after sts_create and a solve
+ * with these options (NULL = defaults): an upper estimate dominated by the
+ * basis capacity 3 Nh 2p (max_outer + 2) doubles that sts_solve reserves.
+ * -1 for an invalid shape. */
+int64_t sts_footprint(const sts_space* space, int64_t nt, int32_t p, const sts_opts* opts);
+
+/* workers: 1..64; mem_budget > 0 bytes.  Errors: STS_E_INVALID, STS_E_DEVICE. */
+sts_status sts_server_create(int32_t workers, int64_t mem_budget, sts_server** out);
+
+/* Queue a request; *ticket identifies it.  The inputs are copied before the
+ * call returns.  Errors: STS_E_INVALID (shape, pointers, leading dimensions;
+ * the full validation of sts_create happens when the request runs and is
+ * reported in its sts_result), STS_E_NOMEM (footprint above the budget),
+ * STS_E_STATE (server shutting down). */
+sts_status sts_server_submit(sts_server* server, const sts_request* req, int64_t* ticket);
+
+/* Wait up to timeout_s seconds (< 0: without limit) for the request to
+ * finish; then fill *result (may be NULL) and *prob (may be NULL) with the
+ * solved problem, which the server owns until sts_server_release (use it
+ * with sts_get_factors, sts_true_residual, ...; do not destroy it).
+ * STS_E_STATE if the request has not finished in time, STS_E_INVALID for an
+ * unknown or released ticket.  A failed request returns STS_OK here with its
+ * status in result->status (sts_last_error describes it). */
+sts_status sts_server_wait(sts_server* server, int64_t ticket, double timeout_s,
+                           sts_result* result, sts_problem** prob);
+
+/* Free a finished request's problem and its footprint.  STS_E_STATE if it
+ * has not finished. */
+sts_status sts_server_release(sts_server* server, int64_t ticket);
+
+sts_status sts_server_get_stats(sts_server* server, sts_server_stats* out);
+
+/* Stop the workers after their current requests, drop queued requests and
+ * free every unreleased problem (NULL-safe).  No other call may overlap. */
+void sts_server_destroy(sts_server* server);
 
 #ifdef __cplusplus
 }

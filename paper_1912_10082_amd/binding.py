@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "STS_OK", 1: "STS_E_INVALID", 2: "STS_E_NOMEM", 3: "STS_E_DEV
 STS_MEM_HOST, STS_MEM_DEVICE = 0, 1
 STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT = 1, 2, 3
 STS_OP_K, STS_OP_M = 0, 1
-STS_K_COUNT = 16
+STS_K_COUNT = 17
 
 
 class STSError(RuntimeError):
@@ -44,7 +44,7 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32), ("verify_true", C.c_int32),
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
-                ("profile", C.c_int32), ("inner_precond", C.c_int32), ("pad_", C.c_int32)]
+                ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -52,10 +52,29 @@ class Info(C.Structure):
                 ("rank", C.c_int64), ("inner_its_K", C.c_int64), ("inner_its_M", C.c_int64),
                 ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
                 ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
-                ("pad_", C.c_int32), ("cg_poll_restarts", C.c_int64)]
+                ("shifts", C.c_int32), ("cg_poll_restarts", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
+class Request(C.Structure):
+    _fields_ = [("space", Space), ("nt", C.c_int64), ("p", C.c_int32), ("pad_", C.c_int32),
+                ("dt_diag", C.POINTER(C.c_double)), ("dt_sub", C.POINTER(C.c_double)),
+                ("mt_diag", C.POINTER(C.c_double)), ("mt_sub", C.POINTER(C.c_double)),
+                ("F1", C.POINTER(C.c_double)), ("ldf1", C.c_int64),
+                ("F2", C.POINTER(C.c_double)), ("ldf2", C.c_int64), ("opts", Opts)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("pad_", C.c_int32), ("queued_seconds", C.c_double),
+                ("latency_seconds", C.c_double), ("footprint", C.c_int64), ("info", Info)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("released", C.c_int64),
+                ("queued", C.c_int64), ("running", C.c_int64), ("mem_in_use", C.c_int64),
+                ("mem_peak", C.c_int64), ("mem_budget", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -82,6 +101,11 @@ _SIGS = {
     "sts_pcg_mg": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64, _I32,
                              C.POINTER(_I32), _P]),
     "sts_mg_vcycle": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _P]),
+    "sts_adaptive_shift": (C.c_int, [_D, _I32, _D, _I32, _F64, _F64, _I32, _D]),
+    "sts_shifted_solve": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _F64, _I32,
+                                    C.POINTER(_I32), _P]),
+    "sts_tridiag_solve": (C.c_int, [C.POINTER(Space), C.POINTER(_I32), _P, _I64, _P, _I64, _I32,
+                                    _P]),
     "sts_mass_solve": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64,
                                  C.POINTER(_I32), _P]),
     "sts_m_orthonormalize": (C.c_int, [C.POINTER(Space), _P, _P, _I64, _I64, _P, _P, _I64, _I32,
@@ -91,6 +115,18 @@ _SIGS = {
     "sts_sym_eig": (C.c_int, [_I64, _P, _I64, _P, _P, _I64, _P]),
     "sts_time_sweep": (C.c_int, [_I64, _I64, _I32, _P, _P, _I64, _P, _I64, _P, _I64,
                                  C.POINTER(Bidiag), C.POINTER(Bidiag), _P, _I64, _P]),
+    "sts_pool_create": (C.c_int, [_I32, C.POINTER(_P)]),
+    "sts_pool_workers": (C.c_int, [_P, C.POINTER(_I32)]),
+    "sts_pool_solve": (C.c_int, [_P, _I32, C.POINTER(_P), C.POINTER(Opts), _I32, C.POINTER(Info),
+                                 C.POINTER(C.c_int)]),
+    "sts_pool_destroy": (None, [_P]),
+    "sts_footprint": (C.c_int64, [C.POINTER(Space), _I64, _I32, C.POINTER(Opts)]),
+    "sts_server_create": (C.c_int, [_I32, _I64, C.POINTER(_P)]),
+    "sts_server_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(_I64)]),
+    "sts_server_wait": (C.c_int, [_P, _I64, _F64, C.POINTER(Result), C.POINTER(_P)]),
+    "sts_server_release": (C.c_int, [_P, _I64]),
+    "sts_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+    "sts_server_destroy": (None, [_P]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -363,6 +399,38 @@ def mass_solve(space: Space, B, rtol: float = 1e-13):
     return X, its[0]
 
 
+def tridiag_solve(space: Space, ops, B):
+    """A X = B with A = Kx or Mx per column (ops), 1-D P1, direct."""
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_empty(B.shape[0], B.shape[1])
+    o = (C.c_int32 * B.shape[1])(*ops)
+    _check(load().sts_tridiag_solve(C.byref(space), o, pb, ldb, C.c_void_p(X.data_ptr()),
+                                    max(X.shape[0], 1), B.shape[1], _stream_handle()))
+    return X
+
+
+def adaptive_shift(ritz, shifts, a: float, b: float, grid: int = 1001) -> float:
+    """Next rational Krylov shift (sts_adaptive_shift)."""
+    r = np.ascontiguousarray(ritz, dtype=np.float64)
+    sh = np.ascontiguousarray(shifts, dtype=np.float64)
+    out = C.c_double()
+    _check(load().sts_adaptive_shift(r.ctypes.data_as(_D) if len(r) else None, len(r),
+                                     sh.ctypes.data_as(_D) if len(sh) else None, len(sh),
+                                     float(a), float(b), int(grid), C.byref(out)))
+    return out.value
+
+
+def shifted_solve(space: Space, shift: float, B, rtol: float = 1e-13, maxit: int = 200000):
+    """(Kx + shift Mx) X = B as the rational Krylov steps solve it; (X, iterations)."""
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_empty(B.shape[0], B.shape[1])
+    its = (C.c_int32 * B.shape[1])()
+    _check(load().sts_shifted_solve(C.byref(space), float(shift), pb, ldb,
+                                    C.c_void_p(X.data_ptr()), max(X.shape[0], 1), B.shape[1],
+                                    rtol, maxit, its, _stream_handle()))
+    return X, list(its)
+
+
 def mg_vcycle(space: Space, R):
     """Z = Bmg R, one multigrid V-cycle (the preconditioner of pcg_mg)."""
     R, pr, ldr = dev_colmajor(R)
@@ -433,3 +501,154 @@ def time_sweep(lam, Q, beta, F2, dt, mt):
     _check(load().sts_time_sweep(k, nt, p, pl, pq, ldq, pb, ldb, pf, ldf, C.byref(Dt), C.byref(Mt),
                                  C.c_void_p(Y.data_ptr()), k, _stream_handle()))
     return Y
+
+
+class Pool:
+    """Solves many problems on one GPU, up to ``workers`` at a time
+    (sts_pool_create / sts_pool_solve / sts_pool_destroy)."""
+
+    def __init__(self, workers: int):
+        self._lib = load()
+        h = C.c_void_p()
+        _check(self._lib.sts_pool_create(int(workers), C.byref(h)))
+        self._h = h
+        self.workers = int(workers)
+
+    def solve(self, problems, opts=None, **common) -> list:
+        """Solve every Problem in ``problems``; ``opts`` is one dict of
+        options per problem (or None: ``common`` for all).  Returns one info
+        dict per problem, with its "status" and "error"."""
+        n = len(problems)
+        handles = (C.c_void_p * max(n, 1))(*[pr._h for pr in problems])
+        if opts is None:
+            arr = (Opts * 1)(default_opts(**common))
+            nopts = 1
+        else:
+            if len(opts) != n:
+                raise ValueError("one options dict per problem")
+            arr = (Opts * max(n, 1))(*[default_opts(**{**common, **o}) for o in opts])
+            nopts = n
+        infos = (Info * max(n, 1))()
+        status = (C.c_int * max(n, 1))(*([-1] * max(n, 1)))
+        code = self._lib.sts_pool_solve(self._h, n, handles, arr, nopts, infos, status)
+        if code != STS_OK and any(status[i] == -1 for i in range(n)):
+            _check(code)          # rejected before any solve started
+        msg = self._lib.sts_last_error().decode() if code != STS_OK else ""
+        out = []
+        for i in range(n):
+            d = infos[i].as_dict()
+            d["status"] = STATUS_NAMES.get(status[i], status[i])
+            d["error"] = ""
+            out.append(d)
+        if code != STS_OK:
+            first = min(i for i in range(n) if status[i] != STS_OK)
+            out[first]["error"] = msg
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sts_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def footprint(dim: int, n: int, nt: int, p: int, **opts) -> int:
+    """Device bytes a problem of this shape holds once solved (sts_footprint)."""
+    space = make_space(dim, n)
+    return int(load().sts_footprint(C.byref(space), nt, p, C.byref(default_opts(**opts))))
+
+
+class ServedProblem:
+    """A finished request's problem, owned by the server until release."""
+
+    def __init__(self, lib, handle, nh: int, nt: int):
+        self._lib, self._h, self.nh, self.nt = lib, handle, nh, nt
+        self._stream = C.c_void_p(0)
+
+    rank = Problem.rank
+    factors = Problem.factors
+    true_residual = Problem.true_residual
+    numerical_rank = Problem.numerical_rank
+
+
+class Server:
+    """Request queue in front of the solver (sts_server_*)."""
+
+    def __init__(self, workers: int, mem_budget: int):
+        self._lib = load()
+        h = C.c_void_p()
+        _check(self._lib.sts_server_create(int(workers), int(mem_budget), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, dim: int, n: int, mu: float, dt, mt, F1, F2, **opts) -> int:
+        """Queue one problem (host arrays); returns its ticket."""
+        dd, ds = (np.ascontiguousarray(a, dtype=np.float64) for a in dt)
+        md, ms = (np.ascontiguousarray(a, dtype=np.float64) for a in mt)
+        f1, f2 = _host_colmajor(F1), _host_colmajor(F2)
+        r = Request()
+        r.space = make_space(dim, n, mu)
+        r.nt = len(dd)
+        r.p = f1.shape[1]
+        ds = ds if len(ds) else np.zeros(1)
+        ms = ms if len(ms) else np.zeros(1)
+        r.dt_diag, r.dt_sub = dd.ctypes.data_as(_D), ds.ctypes.data_as(_D)
+        r.mt_diag, r.mt_sub = md.ctypes.data_as(_D), ms.ctypes.data_as(_D)
+        r.F1, r.ldf1 = f1.ctypes.data_as(_D), f1.shape[0]
+        r.F2, r.ldf2 = f2.ctypes.data_as(_D), f2.shape[0]
+        r.opts = default_opts(**opts)
+        t = C.c_int64()
+        _check(self._lib.sts_server_submit(self._h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = (int(np.prod([r.space.n[d] for d in range(3)])), r.nt)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """(result dict, ServedProblem or None) once the request has finished."""
+        res = Result()
+        h = C.c_void_p()
+        _check(self._lib.sts_server_wait(self._h, int(ticket), float(timeout), C.byref(res),
+                                         C.byref(h)))
+        d = res.info.as_dict()
+        d.update(status=STATUS_NAMES.get(res.status, res.status),
+                 queued_seconds=res.queued_seconds, latency_seconds=res.latency_seconds,
+                 footprint=res.footprint,
+                 error=self._lib.sts_last_error().decode() if res.status != STS_OK else "")
+        nh, nt = self._keep[int(ticket)]
+        return d, (ServedProblem(self._lib, h, nh, nt) if h.value else None)
+
+    def release(self, ticket: int):
+        _check(self._lib.sts_server_release(self._h, int(ticket)))
+        self._keep.pop(int(ticket), None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.sts_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sts_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -527,6 +528,8 @@ struct sts_problem {
   // multigrid-preconditioned CG for Kx (allocated on first use)
   bool mg_ok = false;
   bool mass_cheb = false;   // Mx solves by Chebyshev iteration
+  bool tri_ok = false;      // 1-D: direct tridiagonal solves for Kx and Mx
+  DevBuf tri_fac;           // their elimination factors (4 Nh)
   MGPlan mg_plan_{};
   std::unique_ptr<MGRunner> mg;
   // kernel timing of the last profiled solve
@@ -545,6 +548,7 @@ struct sts_problem {
   double alg_bytes = 0.0;
   int checks = 0;
   double last_cheap = -1.0;
+  std::vector<double> shifts;   // rational Krylov shifts used so far
 
   unsigned* counter(int i) const { return static_cast<unsigned*>(counters.p) + i; }
 
@@ -745,10 +749,101 @@ void check_inner(const CGScal& s) {
 // (plain CG) and the Kx columns after them (preconditioned CG); perm[j] is the
 // source column of result column j.  Otherwise all columns go through plain
 // CG in their order.
+// Inner solves of a rational Krylov step: (Kx + s Mx) x_c = b_c.  1-D: direct
+// (elimination factors of the shifted matrix formed on the fly); otherwise
+// CG on the shifted stencil (plain CG: the multigrid preconditioner is built
+// for Kx alone).
+void run_shifted_block(sts_problem* P, double s, int ncols, const double* const* b,
+                       const sts_opts& o) {
+  double* x0 = P->V.d() + P->k * P->ldv;
+  if (o.inner_precond != 0 && P->tri_ok) {
+    tridiag_shifted_solve(P->grid, P->K, P->M, s, ncols, b, x0, P->ldv, P->cg.w.r[0], P->ldv,
+                          P->stream);
+    P->inner_K += ncols;
+    P->alg_bytes += 40.0 * P->nh * ncols;
+    return;
+  }
+  // Kx + s Mx has the pattern of Mx (a superset of that of Kx): it runs in
+  // the operator slot of Mx
+  Stencil S = P->M;
+  for (int i = 0; i < 27; ++i) S.c[i] = P->K.c[i] + s * P->M.c[i];
+  const Stencil M0 = P->cg.M;
+  const int e0 = P->cg.expect[0], e1 = P->cg.expect[1];
+  P->cg.M = S;
+  P->cg.expect[0] = P->cg.expect[1] = 0;
+  int ops[kMaxCols];
+  for (int c = 0; c < ncols; ++c) ops[c] = STS_OP_M;
+  CGScal out[kMaxCols];
+  P->cg.w.x = x0;
+  P->cg.w.ld = P->ldv;
+  auto restore = [&] {
+    P->cg.M = M0;
+    P->cg.expect[0] = e0;
+    P->cg.expect[1] = e1;
+  };
+  try {
+    P->cg.run(ops, ncols, b, o.inner_rtol, o.inner_maxit, out, P->stream);
+  } catch (...) {
+    restore();
+    throw;
+  }
+  restore();
+  for (int j = 0; j < ncols; ++j) {
+    check_inner(out[j]);
+    P->inner_K += out[j].iters;
+    P->alg_bytes += (48.0 * out[j].iters + 32.0) * P->nh;
+  }
+}
+
+// Greedy shift for real spectra (Druskin and Simoncini 2011, the adaptive
+// choice Sec. 4 refers to): the maximiser over a logarithmic grid of [a, b]
+// of prod_l |s - s_l| / prod_i |s + theta_i|, evaluated in logarithms.
+double adaptive_shift(const double* ritz, int k, const double* shifts, int m, double a, double b,
+                      int grid) {
+  STS_REQUIRE(a > 0.0 && b >= a && grid >= 2 && k >= 0 && m >= 0, STS_E_INVALID,
+              "adaptive shift: need 0 < a <= b, grid >= 2");
+  const double la = std::log(a), step = (std::log(b) - la) / (grid - 1);
+  double best = -std::numeric_limits<double>::infinity(), sbest = a;
+  for (int g = 0; g < grid; ++g) {
+    const double sv = g == 0 ? a : (g == grid - 1 ? b : std::exp(la + step * g));
+    double f = 0.0;
+    for (int l = 0; l < m; ++l) f += std::log(std::fabs(sv - shifts[l]) + 1e-300);
+    for (int i = 0; i < k; ++i) f -= std::log(std::fabs(sv + ritz[i]));
+    if (f > best) {
+      best = f;
+      sbest = sv;
+    }
+  }
+  return sbest;
+}
+
+// Eigenvalues of the reduced pencil (Km, I) of the first k columns (host).
+void ritz_values(sts_problem* P, int64_t k, std::vector<double>& out) {
+  EigWork ew{};
+  ew.base = P->eig_work.d();
+  ew.status = static_cast<int*>(P->eig_meta.p);
+  sym_eig((int)k, P->Kred.d(), P->kcap, P->lam.d(), P->Q.d(), P->kcap, ew, P->stream);
+  out.resize(k);
+  STS_HIP(hipMemcpyAsync(out.data(), P->lam.d(), k * sizeof(double), hipMemcpyDeviceToHost,
+                         P->stream));
+  STS_HIP(hipStreamSynchronize(P->stream));
+  for (double v : out) STS_REQUIRE(std::isfinite(v), STS_E_NUMERIC, "Ritz values not finite");
+}
+
 void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const* b,
                   const sts_opts& o, int* perm) {
   for (int c = 0; c < ncols; ++c) perm[c] = c;
   double* x0 = P->V.d() + P->k * P->ldv;
+  if (o.inner_precond != 0 && P->tri_ok) {
+    // 1-D: Kx and Mx are tridiagonal; solve every column directly
+    tridiag_solve(P->grid, P->K, P->M, ops, ncols, b, x0, P->ldv, P->tri_fac.d(), P->stream);
+    for (int c = 0; c < ncols; ++c) {
+      if (ops[c] == STS_OP_K) ++P->inner_K;
+      else ++P->inner_M;
+    }
+    P->alg_bytes += 32.0 * P->nh * ncols;
+    return;
+  }
   const bool use_mg = o.inner_precond != 0 && P->mg_ok;
   int nm = 0, nk = 0;
   if (use_mg) {
@@ -900,6 +995,48 @@ sts_status cg_status(const CGScal* out, int ncols, int32_t* iters) {
 }
 }  // namespace
 
+// Hooks for the executors in pool.hip.
+namespace sts {
+
+sts_status guarded(const std::function<void()>& f) { return run_guarded(f); }
+
+hipStream_t problem_stream(const sts_problem* P) { return P->stream; }
+
+void problem_bind_stream(sts_problem* P, hipStream_t s) {
+  if (P->stream == s) return;
+  STS_HIP(hipStreamSynchronize(P->stream));
+  P->stream = s;
+}
+
+int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer) {
+  const Grid g = make_grid(space);
+  const Stencil K = make_stencil(space, STS_OP_K);
+  const Stencil M = make_stencil(space, STS_OP_M);
+  const int64_t ld = pad_ld(g.nh);
+  const int64_t kc = 2LL * p * (max_outer + 2);   // the capacity sts_solve reserves
+  int64_t b = 0;
+  b += ld * p * 8 + nt * p * 8 + 4 * nt * 8;                       // F1, F2, time matrices
+  b += 2 * 2 * ld * kMaxCols * 8 + 2 * ld * kMaxCols * 8;          // CG r, p; residual work
+  b += 3 * ld * kc * 8 + 3 * kc * kc * 8 + kc * p * 8;             // V MV KV; Kred Mred Q; beta
+  b += eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8;
+  b += 3 * kc * nt * 8 + nt * (p + 2 * kc) * 8 + kc * 4 * 8;       // Z Y RB; BT; qb
+  b += gemm_tn_partial_size(std::max<int64_t>(g.nh, nt), (int)kc) * 8;
+  b += residual_norm2_partial_size(g.nh, (int)nt) * 8;
+  MGPlan plan{};
+  if (mg_plan(g, K, &plan)) b += 8 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
+  if (tridiag_supported(g, K, M)) b += 4 * g.nh * 8;
+  return b + (1 << 20);                                            // small scratch
+}
+
+double problem_cost(const sts_problem* P) {
+  // inner solves dominate: grid size x columns x (log of the grid size, a
+  // proxy for the outer iteration count), plus the reduced work along time
+  const double nh = (double)P->nh;
+  return P->p * (nh * std::log2(nh + 2.0) + 64.0 * (double)P->nt);
+}
+
+}  // namespace sts
+
 extern "C" {
 
 void sts_default_opts(sts_opts* o) {
@@ -1029,6 +1166,11 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->pinned), 64 * 8, hipHostMallocDefault));
     P->mg_ok = mg_plan(g, P->K, &P->mg_plan_);
     P->mass_cheb = mass_cheb_supported(g, P->M);
+    P->tri_ok = tridiag_supported(g, P->K, P->M);
+    if (P->tri_ok) {
+      P->tri_fac.alloc(4 * g.nh * 8);
+      tridiag_factor(g, P->K, P->M, P->tri_fac.d(), st);
+    }
     // small scratch
     P->gram.alloc(16 * 16 * 8);
     P->rinv.alloc(16 * 16 * 8);
@@ -1077,6 +1219,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       P->inner_K = P->inner_M = 0;
       P->alg_bytes = 0.0;
       P->checks = 0;
+      P->shifts.clear();
     }
     // kernel timing for sts_kernel_profile, active until this call returns
     struct ProfGuard {
@@ -1125,6 +1268,8 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       }
       int next_check = 1;
       int last_check_outer = -1;
+      std::vector<double> ritz;
+      double ritz_lo = std::numeric_limits<double>::infinity(), ritz_hi = 0.0;
       double last_check_res = -1.0;
       // exact / projected residual, learned from exact checks (inexact inner
       // solves make the projected value read low)
@@ -1135,15 +1280,35 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
         int ops[kMaxCols];
         const double* b[kMaxCols];
         int n = 0;
-        for (int64_t j = 0; j < bsz; ++j) {
-          const int tag = P->tags[bs + j];
-          ops[n] = tag == 0 ? STS_OP_M : STS_OP_K;
-          // positive power: Mx^{-1} (Kx v); negative power: Kx^{-1} (Mx v)
-          b[n] = (tag == 0 ? P->KV.d() : P->MV.d()) + (bs + j) * P->ldv;
-          ++n;
-        }
         int perm[kMaxCols];
-        run_cg_block(P, ops, n, b, o, perm);
+        if (o.rational) {
+          // rational Krylov step: (Kx + s Mx)^{-1} Mx applied to the last
+          // block, s from the Ritz values of the current basis
+          ritz_values(P, P->k, ritz);
+          for (double v : ritz) {
+            ritz_lo = std::min(ritz_lo, v);
+            ritz_hi = std::max(ritz_hi, v);
+          }
+          STS_REQUIRE(ritz_lo > 0.0, STS_E_NUMERIC, "reduced stiffness is not positive definite");
+          const double sft = adaptive_shift(ritz.data(), (int)ritz.size(), P->shifts.data(),
+                                            (int)P->shifts.size(), ritz_lo, ritz_hi, 1001);
+          P->shifts.push_back(sft);
+          for (int64_t j = 0; j < bsz; ++j) {
+            b[n] = P->MV.d() + (bs + j) * P->ldv;
+            perm[n] = n;
+            ++n;
+          }
+          run_shifted_block(P, sft, n, b, o);
+        } else {
+          for (int64_t j = 0; j < bsz; ++j) {
+            const int tag = P->tags[bs + j];
+            ops[n] = tag == 0 ? STS_OP_M : STS_OP_K;
+            // positive power: Mx^{-1} (Kx v); negative power: Kx^{-1} (Mx v)
+            b[n] = (tag == 0 ? P->KV.d() : P->MV.d()) + (bs + j) * P->ldv;
+            ++n;
+          }
+          run_cg_block(P, ops, n, b, o, perm);
+        }
         std::vector<int> src_tag(n);
         for (int j = 0; j < n; ++j) src_tag[j] = P->tags[bs + perm[j]];
         int idx[16];
@@ -1164,6 +1329,35 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
         const bool due = o.check_every > 0 ? (outer % o.check_every == 0 || outer == o.max_outer)
                                            : (outer >= next_check || outer == o.max_outer);
         if (!due) continue;
+        if (o.rational) {
+          // no projected-residual formula for this space: the exact residual
+          // of the Galerkin solution on the whole basis decides
+          P->k_sol = P->k;
+          reduced_solve(P, P->k, 0);
+          cheap = true_residual(P);
+          truer = cheap;
+          P->last_cheap = cheap;
+          if (trace)
+            std::fprintf(stderr, "sts: outer %d k %lld exact residual %.3e (rational)\n", outer,
+                         (long long)P->k, cheap);
+          if (cheap <= o.tol) {
+            result = STS_OK;
+            break;
+          }
+          if (o.check_every == 0) {
+            int step = 1;
+            if (last_check_res > 0.0 && cheap < last_check_res) {
+              const double rate =
+                  std::pow(cheap / last_check_res, 1.0 / std::max(1, outer - last_check_outer));
+              const double need = std::log(o.tol / cheap) / std::log(rate);
+              step = std::max(1, std::min(8, (int)std::ceil(need)));
+            }
+            last_check_outer = outer;
+            last_check_res = cheap;
+            next_check = outer + step;
+          }
+          continue;
+        }
         P->k_sol = kprev;
         cheap = reduced_solve(P, kprev, kept);
         P->last_cheap = cheap;
@@ -1214,6 +1408,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       info->inner_its_M = P->inner_M;
       info->res_cheap = cheap;
       info->breakdown = breakdown ? 1 : 0;
+      info->shifts = (int32_t)P->shifts.size();
       if (truer < 0.0 && o.verify_true && P->k_sol > 0) truer = true_residual(P);
       info->res_true = truer;
       info->orth_err = orth_error(P);
@@ -1294,7 +1489,7 @@ const char* sts_kernel_name(int32_t kernel) {
   static const char* names[STS_K_COUNT] = {
       "cg_iter",   "mg_down",  "mg_up",   "mg_coarse",     "pcg_a", "pcg_b",
       "mass_cheb", "gram",     "basis_update", "residual", "tridiag", "bisect",
-      "inviter",   "backtransform", "sweep", "stencil"};
+      "inviter",   "backtransform", "sweep", "stencil", "tridiag_solve"};
   return (kernel >= 0 && kernel < STS_K_COUNT) ? names[kernel] : "";
 }
 
@@ -1385,6 +1580,73 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops_in, const double* B
   return s;
 }
 
+sts_status sts_adaptive_shift(const double* ritz, int32_t k, const double* shifts, int32_t m,
+                              double a, double b, int32_t grid, double* s) {
+  return run_guarded([&] {
+    STS_REQUIRE(s != nullptr && (k == 0 || ritz) && (m == 0 || shifts), STS_E_INVALID,
+                "sts_adaptive_shift: null argument");
+    *s = adaptive_shift(ritz, k, shifts, m, a, b, grid);
+  });
+}
+
+sts_status sts_shifted_solve(const sts_space* space, double shift, const double* B, int64_t ldb,
+                             double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                             int32_t* iters, void* stream) {
+  sts_status bad = STS_OK;
+  sts_status s = run_guarded([&] {
+    validate_space(space);
+    const Grid g = make_grid(*space);
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(shift >= 0.0 && std::isfinite(shift), STS_E_INVALID, "shift must be >= 0");
+    STS_REQUIRE(rtol > 0.0 && maxit >= 1, STS_E_INVALID, "bad rtol / maxit");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Stencil K = make_stencil(*space, STS_OP_K);
+    const Stencil M = make_stencil(*space, STS_OP_M);
+    Scratch sc;
+    const int64_t ld = pad_ld(g.nh);
+    const double* bcols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
+    if (tridiag_supported(g, K, M)) {
+      double* work = sc.get<double>(ld * ncols);
+      tridiag_shifted_solve(g, K, M, shift, ncols, bcols, X, ldx, work, ld, st);
+      STS_HIP(hipStreamSynchronize(st));
+      if (iters)
+        for (int c = 0; c < ncols; ++c) iters[c] = 1;
+      return;
+    }
+    const int tiles = cg_tiles(g);
+    CGRunner r;
+    r.g = g;
+    r.K = K;
+    r.M = M;   // Kx + shift Mx, in the operator slot whose pattern contains both
+    for (int i = 0; i < 27; ++i) r.M.c[i] = K.c[i] + shift * M.c[i];
+    r.w.r[0] = sc.get<double>(ld * ncols);
+    r.w.r[1] = sc.get<double>(ld * ncols);
+    r.w.p[0] = sc.get<double>(ld * ncols);
+    r.w.p[1] = sc.get<double>(ld * ncols);
+    double* xs = ldx == ld ? X : sc.get<double>(ld * ncols);
+    r.w.x = xs;
+    r.w.ld = ld;
+    r.w.scal = sc.get<CGScal>(2 * kMaxCols);
+    r.w.partials = sc.get<double>((size_t)2 * 2 * kMaxCols * tiles);
+    r.w.max_tiles = tiles;
+    r.poll.init();
+    int ops[kMaxCols];
+    for (int c = 0; c < ncols; ++c) ops[c] = STS_OP_M;
+    CGScal out[kMaxCols];
+    r.run(ops, ncols, bcols, rtol, maxit, out, st);
+    if (xs != X) copy_cols(g.nh, ncols, xs, ld, X, ldx, st);
+    STS_HIP(hipStreamSynchronize(st));
+    bad = cg_status(out, ncols, iters);
+  });
+  if (s == STS_OK && bad != STS_OK) {
+    set_error(bad == STS_E_NUMERIC ? "CG breakdown" : "CG reached maxit");
+    return bad;
+  }
+  return s;
+}
+
 sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, double* X,
                       int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
                       void* stream) {
@@ -1437,6 +1699,35 @@ sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, 
     STS_HIP(hipStreamSynchronize(st));
     if (iters)
       for (int c = 0; c < ncols; ++c) iters[c] = its;
+  });
+}
+
+sts_status sts_tridiag_solve(const sts_space* space, const int32_t* ops, const double* B,
+                             int64_t ldb, double* X, int64_t ldx, int32_t ncols, void* stream) {
+  return run_guarded([&] {
+    validate_space(space);
+    const Grid g = make_grid(*space);
+    const Stencil K = make_stencil(*space, STS_OP_K);
+    const Stencil M = make_stencil(*space, STS_OP_M);
+    STS_REQUIRE(tridiag_supported(g, K, M), STS_E_INVALID,
+                "direct tridiagonal solve needs a 1-D P1 space");
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(ops != nullptr, STS_E_INVALID, "ops is null");
+    for (int c = 0; c < ncols; ++c)
+      STS_REQUIRE(ops[c] == STS_OP_K || ops[c] == STS_OP_M, STS_E_INVALID, "bad operator");
+    STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    double* fac = sc.get<double>(4 * g.nh);
+    tridiag_factor(g, K, M, fac, st);
+    const double* bc[kMaxCols];
+    int op[kMaxCols];
+    for (int c = 0; c < ncols; ++c) {
+      bc[c] = B + c * ldb;
+      op[c] = ops[c];
+    }
+    tridiag_solve(g, K, M, op, ncols, bc, X, ldx, fac, st);
+    STS_HIP(hipStreamSynchronize(st));
   });
 }
 

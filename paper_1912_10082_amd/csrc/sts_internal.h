@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -382,5 +383,37 @@ void fill(double* p, int64_t n, double v, hipStream_t st);
 // sum of squares of a column-major block (deterministic), result to *out.
 void sumsq(int64_t rows, int ncols, const double* A, int64_t lda, double* out, double* partial,
            unsigned* counter, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// direct tridiagonal inner solves (1-D P1), tridiag.hip
+// ---------------------------------------------------------------------------
+bool tridiag_supported(const Grid& g, const Stencil& K, const Stencil& M);
+// fac: 4 Nh doubles of elimination factors of Kx and Mx
+void tridiag_factor(const Grid& g, const Stencil& K, const Stencil& M, double* fac,
+                    hipStream_t st);
+void tridiag_solve(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
+                   const double* const* b, double* x, int64_t ldx, const double* fac,
+                   hipStream_t st);
+// (Kx + s Mx) x = b, s >= 0, factors formed on the fly; work: ncols columns
+// of at least Nh doubles (ldw).
+void tridiag_shifted_solve(const Grid& g, const Stencil& K, const Stencil& M, double s, int ncols,
+                           const double* const* b, double* x, int64_t ldx, double* work,
+                           int64_t ldw, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// problem hooks for the executors (pool.hip)
+// ---------------------------------------------------------------------------
+// Run f, mapping library exceptions to a status and the calling thread's
+// last-error message.
+sts_status guarded(const std::function<void()>& f);
+hipStream_t problem_stream(const sts_problem* P);
+// Make s the problem's stream after the work queued on its current stream
+// has finished.
+void problem_bind_stream(sts_problem* P, hipStream_t s);
+// Relative cost estimate of a solve (for largest-first scheduling).
+double problem_cost(const sts_problem* P);
+// Device bytes a problem holds after sts_create and an sts_solve with this
+// max_outer (upper estimate; the capacity reserved by sts_solve dominates).
+int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer);
 
 }  // namespace sts

@@ -127,3 +127,56 @@ def test_package_has_no_cpu_fallback():
             src = open(os.path.join(pkg, fn)).read()
             for banned in ("import oracle", "from oracle", "import scipy", "from scipy"):
                 assert banned not in src, (fn, banned)
+
+
+def test_pool_rejects_bad_arguments_without_a_gpu():
+    lib = b.load()
+    h = C.c_void_p()
+    assert lib.sts_pool_create(0, C.byref(h)) == b.STS_E_INVALID
+    assert lib.sts_pool_create(65, C.byref(h)) == b.STS_E_INVALID
+    assert lib.sts_pool_solve(None, 0, None, None, 0, None, None) == b.STS_E_INVALID
+    w = C.c_int32()
+    assert lib.sts_pool_workers(None, C.byref(w)) == b.STS_E_INVALID
+    lib.sts_pool_destroy(None)
+
+
+def test_server_and_footprint_reject_bad_arguments_without_a_gpu():
+    lib = b.load()
+    h = C.c_void_p()
+    assert lib.sts_server_create(0, 1 << 30, C.byref(h)) == b.STS_E_INVALID
+    assert lib.sts_server_create(2, 0, C.byref(h)) == b.STS_E_INVALID
+    assert lib.sts_server_submit(None, None, None) == b.STS_E_INVALID
+    assert lib.sts_server_release(None, 1) == b.STS_E_INVALID
+    lib.sts_server_destroy(None)
+    sp = b.make_space(2, 63)
+    assert lib.sts_footprint(C.byref(sp), 1, 2, None) == -1          # nt < 2
+    assert lib.sts_footprint(C.byref(sp), 16, 5, None) == -1         # p > 4
+    # the basis capacity dominates: 3 Nh doubles per reserved column
+    small = sts.footprint(2, 63, 16, 1, max_outer=10)
+    big = sts.footprint(2, 63, 16, 1, max_outer=100)
+    cols = 2 * 1 * (100 - 10)
+    assert big - small >= 3 * 63 * 63 * 8 * cols
+
+
+def test_adaptive_shift_host_rule_matches_oracle():
+    """The library's shift rule is host code: check it against the oracle's
+    restatement on random inputs (same grid) and the closed-form cases."""
+    from oracle import projection
+    rng = np.random.default_rng(12)
+    for trial in range(20):
+        lo = float(np.exp(rng.uniform(-1, 2)))
+        hi = lo * float(np.exp(rng.uniform(1, 12)))
+        ritz = np.exp(rng.uniform(np.log(lo), np.log(hi), size=rng.integers(0, 40)))
+        shifts = np.exp(rng.uniform(np.log(lo), np.log(hi), size=rng.integers(0, 15)))
+        s_lib = sts.adaptive_shift(ritz, shifts, lo, hi, grid=1001)
+        s_ref = projection.adaptive_shift(ritz, shifts, lo, hi, grid=1001)
+
+        def f(s):
+            return (np.sum(np.log(np.abs(s - shifts) + 1e-300)) - np.sum(np.log(np.abs(s + ritz))))
+        # equal maximisers, or (rounding-level ties) equal objective values
+        assert s_lib == pytest.approx(s_ref, rel=1e-12) or abs(f(s_lib) - f(s_ref)) <= 1e-9
+        assert lo <= s_lib <= hi
+    assert sts.adaptive_shift([3.0, 40.0], [], 2.0, 500.0) == 2.0
+    assert sts.adaptive_shift([], [900.0], 1.0, 1000.0) == 1.0
+    with pytest.raises(b.STSError):
+        sts.adaptive_shift([1.0], [], 0.0, 1.0)

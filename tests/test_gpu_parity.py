@@ -90,6 +90,49 @@ def test_cg_is_bitwise_deterministic():
     assert torch.equal(X1, X2)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 127, 4097, 65536])
+def test_tridiag_solve_1d_backward_stable_and_matches_sparse_direct(n):
+    """a3 in 1-D: Kx, Mx are tridiagonal and solved directly."""
+    mu = 0.37
+    rng = np.random.default_rng(n)
+    B = rng.normal(size=(n, 4))
+    B[:, 3] = 0.0
+    ops = [0, 1, 0, 1]                                   # K, M, K, M (zero column)
+    X = host(sts.tridiag_solve(sts.make_space(1, n, mu), ops, dev(B)))
+    K, M = fem.spatial_operators(1, n, mu)
+    assert np.all(X[:, 3] == 0.0)
+    for c, op in enumerate(ops[:3]):
+        A = (K if op == 0 else M).tocsc()
+        r = B[:, c] - A @ X[:, c]
+        anorm = abs(A).sum(axis=1).max()
+        # normwise backward error of an elimination without pivoting on an SPD,
+        # diagonally dominant tridiagonal matrix
+        assert np.linalg.norm(r) <= 1e-14 * (anorm * np.linalg.norm(X[:, c]) +
+                                             np.linalg.norm(B[:, c]))
+        if n <= 4097:
+            # forward error within kappa eps of the sparse LU solution
+            assert rel(X[:, c], spla.spsolve(A, B[:, c])) < 1e-15 * max(1.0, n * n)
+
+
+def test_tridiag_solve_rejects_other_spaces():
+    with pytest.raises(sts.STSError) as e:
+        sts.tridiag_solve(sts.make_space(2, 15), [0], dev(np.ones((225, 1))))
+    assert e.value.code == 1
+
+
+def test_1d_large_solve_with_direct_inner_solves():
+    """A 1-D problem whose plain-CG inner solves would need ~10^4 iterations each."""
+    w = wl.heat_1d_sine(nx=8191, nt=256, seed=21)
+    w.F1 = np.asfortranarray(np.random.default_rng(2).normal(size=(8191, 2)) / 8192)
+    w.F2 = np.asfortranarray(np.column_stack([w.F2[:, 0], np.cos(np.arange(256)) / 256]))
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    K, M, Dt, Mt, U = _oracle(w)
+    assert info["status"] == "STS_OK", info
+    assert info["inner_its_K"] + info["inner_its_M"] <= 4 * (info["outer_its"] + 2)
+    assert rel(V @ Y, U) <= 1e-8, rel(V @ Y, U)
+    prob.close()
+
+
 # ---------------------------------------------------------------- a4: Gram-Schmidt
 
 # Covers one, two and four 16-column tiles per work-group, odd leading
@@ -292,3 +335,51 @@ def test_full_size_2d_bump_problem_properties():
     assert rel(V @ Y[:, :12], U) <= 1e-8
     np.testing.assert_allclose(V.T @ (M @ V), np.eye(V.shape[1]), atol=1e-11)
     prob.close()
+
+
+# ---------------------------------------------------------------- rational Krylov (Sec. 4)
+
+@pytest.mark.parametrize("dim,n,shift", [(1, 1, 3.0), (1, 4097, 250.0), (1, 65536, 1e5),
+                                         (2, 31, 40.0), (2, 100, 1e4), (3, 9, 7.5)])
+def test_shifted_solve_matches_sparse_direct(dim, n, shift):
+    mu = 0.8
+    space = sts.make_space(dim, n, mu)
+    nh = n ** dim
+    B = np.random.default_rng(n + dim).normal(size=(nh, 3))
+    X, its = sts.shifted_solve(space, shift, dev(B), rtol=1e-13)
+    X = host(X)
+    K, M = fem.spatial_operators(dim, n, mu)
+    A = (K + shift * M).tocsc()
+    for c in range(3):
+        r = B[:, c] - A @ X[:, c]
+        if dim == 1:
+            assert its[c] == 1
+            anorm = abs(A).sum(axis=1).max()
+            assert np.linalg.norm(r) <= 1e-14 * (anorm * np.linalg.norm(X[:, c]) +
+                                                 np.linalg.norm(B[:, c]))
+        else:
+            assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(B[:, c])
+        if nh <= 5000:
+            assert rel(X[:, c], spla.spsolve(A, B[:, c])) < 1e-9
+
+
+@pytest.mark.parametrize("dim,n,nt,p", [(1, 1023, 64, 2), (2, 31, 32, 2), (2, 63, 48, 1),
+                                        (3, 7, 20, 2)])
+def test_rational_krylov_solve_matches_crank_nicolson(dim, n, nt, p):
+    if dim == 1:
+        w = wl.heat_1d_profiles(n=n, nt=nt, p=p, seed=31)
+    elif dim == 2:
+        w = wl.heat_2d_bumps(n=n, nt=nt, p=p, seed=32)
+    else:
+        w = wl.heat_3d_separable(n=n, nt=nt, p=p, seed=33)
+    prob, info, V, Y = _solve(w, tol=1e-10, rational=1)
+    K, M, Dt, Mt, U = _oracle(w)
+    assert info["status"] == "STS_OK", info
+    assert info["shifts"] >= 1 and info["res_true"] <= 1e-10
+    assert rel(V @ Y, U) <= 1e-8, rel(V @ Y, U)
+    np.testing.assert_allclose(V.T @ (M @ V), np.eye(V.shape[1]), atol=1e-11)
+    # the rational space reaches the tolerance with a smaller basis
+    prob2, info2, _, _ = _solve(w, tol=1e-10)
+    assert info["k"] < info2["k"], (info["k"], info2["k"])
+    prob.close()
+    prob2.close()

@@ -29,7 +29,9 @@ __all__ = [
     "Workload", "node_coords", "time_grid", "sine_load_1d",
     "cubic_interval_integrals", "trig_series_interval_integrals",
     "gaussian_bump_field_2d", "heat_1d_sine", "heat_2d_bumps",
-    "heat_3d_separable", "random_spd_pencil", "random_reduced_problem",
+    "heat_3d_separable", "heat_2d_separable", "heat_1d_profiles", "batch_2d_uneven",
+    "serving_mix", "make_request_workload", "random_spd_pencil",
+    "random_reduced_problem",
 ]
 
 
@@ -198,6 +200,118 @@ def heat_3d_separable(n: int = 31, nt: int = 64, p: int = 4, seed: int = 3,
         F2[:, q] = trig_series_interval_integrals(a, b, t)
     return Workload(f"heat3d_sep_n{n}", 3, (n, n, n), mu, T, nt, F1, F2,
                     meta={"seed": seed})
+
+
+def heat_2d_separable(n: int = 127, nt: int = 256, p: int = 2, seed: int = 4000,
+                      T: float = 1.0, mu: float = 1.0, nmodes: int = 9) -> Workload:
+    """2-D heat on the unit square with a rank-p separable right-hand side.
+
+    f_p(x, y) = X_p(x) Y_p(y), each 1-D profile as in heat_3d_separable; the
+    load is the vertex-quadrature value h^2 f_p(x_j).  Temporal factors as in
+    the 2-D bump recipe.  Draw order: for each p the profiles X, Y, then the
+    temporal coefficients.
+    """
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n + 1)
+    x = node_coords(n)
+    F1 = np.empty((n * n, p), order="F")
+    for q in range(p):
+        fx, fy = (_profile_1d(x, rng) for _ in range(2))
+        F1[:, q] = h * h * np.outer(fy, fx).ravel()
+    t = time_grid(nt, T)
+    F2 = np.empty((nt, p), order="F")
+    for q in range(p):
+        a = rng.normal(size=nmodes)
+        b = rng.normal(size=nmodes)
+        F2[:, q] = trig_series_interval_integrals(a, b, t)
+    return Workload(f"heat2d_sep_n{n}", 2, (n, n), mu, T, nt, F1, F2,
+                    meta={"seed": seed})
+
+
+def heat_1d_profiles(n: int = 1023, nt: int = 256, p: int = 2, seed: int = 5,
+                     T: float = 1.0, mu: float = 1.0, nmodes: int = 9) -> Workload:
+    """1-D heat on the unit interval with a rank-p right-hand side: each
+    spatial factor a profile as in heat_3d_separable, vertex-quadrature load
+    h X_p(x_j); temporal factors as in the 2-D bump recipe.  Draw order: for
+    each p the profile, then the temporal coefficients."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n + 1)
+    x = node_coords(n)
+    F1 = np.empty((n, p), order="F")
+    for q in range(p):
+        F1[:, q] = h * _profile_1d(x, rng)
+    t = time_grid(nt, T)
+    F2 = np.empty((nt, p), order="F")
+    for q in range(p):
+        a = rng.normal(size=nmodes)
+        b = rng.normal(size=nmodes)
+        F2[:, q] = trig_series_interval_integrals(a, b, t)
+    return Workload(f"heat1d_prof_n{n}", 1, (n,), mu, T, nt, F1, F2, meta={"seed": seed})
+
+
+def serving_mix(count: int, seed: int = 5, frac_1d: float = 0.45, frac_2d: float = 0.45,
+                nx_1d=(1000, 8192), sides_2d=(63, 95, 127, 191, 255, 383, 511),
+                sides_3d=(15, 23, 31), nt_range=(128, 2048)) -> list:
+    """Request shapes of a serving workload: (dim, n, nt, p, mu, seed) tuples.
+
+    One generator default_rng(seed) draws, per request and in this order: a
+    uniform u choosing the dimension (1-D if u < frac_1d, 2-D if below
+    frac_1d + frac_2d, else 3-D), Nt = round(exp(U[log a, log b])) over
+    nt_range, mu = exp(U[log 0.1, log 10]), P uniform in 1..4, the grid size
+    (1-D: log-uniform over nx_1d, rounded; 2-D / 3-D: uniform over the
+    sides), and a 31-bit seed for the request's load.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        u = rng.uniform()
+        nt = int(round(np.exp(rng.uniform(np.log(nt_range[0]), np.log(nt_range[1])))))
+        mu = float(np.exp(rng.uniform(np.log(0.1), np.log(10.0))))
+        p = int(rng.integers(1, 5))
+        if u < frac_1d:
+            dim = 1
+            n = int(round(np.exp(rng.uniform(np.log(nx_1d[0]), np.log(nx_1d[1])))))
+        elif u < frac_1d + frac_2d:
+            dim = 2
+            n = int(sides_2d[rng.integers(len(sides_2d))])
+        else:
+            dim = 3
+            n = int(sides_3d[rng.integers(len(sides_3d))])
+        out.append((dim, n, nt, p, mu, int(rng.integers(1 << 31))))
+    return out
+
+
+def make_request_workload(dim: int, n: int, nt: int, p: int, mu: float, seed: int) -> Workload:
+    """The load of one serving_mix request."""
+    if dim == 1:
+        return heat_1d_profiles(n=n, nt=nt, p=p, seed=seed, mu=mu)
+    if dim == 2:
+        return heat_2d_separable(n=n, nt=nt, p=p, seed=seed, mu=mu)
+    return heat_3d_separable(n=n, nt=nt, p=p, seed=seed, mu=mu)
+
+
+def batch_2d_uneven(count: int = 256, seed0: int = 4000, sides=(63, 127, 255),
+                    nts=(128, 256, 512, 1024), ps=(1, 2, 3)) -> list:
+    """A batch of independent 2-D problems of uneven size.
+
+    Problem i uses default_rng(seed0 + i) and draws, in this order: the
+    diffusion coefficient mu = exp(U[log 0.1, log 10]), the grid side
+    (uniform over ``sides``), Nt (uniform over ``nts``), P (uniform over
+    ``ps``); its right-hand side is heat_2d_separable with the seed
+    seed0 + i + 1000000.
+    """
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        mu = float(np.exp(rng.uniform(np.log(0.1), np.log(10.0))))
+        n = int(sides[rng.integers(len(sides))])
+        nt = int(nts[rng.integers(len(nts))])
+        p = int(ps[rng.integers(len(ps))])
+        w = heat_2d_separable(n=n, nt=nt, p=p, seed=seed0 + i + 1000000, mu=mu)
+        w.name = f"batch{i}_n{n}_nt{nt}_p{p}"
+        w.meta["index"] = i
+        out.append(w)
+    return out
 
 
 def random_spd_pencil(k: int, seed: int, spread: float = 6.0):
