@@ -258,7 +258,8 @@ def bench_serve(args) -> int:
     """Poisson arrivals (rate --serve-rate, seed 5) over --serve-seconds of
     requests drawn by workloads.serving_mix (45% 1-D, 45% 2-D, 10% 3-D; Nt
     log-uniform in [128, 2048]; P in 1..4; mu log-uniform in [0.1, 10]),
-    served by --serve-workers workers under a 64 GiB footprint budget.
+    served by --serve-workers workers under a 200 GiB footprint budget, each
+    to a relative residual of 1e-8.
     Reports completed solves/s, p50/p99 latency (submission to factors ready)
     and queueing delay; re-solves every 20th request alone to check that its
     factors are bitwise those it got in the mix, and checks the sampled
@@ -285,7 +286,9 @@ def bench_serve(args) -> int:
         w = wl.make_request_workload(*sh)
         dd, ds, md, ms = sts.time_matrices(wl.time_grid(w.nt, w.T))
         reqs.append((w, (dd, ds), (md, ms)))
-    opts = dict(tol=1e-9, max_outer=100)
+    # residual 1e-8: the 1-D requests (Nx up to 8192) cannot resolve residuals
+    # much below 1e-9 in FP64; the error gate is 1e-8
+    opts = dict(tol=1e-8, max_outer=100)
     budget = 200 << 30
     sample = set(range(0, len(reqs), 20))
     results = [None] * len(reqs)
