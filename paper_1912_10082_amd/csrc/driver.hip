@@ -422,17 +422,22 @@ struct MGRunner {
     for (int l = 1; l <= plan.nlev; ++l) {
       w.ld[l] = pad_ld((int64_t)plan.n[l] * plan.n[l]);
       tot += 2 * w.ld[l] * kMaxCols;
+      if (l < plan.nlev) tot += w.ld[l] * kMaxCols;   // pre-smoothed iterate
     }
     const bool big = plan.exact > kMGCoarseMax;
     if (big) tot += 2 * w.ld[plan.nlev] * kMaxCols;
     w.ld[0] = pad_ld((int64_t)plan.n[0] * plan.n[0]);
     levels.alloc(std::max<int64_t>(tot, 1) * 8);
-    vecs.alloc(5 * w.ld[0] * kMaxCols * 8);
+    vecs.alloc(6 * w.ld[0] * kMaxCols * 8);
     double* q = levels.d();
     for (int l = 1; l <= plan.nlev; ++l) {
       w.b[l] = q;
       w.e[l] = q + w.ld[l] * kMaxCols;
       q += 2 * w.ld[l] * kMaxCols;
+      if (l < plan.nlev) {
+        w.xp[l] = q;
+        q += w.ld[l] * kMaxCols;
+      }
     }
     if (big) {
       w.t1 = q;
@@ -444,6 +449,7 @@ struct MGRunner {
     w.p[0] = v + 2 * w.ld[0] * kMaxCols;
     w.p[1] = v + 3 * w.ld[0] * kMaxCols;
     w.q = v + 4 * w.ld[0] * kMaxCols;
+    w.xp[0] = v + 5 * w.ld[0] * kMaxCols;
     w.max_tiles = mg_max_tiles(plan);
     scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
     w.scal = static_cast<CGScal*>(scal.p);
@@ -462,8 +468,8 @@ struct MGRunner {
   }
 
   // Algorithmic bytes of one column-iteration per fine node: each level's
-  // down reads b_l and writes b_{l+1}, its up reads b_l and e_{l+1} and
-  // writes e_l, the coarse launch reads b_L and writes e_L, A reads z, p and
+  // down reads b_l and writes b_{l+1} and the pre-smoothed iterate, its up
+  // reads b_l, that iterate and e_{l+1} and writes e_l, the coarse launch reads b_L and writes e_L, A reads z, p and
   // writes p, q, B reads x, p, r, q and writes x, r.
   double bytes_per_node() const {
     const double n0 = (double)w.plan.n[0] * w.plan.n[0];
@@ -471,7 +477,7 @@ struct MGRunner {
     for (int l = 0; l < w.plan.nlev; ++l) {
       const double nf = (double)w.plan.n[l] * w.plan.n[l];
       const double nc = (double)w.plan.n[l + 1] * w.plan.n[l + 1];
-      b += 8.0 * (nf + nc) + 8.0 * (2.0 * nf + nc);
+      b += 8.0 * (2.0 * nf + nc) + 8.0 * (3.0 * nf + nc);
     }
     const double nL = (double)w.plan.n[w.plan.nlev] * w.plan.n[w.plan.nlev];
     b += 16.0 * nL;
@@ -1023,7 +1029,7 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   b += gemm_tn_partial_size(std::max<int64_t>(g.nh, nt), (int)kc) * 8;
   b += residual_norm2_partial_size(g.nh, (int)nt) * 8;
   MGPlan plan{};
-  if (mg_plan(g, K, &plan)) b += 8 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
+  if (mg_plan(g, K, &plan)) b += 9 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
   if (tridiag_supported(g, K, M)) b += 4 * g.nh * 8;
   return b + (1 << 20);                                            // small scratch
 }

@@ -27,9 +27,10 @@
 // iteration is ordinary preconditioned CG.
 //
 // Launches per PCG iteration: per tiled level a "down" (smoothing from
-// zero, residual, restriction -- recomputed on LDS halos, only the restricted
-// right-hand side is stored) and an "up" (pre-smoothed values recomputed
-// from the level's right-hand side, interpolated correction, smoothing), one
+// zero, residual, restriction -- recomputed on LDS halos; the restricted
+// right-hand side and the pre-smoothed iterate on the tile's own nodes are
+// stored) and an "up" (pre-smoothed iterate loaded with the halo its kNu
+// smoothing steps need, interpolated correction, smoothing), one
 // coarse launch, and two PCG launches: A {beta from (r, z); p = z + beta p;
 // q = K p; (p, q)} and B {alpha = rho / (p, q); x += alpha p; r -= alpha q;
 // (r, r)}.  Global sums are per-tile partials that the consuming work-groups
@@ -163,6 +164,7 @@ struct LevelArgs {
   double* bc;          // down: restricted residual
   const double* ec;    // up: coarse correction
   double* ef;          // up: result on the fine level
+  double* xp;          // pre-smoothed fine iterate: written by down, read by up
   int ntx, nty;        // coarse tiles
   int nlaunch;
   int cols[kMaxCols];
@@ -197,6 +199,17 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
   }
   __syncthreads();
   const int cur = presmooth<W, H>(R, a.sm, inv_d, bs, us, ds, mu);
+  // the pre-smoothed iterate on the tile's own fine nodes, for the up launch
+  {
+    const int x1 = (cx0 + CX >= nc) ? nf : 2 * (cx0 + CX);
+    const int y1 = (cy0 + CY >= nc) ? nf : 2 * (cy0 + CY);
+    const int ow = x1 - 2 * cx0, oh = y1 - 2 * cy0;
+    double* xpg = a.xp + (size_t)col * a.ldf;
+    for (int i = threadIdx.x; i < ow * oh; i += kT) {
+      const int gx = 2 * cx0 + i % ow, gy = 2 * cy0 + i / ow;
+      xpg[(size_t)gy * nf + gx] = us[cur][(gy - R.oy) * W + (gx - R.ox)];
+    }
+  }
   // residual on shrink kNu into ds
   for (int i = threadIdx.x; i < W * H; i += kT) {
     const int lx = i % W, ly = i / W;
@@ -222,7 +235,7 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
 // nf).  Fine region [2 cx0 - (2 kNu - 1), ...), coarse [cx0 - kNu, ...).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
-  constexpr int HL = 2 * kNu - 1;
+  constexpr int HL = kNu;   // halo of the kNu post-smoothing steps
   constexpr int W = 2 * CX + 1 + 2 * HL, H = 2 * CY + 1 + 2 * HL;
   constexpr int EW = CX + 2 * kNu, EH = CY + 2 * kNu;
   __shared__ double bs[W * H];
@@ -240,27 +253,35 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   const int cox = cx0 - kNu, coy = cy0 - kNu;
   const double mu = a.mu, inv_d = 1.0 / (4.0 * mu);
   const double* bf = a.bf + (size_t)col * a.ldf;
+  const double* xpg = a.xp + (size_t)col * a.ldf;
   const double* ecg = a.ec + (size_t)col * a.ldc;
+  // b and the pre-smoothed iterate of the down launch (zero outside the
+  // domain in both buffers: the Dirichlet values the stencil reads)
   for (int i = threadIdx.x; i < W * H; i += kT) {
     const int gx = R.ox + i % W, gy = R.oy + i / W;
-    bs[i] = (gx >= 0 && gx < nf && gy >= 0 && gy < nf) ? bf[(size_t)gy * nf + gx] : 0.0;
+    const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf;
+    const size_t g = (size_t)gy * nf + gx;
+    bs[i] = in ? bf[g] : 0.0;
+    us[0][i] = in ? xpg[g] : 0.0;
+    us[1][i] = 0.0;
+    ds[i] = 0.0;
   }
   for (int i = threadIdx.x; i < EW * EH; i += kT) {
     const int I = cox + i % EW, J = coy + i / EW;
     es[i] = (I >= 0 && I < nc && J >= 0 && J < nc) ? ecg[(size_t)J * nc + I] : 0.0;
   }
   __syncthreads();
-  int cur = presmooth<W, H>(R, a.sm, inv_d, bs, us, ds, mu);
   for (int i = threadIdx.x; i < W * H; i += kT) {
-    if (R.inside(i, kNu - 1)) {
+    if (R.inside(i, 0)) {
       const int gx = R.ox + i % W, gy = R.oy + i / W;
-      us[cur][i] += interp(es, EW, cox, coy, gx, gy);
+      us[0][i] += interp(es, EW, cox, coy, gx, gy);
     }
   }
   __syncthreads();
+  int cur = 0;
   // post-smoothing; the last step's new values are needed on the owned nodes only
   for (int k = 0; k + 1 < kNu; ++k) {
-    cheb_step<W, H>(R, kNu + k, k == 0 ? 0.0 : a.sm.a[k], a.sm.c[k], inv_d, bs, us[cur],
+    cheb_step<W, H>(R, 1 + k, k == 0 ? 0.0 : a.sm.a[k], a.sm.c[k], inv_d, bs, us[cur],
                     us[cur ^ 1], ds, mu);
     cur ^= 1;
   }
@@ -777,6 +798,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.ldc = w.ld[l + 1];
     a.bf = w.b[l];
     a.bc = w.b[l + 1];
+    a.xp = w.xp[l];
     a.ntx = (a.nc + CX - 1) / CX;
     a.nty = (a.nc + CY - 1) / CY;
     a.nlaunch = nlaunch;
@@ -784,7 +806,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.st = act;
     a.mu = p.mu;
     a.sm = sm;
-    launch(STS_K_MG_DOWN, 8.0 * ((double)a.nf * a.nf + (double)a.nc * a.nc) * nlaunch,
+    launch(STS_K_MG_DOWN, 8.0 * (2.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch,
            mg_down_kernel, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
   }
@@ -843,6 +865,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.bf = w.b[l];
     a.ec = w.e[l + 1];
     a.ef = w.e[l];
+    a.xp = w.xp[l];
     a.ntx = (a.nc + CX - 1) / CX;
     a.nty = (a.nc + CY - 1) / CY;
     a.nlaunch = nlaunch;
@@ -852,7 +875,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.sm = sm;
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
     a.max_tiles = w.max_tiles;
-    launch(STS_K_MG_UP, 8.0 * (2.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch, mg_up_kernel,
+    launch(STS_K_MG_UP, 8.0 * (3.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch, mg_up_kernel,
            dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
   }

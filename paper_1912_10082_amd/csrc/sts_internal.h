@@ -193,6 +193,7 @@ struct MGWork {
   MGPlan plan;
   double* b[kMGMaxLevels + 1];   // right-hand side per level; b[0] is the PCG residual r
   double* e[kMGMaxLevels + 1];   // V-cycle result per level; e[0] is z
+  double* xp[kMGMaxLevels + 1];  // pre-smoothed iterate per smoothed level (stride ld)
   int64_t ld[kMGMaxLevels + 1];  // column stride per level
   double* x;                     // solution columns (x + c * ldx)
   int64_t ldx;
