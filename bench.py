@@ -507,9 +507,10 @@ def main() -> int:
         if name == "residual":
             # ||[F1, Kx V, Mx V] B||: 2 Nh (p + 2k) Nt flops per launch on the FP64 matrix cores
             flops = 2.0 * w.nh * (2 + 2 * last["k"]) * w.nt * n
-        elif name == "mg_coarse":
+        elif name == "mg_coarse" and (_coarse_order(w.n[0]) + 1) not in (128, 256):
             # exact coarse solve as m x m GEMMs on the matrix cores (operands
-            # L2-resident, 2 m^3 flops per 24 m^2 algorithmic bytes per column)
+            # L2-resident, 2 m^3 flops per 24 m^2 algorithmic bytes per column);
+            # orders m = 127, 255 use fast sine transforms instead (memory-bound)
             m = _coarse_order(w.n[0])
             flops = by * m / 12.0
         if flops is not None:

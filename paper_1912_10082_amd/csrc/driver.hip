@@ -459,7 +459,7 @@ struct MGRunner {
     w.part_pq = w.part_rz + (size_t)w.max_tiles * kMaxCols;
     w.alpha = w.part_pq + (size_t)w.max_tiles * kMaxCols;
     const int m = plan.exact;
-    std::vector<double> tab((size_t)m * (m + 1));
+    std::vector<double> tab(mg_dst_table_size(m));
     mg_dst_table(m, tab.data());
     dst.alloc(tab.size() * 8);
     STS_HIP(hipMemcpy(dst.p, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));

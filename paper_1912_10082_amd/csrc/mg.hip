@@ -476,6 +476,135 @@ __global__ __launch_bounds__(64 * kDstWaves) void dst_gemm_kernel(DstGemmArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// coarse level with m + 1 = L a power of two (128 or 256): the same exact
+// solve, U = S [(S B S) / (mu (l_r + l_c))] S, by fast sine transforms.  The
+// raw transform y_k = sum_j x_j sin(pi j k / L) of a length-m vector is, up to
+// the factor -2i, the discrete Fourier transform of length N = 2L of its odd
+// extension (0, x_1 .. x_m, 0, -x_m .. -x_1); the transforms of two real
+// vectors x1, x2 come from one complex transform of x1 + i x2 (the transform
+// of each odd real sequence is imaginary): y1 = -Im(Z) / 2, y2 = Re(Z) / 2.
+// One work-group of L threads transforms two rows (or two columns) with a
+// radix-2 decimation-in-time FFT in LDS, one butterfly per thread per stage.
+// Three launches: rows (B S), columns (S . , the division, S .), rows (. S).
+// ---------------------------------------------------------------------------
+struct FstArgs {
+  int m;
+  int nlaunch;
+  int cols[kMaxCols];
+  const double* in;    // per column (stride in_ld), m x m row-major
+  int64_t in_ld;
+  double* out;
+  int64_t out_ld;
+  const double* lv;    // l_0 .. l_{m-1}
+  const double* tw;    // cos, sin of pi k / L, k < L
+  double mu;
+  const CGScal* st;
+};
+
+// In-place FFT of N = 2L complex values held in bit-reversed order.
+template <int L>
+__device__ __forceinline__ void fft_lds(double2* z, const double* tw) {
+  constexpr int N = 2 * L;
+  const int b = threadIdx.x;
+#pragma unroll
+  for (int h = 1; h < N; h <<= 1) {
+    const int j = b & (h - 1);
+    const int i0 = ((b - j) << 1) + j, i1 = i0 + h;
+    const int k = j * (L / h);                      // exp(-i pi j / h) = exp(-i pi k / L)
+    const double wr = tw[2 * k], wi = -tw[2 * k + 1];
+    const double2 a = z[i0], c = z[i1];
+    const double cr = c.x * wr - c.y * wi, ci = c.x * wi + c.y * wr;
+    z[i0] = double2{a.x + cr, a.y + ci};
+    z[i1] = double2{a.x - cr, a.y - ci};
+    __syncthreads();
+  }
+}
+
+template <int L>
+__device__ __forceinline__ int bitrev(int j) {
+  constexpr int bits = L == 128 ? 8 : 9;   // log2 (2 L)
+  return (int)(__brev((unsigned)j) >> (32 - bits));
+}
+
+// Load the odd extensions of two length-m vectors (x1[j - 1], x2[j - 1] read
+// through `get`) in bit-reversed order: thread t places entries t and t + L.
+template <int L, class Get>
+__device__ __forceinline__ void fst_load(double2* z, int m, Get get) {
+  const int t = threadIdx.x;
+  double2 v = double2{0.0, 0.0}, w = double2{0.0, 0.0};
+  if (t >= 1 && t <= m) v = get(t - 1);                         // z_t = x_t
+  if (t >= 1 && L - t <= m) {                                    // z_{L+t} = -x_{L-t}
+    const double2 u = get(L - t - 1);
+    w = double2{-u.x, -u.y};
+  }
+  z[bitrev<L>(t)] = v;
+  z[bitrev<L>(t + L)] = w;
+  __syncthreads();
+}
+
+template <int L>
+__global__ __launch_bounds__(L) void fst_row_kernel(FstArgs a) {
+  __shared__ double2 z[2 * L];
+  __shared__ double tw[2 * L];
+  const int col = a.cols[blockIdx.y];
+  if (a.st && !a.st[col].active) return;
+  const int m = a.m;
+  for (int i = threadIdx.x; i < 2 * L; i += L) tw[i] = a.tw[i];
+  const int r1 = 2 * blockIdx.x, r2 = r1 + 1;
+  const double* in = a.in + (size_t)col * a.in_ld;
+  double* out = a.out + (size_t)col * a.out_ld;
+  fst_load<L>(z, m, [&](int j) {
+    return double2{in[(size_t)r1 * m + j], r2 < m ? in[(size_t)r2 * m + j] : 0.0};
+  });
+  fft_lds<L>(z, tw);
+  const double sc = 0.5 * sqrt(2.0 / L);
+  const int k = threadIdx.x + 1;   // frequency 1 .. m
+  if (k <= m) {
+    const double2 Z = z[k];
+    out[(size_t)r1 * m + k - 1] = -Z.y * sc;
+    if (r2 < m) out[(size_t)r2 * m + k - 1] = Z.x * sc;
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(L) void fst_col_kernel(FstArgs a) {
+  __shared__ double2 z[2 * L];
+  __shared__ double tw[2 * L];
+  __shared__ double2 v[L];
+  const int col = a.cols[blockIdx.y];
+  if (a.st && !a.st[col].active) return;
+  const int m = a.m;
+  for (int i = threadIdx.x; i < 2 * L; i += L) tw[i] = a.tw[i];
+  const int c1 = 2 * blockIdx.x, c2 = c1 + 1;
+  const double* in = a.in + (size_t)col * a.in_ld;
+  double* out = a.out + (size_t)col * a.out_ld;
+  fst_load<L>(z, m, [&](int j) {
+    return double2{in[(size_t)j * m + c1], c2 < m ? in[(size_t)j * m + c2] : 0.0};
+  });
+  fft_lds<L>(z, tw);
+  const double sc = 0.5 * sqrt(2.0 / L);
+  const int t = threadIdx.x;
+  if (t < m) {
+    // frequency t + 1 along the rows; the columns already hold frequencies c1, c2
+    const double2 Z = z[t + 1];
+    const double lr = a.lv[t];
+    const double d1 = a.mu * (lr + a.lv[c1]);
+    const double d2 = c2 < m ? a.mu * (lr + a.lv[c2]) : 1.0;
+    v[t] = double2{-Z.y * sc / d1, c2 < m ? Z.x * sc / d2 : 0.0};
+  }
+  __syncthreads();
+  fst_load<L>(z, m, [&](int j) { return v[j]; });
+  fft_lds<L>(z, tw);
+  if (t < m) {
+    const double2 Z = z[t + 1];
+    out[(size_t)t * m + c1] = -Z.y * sc;
+    if (c2 < m) out[(size_t)t * m + c2] = Z.x * sc;
+  }
+}
+
+bool fst_supported(int m) { return m + 1 == 128 || m + 1 == 256; }
+
+// ---------------------------------------------------------------------------
 // PCG launches on the finest grid (tiles TX x TY)
 // ---------------------------------------------------------------------------
 struct PCGArgs {
@@ -773,7 +902,8 @@ int mg_max_tiles(const MGPlan& p) {
 }
 
 void mg_dst_table(int m, double* out) {
-  // S[y][x] = sqrt(2 / (m + 1)) sin(pi (y + 1)(x + 1) / (m + 1)); l_y = 2 - 2 cos(pi (y + 1) / (m + 1))
+  // S[y][x] = sqrt(2 / (m + 1)) sin(pi (y + 1)(x + 1) / (m + 1)); l_y = 2 - 2 cos(pi (y + 1) / (m + 1));
+  // then cos, sin of pi k / (m + 1), k <= m (the twiddles of the fast transform)
   const double pi = 3.14159265358979323846;
   const double s = std::sqrt(2.0 / (m + 1));
   for (int y = 0; y < m; ++y)
@@ -783,7 +913,14 @@ void mg_dst_table(int m, double* out) {
       out[y * m + x] = s * std::sin(pi * (double)num / (m + 1));
     }
   for (int y = 0; y < m; ++y) out[m * m + y] = 2.0 - 2.0 * std::cos(pi * (y + 1) / (m + 1));
+  double* tw = out + (size_t)m * (m + 1);
+  for (int k = 0; k <= m; ++k) {
+    tw[2 * k] = std::cos(pi * k / (m + 1));
+    tw[2 * k + 1] = std::sin(pi * k / (m + 1));
+  }
 }
+
+size_t mg_dst_table_size(int m) { return (size_t)m * (m + 1) + 2 * (size_t)(m + 1); }
 
 void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
                hipStream_t st) {
@@ -825,6 +962,37 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     c.max_tiles = w.max_tiles;
     launch(STS_K_MG_COARSE, 16.0 * c.n * c.n * nlaunch, mg_coarse_kernel, dim3(nlaunch), dim3(kCT),
            0, st, c);
+  } else if (fst_supported(p.n[L])) {
+    // e_L = S (S b_L S ./ (mu (l_r + l_c))) S by fast sine transforms
+    const int m = p.n[L];
+    FstArgs f{};
+    f.m = m;
+    f.nlaunch = nlaunch;
+    for (int j = 0; j < nlaunch; ++j) f.cols[j] = cols[j];
+    f.lv = w.dst + (size_t)m * m;
+    f.tw = w.dst + (size_t)m * (m + 1);
+    f.mu = p.mu;
+    f.st = act;
+    const int64_t ld = w.ld[L];
+    const dim3 grid((m + 1) / 2, nlaunch);
+    const double by = 16.0 * (double)m * m * nlaunch;   // read and write one m x m array
+    auto stage = [&](int kind, const double* in, double* out) {
+      f.in = in;
+      f.in_ld = ld;
+      f.out = out;
+      f.out_ld = ld;
+      if (m + 1 == 256) {
+        if (kind == 0) launch(STS_K_MG_COARSE, by, fst_row_kernel<256>, grid, dim3(256), 0, st, f);
+        else launch(STS_K_MG_COARSE, by, fst_col_kernel<256>, grid, dim3(256), 0, st, f);
+      } else {
+        if (kind == 0) launch(STS_K_MG_COARSE, by, fst_row_kernel<128>, grid, dim3(128), 0, st, f);
+        else launch(STS_K_MG_COARSE, by, fst_col_kernel<128>, grid, dim3(128), 0, st, f);
+      }
+      STS_HIP(hipGetLastError());
+    };
+    stage(0, w.b[L], w.t1);      // T = B S (rows)
+    stage(1, w.t1, w.t2);        // X = S (S T ./ D) (columns)
+    stage(0, w.t2, w.e[L]);      // e = X S (rows)
   } else {
     // e_L = S (S b_L S ./ (mu (l_r + l_c))) S, four GEMMs (L >= 1 here)
     const int m = p.n[L];

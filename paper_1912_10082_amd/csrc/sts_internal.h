@@ -183,6 +183,7 @@ struct MGPlan {
 // The m x m sine-transform matrix (row-major) followed by the m eigenvalues
 // 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.
 void mg_dst_table(int m, double* out);
+size_t mg_dst_table_size(int m);   // doubles written by mg_dst_table
 // True (and *plan filled) if Kx is the 2-D five-point P1 stiffness on a square
 // grid that halves, n -> (n-1)/2, down to at most kMGCoarseMax nodes.
 bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan);
