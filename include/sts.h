@@ -257,13 +257,15 @@ sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, doub
                       int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
                       void* stream);
 
-/* Mx X[:, c] = B[:, c] for c < ncols by Chebyshev iteration (the Mx^{-1}
- * applications of the extended Krylov space, Sec. 4; the solver is this
- * library's choice).  For the 2-D P1 mass matrix the spectrum of
- * diag(Mx)^{-1} Mx lies in [1/2, 2], so k steps guarantee
- * ||r|| <= 2 (1/3)^k ||b||; k is the smallest count meeting rtol (at most
- * 64) and is written to iters (host, may be NULL).  Only STS_FE_P1_2D spaces
- * (else STS_E_INVALID).  B, X: Nh x ncols (ldb, ldx), device, ncols <= 8. */
+/* Mx X[:, c] = B[:, c] for c < ncols (the Mx^{-1} applications of the
+ * extended Krylov space, Sec. 4; the solvers are this library's choice).
+ * 2-D P1: Chebyshev iteration -- the spectrum of diag(Mx)^{-1} Mx lies in
+ * [1/2, 2], so k steps guarantee ||r|| <= 2 (1/3)^k ||b||; k is the smallest
+ * count meeting rtol (at most 64) and is written to iters (host, may be NULL).
+ * 3-D trilinear (cubic grids): Mx = (h/6)^3 T (x) T (x) T, T = tridiag(1, 4, 1),
+ * solved directly by three passes of tridiagonal solves along the grid lines
+ * (iters = 1).  Other spaces: STS_E_INVALID.  B, X: Nh x ncols (ldb, ldx),
+ * device, ncols <= 8; for the 3-D solve X may equal B. */
 sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, double* X,
                           int64_t ldx, int32_t ncols, double rtol, int32_t* iters,
                           void* stream);

@@ -536,6 +536,8 @@ struct sts_problem {
   bool mass_cheb = false;   // Mx solves by Chebyshev iteration
   bool tri_ok = false;      // 1-D: direct tridiagonal solves for Kx and Mx
   DevBuf tri_fac;           // their elimination factors (4 Nh)
+  bool tensor_mass = false; // 3-D trilinear mass: direct tensor-product Mx solves
+  DevBuf tmass_fac;         // elimination factors of tridiag(1, 4, 1) (2 n)
   MGPlan mg_plan_{};
   std::unique_ptr<MGRunner> mg;
   // kernel timing of the last profiled solve
@@ -850,6 +852,35 @@ void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const
     P->alg_bytes += 32.0 * P->nh * ncols;
     return;
   }
+  if (o.inner_precond != 0 && P->tensor_mass) {
+    // 3-D trilinear mass: Mx columns directly, Kx columns by CG
+    int nm = 0, nk = 0;
+    for (int c = 0; c < ncols; ++c)
+      if (ops[c] == STS_OP_M) perm[nm++] = c;
+    for (int c = 0; c < ncols; ++c)
+      if (ops[c] == STS_OP_K) perm[nm + nk++] = c;
+    const double* b2[kMaxCols];
+    for (int j = 0; j < ncols; ++j) b2[j] = b[perm[j]];
+    if (nm > 0) {
+      tensor_mass_solve(P->grid, P->M, nm, b2, x0, P->ldv, P->tmass_fac.d(), P->stream);
+      P->inner_M += nm;
+      P->alg_bytes += 48.0 * P->nh * nm;
+    }
+    if (nk > 0) {
+      int ops2[kMaxCols];
+      for (int j = 0; j < nk; ++j) ops2[j] = STS_OP_K;
+      CGScal out[kMaxCols];
+      P->cg.w.x = x0 + nm * P->ldv;
+      P->cg.w.ld = P->ldv;
+      P->cg.run(ops2, nk, b2 + nm, o.inner_rtol, o.inner_maxit, out, P->stream);
+      for (int j = 0; j < nk; ++j) {
+        check_inner(out[j]);
+        P->inner_K += out[j].iters;
+        P->alg_bytes += (48.0 * out[j].iters + 32.0) * P->nh;
+      }
+    }
+    return;
+  }
   const bool use_mg = o.inner_precond != 0 && P->mg_ok;
   int nm = 0, nk = 0;
   if (use_mg) {
@@ -1031,6 +1062,7 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   MGPlan plan{};
   if (mg_plan(g, K, &plan)) b += 9 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
   if (tridiag_supported(g, K, M)) b += 4 * g.nh * 8;
+  if (tensor_mass_supported(g, M)) b += 2 * g.nx * 8;
   return b + (1 << 20);                                            // small scratch
 }
 
@@ -1172,6 +1204,11 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     STS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->pinned), 64 * 8, hipHostMallocDefault));
     P->mg_ok = mg_plan(g, P->K, &P->mg_plan_);
     P->mass_cheb = mass_cheb_supported(g, P->M);
+    P->tensor_mass = tensor_mass_supported(g, P->M);
+    if (P->tensor_mass) {
+      P->tmass_fac.alloc(2 * g.nx * 8);
+      tensor_mass_factor(g.nx, P->tmass_fac.d(), st);
+    }
     P->tri_ok = tridiag_supported(g, P->K, P->M);
     if (P->tri_ok) {
       P->tri_fac.alloc(4 * g.nh * 8);
@@ -1688,13 +1725,24 @@ sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, 
     validate_space(space);
     const Grid g = make_grid(*space);
     const Stencil M = make_stencil(*space, STS_OP_M);
-    STS_REQUIRE(mass_cheb_supported(g, M), STS_E_INVALID,
-                "Chebyshev mass solve needs a 2-D P1 space");
     STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
     STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
     STS_REQUIRE(rtol > 0.0 && rtol < 1.0, STS_E_INVALID, "rtol must be in (0, 1)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     Scratch sc;
+    if (tensor_mass_supported(g, M)) {
+      double* fac = sc.get<double>(2 * g.nx);
+      tensor_mass_factor(g.nx, fac, st);
+      const double* bc[kMaxCols];
+      for (int c = 0; c < ncols; ++c) bc[c] = B + c * ldb;
+      tensor_mass_solve(g, M, ncols, bc, X, ldx, fac, st);
+      STS_HIP(hipStreamSynchronize(st));
+      if (iters)
+        for (int c = 0; c < ncols; ++c) iters[c] = 1;
+      return;
+    }
+    STS_REQUIRE(mass_cheb_supported(g, M), STS_E_INVALID,
+                "mass solve needs a 2-D P1 or a 3-D trilinear space");
     const int64_t ld = pad_ld(g.nh);
     double* xb[2] = {sc.get<double>(ld * ncols), sc.get<double>(ld * ncols)};
     double* db[2] = {sc.get<double>(ld * ncols), sc.get<double>(ld * ncols)};

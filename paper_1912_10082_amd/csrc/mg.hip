@@ -40,6 +40,7 @@
 
 #include <cmath>
 
+#include "fst.h"
 #include "sts_internal.h"
 
 namespace sts {
@@ -500,47 +501,6 @@ struct FstArgs {
   double mu;
   const CGScal* st;
 };
-
-// In-place FFT of N = 2L complex values held in bit-reversed order.
-template <int L>
-__device__ __forceinline__ void fft_lds(double2* z, const double* tw) {
-  constexpr int N = 2 * L;
-  const int b = threadIdx.x;
-#pragma unroll
-  for (int h = 1; h < N; h <<= 1) {
-    const int j = b & (h - 1);
-    const int i0 = ((b - j) << 1) + j, i1 = i0 + h;
-    const int k = j * (L / h);                      // exp(-i pi j / h) = exp(-i pi k / L)
-    const double wr = tw[2 * k], wi = -tw[2 * k + 1];
-    const double2 a = z[i0], c = z[i1];
-    const double cr = c.x * wr - c.y * wi, ci = c.x * wi + c.y * wr;
-    z[i0] = double2{a.x + cr, a.y + ci};
-    z[i1] = double2{a.x - cr, a.y - ci};
-    __syncthreads();
-  }
-}
-
-template <int L>
-__device__ __forceinline__ int bitrev(int j) {
-  constexpr int bits = L == 128 ? 8 : 9;   // log2 (2 L)
-  return (int)(__brev((unsigned)j) >> (32 - bits));
-}
-
-// Load the odd extensions of two length-m vectors (x1[j - 1], x2[j - 1] read
-// through `get`) in bit-reversed order: thread t places entries t and t + L.
-template <int L, class Get>
-__device__ __forceinline__ void fst_load(double2* z, int m, Get get) {
-  const int t = threadIdx.x;
-  double2 v = double2{0.0, 0.0}, w = double2{0.0, 0.0};
-  if (t >= 1 && t <= m) v = get(t - 1);                         // z_t = x_t
-  if (t >= 1 && L - t <= m) {                                    // z_{L+t} = -x_{L-t}
-    const double2 u = get(L - t - 1);
-    w = double2{-u.x, -u.y};
-  }
-  z[bitrev<L>(t)] = v;
-  z[bitrev<L>(t + L)] = w;
-  __syncthreads();
-}
 
 template <int L>
 __global__ __launch_bounds__(L) void fst_row_kernel(FstArgs a) {

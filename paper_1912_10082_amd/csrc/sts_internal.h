@@ -403,6 +403,14 @@ void tridiag_shifted_solve(const Grid& g, const Stencil& K, const Stencil& M, do
                            int64_t ldw, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// direct Mx solves for the 3-D trilinear (tensor-product) mass, tensor_mass.hip
+// ---------------------------------------------------------------------------
+bool tensor_mass_supported(const Grid& g, const Stencil& M);
+void tensor_mass_factor(int n, double* fac, hipStream_t st);   // fac: 2 n doubles
+void tensor_mass_solve(const Grid& g, const Stencil& M, int ncols, const double* const* b,
+                       double* x, int64_t ldx, const double* fac, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // problem hooks for the executors (pool.hip)
 // ---------------------------------------------------------------------------
 // Run f, mapping library exceptions to a status and the calling thread's

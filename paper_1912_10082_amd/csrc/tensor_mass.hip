@@ -1,0 +1,124 @@
+// Direct Mx solves for the 3-D trilinear mass matrix.
+//
+// The Q1 mass matrix of Sec. 3 on the uniform grid is the tensor product of
+// three 1-D mass matrices, Mx = (h/6)^3 T (x) T (x) T with T = tridiag(1, 4, 1),
+// so Mx^{-1} = (6/h)^3 T^{-1} (x) T^{-1} (x) T^{-1}: three passes, each solving
+// T y = x along every grid line of one direction (elimination without
+// pivoting; T is strictly diagonally dominant).  The elimination factors of T
+// depend only on the line length and are computed once per problem.  One
+// thread per line; lines along y and z are read and written coalesced across
+// threads, lines along x with stride n.
+#include <hip/hip_runtime.h>
+
+#include "sts_internal.h"
+
+namespace sts {
+
+namespace {
+
+// fac: c (n) | m (n) of T = tridiag(1, 4, 1): m_0 = 1/4, m_i = 1 / (4 - c_{i-1}), c_i = m_i.
+__global__ void tensor_factor_kernel(int n, double* fac) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double cp = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double mi = 1.0 / (4.0 - cp);
+    cp = mi;
+    fac[i] = cp;
+    fac[n + i] = mi;
+  }
+}
+
+struct TensorArgs {
+  int n;
+  int axis;              // 0: x, 1: y, 2: z
+  int ncols;
+  const double* in[kMaxCols];
+  double* out[kMaxCols];
+  const double* fac;
+  double scale;          // 6 / h, applied once per pass
+};
+
+__global__ __launch_bounds__(256) void tensor_mass_kernel(TensorArgs a) {
+  const int n = a.n;
+  const int64_t lines = (int64_t)n * n;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (gid >= lines || c >= a.ncols) return;
+  int64_t base, stride;
+  if (a.axis == 0) {
+    base = gid * n;
+    stride = 1;
+  } else if (a.axis == 1) {
+    const int64_t z = gid / n, x = gid % n;
+    base = z * n * n + x;
+    stride = n;
+  } else {
+    base = gid;
+    stride = lines;
+  }
+  const double* in = a.in[c] + base;
+  double* out = a.out[c] + base;
+  const double* cf = a.fac;
+  const double* mf = a.fac + n;
+  double y = 0.0;
+  for (int i = 0; i < n; ++i) {
+    y = (a.scale * in[i * stride] - y) * mf[i];
+    out[i * stride] = y;
+  }
+  double z = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    z = out[i * stride] - cf[i] * z;
+    out[i * stride] = z;
+  }
+}
+
+}  // namespace
+
+bool tensor_mass_supported(const Grid& g, const Stencil& M) {
+  if (g.dim != 3 || g.nx != g.ny || g.nx != g.nz) return false;
+  const double s = M.c[13] / 64.0;   // centre = s 4^3
+  if (!(s > 0.0)) return false;
+  const double w[3] = {1.0, 4.0, 1.0};
+  for (int dz = 0; dz < 3; ++dz)
+    for (int dy = 0; dy < 3; ++dy)
+      for (int dx = 0; dx < 3; ++dx) {
+        const double want = s * w[dx] * w[dy] * w[dz];
+        const double got = M.c[(dz * 3 + dy) * 3 + dx];
+        if (std::fabs(got - want) > 1e-14 * s * 64.0) return false;
+      }
+  return true;
+}
+
+void tensor_mass_factor(int n, double* fac, hipStream_t st) {
+  tensor_factor_kernel<<<1, 64, 0, st>>>(n, fac);
+  STS_HIP(hipGetLastError());
+}
+
+void tensor_mass_solve(const Grid& g, const Stencil& M, int ncols, const double* const* b,
+                       double* x, int64_t ldx, const double* fac, hipStream_t st) {
+  STS_REQUIRE(ncols >= 0 && ncols <= kMaxCols, STS_E_INVALID, "tensor mass solve: 0..8 columns");
+  if (ncols == 0) return;
+  const int n = g.nx;
+  // Mx = s (4^3) ... with s = (h/6)^3: the per-pass factor is s^{-1/3} = 6 / h
+  const double s = M.c[13] / 64.0;
+  TensorArgs a{};
+  a.n = n;
+  a.ncols = ncols;
+  a.fac = fac;
+  a.scale = 1.0 / std::cbrt(s);
+  const int64_t lines = (int64_t)n * n;
+  const dim3 grid((unsigned)((lines + 255) / 256), (unsigned)ncols);
+  for (int axis = 0; axis < 3; ++axis) {
+    a.axis = axis;
+    for (int c = 0; c < ncols; ++c) {
+      a.in[c] = axis == 0 ? b[c] : x + c * ldx;
+      a.out[c] = x + c * ldx;
+    }
+    // read and write every node once per pass
+    launch(STS_K_MASS_CHEB, 16.0 * (double)g.nh * ncols, tensor_mass_kernel, grid, dim3(256), 0,
+           st, a);
+    STS_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace sts
