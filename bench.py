@@ -161,17 +161,25 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
 
 
 def cpu_baseline(w, U_gpu_cols, sample_steps):
-    """Oracle Crank-Nicolson on the first `sample_steps` intervals (1 core)."""
+    """The oracle on the first `sample_steps` intervals (1 core): Crank-Nicolson
+    in 2-D, the sine-mode exact solve in 3-D (a sparse factorisation of a
+    255^3 step matrix does not fit a bounded sample)."""
     import numpy as np
 
     from oracle import exact, fem
     import workloads as wl
 
-    K, M = fem.spatial_operators(w.dim, w.n[0], w.mu)
     Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
-    t0 = time.perf_counter()
-    U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2, steps=sample_steps)
-    secs = time.perf_counter() - t0
+    S = sample_steps
+    if w.dim == 3:
+        t0 = time.perf_counter()
+        U = exact.modal_solve_3d(w.n[0], w.mu, Dt[:S, :S], Mt[:S, :S], w.F1, w.F2[:S])
+        secs = time.perf_counter() - t0
+    else:
+        K, M = fem.spatial_operators(w.dim, w.n[0], w.mu)
+        t0 = time.perf_counter()
+        U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2, steps=S)
+        secs = time.perf_counter() - t0
     err = float(np.linalg.norm(U_gpu_cols - U) / np.linalg.norm(U))
     return secs, err
 
@@ -399,10 +407,11 @@ def bench_serve(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=511, help="interior nodes per direction")
-    ap.add_argument("--nt", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=None, help="timed solves (heat2d: 50, heat3d: 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed solves (heat2d: 2, heat3d: 1)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="interior nodes per direction (heat2d: 511, heat3d: 255)")
+    ap.add_argument("--nt", type=int, default=None, help="time steps (heat2d: 1024, heat3d: 4096)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--sample-steps", type=int, default=48,
                     help="Crank-Nicolson steps of the CPU baseline / error gate")
@@ -411,10 +420,12 @@ def main() -> int:
                     help="skip the profiled solves (no roofline / kernels table)")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="extra solves with per-dispatch events for the kernel table")
-    ap.add_argument("--workload", choices=("heat2d", "batch2d", "serve"), default="heat2d",
-                    help="heat2d: the 511^2 x 1024 solve (default); batch2d: 256 uneven "
-                         "2-D problems through the batch executor; serve: Poisson arrivals "
-                         "of mixed 1-D / 2-D / 3-D requests through the request server")
+    ap.add_argument("--workload", choices=("heat2d", "heat3d", "batch2d", "serve"),
+                    default="heat2d",
+                    help="heat2d: the 511^2 x 1024 solve (default); heat3d: the 255^3 x 4096 "
+                         "rank-4 solve in FP64; batch2d: 256 uneven 2-D problems through the "
+                         "batch executor; serve: Poisson arrivals of mixed 1-D / 2-D / 3-D "
+                         "requests through the request server")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window")
@@ -425,6 +436,19 @@ def main() -> int:
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "MIB"),
                     help="only write the HBM traffic file from rocprofv3 counter runs")
     args = ap.parse_args()
+    d3 = args.workload == "heat3d"
+    if args.n is None:
+        args.n = 255 if d3 else 511
+    if args.nt is None:
+        args.nt = 4096 if d3 else 1024
+    if args.steps is None:
+        args.steps = 3 if d3 else 50
+    if args.warmup is None:
+        args.warmup = 1 if d3 else 2
+    if d3 and args.profile_steps == 3:
+        args.profile_steps = 1
+    if d3 and args.sample_steps == 48:
+        args.sample_steps = 8
     if args.summarize_pmc:
         f, wr, cf, cw, mib = args.summarize_pmc
         return summarize_pmc(f, wr, cf, cw, int(mib), TRAFFIC_FILE)
@@ -447,13 +471,16 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = wl.heat_2d_bumps(n=args.n, nt=args.nt, p=2, seed=2)
+    if d3:
+        w = wl.heat_3d_separable(n=args.n, nt=args.nt, p=4, seed=3)
+    else:
+        w = wl.heat_2d_bumps(n=args.n, nt=args.nt, p=2, seed=2)
     t = wl.time_grid(w.nt, w.T)
     dd, ds, md, ms = sts.time_matrices(t)
     F1 = torch.from_numpy(np.asarray(w.F1)).cuda()
     F2 = torch.from_numpy(np.asarray(w.F2)).cuda()
     torch.cuda.synchronize()
-    prob = sts.Problem(2, w.n[0], w.mu, (dd, ds), (md, ms), F1, F2)
+    prob = sts.Problem(w.dim, w.n[0], w.mu, (dd, ds), (md, ms), F1, F2)
     opts = dict(tol=args.tol, restart=1, max_outer=150)
     for i in range(args.warmup):
         info = prob.solve(**opts)
@@ -507,7 +534,7 @@ def main() -> int:
         if name == "residual":
             # ||[F1, Kx V, Mx V] B||: 2 Nh (p + 2k) Nt flops per launch on the FP64 matrix cores
             flops = 2.0 * w.nh * (2 + 2 * last["k"]) * w.nt * n
-        elif name == "mg_coarse" and (_coarse_order(w.n[0]) + 1) not in (128, 256):
+        elif name == "mg_coarse" and not d3 and (_coarse_order(w.n[0]) + 1) not in (128, 256):
             # exact coarse solve as m x m GEMMs on the matrix cores (operands
             # L2-resident, 2 m^3 flops per 24 m^2 algorithmic bytes per column);
             # orders m = 127, 255 use fast sine transforms instead (memory-bound)
@@ -537,11 +564,15 @@ def main() -> int:
         cores = 1
         secs, err = cpu_baseline(w, U_cols, S)
         gate = gate and err <= 1e-8
+        if d3:
+            sample = (f"first {S} of {w.nt} steps of the same {w.n[0]}^3 x {w.nt} problem by the "
+                      f"oracle's sine-mode solve ({secs:.1f} s, single-threaded SciPy FFTs)")
+        else:
+            sample = (f"first {S} of {w.nt} Crank-Nicolson steps of the same {w.n[0]}^2 x "
+                      f"{w.nt} problem (SuperLU factorisation once + {S} solves, "
+                      f"{secs:.1f} s, single-threaded SciPy)")
         cpu = {"value": w.nh * S / secs, "unit": "dof/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {S} of {w.nt} Crank-Nicolson steps of the same {w.n[0]}^2 x "
-                         f"{w.nt} problem (SuperLU factorisation once + {S} solves, "
-                         f"{secs:.1f} s, single-threaded SciPy)",
-               "seconds": secs}
+               "sample": sample, "seconds": secs}
     lat_ms = sorted(1e3 * x for x in lat)
     out = {
         "metric": METRIC,
@@ -556,8 +587,10 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"heat2d_p1_courant_{w.n[0]}x{w.n[0]}_nt{w.nt}_rank2_tol{args.tol:g}",
-                   "nh": w.nh, "nt": w.nt, "p": 2, "tol": args.tol, "seed": 2},
+        "config": ({"workload": f"heat3d_q1_7pt_{w.n[0]}^3_nt{w.nt}_rank4_tol{args.tol:g}",
+                    "nh": w.nh, "nt": w.nt, "p": 4, "tol": args.tol, "seed": 3} if d3 else
+                   {"workload": f"heat2d_p1_courant_{w.n[0]}x{w.n[0]}_nt{w.nt}_rank2_tol{args.tol:g}",
+                    "nh": w.nh, "nt": w.nt, "p": 2, "tol": args.tol, "seed": 2}),
         "latency_ms": {"p50": lat_ms[len(lat_ms) // 2],
                        "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
         "gate_passed": bool(gate),

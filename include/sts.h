@@ -249,10 +249,15 @@ sts_status sts_cg(const sts_space* space, const int32_t* ops, const double* B, i
  * with one geometric multigrid V-cycle (the inner Kx^{-1} applications of
  * the extended Krylov space, Sec. 4; the preconditioner is this library's
  * choice, not the paper's).  X0 = 0; stops when ||r|| <= rtol ||b|| or after
- * maxit iterations.  Only for STS_FE_P1_2D spaces with n <= 63, or n odd
- * halving, n -> (n-1)/2 (odd at every step), at least once and down to at
- * most 255 (e.g. 1023, 511, 255, 127, 95); else STS_E_INVALID.  B: Nh x ncols (ldb), X: Nh x ncols (ldx), device.  iters
- * (host, may be NULL) as for sts_cg.  ncols <= 8.  Same errors as sts_cg. */
+ * maxit iterations.  Spaces (else STS_E_INVALID):
+ *  - STS_FE_P1_2D with n <= 63, or n odd halving, n -> (n-1)/2 (odd at every
+ *    step), at least once and down to at most 255 (e.g. 1023, 511, 255, 127,
+ *    95);
+ *  - STS_FE_Q1_3D_7PT (seven-point stiffness) with n <= 63 (the V-cycle is then
+ *    the exact solve), or n odd halving down to at most 63 (e.g. 511, 255,
+ *    127, 95).
+ * B: Nh x ncols (ldb), X: Nh x ncols (ldx), device.  iters (host, may be
+ * NULL) as for sts_cg.  ncols <= 8.  Same errors as sts_cg. */
 sts_status sts_pcg_mg(const sts_space* space, const double* B, int64_t ldb, double* X,
                       int64_t ldx, int32_t ncols, double rtol, int32_t maxit, int32_t* iters,
                       void* stream);
@@ -271,11 +276,12 @@ sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, 
                           void* stream);
 
 /* The preconditioner of sts_pcg_mg: Z[:, c] = Bmg R[:, c], one V-cycle from
- * zero (three Chebyshev smoothing steps for the interval [1/2, 2] of the
- * spectrum of diag(Kx)^{-1} Kx before and after each coarse correction; P1
- * interpolation and its transpose between the nested meshes; the coarsest
- * level solved exactly by the discrete sine transform).  Bmg is symmetric
- * positive definite.
+ * zero: Chebyshev smoothing before and after each coarse correction (2-D:
+ * three steps for the interval [1/2, 2] of the spectrum of diag(Kx)^{-1} Kx;
+ * 3-D: two steps for [1/3, 2]); P1 interpolation and its transpose between
+ * the nested meshes (3-D: of the Kuhn triangulation, whose P1 stiffness is
+ * the seven-point stencil); the coarsest level solved exactly by the discrete
+ * sine transform.  Bmg is symmetric positive definite.
  * Same spaces as sts_pcg_mg.  R: Nh x ncols (ldr), Z: Nh x ncols (ldz),
  * device, ncols <= 8. */
 sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,

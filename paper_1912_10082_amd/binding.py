@@ -378,7 +378,7 @@ def cg(space: Space, ops, B, rtol: float = 1e-12, maxit: int = 200000, check: bo
 
 
 def pcg_mg(space: Space, B, rtol: float = 1e-12, maxit: int = 1000, check: bool = True):
-    """Kx X = B by multigrid-preconditioned CG (2-D P1 spaces whose n halves)."""
+    """Kx X = B by multigrid-preconditioned CG (2-D P1 and 3-D seven-point spaces whose n halves)."""
     B, pb, ldb = dev_colmajor(B)
     X = dev_zeros(B.shape[0], B.shape[1])
     its = (C.c_int32 * B.shape[1])()
@@ -390,7 +390,7 @@ def pcg_mg(space: Space, B, rtol: float = 1e-12, maxit: int = 1000, check: bool 
 
 
 def mass_solve(space: Space, B, rtol: float = 1e-13):
-    """Mx X = B by Chebyshev iteration (2-D P1); returns (X, iterations)."""
+    """Mx X = B: Chebyshev iteration (2-D P1) or direct line solves (3-D trilinear); returns (X, iterations)."""
     B, pb, ldb = dev_colmajor(B)
     X = dev_zeros(B.shape[0], B.shape[1])
     its = (C.c_int32 * B.shape[1])()

@@ -418,17 +418,23 @@ struct MGRunner {
   // Allocate for the plan; x / ldx are set per run.
   void setup(const MGPlan& plan) {
     w.plan = plan;
+    const bool d3 = plan.dim == 3;
+    auto nodes = [&](int l) {
+      const int64_t n = plan.n[l];
+      return d3 ? n * n * n : n * n;
+    };
+    for (int l = 0; l <= plan.nlev; ++l) w.ld[l] = pad_ld(nodes(l));
+    // per smoothed level l >= 1: b, e, the pre-smoothed iterate and, in 3-D,
+    // the two post-smoothing buffers; the exact level: b, e and temporaries
     int64_t tot = 0;
     for (int l = 1; l <= plan.nlev; ++l) {
-      w.ld[l] = pad_ld((int64_t)plan.n[l] * plan.n[l]);
       tot += 2 * w.ld[l] * kMaxCols;
-      if (l < plan.nlev) tot += w.ld[l] * kMaxCols;   // pre-smoothed iterate
+      if (l < plan.nlev) tot += (d3 ? 3 : 1) * w.ld[l] * kMaxCols;
     }
-    const bool big = plan.exact > kMGCoarseMax;
-    if (big) tot += 2 * w.ld[plan.nlev] * kMaxCols;
-    w.ld[0] = pad_ld((int64_t)plan.n[0] * plan.n[0]);
+    const int ntmp = d3 ? 1 : (plan.exact > kMGCoarseMax ? 2 : 0);
+    tot += ntmp * w.ld[plan.nlev] * kMaxCols;
     levels.alloc(std::max<int64_t>(tot, 1) * 8);
-    vecs.alloc(6 * w.ld[0] * kMaxCols * 8);
+    vecs.alloc((d3 ? 7 : 6) * w.ld[0] * kMaxCols * 8);
     double* q = levels.d();
     for (int l = 1; l <= plan.nlev; ++l) {
       w.b[l] = q;
@@ -437,12 +443,15 @@ struct MGRunner {
       if (l < plan.nlev) {
         w.xp[l] = q;
         q += w.ld[l] * kMaxCols;
+        if (d3) {
+          w.u1[l] = q;
+          w.d0[l] = q + w.ld[l] * kMaxCols;
+          q += 2 * w.ld[l] * kMaxCols;
+        }
       }
     }
-    if (big) {
-      w.t1 = q;
-      w.t2 = q + w.ld[plan.nlev] * kMaxCols;
-    }
+    if (ntmp > 0) w.t1 = q;
+    if (ntmp > 1) w.t2 = q + w.ld[plan.nlev] * kMaxCols;
     double* v = vecs.d();
     w.b[0] = v;
     w.e[0] = v + 1 * w.ld[0] * kMaxCols;
@@ -450,6 +459,11 @@ struct MGRunner {
     w.p[1] = v + 3 * w.ld[0] * kMaxCols;
     w.q = v + 4 * w.ld[0] * kMaxCols;
     w.xp[0] = v + 5 * w.ld[0] * kMaxCols;
+    if (d3) {
+      // q is free while the V-cycle runs (the iteration's A launch rewrites it)
+      w.u1[0] = w.q;
+      w.d0[0] = v + 6 * w.ld[0] * kMaxCols;
+    }
     w.max_tiles = mg_max_tiles(plan);
     scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
     w.scal = static_cast<CGScal*>(scal.p);
@@ -472,6 +486,7 @@ struct MGRunner {
   // reads b_l, that iterate and e_{l+1} and writes e_l, the coarse launch reads b_L and writes e_L, A reads z, p and
   // writes p, q, B reads x, p, r, q and writes x, r.
   double bytes_per_node() const {
+    if (w.plan.dim == 3) return mg3_bytes_per_node(w.plan);
     const double n0 = (double)w.plan.n[0] * w.plan.n[0];
     double b = 80.0 * n0;
     for (int l = 0; l < w.plan.nlev; ++l) {
@@ -838,6 +853,22 @@ void ritz_values(sts_problem* P, int64_t k, std::vector<double>& out) {
   for (double v : out) STS_REQUIRE(std::isfinite(v), STS_E_NUMERIC, "Ritz values not finite");
 }
 
+// Kx x_j = b[j] for j < nk by multigrid-preconditioned CG, x_j at x + j * ldv.
+void run_mg_k(sts_problem* P, int nk, const double* const* b, double* x, const sts_opts& o) {
+  if (!P->mg) {
+    P->mg = std::make_unique<MGRunner>();
+    P->mg->setup(P->mg_plan_);
+  }
+  CGScal out[kMaxCols];
+  P->mg->run(x, P->ldv, nk, b, o.inner_rtol, o.inner_maxit, out, P->stream);
+  const double bpn = P->mg->bytes_per_node();
+  for (int j = 0; j < nk; ++j) {
+    check_inner(out[j]);
+    P->inner_K += out[j].iters;
+    P->alg_bytes += (bpn * (out[j].iters + 1) + 40.0) * P->nh;
+  }
+}
+
 void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const* b,
                   const sts_opts& o, int* perm) {
   for (int c = 0; c < ncols; ++c) perm[c] = c;
@@ -853,7 +884,8 @@ void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const
     return;
   }
   if (o.inner_precond != 0 && P->tensor_mass) {
-    // 3-D trilinear mass: Mx columns directly, Kx columns by CG
+    // 3-D trilinear mass: Mx columns directly, Kx columns by multigrid PCG
+    // (plain CG on grids that do not halve)
     int nm = 0, nk = 0;
     for (int c = 0; c < ncols; ++c)
       if (ops[c] == STS_OP_M) perm[nm++] = c;
@@ -866,7 +898,9 @@ void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const
       P->inner_M += nm;
       P->alg_bytes += 48.0 * P->nh * nm;
     }
-    if (nk > 0) {
+    if (nk > 0 && P->mg_ok) {
+      run_mg_k(P, nk, b2 + nm, x0 + nm * P->ldv, o);
+    } else if (nk > 0) {
       int ops2[kMaxCols];
       for (int j = 0; j < nk; ++j) ops2[j] = STS_OP_K;
       CGScal out[kMaxCols];
@@ -920,20 +954,9 @@ void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const
     }
   }
   if (use_mg && nk > 0) {
-    if (!P->mg) {
-      P->mg = std::make_unique<MGRunner>();
-      P->mg->setup(P->mg_plan_);
-    }
     const double* b2[kMaxCols];
     for (int j = 0; j < nk; ++j) b2[j] = b[perm[nm + j]];
-    CGScal out[kMaxCols];
-    P->mg->run(x0 + nm * P->ldv, P->ldv, nk, b2, o.inner_rtol, o.inner_maxit, out, P->stream);
-    const double bpn = P->mg->bytes_per_node();
-    for (int j = 0; j < nk; ++j) {
-      check_inner(out[j]);
-      P->inner_K += out[j].iters;
-      P->alg_bytes += (bpn * (out[j].iters + 1) + 40.0) * P->nh;
-    }
+    run_mg_k(P, nk, b2, x0 + nm * P->ldv, o);
   }
 }
 
@@ -1017,7 +1040,7 @@ MGPlan require_mg(const sts_space* space, Grid* g) {
   *g = make_grid(*space);
   MGPlan plan{};
   STS_REQUIRE(mg_plan(*g, make_stencil(*space, STS_OP_K), &plan), STS_E_INVALID,
-              "multigrid needs a 2-D P1 space whose n halves, n -> (n-1)/2, down to <= 63");
+              "multigrid needs a 2-D P1 or 3-D seven-point space whose n halves, n -> (n-1)/2, down to <= 63");
   return plan;
 }
 

@@ -41,11 +41,14 @@
 #include <cmath>
 
 #include "fst.h"
+#include "mg_common.h"
 #include "sts_internal.h"
 
 namespace sts {
 
 namespace {
+
+using namespace mgc;
 
 constexpr int kT = 256;          // threads per work-group of the level and PCG kernels
 constexpr int CX = 32, CY = 8;   // coarse nodes per level-kernel tile (fine footprint 64 x 16)
@@ -53,36 +56,9 @@ constexpr int TX = 64, TY = 16;  // fine nodes per PCG-kernel tile
 constexpr int kNu = kMGNu;       // smoothing steps
 constexpr int kCT = 1024;        // threads of the coarse kernel
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Consecutive block ids go round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so that halo neighbours share an L2.
-__device__ __forceinline__ int xcd_remap(int bid, int n) {
-  const int q = n >> 3, rem = n & 7;
-  const int x = bid & 7, j = bid >> 3;
-  return x * q + min(x, rem) + j;
-}
-
 // mu (4 u - u_W - u_E - u_S - u_N) on an LDS array of row width W.
 __device__ __forceinline__ double k5(const double* s, int q, int W, double mu) {
   return mu * (4.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - W] + s[q + W]));
-}
-
-// Sum over the work-group (fixed order); every thread gets the result.
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) s += red[w];
-  __syncthreads();
-  return s;
 }
 
 // P1 interpolation at fine node (gx, gy) from a coarse array with origin
@@ -99,13 +75,6 @@ __device__ __forceinline__ double interp(const double* ec, int CW, int cox, int 
   if (odx) return 0.5 * (c[0] + c[CW]);       // vertical edge
   return 0.5 * (c[0] + c[CW + 1]);            // SW-NE diagonal edge
 }
-
-// Chebyshev smoothing coefficients: d_0 = c_0 r_0 / D and, for k >= 1,
-// d_k = a_k d_{k-1} + c_k r_k / D with r_k = b - K u_k; u_{k+1} = u_k + d_k.
-struct Smooth {
-  double a[kNu];
-  double c[kNu];
-};
 
 // An LDS region of W x H fine nodes with global origin (ox, oy) on an n x n
 // grid; `shrink` excludes a band at the region's edge (where neighbours are
@@ -311,14 +280,6 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
 // coarse level (n <= kMGCoarseMax): exact solve by the sine transform, four
 // 64 x 64 GEMMs on the matrix cores in LDS, one work-group per column
 // ---------------------------------------------------------------------------
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-// v_mfma_f64_16x16x4f64: lane l = i + 16 g supplies a = X[i][g] and
-// b = Y[g][i]; element q of the accumulator is (X Y)[4 q + g][i].
-__device__ __forceinline__ d4 mfma(double x, double y, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
-}
-
 constexpr int kE = 64;        // padded order of the exact solve
 constexpr int kEL = kE + 1;   // LDS row stride (odd: no bank conflicts along columns)
 
@@ -630,36 +591,8 @@ __global__ __launch_bounds__(kT) void pcg_a_kernel(PCGArgs a) {
   __syncthreads();
   rr = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
   rz = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-  int go = 0;
-  double beta = 0.0;
-  const int done = s.iters;
-  if (done > 0 && !(a.alpha[col] > 0.0)) {
-    s.active = 0;
-    s.flag = 3;   // (p, K p) was not positive or not finite
-  } else if (!__builtin_isfinite(rr) || !__builtin_isfinite(rz)) {
-    s.active = 0;
-    s.flag = 3;
-  } else if (done == 0 && rr == 0.0) {
-    s.gamma0 = 0.0;
-    s.active = 0;
-    s.flag = 1;   // b = 0: x = 0
-  } else if (done > 0 && rr <= s.rtol2 * s.gamma0) {
-    s.active = 0;
-    s.flag = 1;
-  } else if (done >= s.maxit) {
-    s.active = 0;
-    s.flag = 2;
-  } else if (!(rz > 0.0)) {
-    s.active = 0;
-    s.flag = 3;   // the preconditioner lost definiteness in rounding
-  } else {
-    if (done == 0) s.gamma0 = rr;
-    beta = done == 0 ? 0.0 : rz / s.rho;
-    s.rho = rz;
-    s.iters = done + 1;
-    go = 1;
-  }
-  s.gamma = rr;
+  double beta;
+  const bool go = pcg_decide(s, rr, rz, a.alpha[col], beta);
   if (t == 0 && threadIdx.x == 0) a.next[col] = s;
   if (!go) return;
   const int n = a.n;
@@ -774,24 +707,6 @@ __global__ __launch_bounds__(kT) void pcg_setup_kernel(PCGArgs a, double rtol2, 
 
 int tiles_of(int n, int tx, int ty) { return ((n + tx - 1) / tx) * ((n + ty - 1) / ty); }
 
-// Chebyshev coefficients for [1/2, 2] (the upper three quarters of the
-// spectrum of D^{-1} Kx, which lies in (0, 2)).
-Smooth smooth_coefficients() {
-  const double lo = 0.5, hi = 2.0;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  Smooth s{};
-  double rho = 1.0 / sigma;
-  s.a[0] = 0.0;
-  s.c[0] = 1.0 / theta;
-  for (int k = 1; k < kNu; ++k) {
-    const double rho1 = 1.0 / (2.0 * sigma - rho);
-    s.a[k] = rho1 * rho;
-    s.c[k] = 2.0 * rho1 / delta;
-    rho = rho1;
-  }
-  return s;
-}
-
 PCGArgs pcg_args(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols) {
   PCGArgs a{};
   a.n = w.plan.n[0];
@@ -827,6 +742,7 @@ PCGArgs pcg_args(const MGWork& w, int parity, const int* cols, int nlaunch, int 
 // ---------------------------------------------------------------------------
 
 bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan) {
+  if (g.dim == 3) return mg3_plan(g, K, plan);
   if (g.dim != 2 || g.nx != g.ny || g.nx < 1) return false;
   // Kx must be mu times the five-point pattern (4; -1, -1, -1, -1)
   const double c0 = K.c[13];
@@ -839,6 +755,7 @@ bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan) {
     if (K.c[i] != want) return false;
   }
   MGPlan p{};
+  p.dim = 2;
   p.mu = mu;
   int L = 0, n = g.nx;
   p.n[0] = n;
@@ -856,6 +773,7 @@ bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan) {
 }
 
 int mg_max_tiles(const MGPlan& p) {
+  if (p.dim == 3) return mg3_max_tiles(p);
   int t = tiles_of(p.n[0], TX, TY);
   if (p.nlev > 0) t = std::max(t, tiles_of(p.n[1], CX, CY));
   return std::max(t, 1);
@@ -884,9 +802,10 @@ size_t mg_dst_table_size(int m) { return (size_t)m * (m + 1) + 2 * (size_t)(m + 
 
 void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
                hipStream_t st) {
+  if (w.plan.dim == 3) return mg3_vcycle(w, act, cols, nlaunch, partials, st);
   const MGPlan& p = w.plan;
   const int L = p.nlev;
-  const Smooth sm = smooth_coefficients();
+  const Smooth sm = smooth_coefficients(0.5);   // [1/2, 2]: the oscillatory part in 2-D
   for (int l = 0; l < L; ++l) {
     LevelArgs a{};
     a.nf = p.n[l];
@@ -1011,6 +930,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
 
 void pcg_setup(const MGWork& w, const double* const* b, const int* cols, int nlaunch, int ncols,
                double rtol, int maxit, hipStream_t st) {
+  if (w.plan.dim == 3) return pcg3_setup(w, b, cols, nlaunch, ncols, rtol, maxit, st);
   // state slot 0 is "previous" for the first iteration (parity 1)
   PCGArgs a = pcg_args(w, 0, cols, nlaunch, ncols);
   for (int j = 0; j < nlaunch; ++j) a.b[j] = b[j];
@@ -1020,6 +940,7 @@ void pcg_setup(const MGWork& w, const double* const* b, const int* cols, int nla
 
 void pcg_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
                  hipStream_t st) {
+  if (w.plan.dim == 3) return pcg3_iterate(w, parity, cols, nlaunch, ncols, st);
   mg_vcycle(w, w.scal + (parity ^ 1) * kMaxCols, cols, nlaunch, true, st);
   const PCGArgs a = pcg_args(w, parity, cols, nlaunch, ncols);
   const int blocks = a.ntx * a.nty * nlaunch;

@@ -1,0 +1,723 @@
+// Multigrid-preconditioned conjugate gradients for the 3-D 7-point stiffness.
+//
+// Kx = c (6; -1 x 6), c = mu h, is the P1 stiffness of the Kuhn triangulation
+// of the uniform grid (every cube cut into six tetrahedra around its x+y+z
+// diagonal), the stiffness paired with the Q1 mass in Sec. 3's 3-D example.
+// The Kuhn meshes of widths h, 2h, 4h, ... are nested.  The prolongation P is
+// P1 interpolation: coarse values at coincident nodes, the mean of the two
+// end points at the midpoints of coarse edges, which run in the seven
+// directions x, y, z, x+y, x+z, y+z, x+y+z.  The Galerkin operator P^T Kx P is
+// again the 7-point stencil, with coefficient 2c on the coarse mesh.
+//
+// The preconditioner is one V-cycle started from zero:
+//  - smoothing: two Chebyshev steps on D^{-1} Kx (D = 6c) for [1/3, 2], the
+//    part of its spectrum (0, 2) that the coarse mesh cannot represent, before
+//    and after the coarse correction;
+//  - restriction P^T of the residual (15 fine nodes per coarse node),
+//    prolongation P of the correction;
+//  - the coarsest level (at most kMG3ExactMax nodes per direction) is solved
+//    exactly by the 3-D discrete sine transform: with T = tridiag(-1, 2, -1) =
+//    S diag(l) S, Kx = c (T (x) I (x) I + I (x) T (x) I + I (x) I (x) T), so the
+//    nodal array U of Kx U = B is S3 [(S3 B) / (c (l_i + l_j + l_k))] with S3
+//    the transform along all three axes.  Three launches: a 2-D transform of
+//    every z-plane (two 64 x 64 GEMMs on the matrix cores), then per y-plane
+//    the transform along z, the division and the inverse transform along z,
+//    then the inverse 2-D transform of every z-plane.
+// The V-cycle is a fixed symmetric positive definite operator (the post-
+// smoothing polynomial is the adjoint of the pre-smoothing one), so the outer
+// iteration is ordinary preconditioned CG.
+//
+// Launches per smoothed level: "pre" (both pre-smoothing steps from zero,
+// which need b on a one-node halo only; the iterate is stored), "restrict"
+// (residual on a halo, then P^T), "post1" (iterate + P e_c on a halo, first
+// post-smoothing step) and "post2" (second step, the result).  Fine-level
+// launches work on 32 x 8 x 4 tiles staged in LDS with a one-node halo.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mg_common.h"
+#include "sts_internal.h"
+
+namespace sts {
+
+namespace {
+
+using namespace mgc;
+
+constexpr int kT = 256;
+constexpr int TX = 32, TY = 8, TZ = 4;                 // fine tile
+constexpr int RX = TX + 2, RY = TY + 2, RZ = TZ + 2;   // with a one-node halo
+constexpr int NR = RX * RY * RZ;
+constexpr int CX = 16, CY = 4, CZ = 4;                 // coarse tile of the restriction
+constexpr int kCT = 1024;                              // threads of the coarse launches
+constexpr int kE = 64;                                 // padded order of the exact solve
+constexpr int kEL = kE + 1;                            // LDS row stride
+constexpr double kSmoothLo = 1.0 / 3.0;
+static_assert(kMG3ExactMax < kE, "exact level fits the padded transform");
+
+struct Tile3 {
+  int x0, y0, z0;
+};
+
+__device__ __forceinline__ Tile3 tile_of(int t, int ntx, int nty, int sx, int sy, int sz) {
+  return Tile3{(t % ntx) * sx, ((t / ntx) % nty) * sy, (t / (ntx * nty)) * sz};
+}
+
+// c (6 u - sum of the six neighbours) at LDS point q of an array with rows
+// of X and planes of X * Y.
+template <int X, int Y>
+__device__ __forceinline__ double k7(const double* s, int q, double c) {
+  return c * (6.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - X] + s[q + X]) -
+              (s[q - X * Y] + s[q + X * Y]));
+}
+
+// The tile of g (n^3 nodes, x fastest) with a one-node halo into s; zero
+// outside the domain (the Dirichlet values).
+__device__ __forceinline__ void load_halo(const double* g, int n, const Tile3& T, double* s) {
+  for (int i = threadIdx.x; i < NR; i += kT) {
+    const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
+    const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+    s[i] = in ? g[((size_t)gz * n + gy) * n + gx] : 0.0;
+  }
+}
+
+// Visit the tile's own nodes: f(global index, LDS index in the halo array).
+template <class F>
+__device__ __forceinline__ void for_core(int n, const Tile3& T, F&& f) {
+  for (int i = threadIdx.x; i < TX * TY * TZ; i += kT) {
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int gx = T.x0 + lx, gy = T.y0 + ly, gz = T.z0 + lz;
+    if (gx < n && gy < n && gz < n)
+      f(((size_t)gz * n + gy) * n + gx, ((lz + 1) * RY + ly + 1) * RX + lx + 1);
+  }
+}
+
+struct Level3Args {
+  int nf, nc;           // fine / coarse nodes per direction (nf = 2 nc + 1)
+  int64_t ldf, ldc;     // column strides
+  const double* bf;     // fine right-hand side
+  double* xp;           // pre-smoothed iterate: written by pre, read by post1
+  double* bc;           // restrict: coarse right-hand side
+  const double* ec;     // post1: coarse correction
+  double* u1;           // post1 -> post2: iterate after the first step
+  double* d0;           // post1 -> post2: first Chebyshev direction
+  double* ef;           // post2: result on the fine level
+  int ntx, nty, ntz;    // tiles of the launch
+  int nlaunch;
+  int cols[kMaxCols];
+  const CGScal* st;     // per-column activity, may be null (all active)
+  double c;             // stencil coefficient of the fine level
+  double a1, c0, c1;    // Chebyshev coefficients of steps 0 and 1
+  double* part;         // post2: per-tile (b, e), may be null
+  int max_tiles;
+};
+
+#define STS_MG3_PROLOGUE(A)                                                    \
+  const int ntiles = (A).ntx * (A).nty * (A).ntz;                              \
+  const int lin = xcd_remap(blockIdx.x, (A).nlaunch * ntiles);                 \
+  const int t = lin / (A).nlaunch, col = (A).cols[lin % (A).nlaunch];          \
+  if ((A).st && !(A).st[col].active) return;
+
+// pre: u_1 = c_0 b / D, d_1 = a_1 u_1 + c_1 (b - K u_1) / D, u_2 = u_1 + d_1.
+__global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
+  __shared__ double bs[NR];
+  STS_MG3_PROLOGUE(a)
+  const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
+  load_halo(a.bf + (size_t)col * a.ldf, a.nf, T, bs);
+  __syncthreads();
+  const double inv_d = 1.0 / (6.0 * a.c);
+  double* xp = a.xp + (size_t)col * a.ldf;
+  for_core(a.nf, T, [&](size_t g, int q) {
+    const double b = bs[q];
+    const double u1 = a.c0 * inv_d * b;
+    const double ku1 = a.c0 * inv_d * k7<RX, RY>(bs, q, a.c);
+    const double d1 = a.a1 * u1 + a.c1 * inv_d * (b - ku1);
+    xp[g] = u1 + d1;
+  });
+}
+
+// restrict: r = b - K u_2 on the fine nodes around the coarse tile, then
+// b_c = P^T r: the coincident node plus half of each of its 14 neighbours
+// along the seven edge directions.
+__global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
+  constexpr int SX = 2 * CX + 1, SY = 2 * CY + 1, SZ = 2 * CZ + 1;   // residual region
+  constexpr int UX = SX + 2, UY = SY + 2, UZ = SZ + 2;               // iterate region
+  __shared__ double us[UX * UY * UZ];
+  __shared__ double rs[SX * SY * SZ];
+  STS_MG3_PROLOGUE(a)
+  const Tile3 C = tile_of(t, a.ntx, a.nty, CX, CY, CZ);
+  const int nf = a.nf, nc = a.nc;
+  const int fx0 = 2 * C.x0, fy0 = 2 * C.y0, fz0 = 2 * C.z0;   // residual region origin
+  const double* xp = a.xp + (size_t)col * a.ldf;
+  const double* bf = a.bf + (size_t)col * a.ldf;
+  for (int i = threadIdx.x; i < UX * UY * UZ; i += kT) {
+    const int gx = fx0 - 1 + i % UX, gy = fy0 - 1 + (i / UX) % UY, gz = fz0 - 1 + i / (UX * UY);
+    const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
+    us[i] = in ? xp[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+  }
+  for (int i = threadIdx.x; i < SX * SY * SZ; i += kT) {
+    const int gx = fx0 + i % SX, gy = fy0 + (i / SX) % SY, gz = fz0 + i / (SX * SY);
+    const bool in = gx < nf && gy < nf && gz < nf;
+    rs[i] = in ? bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SX * SY * SZ; i += kT) {
+    const int lx = i % SX, ly = (i / SX) % SY, lz = i / (SX * SY);
+    // nodes outside the domain keep r = 0 (no coarse node gathers them)
+    if (fx0 + lx < nf && fy0 + ly < nf && fz0 + lz < nf)
+      rs[i] -= k7<UX, UY>(us, ((lz + 1) * UY + ly + 1) * UX + lx + 1, a.c);
+  }
+  __syncthreads();
+  double* bc = a.bc + (size_t)col * a.ldc;
+  for (int i = threadIdx.x; i < CX * CY * CZ; i += kT) {
+    const int I = C.x0 + i % CX, J = C.y0 + (i / CX) % CY, K = C.z0 + i / (CX * CY);
+    if (I < nc && J < nc && K < nc) {
+      const int q = ((2 * (K - C.z0) + 1) * SY + 2 * (J - C.y0) + 1) * SX + 2 * (I - C.x0) + 1;
+      double s = 0.0;
+#pragma unroll
+      for (int e = 1; e < 8; ++e) {
+        const int o = (e & 1) + ((e >> 1) & 1) * SX + ((e >> 2) & 1) * SX * SY;
+        s += rs[q + o] + rs[q - o];
+      }
+      bc[((size_t)K * nc + J) * nc + I] = rs[q] + 0.5 * s;
+    }
+  }
+}
+
+// P1 interpolation at fine node (gx, gy, gz) from an LDS block of coarse
+// values with origin (ox, oy, oz) and dimensions EX x EY.  Per axis, fine
+// index 2I+1 coincides with coarse I and an even fine index 2I+2 lies between
+// coarse I and I+1; a node even along the axes in a set E is the midpoint of
+// the coarse edge from (I, J, K) in direction E.
+template <int EX, int EY>
+__device__ __forceinline__ double interp3(const double* es, int ox, int oy, int oz, int gx, int gy,
+                                          int gz) {
+  const int ex = (gx & 1) ^ 1, ey = (gy & 1) ^ 1, ez = (gz & 1) ^ 1;
+  const int I = (gx - 1 - ex) >> 1, J = (gy - 1 - ey) >> 1, K = (gz - 1 - ez) >> 1;
+  const double* c = es + ((K - oz) * EY + (J - oy)) * EX + (I - ox);
+  if ((ex | ey | ez) == 0) return c[0];
+  return 0.5 * (c[0] + c[ex + ey * EX + ez * EX * EY]);
+}
+
+// post1: u = u_2 + P e_c on the tile and its halo; d_0 = c_0 (b - K u) / D,
+// u_1 = u + d_0 on the tile.
+__global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
+  constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = TZ / 2 + 2;
+  __shared__ double us[NR];
+  __shared__ double es[EX * EY * EZ];
+  STS_MG3_PROLOGUE(a)
+  const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
+  const int nf = a.nf, nc = a.nc;
+  load_halo(a.xp + (size_t)col * a.ldf, nf, T, us);
+  const int ox = T.x0 / 2 - 1, oy = T.y0 / 2 - 1, oz = T.z0 / 2 - 1;
+  const double* ec = a.ec + (size_t)col * a.ldc;
+  for (int i = threadIdx.x; i < EX * EY * EZ; i += kT) {
+    const int I = ox + i % EX, J = oy + (i / EX) % EY, K = oz + i / (EX * EY);
+    const bool in = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
+    es[i] = in ? ec[((size_t)K * nc + J) * nc + I] : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NR; i += kT) {
+    const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
+    if (gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf)
+      us[i] += interp3<EX, EY>(es, ox, oy, oz, gx, gy, gz);
+  }
+  __syncthreads();
+  const double inv_d = 1.0 / (6.0 * a.c);
+  const double* bf = a.bf + (size_t)col * a.ldf;
+  double* u1 = a.u1 + (size_t)col * a.ldf;
+  double* d0 = a.d0 + (size_t)col * a.ldf;
+  for_core(nf, T, [&](size_t g, int q) {
+    const double d = a.c0 * inv_d * (bf[g] - k7<RX, RY>(us, q, a.c));
+    d0[g] = d;
+    u1[g] = us[q] + d;
+  });
+}
+
+// post2: d_1 = a_1 d_0 + c_1 (b - K u_1) / D, e = u_1 + d_1; per-tile (b, e).
+__global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
+  __shared__ double us[NR];
+  __shared__ double red[kT / 64];
+  STS_MG3_PROLOGUE(a)
+  const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
+  const int nf = a.nf;
+  load_halo(a.u1 + (size_t)col * a.ldf, nf, T, us);
+  __syncthreads();
+  const double inv_d = 1.0 / (6.0 * a.c);
+  const double* bf = a.bf + (size_t)col * a.ldf;
+  const double* d0 = a.d0 + (size_t)col * a.ldf;
+  double* ef = a.ef + (size_t)col * a.ldf;
+  double part = 0.0;
+  for_core(nf, T, [&](size_t g, int q) {
+    const double b = bf[g];
+    const double e = us[q] + (a.a1 * d0[g] + a.c1 * inv_d * (b - k7<RX, RY>(us, q, a.c)));
+    ef[g] = e;
+    part += b * e;
+  });
+  if (a.part) {
+    part = block_sum<kT>(part, red);
+    if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exact coarse solve by the 3-D sine transform (order m <= kMG3ExactMax)
+// ---------------------------------------------------------------------------
+struct Coarse3Args {
+  int m;
+  int64_t ld;
+  const double* in;     // per column, m^3 (x fastest)
+  double* out;
+  const double* rhs;    // last stage with partials: the right-hand side b
+  const double* dst;    // S (m x m, symmetric), then l (m)
+  double c;             // stencil coefficient of the coarse level
+  int nlaunch;
+  int cols[kMaxCols];
+  const CGScal* st;
+  double* part;         // (b, e) per plane when the exact solve is the whole V-cycle
+  int max_tiles;
+};
+
+// C = A B for 64 x 64 LDS matrices (row stride kEL), one 16 x 16 tile per
+// wave; `epi(y, x, v)` gives the stored value.
+template <class Epi>
+__device__ __forceinline__ void lds_gemm64(const double* A, const double* B, double* C, Epi&& epi) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int r0 = (wv & 3) * 16, c0 = (wv >> 2) * 16;
+  d4 acc[4] = {};
+#pragma unroll
+  for (int k0 = 0; k0 < kE; k0 += 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[j] = mfma(A[(r0 + i) * kEL + k0 + 4 * j + g], B[(k0 + 4 * j + g) * kEL + c0 + i], acc[j]);
+  }
+  const d4 sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int y = r0 + 4 * q + g, x = c0 + i;
+    C[y * kEL + x] = epi(y, x, sum[q]);
+  }
+}
+
+// Stage 0 / 2: every z-plane P (y rows, x columns) becomes S P S.
+__global__ __launch_bounds__(kCT) void coarse3_plane_kernel(Coarse3Args a) {
+  __shared__ double S[kE * kEL];
+  __shared__ double X[kE * kEL];
+  __shared__ double Tm[kE * kEL];
+  __shared__ double red[kCT / 64];
+  const int col = a.cols[blockIdx.y];
+  if (a.st && !a.st[col].active) return;
+  const int m = a.m, z = blockIdx.x;
+  const size_t off = (size_t)col * a.ld + (size_t)z * m * m;
+  const double* in = a.in + off;
+  for (int i = threadIdx.x; i < kE * kE; i += kCT) {
+    const int y = i / kE, x = i % kE;
+    const bool ok = y < m && x < m;
+    S[y * kEL + x] = ok ? a.dst[y * m + x] : 0.0;
+    X[y * kEL + x] = ok ? in[y * m + x] : 0.0;
+  }
+  __syncthreads();
+  auto keep = [](int, int, double v) { return v; };
+  lds_gemm64(S, X, Tm, keep);
+  __syncthreads();
+  lds_gemm64(Tm, S, X, keep);
+  __syncthreads();
+  double* out = a.out + off;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < m * m; i += kCT) {
+    const double v = X[(i / m) * kEL + i % m];
+    out[i] = v;
+    if (a.part) part += a.rhs[off + i] * v;
+  }
+  if (a.part) {
+    part = block_sum<kCT>(part, red);
+    if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + z] = part;
+  }
+}
+
+// Stage 1: every y-plane Q (z rows, x columns) becomes
+// S [(S Q) / (c (l_z + l_y + l_x))], in place.
+__global__ __launch_bounds__(kCT) void coarse3_z_kernel(Coarse3Args a) {
+  __shared__ double S[kE * kEL];
+  __shared__ double X[kE * kEL];
+  __shared__ double Tm[kE * kEL];
+  __shared__ double l[kE];
+  const int col = a.cols[blockIdx.y];
+  if (a.st && !a.st[col].active) return;
+  const int m = a.m, y = blockIdx.x;
+  double* io = a.out + (size_t)col * a.ld;
+  for (int i = threadIdx.x; i < kE * kE; i += kCT) {
+    const int r = i / kE, x = i % kE;
+    const bool ok = r < m && x < m;
+    S[r * kEL + x] = ok ? a.dst[r * m + x] : 0.0;
+    X[r * kEL + x] = ok ? io[((size_t)r * m + y) * m + x] : 0.0;
+  }
+  if (threadIdx.x < kE) l[threadIdx.x] = threadIdx.x < m ? a.dst[(size_t)m * m + threadIdx.x] : 0.0;
+  __syncthreads();
+  const double ly = l[y], c = a.c;
+  lds_gemm64(S, X, Tm, [&](int r, int x, double v) {
+    return (r < m && x < m) ? v / (c * (l[r] + ly + l[x])) : 0.0;
+  });
+  __syncthreads();
+  lds_gemm64(S, Tm, X, [](int, int, double v) { return v; });
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m; i += kCT) {
+    const int r = i / m, x = i % m;
+    io[((size_t)r * m + y) * m + x] = X[r * kEL + x];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCG launches on the finest grid (tiles TX x TY x TZ)
+// ---------------------------------------------------------------------------
+struct PCG3Args {
+  int n;
+  int64_t ld;
+  int ntx, nty, ntz;
+  int ncols;
+  int nlaunch;
+  int cols[kMaxCols];
+  double c;
+  double* x;
+  int64_t ldx;
+  double* r;
+  const double* z;
+  const double* pin;
+  double* pout;
+  double* q;
+  const CGScal* prev;
+  CGScal* next;
+  double* part_rr;
+  double* part_rz;
+  double* part_pq;
+  int rz_tiles;
+  double* alpha;
+  int max_tiles;
+  const double* b[kMaxCols];
+};
+
+#define STS_PCG3_PROLOGUE(A)                                                   \
+  const int ntiles = (A).ntx * (A).nty * (A).ntz;                              \
+  const int lin = xcd_remap(blockIdx.x, (A).nlaunch * ntiles);                 \
+  const int t = lin / (A).nlaunch, jb = lin % (A).nlaunch, col = (A).cols[jb]; \
+  (void)jb;                                                                    \
+  const Tile3 T = tile_of(t, (A).ntx, (A).nty, TX, TY, TZ);
+
+// A: stopping test and beta; p = z + beta p; q = K p; (p, q).
+__global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
+  __shared__ double ps[NR];
+  __shared__ double red[2][kT / 64];
+  STS_PCG3_PROLOGUE(a)
+  if (blockIdx.x == 0) {
+    for (int c = threadIdx.x; c < a.ncols; c += kT) {
+      bool launched = false;
+      for (int j = 0; j < a.nlaunch; ++j) launched |= a.cols[j] == c;
+      if (!launched) a.next[c] = a.prev[c];
+    }
+  }
+  CGScal s = a.prev[col];
+  if (!s.active) {
+    if (t == 0 && threadIdx.x == 0) a.next[col] = s;
+    return;
+  }
+  double rr = 0.0, rz = 0.0;
+  const double* prr = a.part_rr + (size_t)col * a.max_tiles;
+  const double* prz = a.part_rz + (size_t)col * a.max_tiles;
+  for (int u = threadIdx.x; u < ntiles; u += kT) rr += prr[u];
+  for (int u = threadIdx.x; u < a.rz_tiles; u += kT) rz += prz[u];
+  rr = wave_sum(rr);
+  rz = wave_sum(rz);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = rr;
+    red[1][threadIdx.x >> 6] = rz;
+  }
+  __syncthreads();
+  rr = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+  rz = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  double beta;
+  const bool go = pcg_decide(s, rr, rz, a.alpha[col], beta);
+  if (t == 0 && threadIdx.x == 0) a.next[col] = s;
+  if (!go) return;
+  const int n = a.n;
+  const double* zg = a.z + (size_t)col * a.ld;
+  const double* pin = a.pin + (size_t)col * a.ld;
+  for (int i = threadIdx.x; i < NR; i += kT) {
+    const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
+    double v = 0.0;
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
+      const size_t g = ((size_t)gz * n + gy) * n + gx;
+      v = zg[g] + beta * pin[g];
+    }
+    ps[i] = v;
+  }
+  __syncthreads();
+  double* pout = a.pout + (size_t)col * a.ld;
+  double* qg = a.q + (size_t)col * a.ld;
+  double part = 0.0;
+  for_core(n, T, [&](size_t g, int q) {
+    const double pv = ps[q];
+    const double qv = k7<RX, RY>(ps, q, a.c);
+    pout[g] = pv;
+    qg[g] = qv;
+    part += pv * qv;
+  });
+  part = block_sum<kT>(part, red[0]);
+  if (threadIdx.x == 0) a.part_pq[(size_t)col * a.max_tiles + t] = part;
+}
+
+// B: alpha = rho / (p, q); x += alpha p; r -= alpha q; (r, r).
+__global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
+  __shared__ double red[kT / 64];
+  STS_PCG3_PROLOGUE(a)
+  const CGScal s = a.next[col];
+  if (!s.active) return;
+  double pq = 0.0;
+  const double* ppq = a.part_pq + (size_t)col * a.max_tiles;
+  for (int u = threadIdx.x; u < ntiles; u += kT) pq += ppq[u];
+  pq = block_sum<kT>(pq, red);
+  const bool ok = pq > 0.0 && __builtin_isfinite(pq);
+  const double alpha = ok ? s.rho / pq : 0.0;
+  if (t == 0 && threadIdx.x == 0) a.alpha[col] = alpha;
+  if (!ok) return;
+  double* xg = a.x + (size_t)col * a.ldx;
+  double* rg = a.r + (size_t)col * a.ld;
+  const double* pg = a.pout + (size_t)col * a.ld;
+  const double* qg = a.q + (size_t)col * a.ld;
+  double part = 0.0;
+  for_core(a.n, T, [&](size_t g, int) {
+    xg[g] += alpha * pg[g];
+    const double rv = rg[g] - alpha * qg[g];
+    rg[g] = rv;
+    part += rv * rv;
+  });
+  part = block_sum<kT>(part, red);
+  if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = part;
+}
+
+// Set-up: x = 0, r = b, both p buffers 0, partials of (b, b); both state
+// slots initialised (columns in the launch list active), alpha = 1.
+__global__ __launch_bounds__(kT) void pcg3_setup_kernel(PCG3Args a, double rtol2, int maxit) {
+  __shared__ double red[kT / 64];
+  STS_PCG3_PROLOGUE(a)
+  const double* bg = a.b[jb];
+  double* pa = const_cast<double*>(a.pin);
+  double part = 0.0;
+  for_core(a.n, T, [&](size_t g, int) {
+    const double bv = bg[g];
+    a.x[g + (size_t)col * a.ldx] = 0.0;
+    a.r[g + (size_t)col * a.ld] = bv;
+    pa[g + (size_t)col * a.ld] = 0.0;
+    a.pout[g + (size_t)col * a.ld] = 0.0;
+    part += bv * bv;
+  });
+  part = block_sum<kT>(part, red);
+  if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = part;
+  if (blockIdx.x == 0 && threadIdx.x < kMaxCols) {
+    const int c = threadIdx.x;
+    bool launched = false;
+    for (int j = 0; j < a.nlaunch; ++j) launched |= a.cols[j] == c;
+    CGScal s{};
+    s.rtol2 = rtol2;
+    s.maxit = maxit;
+    s.active = launched ? 1 : 0;
+    a.next[c] = s;
+    const_cast<CGScal*>(a.prev)[c] = s;
+    a.alpha[c] = 1.0;
+  }
+}
+
+int tiles3(int n, int sx, int sy, int sz) {
+  return ((n + sx - 1) / sx) * ((n + sy - 1) / sy) * ((n + sz - 1) / sz);
+}
+
+double level_coef(const MGPlan& p, int l) { return std::ldexp(p.mu, l); }
+
+PCG3Args pcg3_args(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols) {
+  PCG3Args a{};
+  a.n = w.plan.n[0];
+  a.ld = w.ld[0];
+  a.ntx = (a.n + TX - 1) / TX;
+  a.nty = (a.n + TY - 1) / TY;
+  a.ntz = (a.n + TZ - 1) / TZ;
+  a.ncols = ncols;
+  a.nlaunch = nlaunch;
+  for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
+  a.c = w.plan.mu;
+  a.x = w.x;
+  a.ldx = w.ldx;
+  a.r = w.b[0];
+  a.z = w.e[0];
+  a.pin = w.p[parity ^ 1];
+  a.pout = w.p[parity];
+  a.q = w.q;
+  a.prev = w.scal + (parity ^ 1) * kMaxCols;
+  a.next = w.scal + parity * kMaxCols;
+  a.part_rr = w.part_rr;
+  a.part_rz = w.part_rz;
+  a.part_pq = w.part_pq;
+  a.rz_tiles = w.plan.nlev > 0 ? tiles3(a.n, TX, TY, TZ) : w.plan.n[0];
+  a.alpha = w.alpha;
+  a.max_tiles = w.max_tiles;
+  return a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+bool mg3_plan(const Grid& g, const Stencil& K, MGPlan* plan) {
+  if (g.dim != 3 || g.nx != g.ny || g.nx != g.nz || g.nx < 1) return false;
+  // Kx must be c times the 7-point pattern (6; -1 x 6); the centre 6 c may
+  // differ from six times the neighbour coefficient by rounding
+  const double c = -K.c[12];
+  if (!(c > 0.0) || std::fabs(K.c[13] - 6.0 * c) > 1e-15 * 6.0 * c) return false;
+  for (int i = 0; i < 27; ++i) {
+    if (i == 13) continue;
+    const double want = (i == 12 || i == 14 || i == 10 || i == 16 || i == 4 || i == 22) ? -c : 0.0;
+    if (K.c[i] != want) return false;
+  }
+  MGPlan p{};
+  p.dim = 3;
+  p.mu = c;
+  int L = 0, n = g.nx;
+  p.n[0] = n;
+  while (n > kMG3ExactMax) {
+    if ((n & 1) == 0 || L + 1 >= kMGMaxLevels) return false;   // does not halve
+    n = (n - 1) / 2;
+    p.n[++L] = n;
+  }
+  p.nlev = L;
+  p.exact = n;
+  *plan = p;
+  return true;
+}
+
+int mg3_max_tiles(const MGPlan& p) {
+  int t = tiles3(p.n[0], TX, TY, TZ);
+  if (p.nlev == 0) t = std::max(t, p.n[0]);
+  return std::max(t, 1);
+}
+
+double mg3_bytes_per_node(const MGPlan& p) {
+  const double n0 = std::pow((double)p.n[0], 3);
+  double b = 80.0 * n0;   // PCG A and B
+  for (int l = 0; l < p.nlev; ++l) {
+    const double nf = std::pow((double)p.n[l], 3), nc = std::pow((double)p.n[l + 1], 3);
+    b += 16.0 * nf + 8.0 * (2.0 * nf + nc) + 8.0 * (4.0 * nf + nc) + 32.0 * nf;
+  }
+  b += 48.0 * std::pow((double)p.exact, 3);
+  return b / n0;
+}
+
+void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
+                hipStream_t st) {
+  const MGPlan& p = w.plan;
+  const int L = p.nlev;
+  const Smooth sm = smooth_coefficients(kSmoothLo);
+  auto level = [&](int l) {
+    Level3Args a{};
+    a.nf = p.n[l];
+    a.nc = p.n[l + 1];
+    a.ldf = w.ld[l];
+    a.ldc = w.ld[l + 1];
+    a.bf = w.b[l];
+    a.xp = w.xp[l];
+    a.bc = w.b[l + 1];
+    a.ec = w.e[l + 1];
+    a.u1 = w.u1[l];
+    a.d0 = w.d0[l];
+    a.ef = w.e[l];
+    a.nlaunch = nlaunch;
+    for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
+    a.st = act;
+    a.c = level_coef(p, l);
+    a.a1 = sm.a[1];
+    a.c0 = sm.c[0];
+    a.c1 = sm.c[1];
+    a.max_tiles = w.max_tiles;
+    return a;
+  };
+  auto fine_tiles = [&](Level3Args& a) {
+    a.ntx = (a.nf + TX - 1) / TX;
+    a.nty = (a.nf + TY - 1) / TY;
+    a.ntz = (a.nf + TZ - 1) / TZ;
+    return a.ntx * a.nty * a.ntz * nlaunch;
+  };
+  for (int l = 0; l < L; ++l) {
+    Level3Args a = level(l);
+    const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
+    int blocks = fine_tiles(a);
+    launch(STS_K_MG_DOWN, 16.0 * nf * nlaunch, mg3_pre_kernel, dim3(blocks), dim3(kT), 0, st, a);
+    STS_HIP(hipGetLastError());
+    a.ntx = (a.nc + CX - 1) / CX;
+    a.nty = (a.nc + CY - 1) / CY;
+    a.ntz = (a.nc + CZ - 1) / CZ;
+    blocks = a.ntx * a.nty * a.ntz * nlaunch;
+    launch(STS_K_MG_DOWN, 8.0 * (2.0 * nf + nc) * nlaunch, mg3_restrict_kernel, dim3(blocks),
+           dim3(kT), 0, st, a);
+    STS_HIP(hipGetLastError());
+  }
+  {
+    const int m = p.exact;
+    Coarse3Args c{};
+    c.m = m;
+    c.ld = w.ld[L];
+    c.dst = w.dst;
+    c.c = level_coef(p, L);
+    c.nlaunch = nlaunch;
+    for (int j = 0; j < nlaunch; ++j) c.cols[j] = cols[j];
+    c.st = act;
+    c.max_tiles = w.max_tiles;
+    const double by = 16.0 * std::pow((double)m, 3) * nlaunch;
+    const dim3 grid(m, nlaunch);
+    c.in = w.b[L];
+    c.out = w.t1;
+    launch(STS_K_MG_COARSE, by, coarse3_plane_kernel, grid, dim3(kCT), 0, st, c);
+    STS_HIP(hipGetLastError());
+    launch(STS_K_MG_COARSE, by, coarse3_z_kernel, grid, dim3(kCT), 0, st, c);
+    STS_HIP(hipGetLastError());
+    c.in = w.t1;
+    c.out = w.e[L];
+    c.rhs = w.b[L];
+    c.part = (partials && L == 0) ? w.part_rz : nullptr;
+    launch(STS_K_MG_COARSE, by, coarse3_plane_kernel, grid, dim3(kCT), 0, st, c);
+    STS_HIP(hipGetLastError());
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    Level3Args a = level(l);
+    const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
+    const int blocks = fine_tiles(a);
+    launch(STS_K_MG_UP, 8.0 * (4.0 * nf + nc) * nlaunch, mg3_post1_kernel, dim3(blocks), dim3(kT),
+           0, st, a);
+    STS_HIP(hipGetLastError());
+    a.part = (partials && l == 0) ? w.part_rz : nullptr;
+    launch(STS_K_MG_UP, 32.0 * nf * nlaunch, mg3_post2_kernel, dim3(blocks), dim3(kT), 0, st, a);
+    STS_HIP(hipGetLastError());
+  }
+}
+
+void pcg3_setup(const MGWork& w, const double* const* b, const int* cols, int nlaunch, int ncols,
+                double rtol, int maxit, hipStream_t st) {
+  PCG3Args a = pcg3_args(w, 0, cols, nlaunch, ncols);
+  for (int j = 0; j < nlaunch; ++j) a.b[j] = b[j];
+  pcg3_setup_kernel<<<a.ntx * a.nty * a.ntz * nlaunch, kT, 0, st>>>(a, rtol * rtol, maxit);
+  STS_HIP(hipGetLastError());
+}
+
+void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
+                  hipStream_t st) {
+  mg3_vcycle(w, w.scal + (parity ^ 1) * kMaxCols, cols, nlaunch, true, st);
+  const PCG3Args a = pcg3_args(w, parity, cols, nlaunch, ncols);
+  const int blocks = a.ntx * a.nty * a.ntz * nlaunch;
+  const double nn = std::pow((double)a.n, 3) * nlaunch;
+  launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel, dim3(blocks), dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+  launch(STS_K_PCG_B, 48.0 * nn, pcg3_b_kernel, dim3(blocks), dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+}
+
+}  // namespace sts

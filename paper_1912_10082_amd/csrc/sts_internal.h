@@ -166,27 +166,35 @@ void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int*
                    const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t st);
 
 // ---------------------------------------------------------------------------
-// multigrid-preconditioned CG for the 2-D P1 stiffness
+// multigrid-preconditioned CG for the 2-D P1 and 3-D seven-point stiffness
 // ---------------------------------------------------------------------------
 
 constexpr int kMGMaxLevels = 12;
 constexpr int kMGCoarseMax = 63;   // coarsest levels up to this size: one work-group per column
 constexpr int kMGExactMax = 255;   // largest exactly solved (coarsest) level
 constexpr int kMGNu = 3;           // Chebyshev smoothing steps before and after
+constexpr int kMG3ExactMax = 63;   // 3-D: largest exactly solved (coarsest) level
 
 struct MGPlan {
-  int nlev;                  // tiled levels 0..nlev-1; level nlev has <= kMGCoarseMax nodes
+  int dim;                   // 2: five-point P1 stiffness, 3: seven-point stiffness
+  int nlev;                  // smoothed levels 0..nlev-1; level nlev is solved exactly
   int n[kMGMaxLevels + 1];   // nodes per direction, n[l+1] = (n[l] - 1) / 2
   int exact;                 // size of the exactly solved coarsest level (= n[nlev])
-  double mu;                 // Kx = mu (4; -1, -1, -1, -1)
+  double mu;                 // 2-D: Kx = mu (4; -1 x 4) on every level;
+                             // 3-D: Kx = mu (6; -1 x 6) on level 0, 2^l mu on level l
 };
 // The m x m sine-transform matrix (row-major) followed by the m eigenvalues
 // 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.
 void mg_dst_table(int m, double* out);
 size_t mg_dst_table_size(int m);   // doubles written by mg_dst_table
 // True (and *plan filled) if Kx is the 2-D five-point P1 stiffness on a square
-// grid that halves, n -> (n-1)/2, down to at most kMGCoarseMax nodes.
+// grid that halves, n -> (n-1)/2, down to at most kMGExactMax nodes, or the
+// 3-D seven-point stiffness on a cube that halves down to kMG3ExactMax.
 bool mg_plan(const Grid& g, const Stencil& K, MGPlan* plan);
+bool mg3_plan(const Grid& g, const Stencil& K, MGPlan* plan);
+int mg3_max_tiles(const MGPlan& p);
+// Algorithmic bytes of one 3-D column-iteration per fine node.
+double mg3_bytes_per_node(const MGPlan& p);
 // Partial-sum slots per column the PCG kernels need.
 int mg_max_tiles(const MGPlan& p);
 
@@ -195,6 +203,8 @@ struct MGWork {
   double* b[kMGMaxLevels + 1];   // right-hand side per level; b[0] is the PCG residual r
   double* e[kMGMaxLevels + 1];   // V-cycle result per level; e[0] is z
   double* xp[kMGMaxLevels + 1];  // pre-smoothed iterate per smoothed level (stride ld)
+  double* u1[kMGMaxLevels + 1];  // 3-D: iterate after the first post-smoothing step
+  double* d0[kMGMaxLevels + 1];  // 3-D: its Chebyshev direction
   int64_t ld[kMGMaxLevels + 1];  // column stride per level
   double* x;                     // solution columns (x + c * ldx)
   int64_t ldx;
@@ -222,6 +232,14 @@ void pcg_setup(const MGWork& w, const double* const* b, const int* cols, int nla
 // One PCG iteration (V-cycle, A, B) writing state slot `parity`.
 void pcg_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
                  hipStream_t st);
+// The 3-D forms of the three calls above (mg_vcycle, pcg_setup and
+// pcg_iterate dispatch on plan.dim).
+void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
+                hipStream_t st);
+void pcg3_setup(const MGWork& w, const double* const* b, const int* cols, int nlaunch, int ncols,
+                double rtol, int maxit, hipStream_t st);
+void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
+                  hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Mx solves by Chebyshev iteration (2-D P1 mass matrix)

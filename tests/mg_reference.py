@@ -25,6 +25,8 @@ and sigma = theta / delta, the textbook three-term recurrence
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
@@ -110,4 +112,116 @@ def supported(n: int) -> bool:
             return False
         n = (n - 1) // 2
         first = False
+    return n >= 1
+
+
+# ---------------------------------------------------------------------------
+# 3-D: the seven-point stiffness mu h (6; -1 x 6), which is the P1 stiffness
+# of the Kuhn triangulation (cubes cut into six tetrahedra around the x+y+z
+# diagonal).  Nested Kuhn meshes give P1 interpolation along the seven edge
+# directions x, y, z, x+y, x+z, y+z, x+y+z.  Two Chebyshev steps for
+# [1/3, 2]; the coarsest level (n <= 63, on any level) is solved exactly by
+# the orthonormal DST-I along the three axes.
+# ---------------------------------------------------------------------------
+CHEB3_STEPS = 2
+CHEB3_INTERVAL = (1.0 / 3.0, 2.0)
+EXACT3 = 63
+
+
+def kuhn_hat(xi, eta, zeta):
+    """P1 hat of a Kuhn-mesh node at offset (xi, eta, zeta) in mesh widths:
+    the tetrahedra of a cube are the orderings of its coordinates, and on the
+    one containing the offset the hat is 1 minus the largest of the
+    magnitudes of the coordinates and of their pairwise differences (the
+    barycentric form of the ordered simplex), clipped at zero."""
+    d = np.max(np.abs([xi, eta, zeta, xi - eta, xi - zeta, eta - zeta]), axis=0)
+    return np.maximum(0.0, 1.0 - d)
+
+
+@functools.lru_cache(maxsize=8)
+def prolongation3(nc: int) -> sp.csr_matrix:
+    """P[f, c] = coarse Kuhn hat c at fine node f, nc^3 -> (2 nc + 1)^3
+    (fine node 2I+1 coincides with coarse I; x fastest)."""
+    n = 2 * nc + 1
+    K, J, I = np.meshgrid(np.arange(nc), np.arange(nc), np.arange(nc), indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    rows, cols, vals = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                w = float(kuhn_hat(dx / 2.0, dy / 2.0, dz / 2.0))
+                if w == 0.0:
+                    continue
+                fx, fy, fz = 2 * I + 1 + dx, 2 * J + 1 + dy, 2 * K + 1 + dz
+                rows.append((fz * n + fy) * n + fx)
+                cols.append((K * nc + J) * nc + I)
+                vals.append(np.full(I.shape, w))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n ** 3, nc ** 3))
+
+
+@functools.lru_cache(maxsize=8)
+def stiffness3(n: int, mu: float) -> sp.csr_matrix:
+    """mu h (T (x) I (x) I + I (x) T (x) I + I (x) I (x) T), T = tridiag(-1, 2, -1):
+    the oracle's 3-D stiffness written as a Kronecker sum (equal to its
+    element assembly, which is too slow for the largest test grids)."""
+    h = 1.0 / (n + 1)
+    T = sp.diags([-np.ones(n - 1), 2.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1])
+    eye = sp.identity(n)
+    K = sp.kron(sp.kron(T, eye), eye) + sp.kron(sp.kron(eye, T), eye) + sp.kron(sp.kron(eye, eye), T)
+    return (mu * h * K).tocsr()
+
+
+def exact3(b: np.ndarray, n: int, mu: float) -> np.ndarray:
+    """Kx^{-1} b for the seven-point stiffness by the sine transform."""
+    from scipy.fft import dstn
+
+    h = 1.0 / (n + 1)
+    lam = 2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi * h)
+    D = mu * h * (lam[:, None, None] + lam[None, :, None] + lam[None, None, :])
+    cols = b.reshape(n ** 3, -1)
+    out = np.empty_like(cols)
+    for j in range(cols.shape[1]):
+        B = cols[:, j].reshape(n, n, n)
+        out[:, j] = dstn(dstn(B, type=1, norm="ortho") / D, type=1, norm="ortho").ravel()
+    return out.reshape(b.shape)
+
+
+def chebyshev3(K, b, u, steps=CHEB3_STEPS, interval=CHEB3_INTERVAL):
+    lo, hi = interval
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    dinv = 1.0 / K.diagonal()
+    if b.ndim == 2:
+        dinv = dinv[:, None]
+    rho = 1.0 / sigma
+    d = dinv * (b - K @ u) / theta
+    u = u + d
+    for _ in range(steps - 1):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * dinv * (b - K @ u)
+        u = u + d
+        rho = rho_new
+    return u
+
+
+def vcycle3(b: np.ndarray, n: int, mu: float) -> np.ndarray:
+    """One 3-D V-cycle from zero applied to b (length n^3, or n^3 x m)."""
+    if n <= EXACT3:
+        return exact3(b, n, mu)
+    assert n % 2 == 1, "levels above the exact size must halve"
+    K = stiffness3(n, mu)
+    u = chebyshev3(K, b, np.zeros_like(b))
+    nc = (n - 1) // 2
+    P = prolongation3(nc)
+    # the coarse stiffness is mu (2h) (6; -1 x 6): the same stencil at nc
+    u = u + P @ vcycle3(P.T @ (b - K @ u), nc, mu)
+    return chebyshev3(K, b, u)
+
+
+def supported3(n: int) -> bool:
+    while n > EXACT3:
+        if n % 2 == 0:
+            return False
+        n = (n - 1) // 2
     return n >= 1

@@ -105,7 +105,7 @@ def test_destroy_null_and_state_errors():
 def test_multigrid_entry_points_reject_unsupported_grids():
     """Argument checks of the multigrid calls run before any device work."""
     lib = b.load()
-    for dim, n in ((2, 100), (2, 130), (2, 510), (1, 127), (3, 15)):
+    for dim, n in ((2, 100), (2, 130), (2, 510), (1, 127), (3, 100), (3, 128), (3, 254)):
         s = sts.make_space(dim, n)
         nh = n ** dim
         assert lib.sts_pcg_mg(C.byref(s), None, nh, None, nh, 1, 1e-12, 10, None,
@@ -117,6 +117,10 @@ def test_multigrid_entry_points_reject_unsupported_grids():
                           None) == b.STS_E_INVALID
     assert "bad buffers" in lib.sts_last_error().decode()
     assert lib.sts_mg_vcycle(C.byref(s), None, 511 ** 2, None, 511 ** 2, 9, None) == b.STS_E_INVALID
+    s = sts.make_space(3, 127)
+    assert lib.sts_pcg_mg(C.byref(s), None, 127 ** 3, None, 127 ** 3, 1, 1e-12, 10, None,
+                          None) == b.STS_E_INVALID
+    assert "bad buffers" in lib.sts_last_error().decode()
 
 
 def test_package_has_no_cpu_fallback():

@@ -107,11 +107,46 @@ def test_pcg_zero_rhs_iteration_cap_and_bad_grids():
     X, its, _ = sts.pcg_mg(sts.make_space(2, 63), dev(B), rtol=1e-12)
     assert its[0] == 1
     for bad in (sts.make_space(2, 100), sts.make_space(2, 130), sts.make_space(1, 127),
-                sts.make_space(3, 15)):
+                sts.make_space(3, 100), sts.make_space(3, 128)):
         nh = int(np.prod([bad.n[d] for d in range(3)]))
         with pytest.raises(sts.STSError) as e:
             sts.pcg_mg(bad, dev(np.ones((nh, 1))))
         assert e.value.code == 1
+
+
+# 3-D sizes: the exact sine-transform solve alone (1, 2, 17, 40, 63), one
+# smoothed level above it with the fine grid ragged against the 32 x 8 x 4
+# tile and the coarse grid against the 16 x 4 x 4 restriction tile (65 -> 32,
+# 95 -> 47, 127 -> 63), and two smoothed levels (191 -> 95 -> 47).
+VC3_SIZES = [1, 2, 17, 40, 63, 65, 95, 127, 191]
+
+
+@pytest.mark.parametrize("n", VC3_SIZES)
+def test_vcycle3_matches_reference(n):
+    mu = 0.25 + 0.1 * (n % 7)
+    rng = np.random.default_rng(600 + n)
+    R = rng.normal(size=(n ** 3, 3))
+    R[:, 1] = 0.0                                   # a zero column stays zero
+    Z = host(sts.mg_vcycle(sts.make_space(3, n, mu), dev(R)))
+    Zr = mgr.vcycle3(R, n, mu)
+    np.testing.assert_allclose(Z, Zr, rtol=0, atol=1e-13 * abs(Zr).max())
+    assert np.all(Z[:, 1] == 0.0)
+
+
+@pytest.mark.parametrize("n,ncols", [(1, 1), (40, 2), (65, 3), (127, 8), (191, 2)])
+def test_pcg3_matches_the_sine_transform_solve(n, ncols):
+    mu = 0.9
+    rng = np.random.default_rng(700 + n)
+    B = rng.normal(size=(n ** 3, ncols))
+    X, its, _ = sts.pcg_mg(sts.make_space(3, n, mu), dev(B), rtol=1e-12)
+    X = host(X)
+    Xr = mgr.exact3(B, n, mu)
+    for c in range(ncols):
+        assert rel(X[:, c], Xr[:, c]) < 1e-10, (c, rel(X[:, c], Xr[:, c]))
+    if n <= mgr.EXACT3:
+        assert max(its) == 1, its          # the V-cycle is the exact inverse
+    else:
+        assert max(its) <= 13, its         # plain CG needs ~700 at n = 191
 
 
 def test_pcg_is_bitwise_deterministic():
@@ -192,3 +227,21 @@ def test_solve_with_and_without_multigrid_match_crank_nicolson(n, nt, p, seed):
         res[pre] = info
     # the preconditioned run needs far fewer inner iterations on Kx
     assert res[1]["inner_its_K"] * 4 < res[0]["inner_its_K"], (res[0], res[1])
+
+
+@pytest.mark.parametrize("n,nt,p,seed", [(65, 24, 2, 41), (95, 12, 3, 42)])
+def test_3d_solve_with_and_without_multigrid_match_the_modal_solution(n, nt, p, seed):
+    """3-D trilinear mass / seven-point stiffness: direct Mx and multigrid Kx
+    inner solves against plain CG for both, and both against the exact
+    space-time solution by sine modes."""
+    w = wl.heat_3d_separable(n=n, nt=nt, p=p, seed=seed)
+    Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+    U = exact.modal_solve_3d(n, w.mu, Dt, Mt, w.F1, w.F2)
+    res = {}
+    for pre in (0, 1):
+        info, V, Y = _solve(w, tol=1e-10, inner_precond=pre)
+        assert info["status"] == "STS_OK", info
+        assert info["res_true"] <= 1e-10
+        assert rel(V @ Y, U) <= 1e-8, (pre, rel(V @ Y, U))
+        res[pre] = info
+    assert res[1]["inner_its_K"] * 10 < res[0]["inner_its_K"], (res[0], res[1])

@@ -107,3 +107,87 @@ def test_mass_spectrum_inside_the_chebyshev_interval(n):
     d = np.diag(M)
     ev = np.linalg.eigvalsh(M / np.sqrt(np.outer(d, d)))
     assert ev.min() >= 0.5 - 1e-12 and ev.max() <= 2.0 + 1e-12, (ev.min(), ev.max())
+
+
+# ---------------------------------------------------------------------------
+# 3-D (seven-point stiffness, Kuhn-mesh interpolation)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_kronecker_stiffness_equals_the_element_assembly(n):
+    from oracle import fem
+    K = fem.spatial_operators(3, n, 0.45)[0]
+    assert abs(mgr.stiffness3(n, 0.45) - K).max() <= 1e-15
+
+
+@pytest.mark.parametrize("nc", [1, 3, 7])
+def test_galerkin_coarse_operator_is_the_coarse_stiffness_3d(nc):
+    """P^T K_h P = K_2h: the seven-point stencil with mu h is the P1 stiffness
+    of the Kuhn mesh, and the meshes nest."""
+    mu = 0.61
+    P = mgr.prolongation3(nc)
+    assert abs(P.T @ mgr.stiffness3(2 * nc + 1, mu) @ P - mgr.stiffness3(nc, mu)).max() <= 1e-13
+
+
+def test_prolongation_reproduces_linear_functions_3d():
+    nc = 5
+    n = 2 * nc + 1
+    xc = np.arange(1, nc + 1) / (nc + 1)
+    xf = np.arange(1, n + 1) / (n + 1)
+    f = lambda x, y, z: 0.3 + 2.0 * x - 1.5 * y + 0.7 * z
+    Zc, Yc, Xc = np.meshgrid(xc, xc, xc, indexing="ij")
+    Zf, Yf, Xf = np.meshgrid(xf, xf, xf, indexing="ij")
+    got = mgr.prolongation3(nc) @ f(Xc, Yc, Zc).ravel()
+    want = f(Xf, Yf, Zf).ravel()
+    lo, hi = xf[0], xf[-1]
+    inner = ((Xf > lo) & (Xf < hi) & (Yf > lo) & (Yf < hi) & (Zf > lo) & (Zf < hi)).ravel()
+    np.testing.assert_allclose(got[inner], want[inner], rtol=0, atol=1e-14)
+
+
+def test_kuhn_hat_pins():
+    assert mgr.kuhn_hat(0.0, 0.0, 0.0) == 1.0
+    # midpoints of the seven edge directions (both orientations)
+    for e in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]:
+        v = np.array(e) / 2.0
+        assert mgr.kuhn_hat(*v) == 0.5 and mgr.kuhn_hat(*-v) == 0.5
+    # mixed-sign diagonals are not edges of the Kuhn mesh
+    for v in [(0.5, -0.5, 0.0), (0.5, 0.0, -0.5), (0.0, 0.5, -0.5), (0.5, 0.5, -0.5),
+              (0.5, -0.5, 0.5), (-0.5, 0.5, 0.5)]:
+        assert mgr.kuhn_hat(*v) == 0.0
+    assert mgr.kuhn_hat(1.0, 0.0, 0.0) == 0.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 9])
+def test_exact3_is_the_inverse(n):
+    K = mgr.stiffness3(n, 0.8)
+    B = np.random.default_rng(n).normal(size=(n ** 3, 2))
+    X = spla.spsolve(K.tocsc(), B).reshape(B.shape)
+    np.testing.assert_allclose(mgr.exact3(B, n, 0.8), X, rtol=1e-12, atol=1e-13 * abs(X).max())
+
+
+def test_vcycle3_is_spd_and_below_the_inverse():
+    n, mu = 65, 1.3
+    R = np.random.default_rng(n).normal(size=(n ** 3, 3))
+    Z = mgr.vcycle3(R, n, mu)
+    G = R.T @ Z
+    np.testing.assert_allclose(G, G.T, rtol=1e-12, atol=1e-14 * abs(G).max())
+    assert np.all(np.diag(G) > 0)
+    X = mgr.exact3(R, n, mu)
+    for j in range(3):
+        assert R[:, j] @ Z[:, j] <= R[:, j] @ X[:, j] * (1 + 1e-12)
+
+
+def test_pcg3_iterations_stay_small():
+    its = []
+    for n in (31, 65):
+        K = mgr.stiffness3(n, 1.0)
+        b = np.random.default_rng(n).normal(size=n ** 3)
+        x, it = _pcg(K, b, lambda r: mgr.vcycle3(r, n, 1.0), 1e-12)
+        assert it > 0 and np.linalg.norm(b - K @ x) <= 1e-12 * np.linalg.norm(b)
+        its.append(it)
+    assert its[0] == 1, its          # n <= 63: the V-cycle is the exact inverse
+    assert its[1] <= 12, its
+
+
+def test_supported_grids_3d():
+    assert all(mgr.supported3(n) for n in (1, 2, 40, 63, 95, 127, 191, 255, 511))
+    assert not any(mgr.supported3(n) for n in (64, 100, 128, 254))

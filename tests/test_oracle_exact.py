@@ -56,6 +56,18 @@ def test_modal_solve_matches_kron_on_random_rhs():
     assert exact.relative_error(exact.crank_nicolson(K, M, Dt, Mt, F1, F2), Uk) < 1e-12
 
 
+@pytest.mark.parametrize("n", [1, 4, 7])
+def test_modal_solve_3d_matches_kron_on_random_rhs(n):
+    rng = np.random.default_rng(12 + n)
+    nt, mu = 9, 0.7
+    K, M = fem.spatial_operators(3, n, mu)
+    t = np.cumsum(np.r_[0.0, rng.uniform(0.02, 0.1, nt)])   # graded time grid
+    Dt, Mt = fem.time_matrices(t)
+    F1, F2 = rng.normal(size=(n ** 3, 2)), rng.normal(size=(nt, 2))
+    Uk = exact.kron_solve(K, M, Dt, Mt, F1, F2)
+    assert exact.relative_error(exact.modal_solve_3d(n, mu, Dt, Mt, F1, F2), Uk) < 1e-12
+
+
 def test_2d_kron_equals_crank_nicolson():
     w = wl.heat_2d_bumps(n=15, nt=24, p=2, seed=3)
     K, M, Dt, Mt = _setup(w)
