@@ -156,7 +156,9 @@ typedef enum {
   STS_K_SWEEP = 14,         /* time sweep */
   STS_K_STENCIL = 15,       /* stencil SpMM Kx V, Mx V */
   STS_K_TRIDIAG_SOLVE = 16, /* direct tridiagonal inner solve (1-D) */
-  STS_K_COUNT = 17
+  STS_K_MG_RESTRICT = 17,   /* multigrid (3-D): residual and restriction */
+  STS_K_PCG_REDUCE = 18,    /* preconditioned CG (3-D): sums of per-tile partials */
+  STS_K_COUNT = 19
 } sts_kernel;
 
 typedef struct sts_problem sts_problem;

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "STS_OK", 1: "STS_E_INVALID", 2: "STS_E_NOMEM", 3: "STS_E_DEV
 STS_MEM_HOST, STS_MEM_DEVICE = 0, 1
 STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT = 1, 2, 3
 STS_OP_K, STS_OP_M = 0, 1
-STS_K_COUNT = 17
+STS_K_COUNT = 19
 
 
 class STSError(RuntimeError):

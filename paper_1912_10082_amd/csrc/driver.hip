@@ -467,11 +467,12 @@ struct MGRunner {
     w.max_tiles = mg_max_tiles(plan);
     scal.alloc(sizeof(CGScal) * 2 * kMaxCols);
     w.scal = static_cast<CGScal*>(scal.p);
-    parts.alloc((size_t)(3 * w.max_tiles + 1) * kMaxCols * 8);
+    parts.alloc((size_t)(3 * w.max_tiles + 4) * kMaxCols * 8);
     w.part_rr = parts.d();
     w.part_rz = w.part_rr + (size_t)w.max_tiles * kMaxCols;
     w.part_pq = w.part_rz + (size_t)w.max_tiles * kMaxCols;
     w.alpha = w.part_pq + (size_t)w.max_tiles * kMaxCols;
+    w.tot = w.alpha + kMaxCols;
     const int m = plan.exact;
     std::vector<double> tab(mg_dst_table_size(m));
     mg_dst_table(m, tab.data());
@@ -542,6 +543,7 @@ struct sts_problem {
   int64_t blk_start = 0, blk_size = 0;
   std::vector<int> tags;  // 0: positive power, 1: negative power
   DevBuf V, MV, KV, Kred, Mred, beta;
+  DevBuf qr_work, qr_R;   // exact residual through the QR of the time factor
 
   // CG
   DevBuf cg_r, cg_p, cg_scal, cg_part, counters;
@@ -753,11 +755,24 @@ double true_residual(sts_problem* P) {
   Seg segs[3] = {{P->F1.d(), P->ldv, (int)p}, {P->KV.d(), P->ldv, (int)ks},
                  {P->MV.d(), P->ldv, (int)ks}};
   const int nseg = ks > 0 ? 3 : 1;
-  residual_norm2(P->nh, (int)nt, segs, nseg, BT, ldbt, P->smallv.d(), P->res_part.d(),
-                 P->counter(1), st);
+  const int mtot = (int)(p + (ks > 0 ? 2 * ks : 0));
+  if (nt >= 2 * (int64_t)mtot && qr_r_supported(nt, mtot)) {
+    // ||A B^T|| = ||A R_B^T|| with B = Q_B R_B: an Nh x mtot x mtot product
+    // instead of Nh x mtot x Nt
+    const size_t wd = qr_r_work_doubles(nt, mtot);
+    if (P->qr_work.bytes < wd * 8) P->qr_work.alloc(wd * 8);
+    if (P->qr_R.bytes < (size_t)mtot * mtot * 8) P->qr_R.alloc((size_t)mtot * mtot * 8);
+    qr_r(nt, mtot, BT, ldbt, P->qr_R.d(), P->qr_work.d(), st);
+    residual_norm2(P->nh, mtot, segs, nseg, P->qr_R.d(), mtot, P->smallv.d(), P->res_part.d(),
+                   P->counter(1), st);
+    P->alg_bytes += 8.0 * P->nh * mtot * ((mtot + 255) / 256);
+  } else {
+    residual_norm2(P->nh, (int)nt, segs, nseg, BT, ldbt, P->smallv.d(), P->res_part.d(),
+                   P->counter(1), st);
+    P->alg_bytes += 8.0 * P->nh * mtot * ((nt + 255) / 256);
+  }
   double r2 = 0.0;
   fetch(P, P->smallv.d(), 1, &r2);
-  P->alg_bytes += 8.0 * P->nh * (p + 2 * ks) * ((nt + 255) / 256);
   return std::sqrt(std::max(r2, 0.0)) / P->fnorm;
 }
 
@@ -1555,7 +1570,8 @@ const char* sts_kernel_name(int32_t kernel) {
   static const char* names[STS_K_COUNT] = {
       "cg_iter",   "mg_down",  "mg_up",   "mg_coarse",     "pcg_a", "pcg_b",
       "mass_cheb", "gram",     "basis_update", "residual", "tridiag", "bisect",
-      "inviter",   "backtransform", "sweep", "stencil", "tridiag_solve"};
+      "inviter",   "backtransform", "sweep", "stencil", "tridiag_solve",
+      "mg_restrict", "pcg_reduce"};
   return (kernel >= 0 && kernel < STS_K_COUNT) ? names[kernel] : "";
 }
 

@@ -28,10 +28,11 @@
 // iteration is ordinary preconditioned CG.
 //
 // Launches per smoothed level: "pre" (both pre-smoothing steps from zero,
-// which need b on a one-node halo only; the iterate is stored), "restrict"
-// (residual on a halo, then P^T), "post1" (iterate + P e_c on a halo, first
-// post-smoothing step) and "post2" (second step, the result).  Fine-level
-// launches work on 32 x 8 x 4 tiles staged in LDS with a one-node halo.
+// which need b on a one-node halo only, on the tile and its halo, then the
+// residual; the iterate and the residual are stored), "restrict" (P^T of the
+// residual), "post1" (iterate + P e_c on a halo, first post-smoothing step)
+// and "post2" (second step, the result).  Fine-level launches work on
+// 32 x 8 x 4 tiles staged in LDS with a one- or two-node halo.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -101,7 +102,7 @@ struct Level3Args {
   double* bc;           // restrict: coarse right-hand side
   const double* ec;     // post1: coarse correction
   double* u1;           // post1 -> post2: iterate after the first step
-  double* d0;           // post1 -> post2: first Chebyshev direction
+  double* d0;           // pre -> restrict: the residual; post1 -> post2: first Chebyshev direction
   double* ef;           // post2: result on the fine level
   int ntx, nty, ntz;    // tiles of the launch
   int nlaunch;
@@ -119,54 +120,92 @@ struct Level3Args {
   const int t = lin / (A).nlaunch, col = (A).cols[lin % (A).nlaunch];          \
   if ((A).st && !(A).st[col].active) return;
 
-// pre: u_1 = c_0 b / D, d_1 = a_1 u_1 + c_1 (b - K u_1) / D, u_2 = u_1 + d_1.
+// pre: u_1 = c_0 b / D, d_1 = a_1 u_1 + c_1 (b - K u_1) / D, u_2 = u_1 + d_1
+// on the tile and a one-node halo (from b on a two-node halo), then the
+// residual r = b - K u_2 on the tile.  Stores u_2 (for post1) and r.  One LDS
+// array holds b first and u_2 after it (the values pass through registers),
+// which keeps five work-groups per compute unit.
 __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
-  __shared__ double bs[NR];
+  constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
+  constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
+  constexpr int NC = TX * TY * TZ / kT;                  // tile nodes per thread
+  static_assert(NR <= BX * BY * BZ, "u_2 fits where b was");
+  __shared__ double sh[BX * BY * BZ];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
-  load_halo(a.bf + (size_t)col * a.ldf, a.nf, T, bs);
+  const int nf = a.nf;
+  const double* bf = a.bf + (size_t)col * a.ldf;
+  for (int i = threadIdx.x; i < BX * BY * BZ; i += kT) {
+    const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
+    const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
+    sh[i] = in ? bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+  }
   __syncthreads();
   const double inv_d = 1.0 / (6.0 * a.c);
+  double u2r[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int i = threadIdx.x + k * kT;
+    double u2 = 0.0;   // zero outside the domain (the Dirichlet values)
+    if (i < NR) {
+      const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+      const int gx = T.x0 - 1 + lx, gy = T.y0 - 1 + ly, gz = T.z0 - 1 + lz;
+      if (gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf) {
+        const int q = ((lz + 1) * BY + ly + 1) * BX + lx + 1;
+        const double b = sh[q];
+        const double u1 = a.c0 * inv_d * b;
+        const double ku1 = a.c0 * inv_d * k7<BX, BY>(sh, q, a.c);
+        u2 = u1 + (a.a1 * u1 + a.c1 * inv_d * (b - ku1));
+      }
+    }
+    u2r[k] = u2;
+  }
+  double bc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int i = threadIdx.x + k * kT;
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    bc[k] = sh[((lz + 2) * BY + ly + 2) * BX + lx + 2];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int i = threadIdx.x + k * kT;
+    if (i < NR) sh[i] = u2r[k];
+  }
+  __syncthreads();
   double* xp = a.xp + (size_t)col * a.ldf;
-  for_core(a.nf, T, [&](size_t g, int q) {
-    const double b = bs[q];
-    const double u1 = a.c0 * inv_d * b;
-    const double ku1 = a.c0 * inv_d * k7<RX, RY>(bs, q, a.c);
-    const double d1 = a.a1 * u1 + a.c1 * inv_d * (b - ku1);
-    xp[g] = u1 + d1;
-  });
+  double* r = a.d0 + (size_t)col * a.ldf;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int i = threadIdx.x + k * kT;
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int gx = T.x0 + lx, gy = T.y0 + ly, gz = T.z0 + lz;
+    if (gx < nf && gy < nf && gz < nf) {
+      const size_t g = ((size_t)gz * nf + gy) * nf + gx;
+      const int q = ((lz + 1) * RY + ly + 1) * RX + lx + 1;
+      xp[g] = sh[q];
+      r[g] = bc[k] - k7<RX, RY>(sh, q, a.c);
+    }
+  }
 }
 
-// restrict: r = b - K u_2 on the fine nodes around the coarse tile, then
-// b_c = P^T r: the coincident node plus half of each of its 14 neighbours
-// along the seven edge directions.
+// restrict: b_c = P^T r, the coincident fine node plus half of each of its 14
+// neighbours along the seven edge directions, from r on the fine nodes
+// around the coarse tile.
 __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
-  constexpr int SX = 2 * CX + 1, SY = 2 * CY + 1, SZ = 2 * CZ + 1;   // residual region
-  constexpr int UX = SX + 2, UY = SY + 2, UZ = SZ + 2;               // iterate region
-  __shared__ double us[UX * UY * UZ];
+  constexpr int SX = 2 * CX + 1, SY = 2 * CY + 1, SZ = 2 * CZ + 1;
   __shared__ double rs[SX * SY * SZ];
   STS_MG3_PROLOGUE(a)
   const Tile3 C = tile_of(t, a.ntx, a.nty, CX, CY, CZ);
   const int nf = a.nf, nc = a.nc;
-  const int fx0 = 2 * C.x0, fy0 = 2 * C.y0, fz0 = 2 * C.z0;   // residual region origin
-  const double* xp = a.xp + (size_t)col * a.ldf;
-  const double* bf = a.bf + (size_t)col * a.ldf;
-  for (int i = threadIdx.x; i < UX * UY * UZ; i += kT) {
-    const int gx = fx0 - 1 + i % UX, gy = fy0 - 1 + (i / UX) % UY, gz = fz0 - 1 + i / (UX * UY);
-    const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
-    us[i] = in ? xp[((size_t)gz * nf + gy) * nf + gx] : 0.0;
-  }
+  const int fx0 = 2 * C.x0, fy0 = 2 * C.y0, fz0 = 2 * C.z0;
+  const double* r = a.d0 + (size_t)col * a.ldf;
   for (int i = threadIdx.x; i < SX * SY * SZ; i += kT) {
     const int gx = fx0 + i % SX, gy = fy0 + (i / SX) % SY, gz = fz0 + i / (SX * SY);
-    const bool in = gx < nf && gy < nf && gz < nf;
-    rs[i] = in ? bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < SX * SY * SZ; i += kT) {
-    const int lx = i % SX, ly = (i / SX) % SY, lz = i / (SX * SY);
-    // nodes outside the domain keep r = 0 (no coarse node gathers them)
-    if (fx0 + lx < nf && fy0 + ly < nf && fz0 + lz < nf)
-      rs[i] -= k7<UX, UY>(us, ((lz + 1) * UY + ly + 1) * UX + lx + 1, a.c);
+    // fine nodes beyond the domain are never gathered (every coarse node's
+    // neighbours lie inside); read them as zero
+    rs[i] = (gx < nf && gy < nf && gz < nf) ? r[((size_t)gz * nf + gy) * nf + gx] : 0.0;
   }
   __syncthreads();
   double* bc = a.bc + (size_t)col * a.ldc;
@@ -395,8 +434,32 @@ struct PCG3Args {
   int rz_tiles;
   double* alpha;
   int max_tiles;
+  const double* tot;   // (r, r), (r, z), (p, q) per column (3 x kMaxCols), or null:
+                       // each work-group then adds the per-tile partials itself
   const double* b[kMaxCols];
 };
+
+// Large grids: one work-group per column and quantity adds the per-tile
+// partials (fixed order) so that the PCG launches read one total each.
+constexpr int kSplitReduceTiles = 1024;
+
+struct Reduce3Args {
+  const double* part[2];   // partial arrays, column stride max_tiles
+  int count[2];            // partials per column
+  double* out[2];          // totals per column
+  int max_tiles;
+  int cols[kMaxCols];
+};
+
+__global__ __launch_bounds__(kT) void pcg3_reduce_kernel(Reduce3Args a) {
+  __shared__ double red[kT / 64];
+  const int col = a.cols[blockIdx.x], q = blockIdx.y;
+  const double* p = a.part[q] + (size_t)col * a.max_tiles;
+  double s = 0.0;
+  for (int u = threadIdx.x; u < a.count[q]; u += kT) s += p[u];
+  s = block_sum<kT>(s, red);
+  if (threadIdx.x == 0) a.out[q][col] = s;
+}
 
 #define STS_PCG3_PROLOGUE(A)                                                   \
   const int ntiles = (A).ntx * (A).nty * (A).ntz;                              \
@@ -423,19 +486,24 @@ __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
     return;
   }
   double rr = 0.0, rz = 0.0;
-  const double* prr = a.part_rr + (size_t)col * a.max_tiles;
-  const double* prz = a.part_rz + (size_t)col * a.max_tiles;
-  for (int u = threadIdx.x; u < ntiles; u += kT) rr += prr[u];
-  for (int u = threadIdx.x; u < a.rz_tiles; u += kT) rz += prz[u];
-  rr = wave_sum(rr);
-  rz = wave_sum(rz);
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = rr;
-    red[1][threadIdx.x >> 6] = rz;
+  if (a.tot) {
+    rr = a.tot[col];
+    rz = a.tot[kMaxCols + col];
+  } else {
+    const double* prr = a.part_rr + (size_t)col * a.max_tiles;
+    const double* prz = a.part_rz + (size_t)col * a.max_tiles;
+    for (int u = threadIdx.x; u < ntiles; u += kT) rr += prr[u];
+    for (int u = threadIdx.x; u < a.rz_tiles; u += kT) rz += prz[u];
+    rr = wave_sum(rr);
+    rz = wave_sum(rz);
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = rr;
+      red[1][threadIdx.x >> 6] = rz;
+    }
+    __syncthreads();
+    rr = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    rz = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
   }
-  __syncthreads();
-  rr = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-  rz = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
   double beta;
   const bool go = pcg_decide(s, rr, rz, a.alpha[col], beta);
   if (t == 0 && threadIdx.x == 0) a.next[col] = s;
@@ -474,9 +542,13 @@ __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
   const CGScal s = a.next[col];
   if (!s.active) return;
   double pq = 0.0;
-  const double* ppq = a.part_pq + (size_t)col * a.max_tiles;
-  for (int u = threadIdx.x; u < ntiles; u += kT) pq += ppq[u];
-  pq = block_sum<kT>(pq, red);
+  if (a.tot) {
+    pq = a.tot[2 * kMaxCols + col];
+  } else {
+    const double* ppq = a.part_pq + (size_t)col * a.max_tiles;
+    for (int u = threadIdx.x; u < ntiles; u += kT) pq += ppq[u];
+    pq = block_sum<kT>(pq, red);
+  }
   const bool ok = pq > 0.0 && __builtin_isfinite(pq);
   const double alpha = ok ? s.rho / pq : 0.0;
   if (t == 0 && threadIdx.x == 0) a.alpha[col] = alpha;
@@ -607,7 +679,7 @@ double mg3_bytes_per_node(const MGPlan& p) {
   double b = 80.0 * n0;   // PCG A and B
   for (int l = 0; l < p.nlev; ++l) {
     const double nf = std::pow((double)p.n[l], 3), nc = std::pow((double)p.n[l + 1], 3);
-    b += 16.0 * nf + 8.0 * (2.0 * nf + nc) + 8.0 * (4.0 * nf + nc) + 32.0 * nf;
+    b += 24.0 * nf + 8.0 * (nf + nc) + 8.0 * (4.0 * nf + nc) + 32.0 * nf;
   }
   b += 48.0 * std::pow((double)p.exact, 3);
   return b / n0;
@@ -651,13 +723,13 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     Level3Args a = level(l);
     const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
     int blocks = fine_tiles(a);
-    launch(STS_K_MG_DOWN, 16.0 * nf * nlaunch, mg3_pre_kernel, dim3(blocks), dim3(kT), 0, st, a);
+    launch(STS_K_MG_DOWN, 24.0 * nf * nlaunch, mg3_pre_kernel, dim3(blocks), dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
     a.ntx = (a.nc + CX - 1) / CX;
     a.nty = (a.nc + CY - 1) / CY;
     a.ntz = (a.nc + CZ - 1) / CZ;
     blocks = a.ntx * a.nty * a.ntz * nlaunch;
-    launch(STS_K_MG_DOWN, 8.0 * (2.0 * nf + nc) * nlaunch, mg3_restrict_kernel, dim3(blocks),
+    launch(STS_K_MG_RESTRICT, 8.0 * (nf + nc) * nlaunch, mg3_restrict_kernel, dim3(blocks),
            dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
   }
@@ -711,11 +783,37 @@ void pcg3_setup(const MGWork& w, const double* const* b, const int* cols, int nl
 void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
                   hipStream_t st) {
   mg3_vcycle(w, w.scal + (parity ^ 1) * kMaxCols, cols, nlaunch, true, st);
-  const PCG3Args a = pcg3_args(w, parity, cols, nlaunch, ncols);
-  const int blocks = a.ntx * a.nty * a.ntz * nlaunch;
+  PCG3Args a = pcg3_args(w, parity, cols, nlaunch, ncols);
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int blocks = ntiles * nlaunch;
   const double nn = std::pow((double)a.n, 3) * nlaunch;
+  const bool split = ntiles > kSplitReduceTiles;
+  Reduce3Args r{};
+  r.max_tiles = w.max_tiles;
+  for (int j = 0; j < nlaunch; ++j) r.cols[j] = cols[j];
+  if (split) {
+    // (r, r) from the previous B (or the set-up), (r, z) from this V-cycle
+    r.part[0] = w.part_rr;
+    r.count[0] = ntiles;
+    r.out[0] = w.tot;
+    r.part[1] = w.part_rz;
+    r.count[1] = a.rz_tiles;
+    r.out[1] = w.tot + kMaxCols;
+    launch(STS_K_PCG_REDUCE, 8.0 * (ntiles + a.rz_tiles) * nlaunch, pcg3_reduce_kernel,
+           dim3(nlaunch, 2), dim3(kT), 0, st, r);
+    STS_HIP(hipGetLastError());
+    a.tot = w.tot;
+  }
   launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
+  if (split) {
+    r.part[0] = w.part_pq;
+    r.count[0] = ntiles;
+    r.out[0] = w.tot + 2 * kMaxCols;
+    launch(STS_K_PCG_REDUCE, 8.0 * ntiles * nlaunch, pcg3_reduce_kernel, dim3(nlaunch, 1),
+           dim3(kT), 0, st, r);
+    STS_HIP(hipGetLastError());
+  }
   launch(STS_K_PCG_B, 48.0 * nn, pcg3_b_kernel, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
 }

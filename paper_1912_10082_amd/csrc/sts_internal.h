@@ -215,6 +215,7 @@ struct MGWork {
   double* part_rz;
   double* part_pq;
   double* alpha;                 // kMaxCols
+  double* tot;                   // 3 x kMaxCols: summed partials (3-D, large grids)
   int max_tiles;
   const double* dst;             // device copy of mg_dst_table(plan.exact)
   double* t1;                    // coarsest-level temporaries above kMGCoarseMax
@@ -298,6 +299,15 @@ struct Seg {
 void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double* B, int64_t ldb,
                     double* out, double* partial, unsigned* counter, hipStream_t st);
 int64_t residual_norm2_partial_size(int64_t rows, int n);
+
+// Upper-triangular factor of a rows x n matrix (rows >= n) by blocked
+// Householder QR: A is overwritten, Rc (n x n, ld n) receives R with zeros
+// below the diagonal.  work: qr_r_work_doubles(rows, n) doubles.
+constexpr int kQrNb = 8;            // panel width
+constexpr int kQrMaxRows = 4096;    // panel held in registers of 1024 threads
+bool qr_r_supported(int64_t rows, int n);
+size_t qr_r_work_doubles(int64_t rows, int n);
+void qr_r(int64_t rows, int n, double* A, int64_t lda, double* Rc, double* work, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // small dense helpers (one work-group)
