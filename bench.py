@@ -269,8 +269,9 @@ def bench_batch(args) -> int:
 
 def bench_serve(args) -> int:
     """Poisson arrivals (rate --serve-rate, seed 5) over --serve-seconds of
-    requests drawn by workloads.serving_mix (45% 1-D, 45% 2-D, 10% 3-D; Nt
-    log-uniform in [128, 2048]; P in 1..4; mu log-uniform in [0.1, 10]),
+    requests drawn by workloads.serving_mix (45% 1-D, 45% 2-D, 10% 3-D with
+    sides 63 to 127; Nt log-uniform in [128, 2048]; P in 1..4; mu
+    log-uniform in [0.1, 10]),
     served by --serve-workers workers under a 200 GiB footprint budget, each
     to a relative residual of 1e-8.
     Reports completed solves/s, p50/p99 latency (submission to factors ready)
@@ -370,7 +371,13 @@ def bench_serve(args) -> int:
             pr.solve(**opts)
             Va, Ya = pr.factors()
         equal += int(np.array_equal(V, Va) and np.array_equal(Y, Ya))
-        if w.nh * w.nt <= 4e6:
+        if w.dim == 3 and w.nh * w.nt <= 1.5e8:
+            # 3-D: the oracle's sine-mode exact solve (a sparse factorisation of
+            # a 63^3 step matrix does not fit the check's time)
+            Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+            U = exact.modal_solve_3d(w.n[0], w.mu, Dt, Mt, w.F1, w.F2)
+            errs.append(float(np.linalg.norm(V @ Y - U) / np.linalg.norm(U)))
+        elif w.dim < 3 and w.nh * w.nt <= 4e6:
             K, M = fem.spatial_operators(w.dim, w.n[0], w.mu)
             Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
             U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
@@ -479,10 +486,11 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    p_rank = 4 if d3 else 2
     if d3:
-        w = wl.heat_3d_separable(n=args.n, nt=args.nt, p=4, seed=3)
+        w = wl.heat_3d_separable(n=args.n, nt=args.nt, p=p_rank, seed=3)
     else:
-        w = wl.heat_2d_bumps(n=args.n, nt=args.nt, p=2, seed=2)
+        w = wl.heat_2d_bumps(n=args.n, nt=args.nt, p=p_rank, seed=2)
     t = wl.time_grid(w.nt, w.T)
     dd, ds, md, ms = sts.time_matrices(t)
     F1 = torch.from_numpy(np.asarray(w.F1)).cuda()
@@ -542,8 +550,11 @@ def main() -> int:
                               "of the same workload after the timed steps"}
         flops = None
         if name == "residual":
-            # ||[F1, Kx V, Mx V] B||: 2 Nh (p + 2k) Nt flops per launch on the FP64 matrix cores
-            flops = 2.0 * w.nh * (2 + 2 * last["k"]) * w.nt * n
+            # ||[F1, Kx V, Mx V] B^T||: 2 Nh m Nt flops per launch on the FP64 matrix cores
+            # (m = P + 2k), or 2 Nh m^2 when B was first reduced to its QR factor
+            m = p_rank + 2 * last["k"]
+            qr = ksum.get("residual_qr", [0.0, 0, 0.0])[1] > 0
+            flops = 2.0 * w.nh * m * (m if qr else w.nt) * n
         elif name == "mg_coarse" and not d3 and (_coarse_order(w.n[0]) + 1) not in (128, 256):
             # exact coarse solve as m x m GEMMs on the matrix cores (operands
             # L2-resident, 2 m^3 flops per 24 m^2 algorithmic bytes per column);

@@ -111,13 +111,21 @@ typedef struct {
                                Kx and Mx by a direct tridiagonal solve; 2-D P1 with n <= 63
                                or n odd halving, n -> (n-1)/2, down to <= 255: Kx by CG
                                preconditioned with one geometric multigrid V-cycle, Mx by
-                               Chebyshev iteration; 0 = plain CG for both; default 1 */
+                               Chebyshev iteration; 3-D trilinear: Mx by direct line solves,
+                               Kx by multigrid-preconditioned CG when n <= 63 or n odd halving
+                               down to <= 63 (else plain CG); 0 = plain CG for both; default 1 */
   int32_t rational;         /* projection space: 0 = extended Krylov (poles 0 and infinity);
                                1 = rational Krylov with adaptive shifts (Sec. 4): after the
                                extended start block, each step applies (Kx + s Mx)^{-1} Mx to
                                the last block, s chosen by the greedy rule of
                                sts_adaptive_shift from the Ritz values; convergence is
                                checked on the exact residual; default 0 */
+  int32_t residual_qr;      /* exact residual ||A B^T|| (A = [F1, Kx V, Mx V], B its time
+                               factor, Nt x (P + 2k)): 1 = through the Householder QR of B,
+                               ||A R_B^T||, whenever 2 (P + 2k) <= Nt <= 4096; -1 = always the
+                               direct Nh x Nt product; 0 = the cheaper of the two by a cost
+                               model; default 0 */
+  int32_t pad_;
 } sts_opts;
 
 typedef struct {
@@ -158,7 +166,8 @@ typedef enum {
   STS_K_TRIDIAG_SOLVE = 16, /* direct tridiagonal inner solve (1-D) */
   STS_K_MG_RESTRICT = 17,   /* multigrid (3-D): residual and restriction */
   STS_K_PCG_REDUCE = 18,    /* preconditioned CG (3-D): sums of per-tile partials */
-  STS_K_COUNT = 19
+  STS_K_RESIDUAL_QR = 19,   /* Householder QR of the residual's time factor */
+  STS_K_COUNT = 20
 } sts_kernel;
 
 typedef struct sts_problem sts_problem;

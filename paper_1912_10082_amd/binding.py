@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "STS_OK", 1: "STS_E_INVALID", 2: "STS_E_NOMEM", 3: "STS_E_DEV
 STS_MEM_HOST, STS_MEM_DEVICE = 0, 1
 STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT = 1, 2, 3
 STS_OP_K, STS_OP_M = 0, 1
-STS_K_COUNT = 19
+STS_K_COUNT = 20
 
 
 class STSError(RuntimeError):
@@ -44,7 +44,8 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32), ("verify_true", C.c_int32),
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
-                ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32)]
+                ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32),
+                ("residual_qr", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Info(C.Structure):

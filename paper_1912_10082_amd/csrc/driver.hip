@@ -544,6 +544,7 @@ struct sts_problem {
   std::vector<int> tags;  // 0: positive power, 1: negative power
   DevBuf V, MV, KV, Kred, Mred, beta;
   DevBuf qr_work, qr_R;   // exact residual through the QR of the time factor
+  int residual_qr = 0;    // sts_opts::residual_qr of the last solve
 
   // CG
   DevBuf cg_r, cg_p, cg_scal, cg_part, counters;
@@ -756,7 +757,15 @@ double true_residual(sts_problem* P) {
                  {P->MV.d(), P->ldv, (int)ks}};
   const int nseg = ks > 0 ? 3 : 1;
   const int mtot = (int)(p + (ks > 0 ? 2 * ks : 0));
-  if (nt >= 2 * (int64_t)mtot && qr_r_supported(nt, mtot)) {
+  bool use_qr = nt >= 2 * (int64_t)mtot && qr_r_supported(nt, mtot) && P->residual_qr >= 0;
+  if (use_qr && P->residual_qr == 0) {
+    // the direct product costs 2 Nh m Nt flops on the matrix cores, the QR
+    // path 2 Nh m^2 flops plus about 60 us per 8-column panel (measured on
+    // the MI355X); take it when it saves more than that at ~40 TFLOP/s
+    const double saved = 2.0 * (double)P->nh * mtot * (double)(nt - mtot) / 40e12;
+    use_qr = saved > (mtot / (double)kQrNb) * 60e-6;
+  }
+  if (use_qr) {
     // ||A B^T|| = ||A R_B^T|| with B = Q_B R_B: an Nh x mtot x mtot product
     // instead of Nh x mtot x Nt
     const size_t wd = qr_r_work_doubles(nt, mtot);
@@ -1287,8 +1296,10 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     sts_default_opts(&o);
     if (opts_in) o = *opts_in;
     STS_REQUIRE(o.tol > 0.0 && o.max_outer >= 1 && o.inner_rtol > 0.0 && o.inner_maxit >= 1 &&
-                    o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0,
+                    o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0 &&
+                    o.residual_qr >= -1 && o.residual_qr <= 1,
                 STS_E_INVALID, "invalid options");
+    P->residual_qr = o.residual_qr;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = P->stream;
     const int p = P->p;
@@ -1571,7 +1582,7 @@ const char* sts_kernel_name(int32_t kernel) {
       "cg_iter",   "mg_down",  "mg_up",   "mg_coarse",     "pcg_a", "pcg_b",
       "mass_cheb", "gram",     "basis_update", "residual", "tridiag", "bisect",
       "inviter",   "backtransform", "sweep", "stencil", "tridiag_solve",
-      "mg_restrict", "pcg_reduce"};
+      "mg_restrict", "pcg_reduce", "residual_qr"};
   return (kernel >= 0 && kernel < STS_K_COUNT) ? names[kernel] : "";
 }
 

@@ -221,19 +221,26 @@ void qr_r(int64_t rows, int n, double* A, int64_t lda, double* Rc, double* work,
   for (int j0 = 0; j0 < n; j0 += kQrNb) {
     const int nb = std::min(kQrNb, n - j0);
     const int64_t L = rows - j0;
+    // profiled as the residual's QR (the Gram products below count under the
+    // Gram kernel)
+    const double pb = 16.0 * (double)L * nb;
     if (L <= kQrT)
-      qr_panel_kernel<1><<<1, kQrT, 0, st>>>(rows, j0, nb, A, lda, V, L, T);
+      launch(STS_K_RESIDUAL_QR, pb, qr_panel_kernel<1>, dim3(1), dim3(kQrT), 0, st, rows, j0, nb, A,
+             lda, V, L, T);
     else if (L <= 2 * kQrT)
-      qr_panel_kernel<2><<<1, kQrT, 0, st>>>(rows, j0, nb, A, lda, V, L, T);
+      launch(STS_K_RESIDUAL_QR, pb, qr_panel_kernel<2>, dim3(1), dim3(kQrT), 0, st, rows, j0, nb, A,
+             lda, V, L, T);
     else
-      qr_panel_kernel<4><<<1, kQrT, 0, st>>>(rows, j0, nb, A, lda, V, L, T);
+      launch(STS_K_RESIDUAL_QR, pb, qr_panel_kernel<4>, dim3(1), dim3(kQrT), 0, st, rows, j0, nb, A,
+             lda, V, L, T);
     STS_HIP(hipGetLastError());
     const int m = n - j0 - nb;
     if (m <= 0) continue;
     double* At = A + j0 + (int64_t)(j0 + nb) * lda;
     gemm_tn(L, m, nb, At, lda, V, L, C, m, part, st);   // C = At^T V (m x nb)
     const dim3 grid((unsigned)((L + 255) / 256), (unsigned)((m + kUpdCols - 1) / kUpdCols));
-    qr_update_kernel<<<grid, 256, 0, st>>>(L, m, nb, At, lda, V, L, C, m, T);
+    launch(STS_K_RESIDUAL_QR, 8.0 * (double)L * (2.0 * m + nb), qr_update_kernel, grid, dim3(256), 0,
+           st, L, m, nb, At, lda, (const double*)V, L, (const double*)C, m, (const double*)T);
     STS_HIP(hipGetLastError());
   }
   qr_copy_r_kernel<<<(unsigned)(((int64_t)n * n + 255) / 256), 256, 0, st>>>(n, A, lda, Rc);

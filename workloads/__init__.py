@@ -251,7 +251,7 @@ def heat_1d_profiles(n: int = 1023, nt: int = 256, p: int = 2, seed: int = 5,
 
 def serving_mix(count: int, seed: int = 5, frac_1d: float = 0.45, frac_2d: float = 0.45,
                 nx_1d=(1000, 8192), sides_2d=(63, 95, 127, 191, 255, 383, 511),
-                sides_3d=(15, 23, 31), nt_range=(128, 2048)) -> list:
+                sides_3d=(63, 95, 127), nt_range=(128, 2048)) -> list:
     """Request shapes of a serving workload: (dim, n, nt, p, mu, seed) tuples.
 
     One generator default_rng(seed) draws, per request and in this order: a
