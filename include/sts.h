@@ -125,7 +125,11 @@ typedef struct {
                                ||A R_B^T||, whenever 2 (P + 2k) <= Nt <= 4096; -1 = always the
                                direct Nh x Nt product; 0 = the cheaper of the two by a cost
                                model; default 0 */
-  int32_t pad_;
+  int32_t inner_relax;      /* j = 1..6: relax the inner tolerance as the residual falls
+                               (inexact Krylov): the inner solves of each block stop at
+                               max(inner_rtol, min(1e-4, 10^-j tol / r)), r the last projected
+                               residual estimate (1 before the first check); the exact residual
+                               still decides convergence; 0 = inner_rtol throughout; default 0 */
 } sts_opts;
 
 typedef struct {

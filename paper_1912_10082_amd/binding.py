@@ -45,7 +45,7 @@ class Opts(C.Structure):
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32), ("verify_true", C.c_int32),
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
                 ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32),
-                ("residual_qr", C.c_int32), ("pad_", C.c_int32)]
+                ("residual_qr", C.c_int32), ("inner_relax", C.c_int32)]
 
 
 class Info(C.Structure):

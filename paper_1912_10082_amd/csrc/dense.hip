@@ -46,7 +46,10 @@ struct TnPlan {
 TnPlan tn_plan(int64_t rows, int m) {
   TnPlan p{};
   const int tiles = (m + 15) / 16;
-  p.T = tiles >= 4 ? 4 : (tiles >= 2 ? 2 : 1);
+  // four tiles per work-group once there are at least two such groups; below
+  // that two tiles, so that narrow bases still spread over two or more groups
+  // (m = 60 on 261121 rows: 4.0 TB/s against 2.9 TB/s with one 4-tile group)
+  p.T = tiles >= 8 ? 4 : (tiles >= 2 ? 2 : 1);
   p.NW = p.T == 1 ? 16 : 4;
   p.groups = (tiles + p.T - 1) / p.T;
   // about 512 work-groups in all, at least 64 rows per wave
@@ -201,6 +204,57 @@ __global__ __launch_bounds__(256) void gemm_nn_sub_kernel(int64_t rows, int m, i
     for (int q = 0; q < 4; ++q) {
       const int64_t row = r0 + 4 * q + g;
       if (row < rows) W[row + (int64_t)i * ldw] -= acc[q];
+    }
+  }
+}
+
+// The same product with 64 rows per wave: lane (i, g) feeds rows
+// r0 + 4 i .. r0 + 4 i + 3 of column k0 + g to four MFMAs with independent
+// accumulators (one 32-byte load per lane and step, four chains instead of
+// one); accumulator s of the lane holds rows r0 + 4 (4 q + g) + s.
+template <bool VEC>
+__global__ __launch_bounds__(256) void gemm_nn_sub4_kernel(int64_t rows, int m, int n,
+                                                           const double* A, int64_t lda,
+                                                           const double* C, int64_t ldc,
+                                                           double* W, int64_t ldw) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+  if (r0 >= rows) return;
+  const int64_t ra = r0 + 4 * i;
+  const bool full = ra + 3 < rows;
+  const bool cok = i < n;
+  d4 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += 4) {
+    const int kk = k0 + g;
+    const bool kok = kk < m;
+    const double* ap = A + ra + (int64_t)(kok ? kk : 0) * lda;
+    double a[4];
+    if (VEC && full) {
+      const double2 x = kok ? *(const double2*)ap : double2{0.0, 0.0};
+      const double2 y = kok ? *(const double2*)(ap + 2) : double2{0.0, 0.0};
+      a[0] = x.x;
+      a[1] = x.y;
+      a[2] = y.x;
+      a[3] = y.y;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[s] = (kok && ra + s < rows) ? ap[s] : 0.0;
+    }
+    const double b = (cok && kok) ? C[kk + (int64_t)i * ldc] : 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = mfma(a[s], b, acc[s]);
+  }
+  if (cok) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t row = r0 + 4 * (4 * q + g) + s;
+        if (row < rows) W[row + (int64_t)i * ldw] -= acc[s][q];
+      }
     }
   }
 }
@@ -565,9 +619,21 @@ void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const
                  int64_t ldc, double* W, int64_t ldw, hipStream_t st) {
   if (m <= 0 || n <= 0 || rows <= 0) return;
   STS_REQUIRE(n <= 16, STS_E_INVALID, "gemm_nn_sub: n > 16");
-  const int64_t blocks = (rows + 63) / 64;
-  launch(STS_K_BASIS_UPDATE, 8.0 * (double)rows * (m + 2 * n), gemm_nn_sub_kernel,
-         dim3((unsigned)blocks), dim3(256), 0, st, rows, m, n, A, lda, C, ldc, W, ldw);
+  const double bytes = 8.0 * (double)rows * (m + 2 * n);
+  if (rows >= 64 * 1024) {
+    // tall blocks: 64 rows per wave, four accumulator chains
+    const int64_t blocks = (rows + 255) / 256;
+    if (aligned16(A) && lda % 2 == 0)
+      launch(STS_K_BASIS_UPDATE, bytes, gemm_nn_sub4_kernel<true>, dim3((unsigned)blocks),
+             dim3(256), 0, st, rows, m, n, A, lda, C, ldc, W, ldw);
+    else
+      launch(STS_K_BASIS_UPDATE, bytes, gemm_nn_sub4_kernel<false>, dim3((unsigned)blocks),
+             dim3(256), 0, st, rows, m, n, A, lda, C, ldc, W, ldw);
+  } else {
+    const int64_t blocks = (rows + 63) / 64;
+    launch(STS_K_BASIS_UPDATE, bytes, gemm_nn_sub_kernel, dim3((unsigned)blocks), dim3(256), 0,
+           st, rows, m, n, A, lda, C, ldc, W, ldw);
+  }
   STS_HIP(hipGetLastError());
 }
 

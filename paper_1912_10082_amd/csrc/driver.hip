@@ -1297,7 +1297,8 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     if (opts_in) o = *opts_in;
     STS_REQUIRE(o.tol > 0.0 && o.max_outer >= 1 && o.inner_rtol > 0.0 && o.inner_maxit >= 1 &&
                     o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0 &&
-                    o.residual_qr >= -1 && o.residual_qr <= 1,
+                    o.residual_qr >= -1 && o.residual_qr <= 1 && o.inner_relax >= 0 &&
+                    o.inner_relax <= 6,
                 STS_E_INVALID, "invalid options");
     P->residual_qr = o.residual_qr;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1312,6 +1313,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       P->alg_bytes = 0.0;
       P->checks = 0;
       P->shifts.clear();
+      P->last_cheap = -1.0;
     }
     // kernel timing for sts_kernel_profile, active until this call returns
     struct ProfGuard {
@@ -1347,7 +1349,10 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
           b[c] = b[p + c] = P->F1.d() + c * P->ldv;
         }
         int perm[kMaxCols];
-        run_cg_block(P, ops, b2, b, o, perm);
+        sts_opts oi = o;
+        const double relax = o.inner_relax ? std::pow(10.0, -o.inner_relax) : 0.0;
+        if (o.inner_relax) oi.inner_rtol = std::max(o.inner_rtol, std::min(1e-4, relax * o.tol));
+        run_cg_block(P, ops, b2, b, oi, perm);
         int idx[16];
         const int kept = append_block(P, b2, o.defl_tol, idx);
         P->blk_start = 0;
@@ -1367,6 +1372,14 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       // solves make the projected value read low)
       double ratio = 1.0;
       for (outer = 1; outer <= o.max_outer; ++outer) {
+        // inner tolerance of this block: relaxed in inverse proportion to the
+        // residual (the block's share of the solution shrinks with it)
+        sts_opts oi = o;
+        if (o.inner_relax) {
+          const double r = P->last_cheap > 0.0 ? std::min(1.0, ratio * P->last_cheap) : 1.0;
+          oi.inner_rtol = std::max(o.inner_rtol,
+                                   std::min(1e-4, std::pow(10.0, -o.inner_relax) * o.tol / r));
+        }
         // expand with the last block
         const int64_t bs = P->blk_start, bsz = P->blk_size;
         int ops[kMaxCols];
@@ -1390,7 +1403,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
             perm[n] = n;
             ++n;
           }
-          run_shifted_block(P, sft, n, b, o);
+          run_shifted_block(P, sft, n, b, oi);
         } else {
           for (int64_t j = 0; j < bsz; ++j) {
             const int tag = P->tags[bs + j];
@@ -1399,7 +1412,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
             b[n] = (tag == 0 ? P->KV.d() : P->MV.d()) + (bs + j) * P->ldv;
             ++n;
           }
-          run_cg_block(P, ops, n, b, o, perm);
+          run_cg_block(P, ops, n, b, oi, perm);
         }
         std::vector<int> src_tag(n);
         for (int j = 0; j < n; ++j) src_tag[j] = P->tags[bs + perm[j]];

@@ -245,3 +245,32 @@ def test_3d_solve_with_and_without_multigrid_match_the_modal_solution(n, nt, p, 
         assert rel(V @ Y, U) <= 1e-8, (pre, rel(V @ Y, U))
         res[pre] = info
     assert res[1]["inner_its_K"] * 10 < res[0]["inner_its_K"], (res[0], res[1])
+
+
+@pytest.mark.parametrize("dim,n,nt,p", [(2, 127, 64, 2), (3, 65, 24, 3), (1, 2047, 48, 2)])
+def test_relaxed_inner_tolerance_keeps_the_solution(dim, n, nt, p):
+    """Inner solves stopped at max(inner_rtol, min(1e-4, 10^-j tol / r)), j = 1, 2
+    (inexact Krylov): the same tolerance on the exact residual, the same
+    accuracy against the oracle, fewer inner iterations."""
+    if dim == 1:
+        w = wl.heat_1d_profiles(n=n, nt=nt, p=p, seed=51)
+    elif dim == 2:
+        w = wl.heat_2d_bumps(n=n, nt=nt, p=p, seed=52)
+    else:
+        w = wl.heat_3d_separable(n=n, nt=nt, p=p, seed=53)
+    Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+    if dim == 3:
+        U = exact.modal_solve_3d(n, w.mu, Dt, Mt, w.F1, w.F2)
+    else:
+        K, M = fem.spatial_operators(dim, n, w.mu)
+        U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
+    res = {}
+    for relax in (0, 1, 2):
+        info, V, Y = _solve(w, tol=1e-10, inner_relax=relax)
+        assert info["status"] == "STS_OK", info
+        assert info["res_true"] <= 1e-10
+        assert rel(V @ Y, U) <= 1e-8, (relax, rel(V @ Y, U))
+        res[relax] = info
+    if dim > 1:
+        assert res[1]["inner_its_K"] < res[0]["inner_its_K"], (res[0], res[1])
+        assert res[2]["inner_its_K"] < res[0]["inner_its_K"], (res[0], res[2])

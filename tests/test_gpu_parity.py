@@ -136,9 +136,12 @@ def test_1d_large_solve_with_direct_inner_solves():
 # ---------------------------------------------------------------- a4: Gram-Schmidt
 
 # Covers one, two and four 16-column tiles per work-group, odd leading
-# dimensions (8-byte loads) and even ones (16-byte loads), ragged row chunks.
+# dimensions (8-byte loads) and even ones (16-byte loads), ragged row chunks;
+# from 65536 rows the update takes 64 rows per wave (ragged last waves, m not
+# a multiple of 4, both load widths).
 @pytest.mark.parametrize("rows,m,n", [(1000, 37, 5), (4099, 16, 16), (17, 3, 1), (70000, 130, 8),
-                                      (100003, 240, 8), (100000, 68, 16), (261121, 4, 4)])
+                                      (100003, 240, 8), (100000, 68, 16), (261121, 4, 4),
+                                      (70002, 37, 3), (65536, 1, 16)])
 def test_gram_and_update_match_numpy(rows, m, n):
     rng = np.random.default_rng(rows + m)
     A, B, Cm = rng.normal(size=(rows, m)), rng.normal(size=(rows, n)), rng.normal(size=(m, n))
