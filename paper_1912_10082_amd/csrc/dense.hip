@@ -312,6 +312,7 @@ struct ResArgs {
   int m[3];
   const double* BT;
   int64_t ldbt;
+  int upper;        // 1: BT[j][t] = 0 for j < t (a triangular factor), rows j < t skipped
   double* partial;
   unsigned* counter;
   double* out;
@@ -339,10 +340,17 @@ __global__ __launch_bounds__(256, 2) void residual_kernel(ResArgs a) {
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
   int kb = 0;   // first row of BT of the segment
+  // with a triangular BT this wave's columns c0 .. c0 + 63 need rows j >= c0
+  const int kfirst = a.upper ? (c0 & ~3) : 0;
   for (int s = 0; s < a.nseg; ++s) {
     const double* A = a.A[s];
     const int64_t lda = a.lda[s];
     const int m = a.m[s];
+    const int k00 = kfirst > kb ? ((kfirst - kb) & ~3) : 0;
+    if (k00 >= m) {
+      kb += m;
+      continue;
+    }
     auto load = [&](int k0, double* av, double* bv) {
       const int kk = k0 + g;
       const bool kok = kk < m;
@@ -369,8 +377,8 @@ __global__ __launch_bounds__(256, 2) void residual_kernel(ResArgs a) {
       }
     };
     double av[4], bv[4], an[4], bn[4];
-    load(0, av, bv);
-    for (int k0 = 0; k0 < m; k0 += 4) {
+    load(k00, av, bv);
+    for (int k0 = k00; k0 < m; k0 += 4) {
       if (k0 + 4 < m) load(k0 + 4, an, bn);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
@@ -668,7 +676,7 @@ int64_t residual_norm2_partial_size(int64_t rows, int n) {
 
 void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double* BT,
                     int64_t ldbt, double* out, double* partial, unsigned* counter,
-                    hipStream_t st) {
+                    hipStream_t st, bool upper) {
   STS_REQUIRE(nseg >= 1 && nseg <= 3, STS_E_INVALID, "residual_norm2: 1..3 segments");
   ResArgs a{};
   a.rows = rows;
@@ -685,6 +693,7 @@ void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double
   }
   a.BT = BT;
   a.ldbt = ldbt;
+  a.upper = upper ? 1 : 0;
   a.partial = partial;
   a.counter = counter;
   a.out = out;

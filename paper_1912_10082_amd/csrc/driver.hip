@@ -773,7 +773,7 @@ double true_residual(sts_problem* P) {
     if (P->qr_R.bytes < (size_t)mtot * mtot * 8) P->qr_R.alloc((size_t)mtot * mtot * 8);
     qr_r(nt, mtot, BT, ldbt, P->qr_R.d(), P->qr_work.d(), st);
     residual_norm2(P->nh, mtot, segs, nseg, P->qr_R.d(), mtot, P->smallv.d(), P->res_part.d(),
-                   P->counter(1), st);
+                   P->counter(1), st, true);
     P->alg_bytes += 8.0 * P->nh * mtot * ((mtot + 255) / 256);
   } else {
     residual_norm2(P->nh, (int)nt, segs, nseg, BT, ldbt, P->smallv.d(), P->res_part.d(),

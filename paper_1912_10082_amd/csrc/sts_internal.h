@@ -296,8 +296,10 @@ struct Seg {
   int64_t lda;
   int m;
 };
+// upper: B[j][t] = 0 for j < t (B^T a triangular factor); those products are skipped.
 void residual_norm2(int64_t rows, int n, const Seg* segs, int nseg, const double* B, int64_t ldb,
-                    double* out, double* partial, unsigned* counter, hipStream_t st);
+                    double* out, double* partial, unsigned* counter, hipStream_t st,
+                    bool upper = false);
 int64_t residual_norm2_partial_size(int64_t rows, int n);
 
 // Upper-triangular factor of a rows x n matrix (rows >= n) by blocked

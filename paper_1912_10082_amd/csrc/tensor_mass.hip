@@ -7,7 +7,7 @@
 // pivoting; T is strictly diagonally dominant).  The elimination factors of T
 // depend only on the line length and are computed once per problem.  One
 // thread per line; lines along y and z are read and written coalesced across
-// threads, lines along x with stride n.
+// threads, lines along x are staged through LDS in chunks.
 #include <hip/hip_runtime.h>
 
 #include "sts_internal.h"
@@ -72,6 +72,72 @@ __global__ __launch_bounds__(256) void tensor_mass_kernel(TensorArgs a) {
   }
 }
 
+// Lines along x are contiguous, so one thread per line would read 64
+// different cache lines per wave access.  Here each wave stages chunks of
+// kChunk elements of its 64 lines through LDS: loads and stores are
+// coalesced along x, and each thread runs the recurrences of its own line on
+// the staged chunk.  Forward sweep left to right (y written out), then the
+// backward sweep right to left over y.
+constexpr int kChunk = 16;
+__global__ __launch_bounds__(256) void tensor_mass_x_kernel(TensorArgs a) {
+  __shared__ double tile[4][64][kChunk + 1];
+  const int n = a.n;
+  const int64_t lines = (int64_t)n * n;
+  const int c = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t line0 = (int64_t)blockIdx.x * 256 + wv * 64;   // this wave's first line
+  const double* in = a.in[c];
+  double* out = a.out[c];
+  const double* cf = a.fac;
+  const double* mf = a.fac + n;
+  double (*T)[kChunk + 1] = tile[wv];
+  const int nch = (n + kChunk - 1) / kChunk;
+  double y = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int x0 = ch * kChunk;
+    for (int e = lane; e < 64 * kChunk; e += 64) {
+      const int l = e / kChunk, x = e % kChunk;
+      const int64_t line = line0 + l;
+      T[l][x] = (line < lines && x0 + x < n) ? in[line * n + x0 + x] : 0.0;
+    }
+    __syncthreads();
+    for (int x = 0; x < kChunk && x0 + x < n; ++x) {
+      y = (a.scale * T[lane][x] - y) * mf[x0 + x];
+      T[lane][x] = y;
+    }
+    __syncthreads();
+    for (int e = lane; e < 64 * kChunk; e += 64) {
+      const int l = e / kChunk, x = e % kChunk;
+      const int64_t line = line0 + l;
+      if (line < lines && x0 + x < n) out[line * n + x0 + x] = T[l][x];
+    }
+    __syncthreads();
+  }
+  double z = 0.0;
+  for (int ch = nch - 1; ch >= 0; --ch) {
+    const int x0 = ch * kChunk;
+    for (int e = lane; e < 64 * kChunk; e += 64) {
+      const int l = e / kChunk, x = e % kChunk;
+      const int64_t line = line0 + l;
+      T[l][x] = (line < lines && x0 + x < n) ? out[line * n + x0 + x] : 0.0;
+    }
+    __syncthreads();
+    for (int x = kChunk - 1; x >= 0; --x) {
+      if (x0 + x < n) {
+        z = T[lane][x] - cf[x0 + x] * z;
+        T[lane][x] = z;
+      }
+    }
+    __syncthreads();
+    for (int e = lane; e < 64 * kChunk; e += 64) {
+      const int l = e / kChunk, x = e % kChunk;
+      const int64_t line = line0 + l;
+      if (line < lines && x0 + x < n) out[line * n + x0 + x] = T[l][x];
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 bool tensor_mass_supported(const Grid& g, const Stencil& M) {
@@ -114,9 +180,14 @@ void tensor_mass_solve(const Grid& g, const Stencil& M, int ncols, const double*
       a.in[c] = axis == 0 ? b[c] : x + c * ldx;
       a.out[c] = x + c * ldx;
     }
-    // read and write every node once per pass
-    launch(STS_K_MASS_CHEB, 16.0 * (double)g.nh * ncols, tensor_mass_kernel, grid, dim3(256), 0,
-           st, a);
+    // read and write every node once per pass (the x pass twice: y is stored
+    // between its sweeps)
+    if (axis == 0)
+      launch(STS_K_MASS_CHEB, 32.0 * (double)g.nh * ncols, tensor_mass_x_kernel, grid, dim3(256),
+             0, st, a);
+    else
+      launch(STS_K_MASS_CHEB, 16.0 * (double)g.nh * ncols, tensor_mass_kernel, grid, dim3(256), 0,
+             st, a);
     STS_HIP(hipGetLastError());
   }
 }

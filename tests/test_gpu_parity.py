@@ -259,15 +259,18 @@ def test_2d_solve_matches_crank_nicolson(n, nt, p, seed):
 
 
 @pytest.mark.parametrize("n,nt,p,outer", [(65, 300, 3, 2), (31, 17, 1, 1), (100, 513, 2, 4),
-                                          (47, 1500, 2, 6), (31, 4000, 1, 9), (31, 4500, 1, 3)])
+                                          (47, 1500, 2, 6), (31, 4000, 1, 9), (31, 4500, 1, 3),
+                                          (63, 2600, 3, 12)])
 def test_true_residual_matches_oracle(n, nt, p, outer):
     """a8: the exact Sylvester residual of an unconverged iterate, large
     enough that rounding in either computation is far below the tolerance.
     Row counts not a multiple of 64 and Nt not a multiple of 256 give ragged
     work-group tiles in both directions.  With Nt >= 2 (P + 2k) and Nt <= 4096
     the residual goes through the Householder QR of the time factor (panels
-    of 8 columns held by 1024 threads, 1, 2 or 4 rows per thread); Nt = 17 and
-    Nt = 4500 take the direct product."""
+    of 8 columns held by 1024 threads, 1, 2 or 4 rows per thread), and the
+    product with the triangular factor skips its zero triangle (P + 2k > 64
+    at 63^2: waves whose columns start above row 0); Nt = 17 and Nt = 4500
+    take the direct product."""
     w = wl.heat_2d_bumps(n=n, nt=nt, p=p, seed=40 + n)
     K, M = fem.spatial_operators(2, n, w.mu)
     Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
