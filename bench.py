@@ -44,7 +44,8 @@ sys.path.insert(0, ROOT)
 METRIC = "space-time dof/s at rel. error 1e-8; % HBM roofline; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_2d_n511.json")
+TRAFFIC_FILES = {"heat2d": os.path.join(ROOT, "profiles", "traffic_2d_n511.json"),
+                 "heat3d": os.path.join(ROOT, "profiles", "traffic_3d_n255.json")}
 CSRC = os.path.join(ROOT, "paper_1912_10082_amd", "csrc")
 
 
@@ -52,46 +53,73 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _sources_hash() -> str:
-    h = hashlib.sha256()
-    for fn in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, fn), "rb") as fh:
-            h.update(fn.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+PUBLIC_HEADER = os.path.join(ROOT, "include", "sts.h")
+
+
+def _file_hashes() -> dict:
+    """{source file: first 16 hex digits of its SHA-256} for csrc/ and the
+    public header (which the sources include)."""
+    paths = {fn: os.path.join(CSRC, fn) for fn in sorted(os.listdir(CSRC))}
+    paths["include/sts.h"] = PUBLIC_HEADER
+    out = {}
+    for fn, p in paths.items():
+        with open(p, "rb") as fh:
+            out[fn] = hashlib.sha256(fh.read()).hexdigest()[:16]
+    return out
+
+
+def _kernel_sources(hip_name) -> list:
+    """The source files a kernel's code depends on: the .hip file that defines
+    it and every header."""
+    files = [fn for fn in os.listdir(CSRC) if fn.endswith(".h")] + ["include/sts.h"]
+    for fn in os.listdir(CSRC):
+        if fn.endswith(".hip"):
+            with open(os.path.join(CSRC, fn)) as fh:
+                if f" {hip_name}(" in fh.read():
+                    files.append(fn)
+    return sorted(files)
 
 
 # profiler kernel ids of the library -> HIP kernel names in rocprofv3 output
 HIP_KERNELS = {
-    "mg_coarse": ["dst_gemm_kernel", "mg_coarse_kernel"],
+    "mg_coarse": ["dst_gemm_kernel", "mg_coarse_kernel", "fst_row_kernel", "fst_col_kernel",
+                  "coarse3_plane_kernel", "coarse3_z_kernel"],
     "gram": ["gemm_tn_kernel"],
     "residual": ["residual_kernel"],
-    "basis_update": ["gemm_nn_sub_kernel"],
-    "mg_up": ["mg_up_kernel"],
-    "mg_down": ["mg_down_kernel"],
-    "mass_cheb": ["mass_cheb_kernel"],
-    "pcg_a": ["pcg_a_kernel"],
-    "pcg_b": ["pcg_b_kernel"],
+    "basis_update": ["gemm_nn_sub_kernel", "gemm_nn_sub4_kernel"],
+    "mg_up": ["mg_up_kernel", "mg3_post1_kernel", "mg3_post2_kernel"],
+    "mg_down": ["mg_down_kernel", "mg3_pre_kernel"],
+    "mg_restrict": ["mg3_restrict_kernel"],
+    "mass_cheb": ["mass_cheb_kernel", "tensor_mass_kernel", "tensor_mass_x_kernel"],
+    "pcg_a": ["pcg_a_kernel", "pcg3_a_kernel"],
+    "pcg_b": ["pcg_b_kernel", "pcg3_b_kernel"],
     "stencil": ["apply_kernel"],
 }
 
 
-def _traffic(kernel):
+def _traffic(kernel, path):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    runs (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel factor), if
-    they were taken on the current kernel sources; else None."""
+    runs of the same workload (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    copy-kernel factor), averaged over the HIP kernels behind the profiler id
+    by dispatch count, if every source those kernels depend on is unchanged
+    since the counters were taken; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("sources_sha256_16") != _sources_hash():
-        return None
+    taken, now = d.get("source_sha256_16", {}), _file_hashes()
     ks = d.get("kernels", {})
+    tot, cnt = 0.0, 0
     for name in HIP_KERNELS.get(kernel, [kernel]):
-        if name in ks:
-            return ks[name].get("hbm_bytes_per_launch")
-    return None
+        if name not in ks:
+            continue
+        if any(taken.get(fn) != now.get(fn) for fn in _kernel_sources(name)):
+            return None
+        n = ks[name].get("dispatches", 1)
+        tot += ks[name]["hbm_bytes_per_launch"] * n
+        cnt += n
+    return tot / cnt if cnt else None
 
 
 def _coarse_order(n):
@@ -121,9 +149,9 @@ def calibrate_copy(mib):
     return 0
 
 
-def _pmc_per_kernel(path, counter):
+def _pmc_per_kernel(path, counter, counts=False):
     """Mean value of `counter` per dispatch, by kernel name, from a rocprofv3
-    counter_collection.csv."""
+    counter_collection.csv (with counts: also the number of dispatches)."""
     import csv
     import re
 
@@ -137,6 +165,8 @@ def _pmc_per_kernel(path, counter):
             a = acc.setdefault(name, [0.0, 0])
             a[0] += float(r["Counter_Value"])
             a[1] += 1
+    if counts:
+        return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
     return {k: v[0] / v[1] for k, v in acc.items()}
 
 
@@ -144,7 +174,8 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
     """Write the per-kernel HBM traffic file from two counter runs of the
     benchmark (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) and the same two runs
     of calibrate_copy."""
-    fetch = _pmc_per_kernel(fetch_csv, "FETCH_SIZE")
+    fetch_n = _pmc_per_kernel(fetch_csv, "FETCH_SIZE", counts=True)
+    fetch = {k: v[0] for k, v in fetch_n.items()}
     write = _pmc_per_kernel(write_csv, "WRITE_SIZE")
     cf = _pmc_per_kernel(copy_fetch_csv, "FETCH_SIZE")
     cw = _pmc_per_kernel(copy_write_csv, "WRITE_SIZE")
@@ -157,8 +188,9 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
         fb = 1024.0 * fetch.get(k, 0.0) / f_copy
         wb = 1024.0 * write.get(k, 0.0) / w_copy
         kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-                      "hbm_bytes_per_launch": fb + wb}
-    d = {"sources_sha256_16": _sources_hash(),
+                      "hbm_bytes_per_launch": fb + wb,
+                      "dispatches": fetch_n.get(k, (0.0, 0))[1]}
+    d = {"source_sha256_16": _file_hashes(),
          "copy_calibration": {"copy_mib": copy_mib, "fetch_factor": f_copy,
                               "write_factor": w_copy},
          "kernels": kernels}
@@ -217,7 +249,8 @@ def bench_batch(args) -> int:
                                  torch.from_numpy(np.asarray(w.F1)).cuda(),
                                  torch.from_numpy(np.asarray(w.F2)).cuda()))
     torch.cuda.synchronize()
-    opts = dict(tol=1e-9, max_outer=80, restart=1)
+    # inner solves relaxed as the residual falls (sts_opts.inner_relax, j = 1)
+    opts = dict(tol=1e-9, max_outer=80, restart=1, inner_relax=1)
     t0 = time.perf_counter()
     best, timings = autotune.tune_workers(probs, probe=32, **opts)
     _log(f"autotune {time.perf_counter() - t0:.1f}s: {timings} -> {best} workers")
@@ -306,7 +339,14 @@ def bench_serve(args) -> int:
         reqs.append((w, (dd, ds), (md, ms)))
     # residual 1e-8: the 1-D requests (Nx up to 8192) cannot resolve residuals
     # much below 1e-9 in FP64; the error gate is 1e-8
-    opts = dict(tol=1e-8, max_outer=100)
+    # max_outer bounds the basis capacity each request reserves (and so the
+    # footprint it is admitted by): 60 blocks cover every request of the mix
+    opts = dict(tol=1e-8, max_outer=60)
+
+    def req_opts(w):
+        # relaxed inner solves (sts_opts.inner_relax): j = 2 in 3-D, 1 otherwise
+        return dict(opts, inner_relax=2 if w.dim == 3 else 1)
+
     budget = 200 << 30
     sample = set(range(0, len(reqs), 20))
     results = [None] * len(reqs)
@@ -316,7 +356,7 @@ def bench_serve(args) -> int:
         for d in (1, 2, 3):
             j = next(i for i, sh in enumerate(shapes) if sh[0] == d)
             w, dt, mt = reqs[j]
-            t = server.submit(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2, **opts)
+            t = server.submit(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2, **req_opts(w))
             server.wait(t)
             server.release(t)
         tickets = [None] * len(reqs)
@@ -328,7 +368,7 @@ def bench_serve(args) -> int:
                 delay = arrivals[i] - (time.perf_counter() - t0)
                 if delay > 0:
                     time.sleep(delay)
-                tickets[i] = server.submit(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2, **opts)
+                tickets[i] = server.submit(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2, **req_opts(w))
             done_submit.set()
 
         t_start = time.perf_counter()
@@ -372,7 +412,7 @@ def bench_serve(args) -> int:
     for i, (V, Y) in kept.items():
         w, dt, mt = reqs[i]
         with sts.Problem(w.dim, w.n[0], w.mu, dt, mt, w.F1, w.F2) as pr:
-            pr.solve(**opts)
+            pr.solve(**req_opts(w))
             Va, Ya = pr.factors()
         equal += int(np.array_equal(V, Va) and np.array_equal(Y, Ya))
         if w.dim == 3 and w.nh * w.nt <= 1.5e8:
@@ -470,7 +510,7 @@ def main() -> int:
         args.sample_steps = 8
     if args.summarize_pmc:
         f, wr, cf, cw, mib = args.summarize_pmc
-        return summarize_pmc(f, wr, cf, cw, int(mib), TRAFFIC_FILE)
+        return summarize_pmc(f, wr, cf, cw, int(mib), TRAFFIC_FILES[args.workload])
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.gpus == 1 and args.workload == "batch2d":
@@ -574,14 +614,14 @@ def main() -> int:
             roofline = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 2),
                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                        "traffic": _traffic(name),
+                        "traffic": _traffic(name, TRAFFIC_FILES[args.workload]),
                         "alg_flops_per_launch": flops / max(n, 1), **common}
         else:
             achieved = by / sec / 1e9
             roofline = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": _traffic(name),
+                        "traffic": _traffic(name, TRAFFIC_FILES[args.workload]),
                         "alg_bytes_per_launch": by / max(n, 1), **common}
     gate = last["status"] == "STS_OK" and last["res_true"] <= args.tol
     V, Y = prob.factors(device=True)
