@@ -359,7 +359,13 @@ struct InvArgs {
   const double* bounds;
   double* z;        // k x k, ld k
   double* lu;       // 5 k^2 (factor f, row i, thread j at (f k + i) k + j)
+  double* xt;       // k^2: the iterate of thread j, row i at i k + j
 };
+
+// Steps of the triangular solves whose operands are loaded together: the
+// solves are one dependent chain per thread, so each step's loads are issued
+// a chunk ahead instead of in the chain.
+constexpr int kInvChunk = 8;
 
 __global__ __launch_bounds__(64) void inviter_kernel(InvArgs g) {
   const int j0 = blockIdx.x * 64 + threadIdx.x;
@@ -414,49 +420,97 @@ __global__ __launch_bounds__(64) void inviter_kernel(InvArgs g) {
       }
     }
     at(u1, k - 1) = cd;
-    // pseudo-random start in column j of z
-    double* x = g.z + (int64_t)j * k;
-    for (int i = 0; i < k; ++i) x[i] = start_value(i, j);
+    // pseudo-random start; the iterate is kept row-interleaved across the
+    // threads (row i of thread j0 at xt[i k + j0]) for coalesced access
+    auto x = [&](int i) -> double& { return g.xt[(int64_t)i * k + j0]; };
+    for (int i = 0; i < k; ++i) x(i) = start_value(i, j);
     for (int it = 0; it < kInvIters; ++it) {
-      // forward: row interchanges and L
-      for (int i = 0; i + 1 < k; ++i) {
-        double xi = x[i], xn = x[i + 1];
-        if (at(pv, i) != 0.0) {
-          const double t = xi;
-          xi = xn;
-          xn = t;
+      // forward: row interchanges and L; the chain runs through `carry`
+      // (the updated row i + 1)
+      double carry = x(0);
+      for (int i0 = 0; i0 + 1 < k; i0 += kInvChunk) {
+        const int n = min(kInvChunk, k - 1 - i0);
+        double xn[kInvChunk], mv[kInvChunk], pw[kInvChunk], out[kInvChunk];
+#pragma unroll
+        for (int c = 0; c < kInvChunk; ++c) {
+          if (c < n) {
+            xn[c] = x(i0 + c + 1);
+            mv[c] = at(ml, i0 + c);
+            pw[c] = at(pv, i0 + c);
+          }
         }
-        x[i] = xi;
-        x[i + 1] = xn - at(ml, i) * xi;
+#pragma unroll
+        for (int c = 0; c < kInvChunk; ++c) {
+          if (c < n) {
+            double xi = carry, xnn = xn[c];
+            if (pw[c] != 0.0) {
+              const double t = xi;
+              xi = xnn;
+              xnn = t;
+            }
+            out[c] = xi;
+            carry = xnn - mv[c] * xi;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kInvChunk; ++c)
+          if (c < n) x(i0 + c) = out[c];
       }
+      x(k - 1) = carry;
       // backward: U with two super-diagonals, tiny pivots perturbed
       double x1 = 0.0, x2 = 0.0;
-      for (int i = k - 1; i >= 0; --i) {
-        double p = at(u1, i);
-        if (fabs(p) < ptol) p = p < 0.0 ? -ptol : ptol;
-        const double xi = (x[i] - at(u2, i) * x1 - at(u3, i) * x2) / p;
-        x[i] = xi;
-        x2 = x1;
-        x1 = xi;
+      for (int i1 = k - 1; i1 >= 0; i1 -= kInvChunk) {
+        const int n = min(kInvChunk, i1 + 1);
+        double xv[kInvChunk], a1[kInvChunk], a2[kInvChunk], a3[kInvChunk];
+#pragma unroll
+        for (int c = 0; c < kInvChunk; ++c) {
+          if (c < n) {
+            const int i = i1 - c;
+            xv[c] = x(i);
+            a1[c] = at(u1, i);
+            a2[c] = at(u2, i);
+            a3[c] = at(u3, i);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kInvChunk; ++c) {
+          if (c < n) {
+            double p = a1[c];
+            if (fabs(p) < ptol) p = p < 0.0 ? -ptol : ptol;
+            const double xi = (xv[c] - a2[c] * x1 - a3[c] * x2) / p;
+            xv[c] = xi;
+            x2 = x1;
+            x1 = xi;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kInvChunk; ++c)
+          if (c < n) x(i1 - c) = xv[c];
       }
       // orthogonalise against the earlier members of the cluster
       for (int q = 0; q < mm; ++q) {
         const double* zq = g.z + (int64_t)(j0 + q) * k;
         double s = 0.0;
-        for (int i = 0; i < k; ++i) s += zq[i] * x[i];
-        for (int i = 0; i < k; ++i) x[i] -= s * zq[i];
+        for (int i = 0; i < k; ++i) s += zq[i] * x(i);
+        for (int i = 0; i < k; ++i) x(i) -= s * zq[i];
       }
       // normalise (infinity norm between solves, 2-norm at the end)
       double nrm = 0.0;
       if (it + 1 < kInvIters) {
-        for (int i = 0; i < k; ++i) nrm = fmax(nrm, fabs(x[i]));
+#pragma unroll 8
+        for (int i = 0; i < k; ++i) nrm = fmax(nrm, fabs(x(i)));
       } else {
-        for (int i = 0; i < k; ++i) nrm += x[i] * x[i];
+#pragma unroll 8
+        for (int i = 0; i < k; ++i) nrm += x(i) * x(i);
         nrm = sqrt(nrm);
       }
       const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = 0; i < k; ++i) x[i] *= inv;
+#pragma unroll 8
+      for (int i = 0; i < k; ++i) x(i) *= inv;
     }
+    // the finished vector into column j of z
+    double* zj = g.z + (int64_t)j * k;
+    for (int i = 0; i < k; ++i) zj[i] = x(i);
   }
 }
 
@@ -565,7 +619,7 @@ void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_
   launch(STS_K_BISECT, 24.0 * k, bisect_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, st, k,
          d, e, bounds, lam);
   STS_HIP(hipGetLastError());
-  InvArgs iv{k, d, e, lam, bounds, z, lu};
+  InvArgs iv{k, d, e, lam, bounds, z, lu, B};   // B is free until the Newton-Schulz steps
   launch(STS_K_INVITER, kk8, inviter_kernel, dim3((k + 63) / 64), dim3(64), 0, st, iv);
   STS_HIP(hipGetLastError());
   // two Newton-Schulz steps Z <- Z (3 I - Z^T Z) / 2 (ping-pong z / B)
