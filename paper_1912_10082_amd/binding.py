@@ -102,6 +102,7 @@ _SIGS = {
     "sts_pcg_mg": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64, _I32,
                              C.POINTER(_I32), _P]),
     "sts_mg_vcycle": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _P]),
+    "sts_mg_vcycle_shifted": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _P]),
     "sts_adaptive_shift": (C.c_int, [_D, _I32, _D, _I32, _F64, _F64, _I32, _D]),
     "sts_shifted_solve": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _F64, _I32,
                                     C.POINTER(_I32), _P]),
@@ -432,12 +433,18 @@ def shifted_solve(space: Space, shift: float, B, rtol: float = 1e-13, maxit: int
     return X, list(its)
 
 
-def mg_vcycle(space: Space, R):
-    """Z = Bmg R, one multigrid V-cycle (the preconditioner of pcg_mg)."""
+def mg_vcycle(space: Space, R, shift: float = 0.0):
+    """Z = Bmg R, one multigrid V-cycle (the preconditioner of pcg_mg; with
+    shift > 0 that of the shifted solves, for Kx + shift Mx)."""
     R, pr, ldr = dev_colmajor(R)
     Z = dev_empty(R.shape[0], R.shape[1])
-    _check(load().sts_mg_vcycle(C.byref(space), pr, ldr, C.c_void_p(Z.data_ptr()),
-                                max(Z.shape[0], 1), R.shape[1], _stream_handle()))
+    if shift:
+        _check(load().sts_mg_vcycle_shifted(C.byref(space), float(shift), pr, ldr,
+                                            C.c_void_p(Z.data_ptr()), max(Z.shape[0], 1),
+                                            R.shape[1], _stream_handle()))
+    else:
+        _check(load().sts_mg_vcycle(C.byref(space), pr, ldr, C.c_void_p(Z.data_ptr()),
+                                    max(Z.shape[0], 1), R.shape[1], _stream_handle()))
     return Z
 
 

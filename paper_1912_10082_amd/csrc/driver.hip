@@ -413,7 +413,8 @@ struct MGRunner {
   MGWork w{};
   PollLoop poll;
   DevBuf levels, vecs, scal, parts, dst;
-  int expect = 12;   // iterations the last run needed (first chunk length)
+  int expect = 12;          // iterations the last run needed (first chunk length)
+  int expect_shifted = 12;  // the same for the shifted operator Kx + s Mx
 
   // Allocate for the plan; x / ldx are set per run.
   void setup(const MGPlan& plan) {
@@ -808,6 +809,37 @@ void run_shifted_block(sts_problem* P, double s, int ncols, const double* const*
                           P->stream);
     P->inner_K += ncols;
     P->alg_bytes += 40.0 * P->nh * ncols;
+    return;
+  }
+  if (o.inner_precond != 0 && P->mg_ok && P->grid.dim == 2) {
+    // 2-D: multigrid-preconditioned CG on Kx + s Mx (every level's operator
+    // gets the mass term; see mg.hip)
+    if (!P->mg) {
+      P->mg = std::make_unique<MGRunner>();
+      P->mg->setup(P->mg_plan_);
+    }
+    MGRunner& r = *P->mg;
+    const int e = r.expect;
+    r.w.plan.sw0 = s * P->M.c[13] / 6.0;
+    r.expect = r.expect_shifted;
+    CGScal out[kMaxCols];
+    try {
+      r.run(x0, P->ldv, ncols, b, o.inner_rtol, o.inner_maxit, out, P->stream);
+    } catch (...) {
+      r.w.plan.sw0 = 0.0;
+      r.expect_shifted = r.expect;
+      r.expect = e;
+      throw;
+    }
+    r.w.plan.sw0 = 0.0;
+    r.expect_shifted = r.expect;
+    r.expect = e;
+    const double bpn = r.bytes_per_node();
+    for (int j = 0; j < ncols; ++j) {
+      check_inner(out[j]);
+      P->inner_K += out[j].iters;
+      P->alg_bytes += (bpn * (out[j].iters + 1) + 40.0) * P->nh;
+    }
     return;
   }
   // Kx + s Mx has the pattern of Mx (a superset of that of Kx): it runs in
@@ -1721,6 +1753,18 @@ sts_status sts_shifted_solve(const sts_space* space, double shift, const double*
         for (int c = 0; c < ncols; ++c) iters[c] = 1;
       return;
     }
+    MGPlan plan{};
+    if (g.dim == 2 && mg_plan(g, K, &plan)) {
+      // multigrid-preconditioned CG on Kx + shift Mx
+      plan.sw0 = shift * M.c[13] / 6.0;
+      MGRunner r;
+      r.setup(plan);
+      CGScal out[kMaxCols];
+      r.run(X, ldx, ncols, bcols, rtol, maxit, out, st);
+      STS_HIP(hipStreamSynchronize(st));
+      bad = cg_status(out, ncols, iters);
+      return;
+    }
     const int tiles = cg_tiles(g);
     CGRunner r;
     r.g = g;
@@ -1844,6 +1888,30 @@ sts_status sts_tridiag_solve(const sts_space* space, const int32_t* ops, const d
       op[c] = ops[c];
     }
     tridiag_solve(g, K, M, op, ncols, bc, X, ldx, fac, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_mg_vcycle_shifted(const sts_space* space, double shift, const double* R,
+                                 int64_t ldr, double* Z, int64_t ldz, int32_t ncols,
+                                 void* stream) {
+  return run_guarded([&] {
+    Grid g;
+    MGPlan plan = require_mg(space, &g);
+    STS_REQUIRE(shift >= 0.0 && std::isfinite(shift), STS_E_INVALID, "shift must be >= 0");
+    STS_REQUIRE(shift == 0.0 || g.dim == 2, STS_E_INVALID,
+                "the shifted V-cycle is for 2-D P1 spaces");
+    plan.sw0 = shift * make_stencil(*space, STS_OP_M).c[13] / 6.0;
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(R && Z && ldr >= g.nh && ldz >= g.nh, STS_E_INVALID, "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MGRunner r;
+    r.setup(plan);
+    copy_cols(g.nh, ncols, R, ldr, r.w.b[0], r.w.ld[0], st);
+    int cols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) cols[c] = c;
+    mg_vcycle(r.w, nullptr, cols, ncols, false, st);
+    copy_cols(g.nh, ncols, r.w.e[0], r.w.ld[0], Z, ldz, st);
     STS_HIP(hipStreamSynchronize(st));
   });
 }

@@ -56,9 +56,27 @@ constexpr int TX = 64, TY = 16;  // fine nodes per PCG-kernel tile
 constexpr int kNu = kMGNu;       // smoothing steps
 constexpr int kCT = 1024;        // threads of the coarse kernel
 
-// mu (4 u - u_W - u_E - u_S - u_N) on an LDS array of row width W.
-__device__ __forceinline__ double k5(const double* s, int q, int W, double mu) {
-  return mu * (4.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - W] + s[q + W]));
+// The level operator Kx + s Mx on the Courant triangulation: mu (4; -1 x 4)
+// plus s w (6; 1 at W, E, S, N, SW, NE), w = h^2 / 12 of the level.  Both
+// matrices are Galerkin products of nested P1 spaces, so every coarse level
+// carries the same form with its own w (four times the finer one).
+struct Op {
+  double mu;           // stiffness coefficient (every level)
+  double c0, cx, cd;   // shifted: centre, axis neighbours, SW-NE neighbours
+};
+
+// Op applied at LDS point q of an array of row width W; SH = false is the
+// unshifted stiffness mu (4 u - u_W - u_E - u_S - u_N).
+template <bool SH>
+__device__ __forceinline__ double aop(const double* s, int q, int W, const Op& o) {
+  if (!SH) return o.mu * (4.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - W] + s[q + W]));
+  return o.c0 * s[q] + o.cx * ((s[q - 1] + s[q + 1]) + (s[q - W] + s[q + W])) +
+         o.cd * (s[q - W - 1] + s[q + W + 1]);
+}
+
+template <bool SH>
+__device__ __forceinline__ double op_diag(const Op& o) {
+  return SH ? o.c0 : 4.0 * o.mu;
 }
 
 // P1 interpolation at fine node (gx, gy) from a coarse array with origin
@@ -92,13 +110,13 @@ struct Region {
 
 // One smoothing step with ping-pong buffers: d = a d + c (b - K u) / D and
 // u' = u + d on the nodes at least `shrink` inside the region; one barrier.
-template <int W, int H>
+template <bool SH, int W, int H>
 __device__ __forceinline__ void cheb_step(const Region<W, H>& R, int shrink, double ak, double ck,
                                           double inv_d, const double* bs, const double* u,
-                                          double* un, double* ds, double mu) {
+                                          double* un, double* ds, const Op& op) {
   for (int i = threadIdx.x; i < W * H; i += kT) {
     if (R.inside(i, shrink)) {
-      const double d = ak * ds[i] + ck * inv_d * (bs[i] - k5(u, i, W, mu));
+      const double d = ak * ds[i] + ck * inv_d * (bs[i] - aop<SH>(u, i, W, op));
       ds[i] = d;
       un[i] = u[i] + d;
     }
@@ -108,10 +126,10 @@ __device__ __forceinline__ void cheb_step(const Region<W, H>& R, int shrink, dou
 
 // kNu steps from u = 0; step k on shrink k.  Returns the buffer index of u,
 // which is valid on shrink kNu - 1.
-template <int W, int H>
+template <bool SH, int W, int H>
 __device__ __forceinline__ int presmooth(const Region<W, H>& R, const Smooth& sm, double inv_d,
                                          const double* bs, double (*us)[W * H], double* ds,
-                                         double mu) {
+                                         const Op& op) {
   for (int i = threadIdx.x; i < W * H; i += kT) {
     const double v = R.inside(i, 0) ? sm.c[0] * inv_d * bs[i] : 0.0;
     ds[i] = v;
@@ -121,7 +139,7 @@ __device__ __forceinline__ int presmooth(const Region<W, H>& R, const Smooth& sm
   __syncthreads();
   int cur = 0;
   for (int k = 1; k < kNu; ++k) {
-    cheb_step<W, H>(R, k, sm.a[k], sm.c[k], inv_d, bs, us[cur], us[cur ^ 1], ds, mu);
+    cheb_step<SH, W, H>(R, k, sm.a[k], sm.c[k], inv_d, bs, us[cur], us[cur ^ 1], ds, op);
     cur ^= 1;
   }
   return cur;
@@ -139,7 +157,7 @@ struct LevelArgs {
   int nlaunch;
   int cols[kMaxCols];
   const CGScal* st;    // per-column activity, may be null (all active)
-  double mu;
+  Op op;               // operator of the fine level
   Smooth sm;
   double* part;        // up: per-tile (b, e), may be null
   int max_tiles;
@@ -149,6 +167,7 @@ struct LevelArgs {
 // down: u = smoothing from zero; res = b - K u; b_c = P^T res at the tile's
 // coarse nodes.  Fine region [2 cx0 - kNu, 2 cx0 + 2 CX + kNu] per direction.
 // ---------------------------------------------------------------------------
+template <bool SH>
 __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
   constexpr int W = 2 * CX + 1 + 2 * kNu, H = 2 * CY + 1 + 2 * kNu;
   __shared__ double bs[W * H];
@@ -161,14 +180,15 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
   const int cx0 = (t % a.ntx) * CX, cy0 = (t / a.ntx) * CY;
   const int nf = a.nf, nc = a.nc;
   const Region<W, H> R{2 * cx0 - kNu, 2 * cy0 - kNu, nf};
-  const double mu = a.mu, inv_d = 1.0 / (4.0 * mu);
+  const Op op = a.op;
+  const double inv_d = 1.0 / op_diag<SH>(op);
   const double* bf = a.bf + (size_t)col * a.ldf;
   for (int i = threadIdx.x; i < W * H; i += kT) {
     const int gx = R.ox + i % W, gy = R.oy + i / W;
     bs[i] = (gx >= 0 && gx < nf && gy >= 0 && gy < nf) ? bf[(size_t)gy * nf + gx] : 0.0;
   }
   __syncthreads();
-  const int cur = presmooth<W, H>(R, a.sm, inv_d, bs, us, ds, mu);
+  const int cur = presmooth<SH, W, H>(R, a.sm, inv_d, bs, us, ds, op);
   // the pre-smoothed iterate on the tile's own fine nodes, for the up launch
   {
     const int x1 = (cx0 + CX >= nc) ? nf : 2 * (cx0 + CX);
@@ -184,7 +204,7 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
   for (int i = threadIdx.x; i < W * H; i += kT) {
     const int lx = i % W, ly = i / W;
     if (lx >= kNu && lx < W - kNu && ly >= kNu && ly < H - kNu)
-      ds[i] = bs[i] - k5(us[cur], i, W, mu);
+      ds[i] = bs[i] - aop<SH>(us[cur], i, W, op);
   }
   __syncthreads();
   double* bc = a.bc + (size_t)col * a.ldc;
@@ -204,6 +224,7 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
 // fine nodes [2 cx0, x1) x [2 cy0, y1) (the last tile in a direction runs to
 // nf).  Fine region [2 cx0 - (2 kNu - 1), ...), coarse [cx0 - kNu, ...).
 // ---------------------------------------------------------------------------
+template <bool SH>
 __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   constexpr int HL = kNu;   // halo of the kNu post-smoothing steps
   constexpr int W = 2 * CX + 1 + 2 * HL, H = 2 * CY + 1 + 2 * HL;
@@ -221,7 +242,8 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   const int nf = a.nf, nc = a.nc;
   const Region<W, H> R{2 * cx0 - HL, 2 * cy0 - HL, nf};
   const int cox = cx0 - kNu, coy = cy0 - kNu;
-  const double mu = a.mu, inv_d = 1.0 / (4.0 * mu);
+  const Op op = a.op;
+  const double inv_d = 1.0 / op_diag<SH>(op);
   const double* bf = a.bf + (size_t)col * a.ldf;
   const double* xpg = a.xp + (size_t)col * a.ldf;
   const double* ecg = a.ec + (size_t)col * a.ldc;
@@ -251,8 +273,8 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   int cur = 0;
   // post-smoothing; the last step's new values are needed on the owned nodes only
   for (int k = 0; k + 1 < kNu; ++k) {
-    cheb_step<W, H>(R, 1 + k, k == 0 ? 0.0 : a.sm.a[k], a.sm.c[k], inv_d, bs, us[cur],
-                    us[cur ^ 1], ds, mu);
+    cheb_step<SH, W, H>(R, 1 + k, k == 0 ? 0.0 : a.sm.a[k], a.sm.c[k], inv_d, bs, us[cur],
+                        us[cur ^ 1], ds, op);
     cur ^= 1;
   }
   const int x1 = (cx0 + CX >= nc) ? nf : 2 * (cx0 + CX);
@@ -265,7 +287,7 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   for (int i = threadIdx.x; i < ow * oh; i += kT) {
     const int gx = 2 * cx0 + i % ow, gy = 2 * cy0 + i / ow;
     const int q = (gy - R.oy) * W + (gx - R.ox);
-    const double d = ak * ds[q] + ck * inv_d * (bs[q] - k5(u, q, W, mu));
+    const double d = ak * ds[q] + ck * inv_d * (bs[q] - aop<SH>(u, q, W, op));
     const double e = u[q] + d;
     ef[(size_t)gy * nf + gx] = e;
     part += bs[q] * e;
@@ -290,6 +312,7 @@ struct CoarseArgs {
   double* e;
   const double* dst;   // n x n sine-transform matrix S (row-major, symmetric), then l (n)
   double mu;
+  double sw;           // s w of the level: the solve is with Kx + s Mx~ (see mg_vcycle)
   int nlaunch;
   int cols[kMaxCols];
   const CGScal* st;
@@ -301,7 +324,7 @@ struct CoarseArgs {
 // is divided by mu (l_y + l_x) (zero outside the n x n block).  One 16 x 16
 // tile per wave.
 __device__ __forceinline__ void lds_gemm(const double* A, const double* B, double* C, bool scale,
-                                         const double* l, double mu, int n) {
+                                         const double* l, double mu, double sw, int n) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int r0 = (wv & 3) * 16, c0 = (wv >> 2) * 16;
@@ -317,7 +340,8 @@ __device__ __forceinline__ void lds_gemm(const double* A, const double* B, doubl
   for (int q = 0; q < 4; ++q) {
     const int y = r0 + 4 * q + g, x = c0 + i;
     double v = sum[q];
-    if (scale) v = (y < n && x < n) ? v / (mu * (l[y] + l[x])) : 0.0;
+    if (scale)
+      v = (y < n && x < n) ? v / (mu * (l[y] + l[x]) + sw * (10.0 - l[y] - l[x])) : 0.0;
     C[y * kEL + x] = v;
   }
 }
@@ -341,13 +365,13 @@ __global__ __launch_bounds__(kCT) void mg_coarse_kernel(CoarseArgs a) {
   }
   if (threadIdx.x < kE) l[threadIdx.x] = threadIdx.x < n ? a.dst[n * n + threadIdx.x] : 0.0;
   __syncthreads();
-  lds_gemm(S, X, T, false, l, a.mu, n);   // T = S B
+  lds_gemm(S, X, T, false, l, a.mu, a.sw, n);   // T = S B
   __syncthreads();
-  lds_gemm(T, S, X, true, l, a.mu, n);    // X = (T S) ./ (mu (l_y + l_x))
+  lds_gemm(T, S, X, true, l, a.mu, a.sw, n);    // X = (T S) ./ (mu (l_y + l_x) + ...)
   __syncthreads();
-  lds_gemm(S, X, T, false, l, a.mu, n);   // T = S X
+  lds_gemm(S, X, T, false, l, a.mu, a.sw, n);   // T = S X
   __syncthreads();
-  lds_gemm(T, S, X, false, l, a.mu, n);   // X = T S
+  lds_gemm(T, S, X, false, l, a.mu, a.sw, n);   // X = T S
   __syncthreads();
   double part = 0.0;
   for (int i = threadIdx.x; i < n * n; i += kCT) {
@@ -388,6 +412,7 @@ struct DstGemmArgs {
   int64_t c_ld;
   const double* l;     // eigenvalues if the product is scaled, else null
   double mu;
+  double sw;
   const CGScal* st;
 };
 
@@ -431,7 +456,7 @@ __global__ __launch_bounds__(64 * kDstWaves) void dst_gemm_kernel(DstGemmArgs a)
 #pragma unroll
     for (int w = 0; w < kDstWaves - 1; ++w) v += red[w][(4 * q + g) * 16 + i];
     if (rr < m && c < m) {
-      if (a.l) v /= a.mu * (a.l[rr] + a.l[c]);
+      if (a.l) v /= a.mu * (a.l[rr] + a.l[c]) + a.sw * (10.0 - a.l[rr] - a.l[c]);
       C[(size_t)rr * m + c] = v;
     }
   }
@@ -460,6 +485,7 @@ struct FstArgs {
   const double* lv;    // l_0 .. l_{m-1}
   const double* tw;    // cos, sin of pi k / L, k < L
   double mu;
+  double sw;
   const CGScal* st;
 };
 
@@ -509,8 +535,8 @@ __global__ __launch_bounds__(L) void fst_col_kernel(FstArgs a) {
     // frequency t + 1 along the rows; the columns already hold frequencies c1, c2
     const double2 Z = z[t + 1];
     const double lr = a.lv[t];
-    const double d1 = a.mu * (lr + a.lv[c1]);
-    const double d2 = c2 < m ? a.mu * (lr + a.lv[c2]) : 1.0;
+    const double d1 = a.mu * (lr + a.lv[c1]) + a.sw * (10.0 - lr - a.lv[c1]);
+    const double d2 = c2 < m ? a.mu * (lr + a.lv[c2]) + a.sw * (10.0 - lr - a.lv[c2]) : 1.0;
     v[t] = double2{-Z.y * sc / d1, c2 < m ? Z.x * sc / d2 : 0.0};
   }
   __syncthreads();
@@ -535,7 +561,7 @@ struct PCGArgs {
   int ncols;
   int nlaunch;
   int cols[kMaxCols];
-  double mu;
+  Op op;               // operator of the finest level
   double* x;
   int64_t ldx;
   double* r;
@@ -557,6 +583,7 @@ struct PCGArgs {
 // A: stopping test and beta from (r, r) and (r, z) of this work-group's
 // column; p = z + beta p; q = K p; (p, q).  Tile 0 of each column writes its
 // state; work-group 0 carries over the state of columns not launched.
+template <bool SH>
 __global__ __launch_bounds__(kT) void pcg_a_kernel(PCGArgs a) {
   constexpr int RW = TX + 2, RH = TY + 2;
   __shared__ double ps[RW * RH];
@@ -617,7 +644,7 @@ __global__ __launch_bounds__(kT) void pcg_a_kernel(PCGArgs a) {
     if (gx < n && gy < n) {
       const int qi = (i / TX + 1) * RW + (i % TX + 1);
       const double pv = ps[qi];
-      const double qv = k5(ps, qi, RW, a.mu);
+      const double qv = aop<SH>(ps, qi, RW, a.op);
       const size_t g = (size_t)gy * n + gx;
       pout[g] = pv;
       qg[g] = qv;
@@ -707,6 +734,12 @@ __global__ __launch_bounds__(kT) void pcg_setup_kernel(PCGArgs a, double rtol2, 
 
 int tiles_of(int n, int tx, int ty) { return ((n + tx - 1) / tx) * ((n + ty - 1) / ty); }
 
+// Operator of level l: w_l = 4^l w_0, s w_l = 4^l sw0.
+Op level_op(const MGPlan& p, int l) {
+  const double swl = std::ldexp(p.sw0, 2 * l);
+  return Op{p.mu, 4.0 * p.mu + 6.0 * swl, -p.mu + swl, swl};
+}
+
 PCGArgs pcg_args(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols) {
   PCGArgs a{};
   a.n = w.plan.n[0];
@@ -716,7 +749,7 @@ PCGArgs pcg_args(const MGWork& w, int parity, const int* cols, int nlaunch, int 
   a.ncols = ncols;
   a.nlaunch = nlaunch;
   for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
-  a.mu = w.plan.mu;
+  a.op = level_op(w.plan, 0);
   a.x = w.x;
   a.ldx = w.ldx;
   a.r = w.b[0];
@@ -806,6 +839,11 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
   const MGPlan& p = w.plan;
   const int L = p.nlev;
   const Smooth sm = smooth_coefficients(0.5);   // [1/2, 2]: the oscillatory part in 2-D
+  const bool sh = p.sw0 != 0.0;
+  // the coarsest level's s w: its exact sine-transform solve takes the mass
+  // part without the SW-NE coupling, s w (6; 1 x 4), which the transform
+  // diagonalises (symbol s w (10 - l_r - l_c)); with s = 0 it is exact
+  const double swL = std::ldexp(p.sw0, 2 * L);
   for (int l = 0; l < L; ++l) {
     LevelArgs a{};
     a.nf = p.n[l];
@@ -820,10 +858,15 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.nlaunch = nlaunch;
     for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
     a.st = act;
-    a.mu = p.mu;
+    a.op = level_op(p, l);
     a.sm = sm;
-    launch(STS_K_MG_DOWN, 8.0 * (2.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch,
-           mg_down_kernel, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
+    const double by = 8.0 * (2.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch;
+    if (sh)
+      launch(STS_K_MG_DOWN, by, mg_down_kernel<true>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0,
+             st, a);
+    else
+      launch(STS_K_MG_DOWN, by, mg_down_kernel<false>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0,
+             st, a);
     STS_HIP(hipGetLastError());
   }
   if (p.n[L] <= kMGCoarseMax) {
@@ -834,6 +877,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     c.e = w.e[L];
     c.dst = w.dst;
     c.mu = p.mu;
+    c.sw = swL;
     c.nlaunch = nlaunch;
     for (int j = 0; j < nlaunch; ++j) c.cols[j] = cols[j];
     c.st = act;
@@ -851,6 +895,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     f.lv = w.dst + (size_t)m * m;
     f.tw = w.dst + (size_t)m * (m + 1);
     f.mu = p.mu;
+    f.sw = swL;
     f.st = act;
     const int64_t ld = w.ld[L];
     const dim3 grid((m + 1) / 2, nlaunch);
@@ -882,6 +927,7 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     g.nlaunch = nlaunch;
     for (int j = 0; j < nlaunch; ++j) g.cols[j] = cols[j];
     g.mu = p.mu;
+    g.sw = swL;
     g.st = act;
     const int nt = (m + 15) / 16;
     const dim3 grid(nt * nt, nlaunch);
@@ -918,12 +964,17 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.nlaunch = nlaunch;
     for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
     a.st = act;
-    a.mu = p.mu;
+    a.op = level_op(p, l);
     a.sm = sm;
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
     a.max_tiles = w.max_tiles;
-    launch(STS_K_MG_UP, 8.0 * (3.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch, mg_up_kernel,
-           dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st, a);
+    const double by = 8.0 * (3.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch;
+    if (sh)
+      launch(STS_K_MG_UP, by, mg_up_kernel<true>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st,
+             a);
+    else
+      launch(STS_K_MG_UP, by, mg_up_kernel<false>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st,
+             a);
     STS_HIP(hipGetLastError());
   }
 }
@@ -945,7 +996,10 @@ void pcg_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int 
   const PCGArgs a = pcg_args(w, parity, cols, nlaunch, ncols);
   const int blocks = a.ntx * a.nty * nlaunch;
   const double nn = (double)a.n * a.n * nlaunch;
-  launch(STS_K_PCG_A, 32.0 * nn, pcg_a_kernel, dim3(blocks), dim3(kT), 0, st, a);
+  if (w.plan.sw0 != 0.0)
+    launch(STS_K_PCG_A, 32.0 * nn, pcg_a_kernel<true>, dim3(blocks), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_PCG_A, 32.0 * nn, pcg_a_kernel<false>, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
   launch(STS_K_PCG_B, 48.0 * nn, pcg_b_kernel, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());

@@ -90,16 +90,32 @@ def chebyshev(K, b, u, steps=CHEB_STEPS):
     return u
 
 
-def vcycle(b: np.ndarray, n: int, mu: float, finest: bool = True) -> np.ndarray:
-    """One V-cycle from zero applied to b (length n^2, or n^2 x m)."""
+def mass_stand_in(n: int) -> sp.csr_matrix:
+    """The coarsest level's mass in the shifted solve: the 2-D P1 mass without
+    its SW-NE coupling, (h^2 / 12) (6; 1 at W, E, S, N), which the sine
+    transform diagonalises."""
+    w = (1.0 / (n + 1)) ** 2 / 12.0
+    e = np.ones(n)
+    T1 = sp.diags([e[:-1], e[:-1]], [-1, 1])
+    eye = sp.identity(n)
+    return (w * (6.0 * sp.identity(n * n) + sp.kron(eye, T1) + sp.kron(T1, eye))).tocsr()
+
+
+def vcycle(b: np.ndarray, n: int, mu: float, finest: bool = True, shift: float = 0.0) -> np.ndarray:
+    """One V-cycle from zero applied to b (length n^2, or n^2 x m) for
+    Kx + shift Mx; each level's operator is the Galerkin product of the finer
+    one (nested P1 spaces: the coarse Kx + shift Mx)."""
     K = stiffness(n, mu)
+    if shift:
+        K = (K + shift * fem.spatial_operators(2, n, mu)[1]).tocsr()
     if n <= (EXACT_FINEST if finest else EXACT_COARSE):
-        return spla.spsolve(K.tocsc(), b).reshape(b.shape)
+        A = stiffness(n, mu) + shift * mass_stand_in(n) if shift else K
+        return spla.spsolve(A.tocsc(), b).reshape(b.shape)
     assert n % 2 == 1, "levels that do not fit the exact solve must halve"
     u = chebyshev(K, b, np.zeros_like(b))
     nc = (n - 1) // 2
     P = prolongation(nc)
-    u = u + P @ vcycle(P.T @ (b - K @ u), nc, mu, finest=False)
+    u = u + P @ vcycle(P.T @ (b - K @ u), nc, mu, finest=False, shift=shift)
     return chebyshev(K, b, u)
 
 

@@ -114,6 +114,28 @@ def test_pcg_zero_rhs_iteration_cap_and_bad_grids():
         assert e.value.code == 1
 
 
+@pytest.mark.parametrize("n,shift", [(1, 3.0), (31, 40.0), (65, 300.0), (127, 2e4), (191, 7.0),
+                                     (255, 50.0), (511, 1e5)])
+def test_shifted_vcycle_matches_reference(n, shift):
+    """The V-cycle for Kx + shift Mx (rational Krylov's shifted solves): every
+    level's operator carries the mass term, the coarsest solve its stand-in."""
+    mu = 0.6
+    rng = np.random.default_rng(800 + n)
+    R = rng.normal(size=(n * n, 2))
+    Z = host(sts.mg_vcycle(sts.make_space(2, n, mu), dev(R), shift=shift))
+    Zr = mgr.vcycle(R, n, mu, shift=shift)
+    np.testing.assert_allclose(Z, Zr, rtol=0, atol=1e-12 * abs(Zr).max())
+
+
+def test_shifted_vcycle_rejects_bad_arguments():
+    with pytest.raises(sts.STSError) as e:
+        sts.mg_vcycle(sts.make_space(2, 31), dev(np.ones((31 * 31, 1))), shift=-1.0)
+    assert e.value.code == 1
+    with pytest.raises(sts.STSError) as e:
+        sts.mg_vcycle(sts.make_space(3, 15), dev(np.ones((15 ** 3, 1))), shift=2.0)
+    assert e.value.code == 1
+
+
 # 3-D sizes: the exact sine-transform solve alone (1, 2, 17, 40, 63), one
 # smoothed level above it with the fine grid ragged against the 32 x 8 x 4
 # tile and the coarse grid against the 16 x 4 x 4 restriction tile (65 -> 32,

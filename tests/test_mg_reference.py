@@ -92,6 +92,51 @@ def test_pcg_iterations_do_not_grow_with_refinement():
     assert max(its[1:]) <= 12 and its[-1] - its[1] <= 2, its
 
 
+def test_galerkin_coarse_mass_is_the_coarse_mass():
+    """The shifted V-cycle relies on P^T Mx_h P = Mx_2h as well (nested P1)."""
+    from oracle import fem
+    for nc in (1, 3, 15):
+        P = mgr.prolongation(nc)
+        Mf = fem.spatial_operators(2, 2 * nc + 1)[1]
+        Mc = fem.spatial_operators(2, nc)[1]
+        assert abs(P.T @ Mf @ P - Mc).max() <= 1e-15
+
+
+def test_mass_stand_in_is_the_mass_without_the_diagonal_coupling():
+    from oracle import fem
+    n = 9
+    M = fem.spatial_operators(2, n)[1].toarray()
+    Ms = mgr.mass_stand_in(n).toarray()
+    D = M - Ms
+    w = (1.0 / (n + 1)) ** 2 / 12.0
+    # what is left is w at the SW and NE neighbours only
+    idx = np.arange(n * n)
+    x, y = idx % n, idx // n
+    for a in range(n * n):
+        for b in np.nonzero(abs(D[a]) > 1e-3 * w)[0]:
+            assert (x[b] - x[a], y[b] - y[a]) in ((1, 1), (-1, -1))
+            assert abs(D[a, b] - w) <= 1e-12 * w
+    assert np.all(np.linalg.eigvalsh(Ms) > 0)
+
+
+@pytest.mark.parametrize("n,shift", [(40, 50.0), (127, 300.0), (127, 2.0e4)])
+def test_shifted_vcycle_is_spd_and_converges(n, shift):
+    from oracle import fem
+    mu = 0.8
+    K, M = fem.spatial_operators(2, n, mu)
+    A = (K + shift * M).tocsc()
+    rng = np.random.default_rng(n)
+    R = rng.normal(size=(n * n, 2))
+    Z = mgr.vcycle(R, n, mu, shift=shift)
+    G = R.T @ Z
+    np.testing.assert_allclose(G, G.T, rtol=1e-12, atol=1e-14 * abs(G).max())
+    assert np.all(np.diag(G) > 0)
+    b = R[:, 0]
+    x, it = _pcg(A, b, lambda r: mgr.vcycle(r, n, mu, shift=shift), 1e-12)
+    assert it > 0 and np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b)
+    assert it <= 20, it
+
+
 def test_supported_grids():
     assert all(mgr.supported(n) for n in (1, 2, 31, 62, 63, 65, 97, 125, 127, 129, 255, 511,
                                           1023, 2047))
