@@ -302,14 +302,18 @@ sts_status sts_mass_solve(const sts_space* space, const double* B, int64_t ldb, 
 sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,
                          int64_t ldz, int32_t ncols, void* stream);
 
-/* The V-cycle for Kx + shift Mx (shift >= 0) on a 2-D P1 space, the
- * preconditioner of the shifted solves of the rational Krylov space (Sec. 4):
- * every level's operator is the coarse Kx + shift Mx (P^T Mx P is the coarse
- * mass for nested P1 spaces), smoothed as in sts_mg_vcycle with its own
- * diagonal; the coarsest level's sine-transform solve takes the mass without
- * its SW-NE coupling, (h^2/12)(6; 1 x 4), which the transform diagonalises.
- * Symmetric positive definite.  Same spaces (2-D only for shift > 0), layout
- * and errors as sts_mg_vcycle; STS_E_INVALID for a negative shift. */
+/* The V-cycle for Kx + shift Mx (shift >= 0), the preconditioner of the
+ * shifted solves of the rational Krylov space (Sec. 4).  Every level's
+ * operator is the coarse Kx + shift Mx, smoothed as in sts_mg_vcycle with its
+ * own diagonal.
+ *  - 2-D P1: P^T Mx P is the coarse mass for nested P1 spaces; the coarsest
+ *    sine-transform solve takes the mass without its SW-NE coupling,
+ *    (h^2/12)(6; 1 x 4), which the transform diagonalises.
+ *  - 3-D: the coarse levels rediscretise the Q1 mass (it is not a Galerkin
+ *    product of the Kuhn-mesh interpolation); the coarsest solve is exact,
+ *    since tridiag(1, 4, 1) has the sine eigenvectors too.
+ * Symmetric positive definite.  Same spaces, layout and errors as
+ * sts_mg_vcycle; STS_E_INVALID for a negative shift. */
 sts_status sts_mg_vcycle_shifted(const sts_space* space, double shift, const double* R,
                                  int64_t ldr, double* Z, int64_t ldz, int32_t ncols,
                                  void* stream);
@@ -333,10 +337,11 @@ sts_status sts_adaptive_shift(const double* ritz, int32_t k, const double* shift
                               double a, double b, int32_t grid, double* s);
 
 /* (Kx + shift Mx) X[:, c] = B[:, c] (shift >= 0) as the rational Krylov steps
- * solve them: 1-D P1 spaces directly (elimination); 2-D P1 spaces that the
- * multigrid accepts by CG preconditioned with sts_mg_vcycle_shifted; other
- * spaces by CG; the iterations stop at relative residual rtol (at most maxit;
- * iters as for sts_cg).  B, X: Nh x ncols (ldb, ldx), device; ncols <= 8. */
+ * solve them: 1-D P1 spaces directly (elimination); 2-D and 3-D spaces that
+ * the multigrid accepts by CG preconditioned with sts_mg_vcycle_shifted;
+ * other spaces by CG; the iterations stop at relative residual rtol (at most
+ * maxit; iters as for sts_cg).  B, X: Nh x ncols (ldb, ldx), device;
+ * ncols <= 8. */
 sts_status sts_shifted_solve(const sts_space* space, double shift, const double* B, int64_t ldb,
                              double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
                              int32_t* iters, void* stream);

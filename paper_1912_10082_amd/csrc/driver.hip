@@ -801,6 +801,12 @@ void check_inner(const CGScal& s) {
 // (elimination factors of the shifted matrix formed on the fly); otherwise
 // CG on the shifted stencil (plain CG: the multigrid preconditioner is built
 // for Kx alone).
+// The multigrid's mass scale of level 0: the 2-D P1 mass is (h^2/12) times
+// its pattern (centre 6), the 3-D Q1 mass (h/6)^3 times (1, 4, 1)^3 (centre 64).
+double mass_scale(const Grid& g, const Stencil& M) {
+  return g.dim == 3 ? M.c[13] / 64.0 : M.c[13] / 6.0;
+}
+
 void run_shifted_block(sts_problem* P, double s, int ncols, const double* const* b,
                        const sts_opts& o) {
   double* x0 = P->V.d() + P->k * P->ldv;
@@ -811,16 +817,16 @@ void run_shifted_block(sts_problem* P, double s, int ncols, const double* const*
     P->alg_bytes += 40.0 * P->nh * ncols;
     return;
   }
-  if (o.inner_precond != 0 && P->mg_ok && P->grid.dim == 2) {
-    // 2-D: multigrid-preconditioned CG on Kx + s Mx (every level's operator
-    // gets the mass term; see mg.hip)
+  if (o.inner_precond != 0 && P->mg_ok) {
+    // multigrid-preconditioned CG on Kx + s Mx (every level's operator gets
+    // the mass term; see mg.hip and mg3.hip)
     if (!P->mg) {
       P->mg = std::make_unique<MGRunner>();
       P->mg->setup(P->mg_plan_);
     }
     MGRunner& r = *P->mg;
     const int e = r.expect;
-    r.w.plan.sw0 = s * P->M.c[13] / 6.0;
+    r.w.plan.sw0 = s * mass_scale(P->grid, P->M);
     r.expect = r.expect_shifted;
     CGScal out[kMaxCols];
     try {
@@ -1754,9 +1760,9 @@ sts_status sts_shifted_solve(const sts_space* space, double shift, const double*
       return;
     }
     MGPlan plan{};
-    if (g.dim == 2 && mg_plan(g, K, &plan)) {
+    if (mg_plan(g, K, &plan)) {
       // multigrid-preconditioned CG on Kx + shift Mx
-      plan.sw0 = shift * M.c[13] / 6.0;
+      plan.sw0 = shift * mass_scale(g, M);
       MGRunner r;
       r.setup(plan);
       CGScal out[kMaxCols];
@@ -1899,9 +1905,7 @@ sts_status sts_mg_vcycle_shifted(const sts_space* space, double shift, const dou
     Grid g;
     MGPlan plan = require_mg(space, &g);
     STS_REQUIRE(shift >= 0.0 && std::isfinite(shift), STS_E_INVALID, "shift must be >= 0");
-    STS_REQUIRE(shift == 0.0 || g.dim == 2, STS_E_INVALID,
-                "the shifted V-cycle is for 2-D P1 spaces");
-    plan.sw0 = shift * make_stencil(*space, STS_OP_M).c[13] / 6.0;
+    plan.sw0 = shift * mass_scale(g, make_stencil(*space, STS_OP_M));
     STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
     STS_REQUIRE(R && Z && ldr >= g.nh && ldz >= g.nh, STS_E_INVALID, "bad buffers");
     hipStream_t st = static_cast<hipStream_t>(stream);

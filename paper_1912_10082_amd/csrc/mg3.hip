@@ -27,6 +27,12 @@
 // smoothing polynomial is the adjoint of the pre-smoothing one), so the outer
 // iteration is ordinary preconditioned CG.
 //
+// Shifted operator Kx + s Mx (the rational Krylov steps, Sec. 4): every level
+// adds s times its own Q1 mass (rediscretised: the Q1 mass is not a Galerkin
+// product of the Kuhn-mesh interpolation), the smoother uses the shifted
+// diagonal, and the coarsest solve stays exact because tridiag(1, 4, 1) is
+// diagonalised by the same sine transform.
+//
 // Launches per smoothed level: "pre" (both pre-smoothing steps from zero,
 // which need b on a one-node halo only, on the tile and its halo, then the
 // residual; the iterate and the residual are stored), "restrict" (P^T of the
@@ -65,12 +71,34 @@ __device__ __forceinline__ Tile3 tile_of(int t, int ntx, int nty, int sx, int sy
   return Tile3{(t % ntx) * sx, ((t / ntx) % nty) * sy, (t / (ntx * nty)) * sz};
 }
 
-// c (6 u - sum of the six neighbours) at LDS point q of an array with rows
-// of X and planes of X * Y.
-template <int X, int Y>
-__device__ __forceinline__ double k7(const double* s, int q, double c) {
-  return c * (6.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - X] + s[q + X]) -
-              (s[q - X * Y] + s[q + X * Y]));
+// The level operator at LDS point q of an array with rows of X and planes of
+// X * Y: c (6 u - sum of the six neighbours), plus with SH the shifted mass
+// term sm (1, 4, 1) x (1, 4, 1) x (1, 4, 1) (s Mx, Mx the Q1 mass with
+// sm = s (h/6)^3 of the level; the coarse levels rediscretise it).
+template <bool SH, int X, int Y>
+__device__ __forceinline__ double k7(const double* s, int q, double c, double sm) {
+  double v = c * (6.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - X] + s[q + X]) -
+                  (s[q - X * Y] + s[q + X * Y]));
+  if (SH) {
+    double m = 0.0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int o = q + dz * X * Y + dy * X;
+        const double w = (dz == 0 ? 4.0 : 1.0) * (dy == 0 ? 4.0 : 1.0);
+        m += w * ((s[o - 1] + s[o + 1]) + 4.0 * s[o]);
+      }
+    }
+    v += sm * m;
+  }
+  return v;
+}
+
+// Diagonal of the level operator.
+template <bool SH>
+__device__ __forceinline__ double k7_diag(double c, double sm) {
+  return SH ? 6.0 * c + 64.0 * sm : 6.0 * c;
 }
 
 // The tile of g (n^3 nodes, x fastest) with a one-node halo into s; zero
@@ -109,6 +137,7 @@ struct Level3Args {
   int cols[kMaxCols];
   const CGScal* st;     // per-column activity, may be null (all active)
   double c;             // stencil coefficient of the fine level
+  double sm;            // shifted mass scale s (h/6)^3 of the fine level (0: Kx alone)
   double a1, c0, c1;    // Chebyshev coefficients of steps 0 and 1
   double* part;         // post2: per-tile (b, e), may be null
   int max_tiles;
@@ -125,6 +154,7 @@ struct Level3Args {
 // residual r = b - K u_2 on the tile.  Stores u_2 (for post1) and r.  One LDS
 // array holds b first and u_2 after it (the values pass through registers),
 // which keeps five work-groups per compute unit.
+template <bool SH>
 __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
   constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
@@ -141,7 +171,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
     sh[i] = in ? bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
   }
   __syncthreads();
-  const double inv_d = 1.0 / (6.0 * a.c);
+  const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
   double u2r[NU];
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
@@ -154,7 +184,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
         const int q = ((lz + 1) * BY + ly + 1) * BX + lx + 1;
         const double b = sh[q];
         const double u1 = a.c0 * inv_d * b;
-        const double ku1 = a.c0 * inv_d * k7<BX, BY>(sh, q, a.c);
+        const double ku1 = a.c0 * inv_d * k7<SH, BX, BY>(sh, q, a.c, a.sm);
         u2 = u1 + (a.a1 * u1 + a.c1 * inv_d * (b - ku1));
       }
     }
@@ -185,7 +215,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
       const size_t g = ((size_t)gz * nf + gy) * nf + gx;
       const int q = ((lz + 1) * RY + ly + 1) * RX + lx + 1;
       xp[g] = sh[q];
-      r[g] = bc[k] - k7<RX, RY>(sh, q, a.c);
+      r[g] = bc[k] - k7<SH, RX, RY>(sh, q, a.c, a.sm);
     }
   }
 }
@@ -241,6 +271,7 @@ __device__ __forceinline__ double interp3(const double* es, int ox, int oy, int 
 
 // post1: u = u_2 + P e_c on the tile and its halo; d_0 = c_0 (b - K u) / D,
 // u_1 = u + d_0 on the tile.
+template <bool SH>
 __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = TZ / 2 + 2;
   __shared__ double us[NR];
@@ -263,18 +294,19 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
       us[i] += interp3<EX, EY>(es, ox, oy, oz, gx, gy, gz);
   }
   __syncthreads();
-  const double inv_d = 1.0 / (6.0 * a.c);
+  const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
   const double* bf = a.bf + (size_t)col * a.ldf;
   double* u1 = a.u1 + (size_t)col * a.ldf;
   double* d0 = a.d0 + (size_t)col * a.ldf;
   for_core(nf, T, [&](size_t g, int q) {
-    const double d = a.c0 * inv_d * (bf[g] - k7<RX, RY>(us, q, a.c));
+    const double d = a.c0 * inv_d * (bf[g] - k7<SH, RX, RY>(us, q, a.c, a.sm));
     d0[g] = d;
     u1[g] = us[q] + d;
   });
 }
 
 // post2: d_1 = a_1 d_0 + c_1 (b - K u_1) / D, e = u_1 + d_1; per-tile (b, e).
+template <bool SH>
 __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
   __shared__ double us[NR];
   __shared__ double red[kT / 64];
@@ -283,14 +315,14 @@ __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
   const int nf = a.nf;
   load_halo(a.u1 + (size_t)col * a.ldf, nf, T, us);
   __syncthreads();
-  const double inv_d = 1.0 / (6.0 * a.c);
+  const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
   const double* bf = a.bf + (size_t)col * a.ldf;
   const double* d0 = a.d0 + (size_t)col * a.ldf;
   double* ef = a.ef + (size_t)col * a.ldf;
   double part = 0.0;
   for_core(nf, T, [&](size_t g, int q) {
     const double b = bf[g];
-    const double e = us[q] + (a.a1 * d0[g] + a.c1 * inv_d * (b - k7<RX, RY>(us, q, a.c)));
+    const double e = us[q] + (a.a1 * d0[g] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
     ef[g] = e;
     part += b * e;
   });
@@ -311,6 +343,7 @@ struct Coarse3Args {
   const double* rhs;    // last stage with partials: the right-hand side b
   const double* dst;    // S (m x m, symmetric), then l (m)
   double c;             // stencil coefficient of the coarse level
+  double sm;            // shifted mass scale of the coarse level (0: Kx alone)
   int nlaunch;
   int cols[kMaxCols];
   const CGScal* st;
@@ -395,9 +428,13 @@ __global__ __launch_bounds__(kCT) void coarse3_z_kernel(Coarse3Args a) {
   }
   if (threadIdx.x < kE) l[threadIdx.x] = threadIdx.x < m ? a.dst[(size_t)m * m + threadIdx.x] : 0.0;
   __syncthreads();
-  const double ly = l[y], c = a.c;
+  // Kx + s Mx in the sine basis: c (l_z + l_y + l_x) + sm (6 - l_z)(6 - l_y)(6 - l_x)
+  // (tridiag(1, 4, 1) = 6 I - tridiag(-1, 2, -1))
+  const double ly = l[y], c = a.c, sm = a.sm;
   lds_gemm64(S, X, Tm, [&](int r, int x, double v) {
-    return (r < m && x < m) ? v / (c * (l[r] + ly + l[x])) : 0.0;
+    return (r < m && x < m)
+               ? v / (c * (l[r] + ly + l[x]) + sm * ((6.0 - l[r]) * (6.0 - ly) * (6.0 - l[x])))
+               : 0.0;
   });
   __syncthreads();
   lds_gemm64(S, Tm, X, [](int, int, double v) { return v; });
@@ -419,6 +456,7 @@ struct PCG3Args {
   int nlaunch;
   int cols[kMaxCols];
   double c;
+  double sm;
   double* x;
   int64_t ldx;
   double* r;
@@ -469,6 +507,7 @@ __global__ __launch_bounds__(kT) void pcg3_reduce_kernel(Reduce3Args a) {
   const Tile3 T = tile_of(t, (A).ntx, (A).nty, TX, TY, TZ);
 
 // A: stopping test and beta; p = z + beta p; q = K p; (p, q).
+template <bool SH>
 __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
   __shared__ double ps[NR];
   __shared__ double red[2][kT / 64];
@@ -526,7 +565,7 @@ __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
   double part = 0.0;
   for_core(n, T, [&](size_t g, int q) {
     const double pv = ps[q];
-    const double qv = k7<RX, RY>(ps, q, a.c);
+    const double qv = k7<SH, RX, RY>(ps, q, a.c, a.sm);
     pout[g] = pv;
     qg[g] = qv;
     part += pv * qv;
@@ -617,6 +656,7 @@ PCG3Args pcg3_args(const MGWork& w, int parity, const int* cols, int nlaunch, in
   a.nlaunch = nlaunch;
   for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
   a.c = w.plan.mu;
+  a.sm = w.plan.sw0;
   a.x = w.x;
   a.ldx = w.ldx;
   a.r = w.b[0];
@@ -690,6 +730,7 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
   const MGPlan& p = w.plan;
   const int L = p.nlev;
   const Smooth sm = smooth_coefficients(kSmoothLo);
+  const bool shifted = p.sw0 != 0.0;
   auto level = [&](int l) {
     Level3Args a{};
     a.nf = p.n[l];
@@ -707,6 +748,7 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     for (int j = 0; j < nlaunch; ++j) a.cols[j] = cols[j];
     a.st = act;
     a.c = level_coef(p, l);
+    a.sm = std::ldexp(p.sw0, 3 * l);   // (h_l / 6)^3 = 8^l (h / 6)^3
     a.a1 = sm.a[1];
     a.c0 = sm.c[0];
     a.c1 = sm.c[1];
@@ -723,7 +765,12 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     Level3Args a = level(l);
     const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
     int blocks = fine_tiles(a);
-    launch(STS_K_MG_DOWN, 24.0 * nf * nlaunch, mg3_pre_kernel, dim3(blocks), dim3(kT), 0, st, a);
+    if (shifted)
+      launch(STS_K_MG_DOWN, 24.0 * nf * nlaunch, mg3_pre_kernel<true>, dim3(blocks), dim3(kT), 0,
+             st, a);
+    else
+      launch(STS_K_MG_DOWN, 24.0 * nf * nlaunch, mg3_pre_kernel<false>, dim3(blocks), dim3(kT), 0,
+             st, a);
     STS_HIP(hipGetLastError());
     a.ntx = (a.nc + CX - 1) / CX;
     a.nty = (a.nc + CY - 1) / CY;
@@ -740,6 +787,7 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     c.ld = w.ld[L];
     c.dst = w.dst;
     c.c = level_coef(p, L);
+    c.sm = std::ldexp(p.sw0, 3 * L);
     c.nlaunch = nlaunch;
     for (int j = 0; j < nlaunch; ++j) c.cols[j] = cols[j];
     c.st = act;
@@ -763,11 +811,20 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     Level3Args a = level(l);
     const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
     const int blocks = fine_tiles(a);
-    launch(STS_K_MG_UP, 8.0 * (4.0 * nf + nc) * nlaunch, mg3_post1_kernel, dim3(blocks), dim3(kT),
-           0, st, a);
+    if (shifted)
+      launch(STS_K_MG_UP, 8.0 * (4.0 * nf + nc) * nlaunch, mg3_post1_kernel<true>, dim3(blocks),
+             dim3(kT), 0, st, a);
+    else
+      launch(STS_K_MG_UP, 8.0 * (4.0 * nf + nc) * nlaunch, mg3_post1_kernel<false>, dim3(blocks),
+             dim3(kT), 0, st, a);
     STS_HIP(hipGetLastError());
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
-    launch(STS_K_MG_UP, 32.0 * nf * nlaunch, mg3_post2_kernel, dim3(blocks), dim3(kT), 0, st, a);
+    if (shifted)
+      launch(STS_K_MG_UP, 32.0 * nf * nlaunch, mg3_post2_kernel<true>, dim3(blocks), dim3(kT), 0,
+             st, a);
+    else
+      launch(STS_K_MG_UP, 32.0 * nf * nlaunch, mg3_post2_kernel<false>, dim3(blocks), dim3(kT), 0,
+             st, a);
     STS_HIP(hipGetLastError());
   }
 }
@@ -804,7 +861,10 @@ void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int
     STS_HIP(hipGetLastError());
     a.tot = w.tot;
   }
-  launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel, dim3(blocks), dim3(kT), 0, st, a);
+  if (w.plan.sw0 != 0.0)
+    launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel<true>, dim3(blocks), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel<false>, dim3(blocks), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
   if (split) {
     r.part[0] = w.part_pq;

@@ -182,7 +182,8 @@ struct MGPlan {
   int exact;                 // size of the exactly solved coarsest level (= n[nlev])
   double mu;                 // 2-D: Kx = mu (4; -1 x 4) on every level;
                              // 3-D: Kx = mu (6; -1 x 6) on level 0, 2^l mu on level l
-  double sw0;                // 2-D: solve with Kx + s Mx, sw0 = s h^2 / 12 (0: Kx alone)
+  double sw0;                // Kx + s Mx: s times the level-0 mass scale (2-D h^2 / 12,
+                             // 3-D (h/6)^3); 0: Kx alone
 };
 // The m x m sine-transform matrix (row-major) followed by the m eigenvalues
 // 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.

@@ -188,13 +188,26 @@ def stiffness3(n: int, mu: float) -> sp.csr_matrix:
     return (mu * h * K).tocsr()
 
 
-def exact3(b: np.ndarray, n: int, mu: float) -> np.ndarray:
-    """Kx^{-1} b for the seven-point stiffness by the sine transform."""
+@functools.lru_cache(maxsize=8)
+def mass3(n: int) -> sp.csr_matrix:
+    """(h/6)^3 Tm (x) Tm (x) Tm, Tm = tridiag(1, 4, 1): the oracle's Q1 mass as a
+    Kronecker product (equal to its element assembly)."""
+    h = 1.0 / (n + 1)
+    Tm = sp.diags([np.ones(n - 1), 4.0 * np.ones(n), np.ones(n - 1)], [-1, 0, 1])
+    return ((h / 6.0) ** 3 * sp.kron(sp.kron(Tm, Tm), Tm)).tocsr()
+
+
+def exact3(b: np.ndarray, n: int, mu: float, shift: float = 0.0) -> np.ndarray:
+    """(Kx + shift Mx)^{-1} b for the seven-point stiffness and the Q1 mass by
+    the sine transform (both are diagonal in the sine basis)."""
     from scipy.fft import dstn
 
     h = 1.0 / (n + 1)
     lam = 2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi * h)
     D = mu * h * (lam[:, None, None] + lam[None, :, None] + lam[None, None, :])
+    if shift:
+        tm = 6.0 - lam
+        D = D + shift * (h / 6.0) ** 3 * (tm[:, None, None] * tm[None, :, None] * tm[None, None, :])
     cols = b.reshape(n ** 3, -1)
     out = np.empty_like(cols)
     for j in range(cols.shape[1]):
@@ -221,17 +234,20 @@ def chebyshev3(K, b, u, steps=CHEB3_STEPS, interval=CHEB3_INTERVAL):
     return u
 
 
-def vcycle3(b: np.ndarray, n: int, mu: float) -> np.ndarray:
-    """One 3-D V-cycle from zero applied to b (length n^3, or n^3 x m)."""
+def vcycle3(b: np.ndarray, n: int, mu: float, shift: float = 0.0) -> np.ndarray:
+    """One 3-D V-cycle from zero applied to b (length n^3, or n^3 x m) for
+    Kx + shift Mx; the coarse levels rediscretise the Q1 mass."""
     if n <= EXACT3:
-        return exact3(b, n, mu)
+        return exact3(b, n, mu, shift)
     assert n % 2 == 1, "levels above the exact size must halve"
     K = stiffness3(n, mu)
+    if shift:
+        K = (K + shift * mass3(n)).tocsr()
     u = chebyshev3(K, b, np.zeros_like(b))
     nc = (n - 1) // 2
     P = prolongation3(nc)
     # the coarse stiffness is mu (2h) (6; -1 x 6): the same stencil at nc
-    u = u + P @ vcycle3(P.T @ (b - K @ u), nc, mu)
+    u = u + P @ vcycle3(P.T @ (b - K @ u), nc, mu, shift)
     return chebyshev3(K, b, u)
 
 

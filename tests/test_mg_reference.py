@@ -233,6 +233,36 @@ def test_pcg3_iterations_stay_small():
     assert its[1] <= 12, its
 
 
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_kronecker_mass_equals_the_element_assembly(n):
+    from oracle import fem
+    M = fem.spatial_operators(3, n, 0.45)[1]
+    assert abs(mgr.mass3(n) - M).max() <= 1e-14 * abs(M).max()
+
+
+def test_exact3_shifted_is_the_inverse():
+    n, mu, s = 9, 0.8, 120.0
+    A = (mgr.stiffness3(n, mu) + s * mgr.mass3(n)).tocsc()
+    B = np.random.default_rng(4).normal(size=(n ** 3, 2))
+    X = spla.spsolve(A, B).reshape(B.shape)
+    np.testing.assert_allclose(mgr.exact3(B, n, mu, s), X, rtol=1e-12, atol=1e-13 * abs(X).max())
+
+
+@pytest.mark.parametrize("shift", [30.0, 3e3])
+def test_shifted_vcycle3_is_spd_and_converges(shift):
+    n, mu = 65, 1.1
+    A = (mgr.stiffness3(n, mu) + shift * mgr.mass3(n)).tocsr()
+    R = np.random.default_rng(9).normal(size=(n ** 3, 2))
+    Z = mgr.vcycle3(R, n, mu, shift)
+    G = R.T @ Z
+    np.testing.assert_allclose(G, G.T, rtol=1e-12, atol=1e-14 * abs(G).max())
+    assert np.all(np.diag(G) > 0)
+    b = R[:, 0]
+    x, it = _pcg(A, b, lambda r: mgr.vcycle3(r, n, mu, shift), 1e-12)
+    assert it > 0 and np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b)
+    assert it <= 20, it
+
+
 def test_supported_grids_3d():
     assert all(mgr.supported3(n) for n in (1, 2, 40, 63, 95, 127, 191, 255, 511))
     assert not any(mgr.supported3(n) for n in (64, 100, 128, 254))
