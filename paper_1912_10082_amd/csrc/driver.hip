@@ -907,7 +907,8 @@ void ritz_values(sts_problem* P, int64_t k, std::vector<double>& out) {
   EigWork ew{};
   ew.base = P->eig_work.d();
   ew.status = static_cast<int*>(P->eig_meta.p);
-  sym_eig((int)k, P->Kred.d(), P->kcap, P->lam.d(), P->Q.d(), P->kcap, ew, P->stream);
+  // the shift rule needs the Ritz values only
+  sym_eigvals((int)k, P->Kred.d(), P->kcap, P->lam.d(), ew, P->stream);
   out.resize(k);
   STS_HIP(hipMemcpyAsync(out.data(), P->lam.d(), k * sizeof(double), hipMemcpyDeviceToHost,
                          P->stream));

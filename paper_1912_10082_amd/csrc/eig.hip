@@ -585,6 +585,35 @@ int64_t eig_work_doubles(int k) {
          + 5 * kk;                 // inverse-iteration factors
 }
 
+void sym_eigvals(int k, const double* A, int64_t lda, double* lam, const EigWork& w,
+                 hipStream_t st) {
+  STS_REQUIRE(k >= 1 && k <= kEigMaxK, STS_E_INVALID, "sym_eigvals: order out of range");
+  // the workspace layout of sym_eig, first two stages only
+  const int64_t kk = (int64_t)k * k;
+  double* p = w.base;
+  double* a = p;
+  p += kk;
+  double* d = p;
+  double* e = p + k;
+  double* tau = p + 2 * k;
+  p += 4 * (int64_t)k;
+  double* vp = p;
+  double* wp = p + (int64_t)k * kEigNB;
+  p += 2 * (int64_t)k * kEigNB;
+  double* bounds = p;
+  TriArgs t{k, A, lda, w.status, a, d, e, tau, vp, wp, bounds};
+  const double kk8 = 8.0 * (double)k * k;
+  if (k <= kLdsPanelMaxK)
+    launch(STS_K_TRIDIAG, kk8, tridiag_kernel<true>, dim3(1), dim3(kTT), 0, st, t);
+  else
+    launch(STS_K_TRIDIAG, kk8, tridiag_kernel<false>, dim3(1), dim3(kTT), 0, st, t);
+  STS_HIP(hipGetLastError());
+  const int nthreads = k * kSect;
+  launch(STS_K_BISECT, 24.0 * k, bisect_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, st, k,
+         d, e, bounds, lam);
+  STS_HIP(hipGetLastError());
+}
+
 void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_t ldq,
              const EigWork& w, hipStream_t st) {
   STS_REQUIRE(k >= 1 && k <= kEigMaxK, STS_E_INVALID, "sym_eig: order out of range");

@@ -374,6 +374,10 @@ int64_t eig_work_doubles(int k);
 // iteration, Rayleigh-Ritz correction, back-transformation.
 void sym_eig(int k, const double* A, int64_t lda, double* lam, double* Q, int64_t ldq,
              const EigWork& w, hipStream_t st);
+// Eigenvalues only (tridiagonalisation and bisection), ascending, into lam
+// (device, k); same workspace as sym_eig.
+void sym_eigvals(int k, const double* A, int64_t lda, double* lam, const EigWork& w,
+                 hipStream_t st);
 
 struct TimeOps {
   const double* d;   // Dt diagonal (nt)
