@@ -483,6 +483,9 @@ def main() -> int:
                          "rank-4 solve in FP64; batch2d: 256 uneven 2-D problems through the "
                          "batch executor; serve: Poisson arrivals of mixed 1-D / 2-D / 3-D "
                          "requests through the request server")
+    ap.add_argument("--precond-fp32", action="store_true",
+                    help="heat3d: multigrid V-cycle vectors in FP32 inside FP64 CG "
+                         "(sts_opts.precond_fp32); the default run is FP64 throughout")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window")
@@ -548,6 +551,10 @@ def main() -> int:
     # still decides convergence.  j = 1 in 2-D, 2 in 3-D (measured best: with
     # j = 1 the 3-D solve needs a second exact residual, 0.7 s)
     opts = dict(tol=args.tol, restart=1, max_outer=60 if d3 else 150, inner_relax=2 if d3 else 1)
+    if args.precond_fp32:
+        # mixed precision: the 3-D multigrid V-cycle stores its vectors in FP32
+        # inside FP64 CG (sts_opts.precond_fp32); everything else stays FP64
+        opts["precond_fp32"] = 1
     for i in range(args.warmup):
         info = prob.solve(**opts)
         _log(f"warmup {i}: {info['status']} outer={info['outer_its']} k={info['k']} "
@@ -654,9 +661,10 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32_precond" if args.precond_fp32 else "f64",
         "data": "synthetic",
-        "config": ({"workload": f"heat3d_q1_7pt_{w.n[0]}^3_nt{w.nt}_rank4_tol{args.tol:g}",
+        "config": ({"workload": f"heat3d_q1_7pt_{w.n[0]}^3_nt{w.nt}_rank4_tol{args.tol:g}"
+                                + ("_mg_fp32" if args.precond_fp32 else ""),
                     "nh": w.nh, "nt": w.nt, "p": 4, "tol": args.tol, "seed": 3} if d3 else
                    {"workload": f"heat2d_p1_courant_{w.n[0]}x{w.n[0]}_nt{w.nt}_rank2_tol{args.tol:g}",
                     "nh": w.nh, "nt": w.nt, "p": 2, "tol": args.tol, "seed": 2}),

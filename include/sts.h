@@ -130,6 +130,13 @@ typedef struct {
                                max(inner_rtol, min(1e-4, 10^-j tol / r)), r the last projected
                                residual estimate (1 before the first check); the exact residual
                                still decides convergence; 0 = inner_rtol throughout; default 0 */
+  int32_t precond_fp32;     /* 1 = mixed precision in the 3-D Kx solves (and the shifted solves
+                               of the rational Krylov space): the multigrid V-cycle that
+                               preconditions CG stores its vectors in FP32 (arithmetic in FP64);
+                               CG itself, its residuals, iterates and stopping test stay FP64, so
+                               the solves reach the same tolerances.  Applies to 3-D seven-point
+                               spaces with n > 63 (at least one smoothed level); elsewhere
+                               ignored.  0 = FP64 throughout; default 0 */
 } sts_opts;
 
 typedef struct {
@@ -317,6 +324,29 @@ sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, d
 sts_status sts_mg_vcycle_shifted(const sts_space* space, double shift, const double* R,
                                  int64_t ldr, double* Z, int64_t ldz, int32_t ncols,
                                  void* stream);
+
+/* Mixed precision (the FP32 bulk / FP64 accuracy split of the solves):
+ * sts_mg_vcycle_shifted with the V-cycle's vectors stored in FP32 -- the
+ * pre-smoothed iterates, residuals and Chebyshev directions of the finest
+ * level and every vector of the coarser ones, the exact coarsest solve
+ * included; R and Z stay FP64 and every operation is computed in FP64, so Z
+ * differs from the FP64 V-cycle's by rounding to single precision (relative
+ * about 1e-7), not by a different operator.  The V-cycle's bytes per node fall
+ * by about a third.  Spaces: 3-D seven-point with n > 63 halving to <= 63
+ * (STS_E_INVALID otherwise, and for a negative shift).  Layout as
+ * sts_mg_vcycle. */
+sts_status sts_mg_vcycle_mixed(const sts_space* space, double shift, const double* R, int64_t ldr,
+                               double* Z, int64_t ldz, int32_t ncols, void* stream);
+
+/* (Kx + shift Mx) X[:, c] = B[:, c] by FP64 conjugate gradients preconditioned
+ * with sts_mg_vcycle_mixed.  The FP32 rounding perturbs the preconditioner, not
+ * the operator or the residual recurrence, so the iteration reaches rtol as the
+ * FP64 one does (the CG iteration acts as the FP64 refinement of the FP32
+ * preconditioner).  Same spaces as sts_mg_vcycle_mixed; arguments, iters and
+ * errors as sts_pcg_mg. */
+sts_status sts_pcg_mg_mixed(const sts_space* space, double shift, const double* B, int64_t ldb,
+                            double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                            int32_t* iters, void* stream);
 
 /* Direct solves A X[:, c] = B[:, c], A = Kx or Mx per column (ops[c]), for a
  * 1-D P1 space (STS_FE_P1_1D; else STS_E_INVALID): both matrices of Sec. 3

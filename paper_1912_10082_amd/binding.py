@@ -45,7 +45,8 @@ class Opts(C.Structure):
                 ("inner_rtol", C.c_double), ("inner_maxit", C.c_int32), ("verify_true", C.c_int32),
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
                 ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32),
-                ("residual_qr", C.c_int32), ("inner_relax", C.c_int32)]
+                ("residual_qr", C.c_int32), ("inner_relax", C.c_int32),
+                ("precond_fp32", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -103,6 +104,9 @@ _SIGS = {
                              C.POINTER(_I32), _P]),
     "sts_mg_vcycle": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _P]),
     "sts_mg_vcycle_shifted": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _P]),
+    "sts_mg_vcycle_mixed": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _P]),
+    "sts_pcg_mg_mixed": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _F64, _I32,
+                                   C.POINTER(_I32), _P]),
     "sts_adaptive_shift": (C.c_int, [_D, _I32, _D, _I32, _F64, _F64, _I32, _D]),
     "sts_shifted_solve": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _F64, _I32,
                                     C.POINTER(_I32), _P]),
@@ -391,6 +395,21 @@ def pcg_mg(space: Space, B, rtol: float = 1e-12, maxit: int = 1000, check: bool 
     return X, list(its), code
 
 
+def pcg_mg_mixed(space: Space, B, shift: float = 0.0, rtol: float = 1e-12, maxit: int = 1000,
+                 check: bool = True):
+    """(Kx + shift Mx) X = B by FP64 CG preconditioned with the FP32-storage
+    V-cycle (3-D seven-point spaces with a smoothed level)."""
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_zeros(B.shape[0], B.shape[1])
+    its = (C.c_int32 * B.shape[1])()
+    code = load().sts_pcg_mg_mixed(C.byref(space), float(shift), pb, ldb,
+                                   C.c_void_p(X.data_ptr()), X.shape[0], B.shape[1], rtol, maxit,
+                                   its, _stream_handle())
+    if check:
+        _check(code)
+    return X, list(its), code
+
+
 def mass_solve(space: Space, B, rtol: float = 1e-13):
     """Mx X = B: Chebyshev iteration (2-D P1) or direct line solves (3-D trilinear); returns (X, iterations)."""
     B, pb, ldb = dev_colmajor(B)
@@ -433,12 +452,17 @@ def shifted_solve(space: Space, shift: float, B, rtol: float = 1e-13, maxit: int
     return X, list(its)
 
 
-def mg_vcycle(space: Space, R, shift: float = 0.0):
+def mg_vcycle(space: Space, R, shift: float = 0.0, fp32: bool = False):
     """Z = Bmg R, one multigrid V-cycle (the preconditioner of pcg_mg; with
-    shift > 0 that of the shifted solves, for Kx + shift Mx)."""
+    shift > 0 that of the shifted solves, for Kx + shift Mx); fp32 = the
+    V-cycle with FP32 storage (sts_mg_vcycle_mixed)."""
     R, pr, ldr = dev_colmajor(R)
     Z = dev_empty(R.shape[0], R.shape[1])
-    if shift:
+    if fp32:
+        _check(load().sts_mg_vcycle_mixed(C.byref(space), float(shift), pr, ldr,
+                                          C.c_void_p(Z.data_ptr()), max(Z.shape[0], 1),
+                                          R.shape[1], _stream_handle()))
+    elif shift:
         _check(load().sts_mg_vcycle_shifted(C.byref(space), float(shift), pr, ldr,
                                             C.c_void_p(Z.data_ptr()), max(Z.shape[0], 1),
                                             R.shape[1], _stream_handle()))

@@ -827,6 +827,7 @@ void run_shifted_block(sts_problem* P, double s, int ncols, const double* const*
     MGRunner& r = *P->mg;
     const int e = r.expect;
     r.w.plan.sw0 = s * mass_scale(P->grid, P->M);
+    r.w.plan.f32 = o.precond_fp32;
     r.expect = r.expect_shifted;
     CGScal out[kMaxCols];
     try {
@@ -923,6 +924,7 @@ void run_mg_k(sts_problem* P, int nk, const double* const* b, double* x, const s
     P->mg->setup(P->mg_plan_);
   }
   CGScal out[kMaxCols];
+  P->mg->w.plan.f32 = o.precond_fp32;
   P->mg->run(x, P->ldv, nk, b, o.inner_rtol, o.inner_maxit, out, P->stream);
   const double bpn = P->mg->bytes_per_node();
   for (int j = 0; j < nk; ++j) {
@@ -1104,6 +1106,18 @@ MGPlan require_mg(const sts_space* space, Grid* g) {
   MGPlan plan{};
   STS_REQUIRE(mg_plan(*g, make_stencil(*space, STS_OP_K), &plan), STS_E_INVALID,
               "multigrid needs a 2-D P1 or 3-D seven-point space whose n halves, n -> (n-1)/2, down to <= 63");
+  return plan;
+}
+
+// Multigrid plan of a space for the mixed-precision V-cycle (STS_E_INVALID
+// where it does not apply: 2-D spaces and 3-D grids without a smoothed level).
+MGPlan require_mg_mixed(const sts_space* space, double shift, Grid* g) {
+  MGPlan plan = require_mg(space, g);
+  STS_REQUIRE(plan.dim == 3 && plan.nlev >= 1, STS_E_INVALID,
+              "the FP32 V-cycle needs a 3-D seven-point space with n > 63 (at least one smoothed level)");
+  STS_REQUIRE(shift >= 0.0 && std::isfinite(shift), STS_E_INVALID, "shift must be >= 0");
+  plan.sw0 = shift * mass_scale(*g, make_stencil(*space, STS_OP_M));
+  plan.f32 = 1;
   return plan;
 }
 
@@ -1337,7 +1351,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     STS_REQUIRE(o.tol > 0.0 && o.max_outer >= 1 && o.inner_rtol > 0.0 && o.inner_maxit >= 1 &&
                     o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0 &&
                     o.residual_qr >= -1 && o.residual_qr <= 1 && o.inner_relax >= 0 &&
-                    o.inner_relax <= 6,
+                    o.inner_relax <= 6 && (o.precond_fp32 == 0 || o.precond_fp32 == 1),
                 STS_E_INVALID, "invalid options");
     P->residual_qr = o.residual_qr;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1919,6 +1933,54 @@ sts_status sts_mg_vcycle_shifted(const sts_space* space, double shift, const dou
     copy_cols(g.nh, ncols, r.w.e[0], r.w.ld[0], Z, ldz, st);
     STS_HIP(hipStreamSynchronize(st));
   });
+}
+
+sts_status sts_mg_vcycle_mixed(const sts_space* space, double shift, const double* R,
+                               int64_t ldr, double* Z, int64_t ldz, int32_t ncols,
+                               void* stream) {
+  return run_guarded([&] {
+    Grid g;
+    const MGPlan plan = require_mg_mixed(space, shift, &g);
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(R && Z && ldr >= g.nh && ldz >= g.nh, STS_E_INVALID, "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MGRunner r;
+    r.setup(plan);
+    copy_cols(g.nh, ncols, R, ldr, r.w.b[0], r.w.ld[0], st);
+    int cols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) cols[c] = c;
+    mg_vcycle(r.w, nullptr, cols, ncols, false, st);
+    copy_cols(g.nh, ncols, r.w.e[0], r.w.ld[0], Z, ldz, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_pcg_mg_mixed(const sts_space* space, double shift, const double* B, int64_t ldb,
+                            double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                            int32_t* iters, void* stream) {
+  sts_status bad = STS_OK;
+  sts_status s = run_guarded([&] {
+    Grid g;
+    const MGPlan plan = require_mg_mixed(space, shift, &g);
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(rtol > 0.0 && maxit >= 1, STS_E_INVALID, "bad rtol / maxit");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MGRunner r;
+    r.setup(plan);
+    const double* bcols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
+    CGScal out[kMaxCols];
+    r.run(X, ldx, ncols, bcols, rtol, maxit, out, st);
+    STS_HIP(hipStreamSynchronize(st));
+    bad = cg_status(out, ncols, iters);
+  });
+  if (s == STS_OK && bad != STS_OK) {
+    set_error(bad == STS_E_NUMERIC ? "preconditioned CG breakdown"
+                                   : "preconditioned CG reached maxit");
+    return bad;
+  }
+  return s;
 }
 
 sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,

@@ -103,11 +103,12 @@ __device__ __forceinline__ double k7_diag(double c, double sm) {
 
 // The tile of g (n^3 nodes, x fastest) with a one-node halo into s; zero
 // outside the domain (the Dirichlet values).
-__device__ __forceinline__ void load_halo(const double* g, int n, const Tile3& T, double* s) {
+template <class S>
+__device__ __forceinline__ void load_halo(const S* g, int n, const Tile3& T, double* s) {
   for (int i = threadIdx.x; i < NR; i += kT) {
     const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
     const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
-    s[i] = in ? g[((size_t)gz * n + gy) * n + gx] : 0.0;
+    s[i] = in ? (double)g[((size_t)gz * n + gy) * n + gx] : 0.0;
   }
 }
 
@@ -122,16 +123,20 @@ __device__ __forceinline__ void for_core(int n, const Tile3& T, F&& f) {
   }
 }
 
+// Vector types: the fine right-hand side bf and result ef are B, every other
+// vector (and both vectors of the coarser levels) S; double / double, or in
+// the mixed-precision V-cycle double / float on the finest level and
+// float / float below it.  Arithmetic is FP64 throughout.
 struct Level3Args {
   int nf, nc;           // fine / coarse nodes per direction (nf = 2 nc + 1)
-  int64_t ldf, ldc;     // column strides
-  const double* bf;     // fine right-hand side
-  double* xp;           // pre-smoothed iterate: written by pre, read by post1
-  double* bc;           // restrict: coarse right-hand side
-  const double* ec;     // post1: coarse correction
-  double* u1;           // post1 -> post2: iterate after the first step
-  double* d0;           // pre -> restrict: the residual; post1 -> post2: first Chebyshev direction
-  double* ef;           // post2: result on the fine level
+  int64_t ldf, ldc;     // column strides, in elements
+  const void* bf;       // fine right-hand side (B)
+  void* xp;             // pre-smoothed iterate: written by pre, read by post1 (S)
+  void* bc;             // restrict: coarse right-hand side (S)
+  const void* ec;       // post1: coarse correction (S)
+  void* u1;             // post1 -> post2: iterate after the first step (S)
+  void* d0;             // pre -> restrict: the residual; post1 -> post2: first Chebyshev direction (S)
+  void* ef;             // post2: result on the fine level (B)
   int ntx, nty, ntz;    // tiles of the launch
   int nlaunch;
   int cols[kMaxCols];
@@ -154,7 +159,7 @@ struct Level3Args {
 // residual r = b - K u_2 on the tile.  Stores u_2 (for post1) and r.  One LDS
 // array holds b first and u_2 after it (the values pass through registers),
 // which keeps five work-groups per compute unit.
-template <bool SH>
+template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
   constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
@@ -164,11 +169,11 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf;
-  const double* bf = a.bf + (size_t)col * a.ldf;
+  const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
   for (int i = threadIdx.x; i < BX * BY * BZ; i += kT) {
     const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
     const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
-    sh[i] = in ? bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+    sh[i] = in ? (double)bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
   }
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
@@ -204,8 +209,8 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
     if (i < NR) sh[i] = u2r[k];
   }
   __syncthreads();
-  double* xp = a.xp + (size_t)col * a.ldf;
-  double* r = a.d0 + (size_t)col * a.ldf;
+  S* xp = static_cast<S*>(a.xp) + (size_t)col * a.ldf;
+  S* r = static_cast<S*>(a.d0) + (size_t)col * a.ldf;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const int i = threadIdx.x + k * kT;
@@ -214,8 +219,8 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
     if (gx < nf && gy < nf && gz < nf) {
       const size_t g = ((size_t)gz * nf + gy) * nf + gx;
       const int q = ((lz + 1) * RY + ly + 1) * RX + lx + 1;
-      xp[g] = sh[q];
-      r[g] = bc[k] - k7<SH, RX, RY>(sh, q, a.c, a.sm);
+      xp[g] = (S)sh[q];
+      r[g] = (S)(bc[k] - k7<SH, RX, RY>(sh, q, a.c, a.sm));
     }
   }
 }
@@ -223,6 +228,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
 // restrict: b_c = P^T r, the coincident fine node plus half of each of its 14
 // neighbours along the seven edge directions, from r on the fine nodes
 // around the coarse tile.
+template <class S>
 __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
   constexpr int SX = 2 * CX + 1, SY = 2 * CY + 1, SZ = 2 * CZ + 1;
   __shared__ double rs[SX * SY * SZ];
@@ -230,15 +236,15 @@ __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
   const Tile3 C = tile_of(t, a.ntx, a.nty, CX, CY, CZ);
   const int nf = a.nf, nc = a.nc;
   const int fx0 = 2 * C.x0, fy0 = 2 * C.y0, fz0 = 2 * C.z0;
-  const double* r = a.d0 + (size_t)col * a.ldf;
+  const S* r = static_cast<const S*>(a.d0) + (size_t)col * a.ldf;
   for (int i = threadIdx.x; i < SX * SY * SZ; i += kT) {
     const int gx = fx0 + i % SX, gy = fy0 + (i / SX) % SY, gz = fz0 + i / (SX * SY);
     // fine nodes beyond the domain are never gathered (every coarse node's
     // neighbours lie inside); read them as zero
-    rs[i] = (gx < nf && gy < nf && gz < nf) ? r[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+    rs[i] = (gx < nf && gy < nf && gz < nf) ? (double)r[((size_t)gz * nf + gy) * nf + gx] : 0.0;
   }
   __syncthreads();
-  double* bc = a.bc + (size_t)col * a.ldc;
+  S* bc = static_cast<S*>(a.bc) + (size_t)col * a.ldc;
   for (int i = threadIdx.x; i < CX * CY * CZ; i += kT) {
     const int I = C.x0 + i % CX, J = C.y0 + (i / CX) % CY, K = C.z0 + i / (CX * CY);
     if (I < nc && J < nc && K < nc) {
@@ -249,7 +255,7 @@ __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
         const int o = (e & 1) + ((e >> 1) & 1) * SX + ((e >> 2) & 1) * SX * SY;
         s += rs[q + o] + rs[q - o];
       }
-      bc[((size_t)K * nc + J) * nc + I] = rs[q] + 0.5 * s;
+      bc[((size_t)K * nc + J) * nc + I] = (S)(rs[q] + 0.5 * s);
     }
   }
 }
@@ -271,7 +277,7 @@ __device__ __forceinline__ double interp3(const double* es, int ox, int oy, int 
 
 // post1: u = u_2 + P e_c on the tile and its halo; d_0 = c_0 (b - K u) / D,
 // u_1 = u + d_0 on the tile.
-template <bool SH>
+template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = TZ / 2 + 2;
   __shared__ double us[NR];
@@ -279,13 +285,13 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf, nc = a.nc;
-  load_halo(a.xp + (size_t)col * a.ldf, nf, T, us);
+  load_halo(static_cast<const S*>(a.xp) + (size_t)col * a.ldf, nf, T, us);
   const int ox = T.x0 / 2 - 1, oy = T.y0 / 2 - 1, oz = T.z0 / 2 - 1;
-  const double* ec = a.ec + (size_t)col * a.ldc;
+  const S* ec = static_cast<const S*>(a.ec) + (size_t)col * a.ldc;
   for (int i = threadIdx.x; i < EX * EY * EZ; i += kT) {
     const int I = ox + i % EX, J = oy + (i / EX) % EY, K = oz + i / (EX * EY);
     const bool in = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
-    es[i] = in ? ec[((size_t)K * nc + J) * nc + I] : 0.0;
+    es[i] = in ? (double)ec[((size_t)K * nc + J) * nc + I] : 0.0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NR; i += kT) {
@@ -295,36 +301,37 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   }
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
-  const double* bf = a.bf + (size_t)col * a.ldf;
-  double* u1 = a.u1 + (size_t)col * a.ldf;
-  double* d0 = a.d0 + (size_t)col * a.ldf;
+  const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
+  S* u1 = static_cast<S*>(a.u1) + (size_t)col * a.ldf;
+  S* d0 = static_cast<S*>(a.d0) + (size_t)col * a.ldf;
   for_core(nf, T, [&](size_t g, int q) {
-    const double d = a.c0 * inv_d * (bf[g] - k7<SH, RX, RY>(us, q, a.c, a.sm));
-    d0[g] = d;
-    u1[g] = us[q] + d;
+    const double d = a.c0 * inv_d * ((double)bf[g] - k7<SH, RX, RY>(us, q, a.c, a.sm));
+    d0[g] = (S)d;
+    u1[g] = (S)(us[q] + d);
   });
 }
 
 // post2: d_1 = a_1 d_0 + c_1 (b - K u_1) / D, e = u_1 + d_1; per-tile (b, e).
-template <bool SH>
+template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
   __shared__ double us[NR];
   __shared__ double red[kT / 64];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf;
-  load_halo(a.u1 + (size_t)col * a.ldf, nf, T, us);
+  load_halo(static_cast<const S*>(a.u1) + (size_t)col * a.ldf, nf, T, us);
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
-  const double* bf = a.bf + (size_t)col * a.ldf;
-  const double* d0 = a.d0 + (size_t)col * a.ldf;
-  double* ef = a.ef + (size_t)col * a.ldf;
+  const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
+  const S* d0 = static_cast<const S*>(a.d0) + (size_t)col * a.ldf;
+  B* ef = static_cast<B*>(a.ef) + (size_t)col * a.ldf;
   double part = 0.0;
   for_core(nf, T, [&](size_t g, int q) {
     const double b = bf[g];
-    const double e = us[q] + (a.a1 * d0[g] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
-    ef[g] = e;
-    part += b * e;
+    const double e =
+        us[q] + (a.a1 * (double)d0[g] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
+    ef[g] = (B)e;
+    part += b * (double)(B)e;   // (b, e) of the stored result
   });
   if (a.part) {
     part = block_sum<kT>(part, red);
@@ -335,12 +342,13 @@ __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
 // ---------------------------------------------------------------------------
 // exact coarse solve by the 3-D sine transform (order m <= kMG3ExactMax)
 // ---------------------------------------------------------------------------
+// in / out / rhs hold T (double, or float in the mixed-precision V-cycle).
 struct Coarse3Args {
   int m;
   int64_t ld;
-  const double* in;     // per column, m^3 (x fastest)
-  double* out;
-  const double* rhs;    // last stage with partials: the right-hand side b
+  const void* in;       // per column, m^3 (x fastest)
+  void* out;
+  const void* rhs;      // last stage with partials: the right-hand side b
   const double* dst;    // S (m x m, symmetric), then l (m)
   double c;             // stencil coefficient of the coarse level
   double sm;            // shifted mass scale of the coarse level (0: Kx alone)
@@ -374,6 +382,7 @@ __device__ __forceinline__ void lds_gemm64(const double* A, const double* B, dou
 }
 
 // Stage 0 / 2: every z-plane P (y rows, x columns) becomes S P S.
+template <class T>
 __global__ __launch_bounds__(kCT) void coarse3_plane_kernel(Coarse3Args a) {
   __shared__ double S[kE * kEL];
   __shared__ double X[kE * kEL];
@@ -383,12 +392,12 @@ __global__ __launch_bounds__(kCT) void coarse3_plane_kernel(Coarse3Args a) {
   if (a.st && !a.st[col].active) return;
   const int m = a.m, z = blockIdx.x;
   const size_t off = (size_t)col * a.ld + (size_t)z * m * m;
-  const double* in = a.in + off;
+  const T* in = static_cast<const T*>(a.in) + off;
   for (int i = threadIdx.x; i < kE * kE; i += kCT) {
     const int y = i / kE, x = i % kE;
     const bool ok = y < m && x < m;
     S[y * kEL + x] = ok ? a.dst[y * m + x] : 0.0;
-    X[y * kEL + x] = ok ? in[y * m + x] : 0.0;
+    X[y * kEL + x] = ok ? (double)in[y * m + x] : 0.0;
   }
   __syncthreads();
   auto keep = [](int, int, double v) { return v; };
@@ -396,12 +405,12 @@ __global__ __launch_bounds__(kCT) void coarse3_plane_kernel(Coarse3Args a) {
   __syncthreads();
   lds_gemm64(Tm, S, X, keep);
   __syncthreads();
-  double* out = a.out + off;
+  T* out = static_cast<T*>(a.out) + off;
   double part = 0.0;
   for (int i = threadIdx.x; i < m * m; i += kCT) {
     const double v = X[(i / m) * kEL + i % m];
-    out[i] = v;
-    if (a.part) part += a.rhs[off + i] * v;
+    out[i] = (T)v;
+    if (a.part) part += (double)static_cast<const T*>(a.rhs)[off + i] * v;
   }
   if (a.part) {
     part = block_sum<kCT>(part, red);
@@ -411,6 +420,7 @@ __global__ __launch_bounds__(kCT) void coarse3_plane_kernel(Coarse3Args a) {
 
 // Stage 1: every y-plane Q (z rows, x columns) becomes
 // S [(S Q) / (c (l_z + l_y + l_x))], in place.
+template <class T>
 __global__ __launch_bounds__(kCT) void coarse3_z_kernel(Coarse3Args a) {
   __shared__ double S[kE * kEL];
   __shared__ double X[kE * kEL];
@@ -419,12 +429,12 @@ __global__ __launch_bounds__(kCT) void coarse3_z_kernel(Coarse3Args a) {
   const int col = a.cols[blockIdx.y];
   if (a.st && !a.st[col].active) return;
   const int m = a.m, y = blockIdx.x;
-  double* io = a.out + (size_t)col * a.ld;
+  T* io = static_cast<T*>(a.out) + (size_t)col * a.ld;
   for (int i = threadIdx.x; i < kE * kE; i += kCT) {
     const int r = i / kE, x = i % kE;
     const bool ok = r < m && x < m;
     S[r * kEL + x] = ok ? a.dst[r * m + x] : 0.0;
-    X[r * kEL + x] = ok ? io[((size_t)r * m + y) * m + x] : 0.0;
+    X[r * kEL + x] = ok ? (double)io[((size_t)r * m + y) * m + x] : 0.0;
   }
   if (threadIdx.x < kE) l[threadIdx.x] = threadIdx.x < m ? a.dst[(size_t)m * m + threadIdx.x] : 0.0;
   __syncthreads();
@@ -441,7 +451,7 @@ __global__ __launch_bounds__(kCT) void coarse3_z_kernel(Coarse3Args a) {
   __syncthreads();
   for (int i = threadIdx.x; i < m * m; i += kCT) {
     const int r = i / m, x = i % m;
-    io[((size_t)r * m + y) * m + x] = X[r * kEL + x];
+    io[((size_t)r * m + y) * m + x] = (T)X[r * kEL + x];
   }
 }
 
@@ -719,11 +729,85 @@ double mg3_bytes_per_node(const MGPlan& p) {
   double b = 80.0 * n0;   // PCG A and B
   for (int l = 0; l < p.nlev; ++l) {
     const double nf = std::pow((double)p.n[l], 3), nc = std::pow((double)p.n[l + 1], 3);
-    b += 24.0 * nf + 8.0 * (nf + nc) + 8.0 * (4.0 * nf + nc) + 32.0 * nf;
+    const double sb = (p.f32 && l > 0) ? 4.0 : 8.0, ss = p.f32 ? 4.0 : 8.0;
+    // pre: b -> xp, r; restrict: r -> b_c; post1: xp, b, e_c -> d0, u1;
+    // post2: u1, b, d0 -> e
+    b += (sb + 2.0 * ss) * nf + ss * (nf + nc) + ((sb + 3.0 * ss) * nf + ss * nc) +
+         (2.0 * sb + 2.0 * ss) * nf;
   }
-  b += 48.0 * std::pow((double)p.exact, 3);
+  b += (p.f32 && p.nlev > 0 ? 24.0 : 48.0) * std::pow((double)p.exact, 3);
   return b / n0;
 }
+
+namespace {
+
+// The smoothed levels' launches with fine vectors B and the others S.
+template <class B, class S>
+void level_down(Level3Args a, bool shifted, int nlaunch, hipStream_t st) {
+  const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
+  const double sb = sizeof(B), ss = sizeof(S);
+  a.ntx = (a.nf + TX - 1) / TX;
+  a.nty = (a.nf + TY - 1) / TY;
+  a.ntz = (a.nf + TZ - 1) / TZ;
+  int blocks = a.ntx * a.nty * a.ntz * nlaunch;
+  const double pre = (sb + 2.0 * ss) * nf * nlaunch;
+  if (shifted)
+    launch(STS_K_MG_DOWN, pre, mg3_pre_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_MG_DOWN, pre, mg3_pre_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+  a.ntx = (a.nc + CX - 1) / CX;
+  a.nty = (a.nc + CY - 1) / CY;
+  a.ntz = (a.nc + CZ - 1) / CZ;
+  blocks = a.ntx * a.nty * a.ntz * nlaunch;
+  launch(STS_K_MG_RESTRICT, ss * (nf + nc) * nlaunch, mg3_restrict_kernel<S>, dim3(blocks),
+         dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+}
+
+template <class B, class S>
+void level_up(Level3Args a, bool shifted, int nlaunch, hipStream_t st) {
+  const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
+  const double sb = sizeof(B), ss = sizeof(S);
+  a.ntx = (a.nf + TX - 1) / TX;
+  a.nty = (a.nf + TY - 1) / TY;
+  a.ntz = (a.nf + TZ - 1) / TZ;
+  const int blocks = a.ntx * a.nty * a.ntz * nlaunch;
+  const double post1 = ((sb + 3.0 * ss) * nf + ss * nc) * nlaunch;
+  const double post2 = (2.0 * sb + 2.0 * ss) * nf * nlaunch;
+  if (shifted)
+    launch(STS_K_MG_UP, post1, mg3_post1_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_MG_UP, post1, mg3_post1_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+  if (shifted)
+    launch(STS_K_MG_UP, post2, mg3_post2_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_MG_UP, post2, mg3_post2_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+}
+
+template <class T>
+void coarse_solve(Coarse3Args c, const void* b, void* e, void* t1, void* part, int nlaunch,
+                  hipStream_t st) {
+  const int m = c.m;
+  const double by = 2.0 * sizeof(T) * std::pow((double)m, 3) * nlaunch;
+  const dim3 grid(m, nlaunch);
+  c.in = b;
+  c.out = t1;
+  launch(STS_K_MG_COARSE, by, coarse3_plane_kernel<T>, grid, dim3(kCT), 0, st, c);
+  STS_HIP(hipGetLastError());
+  launch(STS_K_MG_COARSE, by, coarse3_z_kernel<T>, grid, dim3(kCT), 0, st, c);
+  STS_HIP(hipGetLastError());
+  c.in = t1;
+  c.out = e;
+  c.rhs = b;
+  c.part = static_cast<double*>(part);
+  launch(STS_K_MG_COARSE, by, coarse3_plane_kernel<T>, grid, dim3(kCT), 0, st, c);
+  STS_HIP(hipGetLastError());
+}
+
+}  // namespace
 
 void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch, bool partials,
                 hipStream_t st) {
@@ -731,6 +815,9 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
   const int L = p.nlev;
   const Smooth sm = smooth_coefficients(kSmoothLo);
   const bool shifted = p.sw0 != 0.0;
+  // the mixed-precision V-cycle needs a smoothed level: its finest vectors
+  // (the PCG residual and preconditioned residual) stay FP64
+  const bool f32 = p.f32 && L > 0;
   auto level = [&](int l) {
     Level3Args a{};
     a.nf = p.n[l];
@@ -755,35 +842,14 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     a.max_tiles = w.max_tiles;
     return a;
   };
-  auto fine_tiles = [&](Level3Args& a) {
-    a.ntx = (a.nf + TX - 1) / TX;
-    a.nty = (a.nf + TY - 1) / TY;
-    a.ntz = (a.nf + TZ - 1) / TZ;
-    return a.ntx * a.nty * a.ntz * nlaunch;
-  };
   for (int l = 0; l < L; ++l) {
-    Level3Args a = level(l);
-    const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
-    int blocks = fine_tiles(a);
-    if (shifted)
-      launch(STS_K_MG_DOWN, 24.0 * nf * nlaunch, mg3_pre_kernel<true>, dim3(blocks), dim3(kT), 0,
-             st, a);
-    else
-      launch(STS_K_MG_DOWN, 24.0 * nf * nlaunch, mg3_pre_kernel<false>, dim3(blocks), dim3(kT), 0,
-             st, a);
-    STS_HIP(hipGetLastError());
-    a.ntx = (a.nc + CX - 1) / CX;
-    a.nty = (a.nc + CY - 1) / CY;
-    a.ntz = (a.nc + CZ - 1) / CZ;
-    blocks = a.ntx * a.nty * a.ntz * nlaunch;
-    launch(STS_K_MG_RESTRICT, 8.0 * (nf + nc) * nlaunch, mg3_restrict_kernel, dim3(blocks),
-           dim3(kT), 0, st, a);
-    STS_HIP(hipGetLastError());
+    if (!f32) level_down<double, double>(level(l), shifted, nlaunch, st);
+    else if (l == 0) level_down<double, float>(level(l), shifted, nlaunch, st);
+    else level_down<float, float>(level(l), shifted, nlaunch, st);
   }
   {
-    const int m = p.exact;
     Coarse3Args c{};
-    c.m = m;
+    c.m = p.exact;
     c.ld = w.ld[L];
     c.dst = w.dst;
     c.c = level_coef(p, L);
@@ -792,40 +858,16 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     for (int j = 0; j < nlaunch; ++j) c.cols[j] = cols[j];
     c.st = act;
     c.max_tiles = w.max_tiles;
-    const double by = 16.0 * std::pow((double)m, 3) * nlaunch;
-    const dim3 grid(m, nlaunch);
-    c.in = w.b[L];
-    c.out = w.t1;
-    launch(STS_K_MG_COARSE, by, coarse3_plane_kernel, grid, dim3(kCT), 0, st, c);
-    STS_HIP(hipGetLastError());
-    launch(STS_K_MG_COARSE, by, coarse3_z_kernel, grid, dim3(kCT), 0, st, c);
-    STS_HIP(hipGetLastError());
-    c.in = w.t1;
-    c.out = w.e[L];
-    c.rhs = w.b[L];
-    c.part = (partials && L == 0) ? w.part_rz : nullptr;
-    launch(STS_K_MG_COARSE, by, coarse3_plane_kernel, grid, dim3(kCT), 0, st, c);
-    STS_HIP(hipGetLastError());
+    void* part = (partials && L == 0) ? w.part_rz : nullptr;
+    if (f32) coarse_solve<float>(c, w.b[L], w.e[L], w.t1, part, nlaunch, st);
+    else coarse_solve<double>(c, w.b[L], w.e[L], w.t1, part, nlaunch, st);
   }
   for (int l = L - 1; l >= 0; --l) {
     Level3Args a = level(l);
-    const double nf = std::pow((double)a.nf, 3), nc = std::pow((double)a.nc, 3);
-    const int blocks = fine_tiles(a);
-    if (shifted)
-      launch(STS_K_MG_UP, 8.0 * (4.0 * nf + nc) * nlaunch, mg3_post1_kernel<true>, dim3(blocks),
-             dim3(kT), 0, st, a);
-    else
-      launch(STS_K_MG_UP, 8.0 * (4.0 * nf + nc) * nlaunch, mg3_post1_kernel<false>, dim3(blocks),
-             dim3(kT), 0, st, a);
-    STS_HIP(hipGetLastError());
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
-    if (shifted)
-      launch(STS_K_MG_UP, 32.0 * nf * nlaunch, mg3_post2_kernel<true>, dim3(blocks), dim3(kT), 0,
-             st, a);
-    else
-      launch(STS_K_MG_UP, 32.0 * nf * nlaunch, mg3_post2_kernel<false>, dim3(blocks), dim3(kT), 0,
-             st, a);
-    STS_HIP(hipGetLastError());
+    if (!f32) level_up<double, double>(a, shifted, nlaunch, st);
+    else if (l == 0) level_up<double, float>(a, shifted, nlaunch, st);
+    else level_up<float, float>(a, shifted, nlaunch, st);
   }
 }
 

@@ -184,6 +184,8 @@ struct MGPlan {
                              // 3-D: Kx = mu (6; -1 x 6) on level 0, 2^l mu on level l
   double sw0;                // Kx + s Mx: s times the level-0 mass scale (2-D h^2 / 12,
                              // 3-D (h/6)^3); 0: Kx alone
+  int f32;                   // 3-D with nlev >= 1: the V-cycle stores its vectors in FP32
+                             // (all but the finest right-hand side and result)
 };
 // The m x m sine-transform matrix (row-major) followed by the m eigenvalues
 // 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.

@@ -123,6 +123,30 @@ def test_multigrid_entry_points_reject_unsupported_grids():
     assert "bad buffers" in lib.sts_last_error().decode()
 
 
+def test_mixed_precision_entry_points_reject_unsupported_spaces():
+    """The FP32-storage V-cycle needs a 3-D seven-point grid with a smoothed
+    level; the checks run before any device work."""
+    lib = b.load()
+    for dim, n in ((2, 127), (2, 511), (3, 63), (3, 17), (3, 100), (1, 127)):
+        s = sts.make_space(dim, n)
+        nh = n ** dim
+        assert lib.sts_mg_vcycle_mixed(C.byref(s), 0.0, None, nh, None, nh, 1,
+                                       None) == b.STS_E_INVALID
+        assert lib.sts_pcg_mg_mixed(C.byref(s), 0.0, None, nh, None, nh, 1, 1e-12, 10, None,
+                                    None) == b.STS_E_INVALID
+    s = sts.make_space(3, 127)
+    nh = 127 ** 3
+    assert lib.sts_mg_vcycle_mixed(C.byref(s), -1.0, None, nh, None, nh, 1,
+                                   None) == b.STS_E_INVALID
+    assert "shift" in lib.sts_last_error().decode()
+    assert lib.sts_pcg_mg_mixed(C.byref(s), 0.0, None, nh, None, nh, 1, 1e-12, 10, None,
+                                None) == b.STS_E_INVALID
+    assert "bad buffers" in lib.sts_last_error().decode()
+    assert lib.sts_mg_vcycle_mixed(C.byref(s), 0.0, None, nh, None, nh, 9,
+                                   None) == b.STS_E_INVALID
+    assert b.default_opts().precond_fp32 == 0
+
+
 def test_package_has_no_cpu_fallback():
     """The product package never imports the oracle and has no CPU solver."""
     pkg = os.path.join(ROOT, "paper_1912_10082_amd")
