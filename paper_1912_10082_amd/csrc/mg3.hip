@@ -33,6 +33,13 @@
 // diagonal, and the coarsest solve stays exact because tridiag(1, 4, 1) is
 // diagonalised by the same sine transform.
 //
+// Mixed precision (MGPlan::f32): the same launches store every vector of the
+// V-cycle in FP32 except the finest right-hand side (the CG residual) and the
+// result (the preconditioned residual), which stay FP64; loads widen to FP64
+// and all arithmetic is FP64.  The rounding perturbs the preconditioner only,
+// so the FP64 CG around it reaches the same tolerances, and the finest level
+// moves 64 instead of 96 bytes per node and column.
+//
 // Launches per smoothed level: "pre" (both pre-smoothing steps from zero,
 // which need b on a one-node halo only, on the tile and its halo, then the
 // residual; the iterate and the residual are stored), "restrict" (P^T of the
