@@ -82,10 +82,11 @@ __device__ __forceinline__ Tile3 tile_of(int t, int ntx, int nty, int sx, int sy
 // X * Y: c (6 u - sum of the six neighbours), plus with SH the shifted mass
 // term sm (1, 4, 1) x (1, 4, 1) x (1, 4, 1) (s Mx, Mx the Q1 mass with
 // sm = s (h/6)^3 of the level; the coarse levels rediscretise it).
-template <bool SH, int X, int Y>
-__device__ __forceinline__ double k7(const double* s, int q, double c, double sm) {
-  double v = c * (6.0 * s[q] - (s[q - 1] + s[q + 1]) - (s[q - X] + s[q + X]) -
-                  (s[q - X * Y] + s[q + X * Y]));
+template <bool SH, int X, int Y, class T>
+__device__ __forceinline__ double k7(const T* s, int q, double c, double sm) {
+  auto at = [&](int o) { return (double)s[o]; };
+  double v = c * (6.0 * at(q) - (at(q - 1) + at(q + 1)) - (at(q - X) + at(q + X)) -
+                  (at(q - X * Y) + at(q + X * Y)));
   if (SH) {
     double m = 0.0;
 #pragma unroll
@@ -94,7 +95,7 @@ __device__ __forceinline__ double k7(const double* s, int q, double c, double sm
       for (int dy = -1; dy <= 1; ++dy) {
         const int o = q + dz * X * Y + dy * X;
         const double w = (dz == 0 ? 4.0 : 1.0) * (dy == 0 ? 4.0 : 1.0);
-        m += w * ((s[o - 1] + s[o + 1]) + 4.0 * s[o]);
+        m += w * ((at(o - 1) + at(o + 1)) + 4.0 * at(o));
       }
     }
     v += sm * m;
@@ -111,11 +112,11 @@ __device__ __forceinline__ double k7_diag(double c, double sm) {
 // The tile of g (n^3 nodes, x fastest) with a one-node halo into s; zero
 // outside the domain (the Dirichlet values).
 template <class S>
-__device__ __forceinline__ void load_halo(const S* g, int n, const Tile3& T, double* s) {
+__device__ __forceinline__ void load_halo(const S* g, int n, const Tile3& T, S* s) {
   for (int i = threadIdx.x; i < NR; i += kT) {
     const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
     const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
-    s[i] = in ? (double)g[((size_t)gz * n + gy) * n + gx] : 0.0;
+    s[i] = in ? g[((size_t)gz * n + gy) * n + gx] : (S)0;
   }
 }
 
@@ -165,14 +166,16 @@ struct Level3Args {
 // on the tile and a one-node halo (from b on a two-node halo), then the
 // residual r = b - K u_2 on the tile.  Stores u_2 (for post1) and r.  One LDS
 // array holds b first and u_2 after it (the values pass through registers),
-// which keeps five work-groups per compute unit.
+// which keeps five work-groups per compute unit.  LDS arrays hold the storage
+// type S (b rounded to it in the mixed-precision V-cycle); every value is
+// widened to FP64 before it is used.
 template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
   constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
   constexpr int NC = TX * TY * TZ / kT;                  // tile nodes per thread
   static_assert(NR <= BX * BY * BZ, "u_2 fits where b was");
-  __shared__ double sh[BX * BY * BZ];
+  __shared__ S sh[BX * BY * BZ];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf;
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   for (int i = threadIdx.x; i < BX * BY * BZ; i += kT) {
     const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
     const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
-    sh[i] = in ? (double)bf[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+    sh[i] = in ? (S)bf[((size_t)gz * nf + gy) * nf + gx] : (S)0;
   }
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
     const int i = threadIdx.x + k * kT;
-    if (i < NR) sh[i] = u2r[k];
+    if (i < NR) sh[i] = (S)u2r[k];
   }
   __syncthreads();
   S* xp = static_cast<S*>(a.xp) + (size_t)col * a.ldf;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
 template <class S>
 __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
   constexpr int SX = 2 * CX + 1, SY = 2 * CY + 1, SZ = 2 * CZ + 1;
-  __shared__ double rs[SX * SY * SZ];
+  __shared__ S rs[SX * SY * SZ];
   STS_MG3_PROLOGUE(a)
   const Tile3 C = tile_of(t, a.ntx, a.nty, CX, CY, CZ);
   const int nf = a.nf, nc = a.nc;
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
     const int gx = fx0 + i % SX, gy = fy0 + (i / SX) % SY, gz = fz0 + i / (SX * SY);
     // fine nodes beyond the domain are never gathered (every coarse node's
     // neighbours lie inside); read them as zero
-    rs[i] = (gx < nf && gy < nf && gz < nf) ? (double)r[((size_t)gz * nf + gy) * nf + gx] : 0.0;
+    rs[i] = (gx < nf && gy < nf && gz < nf) ? r[((size_t)gz * nf + gy) * nf + gx] : (S)0;
   }
   __syncthreads();
   S* bc = static_cast<S*>(a.bc) + (size_t)col * a.ldc;
@@ -260,9 +263,9 @@ __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
 #pragma unroll
       for (int e = 1; e < 8; ++e) {
         const int o = (e & 1) + ((e >> 1) & 1) * SX + ((e >> 2) & 1) * SX * SY;
-        s += rs[q + o] + rs[q - o];
+        s += (double)rs[q + o] + (double)rs[q - o];
       }
-      bc[((size_t)K * nc + J) * nc + I] = (S)(rs[q] + 0.5 * s);
+      bc[((size_t)K * nc + J) * nc + I] = (S)((double)rs[q] + 0.5 * s);
     }
   }
 }
@@ -272,14 +275,14 @@ __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
 // index 2I+1 coincides with coarse I and an even fine index 2I+2 lies between
 // coarse I and I+1; a node even along the axes in a set E is the midpoint of
 // the coarse edge from (I, J, K) in direction E.
-template <int EX, int EY>
-__device__ __forceinline__ double interp3(const double* es, int ox, int oy, int oz, int gx, int gy,
+template <int EX, int EY, class S>
+__device__ __forceinline__ double interp3(const S* es, int ox, int oy, int oz, int gx, int gy,
                                           int gz) {
   const int ex = (gx & 1) ^ 1, ey = (gy & 1) ^ 1, ez = (gz & 1) ^ 1;
   const int I = (gx - 1 - ex) >> 1, J = (gy - 1 - ey) >> 1, K = (gz - 1 - ez) >> 1;
-  const double* c = es + ((K - oz) * EY + (J - oy)) * EX + (I - ox);
-  if ((ex | ey | ez) == 0) return c[0];
-  return 0.5 * (c[0] + c[ex + ey * EX + ez * EX * EY]);
+  const S* c = es + ((K - oz) * EY + (J - oy)) * EX + (I - ox);
+  if ((ex | ey | ez) == 0) return (double)c[0];
+  return 0.5 * ((double)c[0] + (double)c[ex + ey * EX + ez * EX * EY]);
 }
 
 // post1: u = u_2 + P e_c on the tile and its halo; d_0 = c_0 (b - K u) / D,
@@ -287,8 +290,8 @@ __device__ __forceinline__ double interp3(const double* es, int ox, int oy, int 
 template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   constexpr int EX = TX / 2 + 2, EY = TY / 2 + 2, EZ = TZ / 2 + 2;
-  __shared__ double us[NR];
-  __shared__ double es[EX * EY * EZ];
+  __shared__ S us[NR];
+  __shared__ S es[EX * EY * EZ];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf, nc = a.nc;
@@ -298,13 +301,13 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   for (int i = threadIdx.x; i < EX * EY * EZ; i += kT) {
     const int I = ox + i % EX, J = oy + (i / EX) % EY, K = oz + i / (EX * EY);
     const bool in = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
-    es[i] = in ? (double)ec[((size_t)K * nc + J) * nc + I] : 0.0;
+    es[i] = in ? ec[((size_t)K * nc + J) * nc + I] : (S)0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NR; i += kT) {
     const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
     if (gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf)
-      us[i] += interp3<EX, EY>(es, ox, oy, oz, gx, gy, gz);
+      us[i] = (S)((double)us[i] + interp3<EX, EY>(es, ox, oy, oz, gx, gy, gz));
   }
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
@@ -314,14 +317,14 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   for_core(nf, T, [&](size_t g, int q) {
     const double d = a.c0 * inv_d * ((double)bf[g] - k7<SH, RX, RY>(us, q, a.c, a.sm));
     d0[g] = (S)d;
-    u1[g] = (S)(us[q] + d);
+    u1[g] = (S)((double)us[q] + d);
   });
 }
 
 // post2: d_1 = a_1 d_0 + c_1 (b - K u_1) / D, e = u_1 + d_1; per-tile (b, e).
 template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
-  __shared__ double us[NR];
+  __shared__ S us[NR];
   __shared__ double red[kT / 64];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
   for_core(nf, T, [&](size_t g, int q) {
     const double b = bf[g];
     const double e =
-        us[q] + (a.a1 * (double)d0[g] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
+        (double)us[q] + (a.a1 * (double)d0[g] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
     ef[g] = (B)e;
     part += b * (double)(B)e;   // (b, e) of the stored result
   });
