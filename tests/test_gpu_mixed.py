@@ -146,3 +146,36 @@ def test_mixed_option_is_ignored_where_it_does_not_apply():
         assert a["status"] == b["status"] == "STS_OK"
         assert a["outer_its"] == b["outer_its"] and a["inner_its_K"] == b["inner_its_K"]
         assert np.array_equal(Va @ Ya, Vb @ Yb)
+
+
+def test_mixed_entry_points_with_padded_leading_dimensions():
+    """Eight columns (the maximum) in buffers with ld > Nh, through the C ABI:
+    the same V-cycle and the same solve as from packed buffers, bit for bit;
+    the padding rows of Z and X are left untouched."""
+    import ctypes as C
+    from paper_1912_10082_amd import binding as b
+    n, ncols, pad = 65, 8, 7
+    nh, ld = n ** 3, n ** 3 + pad
+    space = sts.make_space(3, n, 0.7)
+    R = np.random.default_rng(1400).normal(size=(nh, ncols))
+    Rp = torch.full((ncols, ld), 3.0, dtype=torch.float64, device="cuda")
+    Rp[:, :nh] = torch.from_numpy(R.T.copy()).cuda()
+    lib = b.load()
+    st = b._stream_handle()
+    for shift in (0.0, 25.0):
+        Zp = torch.full((ncols, ld), -5.0, dtype=torch.float64, device="cuda")
+        assert lib.sts_mg_vcycle_mixed(C.byref(space), shift, C.c_void_p(Rp.data_ptr()), ld,
+                                       C.c_void_p(Zp.data_ptr()), ld, ncols, st) == 0
+        Z = host(sts.mg_vcycle(space, dev(R), shift=shift, fp32=True))
+        Zh = host(Zp)
+        assert np.array_equal(Zh[:, :nh].T, Z)
+        assert np.all(Zh[:, nh:] == -5.0)
+        Xp = torch.full((ncols, ld), -5.0, dtype=torch.float64, device="cuda")
+        its = (C.c_int32 * ncols)()
+        assert lib.sts_pcg_mg_mixed(C.byref(space), shift, C.c_void_p(Rp.data_ptr()), ld,
+                                    C.c_void_p(Xp.data_ptr()), ld, ncols, 1e-12, 100, its,
+                                    st) == 0
+        X, its2, _ = sts.pcg_mg_mixed(space, dev(R), shift=shift, rtol=1e-12)
+        Xh = host(Xp)
+        assert np.array_equal(Xh[:, :nh].T, host(X)) and list(its) == its2
+        assert np.all(Xh[:, nh:] == -5.0)
