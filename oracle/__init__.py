@@ -13,7 +13,9 @@ Contents (each function cites the passage it follows):
                   stiffness and mass matrices by element assembly.
 * ``exact``       the exact discrete space-time solution: Kronecker system
                   (Sec. 3 and Sec. 4, eq. (Kroneckersum)), Crank-Nicolson
-                  stepping (Sec. 3, equivalence remark), 1-D modal solve,
+                  stepping (Sec. 3, equivalence remark), also in resumable
+                  chunks, 1-D modal solves (mode loop; DST-based for large
+                  grids), 3-D modal solve,
                   Sylvester residual (Sec. 4, eq. (Sylv_Heat)).
 * ``projection``  the Galerkin projection method of Sec. 4 with an extended
                   Krylov space, exact inner solves and a dense reduced solve.

@@ -56,6 +56,47 @@ def test_modal_solve_matches_kron_on_random_rhs():
     assert exact.relative_error(exact.crank_nicolson(K, M, Dt, Mt, F1, F2), Uk) < 1e-12
 
 
+@pytest.mark.parametrize("n", [1, 2, 23, 100])
+def test_modal_solve_1d_fast_matches_kron_and_mode_loop(n):
+    """The DST-based 1-D modal solve against the assembled Kronecker system
+    (graded time grid, random data) and against the explicit mode loop."""
+    rng = np.random.default_rng(40 + n)
+    nt = 13
+    K, M = fem.p1_1d(n, 0.45)
+    t = np.cumsum(np.r_[0.0, rng.uniform(0.02, 0.1, nt)])
+    Dt, Mt = fem.time_matrices(t)
+    F1, F2 = rng.normal(size=(n, 2)), rng.normal(size=(nt, 2))
+    Uf = exact.modal_solve_1d_fast(n, 0.45, Dt, Mt, F1, F2)
+    assert exact.relative_error(Uf, exact.kron_solve(K, M, Dt, Mt, F1, F2)) < 1e-12
+    assert exact.relative_error(Uf, exact.modal_solve_1d(n, 0.45, Dt, Mt, F1, F2)) < 1e-12
+
+
+def test_modal_solve_1d_fast_sylvester_residual_at_large_n():
+    """At n = 4095 (Kronecker too large) the fast modal solution satisfies
+    eq. (Sylv_Heat) to its FP64 rounding level, and Crank-Nicolson agrees."""
+    w = wl.heat_1d_profiles(n=4095, nt=64, p=2, seed=7)
+    K, M, Dt, Mt = _setup(w)
+    Uf = exact.modal_solve_1d_fast(4095, w.mu, Dt, Mt, w.F1, w.F2)
+    assert exact.sylvester_residual(K, M, Dt, Mt, w.F1, w.F2, Uf) < 1e-8
+    assert exact.relative_error(exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2), Uf) < 1e-9
+
+
+def test_crank_nicolson_chunks_equal_one_march():
+    """The chunked march carries u^{l0} exactly: its pieces concatenate to the
+    single march bitwise, also for a graded grid and a chunk that leaves a
+    ragged tail."""
+    rng = np.random.default_rng(3)
+    n, nt = 15, 23
+    K, M = fem.spatial_operators(2, n, 0.8)
+    t = np.cumsum(np.r_[0.0, rng.uniform(0.02, 0.1, nt)])
+    Dt, Mt = fem.time_matrices(t)
+    F1, F2 = rng.normal(size=(n * n, 2)), rng.normal(size=(nt, 2))
+    U = exact.crank_nicolson(K, M, Dt, Mt, F1, F2)
+    parts = list(exact.crank_nicolson_chunks(K, M, Dt, Mt, F1, F2, chunk=5))
+    assert [l0 for l0, _ in parts] == [0, 5, 10, 15, 20]
+    assert np.array_equal(np.hstack([P for _, P in parts]), U)
+
+
 @pytest.mark.parametrize("n", [1, 4, 7])
 def test_modal_solve_3d_matches_kron_on_random_rhs(n):
     rng = np.random.default_rng(12 + n)
