@@ -154,6 +154,10 @@ typedef struct {
   int32_t breakdown;        /* 1 = the space became invariant (exact solution) */
   int32_t shifts;           /* shifted solves of a rational Krylov space (0 otherwise) */
   int64_t cg_poll_restarts; /* times a polled CG state was stale and iterations resumed */
+  double res_floor;         /* estimated rounding floor of the exact residual in FP64 (see
+                               sts_solve), or -1 where it was not needed */
+  int32_t floor_limited;    /* 1 = accepted with res_true above tol but within res_floor of it */
+  int32_t pad_;
 } sts_info;
 
 /* Kernels timed by sts_kernel_profile. */
@@ -178,7 +182,8 @@ typedef enum {
   STS_K_MG_RESTRICT = 17,   /* multigrid (3-D): residual and restriction */
   STS_K_PCG_REDUCE = 18,    /* preconditioned CG (3-D): sums of per-tile partials */
   STS_K_RESIDUAL_QR = 19,   /* Householder QR of the residual's time factor */
-  STS_K_COUNT = 20
+  STS_K_GRAM_REDUCE = 20,   /* sum of the Gram contraction's per-chunk partial products */
+  STS_K_COUNT = 21
 } sts_kernel;
 
 typedef struct sts_problem sts_problem;
@@ -192,29 +197,65 @@ void sts_default_opts(sts_opts* o);
 sts_status sts_time_matrices(int64_t nt, const double* t, double* dt_diag, double* dt_sub,
                              double* mt_diag, double* mt_sub);
 
-/* Create a problem.  Copies F1 (Nh x p, ld ldf1) and F2 (nt x p, ld ldf2) from
- * `mem` into library memory; the caller keeps its arrays.  Dt, Mt are host
- * bidiagonals.  Errors: STS_E_INVALID for nt < 2, p < 1 or p > 4, ld < rows,
- * non-positive diagonals of Dt or Mt, non-finite data or an unsupported space;
- * STS_E_NOMEM / STS_E_DEVICE on allocation or copy failure.  Synchronous. */
+/* Create a problem: the generalized Sylvester equation of Sec. 4, eq.
+ * (Sylv_Heat), Kx U Mt^T + Mx U Dt^T = F1 F2^T, for the space-time
+ * discretisation of Sec. 3 (eq. (par1)-(par2)) with a low-rank load F1 F2^T
+ * (Sec. 3, eq. (EIM)).  The spatial matrices are not passed: Kx and Mx are the
+ * matrix-free stencils of the built-in space kinds (sts_fe_kind), so a caller
+ * cannot supply its own sparse matrices.  Dt, Mt are host lower bidiagonals
+ * (any strictly positive diagonals: uniform or graded time steps).  Copies F1
+ * (Nh x p, ld ldf1) and F2 (nt x p, ld ldf2) from `mem` into library memory;
+ * the caller keeps its arrays.  Errors: STS_E_INVALID for nt < 2, p < 1 or
+ * p > 4, ld < rows, non-positive diagonals of Dt or Mt, non-finite data or an
+ * unsupported space; STS_E_NOMEM / STS_E_DEVICE on allocation or copy
+ * failure.  Synchronous. */
 sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bidiag* Mt,
                       int64_t nt, int32_t p, const double* F1, int64_t ldf1,
                       const double* F2, int64_t ldf2, int32_t mem, void* stream,
                       sts_problem** out);
 
-/* Solve to opts->tol (NULL = defaults).  Fills *info if non-NULL.  May be
- * called again on the same problem with a tighter tolerance: the space is
- * extended from where the previous call stopped.  Returns STS_OK,
- * STS_E_NOT_CONVERGED (factors of the last iterate are kept), STS_E_NUMERIC
- * or STS_E_NOMEM.  Synchronous. */
+/* Solve to opts->tol (NULL = defaults) by the Galerkin projection of Sec. 4:
+ * grow the spatial space block by block, solve the reduced equation
+ * (V^T Kx V) Y Mt^T + (V^T Mx V) Y Dt^T = (V^T F1) F2^T, and stop on the
+ * relative residual R_m of Sec. 4 (Sec. 5 uses 1e-8).  Fills *info if
+ * non-NULL.  May be called again on the same problem with a tighter tolerance:
+ * the space is extended from where the previous call stopped.
+ *
+ * Device memory: V, Mx V and Kx V (Nh x k each) grow in place as the space
+ * grows, 16p columns at a time, inside an address range reserved for
+ * max_outer + 2 more blocks (HIP virtual memory; reallocation and copy on
+ * devices without it), so the problem holds what the basis uses, not what
+ * max_outer allows.  opts->mem_budget bounds the total.
+ *
+ * Convergence is decided by the projected residual and confirmed by the
+ * exact one (opts->verify_true).  The exact residual is evaluated from the
+ * solution stored in FP64, which rounds U's entries; that alone moves the
+ * residual by about u kappa(Mx^{-1} Kx) relative to F (u = 2^-53; about 1e-7
+ * for the 1-D problem with 65535 nodes, where no FP64 representation of the
+ * exact solution has a smaller residual).  When the projected residual meets
+ * tol but the exact one does not, the library estimates that floor
+ * (info->res_floor); if it is at least tol / 2 and the exact residual lies
+ * within tol + floor, the solve is accepted (info->floor_limited = 1).
+ *
+ * Returns STS_OK; STS_E_NOT_CONVERGED when max_outer blocks did not reach tol
+ * (the factors of the last iterate are kept and fetchable); STS_E_NUMERIC on a
+ * breakdown -- a non-positive curvature or non-finite value in an inner solve,
+ * a non-finite reduced matrix, or a block whose every column deflated while
+ * the exact residual is still above tol (the factors are kept); STS_E_NOMEM.
+ * A block that deflates entirely with the exact residual at tol is the
+ * invariant-space case: STS_OK with info->breakdown = 1.  Synchronous. */
 sts_status sts_solve(sts_problem* prob, const sts_opts* opts, sts_info* info);
 
-/* Number of columns of V (rows of Y) of the current solution. */
+/* Number of columns of V (rows of Y) of the current solution U ~= V Y:
+ * the basis size mu_mem that Sec. 5, Table 1 reports. */
 sts_status sts_rank(const sts_problem* prob, int64_t* k);
 
-/* Copy the factors into caller buffers: V (Nh x k, ld ldv >= Nh) and
- * Y (k x nt, ld ldy >= k), either may be NULL.  STS_E_STATE before a
- * successful or not-converged solve.  Synchronous. */
+/* Copy the factors of the low-rank solution U ~= V Y of Sec. 4 (V the
+ * Mx-orthonormal spatial basis, Y the reduced solution) into caller buffers:
+ * V (Nh x k, ld ldv >= Nh) and Y (k x nt, ld ldy >= k), either may be NULL;
+ * `mem` says whether the buffers are host or device memory.  The library
+ * keeps its copies.  STS_E_STATE before a successful or not-converged solve.
+ * Synchronous. */
 sts_status sts_get_factors(const sts_problem* prob, double* V, int64_t ldv, double* Y,
                            int64_t ldy, int32_t mem, void* stream);
 
@@ -390,12 +431,20 @@ sts_status sts_m_orthonormalize(const sts_space* space, const double* V, const d
                                 int32_t* keep_idx, void* stream);
 
 /* The contraction of block Gram-Schmidt, C (m x n, ldc) = A^T B, for a tall
- * A (rows x m, lda) and a thin B (rows x n, ldb), n <= 16; FP64 matrix cores. */
+ * A (rows x m, lda) and a thin B (rows x n, ldb), n <= 16; FP64 matrix cores.
+ * With A = Mx V it gives the coefficients that orthogonalise a new block
+ * against the basis, whose columns Sec. 4 takes orthonormal.  All pointers
+ * device; rows >= 0, m >= 1, 1 <= n <= 16, ldc >= m; A and B must not overlap
+ * C; scratch is allocated and freed inside the call.  Errors: STS_E_INVALID
+ * for sizes out of range or ld < rows. */
 sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 
 /* The basis update of block Gram-Schmidt, W (rows x n, ldw) -= A (rows x m,
- * lda) C (m x n, ldc), n <= 16; FP64 matrix cores. */
+ * lda) C (m x n, ldc), n <= 16; FP64 matrix cores.  With A = V and C from
+ * sts_gram it removes the new block's components along the orthonormal basis
+ * of Sec. 4.  All pointers device; W must not overlap A or C.  Errors:
+ * STS_E_INVALID for n > 16 or ld < rows. */
 sts_status sts_basis_update(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
                             const double* C, int64_t ldc, double* W, int64_t ldw, void* stream);
 
@@ -500,10 +549,11 @@ typedef struct {
   int64_t mem_in_use, mem_peak, mem_budget;   /* bytes of footprint */
 } sts_server_stats;
 
-/* Device bytes a problem of this shape holds after sts_create and a solve
- * with these options (NULL = defaults): an upper estimate dominated by the
- * basis capacity 3 Nh 2p (max_outer + 2) doubles that sts_solve reserves.
- * -1 for an invalid shape. */
+/* Device bytes a problem of this shape holds after sts_create and the first
+ * basis capacity a solve with these options (NULL = defaults) maps: inputs,
+ * inner-solve work and 3 Nh doubles for each of min(8, max_outer + 2) blocks
+ * of 2p columns.  The basis then grows in place by 3 Nh doubles per column as
+ * the space grows (sts_solve).  -1 for an invalid shape. */
 int64_t sts_footprint(const sts_space* space, int64_t nt, int32_t p, const sts_opts* opts);
 
 /* workers: 1..64; mem_budget > 0 bytes.  Errors: STS_E_INVALID, STS_E_DEVICE. */

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "STS_OK", 1: "STS_E_INVALID", 2: "STS_E_NOMEM", 3: "STS_E_DEV
 STS_MEM_HOST, STS_MEM_DEVICE = 0, 1
 STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT = 1, 2, 3
 STS_OP_K, STS_OP_M = 0, 1
-STS_K_COUNT = 20
+STS_K_COUNT = 21
 
 
 class STSError(RuntimeError):
@@ -54,7 +54,8 @@ class Info(C.Structure):
                 ("rank", C.c_int64), ("inner_its_K", C.c_int64), ("inner_its_M", C.c_int64),
                 ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
                 ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
-                ("shifts", C.c_int32), ("cg_poll_restarts", C.c_int64)]
+                ("shifts", C.c_int32), ("cg_poll_restarts", C.c_int64),
+                ("res_floor", C.c_double), ("floor_limited", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}

@@ -620,9 +620,10 @@ void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
       launch_tn<1, 16>(vec, p, rows, m, n, A, lda, B1, B2, n1, ldb, partial, m16, st);
   }
   STS_HIP(hipGetLastError());
-  gemm_tn_reduce<<<(m * n + 3) / 4, 256, 0, st>>>(m, n, rows <= 0 ? 1 : p.nch, m16, partial, C1,
-                                                  C2, n1, ldc);
-  STS_HIP(hipGetLastError());
+  const int64_t nch = rows <= 0 ? 1 : p.nch;
+  launch(STS_K_GRAM_REDUCE, 8.0 * ((double)nch * m16 * 16 + (double)m * n), gemm_tn_reduce,
+         dim3((m * n + 3) / 4), dim3(256), 0, st, m, n, nch, m16, (const double*)partial, C1, C2,
+         n1, ldc);
 }
 
 void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const double* B,

@@ -199,7 +199,175 @@ struct DevBuf {
   double* d() const { return static_cast<double*>(p); }
 };
 
+// A device array that grows in place.  A virtual address range is reserved
+// once for the largest size the caller may ask for, and physical memory is
+// mapped behind it in chunks as the array grows (HIP virtual memory
+// management): contents never move, nothing is copied, and the device holds
+// only the mapped chunks.  Where the device lacks virtual memory support the
+// array is reallocated and its contents copied instead.
+struct GrowBuf {
+  char* base = nullptr;
+  size_t reserved = 0;   // bytes of address range (vmm) or of the allocation (fallback)
+  size_t mapped = 0;     // bytes backed by memory
+  bool vmm = false;
+  std::vector<std::pair<hipMemGenericAllocationHandle_t, size_t>> chunks;
+
+  GrowBuf() = default;
+  GrowBuf(const GrowBuf&) = delete;
+  GrowBuf& operator=(const GrowBuf&) = delete;
+  ~GrowBuf() { release(); }
+
+  static bool vmm_supported(int dev) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeVirtualMemoryManagementSupported, dev) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return v != 0;
+  }
+  static hipMemAllocationProp prop_for(int dev) {
+    hipMemAllocationProp pr = {};
+    pr.type = hipMemAllocationTypePinned;
+    pr.location.type = hipMemLocationTypeDevice;
+    pr.location.id = dev;
+    return pr;
+  }
+  void release() {
+    if (vmm && base) {
+      size_t off = 0;
+      for (auto& c : chunks) {
+        (void)hipMemUnmap(base + off, c.second);
+        (void)hipMemRelease(c.first);
+        off += c.second;
+      }
+      (void)hipMemAddressFree(base, reserved);
+    } else if (base) {
+      (void)hipFree(base);
+    }
+    chunks.clear();
+    base = nullptr;
+    reserved = mapped = 0;
+    vmm = false;
+  }
+  double* d() const { return reinterpret_cast<double*>(base); }
+
+  // Make `need` bytes usable, of at most `limit` bytes ever asked for from
+  // this reservation; the first `keep` bytes keep their contents.  Grows
+  // past `limit` by a new reservation and one copy.
+  void ensure(size_t need, size_t limit, size_t keep, hipStream_t st) {
+    if (need <= mapped) return;
+    int dev = 0;
+    STS_HIP(hipGetDevice(&dev));
+    if (need > reserved && base) {
+      // outgrew the reservation: move into a larger one
+      GrowBuf nb;
+      nb.ensure(need, std::max(limit, need), 0, st);
+      if (keep) STS_HIP(hipMemcpyAsync(nb.base, base, keep, hipMemcpyDeviceToDevice, st));
+      STS_HIP(hipStreamSynchronize(st));
+      std::swap(base, nb.base);
+      std::swap(reserved, nb.reserved);
+      std::swap(mapped, nb.mapped);
+      std::swap(vmm, nb.vmm);
+      std::swap(chunks, nb.chunks);
+      return;
+    }
+    if (!base) {
+      vmm = vmm_supported(dev);
+      if (vmm) {
+        const hipMemAllocationProp pr = prop_for(dev);
+        size_t gran = 0;
+        if (hipMemGetAllocationGranularity(&gran, &pr, hipMemAllocationGranularityRecommended) !=
+                hipSuccess || gran == 0) {
+          (void)hipGetLastError();
+          vmm = false;
+        } else {
+          const size_t want = ((std::max(limit, need) + gran - 1) / gran) * gran;
+          void* va = nullptr;
+          if (hipMemAddressReserve(&va, want, 0, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            vmm = false;
+          } else {
+            base = static_cast<char*>(va);
+            reserved = want;
+          }
+        }
+      }
+      if (!vmm) {
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+          (void)hipGetLastError();
+          throw Error{STS_E_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
+        }
+        base = static_cast<char*>(p);
+        reserved = mapped = need;
+        return;
+      }
+    }
+    if (!vmm) {
+      // fallback: reallocate and copy
+      void* p = nullptr;
+      if (hipMalloc(&p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{STS_E_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
+      }
+      if (keep) STS_HIP(hipMemcpyAsync(p, base, keep, hipMemcpyDeviceToDevice, st));
+      STS_HIP(hipStreamSynchronize(st));
+      (void)hipFree(base);
+      base = static_cast<char*>(p);
+      reserved = mapped = need;
+      return;
+    }
+    const hipMemAllocationProp pr = prop_for(dev);
+    size_t gran = 0;
+    STS_HIP(hipMemGetAllocationGranularity(&gran, &pr, hipMemAllocationGranularityRecommended));
+    const size_t add = ((need - mapped + gran - 1) / gran) * gran;
+    STS_REQUIRE(mapped + add <= reserved, STS_E_DEVICE, "growable buffer: mapping beyond its reservation");
+    hipMemGenericAllocationHandle_t h{};
+    if (hipMemCreate(&h, add, &pr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{STS_E_NOMEM, "could not map " + std::to_string(add) + " more bytes of device memory"};
+    }
+    if (hipMemMap(base + mapped, add, 0, h, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipMemRelease(h);
+      throw Error{STS_E_DEVICE, "hipMemMap failed"};
+    }
+    hipMemAccessDesc acc = {};
+    acc.location.type = hipMemLocationTypeDevice;
+    acc.location.id = dev;
+    acc.flags = hipMemAccessFlagsProtReadWrite;
+    if (hipMemSetAccess(base + mapped, add, &acc, 1) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipMemUnmap(base + mapped, add);
+      (void)hipMemRelease(h);
+      throw Error{STS_E_DEVICE, "hipMemSetAccess failed"};
+    }
+    chunks.emplace_back(h, add);
+    mapped += add;
+  }
+};
+
 static inline int64_t pad_ld(int64_t n) { return ((n + 31) / 32) * 32; }
+
+// Basis columns mapped per growth step, in blocks of 2p columns.
+constexpr int kGrowBlocks = 8;
+
+// Bytes of the k-dependent buffers for a basis capacity of kc columns
+// (leading dimension ld): V, Mx V, Kx V, the reduced matrices and beta, the
+// eigensolver's Q and workspace, Z, Y and the refinement scratch, and the time
+// factor of the exact residual.
+int64_t basis_capacity_bytes(int64_t ld, int64_t nt, int p, int64_t kc) {
+  return 3 * ld * kc * 8 + 2 * kc * kc * 8 + kc * p * 8 + kc * kc * 8 +
+         eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8 + kc * 8 * 3 +
+         3 * kc * nt * 8 + nt * (p + 2 * kc) * 8;
+}
+
+// The first capacity sts_solve maps: kGrowBlocks blocks, or the whole
+// max_outer + 2 blocks if fewer.
+int64_t initial_capacity(int p, int max_outer) {
+  return 2LL * p * std::min<int64_t>(kGrowBlocks, (int64_t)max_outer + 2);
+}
 
 // Scratch of the step-level calls: freed when the call returns.
 struct Scratch {
@@ -533,6 +701,7 @@ struct sts_problem {
   int p = 0;
   hipStream_t stream = nullptr;
   double fnorm = 0.0;
+  double floor_coef = 0.0;   // residual_floor() / ||U||_F / kFloorFactor
 
   std::vector<double> h_td, h_ts, h_md, h_ms;
   DevBuf F1, F2, tdv;   // tdv: d (nt) | e (nt) | m (nt) | n (nt)
@@ -543,7 +712,11 @@ struct sts_problem {
   int64_t k_sol = 0;      // columns of the current Galerkin solution
   int64_t blk_start = 0, blk_size = 0;
   std::vector<int> tags;  // 0: positive power, 1: negative power
-  DevBuf V, MV, KV, Kred, Mred, beta;
+  GrowBuf V, MV, KV;      // basis and its images, grown in place
+  DevBuf Kred, Mred, beta;
+  // called with the extra bytes before the basis grows (the server's
+  // footprint accounting; may block or throw)
+  std::function<void(int64_t)> grow_hook;
   DevBuf qr_work, qr_R;   // exact residual through the QR of the time factor
   int residual_qr = 0;    // sts_opts::residual_qr of the last solve
 
@@ -586,62 +759,58 @@ struct sts_problem {
 
 namespace {
 
-void ensure_capacity(sts_problem* P, int64_t need, int64_t budget) {
+int64_t capacity_bytes(const sts_problem* P, int64_t kc) {
+  return basis_capacity_bytes(P->ldv, P->nt, P->p, kc);
+}
+
+// Make room for `need` basis columns.  V, Mx V and Kx V grow in place
+// (GrowBuf), kGrowBlocks blocks ahead of the need, within an address range
+// reserved for `limit` columns; the reduced matrices, beta and the current
+// solution Y are copied to their new leading dimension; the rest is scratch.
+void ensure_capacity(sts_problem* P, int64_t need, int64_t limit, int64_t budget) {
   if (need <= P->kcap) return;
-  const int64_t kc = need;
+  const int64_t b2 = 2 * P->p;
+  limit = std::max(limit, need);
+  const int64_t kc = std::min(std::max(need, P->kcap + b2 * kGrowBlocks), limit);
   const int64_t ld = P->ldv;
   const int64_t nt = P->nt;
-  const int64_t bytes = 3 * ld * kc * 8 + 2 * kc * kc * 8 + kc * P->p * 8 +   // V MV KV Kred Mred beta
-                        kc * kc * 8 + eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8 +
-                        kc * 8 * 3 + 3 * kc * nt * 8 +                         // Q, eigen work, Z Y RB
-                        nt * (P->p + 2 * kc) * 8;                              // BT
+  const int64_t bytes = capacity_bytes(P, kc);
   STS_REQUIRE(budget <= 0 || bytes <= budget, STS_E_NOMEM,
               "basis of " + std::to_string(kc) + " columns needs " + std::to_string(bytes) +
                   " bytes, above the memory budget");
+  if (P->grow_hook) P->grow_hook(bytes - capacity_bytes(P, P->kcap));
   hipStream_t st = P->stream;
-  auto grow = [&](DevBuf& b, size_t nbytes, size_t keep) {
-    DevBuf nb;
-    nb.alloc(nbytes);
-    if (keep && b.p) STS_HIP(hipMemcpyAsync(nb.p, b.p, keep, hipMemcpyDeviceToDevice, st));
-    STS_HIP(hipStreamSynchronize(st));
-    std::swap(b.p, nb.p);
-    std::swap(b.bytes, nb.bytes);
-  };
   const int64_t old = P->kcap;
-  grow(P->V, ld * kc * 8, ld * old * 8);
-  grow(P->MV, ld * kc * 8, ld * old * 8);
-  grow(P->KV, ld * kc * 8, ld * old * 8);
-  // reduced matrices change leading dimension: copy column by column
-  auto grow_sq = [&](DevBuf& b) {
+  P->V.ensure(ld * kc * 8, ld * limit * 8, ld * P->k * 8, st);
+  P->MV.ensure(ld * kc * 8, ld * limit * 8, ld * P->k * 8, st);
+  P->KV.ensure(ld * kc * 8, ld * limit * 8, ld * P->k * 8, st);
+  // small buffers with leading dimension kc: copy column by column
+  auto regrow = [&](DevBuf& b, int64_t cols, int64_t rows_keep, int64_t cols_keep) {
     DevBuf nb;
-    nb.alloc(kc * kc * 8);
-    fill(nb.d(), kc * kc, 0.0, st);
-    if (old && b.p) copy_cols(old, (int)old, b.d(), old, nb.d(), kc, st);
+    nb.alloc(kc * cols * 8);
+    fill(nb.d(), kc * cols, 0.0, st);
+    if (old && b.p && rows_keep > 0 && cols_keep > 0)
+      copy_cols(rows_keep, (int)cols_keep, b.d(), old, nb.d(), kc, st);
     STS_HIP(hipStreamSynchronize(st));
     std::swap(b.p, nb.p);
     std::swap(b.bytes, nb.bytes);
   };
-  grow_sq(P->Kred);
-  grow_sq(P->Mred);
-  {
-    DevBuf nb;
-    nb.alloc(kc * P->p * 8);
-    if (old && P->beta.p) copy_cols(old, P->p, P->beta.d(), old, nb.d(), kc, st);
-    STS_HIP(hipStreamSynchronize(st));
-    std::swap(P->beta.p, nb.p);
-    std::swap(P->beta.bytes, nb.bytes);
-  }
+  regrow(P->Kred, kc, old, old);
+  regrow(P->Mred, kc, old, old);
+  regrow(P->beta, P->p, old, P->p);
+  regrow(P->Y, nt, P->k_sol, P->k_sol > 0 ? nt : 0);
   P->lam.alloc(kc * 8);
   P->Q.alloc(kc * kc * 8);
   P->eig_work.alloc(eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8);
   P->eig_meta.alloc(64);
   P->qb.alloc(kc * 4 * 8);
   P->Z.alloc(kc * nt * 8);
-  P->Y.alloc(kc * nt * 8);
   P->RB.alloc(kc * nt * 8);
   P->BT.alloc(nt * (P->p + 2 * kc) * 8);
-  P->tn_part.alloc(gemm_tn_partial_size(P->nh, (int)kc) * 8);
+  P->tn_part.alloc(gemm_tn_partial_size(std::max<int64_t>(P->nh, nt), (int)kc) * 8);
   P->kcap = kc;
+  if (!P->smallv.p || P->smallv.bytes < (size_t)std::max<int64_t>(kc * 16, 4096) * 8)
+    P->smallv.alloc(std::max<int64_t>(kc * 16, 4096) * 8);
 }
 
 TimeOps time_ops(const sts_problem* P) {
@@ -744,20 +913,13 @@ double reduced_solve(sts_problem* P, int64_t ks, int64_t b) {
   return std::sqrt(std::max(res2, 0.0)) / P->fnorm;
 }
 
-double true_residual(sts_problem* P) {
+// ||A B^T||_F^2 for A = the column segments `segs` (mtot columns in all) and
+// BT (Nt x mtot, ld Nt; overwritten when the QR path is taken), without
+// forming the Nh x Nt product: directly, or through the Householder QR of BT
+// (||A B^T|| = ||A R^T||) when that saves work.
+double lowrank_norm2(sts_problem* P, const Seg* segs, int nseg, int mtot, double* BT) {
   hipStream_t st = P->stream;
-  const int64_t ks = P->k_sol, nt = P->nt, p = P->p;
-  double* BT = P->BT.d();
-  const int64_t ldbt = nt;
-  copy_cols(nt, (int)p, P->F2.d(), nt, BT, ldbt, st);
-  const TimeOps t = time_ops(P);
-  bidiag_right((int)ks, (int)nt, P->Y.d(), P->kcap, t.m, t.n, -1.0, BT + p * ldbt, ldbt, st);
-  bidiag_right((int)ks, (int)nt, P->Y.d(), P->kcap, t.d, t.e, -1.0, BT + (p + ks) * ldbt, ldbt,
-               st);
-  Seg segs[3] = {{P->F1.d(), P->ldv, (int)p}, {P->KV.d(), P->ldv, (int)ks},
-                 {P->MV.d(), P->ldv, (int)ks}};
-  const int nseg = ks > 0 ? 3 : 1;
-  const int mtot = (int)(p + (ks > 0 ? 2 * ks : 0));
+  const int64_t nt = P->nt, ldbt = nt;
   bool use_qr = nt >= 2 * (int64_t)mtot && qr_r_supported(nt, mtot) && P->residual_qr >= 0;
   if (use_qr && P->residual_qr == 0) {
     // the direct product costs 2 Nh m Nt flops on the matrix cores, the QR
@@ -767,8 +929,7 @@ double true_residual(sts_problem* P) {
     use_qr = saved > (mtot / (double)kQrNb) * 60e-6;
   }
   if (use_qr) {
-    // ||A B^T|| = ||A R_B^T|| with B = Q_B R_B: an Nh x mtot x mtot product
-    // instead of Nh x mtot x Nt
+    // an Nh x mtot x mtot product instead of Nh x mtot x Nt
     const size_t wd = qr_r_work_doubles(nt, mtot);
     if (P->qr_work.bytes < wd * 8) P->qr_work.alloc(wd * 8);
     if (P->qr_R.bytes < (size_t)mtot * mtot * 8) P->qr_R.alloc((size_t)mtot * mtot * 8);
@@ -783,7 +944,59 @@ double true_residual(sts_problem* P) {
   }
   double r2 = 0.0;
   fetch(P, P->smallv.d(), 1, &r2);
-  return std::sqrt(std::max(r2, 0.0)) / P->fnorm;
+  return std::max(r2, 0.0);
+}
+
+// Exact relative residual ||F1 F2^T - Kx V Y Mt^T - Mx V Y Dt^T||_F / ||F||_F
+// = ||[F1, Kx V, Mx V] [F2, -Mt Y^T, -Dt Y^T]^T||_F / ||F||_F.
+double true_residual(sts_problem* P) {
+  hipStream_t st = P->stream;
+  const int64_t ks = P->k_sol, nt = P->nt, p = P->p;
+  double* BT = P->BT.d();
+  const int64_t ldbt = nt;
+  copy_cols(nt, (int)p, P->F2.d(), nt, BT, ldbt, st);
+  const TimeOps t = time_ops(P);
+  bidiag_right((int)ks, (int)nt, P->Y.d(), P->kcap, t.m, t.n, -1.0, BT + p * ldbt, ldbt, st);
+  bidiag_right((int)ks, (int)nt, P->Y.d(), P->kcap, t.d, t.e, -1.0, BT + (p + ks) * ldbt, ldbt,
+               st);
+  Seg segs[3] = {{P->F1.d(), P->ldv, (int)p}, {P->KV.d(), P->ldv, (int)ks},
+                 {P->MV.d(), P->ldv, (int)ks}};
+  const int nseg = ks > 0 ? 3 : 1;
+  const int mtot = (int)(p + (ks > 0 ? 2 * ks : 0));
+  return std::sqrt(lowrank_norm2(P, segs, nseg, mtot, BT)) / P->fnorm;
+}
+
+// ||V Y||_F of the current solution.
+double solution_fnorm(sts_problem* P) {
+  const int64_t ks = P->k_sol;
+  if (ks == 0) return 0.0;
+  transpose((int)ks, (int)P->nt, P->Y.d(), P->kcap, P->BT.d(), P->nt, P->stream);
+  Seg seg{P->V.d(), P->ldv, (int)ks};
+  return std::sqrt(lowrank_norm2(P, &seg, 1, (int)ks, P->BT.d()));
+}
+
+// The exact residual is evaluated from the solution stored in FP64.  Rounding
+// U's entries (relative u = 2^-53) alone moves the residual by
+// Kx (delta o U) Mt^T + Mx (delta o U) Dt^T, whose expected Frobenius norm is
+// u / sqrt(3) (||c_K|| rms(Mt) + ||c_M|| rms(Dt)) ||U||_F, with c_K, c_M the
+// stencil coefficients and rms(A) the root mean square of the row norms of a
+// time matrix.  Relative to ||F||, this grows like the condition number of
+// Mx^{-1} Kx (about 1e-7 for the 1-D problem with 65535 nodes, where no FP64
+// representation of the exact solution has a smaller residual).  The floor
+// reported is kFloorFactor times that estimate, above what the rounded exact
+// solution measures (about 3.5 times it).
+constexpr double kFloorFactor = 8.0;
+
+double residual_floor(sts_problem* P) {
+  return kFloorFactor * P->floor_coef * solution_fnorm(P);
+}
+
+// Whether an exact residual res above tol is explained by the rounding floor:
+// the floor must be at least tol / 2 (else the residual can still be resolved
+// to tol) and res within tol + floor.  *floor receives the floor.
+bool floor_accepts(sts_problem* P, double tol, double res, double* floor) {
+  *floor = residual_floor(P);
+  return *floor >= 0.5 * tol && res <= tol + *floor;
 }
 
 void check_inner(const CGScal& s) {
@@ -1150,13 +1363,11 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   const Stencil K = make_stencil(space, STS_OP_K);
   const Stencil M = make_stencil(space, STS_OP_M);
   const int64_t ld = pad_ld(g.nh);
-  const int64_t kc = 2LL * p * (max_outer + 2);   // the capacity sts_solve reserves
+  const int64_t kc = initial_capacity(p, max_outer);   // the capacity sts_solve maps first
   int64_t b = 0;
   b += ld * p * 8 + nt * p * 8 + 4 * nt * 8;                       // F1, F2, time matrices
   b += 2 * 2 * ld * kMaxCols * 8 + 2 * ld * kMaxCols * 8;          // CG r, p; residual work
-  b += 3 * ld * kc * 8 + 3 * kc * kc * 8 + kc * p * 8;             // V MV KV; Kred Mred Q; beta
-  b += eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8;
-  b += 3 * kc * nt * 8 + nt * (p + 2 * kc) * 8 + kc * 4 * 8;       // Z Y RB; BT; qb
+  b += basis_capacity_bytes(ld, nt, p, kc);
   b += gemm_tn_partial_size(std::max<int64_t>(g.nh, nt), (int)kc) * 8;
   b += residual_norm2_partial_size(g.nh, (int)nt) * 8;
   MGPlan plan{};
@@ -1164,6 +1375,15 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   if (tridiag_supported(g, K, M)) b += 4 * g.nh * 8;
   if (tensor_mass_supported(g, M)) b += 2 * g.nx * 8;
   return b + (1 << 20);                                            // small scratch
+}
+
+int64_t problem_growth_bytes(const sts_space& space, int64_t nt, int p, int64_t cols) {
+  const Grid g = make_grid(space);
+  return basis_capacity_bytes(pad_ld(g.nh), nt, p, cols) - basis_capacity_bytes(pad_ld(g.nh), nt, p, 0);
+}
+
+void problem_set_grow_hook(sts_problem* P, std::function<void(int64_t)> hook) {
+  P->grow_hook = std::move(hook);
 }
 
 double problem_cost(const sts_problem* P) {
@@ -1338,6 +1558,25 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
       for (int j = 0; j < p; ++j) tr += h1[i + 16 * j] * h2[j + 16 * i];
     P->fnorm = std::sqrt(std::max(tr, 0.0));
     STS_REQUIRE(std::isfinite(P->fnorm), STS_E_INVALID, "F1 or F2 is not finite");
+    {
+      // coefficient of the FP64 rounding floor of the exact residual (see
+      // residual_floor)
+      double cK = 0.0, cM = 0.0;
+      for (int i = 0; i < 27; ++i) {
+        cK += P->K.c[i] * P->K.c[i];
+        cM += P->M.c[i] * P->M.c[i];
+      }
+      double sm = 0.0, sd = 0.0;
+      for (int64_t l = 0; l < nt; ++l) {
+        const double mlo = l + 1 < nt ? P->h_ms[l] : 0.0, dlo = l + 1 < nt ? P->h_ts[l] : 0.0;
+        sm += P->h_md[l] * P->h_md[l] + mlo * mlo;
+        sd += P->h_td[l] * P->h_td[l] + dlo * dlo;
+      }
+      const double u = std::ldexp(1.0, -53);
+      if (P->fnorm > 0.0)
+        P->floor_coef = u / std::sqrt(3.0) *
+                        (std::sqrt(cK * sm / nt) + std::sqrt(cM * sd / nt)) / P->fnorm;
+    }
     *out = P.release();
   });
 }
@@ -1375,14 +1614,18 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     } prof_guard(o.profile ? &P->prof : nullptr);
     if (o.profile) P->prof.reset();
     P->profiled = o.profile != 0;
-    ensure_capacity(P, P->k + (int64_t)b2 * (o.max_outer + 2), o.mem_budget);
-    if (!P->smallv.p) P->smallv.alloc(std::max<int64_t>(P->kcap * 16, 4096) * 8);
-    if (P->smallv.bytes < (size_t)P->kcap * 16 * 8) P->smallv.alloc(P->kcap * 16 * 8);
+    // the basis grows in place as the space grows, within an address range
+    // reserved for max_outer + 2 more blocks
+    const int64_t cap_limit = P->k + (int64_t)b2 * (o.max_outer + 2);
+    ensure_capacity(P, P->k + initial_capacity(p, o.max_outer), cap_limit, o.mem_budget);
     // STS_TRACE=1: one line per residual check on stderr
     const char* tr = std::getenv("STS_TRACE");
     const bool trace = tr && tr[0] == '1';
     sts_status result = STS_E_NOT_CONVERGED;
+    std::string fail_msg;
     bool breakdown = false;
+    bool floor_limited = false;
+    double floor = -1.0;
     double cheap = -1.0, truer = -1.0;
     int outer = 0;
     if (P->fnorm == 0.0) {
@@ -1425,6 +1668,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       // solves make the projected value read low)
       double ratio = 1.0;
       for (outer = 1; outer <= o.max_outer; ++outer) {
+        ensure_capacity(P, P->k + b2, cap_limit, o.mem_budget);
         // inner tolerance of this block: relaxed in inverse proportion to the
         // residual (the block's share of the solution shrinks with it)
         sts_opts oi = o;
@@ -1477,10 +1721,24 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
         P->blk_size = kept;
         P->k = kprev + kept;
         if (kept == 0) {
-          // the space is invariant under A and A^{-1}: the Galerkin solution is exact
+          // every new column lies in the space: it is invariant under A and
+          // A^{-1}, so the Galerkin solution is exact in exact arithmetic.  A
+          // deflation threshold too coarse for the problem can also empty a
+          // block, so the exact residual confirms before success.
           breakdown = true;
           P->k_sol = kprev;
           cheap = reduced_solve(P, kprev, 0);
+          if (o.verify_true) {
+            truer = true_residual(P);
+            if (trace) std::fprintf(stderr, "sts: outer %d breakdown, exact residual %.3e\n", outer, truer);
+            if (truer > o.tol && floor_accepts(P, o.tol, truer, &floor)) floor_limited = true;
+            else if (truer > o.tol) {
+              result = STS_E_NUMERIC;
+              fail_msg = "the space stopped growing (every new column deflated) with exact residual " +
+                         std::to_string(truer) + " above tol; the factors of this iterate are kept";
+              break;
+            }
+          }
           result = STS_OK;
           break;
         }
@@ -1533,6 +1791,13 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
             result = STS_OK;
             break;
           }
+          if (floor_accepts(P, o.tol, truer, &floor)) {
+            // the projected residual met tol; the exact one is above it only
+            // by the rounding floor of its own evaluation
+            result = STS_OK;
+            floor_limited = true;
+            break;
+          }
           if (cheap > 0.0) ratio = std::max(ratio, truer / cheap);
         }
         // schedule the next check from the observed convergence rate and the
@@ -1573,14 +1838,18 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       info->rank = -1;
       info->alg_bytes = P->alg_bytes;
       info->cg_poll_restarts = P->cg.poll.poll_restarts;
+      info->res_floor = floor;
+      info->floor_limited = floor_limited ? 1 : 0;
     }
     STS_HIP(hipStreamSynchronize(st));
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) info->seconds = secs;
     if (result != STS_OK)
-      throw Error{result, "max_outer reached before the residual met tol (last projected residual " +
-                              std::to_string(cheap) + ")"};
+      throw Error{result, fail_msg.empty()
+                              ? "max_outer reached before the residual met tol (last projected residual " +
+                                    std::to_string(cheap) + ")"
+                              : fail_msg};
   });
 }
 
@@ -1604,7 +1873,7 @@ sts_status sts_get_factors(const sts_problem* Pc, double* V, int64_t ldv, double
     const hipMemcpyKind kind = mem == STS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (V && ks > 0) {
       STS_REQUIRE(ldv >= P->nh, STS_E_INVALID, "ldv < Nh");
-      STS_HIP(hipMemcpy2DAsync(V, ldv * 8, P->V.p, P->ldv * 8, P->nh * 8, ks, kind, st));
+      STS_HIP(hipMemcpy2DAsync(V, ldv * 8, P->V.d(), P->ldv * 8, P->nh * 8, ks, kind, st));
     }
     if (Y && ks > 0) {
       STS_REQUIRE(ldy >= ks, STS_E_INVALID, "ldy < k");
@@ -1648,7 +1917,7 @@ const char* sts_kernel_name(int32_t kernel) {
       "cg_iter",   "mg_down",  "mg_up",   "mg_coarse",     "pcg_a", "pcg_b",
       "mass_cheb", "gram",     "basis_update", "residual", "tridiag", "bisect",
       "inviter",   "backtransform", "sweep", "stencil", "tridiag_solve",
-      "mg_restrict", "pcg_reduce", "residual_qr"};
+      "mg_restrict", "pcg_reduce", "residual_qr", "gram_reduce"};
   return (kernel >= 0 && kernel < STS_K_COUNT) ? names[kernel] : "";
 }
 

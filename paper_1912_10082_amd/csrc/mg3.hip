@@ -2,7 +2,10 @@
 //
 // Kx = c (6; -1 x 6), c = mu h, is the P1 stiffness of the Kuhn triangulation
 // of the uniform grid (every cube cut into six tetrahedra around its x+y+z
-// diagonal), the stiffness paired with the Q1 mass in Sec. 3's 3-D example.
+// diagonal).  The paper's 3-D heat problem (Sec. 5, Example 1) uses linear
+// elements; pairing this 7-point stiffness with the consistent trilinear (Q1)
+// mass is this library's reading of a trilinear-mass / 7-point-stiffness
+// discretisation, which the paper itself does not define.
 // The Kuhn meshes of widths h, 2h, 4h, ... are nested.  The prolongation P is
 // P1 interpolation: coarse values at coincident nodes, the mean of the two
 // end points at the midpoints of coarse edges, which run in the seven
@@ -23,9 +26,10 @@
 //    every z-plane (two 64 x 64 GEMMs on the matrix cores), then per y-plane
 //    the transform along z, the division and the inverse transform along z,
 //    then the inverse 2-D transform of every z-plane.
-// The V-cycle is a fixed symmetric positive definite operator (the post-
-// smoothing polynomial is the adjoint of the pre-smoothing one), so the outer
-// iteration is ordinary preconditioned CG.
+// In FP64 the V-cycle is a fixed symmetric positive definite operator (the
+// post-smoothing polynomial is the adjoint of the pre-smoothing one), so the
+// outer iteration is ordinary preconditioned CG.  The FP32-storage variant
+// below is symmetric and linear only up to single-precision rounding.
 //
 // Shifted operator Kx + s Mx (the rational Krylov steps, Sec. 4): every level
 // adds s times its own Q1 mass (rediscretised: the Q1 mass is not a Galerkin
@@ -36,9 +40,12 @@
 // Mixed precision (MGPlan::f32): the same launches store every vector of the
 // V-cycle in FP32 except the finest right-hand side (the CG residual) and the
 // result (the preconditioned residual), which stay FP64; loads widen to FP64
-// and all arithmetic is FP64.  The rounding perturbs the preconditioner only,
-// so the FP64 CG around it reaches the same tolerances, and the finest level
-// moves 64 instead of 96 bytes per node and column.
+// and all arithmetic is FP64.  The pre-smoothing launch rounds its input b to
+// FP32 in the LDS tile while the post-smoothing launches read b in FP64, so
+// the variant is linear and symmetric only up to single-precision rounding.
+// The rounding perturbs the preconditioner only, so the FP64 CG around it
+// reaches the same tolerances, and the finest level moves 64 instead of 96
+// bytes per node and column.
 //
 // Launches per smoothed level: "pre" (both pre-smoothing steps from zero,
 // which need b on a one-node halo only, on the tile and its halo, then the

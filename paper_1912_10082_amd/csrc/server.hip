@@ -5,13 +5,18 @@
 // host inputs and returns a ticket at once.  `workers` worker threads, each
 // with its own non-blocking HIP stream, take requests in arrival order
 // (first come, first served).  A request is admitted only if the device
-// memory it will hold -- the estimate of problem_footprint, dominated by the
-// basis capacity Nh x 6 p (max_outer + 2) that sts_solve reserves -- fits in
-// the budget next to the requests admitted and not yet released; otherwise
-// the queue waits until a release frees enough.  A request that could never
-// fit is refused at submission.  A finished request keeps its problem (basis,
-// factors) in device memory until sts_server_release, so a client can fetch
-// factors, evaluate residuals or continue the solve on the device.
+// memory it holds at the start -- problem_footprint: inputs, inner-solve work
+// and the first basis capacity sts_solve maps -- fits in the budget next to
+// the requests admitted and not yet released; otherwise the queue waits until
+// a release frees enough.  A request that could never fit is refused at
+// submission.  While it runs, its basis grows in place; each growth step asks
+// the server for its bytes first and waits until they fit, except for the
+// oldest running request, which always proceeds (it cannot wait on requests
+// younger than itself, so some request always makes progress; the budget may
+// be exceeded by that request's growth).  A finished request keeps its
+// problem (basis, factors) in device memory until sts_server_release, so a
+// client can fetch factors, evaluate residuals or continue the solve on the
+// device.
 //
 // Every request is solved by the same deterministic kernels as a lone
 // sts_solve, so its factors do not depend on what else is being served.
@@ -44,7 +49,8 @@ struct Request {
   std::vector<double> F1, F2;               // packed: ld = rows
   int64_t nh = 0;
   sts_opts opts{};
-  int64_t footprint = 0;
+  int64_t footprint = 0;                    // bytes held: admission + growth
+  int64_t admit_seq = 0;                    // admission order
   Clock::time_point submitted, admitted, finished;
   bool done = false;
   sts_status status = STS_E_STATE;
@@ -65,6 +71,7 @@ struct sts_server {
   std::deque<std::shared_ptr<Request>> queue;
   std::map<int64_t, std::shared_ptr<Request>> live;   // submitted and not released
   int64_t next_ticket = 1;
+  int64_t next_admit = 1;
   int64_t in_use = 0, peak = 0;
   int64_t submitted = 0, completed = 0, released = 0, running = 0;
   bool stop = false;
@@ -77,6 +84,25 @@ constexpr int kMaxServerWorkers = 64;
 
 double seconds(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double>(b - a).count();
+}
+
+// Account for `add` more bytes of a running request before its basis grows:
+// wait until they fit in the budget, unless the request is the oldest one
+// running (then proceed at once).
+void grow_reservation(sts_server* S, Request* r, int64_t add) {
+  if (add <= 0) return;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto oldest = [&] {
+    for (auto& kv : S->live) {
+      const Request& o = *kv.second;
+      if (o.admit_seq > 0 && !o.done && o.admit_seq < r->admit_seq) return false;
+    }
+    return true;
+  };
+  S->cv_work.wait(lk, [&] { return S->stop || S->in_use + add <= S->budget || oldest(); });
+  S->in_use += add;
+  S->peak = std::max(S->peak, S->in_use);
+  r->footprint += add;
 }
 
 void server_worker(sts_server* S, int w) {
@@ -95,6 +121,7 @@ void server_worker(sts_server* S, int w) {
       S->in_use += r->footprint;
       S->peak = std::max(S->peak, S->in_use);
       ++S->running;
+      r->admit_seq = S->next_admit++;
       r->admitted = Clock::now();
     }
     // the head may have changed: let another idle worker look at it
@@ -108,7 +135,11 @@ void server_worker(sts_server* S, int w) {
       const sts_bidiag Mt{r->mtd.data(), r->mts.data()};
       st = sts_create(&r->space, &Dt, &Mt, r->nt, r->p, r->F1.data(), r->nh, r->F2.data(), r->nt,
                       STS_MEM_HOST, S->streams[w], &P);
-      if (st == STS_OK) st = sts_solve(P, &r->opts, &info);
+      if (st == STS_OK) {
+        Request* rr = r.get();
+        problem_set_grow_hook(P, [S, rr](int64_t add) { grow_reservation(S, rr, add); });
+        st = sts_solve(P, &r->opts, &info);
+      }
       err = st == STS_OK ? std::string() : std::string(sts_last_error());
     }
     {
@@ -126,6 +157,7 @@ void server_worker(sts_server* S, int w) {
       ++S->completed;
     }
     S->cv_done.notify_all();
+    S->cv_work.notify_all();   // growth waiters: the oldest running request may have changed
   }
 }
 

@@ -460,8 +460,14 @@ hipStream_t problem_stream(const sts_problem* P);
 void problem_bind_stream(sts_problem* P, hipStream_t s);
 // Relative cost estimate of a solve (for largest-first scheduling).
 double problem_cost(const sts_problem* P);
-// Device bytes a problem holds after sts_create and an sts_solve with this
-// max_outer (upper estimate; the capacity reserved by sts_solve dominates).
+// Device bytes a problem holds after sts_create and the first capacity an
+// sts_solve with this max_outer maps (upper estimate); the basis then grows
+// in place as the space grows.
 int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer);
+// Extra device bytes of `cols` more basis columns.
+int64_t problem_growth_bytes(const sts_space& space, int64_t nt, int p, int64_t cols);
+// Called with the extra bytes before the problem's basis grows; may block
+// (to wait for memory) or throw (the solve then fails with that error).
+void problem_set_grow_hook(sts_problem* P, std::function<void(int64_t)> hook);
 
 }  // namespace sts

@@ -1,6 +1,8 @@
 // Direct Mx solves for the 3-D trilinear mass matrix.
 //
-// The Q1 mass matrix of Sec. 3 on the uniform grid is the tensor product of
+// The consistent trilinear (Q1) mass matrix on the uniform grid (this
+// library's reading of the 3-D discretisation; the paper's 3-D heat problem,
+// Sec. 5, Example 1, uses linear elements) is the tensor product of
 // three 1-D mass matrices, Mx = (h/6)^3 T (x) T (x) T with T = tridiag(1, 4, 1),
 // so Mx^{-1} = (6/h)^3 T^{-1} (x) T^{-1} (x) T^{-1}: three passes, each solving
 // T y = x along every grid line of one direction (elimination without

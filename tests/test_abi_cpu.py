@@ -179,11 +179,13 @@ def test_server_and_footprint_reject_bad_arguments_without_a_gpu():
     sp = b.make_space(2, 63)
     assert lib.sts_footprint(C.byref(sp), 1, 2, None) == -1          # nt < 2
     assert lib.sts_footprint(C.byref(sp), 16, 5, None) == -1         # p > 4
-    # the basis capacity dominates: 3 Nh doubles per reserved column
-    small = sts.footprint(2, 63, 16, 1, max_outer=10)
+    # the solve first maps 8 blocks of 2p basis columns (max_outer + 2 blocks
+    # if fewer) and grows in place from there: 3 Nh doubles per column
+    small = sts.footprint(2, 63, 16, 1, max_outer=2)
+    six = sts.footprint(2, 63, 16, 1, max_outer=6)
     big = sts.footprint(2, 63, 16, 1, max_outer=100)
-    cols = 2 * 1 * (100 - 10)
-    assert big - small >= 3 * 63 * 63 * 8 * cols
+    assert six == big
+    assert big - small >= 3 * 63 * 63 * 8 * (2 * 1 * (8 - 4))
 
 
 def test_adaptive_shift_host_rule_matches_oracle():

@@ -61,6 +61,27 @@ def test_pool_matches_solo_bitwise_and_oracle():
         pr.close()
 
 
+def test_pool_at_batch_benchmark_sizes_matches_oracle():
+    """Sides 127 and 255 with Nt = 1024, ranks 1..3, mu across [0.1, 10], with
+    the batch benchmark's options: every problem against Crank-Nicolson."""
+    batch = [wl.heat_2d_separable(n=255, nt=1024, p=3, seed=4101, mu=0.13),
+             wl.heat_2d_separable(n=127, nt=1024, p=1, seed=4102, mu=7.5),
+             wl.heat_2d_separable(n=255, nt=1024, p=2, seed=4103, mu=1.9),
+             wl.heat_2d_separable(n=127, nt=1024, p=2, seed=4104, mu=0.4)]
+    opts = dict(tol=1e-9, max_outer=80, inner_relax=1)
+    probs = [_make(w) for w in batch]
+    with sts.Pool(4) as pool:
+        infos = pool.solve(probs, **opts)
+    for w, pr, info in zip(batch, probs, infos):
+        assert info["status"] == "STS_OK", (w.name, info)
+        V, Y = pr.factors()
+        K, M = fem.spatial_operators(2, w.n[0], w.mu)
+        Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+        U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
+        assert rel(V @ Y, U) <= 1e-8, (w.name, rel(V @ Y, U))
+        pr.close()
+
+
 def test_pool_per_problem_options_and_failures():
     batch = wl.batch_2d_uneven(count=4, seed0=91, sides=(31,), nts=(32,), ps=(2,))
     probs = [_make(w) for w in batch]

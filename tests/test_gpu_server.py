@@ -71,26 +71,67 @@ def test_served_requests_equal_alone_and_oracle():
         assert st["mem_in_use"] == 0 and st["queued"] == 0 and st["running"] == 0
 
 
-def test_budget_admission_and_refusal():
+def test_budget_admission_growth_and_refusal():
+    """Admission by the starting footprint; a running request's basis then
+    grows in place, each step waiting for budget unless the request is the
+    oldest running one, so the peak stays within the budget plus one
+    request's growth."""
     mix = [wl.heat_2d_separable(n=63, nt=32, p=2, seed=s) for s in range(6)]
     opts = dict(tol=1e-9, max_outer=60)
     one = sts.footprint(2, 63, 32, 2, **opts)
     assert one > 63 * 63 * 8
-    # room for two requests at a time
-    with sts.Server(workers=4, mem_budget=2 * one + one // 2) as server:
+    budget = 2 * one + one // 2                       # two requests at their start
+    with sts.Server(workers=4, mem_budget=budget) as server:
         tickets = [_submit(server, w, **opts) for w in mix]
+        held = []
         for t in tickets:
-            res, _ = server.wait(t)
+            res, prob = server.wait(t)
             assert res["status"] == "STS_OK", res
+            assert res["footprint"] >= one
+            held.append(res["footprint"])
             server.release(t)
         st = server.stats()
-        assert st["mem_peak"] <= 2 * one + one // 2 and st["mem_peak"] >= one
+        assert max(held) > one                        # the bases grew past the first capacity
+        assert one <= st["mem_peak"] <= budget + max(held) - one, (st, one, held)
         with pytest.raises(sts.STSError) as e:
             _submit(server, wl.heat_2d_separable(n=127, nt=32, p=2, seed=1), **opts)
         assert e.value.code == 2                      # STS_E_NOMEM: can never fit
         with pytest.raises(sts.STSError) as e:
             server.release(tickets[0])                # already released
         assert e.value.code == 1
+
+
+def test_serving_sizes_alone_equal_mixed_and_oracle():
+    """Requests at the serving mix's sizes in flight together: a 1-D grid of
+    32767 nodes, 3-D cubes of side 63 and 127, a 2-D grid of side 255.  Each
+    served result equals the same request solved alone, bitwise, and matches
+    the oracle (sine-mode solutions in 1-D and 3-D, Crank-Nicolson in 2-D)."""
+    mix = [wl.heat_1d_profiles(n=32767, nt=512, p=3, seed=71, mu=2.5),
+           wl.heat_3d_separable(n=63, nt=256, p=3, seed=72, mu=0.5),
+           wl.heat_3d_separable(n=127, nt=128, p=2, seed=73, mu=3.0),
+           wl.heat_2d_separable(n=255, nt=300, p=4, seed=74, mu=0.2)]
+
+    def ropts(w):   # the serving benchmark's options
+        return dict(tol=1e-8, max_outer=60, inner_relax=2 if w.dim == 3 else 1)
+
+    with sts.Server(workers=3, mem_budget=64 << 30) as server:
+        tickets = [_submit(server, w, **ropts(w)) for w in mix]
+        for w, t in zip(mix, tickets):
+            res, prob = server.wait(t)
+            assert res["status"] == "STS_OK", (w.name, res)
+            V, Y = prob.factors()
+            server.release(t)
+            info, Va, Ya = _alone(w, **ropts(w))
+            assert np.array_equal(V, Va) and np.array_equal(Y, Ya), w.name
+            Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
+            if w.dim == 1:
+                U = exact.modal_solve_1d_fast(w.n[0], w.mu, Dt, Mt, w.F1, w.F2)
+            elif w.dim == 3:
+                U = exact.modal_solve_3d(w.n[0], w.mu, Dt, Mt, w.F1, w.F2)
+            else:
+                K, M = fem.spatial_operators(2, w.n[0], w.mu)
+                U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
+            assert rel(V @ Y, U) <= 1e-8, (w.name, rel(V @ Y, U))
 
 
 def test_failed_request_is_reported_and_others_finish():
