@@ -566,8 +566,8 @@ def main() -> int:
     # solves stop at max(1e-13, min(1e-4, 10^-j tol / r)); the exact residual
     # still decides convergence.  j = 1 in 2-D, 2 in 3-D (measured best: with
     # j = 1 the 3-D solve needs a second exact residual, 0.7 s).  The basis
-    # grows in place as the space grows (the 255^3 rank-4 run maps about 424
-    # of the 808 columns max_outer allows)
+    # grows with the space (the 255^3 rank-4 run holds about 424 of the 808
+    # columns max_outer allows)
     opts = dict(tol=args.tol, restart=1, max_outer=100 if d3 else 150, inner_relax=2 if d3 else 1)
     if args.precond_fp32:
         # mixed precision: the 3-D multigrid V-cycle stores its vectors in FP32

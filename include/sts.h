@@ -221,10 +221,10 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
  * non-NULL.  May be called again on the same problem with a tighter tolerance:
  * the space is extended from where the previous call stopped.
  *
- * Device memory: V, Mx V and Kx V (Nh x k each) grow in place as the space
- * grows, 16p columns at a time, inside an address range reserved for
- * max_outer + 2 more blocks (HIP virtual memory; reallocation and copy on
- * devices without it), so the problem holds what the basis uses, not what
+ * Device memory: V, Mx V and Kx V (Nh x k each) grow with the space, 16p
+ * columns at a time and to at most max_outer + 2 more blocks, by
+ * reallocation and a device copy (old and new copies of one array coexist
+ * for that moment), so the problem holds what the basis uses, not what
  * max_outer allows.  opts->mem_budget bounds the total.
  *
  * Convergence is decided by the projected residual and confirmed by the
@@ -552,8 +552,8 @@ typedef struct {
 /* Device bytes a problem of this shape holds after sts_create and the first
  * basis capacity a solve with these options (NULL = defaults) maps: inputs,
  * inner-solve work and 3 Nh doubles for each of min(8, max_outer + 2) blocks
- * of 2p columns.  The basis then grows in place by 3 Nh doubles per column as
- * the space grows (sts_solve).  -1 for an invalid shape. */
+ * of 2p columns.  The basis then grows by 3 Nh doubles per column as the
+ * space grows (sts_solve).  -1 for an invalid shape. */
 int64_t sts_footprint(const sts_space* space, int64_t nt, int32_t p, const sts_opts* opts);
 
 /* workers: 1..64; mem_budget > 0 bytes.  Errors: STS_E_INVALID, STS_E_DEVICE. */

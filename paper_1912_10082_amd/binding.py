@@ -299,7 +299,10 @@ class Problem:
         code = self._lib.sts_solve(self._h, C.byref(o), C.byref(info))
         d = info.as_dict()
         d["status"] = STATUS_NAMES.get(code, code)
-        if code not in (STS_OK, STS_E_NOT_CONVERGED):
+        # not converged, or a space that stopped growing above tol (breakdown):
+        # the factors of the last iterate are kept and the info is returned
+        if code not in (STS_OK, STS_E_NOT_CONVERGED) and not (code == STS_E_NUMERIC
+                                                              and d["breakdown"] == 1):
             _check(code)
         d["error"] = self._lib.sts_last_error().decode() if code != STS_OK else ""
         return d

@@ -522,12 +522,13 @@ __global__ void apply_rinv_kernel(int64_t rows, int b, const CholInfo* info, con
   }
 }
 
+// Grid-stride over rows (x) and columns (y): any size fits a bounded grid.
 __global__ void copy_cols_kernel(int64_t rows, int ncols, const double* src, int64_t lds,
                                  double* dst, int64_t ldd) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * ncols) return;
-  const int64_t r = idx % rows, c = idx / rows;
-  dst[r + c * ldd] = src[r + c * lds];
+  for (int c = blockIdx.y; c < ncols; c += gridDim.y)
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x)
+      dst[r + (int64_t)c * ldd] = src[r + (int64_t)c * lds];
 }
 
 __global__ void scale_kernel(double* p, int64_t n, double v) {
@@ -536,8 +537,9 @@ __global__ void scale_kernel(double* p, int64_t n, double v) {
 }
 
 __global__ void fill_kernel(double* p, int64_t n, double v) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < n) p[idx] = v;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    p[idx] = v;
 }
 
 __global__ void sumsq_kernel(int64_t rows, int ncols, const double* A, int64_t lda,
@@ -731,15 +733,16 @@ void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, d
 
 void copy_cols(int64_t rows, int ncols, const double* src, int64_t lds, double* dst, int64_t ldd,
                hipStream_t st) {
-  const int64_t n = rows * ncols;
-  if (n <= 0) return;
-  copy_cols_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(rows, ncols, src, lds, dst, ldd);
+  if (rows <= 0 || ncols <= 0) return;
+  const dim3 grid((unsigned)std::min<int64_t>((rows + 255) / 256, 8192),
+                  (unsigned)std::min(ncols, 1024));
+  copy_cols_kernel<<<grid, 256, 0, st>>>(rows, ncols, src, lds, dst, ldd);
   STS_HIP(hipGetLastError());
 }
 
 void fill(double* p, int64_t n, double v, hipStream_t st) {
   if (n <= 0) return;
-  fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+  fill_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(p, n, v);
   STS_HIP(hipGetLastError());
 }
 

@@ -199,158 +199,46 @@ struct DevBuf {
   double* d() const { return static_cast<double*>(p); }
 };
 
-// A device array that grows in place.  A virtual address range is reserved
-// once for the largest size the caller may ask for, and physical memory is
-// mapped behind it in chunks as the array grows (HIP virtual memory
-// management): contents never move, nothing is copied, and the device holds
-// only the mapped chunks.  Where the device lacks virtual memory support the
-// array is reallocated and its contents copied instead.
+// A device array that grows: a larger allocation replaces the old one and a
+// kernel copies the kept prefix across.  Old and new coexist for the copy.
 struct GrowBuf {
   char* base = nullptr;
-  size_t reserved = 0;   // bytes of address range (vmm) or of the allocation (fallback)
-  size_t mapped = 0;     // bytes backed by memory
-  bool vmm = false;
-  std::vector<std::pair<hipMemGenericAllocationHandle_t, size_t>> chunks;
+  size_t bytes = 0;
 
   GrowBuf() = default;
   GrowBuf(const GrowBuf&) = delete;
   GrowBuf& operator=(const GrowBuf&) = delete;
   ~GrowBuf() { release(); }
 
-  static bool vmm_supported(int dev) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeVirtualMemoryManagementSupported, dev) !=
-        hipSuccess) {
-      (void)hipGetLastError();
-      return false;
-    }
-    return v != 0;
-  }
-  static hipMemAllocationProp prop_for(int dev) {
-    hipMemAllocationProp pr = {};
-    pr.type = hipMemAllocationTypePinned;
-    pr.location.type = hipMemLocationTypeDevice;
-    pr.location.id = dev;
-    return pr;
-  }
   void release() {
-    if (vmm && base) {
-      size_t off = 0;
-      for (auto& c : chunks) {
-        (void)hipMemUnmap(base + off, c.second);
-        (void)hipMemRelease(c.first);
-        off += c.second;
-      }
-      (void)hipMemAddressFree(base, reserved);
-    } else if (base) {
-      (void)hipFree(base);
-    }
-    chunks.clear();
+    if (base) (void)hipFree(base);
     base = nullptr;
-    reserved = mapped = 0;
-    vmm = false;
+    bytes = 0;
   }
   double* d() const { return reinterpret_cast<double*>(base); }
 
-  // Make `need` bytes usable, of at most `limit` bytes ever asked for from
-  // this reservation; the first `keep` bytes keep their contents.  Grows
-  // past `limit` by a new reservation and one copy.
-  void ensure(size_t need, size_t limit, size_t keep, hipStream_t st) {
-    if (need <= mapped) return;
-    int dev = 0;
-    STS_HIP(hipGetDevice(&dev));
-    if (need > reserved && base) {
-      // outgrew the reservation: move into a larger one
-      GrowBuf nb;
-      nb.ensure(need, std::max(limit, need), 0, st);
-      if (keep) STS_HIP(hipMemcpyAsync(nb.base, base, keep, hipMemcpyDeviceToDevice, st));
-      STS_HIP(hipStreamSynchronize(st));
-      std::swap(base, nb.base);
-      std::swap(reserved, nb.reserved);
-      std::swap(mapped, nb.mapped);
-      std::swap(vmm, nb.vmm);
-      std::swap(chunks, nb.chunks);
-      return;
-    }
-    if (!base) {
-      vmm = vmm_supported(dev);
-      if (vmm) {
-        const hipMemAllocationProp pr = prop_for(dev);
-        size_t gran = 0;
-        if (hipMemGetAllocationGranularity(&gran, &pr, hipMemAllocationGranularityRecommended) !=
-                hipSuccess || gran == 0) {
-          (void)hipGetLastError();
-          vmm = false;
-        } else {
-          const size_t want = ((std::max(limit, need) + gran - 1) / gran) * gran;
-          void* va = nullptr;
-          if (hipMemAddressReserve(&va, want, 0, nullptr, 0) != hipSuccess) {
-            (void)hipGetLastError();
-            vmm = false;
-          } else {
-            base = static_cast<char*>(va);
-            reserved = want;
-          }
-        }
-      }
-      if (!vmm) {
-        void* p = nullptr;
-        if (hipMalloc(&p, need) != hipSuccess) {
-          (void)hipGetLastError();
-          throw Error{STS_E_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
-        }
-        base = static_cast<char*>(p);
-        reserved = mapped = need;
-        return;
-      }
-    }
-    if (!vmm) {
-      // fallback: reallocate and copy
-      void* p = nullptr;
-      if (hipMalloc(&p, need) != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error{STS_E_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
-      }
-      if (keep) STS_HIP(hipMemcpyAsync(p, base, keep, hipMemcpyDeviceToDevice, st));
-      STS_HIP(hipStreamSynchronize(st));
-      (void)hipFree(base);
-      base = static_cast<char*>(p);
-      reserved = mapped = need;
-      return;
-    }
-    const hipMemAllocationProp pr = prop_for(dev);
-    size_t gran = 0;
-    STS_HIP(hipMemGetAllocationGranularity(&gran, &pr, hipMemAllocationGranularityRecommended));
-    const size_t add = ((need - mapped + gran - 1) / gran) * gran;
-    STS_REQUIRE(mapped + add <= reserved, STS_E_DEVICE, "growable buffer: mapping beyond its reservation");
-    hipMemGenericAllocationHandle_t h{};
-    if (hipMemCreate(&h, add, &pr, 0) != hipSuccess) {
+  // Make `need` bytes usable; the first `keep` bytes (a multiple of 8) keep
+  // their contents.
+  void ensure(size_t need, size_t keep, hipStream_t st) {
+    if (need <= bytes) return;
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) {
       (void)hipGetLastError();
-      throw Error{STS_E_NOMEM, "could not map " + std::to_string(add) + " more bytes of device memory"};
+      throw Error{STS_E_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed"};
     }
-    if (hipMemMap(base + mapped, add, 0, h, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipMemRelease(h);
-      throw Error{STS_E_DEVICE, "hipMemMap failed"};
-    }
-    hipMemAccessDesc acc = {};
-    acc.location.type = hipMemLocationTypeDevice;
-    acc.location.id = dev;
-    acc.flags = hipMemAccessFlagsProtReadWrite;
-    if (hipMemSetAccess(base + mapped, add, &acc, 1) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipMemUnmap(base + mapped, add);
-      (void)hipMemRelease(h);
-      throw Error{STS_E_DEVICE, "hipMemSetAccess failed"};
-    }
-    chunks.emplace_back(h, add);
-    mapped += add;
+    if (base && keep)
+      copy_cols((int64_t)(std::min(keep, bytes) / 8), 1, reinterpret_cast<const double*>(base), 0,
+                static_cast<double*>(p), 0, st);
+    STS_HIP(hipStreamSynchronize(st));
+    release();
+    base = static_cast<char*>(p);
+    bytes = need;
   }
 };
 
 static inline int64_t pad_ld(int64_t n) { return ((n + 31) / 32) * 32; }
 
-// Basis columns mapped per growth step, in blocks of 2p columns.
+// Basis columns added per growth step, in blocks of 2p columns.
 constexpr int kGrowBlocks = 8;
 
 // Bytes of the k-dependent buffers for a basis capacity of kc columns
@@ -363,7 +251,7 @@ int64_t basis_capacity_bytes(int64_t ld, int64_t nt, int p, int64_t kc) {
          3 * kc * nt * 8 + nt * (p + 2 * kc) * 8;
 }
 
-// The first capacity sts_solve maps: kGrowBlocks blocks, or the whole
+// The first capacity sts_solve allocates: kGrowBlocks blocks, or the whole
 // max_outer + 2 blocks if fewer.
 int64_t initial_capacity(int p, int max_outer) {
   return 2LL * p * std::min<int64_t>(kGrowBlocks, (int64_t)max_outer + 2);
@@ -712,7 +600,7 @@ struct sts_problem {
   int64_t k_sol = 0;      // columns of the current Galerkin solution
   int64_t blk_start = 0, blk_size = 0;
   std::vector<int> tags;  // 0: positive power, 1: negative power
-  GrowBuf V, MV, KV;      // basis and its images, grown in place
+  GrowBuf V, MV, KV;      // basis and its images, grown with the space
   DevBuf Kred, Mred, beta;
   // called with the extra bytes before the basis grows (the server's
   // footprint accounting; may block or throw)
@@ -763,10 +651,12 @@ int64_t capacity_bytes(const sts_problem* P, int64_t kc) {
   return basis_capacity_bytes(P->ldv, P->nt, P->p, kc);
 }
 
-// Make room for `need` basis columns.  V, Mx V and Kx V grow in place
-// (GrowBuf), kGrowBlocks blocks ahead of the need, within an address range
-// reserved for `limit` columns; the reduced matrices, beta and the current
-// solution Y are copied to their new leading dimension; the rest is scratch.
+// Make room for `need` basis columns.  V, Mx V and Kx V grow (GrowBuf)
+// kGrowBlocks blocks ahead of the need, to at most `limit` columns; the
+// reduced matrices, beta and the current solution Y are copied to their new
+// leading dimension; the rest is scratch.  The growth hook is told the
+// persistent increase plus the transient of the largest copy (the old array
+// and its replacement coexist), and then that the transient is returned.
 void ensure_capacity(sts_problem* P, int64_t need, int64_t limit, int64_t budget) {
   if (need <= P->kcap) return;
   const int64_t b2 = 2 * P->p;
@@ -778,12 +668,13 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t limit, int64_t budget
   STS_REQUIRE(budget <= 0 || bytes <= budget, STS_E_NOMEM,
               "basis of " + std::to_string(kc) + " columns needs " + std::to_string(bytes) +
                   " bytes, above the memory budget");
-  if (P->grow_hook) P->grow_hook(bytes - capacity_bytes(P, P->kcap));
+  const int64_t transient = ld * P->kcap * 8;
+  if (P->grow_hook) P->grow_hook(bytes - capacity_bytes(P, P->kcap) + transient);
   hipStream_t st = P->stream;
   const int64_t old = P->kcap;
-  P->V.ensure(ld * kc * 8, ld * limit * 8, ld * P->k * 8, st);
-  P->MV.ensure(ld * kc * 8, ld * limit * 8, ld * P->k * 8, st);
-  P->KV.ensure(ld * kc * 8, ld * limit * 8, ld * P->k * 8, st);
+  P->V.ensure(ld * kc * 8, ld * P->k * 8, st);
+  P->MV.ensure(ld * kc * 8, ld * P->k * 8, st);
+  P->KV.ensure(ld * kc * 8, ld * P->k * 8, st);
   // small buffers with leading dimension kc: copy column by column
   auto regrow = [&](DevBuf& b, int64_t cols, int64_t rows_keep, int64_t cols_keep) {
     DevBuf nb;
@@ -809,6 +700,7 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t limit, int64_t budget
   P->BT.alloc(nt * (P->p + 2 * kc) * 8);
   P->tn_part.alloc(gemm_tn_partial_size(std::max<int64_t>(P->nh, nt), (int)kc) * 8);
   P->kcap = kc;
+  if (P->grow_hook && transient > 0) P->grow_hook(-transient);
   if (!P->smallv.p || P->smallv.bytes < (size_t)std::max<int64_t>(kc * 16, 4096) * 8)
     P->smallv.alloc(std::max<int64_t>(kc * 16, 4096) * 8);
 }
@@ -1363,7 +1255,7 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   const Stencil K = make_stencil(space, STS_OP_K);
   const Stencil M = make_stencil(space, STS_OP_M);
   const int64_t ld = pad_ld(g.nh);
-  const int64_t kc = initial_capacity(p, max_outer);   // the capacity sts_solve maps first
+  const int64_t kc = initial_capacity(p, max_outer);   // the capacity sts_solve allocates first
   int64_t b = 0;
   b += ld * p * 8 + nt * p * 8 + 4 * nt * 8;                       // F1, F2, time matrices
   b += 2 * 2 * ld * kMaxCols * 8 + 2 * ld * kMaxCols * 8;          // CG r, p; residual work
@@ -1614,8 +1506,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     } prof_guard(o.profile ? &P->prof : nullptr);
     if (o.profile) P->prof.reset();
     P->profiled = o.profile != 0;
-    // the basis grows in place as the space grows, within an address range
-    // reserved for max_outer + 2 more blocks
+    // the basis grows with the space, to at most max_outer + 2 more blocks
     const int64_t cap_limit = P->k + (int64_t)b2 * (o.max_outer + 2);
     ensure_capacity(P, P->k + initial_capacity(p, o.max_outer), cap_limit, o.mem_budget);
     // STS_TRACE=1: one line per residual check on stderr
@@ -1873,7 +1764,22 @@ sts_status sts_get_factors(const sts_problem* Pc, double* V, int64_t ldv, double
     const hipMemcpyKind kind = mem == STS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (V && ks > 0) {
       STS_REQUIRE(ldv >= P->nh, STS_E_INVALID, "ldv < Nh");
-      STS_HIP(hipMemcpy2DAsync(V, ldv * 8, P->V.d(), P->ldv * 8, P->nh * 8, ks, kind, st));
+      // a kernel reads V, into the caller's device buffer directly or
+      // through a bounded device staging buffer for the host
+      if (mem == STS_MEM_DEVICE) {
+        copy_cols(P->nh, (int)ks, P->V.d(), P->ldv, V, ldv, st);
+      } else {
+        const int64_t per = std::max<int64_t>(1, std::min<int64_t>(ks, (32 << 20) / std::max<int64_t>(P->nh, 1)));
+        DevBuf stage;
+        stage.alloc((size_t)(per * P->nh) * 8);
+        for (int64_t c0 = 0; c0 < ks; c0 += per) {
+          const int64_t nc = std::min(per, ks - c0);
+          copy_cols(P->nh, (int)nc, P->V.d() + c0 * P->ldv, P->ldv, stage.d(), P->nh, st);
+          STS_HIP(hipMemcpy2DAsync(V + c0 * ldv, ldv * 8, stage.d(), P->nh * 8, P->nh * 8, nc,
+                                   hipMemcpyDeviceToHost, st));
+          STS_HIP(hipStreamSynchronize(st));
+        }
+      }
     }
     if (Y && ks > 0) {
       STS_REQUIRE(ldy >= ks, STS_E_INVALID, "ldy < k");

@@ -9,8 +9,9 @@
 // and the first basis capacity sts_solve maps -- fits in the budget next to
 // the requests admitted and not yet released; otherwise the queue waits until
 // a release frees enough.  A request that could never fit is refused at
-// submission.  While it runs, its basis grows in place; each growth step asks
-// the server for its bytes first and waits until they fit, except for the
+// submission.  While it runs, its basis grows; each growth step asks the
+// server for its bytes (with the transient of its copy, returned after it)
+// first and waits until they fit, except for the
 // oldest running request, which always proceeds (it cannot wait on requests
 // younger than itself, so some request always makes progress; the budget may
 // be exceeded by that request's growth).  A finished request keeps its
@@ -90,8 +91,16 @@ double seconds(Clock::time_point a, Clock::time_point b) {
 // wait until they fit in the budget, unless the request is the oldest one
 // running (then proceed at once).
 void grow_reservation(sts_server* S, Request* r, int64_t add) {
-  if (add <= 0) return;
+  if (add == 0) return;
   std::unique_lock<std::mutex> lk(S->mu);
+  if (add < 0) {
+    // a transient of the growth step returned
+    S->in_use += add;
+    r->footprint += add;
+    lk.unlock();
+    S->cv_work.notify_all();
+    return;
+  }
   auto oldest = [&] {
     for (auto& kv : S->live) {
       const Request& o = *kv.second;

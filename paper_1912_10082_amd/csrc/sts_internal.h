@@ -461,8 +461,8 @@ void problem_bind_stream(sts_problem* P, hipStream_t s);
 // Relative cost estimate of a solve (for largest-first scheduling).
 double problem_cost(const sts_problem* P);
 // Device bytes a problem holds after sts_create and the first capacity an
-// sts_solve with this max_outer maps (upper estimate); the basis then grows
-// in place as the space grows.
+// sts_solve with this max_outer allocates (upper estimate); the basis then
+// grows with the space.
 int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer);
 // Extra device bytes of `cols` more basis columns.
 int64_t problem_growth_bytes(const sts_space& space, int64_t nt, int p, int64_t cols);
