@@ -137,6 +137,21 @@ typedef struct {
                                the solves reach the same tolerances.  Applies to 3-D seven-point
                                spaces with n > 63 (at least one smoothed level); elsewhere
                                ignored.  0 = FP64 throughout; default 0 */
+  int32_t mixed;            /* 1 = FP32 bulk with FP64 refinement: the 3-D Kx solves run
+                               multigrid PCG in FP32 (every vector, the stencil product, the
+                               V-cycle, per-tile inner products) inside FP64 defect correction
+                               (x += d, r = b - Kx x in FP64 until ||r|| <= rtol ||b||, FP64 PCG
+                               finishing a column whose FP32 rounds stall), and the first
+                               classical Gram-Schmidt pass takes its coefficients from an FP32
+                               copy of V with FP32 accumulation (the update uses the FP64 basis,
+                               so each block stays in the span of the expansion); the second
+                               (re-orthogonalisation) pass, the reduced
+                               matrices, eigensolve, time sweep and the exact Sylvester
+                               residual that decides convergence stay FP64.  Applies to 3-D
+                               seven-point spaces with n > 63; elsewhere ignored.  Takes
+                               precedence over precond_fp32 in the FP32 rounds.  2 = the FP32
+                               Kx solves only, 3 = the FP32 Gram-Schmidt pass only (the two
+                               parts apart); 0 = FP64 throughout; default 0 */
 } sts_opts;
 
 typedef struct {
@@ -158,6 +173,9 @@ typedef struct {
                                sts_solve), or -1 where it was not needed */
   int32_t floor_limited;    /* 1 = accepted with res_true above tol but within res_floor of it */
   int32_t pad_;
+  int64_t inner_its_fp32;   /* FP32 PCG iterations of the mixed-precision Kx solves (included
+                               in inner_its_K) */
+  int64_t defect_rounds;    /* FP64 defect corrections of the mixed-precision Kx solves */
 } sts_info;
 
 /* Kernels timed by sts_kernel_profile. */
@@ -394,6 +412,23 @@ sts_status sts_pcg_mg_mixed(const sts_space* space, double shift, const double* 
  * are constant-coefficient symmetric tridiagonal, solved by elimination
  * without pivoting (the inner solves of the extended Krylov space, Sec. 4).
  * B, X: Nh x ncols (ldb, ldx), device, must not overlap; ncols <= 8. */
+/* Kx X = B for the 3-D seven-point stiffness with FP32 bulk work: FP32
+ * multigrid PCG (vectors, stencil product, V-cycle and per-tile inner
+ * products in FP32) as the correction solver of FP64 iterative refinement
+ * (x += d, r = B - Kx x in FP64, until ||r|| <= rtol ||b|| per column; FP64
+ * PCG finishes a column whose FP32 rounds stall).  These are the Kx solves
+ * of the extended Krylov expansion (Sec. 4, the pole 0) under
+ * sts_opts.mixed.  Needs a grid with a smoothed level (n > 63, halving to
+ * <= 63).  B, X device, Nh x ncols (ldb, ldx >= Nh), 1 <= ncols <= 8;
+ * 0 < rtol < 1.  *iters_fp32 / *iters_fp64 (nullable) receive the FP32 and
+ * FP64 PCG iterations over all columns, *rounds the defect corrections.
+ * Synchronous.  Errors: STS_E_INVALID; STS_E_NUMERIC for a non-finite
+ * residual or a breakdown of the FP64 finish. */
+sts_status sts_pcg_mg_refined(const sts_space* space, const double* B, int64_t ldb, double* X,
+                              int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                              int64_t* iters_fp32, int64_t* iters_fp64, int64_t* rounds,
+                              void* stream);
+
 sts_status sts_tridiag_solve(const sts_space* space, const int32_t* ops, const double* B,
                              int64_t ldb, double* X, int64_t ldx, int32_t ncols, void* stream);
 
@@ -440,6 +475,7 @@ sts_status sts_m_orthonormalize(const sts_space* space, const double* V, const d
 sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 
+
 /* The basis update of block Gram-Schmidt, W (rows x n, ldw) -= A (rows x m,
  * lda) C (m x n, ldc), n <= 16; FP64 matrix cores.  With A = V and C from
  * sts_gram it removes the new block's components along the orthonormal basis
@@ -447,6 +483,18 @@ sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t
  * STS_E_INVALID for n > 16 or ld < rows. */
 sts_status sts_basis_update(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
                             const double* C, int64_t ldc, double* W, int64_t ldw, void* stream);
+
+/* The contraction of sts_gram in FP32, as the first Gram-Schmidt pass of the
+ * mixed-precision solve (sts_opts.mixed) runs it against the FP32 copy of the
+ * basis for its coefficients: C (m x n, FP64 storage) = A^T B with A FP32
+ * (rows x m, lda) and B FP64 rounded to FP32 as it is read.  Products and
+ * sums are FP32 on the matrix cores (relative accuracy about 1e-7 of
+ * |A|^T |B|).  The solve removes these coefficients with the FP64 basis and
+ * re-orthogonalises in FP64, keeping the Mx-orthonormal basis of Sec. 4 in
+ * the span of the expansion.  Sizes, pointers and errors as for sts_gram;
+ * synchronous. */
+sts_status sts_gram_fp32(int64_t rows, int32_t m, int32_t n, const float* A, int64_t lda,
+                         const double* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 
 /* Eigendecomposition of a symmetric k x k matrix A (lda): A Q = Q diag(lam),
  * Q^T Q = I, by Householder tridiagonalisation, bisection, inverse iteration

@@ -46,7 +46,7 @@ class Opts(C.Structure):
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
                 ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32),
                 ("residual_qr", C.c_int32), ("inner_relax", C.c_int32),
-                ("precond_fp32", C.c_int32)]
+                ("precond_fp32", C.c_int32), ("mixed", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -55,7 +55,8 @@ class Info(C.Structure):
                 ("res_cheap", C.c_double), ("res_true", C.c_double), ("orth_err", C.c_double),
                 ("seconds", C.c_double), ("alg_bytes", C.c_double), ("breakdown", C.c_int32),
                 ("shifts", C.c_int32), ("cg_poll_restarts", C.c_int64),
-                ("res_floor", C.c_double), ("floor_limited", C.c_int32), ("pad_", C.c_int32)]
+                ("res_floor", C.c_double), ("floor_limited", C.c_int32), ("pad_", C.c_int32),
+                ("inner_its_fp32", C.c_int64), ("defect_rounds", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
@@ -108,6 +109,8 @@ _SIGS = {
     "sts_mg_vcycle_mixed": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _P]),
     "sts_pcg_mg_mixed": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _F64, _I32,
                                    C.POINTER(_I32), _P]),
+    "sts_pcg_mg_refined": (C.c_int, [C.POINTER(Space), _P, _I64, _P, _I64, _I32, _F64, _I32,
+                                     C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), _P]),
     "sts_adaptive_shift": (C.c_int, [_D, _I32, _D, _I32, _F64, _F64, _I32, _D]),
     "sts_shifted_solve": (C.c_int, [C.POINTER(Space), _F64, _P, _I64, _P, _I64, _I32, _F64, _I32,
                                     C.POINTER(_I32), _P]),
@@ -119,6 +122,7 @@ _SIGS = {
                                        _F64, C.POINTER(_I32), C.POINTER(_I32), _P]),
     "sts_gram": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_basis_update": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "sts_gram_fp32": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_sym_eig": (C.c_int, [_I64, _P, _I64, _P, _P, _I64, _P]),
     "sts_time_sweep": (C.c_int, [_I64, _I64, _I32, _P, _P, _I64, _P, _I64, _P, _I64,
                                  C.POINTER(Bidiag), C.POINTER(Bidiag), _P, _I64, _P]),
@@ -414,6 +418,19 @@ def pcg_mg_mixed(space: Space, B, shift: float = 0.0, rtol: float = 1e-12, maxit
     return X, list(its), code
 
 
+def pcg_mg_refined(space: Space, B, rtol: float = 1e-12, maxit: int = 1000):
+    """Kx X = B by FP32 multigrid PCG inside FP64 defect correction (3-D
+    seven-point spaces with a smoothed level); returns (X, FP32 iterations,
+    FP64 iterations, defect corrections)."""
+    B, pb, ldb = dev_colmajor(B)
+    X = dev_zeros(B.shape[0], B.shape[1])
+    i32, i64, rounds = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(load().sts_pcg_mg_refined(C.byref(space), pb, ldb, C.c_void_p(X.data_ptr()), X.shape[0],
+                                     B.shape[1], rtol, maxit, C.byref(i32), C.byref(i64),
+                                     C.byref(rounds), _stream_handle()))
+    return X, i32.value, i64.value, rounds.value
+
+
 def mass_solve(space: Space, B, rtol: float = 1e-13):
     """Mx X = B: Chebyshev iteration (2-D P1) or direct line solves (3-D trilinear); returns (X, iterations)."""
     B, pb, ldb = dev_colmajor(B)
@@ -503,6 +520,29 @@ def gram(A, B):
     Cm = dev_empty(A.shape[1], B.shape[1])
     _check(load().sts_gram(A.shape[0], A.shape[1], B.shape[1], pa, lda, pb, ldb,
                            C.c_void_p(Cm.data_ptr()), A.shape[1], _stream_handle()))
+    return Cm
+
+
+def dev_colmajor32(t):
+    """A float32 CUDA tensor viewed as a column-major matrix -> (tensor, ptr, ld)."""
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError("expected a float32 CUDA tensor")
+    if t.dim() == 1:
+        t = t[:, None]
+    if t.stride(0) != 1 or (t.shape[1] > 1 and t.stride(1) < t.shape[0]):
+        t = t.t().contiguous().t()
+    ld = t.stride(1) if t.shape[1] > 1 else max(t.shape[0], 1)
+    return t, C.c_void_p(t.data_ptr()), int(ld)
+
+
+def gram_fp32(A32, B):
+    """C = A32^T B in FP32 (A32 float32, B float64; C returned as float64)."""
+    A32, pa, lda = dev_colmajor32(A32)
+    B, pb, ldb = dev_colmajor(B)
+    Cm = dev_empty(A32.shape[1], B.shape[1])
+    _check(load().sts_gram_fp32(A32.shape[0], A32.shape[1], B.shape[1], pa, lda, pb, ldb,
+                                C.c_void_p(Cm.data_ptr()), A32.shape[1], _stream_handle()))
     return Cm
 
 

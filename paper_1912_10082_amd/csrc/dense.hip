@@ -181,6 +181,148 @@ __global__ __launch_bounds__(256) void gemm_tn_reduce(int m, int n, int64_t nchu
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 form of the Gram-Schmidt contraction (the coefficients of the first
+// classical Gram-Schmidt pass of the mixed-precision solve): A is an FP32
+// copy of the basis, the thin FP64 operand is rounded to FP32 as it is
+// loaded, products and sums are FP32 on v_mfma_f32_16x16x4f32.  Its operands are laid out as
+// in the FP64 16x16x4 instruction above (lane i + 16 g supplies a = X[i][g],
+// b = Y[g][i]), but its accumulator is not: element q of lane i + 16 g is
+// (X Y)[4 g + q][i] (four consecutive rows per lane group).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float wave_sum32(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partial[chunk][c][j] (c < m16, j < 16) of A^T B over the chunk's rows, in
+// FP32; the work split of gemm_tn_kernel.  VEC: one 16-byte load of four A
+// rows and two of four B rows per lane (A 16-byte aligned with ld % 4 == 0,
+// B 16-byte aligned with even ld).
+template <int T, int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW) void gemm_tn32_kernel(int64_t rows, int m, int n,
+                                                            const float* A, int64_t lda,
+                                                            const double* B, int64_t ldb,
+                                                            float* partial, int m16, int rpw) {
+  __shared__ float red[NW - 1][T][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int c0 = blockIdx.x * 16 * T;
+  const int64_t chunk = blockIdx.y;
+  const int64_t rb = (chunk * NW + wv) * (int64_t)rpw;
+  const int64_t re = min(rb + rpw, rows);
+  const float* Ap[T];
+  bool aok[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int col = c0 + 16 * t + i;
+    aok[t] = col < m;
+    Ap[t] = A + (int64_t)(aok[t] ? col : 0) * lda;
+  }
+  const bool bok = i < n;
+  const double* Bp = B + (int64_t)(bok ? i : 0) * ldb;
+  f4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  int64_t r = rb;
+  for (; r + 16 <= re; r += 16) {
+    const int64_t rr = r + 4 * g;
+    float av[T][4], bv[4];
+    if (VEC) {
+      const double2 b0 = bok ? *(const double2*)(Bp + rr) : double2{0.0, 0.0};
+      const double2 b1 = bok ? *(const double2*)(Bp + rr + 2) : double2{0.0, 0.0};
+      bv[0] = (float)b0.x;
+      bv[1] = (float)b0.y;
+      bv[2] = (float)b1.x;
+      bv[3] = (float)b1.y;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float4 a4 = aok[t] ? *(const float4*)(Ap[t] + rr) : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        av[t][0] = a4.x;
+        av[t][1] = a4.y;
+        av[t][2] = a4.z;
+        av[t][3] = a4.w;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bv[s] = bok ? (float)Bp[rr + s] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < T; ++t) av[t][s] = aok[t] ? Ap[t][rr + s] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma32(av[t][s], bv[s], acc[t]);
+  }
+  if (r < re) {   // ragged end of the wave's rows
+    const int64_t rr = r + 4 * g;
+    float av[T][4], bv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool ok = rr + s < re;
+      bv[s] = (ok && bok) ? (float)Bp[rr + s] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < T; ++t) av[t][s] = (ok && aok[t]) ? Ap[t][rr + s] : 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma32(av[t][s], bv[s], acc[t]);
+  }
+  // element q of a lane's accumulator is (tile row 4 g + q, column i)
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wv - 1][t][(4 * g + q) * 16 + i] = acc[t][q];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    if (c0 + 16 * t >= m16) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = (4 * g + q) * 16 + i;
+      float v = acc[t][q];
+#pragma unroll
+      for (int w = 0; w < NW - 1; ++w) v += red[w][t][e];
+      partial[(chunk * m16 + c0 + 16 * t + 4 * g + q) * 16 + i] = v;
+    }
+  }
+}
+
+// C (m x n, FP64 storage) = the sum of the FP32 chunk partials, in FP32.
+__global__ __launch_bounds__(256) void gemm_tn32_reduce(int m, int n, int64_t nchunks, int m16,
+                                                        const float* partial, double* C,
+                                                        int64_t ldc) {
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (idx >= m * n) return;
+  const int i = idx % m, j = idx / m;
+  float s = 0.0f;
+  for (int64_t c = lane; c < nchunks; c += 64) s += partial[(c * m16 + i) * 16 + j];
+  s = wave_sum32(s);
+  if (lane == 0) C[i + (int64_t)j * ldc] = (double)s;
+}
+
+// FP64 -> FP32 copy of columns (the FP32 copy of new basis columns).
+__global__ void round_cols_kernel(int64_t rows, int ncols, const double* src, int64_t lds,
+                                  float* dst, int64_t ldd) {
+  for (int c = blockIdx.y; c < ncols; c += gridDim.y)
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x)
+      dst[r + (int64_t)c * ldd] = (float)src[r + (int64_t)c * lds];
+}
+
 // W (rows x n) -= A (rows x m) C (m x n); each wave owns 16 rows.
 __global__ __launch_bounds__(256) void gemm_nn_sub_kernel(int64_t rows, int m, int n,
                                                           const double* A, int64_t lda,
@@ -752,6 +894,49 @@ void sumsq(int64_t rows, int ncols, const double* A, int64_t lda, double* out, d
   int blocks = (int)std::min<int64_t>((total + 255) / 256, 1024);
   if (blocks < 1) blocks = 1;
   sumsq_kernel<<<blocks, 256, 0, st>>>(rows, ncols, A, lda, partial, counter, out);
+  STS_HIP(hipGetLastError());
+}
+
+// FP32 Gram-Schmidt contraction (see the kernels above).
+void gemm_tn32(int64_t rows, int m, int n, const float* A, int64_t lda, const double* B,
+               int64_t ldb, double* C, int64_t ldc, float* partial, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  STS_REQUIRE(n <= 16, STS_E_INVALID, "gemm_tn32: n > 16");
+  const int m16 = ((m + 15) / 16) * 16;
+  const TnPlan p = tn_plan(rows, m);
+  if (rows <= 0) {
+    fill_kernel<<<1, 256, 0, st>>>(reinterpret_cast<double*>(partial), (int64_t)m16 * 8, 0.0);
+  } else {
+    const bool vec = aligned16(A) && aligned16(B) && lda % 4 == 0 && ldb % 2 == 0;
+    const dim3 grid((unsigned)p.groups, (unsigned)p.nch);
+    const double bytes = 4.0 * (double)rows * m + 8.0 * (double)rows * n;
+    auto go = [&](auto kern, int nw) {
+      launch(STS_K_GRAM, bytes, kern, grid, dim3(64 * nw), 0, st, rows, m, n, A, lda, B, ldb,
+             partial, m16, p.rpw);
+    };
+    if (p.T == 4) {
+      if (vec) go(gemm_tn32_kernel<4, 4, true>, 4);
+      else go(gemm_tn32_kernel<4, 4, false>, 4);
+    } else if (p.T == 2) {
+      if (vec) go(gemm_tn32_kernel<2, 4, true>, 4);
+      else go(gemm_tn32_kernel<2, 4, false>, 4);
+    } else {
+      if (vec) go(gemm_tn32_kernel<1, 16, true>, 16);
+      else go(gemm_tn32_kernel<1, 16, false>, 16);
+    }
+  }
+  STS_HIP(hipGetLastError());
+  const int64_t nch = rows <= 0 ? 1 : p.nch;
+  launch(STS_K_GRAM_REDUCE, 4.0 * ((double)nch * m16 * 16) + 8.0 * m * n, gemm_tn32_reduce,
+         dim3((m * n + 3) / 4), dim3(256), 0, st, m, n, nch, m16, (const float*)partial, C, ldc);
+}
+
+void round_cols(int64_t rows, int ncols, const double* src, int64_t lds, float* dst, int64_t ldd,
+                hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return;
+  const dim3 grid((unsigned)std::min<int64_t>((rows + 255) / 256, 8192),
+                  (unsigned)std::min(ncols, 1024));
+  round_cols_kernel<<<grid, 256, 0, st>>>(rows, ncols, src, lds, dst, ldd);
   STS_HIP(hipGetLastError());
 }
 

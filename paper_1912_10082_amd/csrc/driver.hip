@@ -242,11 +242,12 @@ static inline int64_t pad_ld(int64_t n) { return ((n + 31) / 32) * 32; }
 constexpr int kGrowBlocks = 8;
 
 // Bytes of the k-dependent buffers for a basis capacity of kc columns
-// (leading dimension ld): V, Mx V, Kx V, the reduced matrices and beta, the
+// (leading dimension ld): V, Mx V, Kx V (and V's FP32 copy in the mixed-
+// precision solve), the reduced matrices and beta, the
 // eigensolver's Q and workspace, Z, Y and the refinement scratch, and the time
 // factor of the exact residual.
-int64_t basis_capacity_bytes(int64_t ld, int64_t nt, int p, int64_t kc) {
-  return 3 * ld * kc * 8 + 2 * kc * kc * 8 + kc * p * 8 + kc * kc * 8 +
+int64_t basis_capacity_bytes(int64_t ld, int64_t nt, int p, int64_t kc, bool v32) {
+  return 3 * ld * kc * 8 + (v32 ? ld * kc * 4 : 0) + 2 * kc * kc * 8 + kc * p * 8 + kc * kc * 8 +
          eig_work_doubles((int)std::min<int64_t>(kc, kEigMaxK)) * 8 + kc * 8 * 3 +
          3 * kc * nt * 8 + nt * (p + 2 * kc) * 8;
 }
@@ -287,16 +288,30 @@ constexpr double kThirdPassRatio = 1e-2;
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
                          int64_t ldw, int ncols, double defl, OrthScratch& s, int* idx,
-                         hipStream_t st) {
+                         hipStream_t st, double* KW) {
   const int64_t nh = g.nh;
   int opsM[16];
   for (int c = 0; c < 16; ++c) opsM[c] = STS_OP_M;
   s.cgs_passes = 0;
+  s.cgs32_passes = 0;
   auto cgs = [&](int nc) {
     if (k <= 0) return;
     ++s.cgs_passes;
     gemm_tn(nh, (int)k, nc, MV, ldv, W, ldw, s.C, s.ldc, s.part, st);   // C = V^T Mx W
     gemm_nn_sub(nh, (int)k, nc, V, ldv, s.C, s.ldc, W, ldw, st);        // W -= V C
+  };
+  // mixed precision: the first pass takes its coefficients from the FP32
+  // copy of V contracted with Mx W (rounded to FP32) in FP32, and removes
+  // them with the FP64 basis, so the new block stays in the span of W and V
+  // exactly (an update with the rounded basis would add the rounding of V,
+  // which lies outside that span, to every block); the FP64 pass after it
+  // re-orthogonalises
+  auto cgs32 = [&](int nc) {
+    if (k <= 0) return;
+    ++s.cgs32_passes;
+    gemm_tn32(nh, (int)k, nc, s.V32, ldv, MW, ldw, s.C, s.ldc, reinterpret_cast<float*>(s.part),
+              st);                                                         // C = V^T (Mx W)
+    gemm_nn_sub(nh, (int)k, nc, V, ldv, s.C, s.ldc, W, ldw, st);           // W -= V C
   };
   auto fetch_info = [&]() {
     STS_HIP(hipMemcpyAsync(s.host, s.info, sizeof(CholInfo), hipMemcpyDeviceToHost, st));
@@ -308,7 +323,8 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
   gemm_tn(nh, ncols, ncols, W, ldw, MW, ldw, s.G, 16, s.part, st);
   copy_cols(1, ncols, s.G, 17, s.norm0, 1, st);
   // classical Gram-Schmidt against V, twice
-  cgs(ncols);
+  if (s.V32) cgs32(ncols);
+  else cgs(ncols);
   cgs(ncols);
   // Cholesky-QR of the block with deflation
   stencil_apply(g, K, M, opsM, ncols, W, ldw, MW, ldw, st);
@@ -329,7 +345,8 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
   apply_rinv(nh, kept, s.info, s.Rinv, W, nullptr, ldw, nullptr, st);
   h = fetch_info();
   STS_REQUIRE(h.kept == kept, STS_E_NUMERIC, "block lost rank in the second Cholesky-QR pass");
-  stencil_apply(g, K, M, opsM, kept, W, ldw, MW, ldw, st);   // exact Mx image
+  if (KW) stencil_apply_km(g, K, M, kept, W, ldw, KW, ldw, MW, ldw, st);   // exact images
+  else stencil_apply(g, K, M, opsM, kept, W, ldw, MW, ldw, st);            // exact Mx image
   return kept;
 }
 
@@ -471,6 +488,8 @@ struct MGRunner {
   DevBuf levels, vecs, scal, parts, dst;
   int expect = 12;          // iterations the last run needed (first chunk length)
   int expect_shifted = 12;  // the same for the shifted operator Kx + s Mx
+  int expect32 = 6;         // the same for one FP32 round of a mixed-precision solve
+  DevBuf corr, defect, norms;   // mixed precision: correction, FP64 residual, (r, r)
 
   // Allocate for the plan; x / ldx are set per run.
   void setup(const MGPlan& plan) {
@@ -601,6 +620,10 @@ struct sts_problem {
   int64_t blk_start = 0, blk_size = 0;
   std::vector<int> tags;  // 0: positive power, 1: negative power
   GrowBuf V, MV, KV;      // basis and its images, grown with the space
+  GrowBuf V32;            // mixed precision: FP32 copy of V (first Gram-Schmidt pass)
+  bool want_v32 = false;  // V32 is allocated and grown with the basis
+  bool use_v32 = false;   // this solve's first Gram-Schmidt pass reads V32
+  int64_t v32_cols = 0;   // leading columns of V32 that hold V rounded
   DevBuf Kred, Mred, beta;
   // called with the extra bytes before the basis grows (the server's
   // footprint accounting; may block or throw)
@@ -633,6 +656,7 @@ struct sts_problem {
   double* pinned = nullptr;   // 64 doubles
   bool solved = false;
   int64_t inner_K = 0, inner_M = 0;
+  int64_t inner_K32 = 0, defect_rounds = 0;   // mixed-precision Kx solves
   double alg_bytes = 0.0;
   int checks = 0;
   double last_cheap = -1.0;
@@ -648,7 +672,7 @@ struct sts_problem {
 namespace {
 
 int64_t capacity_bytes(const sts_problem* P, int64_t kc) {
-  return basis_capacity_bytes(P->ldv, P->nt, P->p, kc);
+  return basis_capacity_bytes(P->ldv, P->nt, P->p, kc, P->want_v32);
 }
 
 // Make room for `need` basis columns.  V, Mx V and Kx V grow (GrowBuf)
@@ -675,6 +699,7 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t limit, int64_t budget
   P->V.ensure(ld * kc * 8, ld * P->k * 8, st);
   P->MV.ensure(ld * kc * 8, ld * P->k * 8, st);
   P->KV.ensure(ld * kc * 8, ld * P->k * 8, st);
+  if (P->want_v32) P->V32.ensure(ld * kc * 4, ld * P->v32_cols * 4, st);
   // small buffers with leading dimension kc: copy column by column
   auto regrow = [&](DevBuf& b, int64_t cols, int64_t rows_keep, int64_t cols_keep) {
     DevBuf nb;
@@ -735,15 +760,17 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
   s.Rinv = P->rinv.d();
   s.info = static_cast<CholInfo*>(P->cinfo.p);
   s.host = reinterpret_cast<CholInfo*>(P->pinned);
-  const int kept = orthonormalize_block(P->grid, P->K, P->M, P->V.d(), P->MV.d(), ld, k, W, MW,
-                                        ld, ncols, defl, s, keep_idx, st);
-  P->alg_bytes += 2.0 * s.cgs_passes * 8.0 * nh * k + 8.0 * 16.0 * nh * ncols;
-  if (kept == 0) return 0;
-  // Kx image of the new columns
-  int opsK[16];
-  for (int c = 0; c < 16; ++c) opsK[c] = STS_OP_K;
+  s.V32 = P->use_v32 ? reinterpret_cast<const float*>(P->V32.base) : nullptr;
   double* KW = P->KV.d() + k * ld;
-  stencil_apply(P->grid, P->K, P->M, opsK, kept, W, ld, KW, ld, st);
+  const int kept = orthonormalize_block(P->grid, P->K, P->M, P->V.d(), P->MV.d(), ld, k, W, MW,
+                                        ld, ncols, defl, s, keep_idx, st, KW);
+  P->alg_bytes += 2.0 * s.cgs_passes * 8.0 * nh * k + s.cgs32_passes * 12.0 * nh * k +
+                  8.0 * 16.0 * nh * ncols;
+  if (kept == 0) return 0;
+  if (P->use_v32) {
+    round_cols(nh, kept, W, ld, reinterpret_cast<float*>(P->V32.base) + k * ld, ld, st);
+    P->v32_cols = k + kept;
+  }
   // reduced matrices: new columns and their mirror rows
   const int64_t kn = k + kept, kc = P->kcap;
   // one pass over V for both: [Kred Mred](:, new) = V^T [Kx W, Mx W]
@@ -752,7 +779,7 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
   mirror((int)k, kept, P->Kred.d() + k * kc, kc, P->Kred.d() + k, kc, st);
   mirror((int)k, kept, P->Mred.d() + k * kc, kc, P->Mred.d() + k, kc, st);
   gemm_tn(nh, kept, P->p, W, ld, P->F1.d(), ld, P->beta.d() + k, kc, P->tn_part.d(), st);
-  P->alg_bytes += 8.0 * nh * kn + 4.0 * 16.0 * nh * kept;
+  P->alg_bytes += 8.0 * nh * kn + (4.0 * 16.0 - 8.0) * nh * kept;
   return kept;
 }
 
@@ -1023,11 +1050,193 @@ void ritz_values(sts_problem* P, int64_t k, std::vector<double>& out) {
 }
 
 // Kx x_j = b[j] for j < nk by multigrid-preconditioned CG, x_j at x + j * ldv.
+// Mixed-precision Kx solves (opts.mixed, 3-D grids with a smoothed level):
+// iterative refinement with FP32 multigrid PCG as the correction solver.
+// x = 0, r = b; each round solves K d = r in FP32 to the relative tolerance
+// max(target / ||r||, kF32RoundRtol), then in FP64 x += d and r = b - K x,
+// until ||r|| <= target = rtol ||b||.  The FP32 solve's own accuracy is
+// bounded by single-precision rounding, so a round asks for no more than
+// kF32RoundRtol; a round that does not reduce ||r|| by kF32MinGain (the FP32
+// solve stalled or broke down in rounding) ends the FP32 rounds of that
+// column and FP64 PCG solves for the rest of the correction.
+constexpr double kF32RoundRtol = 1e-5;
+constexpr double kF32MinGain = 0.1;
+constexpr int kF32MaxRounds = 6;
+
+bool mixed_applies(const sts_problem* P, const sts_opts& o) {
+  return o.mixed != 0 && P->mg_ok && P->mg_plan_.dim == 3 && P->mg_plan_.nlev >= 1;
+}
+// The parts of the mixed mode: 1 = both, 2 = the Kx solves only, 3 = the
+// Gram-Schmidt pass only.
+bool mixed_inner(const sts_problem* P, const sts_opts& o) {
+  return mixed_applies(P, o) && o.mixed != 3;
+}
+bool mixed_gs(const sts_problem* P, const sts_opts& o) {
+  return mixed_applies(P, o) && o.mixed != 2;
+}
+
+struct RefineCount {
+  int64_t its32 = 0, its64 = 0, rounds = 0;
+  double bytes = 0.0;   // algorithmic bytes
+};
+
+// K x_j = b_j (j < nk, x_j at x + j * ldx, zeroed here) by the refinement
+// above, on the multigrid runner r of a 3-D plan with a smoothed level.
+void refined_kx_solve(MGRunner& r, int64_t nh, int nk, const double* const* b, double* x,
+                      int64_t ldx, double rtol, int maxit, int precond_fp32, RefineCount& cnt,
+                      hipStream_t st) {
+  const int64_t ld0 = r.w.ld[0];
+  if (!r.corr.p) {
+    r.corr.alloc(ld0 * kMaxCols * 8);     // FP32 d (packed) or the FP64 finishing correction
+    r.defect.alloc(ld0 * kMaxCols * 8);   // FP64 residuals b - K x
+    r.norms.alloc(kMaxCols * 8);
+  }
+  float* d32 = reinterpret_cast<float*>(r.corr.d());
+  for (int j = 0; j < nk; ++j) fill(x + j * ldx, nh, 0.0, st);
+  const double bpn32 = [&] {
+    MGPlan q = r.w.plan;
+    q.f32 = 0;
+    q.f32cg = 1;
+    return mg3_bytes_per_node(q);
+  }();
+  const double nn = (double)nh;
+  auto norms = [&](int n, double* out) {
+    STS_HIP(hipMemcpyAsync(out, r.norms.d(), n * sizeof(double), hipMemcpyDeviceToHost, st));
+    STS_HIP(hipStreamSynchronize(st));
+  };
+  std::vector<double> bnorm(nk, 0.0), rnorm(nk, 0.0), target(nk, 0.0);
+  std::vector<int> act, fin;   // columns still in FP32 rounds / for the FP64 finish
+  for (int j = 0; j < nk; ++j) act.push_back(j);
+  CGScal out[kMaxCols];
+  const int saved_f32 = r.w.plan.f32;
+  auto restore = [&](int e) {
+    r.w.plan.f32 = saved_f32;
+    r.w.plan.f32cg = 0;
+    r.w.col_rtol = nullptr;
+    r.expect32 = r.expect;
+    r.expect = e;
+  };
+  for (int round = 0; !act.empty(); ++round) {
+    const int na = (int)act.size();
+    const double* in[kMaxCols];
+    double rt[kMaxCols];
+    for (int s = 0; s < na; ++s) {
+      const int j = act[s];
+      in[s] = round == 0 ? b[j] : r.defect.d() + j * ld0;
+      rt[s] = round == 0 ? std::max(rtol, kF32RoundRtol)
+                         : std::max(target[j] / std::max(rnorm[j], 1e-300), kF32RoundRtol);
+    }
+    // FP32 PCG on the active columns, packed: slot s -> d32 column s
+    r.w.plan.f32 = 0;
+    r.w.plan.f32cg = 1;
+    r.w.col_rtol = rt;
+    const int e = r.expect;
+    r.expect = r.expect32;
+    try {
+      r.run(reinterpret_cast<double*>(d32), ld0, na, in, kF32RoundRtol, maxit, out, st);
+    } catch (...) {
+      restore(e);
+      throw;
+    }
+    restore(e);
+    for (int s = 0; s < na; ++s) {
+      cnt.its32 += out[s].iters;
+      cnt.bytes += (bpn32 * (out[s].iters + 1) + 12.0) * nn;
+      if (round == 0) {
+        // ||b|| from the FP32 set-up's (b, b): enough for a tolerance
+        bnorm[act[s]] = std::sqrt(std::max(out[s].gamma0, 0.0));
+        target[act[s]] = rtol * bnorm[act[s]];
+      }
+    }
+    // FP64: x += d, r = b - K x, (r, r)
+    double* xs[kMaxCols];
+    const void* ds[kMaxCols];
+    const double* bs[kMaxCols];
+    double* rs[kMaxCols];
+    for (int s = 0; s < na; ++s) {
+      const int j = act[s];
+      xs[s] = x + j * ldx;
+      // a column whose FP32 solve broke down contributes no correction
+      ds[s] = out[s].flag == 3 ? nullptr : static_cast<const void*>(d32 + s * ld0);
+      bs[s] = b[j];
+      rs[s] = r.defect.d() + j * ld0;
+    }
+    mg3_defect(r.w, na, xs, ds, true, bs, rs, r.norms.d(), st);
+    ++cnt.rounds;
+    cnt.bytes += 44.0 * nn * na;
+    double n2[kMaxCols];
+    norms(na, n2);
+    std::vector<int> next;
+    for (int s = 0; s < na; ++s) {
+      const int j = act[s];
+      const double rn = std::sqrt(std::max(n2[s], 0.0));
+      STS_REQUIRE(std::isfinite(rn), STS_E_NUMERIC,
+                  "mixed-precision inner solve: non-finite residual");
+      const double prev = round == 0 ? bnorm[j] : rnorm[j];
+      rnorm[j] = rn;
+      if (rn <= target[j]) continue;
+      if (rn > kF32MinGain * prev || round + 1 >= kF32MaxRounds || out[s].flag >= 2)
+        fin.push_back(j);
+      else
+        next.push_back(j);
+    }
+    act.swap(next);
+  }
+  if (fin.empty()) return;
+  // FP64 PCG for the rest of the correction: K e = r, x += e
+  const int nf = (int)fin.size();
+  const double* in[kMaxCols];
+  double rt[kMaxCols];
+  for (int s = 0; s < nf; ++s) {
+    in[s] = r.defect.d() + fin[s] * ld0;
+    rt[s] = std::max(target[fin[s]] / std::max(rnorm[fin[s]], 1e-300), rtol);
+  }
+  r.w.plan.f32 = precond_fp32;
+  r.w.col_rtol = rt;
+  try {
+    r.run(r.corr.d(), ld0, nf, in, rtol, maxit, out, st);
+  } catch (...) {
+    r.w.plan.f32 = saved_f32;
+    r.w.col_rtol = nullptr;
+    throw;
+  }
+  r.w.plan.f32 = saved_f32;
+  r.w.col_rtol = nullptr;
+  const double bpn = r.bytes_per_node();
+  double* xs[kMaxCols];
+  const void* ds[kMaxCols];
+  const double* bs[kMaxCols];
+  double* rs[kMaxCols];
+  for (int s = 0; s < nf; ++s) {
+    check_inner(out[s]);
+    cnt.its64 += out[s].iters;
+    cnt.bytes += (bpn * (out[s].iters + 1) + 40.0) * nn;
+    xs[s] = x + fin[s] * ldx;
+    ds[s] = r.corr.d() + s * ld0;
+    bs[s] = b[fin[s]];
+    rs[s] = r.defect.d() + fin[s] * ld0;
+  }
+  mg3_defect(r.w, nf, xs, ds, false, bs, rs, r.norms.d(), st);
+  ++cnt.rounds;
+  cnt.bytes += 48.0 * nn * nf;
+}
+
+void run_mg_k_mixed(sts_problem* P, int nk, const double* const* b, double* x, const sts_opts& o) {
+  RefineCount c;
+  refined_kx_solve(*P->mg, P->nh, nk, b, x, P->ldv, o.inner_rtol, o.inner_maxit, o.precond_fp32,
+                   c, P->stream);
+  P->inner_K += c.its32 + c.its64;
+  P->inner_K32 += c.its32;
+  P->defect_rounds += c.rounds;
+  P->alg_bytes += c.bytes;
+}
+
 void run_mg_k(sts_problem* P, int nk, const double* const* b, double* x, const sts_opts& o) {
   if (!P->mg) {
     P->mg = std::make_unique<MGRunner>();
     P->mg->setup(P->mg_plan_);
   }
+  if (mixed_inner(P, o)) return run_mg_k_mixed(P, nk, b, x, o);
   CGScal out[kMaxCols];
   P->mg->w.plan.f32 = o.precond_fp32;
   P->mg->run(x, P->ldv, nk, b, o.inner_rtol, o.inner_maxit, out, P->stream);
@@ -1250,7 +1459,7 @@ void problem_bind_stream(sts_problem* P, hipStream_t s) {
   P->stream = s;
 }
 
-int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer) {
+int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer, bool mixed) {
   const Grid g = make_grid(space);
   const Stencil K = make_stencil(space, STS_OP_K);
   const Stencil M = make_stencil(space, STS_OP_M);
@@ -1259,11 +1468,14 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   int64_t b = 0;
   b += ld * p * 8 + nt * p * 8 + 4 * nt * 8;                       // F1, F2, time matrices
   b += 2 * 2 * ld * kMaxCols * 8 + 2 * ld * kMaxCols * 8;          // CG r, p; residual work
-  b += basis_capacity_bytes(ld, nt, p, kc);
+  MGPlan plan{};
+  const bool mg = mg_plan(g, K, &plan);
+  const bool mixed32 = mixed && mg && plan.dim == 3 && plan.nlev >= 1;
+  b += basis_capacity_bytes(ld, nt, p, kc, mixed32);
   b += gemm_tn_partial_size(std::max<int64_t>(g.nh, nt), (int)kc) * 8;
   b += residual_norm2_partial_size(g.nh, (int)nt) * 8;
-  MGPlan plan{};
-  if (mg_plan(g, K, &plan)) b += 9 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
+  if (mg) b += 9 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
+  if (mixed32) b += 2 * ld * kMaxCols * 8;                       // refinement buffers
   if (tridiag_supported(g, K, M)) b += 4 * g.nh * 8;
   if (tensor_mass_supported(g, M)) b += 2 * g.nx * 8;
   return b + (1 << 20);                                            // small scratch
@@ -1271,7 +1483,8 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
 
 int64_t problem_growth_bytes(const sts_space& space, int64_t nt, int p, int64_t cols) {
   const Grid g = make_grid(space);
-  return basis_capacity_bytes(pad_ld(g.nh), nt, p, cols) - basis_capacity_bytes(pad_ld(g.nh), nt, p, 0);
+  return basis_capacity_bytes(pad_ld(g.nh), nt, p, cols, false) -
+         basis_capacity_bytes(pad_ld(g.nh), nt, p, 0, false);
 }
 
 void problem_set_grow_hook(sts_problem* P, std::function<void(int64_t)> hook) {
@@ -1482,7 +1695,8 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     STS_REQUIRE(o.tol > 0.0 && o.max_outer >= 1 && o.inner_rtol > 0.0 && o.inner_maxit >= 1 &&
                     o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0 &&
                     o.residual_qr >= -1 && o.residual_qr <= 1 && o.inner_relax >= 0 &&
-                    o.inner_relax <= 6 && (o.precond_fp32 == 0 || o.precond_fp32 == 1),
+                    o.inner_relax <= 6 && (o.precond_fp32 == 0 || o.precond_fp32 == 1) &&
+                    o.mixed >= 0 && o.mixed <= 3,
                 STS_E_INVALID, "invalid options");
     P->residual_qr = o.residual_qr;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1494,6 +1708,8 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       P->tags.clear();
       P->solved = false;
       P->inner_K = P->inner_M = 0;
+      P->inner_K32 = P->defect_rounds = 0;
+      P->v32_cols = 0;
       P->alg_bytes = 0.0;
       P->checks = 0;
       P->shifts.clear();
@@ -1506,9 +1722,26 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     } prof_guard(o.profile ? &P->prof : nullptr);
     if (o.profile) P->prof.reset();
     P->profiled = o.profile != 0;
+    // mixed precision keeps an FP32 copy of V for the first Gram-Schmidt pass
+    const bool v32 = mixed_gs(P, o);
+    if (v32 && !P->want_v32) {
+      P->want_v32 = true;
+      P->v32_cols = 0;
+      if (P->kcap > 0) {
+        if (P->grow_hook) P->grow_hook(P->ldv * P->kcap * 4);
+        P->V32.ensure(P->ldv * P->kcap * 4, 0, st);
+      }
+    }
     // the basis grows with the space, to at most max_outer + 2 more blocks
     const int64_t cap_limit = P->k + (int64_t)b2 * (o.max_outer + 2);
     ensure_capacity(P, P->k + initial_capacity(p, o.max_outer), cap_limit, o.mem_budget);
+    if (v32 && P->v32_cols < P->k) {
+      // a basis extended from an FP64 solve: round its columns once
+      round_cols(P->nh, (int)(P->k - P->v32_cols), P->V.d() + P->v32_cols * P->ldv, P->ldv,
+                 reinterpret_cast<float*>(P->V32.base) + P->v32_cols * P->ldv, P->ldv, st);
+      P->v32_cols = P->k;
+    }
+    P->use_v32 = v32;
     // STS_TRACE=1: one line per residual check on stderr
     const char* tr = std::getenv("STS_TRACE");
     const bool trace = tr && tr[0] == '1';
@@ -1719,6 +1952,8 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       info->checks = P->checks;
       info->k = P->k_sol;
       info->inner_its_K = P->inner_K;
+      info->inner_its_fp32 = P->inner_K32;
+      info->defect_rounds = P->defect_rounds;
       info->inner_its_M = P->inner_M;
       info->res_cheap = cheap;
       info->breakdown = breakdown ? 1 : 0;
@@ -2158,6 +2393,33 @@ sts_status sts_pcg_mg_mixed(const sts_space* space, double shift, const double* 
   return s;
 }
 
+sts_status sts_pcg_mg_refined(const sts_space* space, const double* B, int64_t ldb, double* X,
+                              int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
+                              int64_t* iters_fp32, int64_t* iters_fp64, int64_t* rounds,
+                              void* stream) {
+  return run_guarded([&] {
+    Grid g;
+    const MGPlan plan = require_mg(space, &g);
+    STS_REQUIRE(plan.dim == 3 && plan.nlev >= 1, STS_E_INVALID,
+                "the refined FP32 solve needs a 3-D grid with a smoothed multigrid level "
+                "(n > 63, halving to <= 63)");
+    STS_REQUIRE(ncols >= 1 && ncols <= kMaxCols, STS_E_INVALID, "ncols must be 1..8");
+    STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
+    STS_REQUIRE(rtol > 0.0 && rtol < 1.0 && maxit >= 1, STS_E_INVALID, "bad rtol / maxit");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MGRunner r;
+    r.setup(plan);
+    const double* bcols[kMaxCols];
+    for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
+    RefineCount cnt;
+    refined_kx_solve(r, g.nh, ncols, bcols, X, ldx, rtol, maxit, 0, cnt, st);
+    STS_HIP(hipStreamSynchronize(st));
+    if (iters_fp32) *iters_fp32 = cnt.its32;
+    if (iters_fp64) *iters_fp64 = cnt.its64;
+    if (rounds) *rounds = cnt.rounds;
+  });
+}
+
 sts_status sts_mg_vcycle(const sts_space* space, const double* R, int64_t ldr, double* Z,
                          int64_t ldz, int32_t ncols, void* stream) {
   return run_guarded([&] {
@@ -2222,6 +2484,20 @@ sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t
     Scratch sc;
     double* part = sc.get<double>(gemm_tn_partial_size(std::max<int64_t>(rows, 1), m));
     gemm_tn(rows, m, n, A, lda, B, ldb, C, ldc, part, st);
+    STS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+sts_status sts_gram_fp32(int64_t rows, int32_t m, int32_t n, const float* A, int64_t lda,
+                         const double* B, int64_t ldb, double* C, int64_t ldc, void* stream) {
+  return run_guarded([&] {
+    STS_REQUIRE(rows >= 0 && m >= 1 && n >= 1 && n <= 16, STS_E_INVALID, "bad sizes");
+    STS_REQUIRE(A && B && C && lda >= rows && ldb >= rows && ldc >= m, STS_E_INVALID,
+                "bad buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    float* part = sc.get<float>(gemm_tn_partial_size(std::max<int64_t>(rows, 1), m));
+    gemm_tn32(rows, m, n, A, lda, B, ldb, C, ldc, part, st);
     STS_HIP(hipStreamSynchronize(st));
   });
 }

@@ -475,6 +475,11 @@ __global__ __launch_bounds__(kCT) void coarse3_z_kernel(Coarse3Args a) {
 // ---------------------------------------------------------------------------
 // PCG launches on the finest grid (tiles TX x TY x TZ)
 // ---------------------------------------------------------------------------
+// The vectors x, r, z, p and q hold V: double, or float in the FP32 PCG of
+// the mixed-precision inner solves, where the vector arithmetic (the stencil
+// product q = K p, the updates and the per-tile inner products) runs in FP32
+// too.  The CG scalars (alpha, beta, rho) and the cross-tile sums of the
+// per-tile partials stay FP64.
 struct PCG3Args {
   int n;
   int64_t ld;
@@ -484,13 +489,13 @@ struct PCG3Args {
   int cols[kMaxCols];
   double c;
   double sm;
-  double* x;
+  void* x;
   int64_t ldx;
-  double* r;
-  const double* z;
-  const double* pin;
-  double* pout;
-  double* q;
+  void* r;
+  const void* z;
+  const void* pin;
+  void* pout;
+  void* q;
   const CGScal* prev;
   CGScal* next;
   double* part_rr;
@@ -502,6 +507,7 @@ struct PCG3Args {
   const double* tot;   // (r, r), (r, z), (p, q) per column (3 x kMaxCols), or null:
                        // each work-group then adds the per-tile partials itself
   const double* b[kMaxCols];
+  double rtol2[kMaxCols];   // set-up: squared relative tolerance per column
 };
 
 // Large grids: one work-group per column and quantity adds the per-tile
@@ -526,6 +532,52 @@ __global__ __launch_bounds__(kT) void pcg3_reduce_kernel(Reduce3Args a) {
   if (threadIdx.x == 0) a.out[q][col] = s;
 }
 
+// Work-group sum in the vector type (FP32 sums for the FP32 PCG).
+__device__ __forceinline__ float wave_sum_v(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_v(double v) { return wave_sum(v); }
+
+template <class V>
+__device__ __forceinline__ double block_sum_v(V v, V* red) {
+  v = wave_sum_v(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  V s = (V)0;
+#pragma unroll
+  for (int w = 0; w < kT / 64; ++w) s += red[w];
+  __syncthreads();
+  return (double)s;
+}
+
+// q = K p in the vector type: FP64 as in the V-cycle, or FP32 arithmetic.
+template <bool SH, class V>
+__device__ __forceinline__ V k7_vec(const V* s, int q, double c, double sm) {
+  if constexpr (sizeof(V) == 8) {
+    return k7<SH, RX, RY>(s, q, c, sm);
+  } else {
+    const float cf = (float)c;
+    float v = cf * (6.0f * s[q] - (s[q - 1] + s[q + 1]) - (s[q - RX] + s[q + RX]) -
+                    (s[q - RX * RY] + s[q + RX * RY]));
+    if (SH) {
+      float m = 0.0f;
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int o = q + dz * RX * RY + dy * RX;
+          const float w = (dz == 0 ? 4.0f : 1.0f) * (dy == 0 ? 4.0f : 1.0f);
+          m += w * ((s[o - 1] + s[o + 1]) + 4.0f * s[o]);
+        }
+      }
+      v += (float)sm * m;
+    }
+    return v;
+  }
+}
+
 #define STS_PCG3_PROLOGUE(A)                                                   \
   const int ntiles = (A).ntx * (A).nty * (A).ntz;                              \
   const int lin = xcd_remap(blockIdx.x, (A).nlaunch * ntiles);                 \
@@ -534,10 +586,11 @@ __global__ __launch_bounds__(kT) void pcg3_reduce_kernel(Reduce3Args a) {
   const Tile3 T = tile_of(t, (A).ntx, (A).nty, TX, TY, TZ);
 
 // A: stopping test and beta; p = z + beta p; q = K p; (p, q).
-template <bool SH>
+template <bool SH, class V>
 __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
-  __shared__ double ps[NR];
+  __shared__ V ps[NR];
   __shared__ double red[2][kT / 64];
+  __shared__ V redv[kT / 64];
   STS_PCG3_PROLOGUE(a)
   if (blockIdx.x == 0) {
     for (int c = threadIdx.x; c < a.ncols; c += kT) {
@@ -575,35 +628,38 @@ __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
   if (t == 0 && threadIdx.x == 0) a.next[col] = s;
   if (!go) return;
   const int n = a.n;
-  const double* zg = a.z + (size_t)col * a.ld;
-  const double* pin = a.pin + (size_t)col * a.ld;
+  const V* zg = static_cast<const V*>(a.z) + (size_t)col * a.ld;
+  const V* pin = static_cast<const V*>(a.pin) + (size_t)col * a.ld;
+  const V bv = (V)beta;
   for (int i = threadIdx.x; i < NR; i += kT) {
     const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
-    double v = 0.0;
+    V v = (V)0;
     if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
       const size_t g = ((size_t)gz * n + gy) * n + gx;
-      v = zg[g] + beta * pin[g];
+      v = zg[g] + bv * pin[g];
     }
     ps[i] = v;
   }
   __syncthreads();
-  double* pout = a.pout + (size_t)col * a.ld;
-  double* qg = a.q + (size_t)col * a.ld;
-  double part = 0.0;
+  V* pout = static_cast<V*>(a.pout) + (size_t)col * a.ld;
+  V* qg = static_cast<V*>(a.q) + (size_t)col * a.ld;
+  V part = (V)0;
   for_core(n, T, [&](size_t g, int q) {
-    const double pv = ps[q];
-    const double qv = k7<SH, RX, RY>(ps, q, a.c, a.sm);
+    const V pv = ps[q];
+    const V qv = k7_vec<SH, V>(ps, q, a.c, a.sm);
     pout[g] = pv;
     qg[g] = qv;
     part += pv * qv;
   });
-  part = block_sum<kT>(part, red[0]);
-  if (threadIdx.x == 0) a.part_pq[(size_t)col * a.max_tiles + t] = part;
+  const double tot = block_sum_v<V>(part, redv);
+  if (threadIdx.x == 0) a.part_pq[(size_t)col * a.max_tiles + t] = tot;
 }
 
 // B: alpha = rho / (p, q); x += alpha p; r -= alpha q; (r, r).
+template <class V>
 __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
   __shared__ double red[kT / 64];
+  __shared__ V redv[kT / 64];
   STS_PCG3_PROLOGUE(a)
   const CGScal s = a.next[col];
   if (!s.active) return;
@@ -619,51 +675,106 @@ __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
   const double alpha = ok ? s.rho / pq : 0.0;
   if (t == 0 && threadIdx.x == 0) a.alpha[col] = alpha;
   if (!ok) return;
-  double* xg = a.x + (size_t)col * a.ldx;
-  double* rg = a.r + (size_t)col * a.ld;
-  const double* pg = a.pout + (size_t)col * a.ld;
-  const double* qg = a.q + (size_t)col * a.ld;
-  double part = 0.0;
+  V* xg = static_cast<V*>(a.x) + (size_t)col * a.ldx;
+  V* rg = static_cast<V*>(a.r) + (size_t)col * a.ld;
+  const V* pg = static_cast<const V*>(a.pout) + (size_t)col * a.ld;
+  const V* qg = static_cast<const V*>(a.q) + (size_t)col * a.ld;
+  const V av = (V)alpha;
+  V part = (V)0;
   for_core(a.n, T, [&](size_t g, int) {
-    xg[g] += alpha * pg[g];
-    const double rv = rg[g] - alpha * qg[g];
+    xg[g] += av * pg[g];
+    const V rv = rg[g] - av * qg[g];
     rg[g] = rv;
     part += rv * rv;
   });
-  part = block_sum<kT>(part, red);
-  if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = part;
+  const double tot = block_sum_v<V>(part, redv);
+  if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = tot;
 }
 
-// Set-up: x = 0, r = b, both p buffers 0, partials of (b, b); both state
-// slots initialised (columns in the launch list active), alpha = 1.
-__global__ __launch_bounds__(kT) void pcg3_setup_kernel(PCG3Args a, double rtol2, int maxit) {
-  __shared__ double red[kT / 64];
+// Set-up: x = 0, r = b (rounded to V), both p buffers 0, partials of (r, r);
+// both state slots initialised (columns in the launch list active), alpha = 1.
+template <class V>
+__global__ __launch_bounds__(kT) void pcg3_setup_kernel(PCG3Args a, int maxit) {
+  __shared__ V redv[kT / 64];
   STS_PCG3_PROLOGUE(a)
   const double* bg = a.b[jb];
-  double* pa = const_cast<double*>(a.pin);
-  double part = 0.0;
+  V* xa = static_cast<V*>(a.x);
+  V* ra = static_cast<V*>(a.r);
+  V* pa = static_cast<V*>(const_cast<void*>(a.pin));
+  V* pb = static_cast<V*>(a.pout);
+  V part = (V)0;
   for_core(a.n, T, [&](size_t g, int) {
-    const double bv = bg[g];
-    a.x[g + (size_t)col * a.ldx] = 0.0;
-    a.r[g + (size_t)col * a.ld] = bv;
-    pa[g + (size_t)col * a.ld] = 0.0;
-    a.pout[g + (size_t)col * a.ld] = 0.0;
+    const V bv = (V)bg[g];
+    xa[g + (size_t)col * a.ldx] = (V)0;
+    ra[g + (size_t)col * a.ld] = bv;
+    pa[g + (size_t)col * a.ld] = (V)0;
+    pb[g + (size_t)col * a.ld] = (V)0;
     part += bv * bv;
   });
-  part = block_sum<kT>(part, red);
-  if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = part;
+  const double tot = block_sum_v<V>(part, redv);
+  if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = tot;
   if (blockIdx.x == 0 && threadIdx.x < kMaxCols) {
     const int c = threadIdx.x;
     bool launched = false;
     for (int j = 0; j < a.nlaunch; ++j) launched |= a.cols[j] == c;
     CGScal s{};
-    s.rtol2 = rtol2;
+    s.rtol2 = a.rtol2[c];
     s.maxit = maxit;
     s.active = launched ? 1 : 0;
     a.next[c] = s;
     const_cast<CGScal*>(a.prev)[c] = s;
     a.alpha[c] = 1.0;
   }
+}
+
+// Defect correction of the FP32 inner solves, in FP64: x += d (one
+// elementwise launch; the stencil launch after it reads x on halos that other
+// work-groups own, so x must not change under it), then r = b - (Kx + s Mx) x
+// and the per-tile partials of (r, r), for the columns of the launch slots
+// (own pointers per slot: x FP64, d FP32 or FP64, b and r FP64).
+struct Defect3Args {
+  int n;
+  int ntx, nty, ntz;
+  int nlaunch;
+  double c, sm;
+  double* x[kMaxCols];
+  const void* d[kMaxCols];   // null: x unchanged
+  const double* b[kMaxCols];
+  double* r[kMaxCols];
+  double* part;              // per-tile (r, r), slot stride max_tiles
+  int max_tiles;
+};
+
+template <class D>
+__global__ __launch_bounds__(kT) void add_corr3_kernel(Defect3Args a, int64_t nn) {
+  const int jb = blockIdx.y;
+  const D* d = static_cast<const D*>(a.d[jb]);
+  if (!d) return;
+  double* x = a.x[jb];
+  for (int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x; g < nn; g += (int64_t)gridDim.x * kT)
+    x[g] += (double)d[g];
+}
+
+template <bool SH>
+__global__ __launch_bounds__(kT) void defect3_kernel(Defect3Args a) {
+  __shared__ double us[NR];
+  __shared__ double red[kT / 64];
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int lin = xcd_remap(blockIdx.x, a.nlaunch * ntiles);
+  const int t = lin / a.nlaunch, jb = lin % a.nlaunch;
+  const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
+  load_halo(a.x[jb], a.n, T, us);
+  __syncthreads();
+  const double* bg = a.b[jb];
+  double* rg = a.r[jb];
+  double part = 0.0;
+  for_core(a.n, T, [&](size_t g, int q) {
+    const double rv = bg[g] - k7<SH, RX, RY>(us, q, a.c, a.sm);
+    rg[g] = rv;
+    part += rv * rv;
+  });
+  part = block_sum<kT>(part, red);
+  if (threadIdx.x == 0) a.part[(size_t)jb * a.max_tiles + t] = part;
 }
 
 int tiles3(int n, int sx, int sy, int sz) {
@@ -743,16 +854,17 @@ int mg3_max_tiles(const MGPlan& p) {
 
 double mg3_bytes_per_node(const MGPlan& p) {
   const double n0 = std::pow((double)p.n[0], 3);
-  double b = 80.0 * n0;   // PCG A and B
+  const bool all32 = p.f32cg && p.nlev > 0, f32 = (p.f32 || p.f32cg) && p.nlev > 0;
+  double b = (all32 ? 40.0 : 80.0) * n0;   // PCG A and B
   for (int l = 0; l < p.nlev; ++l) {
     const double nf = std::pow((double)p.n[l], 3), nc = std::pow((double)p.n[l + 1], 3);
-    const double sb = (p.f32 && l > 0) ? 4.0 : 8.0, ss = p.f32 ? 4.0 : 8.0;
+    const double sb = (f32 && (l > 0 || all32)) ? 4.0 : 8.0, ss = f32 ? 4.0 : 8.0;
     // pre: b -> xp, r; restrict: r -> b_c; post1: xp, b, e_c -> d0, u1;
     // post2: u1, b, d0 -> e
     b += (sb + 2.0 * ss) * nf + ss * (nf + nc) + ((sb + 3.0 * ss) * nf + ss * nc) +
          (2.0 * sb + 2.0 * ss) * nf;
   }
-  b += (p.f32 && p.nlev > 0 ? 24.0 : 48.0) * std::pow((double)p.exact, 3);
+  b += (f32 ? 24.0 : 48.0) * std::pow((double)p.exact, 3);
   return b / n0;
 }
 
@@ -834,7 +946,9 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
   const bool shifted = p.sw0 != 0.0;
   // the mixed-precision V-cycle needs a smoothed level: its finest vectors
   // (the PCG residual and preconditioned residual) stay FP64
-  const bool f32 = p.f32 && L > 0;
+  const bool f32 = (p.f32 || p.f32cg) && L > 0;
+  // the FP32 PCG: its residual and preconditioned residual are FP32 as well
+  const bool all32 = p.f32cg && L > 0;
   auto level = [&](int l) {
     Level3Args a{};
     a.nf = p.n[l];
@@ -861,7 +975,7 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
   };
   for (int l = 0; l < L; ++l) {
     if (!f32) level_down<double, double>(level(l), shifted, nlaunch, st);
-    else if (l == 0) level_down<double, float>(level(l), shifted, nlaunch, st);
+    else if (l == 0 && !all32) level_down<double, float>(level(l), shifted, nlaunch, st);
     else level_down<float, float>(level(l), shifted, nlaunch, st);
   }
   {
@@ -883,7 +997,7 @@ void mg3_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch
     Level3Args a = level(l);
     a.part = (partials && l == 0) ? w.part_rz : nullptr;
     if (!f32) level_up<double, double>(a, shifted, nlaunch, st);
-    else if (l == 0) level_up<double, float>(a, shifted, nlaunch, st);
+    else if (l == 0 && !all32) level_up<double, float>(a, shifted, nlaunch, st);
     else level_up<float, float>(a, shifted, nlaunch, st);
   }
 }
@@ -892,7 +1006,17 @@ void pcg3_setup(const MGWork& w, const double* const* b, const int* cols, int nl
                 double rtol, int maxit, hipStream_t st) {
   PCG3Args a = pcg3_args(w, 0, cols, nlaunch, ncols);
   for (int j = 0; j < nlaunch; ++j) a.b[j] = b[j];
-  pcg3_setup_kernel<<<a.ntx * a.nty * a.ntz * nlaunch, kT, 0, st>>>(a, rtol * rtol, maxit);
+  for (int c = 0; c < kMaxCols; ++c) {
+    const double rt = (w.col_rtol && c < ncols) ? w.col_rtol[c] : rtol;
+    a.rtol2[c] = rt * rt;
+  }
+  const dim3 grid(a.ntx * a.nty * a.ntz * nlaunch);
+  if (w.plan.f32cg)
+    launch(STS_K_PCG_B, 12.0 * std::pow((double)a.n, 3) * nlaunch, pcg3_setup_kernel<float>, grid,
+           dim3(kT), 0, st, a, maxit);
+  else
+    launch(STS_K_PCG_B, 40.0 * std::pow((double)a.n, 3) * nlaunch, pcg3_setup_kernel<double>,
+           grid, dim3(kT), 0, st, a, maxit);
   STS_HIP(hipGetLastError());
 }
 
@@ -920,10 +1044,18 @@ void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int
     STS_HIP(hipGetLastError());
     a.tot = w.tot;
   }
-  if (w.plan.sw0 != 0.0)
-    launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel<true>, dim3(blocks), dim3(kT), 0, st, a);
-  else
-    launch(STS_K_PCG_A, 32.0 * nn, pcg3_a_kernel<false>, dim3(blocks), dim3(kT), 0, st, a);
+  const double vb = w.plan.f32cg ? 4.0 : 8.0;   // bytes per vector element
+  if (w.plan.f32cg) {
+    if (w.plan.sw0 != 0.0)
+      launch(STS_K_PCG_A, 4.0 * vb * nn, pcg3_a_kernel<true, float>, dim3(blocks), dim3(kT), 0, st, a);
+    else
+      launch(STS_K_PCG_A, 4.0 * vb * nn, pcg3_a_kernel<false, float>, dim3(blocks), dim3(kT), 0, st, a);
+  } else {
+    if (w.plan.sw0 != 0.0)
+      launch(STS_K_PCG_A, 4.0 * vb * nn, pcg3_a_kernel<true, double>, dim3(blocks), dim3(kT), 0, st, a);
+    else
+      launch(STS_K_PCG_A, 4.0 * vb * nn, pcg3_a_kernel<false, double>, dim3(blocks), dim3(kT), 0, st, a);
+  }
   STS_HIP(hipGetLastError());
   if (split) {
     r.part[0] = w.part_pq;
@@ -933,7 +1065,58 @@ void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int
            dim3(kT), 0, st, r);
     STS_HIP(hipGetLastError());
   }
-  launch(STS_K_PCG_B, 48.0 * nn, pcg3_b_kernel, dim3(blocks), dim3(kT), 0, st, a);
+  if (w.plan.f32cg)
+    launch(STS_K_PCG_B, 6.0 * vb * nn, pcg3_b_kernel<float>, dim3(blocks), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_PCG_B, 6.0 * vb * nn, pcg3_b_kernel<double>, dim3(blocks), dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+}
+
+void mg3_defect(const MGWork& w, int ncols, double* const* x, const void* const* d, bool d32,
+                const double* const* b, double* const* r, double* norms2, hipStream_t st) {
+  Defect3Args a{};
+  a.n = w.plan.n[0];
+  a.ntx = (a.n + TX - 1) / TX;
+  a.nty = (a.n + TY - 1) / TY;
+  a.ntz = (a.n + TZ - 1) / TZ;
+  a.nlaunch = ncols;
+  bool any_d = false;
+  for (int j = 0; j < ncols; ++j) {
+    a.x[j] = x[j];
+    a.d[j] = d ? d[j] : nullptr;
+    a.b[j] = b[j];
+    a.r[j] = r[j];
+    any_d |= a.d[j] != nullptr;
+  }
+  a.c = w.plan.mu;
+  a.sm = w.plan.sw0;
+  a.part = w.part_rr;
+  a.max_tiles = w.max_tiles;
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int64_t nodes = (int64_t)a.n * a.n * a.n;
+  const double nn = (double)nodes * ncols;
+  if (any_d) {
+    const dim3 ag((unsigned)std::min<int64_t>((nodes + kT - 1) / kT, 4096), (unsigned)ncols);
+    if (d32)
+      launch(STS_K_STENCIL, 20.0 * nn, add_corr3_kernel<float>, ag, dim3(kT), 0, st, a, nodes);
+    else
+      launch(STS_K_STENCIL, 24.0 * nn, add_corr3_kernel<double>, ag, dim3(kT), 0, st, a, nodes);
+    STS_HIP(hipGetLastError());
+  }
+  const dim3 grid(ntiles * ncols);
+  if (a.sm != 0.0)
+    launch(STS_K_STENCIL, 24.0 * nn, defect3_kernel<true>, grid, dim3(kT), 0, st, a);
+  else
+    launch(STS_K_STENCIL, 24.0 * nn, defect3_kernel<false>, grid, dim3(kT), 0, st, a);
+  STS_HIP(hipGetLastError());
+  Reduce3Args rd{};
+  rd.max_tiles = w.max_tiles;
+  for (int j = 0; j < ncols; ++j) rd.cols[j] = j;
+  rd.part[0] = w.part_rr;
+  rd.count[0] = ntiles;
+  rd.out[0] = norms2;
+  launch(STS_K_PCG_REDUCE, 8.0 * ntiles * ncols, pcg3_reduce_kernel, dim3(ncols, 1), dim3(kT), 0,
+         st, rd);
   STS_HIP(hipGetLastError());
 }
 

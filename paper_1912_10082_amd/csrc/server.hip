@@ -188,7 +188,7 @@ int64_t sts_footprint(const sts_space* space, int64_t nt, int32_t p, const sts_o
     if (opts) o = *opts;
     else sts_default_opts(&o);
     STS_REQUIRE(o.max_outer >= 1, STS_E_INVALID, "sts_footprint: max_outer < 1");
-    out = problem_footprint(*space, nt, p, o.max_outer);
+    out = problem_footprint(*space, nt, p, o.max_outer, o.mixed != 0);
   });
   return s == STS_OK ? out : -1;
 }

@@ -544,6 +544,8 @@ struct ApplyArgs {
   int64_t ldx;
   double* Y;
   int64_t ldy;
+  double* Y2;     // non-null: Y = Kx X and Y2 = Mx X from one read of X (ops ignored)
+  int64_t ldy2;
   Coefs cf;
 };
 
@@ -580,6 +582,20 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
     xs[i] = v;
   }
   __syncthreads();
+  if (a.Y2) {
+    // both images of the column from the one LDS tile
+    double* y2 = a.Y2 + (size_t)c * a.ldy2;
+    for (int i = threadIdx.x; i < NI; i += kThreads) {
+      const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
+      const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
+      if (gx < nx && gy < ny && gz < nz) {
+        const size_t g = (size_t)gz * sxy + (size_t)gy * nx + gx;
+        yg[g] = apply_lds<Masks<DIM>::K, RX, RY>(a.cf.k, xs, ux + 1, uy + IY, uz + IZ);
+        y2[g] = apply_lds<Masks<DIM>::M, RX, RY>(a.cf.m, xs, ux + 1, uy + IY, uz + IZ);
+      }
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < NI; i += kThreads) {
     const int ux = i % T::X, uy = (i / T::X) % T::Y, uz = i / (T::X * T::Y);
     const int gx = x0 + ux, gy = y0 + uy, gz = z0 + uz;
@@ -710,6 +726,37 @@ void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int*
   }
   const int blocks = a.ntx * a.nty * a.ntz * ncols;
   const double by = 16.0 * (double)g.nh * ncols;
+  if (g.dim == 1) launch(STS_K_STENCIL, by, apply_kernel<1>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else if (g.dim == 2)
+    launch(STS_K_STENCIL, by, apply_kernel<2>, dim3(blocks), dim3(kThreads), 0, st, a);
+  else launch(STS_K_STENCIL, by, apply_kernel<3>, dim3(blocks), dim3(kThreads), 0, st, a);
+  STS_HIP(hipGetLastError());
+}
+
+void stencil_apply_km(const Grid& g, const Stencil& K, const Stencil& M, int ncols,
+                      const double* X, int64_t ldx, double* KX, int64_t ldk, double* MX,
+                      int64_t ldm, hipStream_t st) {
+  if (ncols <= 0) return;
+  STS_REQUIRE(ncols <= 16, STS_E_INVALID, "stencil_apply_km: at most 16 columns");
+  check_patterns(g, K, M);
+  ApplyArgs a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  tiles_any(g, a.ntx, a.nty, a.ntz);
+  a.ncols = ncols;
+  a.X = X;
+  a.ldx = ldx;
+  a.Y = KX;
+  a.ldy = ldk;
+  a.Y2 = MX;
+  a.ldy2 = ldm;
+  for (int i = 0; i < 27; ++i) {
+    a.cf.k[i] = K.c[i];
+    a.cf.m[i] = M.c[i];
+  }
+  const int blocks = a.ntx * a.nty * a.ntz * ncols;
+  const double by = 24.0 * (double)g.nh * ncols;
   if (g.dim == 1) launch(STS_K_STENCIL, by, apply_kernel<1>, dim3(blocks), dim3(kThreads), 0, st, a);
   else if (g.dim == 2)
     launch(STS_K_STENCIL, by, apply_kernel<2>, dim3(blocks), dim3(kThreads), 0, st, a);

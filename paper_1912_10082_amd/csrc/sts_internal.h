@@ -164,6 +164,10 @@ int cg_tiles(const Grid& g);
 // Y[:, c] = A_c X[:, c], A_c = ops[c] ? M : K (ncols <= 16)
 void stencil_apply(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
                    const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t st);
+// KX = Kx X and MX = Mx X (ncols <= 16 columns) from one read of X.
+void stencil_apply_km(const Grid& g, const Stencil& K, const Stencil& M, int ncols,
+                      const double* X, int64_t ldx, double* KX, int64_t ldk, double* MX,
+                      int64_t ldm, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // multigrid-preconditioned CG for the 2-D P1 and 3-D seven-point stiffness
@@ -186,6 +190,8 @@ struct MGPlan {
                              // 3-D (h/6)^3); 0: Kx alone
   int f32;                   // 3-D with nlev >= 1: the V-cycle stores its vectors in FP32
                              // (all but the finest right-hand side and result)
+  int f32cg;                 // 3-D with nlev >= 1: FP32 PCG -- x, r, z, p, q and every
+                             // V-cycle vector in FP32, FP32 vector arithmetic in the PCG
 };
 // The m x m sine-transform matrix (row-major) followed by the m eigenvalues
 // 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.
@@ -224,6 +230,7 @@ struct MGWork {
   const double* dst;             // device copy of mg_dst_table(plan.exact)
   double* t1;                    // coarsest-level temporaries above kMGCoarseMax
   double* t2;                    //   (stride ld[nlev], kMaxCols columns)
+  const double* col_rtol;        // host, per column (set-up), or null: the scalar rtol
 };
 // e[0][:, c] = B b[0][:, c] (one V-cycle) for the columns cols[0..nlaunch);
 // columns whose state in `act` (may be null) is inactive are skipped; with
@@ -245,6 +252,12 @@ void pcg3_setup(const MGWork& w, const double* const* b, const int* cols, int nl
                 double rtol, int maxit, hipStream_t st);
 void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int ncols,
                   hipStream_t st);
+// Defect correction of the 3-D FP32 inner solves, in FP64: for slot j <
+// ncols, x[j] += d[j] (FP32 if d32, else FP64; d or d[j] null: x[j]
+// unchanged), r[j] = b[j] - (Kx + s Mx) x[j] and norms2[j] = (r[j], r[j])
+// (device).  Every vector is one fine-grid column.  Uses w.part_rr.
+void mg3_defect(const MGWork& w, int ncols, double* const* x, const void* const* d, bool d32,
+                const double* const* b, double* const* r, double* norms2, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Mx solves by Chebyshev iteration (2-D P1 mass matrix)
@@ -282,6 +295,16 @@ void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
 // W (rows x n, ldw) -= A (rows x m, lda) C (m x n, ldc), n <= 16.
 void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const double* C,
                  int64_t ldc, double* W, int64_t ldw, hipStream_t st);
+
+// FP32 form for the coefficients of the first Gram-Schmidt pass of the
+// mixed-precision solve: C (m x n, FP64 storage) = A^T B with A FP32 and B
+// FP64 rounded to FP32, products and sums in FP32 (partial:
+// gemm_tn_partial_size(rows, m) floats or more).
+void gemm_tn32(int64_t rows, int m, int n, const float* A, int64_t lda, const double* B,
+               int64_t ldb, double* C, int64_t ldc, float* partial, hipStream_t st);
+// dst (FP32) = src (FP64) rounded, rows x ncols.
+void round_cols(int64_t rows, int ncols, const double* src, int64_t lds, float* dst, int64_t ldd,
+                hipStream_t st);
 
 // D (m x n, ldd) = alpha op(A) B + beta D, op(A) = A (m x kk) or A^T (A kk x m);
 // small/medium sizes.
@@ -349,12 +372,14 @@ struct OrthScratch {
   double* Rinv;   // 256
   CholInfo* info; // device
   CholInfo* host; // pinned host copy
-  int cgs_passes; // out: Gram-Schmidt passes made against V (2 or 3)
+  int cgs_passes; // out: FP64 Gram-Schmidt passes made against V (1 to 3)
+  int cgs32_passes;       // out: FP32 passes (0 or 1)
+  const float* V32 = nullptr;   // FP32 copy of V (same ld): the first pass in FP32
 };
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
                          int64_t ldw, int ncols, double defl, OrthScratch& s, int* idx,
-                         hipStream_t st);
+                         hipStream_t st, double* KW = nullptr);
 // W[:, 0:kept] = W[:, idx] * Rinv (kept x kept upper triangular), also for MW.
 void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, double* W,
                 double* MW, int64_t ldw, double* tmp, hipStream_t st);
@@ -463,7 +488,8 @@ double problem_cost(const sts_problem* P);
 // Device bytes a problem holds after sts_create and the first capacity an
 // sts_solve with this max_outer allocates (upper estimate); the basis then
 // grows with the space.
-int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer);
+int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_outer,
+                          bool mixed = false);
 // Extra device bytes of `cols` more basis columns.
 int64_t problem_growth_bytes(const sts_space& space, int64_t nt, int p, int64_t cols);
 // Called with the extra bytes before the problem's basis grows; may block

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "sts.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sts_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(sts_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_symbols_exported():
@@ -210,3 +210,38 @@ def test_adaptive_shift_host_rule_matches_oracle():
     assert sts.adaptive_shift([], [900.0], 1.0, 1000.0) == 1.0
     with pytest.raises(b.STSError):
         sts.adaptive_shift([1.0], [], 0.0, 1.0)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding passes by pointer has the header's size and
+    field offsets: a C program built with gcc from include/sts.h prints them,
+    so a field added on one side only (which would let the library write past
+    a Python-owned buffer) fails here."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    pairs = [("sts_space", b.Space), ("sts_bidiag", b.Bidiag), ("sts_opts", b.Opts),
+             ("sts_info", b.Info), ("sts_request", b.Request), ("sts_result", b.Result),
+             ("sts_server_stats", b.ServerStats)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sts.h"', 'int main(void) {']
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -73,9 +73,10 @@ def test_served_requests_equal_alone_and_oracle():
 
 def test_budget_admission_growth_and_refusal():
     """Admission by the starting footprint; a running request's basis then
-    grows in place, each step waiting for budget unless the request is the
-    oldest running one, so the peak stays within the budget plus one
-    request's growth."""
+    grows, each step waiting for budget (its growth and the transient of its
+    copy) unless the request is the oldest running one, so the peak stays
+    within the budget plus one request's growth and one transient (the old
+    copy of one of its three basis arrays: under a third of its footprint)."""
     mix = [wl.heat_2d_separable(n=63, nt=32, p=2, seed=s) for s in range(6)]
     opts = dict(tol=1e-9, max_outer=60)
     one = sts.footprint(2, 63, 32, 2, **opts)
@@ -92,7 +93,7 @@ def test_budget_admission_growth_and_refusal():
             server.release(t)
         st = server.stats()
         assert max(held) > one                        # the bases grew past the first capacity
-        assert one <= st["mem_peak"] <= budget + max(held) - one, (st, one, held)
+        assert one <= st["mem_peak"] <= budget + max(held) - one + max(held) // 3, (st, one, held)
         with pytest.raises(sts.STSError) as e:
             _submit(server, wl.heat_2d_separable(n=127, nt=32, p=2, seed=1), **opts)
         assert e.value.code == 2                      # STS_E_NOMEM: can never fit

@@ -249,8 +249,8 @@ def heat_1d_profiles(n: int = 1023, nt: int = 256, p: int = 2, seed: int = 5,
     return Workload(f"heat1d_prof_n{n}", 1, (n,), mu, T, nt, F1, F2, meta={"seed": seed})
 
 
-def serving_mix(count: int, seed: int = 5, frac_1d: float = 0.45, frac_2d: float = 0.45,
-                nx_1d=(1000, 8192), sides_2d=(63, 95, 127, 191, 255, 383, 511),
+def serving_mix(count: int, seed: int = 5, frac_1d: float = 0.5, frac_2d: float = 0.4,
+                nx_1d=(1000, 65536), sides_2d=(63, 95, 127, 191, 255, 383, 511),
                 sides_3d=(63, 95, 127), nt_range=(128, 2048)) -> list:
     """Request shapes of a serving workload: (dim, n, nt, p, mu, seed) tuples.
 
