@@ -475,6 +475,20 @@ sts_status sts_m_orthonormalize(const sts_space* space, const double* V, const d
 sts_status sts_gram(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 
+/* sts_gram for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * contraction C (m x n, ldc) = A^T B with the same kernels, its partial
+ * products kept in a device array built into the library (16 MiB, one copy
+ * per device, held until the process ends) instead of memory allocated per
+ * call.  Calls no hipMalloc / hipFree.  Asynchronous: the work is ordered on
+ * `stream` and C is ready when the stream reaches it.  Every call on a device
+ * uses that device's one array, so calls that overlap on a device (other
+ * streams, other host threads) race; nothing needs clearing between calls.
+ * Sizes and pointers as for sts_gram, and m <= 512.  Errors: STS_E_INVALID
+ * for sizes out of range (m > 512 included), STS_E_DEVICE if the array's
+ * device address cannot be obtained or a launch fails. */
+sts_status sts_gram_noalloc(int64_t rows, int32_t m, int32_t n, const double* A, int64_t lda,
+                            const double* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 
 /* The basis update of block Gram-Schmidt, W (rows x n, ldw) -= A (rows x m,
  * lda) C (m x n, ldc), n <= 16; FP64 matrix cores.  With A = V and C from

@@ -121,6 +121,7 @@ _SIGS = {
     "sts_m_orthonormalize": (C.c_int, [C.POINTER(Space), _P, _P, _I64, _I64, _P, _P, _I64, _I32,
                                        _F64, C.POINTER(_I32), C.POINTER(_I32), _P]),
     "sts_gram": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "sts_gram_noalloc": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_basis_update": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_gram_fp32": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_sym_eig": (C.c_int, [_I64, _P, _I64, _P, _P, _I64, _P]),
@@ -520,6 +521,17 @@ def gram(A, B):
     Cm = dev_empty(A.shape[1], B.shape[1])
     _check(load().sts_gram(A.shape[0], A.shape[1], B.shape[1], pa, lda, pb, ldb,
                            C.c_void_p(Cm.data_ptr()), A.shape[1], _stream_handle()))
+    return Cm
+
+
+def gram_noalloc(A, B, out=None):
+    """C = A^T B through sts_gram_noalloc (no device allocation inside the
+    call; `out`, an m x n column-major device tensor, receives C if given)."""
+    A, pa, lda = dev_colmajor(A)
+    B, pb, ldb = dev_colmajor(B)
+    Cm = dev_empty(A.shape[1], B.shape[1]) if out is None else out
+    _check(load().sts_gram_noalloc(A.shape[0], A.shape[1], B.shape[1], pa, lda, pb, ldb,
+                                   C.c_void_p(Cm.data_ptr()), A.shape[1], _stream_handle()))
     return Cm
 
 
