@@ -361,8 +361,13 @@ def bench_serve(args) -> int:
     opts = dict(tol=1e-8, max_outer=100)
 
     def req_opts(w):
-        # relaxed inner solves (sts_opts.inner_relax): j = 2 in 3-D, 1 otherwise
-        return dict(opts, inner_relax=2 if w.dim == 3 else 1)
+        # relaxed inner solves (sts_opts.inner_relax): j = 2 in 3-D, 1 otherwise;
+        # with --serve-mixed, FP32 bulk with FP64 refinement where it applies
+        # (3-D grids with n > 63)
+        o = dict(opts, inner_relax=2 if w.dim == 3 else 1)
+        if args.serve_mixed:
+            o["mixed"] = 1
+        return o
 
     budget = 200 << 30
     sample = set(range(0, len(reqs), 20))
@@ -460,7 +465,8 @@ def bench_serve(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "serve_mix_50_40_10", "rate_per_s": args.serve_rate,
                    "window_s": args.serve_seconds, "workers": args.serve_workers,
-                   "mem_budget_bytes": budget, "tol": opts["tol"]},
+                   "mem_budget_bytes": budget, "tol": opts["tol"],
+                   "mixed": bool(args.serve_mixed)},
         "latency_ms": {"p50": 1e3 * pct(lat, 0.5), "p99": 1e3 * pct(lat, 0.99)},
         "queued_ms": {"p50": 1e3 * pct(qd, 0.5), "p99": 1e3 * pct(qd, 0.99)},
         "latency_p50_ms_by_dim": {str(d): 1e3 * sorted(v)[len(v) // 2] for d, v in by_dim.items()},
@@ -504,6 +510,10 @@ def main() -> int:
                     help="heat3d: FP32 bulk with FP64 refinement (sts_opts.mixed): FP32 multigrid "
                          "PCG inside FP64 defect correction for the Kx solves and an FP32 first "
                          "Gram-Schmidt pass; reduced solve and exact residual FP64")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="heat3d (FP64 run): timed solves of the same problem with sts_opts.mixed, "
+                         "reported as mixed_precision with their error against the FP64 run "
+                         "(0 = skip)")
     ap.add_argument("--precond-fp32", action="store_true",
                     help="heat3d: multigrid V-cycle vectors in FP32 inside FP64 CG "
                          "(sts_opts.precond_fp32); the default run is FP64 throughout")
@@ -511,6 +521,9 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-mixed", action="store_true",
+                    help="serve: FP32 bulk with FP64 refinement (sts_opts.mixed) for the requests "
+                         "it applies to")
     ap.add_argument("--calibrate-copy", type=int, metavar="MIB", default=0,
                     help="only run a plain MIB-MiB device copy (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=5,
@@ -659,13 +672,42 @@ def main() -> int:
                 rsec = ksum["gram_reduce"][0]
                 roofline["frac_with_reduce"] = round(by / (sec + rsec) / 1e9 / HBM_PEAK_GBS, 4)
     gate = last["status"] == "STS_OK" and last["res_true"] <= args.tol
-    V, Y = prob.factors(device=True)
+    S = min(args.sample_steps, w.nt - 1)
+    U_gate = None if args.no_cpu_baseline else prob.solution_columns(list(range(S)))
+    mixed = None
+    if d3 and not args.mixed and args.mixed_steps > 0:
+        cols = sorted(set(int(round(x)) for x in np.linspace(0, w.nt - 1, 64)))
+        Uf = prob.solution_columns(cols, device=True)
+        # the same problem with FP32 bulk work and FP64 refinement
+        # (sts_opts.mixed), gated at relative error 1e-8 against this FP64 run
+        # on sampled time columns
+        mopts = dict(opts, mixed=1)
+        minfo = prob.solve(**mopts)   # first mixed solve: the FP32 copy of V is allocated
+        torch.cuda.synchronize()
+        mlat = []
+        for i in range(args.mixed_steps):
+            t0 = time.perf_counter()
+            minfo = prob.solve(**mopts)
+            torch.cuda.synchronize()
+            mlat.append(time.perf_counter() - t0)
+        _log(f"mixed: {minfo['status']} outer={minfo['outer_its']} k={minfo['k']} "
+             f"res_true={minfo['res_true']:.2e} {[round(x, 3) for x in mlat]} s")
+        Um = prob.solution_columns(cols, device=True)
+        merr = float(torch.linalg.norm(Um - Uf) / torch.linalg.norm(Uf))
+        mt = sum(mlat) / len(mlat)
+        mixed = {"dtype": "f32+f64_refine", "value": w.nh * w.nt / mt, "unit": "dof/s",
+                 "ms_per_step": 1e3 * mt, "steps": len(mlat),
+                 "rel_error_vs_fp64_run": merr, "error_columns": len(cols),
+                 "res_true": minfo["res_true"], "outer_its": minfo["outer_its"], "k": minfo["k"],
+                 "inner_its_K": minfo["inner_its_K"], "inner_its_fp32": minfo["inner_its_fp32"],
+                 "defect_rounds": minfo["defect_rounds"],
+                 "gate_passed": bool(minfo["status"] == "STS_OK" and minfo["res_true"] <= args.tol
+                                     and merr <= 1e-8)}
+        del Um, Uf
     cpu = None
     err = None
     if not args.no_cpu_baseline:
-        S = min(args.sample_steps, w.nt - 1)
-        U_cols = (V @ Y[:, :S]).cpu().numpy()
-        per_step, setup, err, total_s = cpu_baseline(w, U_cols, S)
+        per_step, setup, err, total_s = cpu_baseline(w, U_gate, S)
         gate = gate and err <= 1e-8
         if d3:
             sample = (f"first {S + 1} of {w.nt} time steps of the same {w.n[0]}^3 x {w.nt} problem "
@@ -713,6 +755,7 @@ def main() -> int:
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "mixed_precision": mixed,
     }
     print(json.dumps(out), flush=True)
     prob.close()

@@ -171,7 +171,8 @@ typedef struct {
   int64_t cg_poll_restarts; /* times a polled CG state was stale and iterations resumed */
   double res_floor;         /* estimated rounding floor of the exact residual in FP64 (see
                                sts_solve), or -1 where it was not needed */
-  int32_t floor_limited;    /* 1 = accepted with res_true above tol but within res_floor of it */
+  int32_t floor_limited;    /* 1 = accepted with res_true above tol, within the rounding floor
+                               (sts_solve) */
   int32_t pad_;
   int64_t inner_its_fp32;   /* FP32 PCG iterations of the mixed-precision Kx solves (included
                                in inner_its_K) */
@@ -253,7 +254,11 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
  * exact solution has a smaller residual).  When the projected residual meets
  * tol but the exact one does not, the library estimates that floor
  * (info->res_floor); if it is at least tol / 2 and the exact residual lies
- * within tol + floor, the solve is accepted (info->floor_limited = 1).
+ * within tol + floor, the solve is accepted (info->floor_limited = 1).  Where
+ * the floor is at least tol / 2 the inner solves carry the same rounding, and
+ * the projected residual itself can stall above tol: a solve whose projected
+ * residual has not halved over three checks is accepted with an exact
+ * residual within tol + 4 floor (floor_limited = 1), else it continues.
  *
  * Returns STS_OK; STS_E_NOT_CONVERGED when max_outer blocks did not reach tol
  * (the factors of the last iterate are kept and fetchable); STS_E_NUMERIC on a
@@ -274,6 +279,15 @@ sts_status sts_rank(const sts_problem* prob, int64_t* k);
  * `mem` says whether the buffers are host or device memory.  The library
  * keeps its copies.  STS_E_STATE before a successful or not-converged solve.
  * Synchronous. */
+/* Columns of the low-rank solution U ~= V Y of Sec. 4 at chosen time steps
+ * without copying V: U[:, j] = V Y[:, cols[j]] for j < ncols, computed on the
+ * device (the nodal values at time t^{cols[j] + 1}).  cols (host, ncols >= 1
+ * entries in 0..nt-1); U (Nh x ncols, ldu >= Nh) in host or device memory as
+ * `mem` says.  STS_E_STATE before a solve, STS_E_INVALID for bad indices or
+ * buffers.  Synchronous. */
+sts_status sts_solution_columns(const sts_problem* prob, const int64_t* cols, int32_t ncols,
+                                double* U, int64_t ldu, int32_t mem, void* stream);
+
 sts_status sts_get_factors(const sts_problem* prob, double* V, int64_t ldv, double* Y,
                            int64_t ldy, int32_t mem, void* stream);
 

@@ -121,6 +121,7 @@ _SIGS = {
     "sts_m_orthonormalize": (C.c_int, [C.POINTER(Space), _P, _P, _I64, _I64, _P, _P, _I64, _I32,
                                        _F64, C.POINTER(_I32), C.POINTER(_I32), _P]),
     "sts_gram": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "sts_solution_columns": (C.c_int, [_P, C.POINTER(_I64), _I32, _P, _I64, _I32, _P]),
     "sts_gram_noalloc": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_basis_update": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
     "sts_gram_fp32": (C.c_int, [_I64, _I32, _I32, _P, _I64, _P, _I64, _P, _I64, _P]),
@@ -341,6 +342,21 @@ class Problem:
                                          C.c_void_p(Y.ctypes.data), max(k, 1), STS_MEM_HOST,
                                          self._stream))
         return V, Y
+
+    def solution_columns(self, cols, device: bool = False):
+        """U[:, cols] of U = V Y (time indices 0..nt-1), computed on the device
+        without copying V; a NumPy array, or a CUDA tensor if device=True."""
+        idx = (C.c_int64 * len(cols))(*[int(c) for c in cols])
+        n = len(cols)
+        if device:
+            U = dev_empty(self.nh, n)
+            _check(self._lib.sts_solution_columns(self._h, idx, n, C.c_void_p(U.data_ptr()),
+                                                  max(self.nh, 1), STS_MEM_DEVICE, self._stream))
+            return U
+        U = np.zeros((self.nh, n), order="F")
+        _check(self._lib.sts_solution_columns(self._h, idx, n, C.c_void_p(U.ctypes.data),
+                                              max(self.nh, 1), STS_MEM_HOST, self._stream))
+        return U
 
     def true_residual(self) -> float:
         r = C.c_double()

@@ -231,6 +231,39 @@ __global__ __launch_bounds__(64 * NW) void gemm_tn32_kernel(int64_t rows, int m,
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   int64_t r = rb;
+  if (VEC) {
+    // 32 rows per step: lane group g feeds rows r + 8 g .. r + 8 g + 7 (two
+    // 16-byte loads of A per tile, as many bytes in flight as the FP64
+    // kernel's 16-row step) to eight MFMAs
+    for (; r + 32 <= re; r += 32) {
+      const int64_t rr = r + 8 * g;
+      float av[T][8], bv[8];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double2 b2 = bok ? *(const double2*)(Bp + rr + 2 * h) : double2{0.0, 0.0};
+        bv[2 * h] = (float)b2.x;
+        bv[2 * h + 1] = (float)b2.y;
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float4 a0 = aok[t] ? *(const float4*)(Ap[t] + rr) : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        const float4 a1 =
+            aok[t] ? *(const float4*)(Ap[t] + rr + 4) : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        av[t][0] = a0.x;
+        av[t][1] = a0.y;
+        av[t][2] = a0.z;
+        av[t][3] = a0.w;
+        av[t][4] = a1.x;
+        av[t][5] = a1.y;
+        av[t][6] = a1.z;
+        av[t][7] = a1.w;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = mfma32(av[t][s], bv[s], acc[t]);
+    }
+  }
   for (; r + 16 <= re; r += 16) {
     const int64_t rr = r + 4 * g;
     float av[T][4], bv[4];
@@ -321,6 +354,164 @@ __global__ void round_cols_kernel(int64_t rows, int ncols, const double* src, in
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
          r += (int64_t)gridDim.x * blockDim.x)
       dst[r + (int64_t)c * ldd] = (float)src[r + (int64_t)c * lds];
+}
+
+// The contraction with up to 32 columns of B in up to three segments (each
+// with its own pointer, common ldb): NB 16-column tiles of B per wave, the
+// work split of gemm_tn_kernel.  The Gram-Schmidt pass that re-orthogonalises
+// a new block contracts the basis with the block and, in the same read, with
+// the Kx / Mx images of the previous block (its reduced-matrix columns).
+struct TnSegs {
+  const double* B[3];
+  int end[3];   // cumulative column counts: segment s holds columns [end[s-1], end[s])
+};
+
+__device__ __forceinline__ const double* seg_col(const TnSegs& s, int j, int64_t ldb) {
+  const int g = j < s.end[0] ? 0 : (j < s.end[1] ? 1 : 2);
+  const int j0 = g == 0 ? 0 : s.end[g - 1];
+  return s.B[g] + (int64_t)(j - j0) * ldb;
+}
+
+template <int T, int NW, int NB, bool VEC>
+__global__ __launch_bounds__(64 * NW) void gemm_tnw_kernel(int64_t rows, int m, int n,
+                                                           const double* A, int64_t lda,
+                                                           TnSegs segs, int64_t ldb,
+                                                           double* partial, int m16, int rpw) {
+  __shared__ double red[NW - 1][T][NB][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int c0 = blockIdx.x * 16 * T;
+  const int64_t chunk = blockIdx.y;
+  const int64_t rb = (chunk * NW + wv) * (int64_t)rpw;
+  const int64_t re = min(rb + rpw, rows);
+  const double* Ap[T];
+  bool aok[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int col = c0 + 16 * t + i;
+    aok[t] = col < m;
+    Ap[t] = A + (int64_t)(aok[t] ? col : 0) * lda;
+  }
+  const double* Bp[NB];
+  bool bok[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int j = 16 * u + i;
+    bok[u] = j < n;
+    Bp[u] = seg_col(segs, bok[u] ? j : 0, ldb);
+  }
+  d4 acc[T][NB];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int u = 0; u < NB; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+  int64_t r = rb;
+  for (; r + 16 <= re; r += 16) {
+    const int64_t rr = r + 4 * g;
+    double av[T][4], bv[NB][4];
+    if (VEC) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const double2 b0 = bok[u] ? *(const double2*)(Bp[u] + rr) : double2{0.0, 0.0};
+        const double2 b1 = bok[u] ? *(const double2*)(Bp[u] + rr + 2) : double2{0.0, 0.0};
+        bv[u][0] = b0.x;
+        bv[u][1] = b0.y;
+        bv[u][2] = b1.x;
+        bv[u][3] = b1.y;
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const double2 a0 = aok[t] ? *(const double2*)(Ap[t] + rr) : double2{0.0, 0.0};
+        const double2 a1 = aok[t] ? *(const double2*)(Ap[t] + rr + 2) : double2{0.0, 0.0};
+        av[t][0] = a0.x;
+        av[t][1] = a0.y;
+        av[t][2] = a1.x;
+        av[t][3] = a1.y;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) bv[u][s] = bok[u] ? Bp[u][rr + s] : 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) av[t][s] = aok[t] ? Ap[t][rr + s] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[t][u] = mfma(av[t][s], bv[u][s], acc[t][u]);
+  }
+  if (r < re) {   // ragged end of the wave's rows
+    const int64_t rr = r + 4 * g;
+    double av[T][4], bv[NB][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool ok = rr + s < re;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) bv[u][s] = (ok && bok[u]) ? Bp[u][rr + s] : 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) av[t][s] = (ok && aok[t]) ? Ap[t][rr + s] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[t][u] = mfma(av[t][s], bv[u][s], acc[t][u]);
+  }
+  // element q of a lane's accumulator is (tile row 4 q + g, column i)
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wv - 1][t][u][(4 * q + g) * 16 + i] = acc[t][u][q];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    if (c0 + 16 * t >= m16) break;
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = (4 * q + g) * 16 + i;
+        double v = acc[t][u][q];
+#pragma unroll
+        for (int w = 0; w < NW - 1; ++w) v += red[w][t][u][e];
+        partial[(chunk * m16 + c0 + 16 * t + 4 * q + g) * (16 * NB) + 16 * u + i] = v;
+      }
+  }
+}
+
+struct TnOut {
+  double* C[3];
+  int64_t ldc[3];
+  int end[3];
+};
+
+// One wave per output element, chunks summed in a fixed order; column j goes
+// to the output segment that holds it.
+__global__ __launch_bounds__(256) void gemm_tnw_reduce(int m, int n, int64_t nchunks, int m16,
+                                                       int width, const double* partial,
+                                                       TnOut out) {
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (idx >= m * n) return;
+  const int i = idx % m, j = idx / m;
+  double s = 0.0;
+  for (int64_t c = lane; c < nchunks; c += 64) s += partial[(c * m16 + i) * width + j];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int g = j < out.end[0] ? 0 : (j < out.end[1] ? 1 : 2);
+    const int j0 = g == 0 ? 0 : out.end[g - 1];
+    out.C[g][i + (int64_t)(j - j0) * out.ldc[g]] = s;
+  }
 }
 
 // W (rows x n) -= A (rows x m) C (m x n); each wave owns 16 rows.
@@ -775,6 +966,68 @@ void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const dou
   gemm_tn2(rows, m, n, 0, A, lda, B, B, ldb, C, C, ldc, partial, st);
 }
 
+int64_t gemm_tn_partial_size_wide(int64_t rows, int m) {
+  return 2 * gemm_tn_partial_size(rows, m);
+}
+
+template <int T, int NW, int NB>
+static void launch_tnw(bool vec, const TnPlan& p, int64_t rows, int m, int n, const double* A,
+                       int64_t lda, const TnSegs& sg, int64_t ldb, double* partial, int m16,
+                       hipStream_t st) {
+  const dim3 grid((unsigned)p.groups, (unsigned)p.nch);
+  const double bytes = 8.0 * (double)rows * (m + n);
+  if (vec)
+    launch(STS_K_GRAM, bytes, gemm_tnw_kernel<T, NW, NB, true>, grid, dim3(64 * NW), 0, st, rows,
+           m, n, A, lda, sg, ldb, partial, m16, p.rpw);
+  else
+    launch(STS_K_GRAM, bytes, gemm_tnw_kernel<T, NW, NB, false>, grid, dim3(64 * NW), 0, st, rows,
+           m, n, A, lda, sg, ldb, partial, m16, p.rpw);
+}
+
+void gemm_tn_segs(int64_t rows, int m, const double* A, int64_t lda, int nseg,
+                  const double* const* B, const int* nb, int64_t ldb, double* const* C,
+                  const int64_t* ldc, double* partial, hipStream_t st) {
+  STS_REQUIRE(nseg >= 1 && nseg <= 3, STS_E_INVALID, "gemm_tn_segs: 1..3 segments");
+  TnSegs sg{};
+  TnOut out{};
+  int n = 0;
+  bool vec = aligned16(A) && lda % 2 == 0 && ldb % 2 == 0;
+  for (int s = 0; s < 3; ++s) {
+    const int w = s < nseg ? nb[s] : 0;
+    STS_REQUIRE(w >= 0, STS_E_INVALID, "gemm_tn_segs: negative width");
+    n += w;
+    sg.B[s] = s < nseg ? B[s] : B[0];
+    sg.end[s] = n;
+    out.C[s] = s < nseg ? C[s] : C[0];
+    out.ldc[s] = s < nseg ? ldc[s] : ldc[0];
+    out.end[s] = n;
+    if (s < nseg && w > 0) vec = vec && aligned16(B[s]);
+  }
+  if (m <= 0 || n <= 0) return;
+  STS_REQUIRE(n <= 32, STS_E_INVALID, "gemm_tn_segs: more than 32 columns");
+  const int NB = n > 16 ? 2 : 1;
+  const int width = 16 * NB;
+  const int m16 = ((m + 15) / 16) * 16;
+  const TnPlan p = tn_plan(rows, m);
+  if (rows <= 0) {
+    fill_kernel<<<1, 256, 0, st>>>(partial, (int64_t)m16 * width, 0.0);
+  } else if (NB == 2) {
+    if (p.T == 4) launch_tnw<4, 4, 2>(vec, p, rows, m, n, A, lda, sg, ldb, partial, m16, st);
+    else if (p.T == 2) launch_tnw<2, 4, 2>(vec, p, rows, m, n, A, lda, sg, ldb, partial, m16, st);
+    else launch_tnw<1, 16, 2>(vec, p, rows, m, n, A, lda, sg, ldb, partial, m16, st);
+  } else {
+    if (p.T == 4) launch_tnw<4, 4, 1>(vec, p, rows, m, n, A, lda, sg, ldb, partial, m16, st);
+    else if (p.T == 2) launch_tnw<2, 4, 1>(vec, p, rows, m, n, A, lda, sg, ldb, partial, m16, st);
+    else launch_tnw<1, 16, 1>(vec, p, rows, m, n, A, lda, sg, ldb, partial, m16, st);
+  }
+  STS_HIP(hipGetLastError());
+  const int64_t nch = rows <= 0 ? 1 : p.nch;
+  launch(STS_K_GRAM_REDUCE, 8.0 * ((double)nch * m16 * width + (double)m * n), gemm_tnw_reduce,
+         dim3((m * n + 3) / 4), dim3(256), 0, st, m, n, nch, m16, width, (const double*)partial,
+         out);
+  STS_HIP(hipGetLastError());
+}
+
 void gemm_nn_sub(int64_t rows, int m, int n, const double* A, int64_t lda, const double* C,
                  int64_t ldc, double* W, int64_t ldw, hipStream_t st) {
   if (m <= 0 || n <= 0 || rows <= 0) return;
@@ -879,6 +1132,12 @@ void copy_cols(int64_t rows, int ncols, const double* src, int64_t lds, double* 
   const dim3 grid((unsigned)std::min<int64_t>((rows + 255) / 256, 8192),
                   (unsigned)std::min(ncols, 1024));
   copy_cols_kernel<<<grid, 256, 0, st>>>(rows, ncols, src, lds, dst, ldd);
+  STS_HIP(hipGetLastError());
+}
+
+void scale(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  scale_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
   STS_HIP(hipGetLastError());
 }
 

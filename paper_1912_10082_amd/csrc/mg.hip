@@ -522,7 +522,10 @@ __global__ __launch_bounds__(L) void fst_col_kernel(FstArgs a) {
   if (a.st && !a.st[col].active) return;
   const int m = a.m;
   for (int i = threadIdx.x; i < 2 * L; i += L) tw[i] = a.tw[i];
-  const int c1 = 2 * blockIdx.x, c2 = c1 + 1;
+  // a work-group reads 16 bytes of each row; the eight groups that share a
+  // 128-byte line run on one XCD (consecutive block ids go round-robin over
+  // the XCDs), so the line is fetched into one L2 instead of eight
+  const int c1 = 2 * xcd_remap(blockIdx.x, gridDim.x), c2 = c1 + 1;
   const double* in = a.in + (size_t)col * a.in_ld;
   double* out = a.out + (size_t)col * a.out_ld;
   fst_load<L>(z, m, [&](int j) {

@@ -286,6 +286,14 @@ void gemm_tn(int64_t rows, int m, int n, const double* A, int64_t lda, const dou
              int64_t ldb, double* C, int64_t ldc, double* partial, hipStream_t st);
 int64_t gemm_tn_partial_size(int64_t rows, int m);
 
+// C_s (m x nb[s], ldc[s]) = A^T B_s for up to three column segments B_s (rows
+// x nb[s], common ldb), 32 columns in all, in one pass over A (partial:
+// gemm_tn_partial_size_wide(rows, m) doubles).
+int64_t gemm_tn_partial_size_wide(int64_t rows, int m);
+void gemm_tn_segs(int64_t rows, int m, const double* A, int64_t lda, int nseg,
+                  const double* const* B, const int* nb, int64_t ldb, double* const* C,
+                  const int64_t* ldc, double* partial, hipStream_t st);
+
 // [C1 C2] = A^T [B1 B2]: B1 rows x n1, B2 rows x n2 (common ldb), n1 + n2 <= 16;
 // C1 (m x n1) and C2 (m x n2) share ldc.  One pass over A.
 void gemm_tn2(int64_t rows, int m, int n1, int n2, const double* A, int64_t lda,
@@ -375,6 +383,15 @@ struct OrthScratch {
   int cgs_passes; // out: FP64 Gram-Schmidt passes made against V (1 to 3)
   int cgs32_passes;       // out: FP32 passes (0 or 1)
   const float* V32 = nullptr;   // FP32 copy of V (same ld): the first pass in FP32
+  // reduced-matrix columns of the previous block, formed in the second pass:
+  // pend_Kout / pend_Mout (ld pend_ldc) = V^T pend_K / pend_M (pend_n columns)
+  int pend_n = 0;
+  const double* pend_K = nullptr;
+  const double* pend_M = nullptr;
+  double* pend_Kout = nullptr;
+  double* pend_Mout = nullptr;
+  int64_t pend_ldc = 0;
+  bool pend_done = false;   // out: the pass formed them
 };
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
@@ -445,6 +462,8 @@ void mirror(int m, int n, const double* src, int64_t lds, double* dst, int64_t l
 void copy_cols(int64_t rows, int ncols, const double* src, int64_t lds, double* dst, int64_t ldd,
                hipStream_t st);
 void fill(double* p, int64_t n, double v, hipStream_t st);
+// p[0..n) *= v (v = 0 stores zeros).
+void scale(double* p, int64_t n, double v, hipStream_t st);
 // sum of squares of a column-major block (deterministic), result to *out.
 void sumsq(int64_t rows, int ncols, const double* A, int64_t lda, double* out, double* partial,
            unsigned* counter, hipStream_t st);

@@ -442,18 +442,21 @@ def test_false_breakdown_is_reported_not_converged():
     prob.close()
 
 
-@pytest.mark.parametrize("n,nt,p", [(16383, 256, 2), (32767, 512, 3), (65535, 256, 2)])
-def test_1d_large_grids_reach_the_error_gate(n, nt, p):
+@pytest.mark.parametrize("n,nt,p,mu", [(16383, 256, 2, 1.0), (32767, 512, 3, 1.0),
+                                       (65535, 256, 2, 1.0), (29139, 225, 3, 0.2),
+                                       (49899, 465, 3, 4.0), (62032, 217, 4, 1.7)])
+def test_1d_large_grids_reach_the_error_gate(n, nt, p, mu):
     """1-D grids whose exact residual cannot be evaluated below ~1e-8 in FP64
     (the residual of the rounded exact solution grows like u kappa(Mx^{-1} Kx),
-    1.5e-7 at 65535 nodes): the solve converges on the projected residual,
-    accepts an exact residual within the reported rounding floor, and the
-    error against the oracle's sine-mode solution meets 1e-8."""
-    w = wl.heat_1d_profiles(n=n, nt=nt, p=p, seed=60 + p)
-    prob, info, V, Y = _solve(w, tol=1e-8, inner_relax=1)
+    1.5e-7 at 65535 nodes): the solve converges on the projected residual, or
+    stalls with it at the floor, accepts an exact residual within the
+    reported floor (4 floors after a stall), and the error against the
+    oracle's sine-mode solution meets 1e-8."""
+    w = wl.heat_1d_profiles(n=n, nt=nt, p=p, seed=60 + p, mu=mu)
+    prob, info, V, Y = _solve(w, tol=1e-8, inner_relax=1, max_outer=100)
     assert info["status"] == "STS_OK", info
     assert info["res_true"] <= 1e-8 or (info["floor_limited"] == 1 and
-                                        info["res_true"] <= 1e-8 + info["res_floor"]), info
+                                        info["res_true"] <= 1e-8 + 4 * info["res_floor"]), info
     Dt, Mt = fem.time_matrices(wl.time_grid(nt, w.T))
     U = exact.modal_solve_1d_fast(n, w.mu, Dt, Mt, w.F1, w.F2)
     assert rel(V @ Y, U) <= 1e-8, rel(V @ Y, U)
@@ -511,3 +514,21 @@ def test_rational_krylov_solve_matches_crank_nicolson(dim, n, nt, p):
     assert info["k"] < info2["k"], (info["k"], info2["k"])
     prob.close()
     prob2.close()
+
+
+def test_solution_columns_match_the_factors():
+    """sts_solution_columns (U = V Y at chosen time steps, on the device) equals
+    V @ Y[:, cols] from the fetched factors: more than one group of 16
+    columns, repeated and unsorted indices, host and device outputs."""
+    w = wl.heat_2d_bumps(n=47, nt=40, p=2, seed=33)
+    prob, info, V, Y = _solve(w, tol=1e-10)
+    assert info["status"] == "STS_OK"
+    cols = [39, 0, 5, 5, 17] + list(range(20, 36))
+    want = V @ Y[:, cols]
+    got_h = prob.solution_columns(cols)
+    got_d = host(prob.solution_columns(cols, device=True))
+    np.testing.assert_allclose(got_h, want, rtol=0, atol=1e-13 * np.abs(want).max())
+    assert np.array_equal(got_h, got_d)
+    with pytest.raises(sts.STSError):
+        prob.solution_columns([40])
+    prob.close()
