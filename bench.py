@@ -448,9 +448,12 @@ def bench_serve(args) -> int:
             Dt, Mt = fem.time_matrices(wl.time_grid(w.nt, w.T))
             U = exact.crank_nicolson(K, M, Dt, Mt, w.F1, w.F2)
             errs.append(float(np.linalg.norm(V @ Y - U) / np.linalg.norm(U)))
-    by_dim = {}
+    by_dim, svc_dim = {}, {}
     for (w, _, _), r in zip(reqs, results):
         by_dim.setdefault(w.dim, []).append(r["latency_seconds"])
+        # admission to factors ready: the request's own time on the GPU, shared
+        # with whatever ran beside it
+        svc_dim.setdefault(w.dim, []).append(r["latency_seconds"] - r["queued_seconds"])
     dof = sum(w.nh * w.nt for (w, _, _), k in zip(reqs, ok) if k)
     failed = {}
     for (w, _, _), r in zip(reqs, results):
@@ -470,6 +473,9 @@ def bench_serve(args) -> int:
         "latency_ms": {"p50": 1e3 * pct(lat, 0.5), "p99": 1e3 * pct(lat, 0.99)},
         "queued_ms": {"p50": 1e3 * pct(qd, 0.5), "p99": 1e3 * pct(qd, 0.99)},
         "latency_p50_ms_by_dim": {str(d): 1e3 * sorted(v)[len(v) // 2] for d, v in by_dim.items()},
+        "service_ms_by_dim": {str(d): {"mean": 1e3 * sum(v) / len(v), "p50": 1e3 * sorted(v)[len(v) // 2],
+                                       "sum_s": sum(v), "count": len(v)}
+                              for d, v in svc_dim.items()},
         "requests": len(reqs), "completed_ok": sum(ok), "wall_s": wall,
         "space_time_dof_per_s": dof / wall,
         "mem_peak_bytes": stats["mem_peak"],

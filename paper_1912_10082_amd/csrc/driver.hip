@@ -593,16 +593,27 @@ struct MGRunner {
     return b / n0;
   }
 
-  // K x_c = b_c for c < ncols, x_c at x + c * ldx.
+  // K x_c = b_c for c < ncols, x_c at x + c * ldx.  With replace_every > 0
+  // (the FP32 PCG with x in FP64) the residual is replaced by b - K x before
+  // every replace_every-th iteration.
   void run(double* x, int64_t ldx, int ncols, const double* const* b, double rtol, int maxit,
-           CGScal* out, hipStream_t st) {
+           CGScal* out, hipStream_t st, int replace_every = 0) {
     w.x = x;
     w.ldx = ldx;
     int cols[kMaxCols];
-    for (int c = 0; c < ncols; ++c) cols[c] = c;
+    for (int c = 0; c < ncols; ++c) {
+      cols[c] = c;
+      w.rhs[c] = b[c];
+    }
     pcg_setup(w, b, cols, ncols, ncols, rtol, maxit, st);
-    poll.run([&](int parity, const int* cl, int nl) { pcg_iterate(w, parity, cl, nl, ncols, st); },
-             w.scal, ncols, std::max(1, std::min(expect, maxit + 1)), 2, false, out, st);
+    int it = 0;
+    poll.run(
+        [&](int parity, const int* cl, int nl) {
+          if (replace_every > 0 && it > 0 && it % replace_every == 0) mg3_replace(w, cl, nl, st);
+          ++it;
+          pcg_iterate(w, parity, cl, nl, ncols, st);
+        },
+        w.scal, ncols, std::max(1, std::min(expect, maxit + 1)), 2, false, out, st);
     int most = 0;
     for (int c = 0; c < ncols; ++c) most = std::max(most, out[c].iters);
     expect = most + 1;   // the iteration after the last update detects convergence
@@ -1113,16 +1124,20 @@ void ritz_values(sts_problem* P, int64_t k, std::vector<double>& out) {
 // Kx x_j = b[j] for j < nk by multigrid-preconditioned CG, x_j at x + j * ldv.
 // Mixed-precision Kx solves (opts.mixed, 3-D grids with a smoothed level):
 // iterative refinement with FP32 multigrid PCG as the correction solver.
-// x = 0, r = b; each round solves K d = r in FP32 to the relative tolerance
-// max(target / ||r||, kF32RoundRtol), then in FP64 x += d and r = b - K x,
-// until ||r|| <= target = rtol ||b||.  The FP32 solve's own accuracy is
-// bounded by single-precision rounding, so a round asks for no more than
-// kF32RoundRtol; a round that does not reduce ||r|| by kF32MinGain (the FP32
-// solve stalled or broke down in rounding) ends the FP32 rounds of that
-// column and FP64 PCG solves for the rest of the correction.
-constexpr double kF32RoundRtol = 1e-5;
+// x = 0, r = b; each round solves K d = r by PCG with FP32 vectors to the
+// relative tolerance max(target / ||r||, kF32ReplacedRtol), then in FP64
+// x += d and r = b - K x, until ||r|| <= target = rtol ||b||.  Within a round
+// d accumulates in FP64 and the FP32 residual is replaced by r - K d every
+// kReplaceEvery iterations (residual replacement, as in reliable-update CG):
+// the recursion cannot drift from the true residual by more than a few
+// iterations' rounding, so one round usually meets the whole target and CG
+// keeps its search directions.  A round that does not reduce ||r|| by
+// kF32MinGain (the FP32 solve stalled or broke down in rounding) ends the
+// FP32 rounds of that column and FP64 PCG solves for the rest.
 constexpr double kF32MinGain = 0.1;
 constexpr int kF32MaxRounds = 6;
+constexpr int kReplaceEvery = 3;
+constexpr double kF32ReplacedRtol = 1e-12;
 
 bool mixed_applies(const sts_problem* P, const sts_opts& o) {
   return o.mixed != 0 && P->mg_ok && P->mg_plan_.dim == 3 && P->mg_plan_.nlev >= 1;
@@ -1152,12 +1167,13 @@ void refined_kx_solve(MGRunner& r, int64_t nh, int nk, const double* const* b, d
     r.defect.alloc(ld0 * kMaxCols * 8);   // FP64 residuals b - K x
     r.norms.alloc(kMaxCols * 8);
   }
-  float* d32 = reinterpret_cast<float*>(r.corr.d());
+  double* d64 = r.corr.d();   // a round's correction, FP64 (packed columns)
   for (int j = 0; j < nk; ++j) fill(x + j * ldx, nh, 0.0, st);
   const double bpn32 = [&] {
     MGPlan q = r.w.plan;
     q.f32 = 0;
     q.f32cg = 1;
+    q.x64 = 1;
     return mg3_bytes_per_node(q);
   }();
   const double nn = (double)nh;
@@ -1173,6 +1189,7 @@ void refined_kx_solve(MGRunner& r, int64_t nh, int nk, const double* const* b, d
   auto restore = [&](int e) {
     r.w.plan.f32 = saved_f32;
     r.w.plan.f32cg = 0;
+    r.w.plan.x64 = 0;
     r.w.col_rtol = nullptr;
     r.expect32 = r.expect;
     r.expect = e;
@@ -1184,17 +1201,19 @@ void refined_kx_solve(MGRunner& r, int64_t nh, int nk, const double* const* b, d
     for (int s = 0; s < na; ++s) {
       const int j = act[s];
       in[s] = round == 0 ? b[j] : r.defect.d() + j * ld0;
-      rt[s] = round == 0 ? std::max(rtol, kF32RoundRtol)
-                         : std::max(target[j] / std::max(rnorm[j], 1e-300), kF32RoundRtol);
+      rt[s] = round == 0 ? std::max(rtol, kF32ReplacedRtol)
+                         : std::max(target[j] / std::max(rnorm[j], 1e-300), kF32ReplacedRtol);
     }
-    // FP32 PCG on the active columns, packed: slot s -> d32 column s
+    // FP32 PCG on the active columns, packed (slot s -> column s of d64),
+    // its correction accumulated in FP64 and its residual replaced from it
     r.w.plan.f32 = 0;
     r.w.plan.f32cg = 1;
+    r.w.plan.x64 = 1;
     r.w.col_rtol = rt;
     const int e = r.expect;
     r.expect = r.expect32;
     try {
-      r.run(reinterpret_cast<double*>(d32), ld0, na, in, kF32RoundRtol, maxit, out, st);
+      r.run(d64, ld0, na, in, kF32ReplacedRtol, maxit, out, st, kReplaceEvery);
     } catch (...) {
       restore(e);
       throw;
@@ -1202,7 +1221,7 @@ void refined_kx_solve(MGRunner& r, int64_t nh, int nk, const double* const* b, d
     restore(e);
     for (int s = 0; s < na; ++s) {
       cnt.its32 += out[s].iters;
-      cnt.bytes += (bpn32 * (out[s].iters + 1) + 12.0) * nn;
+      cnt.bytes += (bpn32 * (out[s].iters + 1) + 16.0 + 20.0 * out[s].iters / kReplaceEvery) * nn;
       if (round == 0) {
         // ||b|| from the FP32 set-up's (b, b): enough for a tolerance
         bnorm[act[s]] = std::sqrt(std::max(out[s].gamma0, 0.0));
@@ -1218,13 +1237,13 @@ void refined_kx_solve(MGRunner& r, int64_t nh, int nk, const double* const* b, d
       const int j = act[s];
       xs[s] = x + j * ldx;
       // a column whose FP32 solve broke down contributes no correction
-      ds[s] = out[s].flag == 3 ? nullptr : static_cast<const void*>(d32 + s * ld0);
+      ds[s] = out[s].flag == 3 ? nullptr : static_cast<const void*>(d64 + s * ld0);
       bs[s] = b[j];
       rs[s] = r.defect.d() + j * ld0;
     }
-    mg3_defect(r.w, na, xs, ds, true, bs, rs, r.norms.d(), st);
+    mg3_defect(r.w, na, xs, ds, false, bs, rs, r.norms.d(), st);
     ++cnt.rounds;
-    cnt.bytes += 44.0 * nn * na;
+    cnt.bytes += 48.0 * nn * na;
     double n2[kMaxCols];
     norms(na, n2);
     std::vector<int> next;

@@ -655,8 +655,9 @@ __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
   if (threadIdx.x == 0) a.part_pq[(size_t)col * a.max_tiles + t] = tot;
 }
 
-// B: alpha = rho / (p, q); x += alpha p; r -= alpha q; (r, r).
-template <class V>
+// B: alpha = rho / (p, q); x += alpha p; r -= alpha q; (r, r).  x holds XT
+// (V, or FP64 for the FP32 PCG whose residual is replaced from x).
+template <class V, class XT>
 __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
   __shared__ double red[kT / 64];
   __shared__ V redv[kT / 64];
@@ -675,14 +676,14 @@ __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
   const double alpha = ok ? s.rho / pq : 0.0;
   if (t == 0 && threadIdx.x == 0) a.alpha[col] = alpha;
   if (!ok) return;
-  V* xg = static_cast<V*>(a.x) + (size_t)col * a.ldx;
+  XT* xg = static_cast<XT*>(a.x) + (size_t)col * a.ldx;
   V* rg = static_cast<V*>(a.r) + (size_t)col * a.ld;
   const V* pg = static_cast<const V*>(a.pout) + (size_t)col * a.ld;
   const V* qg = static_cast<const V*>(a.q) + (size_t)col * a.ld;
   const V av = (V)alpha;
   V part = (V)0;
   for_core(a.n, T, [&](size_t g, int) {
-    xg[g] += av * pg[g];
+    xg[g] += (XT)alpha * (XT)pg[g];
     const V rv = rg[g] - av * qg[g];
     rg[g] = rv;
     part += rv * rv;
@@ -693,19 +694,19 @@ __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
 
 // Set-up: x = 0, r = b (rounded to V), both p buffers 0, partials of (r, r);
 // both state slots initialised (columns in the launch list active), alpha = 1.
-template <class V>
+template <class V, class XT>
 __global__ __launch_bounds__(kT) void pcg3_setup_kernel(PCG3Args a, int maxit) {
   __shared__ V redv[kT / 64];
   STS_PCG3_PROLOGUE(a)
   const double* bg = a.b[jb];
-  V* xa = static_cast<V*>(a.x);
+  XT* xa = static_cast<XT*>(a.x);
   V* ra = static_cast<V*>(a.r);
   V* pa = static_cast<V*>(const_cast<void*>(a.pin));
   V* pb = static_cast<V*>(a.pout);
   V part = (V)0;
   for_core(a.n, T, [&](size_t g, int) {
     const V bv = (V)bg[g];
-    xa[g + (size_t)col * a.ldx] = (V)0;
+    xa[g + (size_t)col * a.ldx] = (XT)0;
     ra[g + (size_t)col * a.ld] = bv;
     pa[g + (size_t)col * a.ld] = (V)0;
     pb[g + (size_t)col * a.ld] = (V)0;
@@ -775,6 +776,44 @@ __global__ __launch_bounds__(kT) void defect3_kernel(Defect3Args a) {
   });
   part = block_sum<kT>(part, red);
   if (threadIdx.x == 0) a.part[(size_t)jb * a.max_tiles + t] = part;
+}
+
+// Residual replacement of the FP32 PCG: r = b - (Kx + s Mx) x from the FP64
+// iterate, stored in FP32, (r, r) per tile in FP64.
+struct Replace3Args {
+  int n;
+  int64_t ld, ldx;
+  int ntx, nty, ntz;
+  int nlaunch;
+  int cols[kMaxCols];
+  double c, sm;
+  const double* x;
+  const double* b[kMaxCols];   // by column
+  float* r;
+  double* part;
+  int max_tiles;
+};
+
+template <bool SH>
+__global__ __launch_bounds__(kT) void replace3_kernel(Replace3Args a) {
+  __shared__ double us[NR];
+  __shared__ double red[kT / 64];
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const int lin = xcd_remap(blockIdx.x, a.nlaunch * ntiles);
+  const int t = lin / a.nlaunch, col = a.cols[lin % a.nlaunch];
+  const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
+  load_halo(a.x + (size_t)col * a.ldx, a.n, T, us);
+  __syncthreads();
+  const double* bg = a.b[col];
+  float* rg = a.r + (size_t)col * a.ld;
+  double part = 0.0;
+  for_core(a.n, T, [&](size_t g, int q) {
+    const double rv = bg[g] - k7<SH, RX, RY>(us, q, a.c, a.sm);
+    rg[g] = (float)rv;
+    part += rv * rv;
+  });
+  part = block_sum<kT>(part, red);
+  if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
 }
 
 int tiles3(int n, int sx, int sy, int sz) {
@@ -855,7 +894,7 @@ int mg3_max_tiles(const MGPlan& p) {
 double mg3_bytes_per_node(const MGPlan& p) {
   const double n0 = std::pow((double)p.n[0], 3);
   const bool all32 = p.f32cg && p.nlev > 0, f32 = (p.f32 || p.f32cg) && p.nlev > 0;
-  double b = (all32 ? 40.0 : 80.0) * n0;   // PCG A and B
+  double b = (all32 ? (p.x64 ? 48.0 : 40.0) : 80.0) * n0;   // PCG A and B
   for (int l = 0; l < p.nlev; ++l) {
     const double nf = std::pow((double)p.n[l], 3), nc = std::pow((double)p.n[l + 1], 3);
     const double sb = (f32 && (l > 0 || all32)) ? 4.0 : 8.0, ss = f32 ? 4.0 : 8.0;
@@ -1011,12 +1050,15 @@ void pcg3_setup(const MGWork& w, const double* const* b, const int* cols, int nl
     a.rtol2[c] = rt * rt;
   }
   const dim3 grid(a.ntx * a.nty * a.ntz * nlaunch);
-  if (w.plan.f32cg)
-    launch(STS_K_PCG_B, 12.0 * std::pow((double)a.n, 3) * nlaunch, pcg3_setup_kernel<float>, grid,
-           dim3(kT), 0, st, a, maxit);
+  if (w.plan.f32cg && w.plan.x64)
+    launch(STS_K_PCG_B, 16.0 * std::pow((double)a.n, 3) * nlaunch,
+           pcg3_setup_kernel<float, double>, grid, dim3(kT), 0, st, a, maxit);
+  else if (w.plan.f32cg)
+    launch(STS_K_PCG_B, 12.0 * std::pow((double)a.n, 3) * nlaunch,
+           pcg3_setup_kernel<float, float>, grid, dim3(kT), 0, st, a, maxit);
   else
-    launch(STS_K_PCG_B, 40.0 * std::pow((double)a.n, 3) * nlaunch, pcg3_setup_kernel<double>,
-           grid, dim3(kT), 0, st, a, maxit);
+    launch(STS_K_PCG_B, 40.0 * std::pow((double)a.n, 3) * nlaunch,
+           pcg3_setup_kernel<double, double>, grid, dim3(kT), 0, st, a, maxit);
   STS_HIP(hipGetLastError());
 }
 
@@ -1065,10 +1107,15 @@ void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int
            dim3(kT), 0, st, r);
     STS_HIP(hipGetLastError());
   }
-  if (w.plan.f32cg)
-    launch(STS_K_PCG_B, 6.0 * vb * nn, pcg3_b_kernel<float>, dim3(blocks), dim3(kT), 0, st, a);
+  if (w.plan.f32cg && w.plan.x64)
+    launch(STS_K_PCG_B, (4.0 * vb + 16.0) * nn, pcg3_b_kernel<float, double>, dim3(blocks),
+           dim3(kT), 0, st, a);
+  else if (w.plan.f32cg)
+    launch(STS_K_PCG_B, 6.0 * vb * nn, pcg3_b_kernel<float, float>, dim3(blocks), dim3(kT), 0, st,
+           a);
   else
-    launch(STS_K_PCG_B, 6.0 * vb * nn, pcg3_b_kernel<double>, dim3(blocks), dim3(kT), 0, st, a);
+    launch(STS_K_PCG_B, 6.0 * vb * nn, pcg3_b_kernel<double, double>, dim3(blocks), dim3(kT), 0,
+           st, a);
   STS_HIP(hipGetLastError());
 }
 
@@ -1117,6 +1164,33 @@ void mg3_defect(const MGWork& w, int ncols, double* const* x, const void* const*
   rd.out[0] = norms2;
   launch(STS_K_PCG_REDUCE, 8.0 * ntiles * ncols, pcg3_reduce_kernel, dim3(ncols, 1), dim3(kT), 0,
          st, rd);
+  STS_HIP(hipGetLastError());
+}
+
+void mg3_replace(const MGWork& w, const int* cols, int nl, hipStream_t st) {
+  if (nl <= 0) return;
+  Replace3Args a{};
+  a.n = w.plan.n[0];
+  a.ld = w.ld[0];
+  a.ldx = w.ldx;
+  a.ntx = (a.n + TX - 1) / TX;
+  a.nty = (a.n + TY - 1) / TY;
+  a.ntz = (a.n + TZ - 1) / TZ;
+  a.nlaunch = nl;
+  for (int j = 0; j < nl; ++j) a.cols[j] = cols[j];
+  for (int c = 0; c < kMaxCols; ++c) a.b[c] = w.rhs[c];
+  a.c = w.plan.mu;
+  a.sm = w.plan.sw0;
+  a.x = w.x;
+  a.r = reinterpret_cast<float*>(w.b[0]);
+  a.part = w.part_rr;
+  a.max_tiles = w.max_tiles;
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const double by = 20.0 * std::pow((double)a.n, 3) * nl;
+  if (a.sm != 0.0)
+    launch(STS_K_PCG_A, by, replace3_kernel<true>, dim3(ntiles * nl), dim3(kT), 0, st, a);
+  else
+    launch(STS_K_PCG_A, by, replace3_kernel<false>, dim3(ntiles * nl), dim3(kT), 0, st, a);
   STS_HIP(hipGetLastError());
 }
 

@@ -192,6 +192,8 @@ struct MGPlan {
                              // (all but the finest right-hand side and result)
   int f32cg;                 // 3-D with nlev >= 1: FP32 PCG -- x, r, z, p, q and every
                              // V-cycle vector in FP32, FP32 vector arithmetic in the PCG
+  int x64;                   // with f32cg: x accumulated in FP64 (x += alpha p), so that
+                             // the residual can be replaced by b - K x (mg3_replace)
 };
 // The m x m sine-transform matrix (row-major) followed by the m eigenvalues
 // 2 - 2 cos(pi j / (m + 1)) of tridiag(-1, 2, -1): m (m + 1) doubles.
@@ -231,6 +233,7 @@ struct MGWork {
   double* t1;                    // coarsest-level temporaries above kMGCoarseMax
   double* t2;                    //   (stride ld[nlev], kMaxCols columns)
   const double* col_rtol;        // host, per column (set-up), or null: the scalar rtol
+  const double* rhs[kMaxCols];   // right-hand side of each column of the current run
 };
 // e[0][:, c] = B b[0][:, c] (one V-cycle) for the columns cols[0..nlaunch);
 // columns whose state in `act` (may be null) is inactive are skipped; with
@@ -258,6 +261,10 @@ void pcg3_iterate(const MGWork& w, int parity, const int* cols, int nlaunch, int
 // (device).  Every vector is one fine-grid column.  Uses w.part_rr.
 void mg3_defect(const MGWork& w, int ncols, double* const* x, const void* const* d, bool d32,
                 const double* const* b, double* const* r, double* norms2, hipStream_t st);
+// Residual replacement in the FP32 PCG with x in FP64 (plan.f32cg, plan.x64):
+// for the columns cols[0..nl), r = rhs - (Kx + s Mx) x in FP64, stored to the
+// PCG's FP32 residual, with its FP64 per-tile (r, r) partials in part_rr.
+void mg3_replace(const MGWork& w, const int* cols, int nl, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Mx solves by Chebyshev iteration (2-D P1 mass matrix)

@@ -1,13 +1,14 @@
 """FP32 bulk work with FP64 refinement (sts_opts.mixed) in the 3-D solve.
 
 Bars, from the arithmetic:
-  * Refined Kx solve: each FP32 round is a correction whose own error is
-    bounded by single-precision rounding; the FP64 defect r = b - Kx x is exact
-    to FP64 rounding, so the refinement reaches the requested rtol on the FP64
-    residual, and the error against the exact sine-transform solve is then
-    what an FP64 solve to that rtol gives: 1e-10 at rtol 1e-12 (the bar of
-    the FP64 PCG test).  More than one defect correction is needed for rtol
-    1e-12 (an FP32 round asks for at most 1e-5).
+  * Refined Kx solve: each FP32 round is a correction accumulated in FP64
+    whose residual is replaced from that FP64 correction every few
+    iterations; the FP64 defect r = b - Kx x is exact to FP64 rounding, so the
+    refinement reaches the requested rtol on the FP64 residual, and the error
+    against the exact sine-transform solve is then what an FP64 solve to that
+    rtol gives: 1e-10 at rtol 1e-12 (the bar of the FP64 PCG test).  With
+    the replacement CG keeps its directions, so the FP32 iterations stay
+    within 1.5x the FP64 PCG's on the same system.
   * Whole solve: the Galerkin projection, reduced solve and exact residual are
     FP64, so the solve meets the same exact-residual tolerance; the relative
     error against the oracle's sine-mode space-time solution and against the
@@ -58,6 +59,7 @@ def test_refined_fp32_kx_solve_matches_the_sine_transform_solve(n, ncols, rtol):
     space = sts.make_space(3, n, mu)
     X, its32, its64, rounds = sts.pcg_mg_refined(space, dev(B), rtol=rtol)
     X = host(X)
+    _, its_ref, _ = sts.pcg_mg(space, dev(B), rtol=rtol)
     K = mgr.stiffness3(n, mu)
     Xr = mgr.exact3(B, n, mu)
     for c in range(ncols):
@@ -66,11 +68,10 @@ def test_refined_fp32_kx_solve_matches_the_sine_transform_solve(n, ncols, rtol):
         assert r <= 1.05 * rtol, (c, r)
         if rtol <= 1e-12:
             assert rel(X[:, c], Xr[:, c]) < 1e-10, (c, rel(X[:, c], Xr[:, c]))
-    assert its32 > 0
-    if rtol <= 1e-12:
-        assert rounds >= 2 and its64 <= 13 * ncols, (its32, its64, rounds)
-    else:
-        assert rounds == 1 and its64 == 0, (its32, its64, rounds)
+    assert its32 > 0 and its64 == 0, (its32, its64, rounds)
+    assert its32 <= 1.5 * sum(its_ref) + 2 * ncols, (its32, its_ref)
+    if rtol > 1e-6:
+        assert rounds == 1, (its32, its64, rounds)
 
 
 def test_refined_fp32_kx_solve_rejects_grids_without_a_smoothed_level():
