@@ -247,8 +247,9 @@ def bench_batch(args) -> int:
     """256 independent 2-D problems of uneven size (grid side 63 / 127 / 255,
     Nt 128..1024, rank 1..3, mu log-uniform in [0.1, 10]) solved to a relative
     residual of 1e-9 through the batch executor, with the worker count picked
-    by the autotuner; the same batch with one worker is the sequential
-    reference.  One step = one pass over the whole batch."""
+    and the inner-solve relaxation picked by the autotuner; the same batch
+    with one worker is the sequential reference.  One step = one pass over
+    the whole batch."""
     import numpy as np
     import torch
 
@@ -267,11 +268,13 @@ def bench_batch(args) -> int:
                                  torch.from_numpy(np.asarray(w.F1)).cuda(),
                                  torch.from_numpy(np.asarray(w.F2)).cuda()))
     torch.cuda.synchronize()
-    # inner solves relaxed as the residual falls (sts_opts.inner_relax, j = 1)
-    opts = dict(tol=1e-9, max_outer=80, restart=1, inner_relax=1)
+    # worker count and inner-solve relaxation (sts_opts.inner_relax) from
+    # timed probe runs over a 32-problem subset
+    opts = dict(tol=1e-9, max_outer=80, restart=1)
     t0 = time.perf_counter()
-    best, timings = autotune.tune_workers(probs, probe=32, **opts)
-    _log(f"autotune {time.perf_counter() - t0:.1f}s: {timings} -> {best} workers")
+    (best, relax), timings = autotune.tune(probs, probe=32, **opts)
+    opts["inner_relax"] = relax
+    _log(f"autotune {time.perf_counter() - t0:.1f}s: {timings} -> {best} workers, j = {relax}")
     dof = sum(w.nh * w.nt for w in batch)
     res = {}
     for workers in (best, 1):
@@ -307,11 +310,11 @@ def bench_batch(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"batch2d_uneven_{len(batch)}", "count": len(batch),
                    "sides": [63, 127, 255], "nt": [128, 256, 512, 1024], "p": [1, 2, 3],
-                   "tol": opts["tol"], "workers": best},
+                   "tol": opts["tol"], "workers": best, "inner_relax": relax},
         "solves_per_s": len(batch) / t_best,
         "one_worker": {"ms_per_step": 1e3 * t_one, "value": dof / t_one},
         "speedup_vs_one_worker": t_one / t_best,
-        "autotune_probe_seconds": timings,
+        "autotune_probe_seconds": {f"w{w}_j{j}": t for (w, j), t in timings.items()},
         "gate_passed": gate, "max_rel_error_sampled": max(errs) if errs else None,
         "errors_sampled": len(errs),
         "outer_its_total": sum(d["outer_its"] for d in infos),

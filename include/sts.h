@@ -421,11 +421,6 @@ sts_status sts_pcg_mg_mixed(const sts_space* space, double shift, const double* 
                             double* X, int64_t ldx, int32_t ncols, double rtol, int32_t maxit,
                             int32_t* iters, void* stream);
 
-/* Direct solves A X[:, c] = B[:, c], A = Kx or Mx per column (ops[c]), for a
- * 1-D P1 space (STS_FE_P1_1D; else STS_E_INVALID): both matrices of Sec. 3
- * are constant-coefficient symmetric tridiagonal, solved by elimination
- * without pivoting (the inner solves of the extended Krylov space, Sec. 4).
- * B, X: Nh x ncols (ldb, ldx), device, must not overlap; ncols <= 8. */
 /* Kx X = B for the 3-D seven-point stiffness with FP32 bulk work: FP32
  * multigrid PCG (vectors, stencil product, V-cycle and per-tile inner
  * products in FP32) as the correction solver of FP64 iterative refinement
@@ -443,6 +438,14 @@ sts_status sts_pcg_mg_refined(const sts_space* space, const double* B, int64_t l
                               int64_t* iters_fp32, int64_t* iters_fp64, int64_t* rounds,
                               void* stream);
 
+/* Direct solves A X[:, c] = B[:, c], A = Kx or Mx per column (ops[c]), for a
+ * 1-D P1 space (STS_FE_P1_1D; else STS_E_INVALID): both matrices of Sec. 3
+ * are constant-coefficient symmetric tridiagonal, solved by elimination
+ * without pivoting (the inner solves of the extended Krylov space, Sec. 4)
+ * in a nested-dissection order: 63-row blocks in parallel, the separators'
+ * Schur complement recursively in LDS (up to 262208 nodes; longer grids
+ * take one sequential sweep per column).  B, X: Nh x ncols (ldb, ldx >= Nh),
+ * device, must not overlap; 1 <= ncols <= 8.  Synchronous. */
 sts_status sts_tridiag_solve(const sts_space* space, const int32_t* ops, const double* B,
                              int64_t ldb, double* X, int64_t ldx, int32_t ncols, void* stream);
 

@@ -669,7 +669,7 @@ struct sts_problem {
   bool mg_ok = false;
   bool mass_cheb = false;   // Mx solves by Chebyshev iteration
   bool tri_ok = false;      // 1-D: direct tridiagonal solves for Kx and Mx
-  DevBuf tri_fac;           // their elimination factors (4 Nh)
+  DevBuf tri_fac;           // their elimination factors (tridiag_factor_doubles)
   bool tensor_mass = false; // 3-D trilinear mass: direct tensor-product Mx solves
   DevBuf tmass_fac;         // elimination factors of tridiag(1, 4, 1) (2 n)
   MGPlan mg_plan_{};
@@ -965,11 +965,19 @@ double solution_fnorm(sts_problem* P) {
 // Mx^{-1} Kx (about 1e-7 for the 1-D problem with 65535 nodes, where no FP64
 // representation of the exact solution has a smaller residual).  The floor
 // reported is kFloorFactor times that estimate, above what the rounded exact
-// solution measures (about 3.5 times it).
+// solution measures (about 3.5 times it).  The Galerkin solution adds the
+// error of the reduced solve: the eigendecomposition of the order-k reduced
+// matrix has a backward error near sqrt(k) u ||T|| (Householder reduction),
+// which moves the small Ritz values, and so the slow modes of Y, by that
+// much; the floor therefore grows like sqrt(k / kFloorCols) beyond
+// kFloorCols basis columns (a 1-D solve with 29139 nodes stalls at about 46
+// times the estimate with k = 600).
 constexpr double kFloorFactor = 8.0;
+constexpr double kFloorCols = 64.0;
 
 double residual_floor(sts_problem* P) {
-  return kFloorFactor * P->floor_coef * solution_fnorm(P);
+  const double grow = std::max(1.0, std::sqrt((double)P->k_sol / kFloorCols));
+  return kFloorFactor * grow * P->floor_coef * solution_fnorm(P);
 }
 
 // Whether an exact residual res above tol is explained by the rounding floor:
@@ -1015,8 +1023,9 @@ void run_shifted_block(sts_problem* P, double s, int ncols, const double* const*
                        const sts_opts& o) {
   double* x0 = P->V.d() + P->k * P->ldv;
   if (o.inner_precond != 0 && P->tri_ok) {
+    // work: the CG residual vectors (2 kMaxCols columns of ldv), idle here
     tridiag_shifted_solve(P->grid, P->K, P->M, s, ncols, b, x0, P->ldv, P->cg.w.r[0], P->ldv,
-                          P->stream);
+                          2 * P->ldv * kMaxCols, P->stream);
     P->inner_K += ncols;
     P->alg_bytes += 40.0 * P->nh * ncols;
     return;
@@ -1556,7 +1565,7 @@ int64_t problem_footprint(const sts_space& space, int64_t nt, int p, int max_out
   b += residual_norm2_partial_size(g.nh, (int)nt) * 8;
   if (mg) b += 9 * ld * kMaxCols * 8 + (int64_t)plan.exact * (plan.exact + 1) * 8;
   if (mixed32) b += 2 * ld * kMaxCols * 8;                       // refinement buffers
-  if (tridiag_supported(g, K, M)) b += 4 * g.nh * 8;
+  if (tridiag_supported(g, K, M)) b += tridiag_factor_doubles(g.nh) * 8;
   if (tensor_mass_supported(g, M)) b += 2 * g.nx * 8;
   return b + (1 << 20);                                            // small scratch
 }
@@ -1716,7 +1725,7 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     }
     P->tri_ok = tridiag_supported(g, P->K, P->M);
     if (P->tri_ok) {
-      P->tri_fac.alloc(4 * g.nh * 8);
+      P->tri_fac.alloc(tridiag_factor_doubles(g.nh) * 8);
       tridiag_factor(g, P->K, P->M, P->tri_fac.d(), st);
     }
     // small scratch
@@ -2322,8 +2331,9 @@ sts_status sts_shifted_solve(const sts_space* space, double shift, const double*
     const double* bcols[kMaxCols];
     for (int c = 0; c < ncols; ++c) bcols[c] = B + c * ldb;
     if (tridiag_supported(g, K, M)) {
-      double* work = sc.get<double>(ld * ncols);
-      tridiag_shifted_solve(g, K, M, shift, ncols, bcols, X, ldx, work, ld, st);
+      const int64_t nw = tridiag_shifted_work_doubles(g.nh, ld, ncols);
+      double* work = sc.get<double>(nw);
+      tridiag_shifted_solve(g, K, M, shift, ncols, bcols, X, ldx, work, ld, nw, st);
       STS_HIP(hipStreamSynchronize(st));
       if (iters)
         for (int c = 0; c < ncols; ++c) iters[c] = 1;
@@ -2455,7 +2465,7 @@ sts_status sts_tridiag_solve(const sts_space* space, const int32_t* ops, const d
     STS_REQUIRE(B && X && ldb >= g.nh && ldx >= g.nh, STS_E_INVALID, "bad buffers");
     hipStream_t st = static_cast<hipStream_t>(stream);
     Scratch sc;
-    double* fac = sc.get<double>(4 * g.nh);
+    double* fac = sc.get<double>(tridiag_factor_doubles(g.nh));
     tridiag_factor(g, K, M, fac, st);
     const double* bc[kMaxCols];
     int op[kMaxCols];

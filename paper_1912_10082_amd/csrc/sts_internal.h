@@ -478,18 +478,38 @@ void sumsq(int64_t rows, int ncols, const double* A, int64_t lda, double* out, d
 // ---------------------------------------------------------------------------
 // direct tridiagonal inner solves (1-D P1), tridiag.hip
 // ---------------------------------------------------------------------------
+constexpr int kTriPeriod = 64;             // 63 block rows, then one separator row
+constexpr int kTriMaxLevels = 8;
+constexpr int64_t kTriMaxReduced = 4096;   // rows of the first reduced level held in LDS
+// The levels of the blocked elimination of an Nh x Nh tridiagonal matrix:
+// n[l] rows at level l (n[l + 1] = its separators), each level's seven factor
+// arrays of ld[l] doubles at off[l]; total doubles per operator.  blocked is
+// false where the first reduced level exceeds kTriMaxReduced rows (then the
+// sequential sweep runs).
+struct TriPlan {
+  int levels;
+  bool blocked;
+  int64_t n[kTriMaxLevels];
+  int64_t ld[kTriMaxLevels];
+  int64_t off[kTriMaxLevels];
+  int64_t total;
+};
+TriPlan tri_plan(int64_t nh);
 bool tridiag_supported(const Grid& g, const Stencil& K, const Stencil& M);
-// fac: 4 Nh doubles of elimination factors of Kx and Mx
+// doubles of the elimination factors of Kx and Mx that tridiag_factor writes
+int64_t tridiag_factor_doubles(int64_t nh);
 void tridiag_factor(const Grid& g, const Stencil& K, const Stencil& M, double* fac,
                     hipStream_t st);
 void tridiag_solve(const Grid& g, const Stencil& K, const Stencil& M, const int* ops, int ncols,
                    const double* const* b, double* x, int64_t ldx, const double* fac,
                    hipStream_t st);
-// (Kx + s Mx) x = b, s >= 0, factors formed on the fly; work: ncols columns
-// of at least Nh doubles (ldw).
+// (Kx + s Mx) x = b, s >= 0, factors formed on the fly in work (work_doubles
+// long, at least tridiag_shifted_work_doubles(Nh, ldw, ncols); the sequential
+// sweep keeps ncols columns of ldw >= Nh doubles there).
+int64_t tridiag_shifted_work_doubles(int64_t nh, int64_t ldw, int ncols);
 void tridiag_shifted_solve(const Grid& g, const Stencil& K, const Stencil& M, double s, int ncols,
                            const double* const* b, double* x, int64_t ldx, double* work,
-                           int64_t ldw, hipStream_t st);
+                           int64_t ldw, int64_t work_doubles, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // direct Mx solves for the 3-D trilinear (tensor-product) mass, tensor_mass.hip

@@ -111,3 +111,13 @@ def test_autotuner_returns_a_measured_candidate():
     assert all(t > 0 for t in timings.values())
     for pr in probs:
         pr.close()
+
+
+def test_joint_autotuner_searches_workers_and_relaxation():
+    batch = wl.batch_2d_uneven(count=6, seed0=6, sides=(31, 63), nts=(32, 64), ps=(1, 2))
+    probs = [_make(w) for w in batch]
+    (w, j), timings = autotune.tune(probs, candidates=(1, 2), relax=(1, 2), probe=4, tol=1e-9)
+    assert set(timings) == {(1, 1), (1, 2), (2, 1), (2, 2)}
+    assert timings[(w, j)] == min(timings.values())
+    for pr in probs:
+        pr.close()
