@@ -85,8 +85,8 @@ def _kernel_sources(hip_name) -> list:
 HIP_KERNELS = {
     "mg_coarse": ["dst_gemm_kernel", "mg_coarse_kernel", "fst_row_kernel", "fst_col_kernel",
                   "coarse3_plane_kernel", "coarse3_z_kernel"],
-    "gram": ["gemm_tn_kernel"],
-    "gram_reduce": ["gemm_tn_reduce"],
+    "gram": ["gemm_tn_kernel", "gemm_tnw_kernel", "gemm_tn32_kernel"],
+    "gram_reduce": ["gemm_tn_reduce", "gemm_tnw_reduce", "gemm_tn32_reduce"],
     "residual": ["residual_kernel"],
     "basis_update": ["gemm_nn_sub_kernel", "gemm_nn_sub4_kernel"],
     "mg_up": ["mg_up_kernel", "mg3_post1_kernel", "mg3_post2_kernel"],
@@ -360,8 +360,10 @@ def bench_serve(args) -> int:
         reqs.append((w, (dd, ds), (md, ms)))
     # residual 1e-8, the error gate: the exact residual of a 1-D request with
     # tens of thousands of nodes has an FP64 rounding floor near 1e-8
-    # (accepted within that floor, sts_solve); each basis grows with its space
-    opts = dict(tol=1e-8, max_outer=100)
+    # (accepted within that floor, sts_solve); each basis grows with its space,
+    # so the cap costs no footprint (the slowest 1-D requests, with ~57k
+    # nodes and P = 4, take ~150 blocks)
+    opts = dict(tol=1e-8, max_outer=250)
 
     def req_opts(w):
         # relaxed inner solves (sts_opts.inner_relax): j = 2 in 3-D, 1 otherwise;

@@ -36,7 +36,13 @@ namespace {
 constexpr int kTT = 1024;            // threads of the tridiagonalisation work-group
 constexpr int kSect = 4;             // threads per eigenvalue in the multisection
 constexpr double kEps = 1.1102230246251565e-16;
-constexpr double kClusterTol = 1e-8;
+// Inverse iteration from a shift within ~eps ||T|| of its eigenvalue leaves
+// an overlap near eps ||T|| / g with an eigenvector g away; down to gaps of
+// 1e-11 ||T|| that is <= 1e-5, which the two Newton-Schulz steps remove
+// (1e-5 -> 1e-10 -> rounding).  Closer eigenvalues are a cluster.  A wider
+// tolerance made the graded spectra of 1-D reduced matrices (||T|| ~ 1e10,
+// gaps ~ 1 among the small Ritz values) one sequential cluster of dozens.
+constexpr double kClusterTol = 1e-11;
 constexpr int kInvIters = 3;
 constexpr int kLdsPanelMaxK = 480;   // orders whose tridiagonalisation panel fits in LDS
 

@@ -301,7 +301,10 @@ def test_relaxed_inner_tolerance_keeps_the_solution(dim, n, nt, p):
     for relax in (0, 1, 2):
         info, V, Y = _solve(w, tol=1e-10, inner_relax=relax)
         assert info["status"] == "STS_OK", info
-        assert info["res_true"] <= 1e-10
+        # the 1-D grid's exact residual has an FP64 floor of the order of tol:
+        # STS_OK then also means within tol + res_floor (floor_limited)
+        assert info["res_true"] <= 1e-10 or (info["floor_limited"] == 1 and
+                                             info["res_true"] <= 1e-10 + info["res_floor"]), info
         assert rel(V @ Y, U) <= 1e-8, (relax, rel(V @ Y, U))
         res[relax] = info
     if dim > 1:

@@ -200,6 +200,33 @@ def test_sym_eig_repeated_and_clustered():
     assert np.linalg.norm(A @ Q - Q * lam) <= 1e-12 * np.linalg.norm(A) * math.sqrt(k)
 
 
+def test_sym_eig_close_but_separated_and_graded():
+    """Eigenvalues 1e-10 .. 1e-8 ||A|| apart (each its own inverse iteration,
+    then Newton-Schulz) and a graded spectrum over ten decades at k = 600 (the
+    reduced matrices of 1-D grids with tens of thousands of nodes)."""
+    rng = np.random.default_rng(2)
+    k = 40
+    Qr, _ = np.linalg.qr(rng.normal(size=(k, k)))
+    top = 1e4
+    lam0 = np.r_[top * (1.0 + np.r_[1e-10, 3e-10, 1e-9, 3e-9, 1e-8, 3e-8] * np.arange(1, 7)[::-1]),
+                 np.linspace(1.0, top, k - 6)]
+    A = (Qr * lam0) @ Qr.T
+    lam, Q = sts.sym_eig(dev(A))
+    lam, Q = host(lam), host(Q)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-12)
+    assert np.linalg.norm(A @ Q - Q * lam) <= 1e-12 * np.linalg.norm(A) * math.sqrt(k)
+    k = 600
+    Qr, _ = np.linalg.qr(rng.normal(size=(k, k)))
+    lam0 = np.logspace(0, 10, k)
+    A = (Qr * lam0) @ Qr.T
+    A = 0.5 * (A + A.T)
+    lam, Q = sts.sym_eig(dev(A))
+    lam, Q = host(lam), host(Q)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-12)
+    assert np.linalg.norm(A @ Q - Q * lam) <= 1e-12 * np.linalg.norm(A) * math.sqrt(k)
+    np.testing.assert_allclose(np.sort(lam), sla.eigvalsh(A), rtol=0, atol=1e-12 * lam0.max())
+
+
 # ---------------------------------------------------------------- a7: time sweep
 
 # nt below, at and far above the number of time chunks per component (16);
