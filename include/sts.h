@@ -152,6 +152,17 @@ typedef struct {
                                precedence over precond_fp32 in the FP32 rounds.  2 = the FP32
                                Kx solves only, 3 = the FP32 Gram-Schmidt pass only (the two
                                parts apart); 0 = FP64 throughout; default 0 */
+  int32_t orth_lag;         /* 1 = lagged re-orthogonalisation of the Mx Gram-Schmidt of the
+                               basis (Sec. 4's orthonormal columns; the block form of the delayed
+                               second pass of classical Gram-Schmidt run twice): a new block is
+                               orthogonalised once and normalised provisionally, the next block
+                               is expanded from it, and its second pass comes with the next
+                               block's first in the same two reads of the basis, halving the
+                               reads per block; blocks before a residual check get both passes
+                               at once.  Not used in the rational space, with the FP32 first
+                               pass (mixed 1 or 3), or in 1-D (small bases, kappa(Mx^-1 Kx) up
+                               to 1e10).  0 = both passes per block; default 1 */
+  int32_t pad_;             /* zero */
 } sts_opts;
 
 typedef struct {

@@ -46,7 +46,8 @@ class Opts(C.Structure):
                 ("defl_tol", C.c_double), ("mem_budget", C.c_int64), ("restart", C.c_int32),
                 ("profile", C.c_int32), ("inner_precond", C.c_int32), ("rational", C.c_int32),
                 ("residual_qr", C.c_int32), ("inner_relax", C.c_int32),
-                ("precond_fp32", C.c_int32), ("mixed", C.c_int32)]
+                ("precond_fp32", C.c_int32), ("mixed", C.c_int32), ("orth_lag", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -382,7 +382,7 @@ constexpr double kThirdPassRatio = 1e-2;
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
                          int64_t ldw, int ncols, double defl, OrthScratch& s, int* idx,
-                         hipStream_t st, double* KW) {
+                         hipStream_t st, double* KW, bool first_done) {
   const int64_t nh = g.nh;
   int opsM[16];
   for (int c = 0; c < 16; ++c) opsM[c] = STS_OP_M;
@@ -412,10 +412,13 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
     STS_HIP(hipStreamSynchronize(st));
     return *s.host;
   };
-  // Mx-norms on entry: the reference for "already in the span of V"
-  stencil_apply(g, K, M, opsM, ncols, W, ldw, MW, ldw, st);
-  gemm_tn(nh, ncols, ncols, W, ldw, MW, ldw, s.G, 16, s.part, st);
-  copy_cols(1, ncols, s.G, 17, s.norm0, 1, st);
+  // Mx-norms on entry: the reference for "already in the span of V" (with
+  // first_done the caller has formed them and the first pass)
+  if (!first_done) {
+    stencil_apply(g, K, M, opsM, ncols, W, ldw, MW, ldw, st);
+    gemm_tn(nh, ncols, ncols, W, ldw, MW, ldw, s.G, 16, s.part, st);
+    copy_cols(1, ncols, s.G, 17, s.norm0, 1, st);
+  }
   // the second pass with the reduced-matrix columns of the previous block in
   // the same read of V: [C | Kred | Mred] = V^T [Mx W, Kx V_p, Mx V_p] (the
   // coefficients from Mx W, formed by the stencil, rather than from the
@@ -433,8 +436,12 @@ int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, cons
   };
   // classical Gram-Schmidt against V, twice
   s.pend_done = false;
-  if (s.V32) cgs32(ncols);
-  else cgs(ncols);
+  if (first_done) {
+  } else if (s.V32) {
+    cgs32(ncols);
+  } else {
+    cgs(ncols);
+  }
   if (s.pend_n > 0 && k > 0) cgs_fused(ncols);
   else cgs(ncols);
   // Cholesky-QR of the block with deflation
@@ -743,7 +750,13 @@ struct sts_problem {
   // block's re-orthogonalisation pass forms them in its read of V
   int64_t pend_start = 0, pend_size = 0;
   int64_t blk_start = 0, blk_size = 0;
-  std::vector<int> tags;  // 0: positive power, 1: negative power
+  // lagged re-orthogonalisation: a block orthogonalised once and normalised
+  // provisionally, at V[:, k .. k + prov) with its exact images in KV, MV; the
+  // next block is expanded from it, and its second pass comes with the next
+  // block's first (prov_norm0: its entry norms, the deflation reference)
+  int64_t prov = 0;
+  DevBuf prov_norm0;
+  std::vector<int> tags;  // 0: positive power, 1: negative power (final and provisional columns)
   GrowBuf V, MV, KV;      // basis and its images, grown with the space
   GrowBuf V32;            // mixed precision: FP32 copy of V (first Gram-Schmidt pass)
   bool want_v32 = false;  // V32 is allocated and grown with the basis
@@ -818,12 +831,15 @@ void ensure_capacity(sts_problem* P, int64_t need, int64_t limit, int64_t budget
               "basis of " + std::to_string(kc) + " columns needs " + std::to_string(bytes) +
                   " bytes, above the memory budget");
   const int64_t transient = ld * P->kcap * 8;
+  STS_REQUIRE(P->k + P->prov <= P->kcap, STS_E_STATE, "basis columns beyond the capacity");
   if (P->grow_hook) P->grow_hook(bytes - capacity_bytes(P, P->kcap) + transient);
   hipStream_t st = P->stream;
   const int64_t old = P->kcap;
-  P->V.ensure(ld * kc * 8, ld * P->k * 8, st);
-  P->MV.ensure(ld * kc * 8, ld * P->k * 8, st);
-  P->KV.ensure(ld * kc * 8, ld * P->k * 8, st);
+  // the kept columns include a provisional block and its images
+  const int64_t keep = ld * (P->k + P->prov) * 8;
+  P->V.ensure(ld * kc * 8, keep, st);
+  P->MV.ensure(ld * kc * 8, keep, st);
+  P->KV.ensure(ld * kc * 8, keep, st);
   if (P->want_v32) P->V32.ensure(ld * kc * 4, ld * P->v32_cols * 4, st);
   // small buffers with leading dimension kc: copy column by column
   auto regrow = [&](DevBuf& b, int64_t cols, int64_t rows_keep, int64_t cols_keep) {
@@ -872,11 +888,9 @@ void fetch(sts_problem* P, const double* src, int n, double* dst) {
 // the Mx inner product (CGS2, then two Cholesky-QR passes with deflation),
 // pack the kept ones at V[:, k..), fill MV, KV, the reduced matrices and beta.
 // Returns the number of kept columns; keep_idx receives their source indices.
-int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
-  hipStream_t st = P->stream;
-  const int64_t nh = P->nh, ld = P->ldv, k = P->k;
-  double* W = P->V.d() + k * ld;
-  double* MW = P->MV.d() + k * ld;
+// Scratch of the block orthogonalisation, with the pending reduced-matrix
+// columns of the last final block (formed in the next pass over V).
+OrthScratch orth_scratch(sts_problem* P) {
   OrthScratch s;
   s.part = P->tn_part.d();
   s.G = P->gram.d();
@@ -887,9 +901,8 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
   s.info = static_cast<CholInfo*>(P->cinfo.p);
   s.host = reinterpret_cast<CholInfo*>(P->pinned);
   s.V32 = P->use_v32 ? reinterpret_cast<const float*>(P->V32.base) : nullptr;
-  const int64_t kc = P->kcap;
   if (P->pend_size > 0) {
-    const int64_t ps = P->pend_start;
+    const int64_t ps = P->pend_start, ld = P->ldv, kc = P->kcap;
     s.pend_n = (int)P->pend_size;
     s.pend_K = P->KV.d() + ps * ld;
     s.pend_M = P->MV.d() + ps * ld;
@@ -897,30 +910,192 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
     s.pend_Mout = P->Mred.d() + ps * kc;
     s.pend_ldc = kc;
   }
+  return s;
+}
+
+// The pass over V formed the pending columns: mirror them into the rows.
+void consume_pending(sts_problem* P, const OrthScratch& s) {
+  if (!s.pend_done) return;
+  const int64_t ps = P->pend_start, pk = P->pend_size, kc = P->kcap;
+  mirror((int)ps, (int)pk, P->Kred.d() + ps * kc, kc, P->Kred.d() + ps, kc, P->stream);
+  mirror((int)ps, (int)pk, P->Mred.d() + ps * kc, kc, P->Mred.d() + ps, kc, P->stream);
+  P->alg_bytes += 8.0 * P->nh * 2 * pk;
+  P->pend_size = 0;
+}
+
+// A final block at V[:, k0 .. k0 + kept): its reduced-matrix columns become
+// pending, its rows of beta = V^T F1 are formed, V32 gets its rounding.
+void register_block(sts_problem* P, int64_t k0, int kept) {
+  const int64_t nh = P->nh, ld = P->ldv;
+  double* W = P->V.d() + k0 * ld;
+  if (P->use_v32) {
+    round_cols(nh, kept, W, ld, reinterpret_cast<float*>(P->V32.base) + k0 * ld, ld, P->stream);
+    P->v32_cols = k0 + kept;
+  }
+  P->pend_start = k0;
+  P->pend_size = kept;
+  gemm_tn(nh, kept, P->p, W, ld, P->F1.d(), ld, P->beta.d() + k0, P->kcap, P->tn_part.d(),
+          P->stream);
+  P->alg_bytes += (4.0 * 16.0 - 8.0) * nh * kept;
+}
+
+int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
+  hipStream_t st = P->stream;
+  const int64_t nh = P->nh, ld = P->ldv, k = P->k;
+  double* W = P->V.d() + k * ld;
+  double* MW = P->MV.d() + k * ld;
+  OrthScratch s = orth_scratch(P);
   double* KW = P->KV.d() + k * ld;
   const int kept = orthonormalize_block(P->grid, P->K, P->M, P->V.d(), P->MV.d(), ld, k, W, MW,
                                         ld, ncols, defl, s, keep_idx, st, KW);
   P->alg_bytes += 2.0 * s.cgs_passes * 8.0 * nh * k + s.cgs32_passes * 12.0 * nh * k +
                   8.0 * 16.0 * nh * ncols;
-  if (s.pend_done) {
-    // the previous block's reduced-matrix columns came with the pass: mirror
-    const int64_t ps = P->pend_start, pk = P->pend_size;
-    mirror((int)ps, (int)pk, P->Kred.d() + ps * kc, kc, P->Kred.d() + ps, kc, st);
-    mirror((int)ps, (int)pk, P->Mred.d() + ps * kc, kc, P->Mred.d() + ps, kc, st);
-    P->alg_bytes += 8.0 * nh * 2 * pk;
-    P->pend_size = 0;
-  }
+  consume_pending(P, s);
   if (kept == 0) return 0;
-  if (P->use_v32) {
-    round_cols(nh, kept, W, ld, reinterpret_cast<float*>(P->V32.base) + k * ld, ld, st);
-    P->v32_cols = k + kept;
+  register_block(P, k, kept);
+  return kept;
+}
+
+// Lagged re-orthogonalisation (the delayed second pass of classical
+// Gram-Schmidt run twice, after Swirydowicz et al., "Low synchronization
+// Gram-Schmidt and GMRES algorithms", 2020, in block form and the Mx inner
+// product).  The new block W (at V[:, k + prov ..), expanded from the
+// provisional block P~ = V[:, k .. k + prov)) and P~ are orthogonalised
+// against the final basis V_k = V[:, 0 .. k) together: one read of V_k forms
+// [c d] = V_k^T Mx [P~ W] (and the pending reduced-matrix columns), one more
+// removes V_k [c d].  That is P~'s second pass and W's first, so each block
+// costs two reads of V instead of four.  P~ - V_k c is then normalised
+// (Cholesky-QR with deflation against its entry norms; P~ was normalised once,
+// so this factor is well conditioned) and becomes final; W drops its
+// components along it and is normalised provisionally, or, when final_now
+// (a residual check follows), gets its second pass at once.  Spans are those
+// of the classical scheme: W was expanded from P~ rather than from the final
+// P, and P~ - P lies in span(V_k), whose images the nested extended Krylov
+// space already holds.  Returns the kept columns of the new block, now at
+// V[:, k' ..) with k' = P->k after the call (final) or provisional (the
+// caller sets P->prov).
+int append_lagged(sts_problem* P, int nw, double defl, bool final_now, int* idx) {
+  const int bp = (int)P->prov;
+  if (bp == 0 && final_now) return append_block(P, nw, defl, idx);
+  hipStream_t st = P->stream;
+  const Grid& g = P->grid;
+  const int64_t nh = P->nh, ld = P->ldv, kc = P->kcap;
+  int64_t k = P->k;
+  int opsM[16];
+  for (int c = 0; c < 16; ++c) opsM[c] = STS_OP_M;
+  OrthScratch s = orth_scratch(P);
+  auto fetch_info = [&]() {
+    STS_HIP(hipMemcpyAsync(s.host, s.info, sizeof(CholInfo), hipMemcpyDeviceToHost, st));
+    STS_HIP(hipStreamSynchronize(st));
+    return *s.host;
+  };
+  double* W = P->V.d() + (k + bp) * ld;
+  double* MW = P->MV.d() + (k + bp) * ld;
+  // entry Mx-norms of the new block (its deflation reference) and Mx W
+  stencil_apply(g, P->K, P->M, opsM, nw, W, ld, MW, ld, st);
+  gemm_tn(nh, nw, nw, W, ld, MW, ld, s.G, 16, s.part, st);
+  copy_cols(1, nw, s.G, 17, s.norm0, 1, st);
+  P->alg_bytes += 40.0 * nh * nw;
+  // [P~ W] against V_k: one read for the coefficients (with the pending
+  // columns), one for the update
+  if (k > 0) {
+    const double* B[3] = {P->MV.d() + k * ld, s.pend_K, s.pend_M};
+    const int nb[3] = {bp + nw, s.pend_n, s.pend_n};
+    double* C[3] = {s.C, s.pend_Kout, s.pend_Mout};
+    const int64_t ldc[3] = {s.ldc, s.pend_ldc, s.pend_ldc};
+    gemm_tn_segs(nh, (int)k, P->V.d(), ld, s.pend_n > 0 ? 3 : 1, B, nb, ld, C, ldc, s.part, st);
+    s.pend_done = s.pend_n > 0;
+    gemm_nn_sub(nh, (int)k, bp + nw, P->V.d(), ld, s.C, s.ldc, P->V.d() + k * ld, ld, st);
+    P->alg_bytes += 16.0 * nh * k + 8.0 * nh * (3 * (bp + nw) + 2 * s.pend_n);
   }
-  // the new block's reduced-matrix columns V^T [Kx W, Mx W] are formed by
-  // the next block's re-orthogonalisation pass (or flush_pending)
-  P->pend_start = k;
-  P->pend_size = kept;
-  gemm_tn(nh, kept, P->p, W, ld, P->F1.d(), ld, P->beta.d() + k, kc, P->tn_part.d(), st);
-  P->alg_bytes += (4.0 * 16.0 - 8.0) * nh * kept;
+  consume_pending(P, s);
+  if (bp > 0) {
+    // P~ - V_k c: normalise, with its entry norms as the deflation reference
+    double* Pc = P->V.d() + k * ld;
+    double* MPc = P->MV.d() + k * ld;
+    double* KPc = P->KV.d() + k * ld;
+    stencil_apply(g, P->K, P->M, opsM, bp, Pc, ld, MPc, ld, st);
+    gemm_tn(nh, bp, bp, Pc, ld, MPc, ld, s.G, 16, s.part, st);
+    chol_deflate(bp, s.G, 16, P->prov_norm0.d(), defl, kBlockDefl, s.Rinv, s.info, st);
+    apply_rinv(nh, bp, s.info, s.Rinv, Pc, nullptr, ld, nullptr, st);
+    CholInfo h = fetch_info();
+    const int kept_p = h.kept;
+    if (kept_p > 0 && h.rmin < kThirdPassRatio && k > 0) {
+      // a small pivot amplified the rounding left along V_k: one more pass
+      stencil_apply(g, P->K, P->M, opsM, kept_p, Pc, ld, MPc, ld, st);
+      gemm_tn(nh, (int)k, kept_p, P->V.d(), ld, MPc, ld, s.C, s.ldc, s.part, st);
+      gemm_nn_sub(nh, (int)k, kept_p, P->V.d(), ld, s.C, s.ldc, Pc, ld, st);
+      stencil_apply(g, P->K, P->M, opsM, kept_p, Pc, ld, MPc, ld, st);
+      gemm_tn(nh, kept_p, kept_p, Pc, ld, MPc, ld, s.G, 16, s.part, st);
+      chol_deflate(kept_p, s.G, 16, nullptr, 0.0, kBlockDefl, s.Rinv, s.info, st);
+      apply_rinv(nh, kept_p, s.info, s.Rinv, Pc, nullptr, ld, nullptr, st);
+      h = fetch_info();
+      STS_REQUIRE(h.kept == kept_p, STS_E_NUMERIC, "block lost rank in its third pass");
+      P->alg_bytes += 16.0 * nh * k;
+    }
+    // the provisional tags of the kept columns, in order
+    std::vector<int> ptag(kept_p);
+    for (int j = 0; j < kept_p; ++j) ptag[j] = P->tags[k + h.idx[j]];
+    P->tags.resize(k);
+    for (int j = 0; j < kept_p; ++j) P->tags.push_back(ptag[j]);
+    P->prov = 0;
+    if (kept_p > 0) {
+      stencil_apply_km(g, P->K, P->M, kept_p, Pc, ld, KPc, ld, MPc, ld, st);   // exact images
+      register_block(P, k, kept_p);
+      P->blk_start = k;
+      P->blk_size = kept_p;
+      P->k = k + kept_p;
+      P->alg_bytes += 64.0 * nh * kept_p;
+    }
+    // W next to the final columns (a deflated P leaves a gap), then W -= P e
+    // with e = (Mx P)^T W
+    if (kept_p < bp)
+      for (int j = 0; j < nw; ++j)
+        copy_cols(nh, 1, P->V.d() + (k + bp + j) * ld, ld, P->V.d() + (k + kept_p + j) * ld, ld,
+                  st);
+    if (kept_p > 0) {
+      double* Wn = P->V.d() + (k + kept_p) * ld;
+      gemm_tn(nh, kept_p, nw, MPc, ld, Wn, ld, s.C, s.ldc, s.part, st);
+      gemm_nn_sub(nh, kept_p, nw, Pc, ld, s.C, s.ldc, Wn, ld, st);
+      P->alg_bytes += 8.0 * nh * (2 * kept_p + 3 * nw);
+    }
+    k = P->k;
+    W = P->V.d() + k * ld;
+    MW = P->MV.d() + k * ld;
+  }
+  if (final_now) {
+    // W's second pass (with the pending columns of P) and its Cholesky-QR;
+    // its entry norms stay in the shared norm0 buffer
+    OrthScratch s2 = orth_scratch(P);
+    s2.V32 = nullptr;
+    const int kept = orthonormalize_block(g, P->K, P->M, P->V.d(), P->MV.d(), ld, k, W, MW, ld,
+                                          nw, defl, s2, idx, st, P->KV.d() + k * ld, true);
+    P->alg_bytes += 2.0 * s2.cgs_passes * 8.0 * nh * k + 8.0 * 16.0 * nh * nw;
+    consume_pending(P, s2);
+    if (kept == 0) return 0;
+    register_block(P, k, kept);
+    return kept;
+  }
+  // provisional normalisation of W (one Cholesky-QR with deflation)
+  stencil_apply(g, P->K, P->M, opsM, nw, W, ld, MW, ld, st);
+  gemm_tn(nh, nw, nw, W, ld, MW, ld, s.G, 16, s.part, st);
+  chol_deflate(nw, s.G, 16, s.norm0, defl, kBlockDefl, s.Rinv, s.info, st);
+  apply_rinv(nh, nw, s.info, s.Rinv, W, nullptr, ld, nullptr, st);
+  const CholInfo h = fetch_info();
+  const int kept = h.kept;
+  for (int j = 0; j < kept; ++j) idx[j] = h.idx[j];
+  if (kept == 0) return 0;
+  stencil_apply_km(g, P->K, P->M, kept, W, ld, P->KV.d() + k * ld, ld, MW, ld, st);
+  // entry norms of the kept columns, the reference of the lagged pass
+  double n0[16];
+  STS_HIP(hipMemcpyAsync(n0, s.norm0, nw * 8, hipMemcpyDeviceToHost, st));
+  STS_HIP(hipStreamSynchronize(st));
+  double n1[16];
+  for (int j = 0; j < kept; ++j) n1[j] = n0[idx[j]];
+  STS_HIP(hipMemcpyAsync(P->prov_norm0.p, n1, kept * 8, hipMemcpyHostToDevice, st));
+  STS_HIP(hipStreamSynchronize(st));
+  P->alg_bytes += 8.0 * nh * (6 * nw + 4 * kept);
+  (void)kc;
   return kept;
 }
 
@@ -1133,7 +1308,7 @@ double mass_scale(const Grid& g, const Stencil& M) {
 
 void run_shifted_block(sts_problem* P, double s, int ncols, const double* const* b,
                        const sts_opts& o) {
-  double* x0 = P->V.d() + P->k * P->ldv;
+  double* x0 = P->V.d() + (P->k + P->prov) * P->ldv;   // after a provisional block
   if (o.inner_precond != 0 && P->tri_ok) {
     // work: the CG residual vectors (2 kMaxCols columns of ldv), idle here
     tridiag_shifted_solve(P->grid, P->K, P->M, s, ncols, b, x0, P->ldv, P->cg.w.r[0], P->ldv,
@@ -1452,7 +1627,7 @@ void run_mg_k(sts_problem* P, int nk, const double* const* b, double* x, const s
 void run_cg_block(sts_problem* P, const int* ops, int ncols, const double* const* b,
                   const sts_opts& o, int* perm) {
   for (int c = 0; c < ncols; ++c) perm[c] = c;
-  double* x0 = P->V.d() + P->k * P->ldv;
+  double* x0 = P->V.d() + (P->k + P->prov) * P->ldv;   // after a provisional block
   if (o.inner_precond != 0 && P->tri_ok) {
     // 1-D: Kx and Mx are tridiagonal; solve every column directly
     tridiag_solve(P->grid, P->K, P->M, ops, ncols, b, x0, P->ldv, P->tri_fac.d(), P->stream);
@@ -1717,6 +1892,7 @@ void sts_default_opts(sts_opts* o) {
   o->restart = 0;
   o->profile = 0;
   o->inner_precond = 1;
+  o->orth_lag = 1;
 }
 
 const char* sts_last_error(void) { return g_last_error.c_str(); }
@@ -1845,6 +2021,7 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
     P->rinv.alloc(16 * 16 * 8);
     P->cinfo.alloc(sizeof(CholInfo));
     P->norm0.alloc(16 * 8);
+    P->prov_norm0.alloc(16 * 8);
     P->Lb.alloc(16 * 16 * 8);
     P->T1.alloc(16 * nt * 8);
     P->okflag.alloc(16);
@@ -1897,7 +2074,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
                     o.defl_tol >= 0.0 && o.defl_tol < 1.0 && o.check_every >= 0 &&
                     o.residual_qr >= -1 && o.residual_qr <= 1 && o.inner_relax >= 0 &&
                     o.inner_relax <= 6 && (o.precond_fp32 == 0 || o.precond_fp32 == 1) &&
-                    o.mixed >= 0 && o.mixed <= 3,
+                    o.mixed >= 0 && o.mixed <= 3 && (o.orth_lag == 0 || o.orth_lag == 1),
                 STS_E_INVALID, "invalid options");
     P->residual_qr = o.residual_qr;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1906,6 +2083,7 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
     const int b2 = 2 * p;
     if (o.restart) {
       P->k = P->k_sol = P->blk_start = P->blk_size = 0;
+      P->prov = 0;
       P->tags.clear();
       P->solved = false;
       P->inner_K = P->inner_M = 0;
@@ -1935,8 +2113,9 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       }
     }
     // the basis grows with the space, to at most max_outer + 2 more blocks
-    const int64_t cap_limit = P->k + (int64_t)b2 * (o.max_outer + 2);
-    ensure_capacity(P, P->k + initial_capacity(p, o.max_outer), cap_limit, o.mem_budget);
+    const int64_t cap_limit = P->k + P->prov + (int64_t)b2 * (o.max_outer + 2);
+    ensure_capacity(P, P->k + P->prov + initial_capacity(p, o.max_outer), cap_limit,
+                    o.mem_budget);
     if (v32 && P->v32_cols < P->k) {
       // a basis extended from an FP64 solve: round its columns once
       round_cols(P->nh, (int)(P->k - P->v32_cols), P->V.d() + P->v32_cols * P->ldv, P->ldv,
@@ -1944,6 +2123,17 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
       P->v32_cols = P->k;
     }
     P->use_v32 = v32;
+    // lagged re-orthogonalisation (sts_opts.orth_lag), except in the rational
+    // space, with the FP32 first pass, and in 1-D: there V is small (its reads
+    // cost microseconds) and kappa(Mx^{-1} Kx) reaches 1e10, so the next block's
+    // expansion from a once-orthogonalised block amplifies its components
+    // along V (a 65535-node solve no longer met its residual floor).  A
+    // provisional block left by an earlier lagged solve is dropped otherwise.
+    const bool lag = o.orth_lag != 0 && !o.rational && !v32 && P->grid.dim > 1;
+    if (!lag && P->prov > 0) {
+      P->tags.resize(P->k);
+      P->prov = 0;
+    }
     // STS_TRACE=1: one line per residual check on stderr
     const char* tr = std::getenv("STS_TRACE");
     const bool trace = tr && tr[0] == '1';
@@ -2003,7 +2193,10 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
           std::fprintf(stderr, "sts: %.4f s outer %d k %lld\n",
                        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(),
                        outer, (long long)P->k);
-        ensure_capacity(P, P->k + b2, cap_limit, o.mem_budget);
+        ensure_capacity(P, P->k + P->prov + b2, cap_limit, o.mem_budget);
+        // a residual check follows this block: it is made final at once
+        const bool due = o.check_every > 0 ? (outer % o.check_every == 0 || outer == o.max_outer)
+                                           : (outer >= next_check || outer == o.max_outer);
         // inner tolerance of this block: relaxed in inverse proportion to the
         // residual (the block's share of the solution shrinks with it)
         sts_opts oi = o;
@@ -2012,8 +2205,9 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
           oi.inner_rtol = std::max(o.inner_rtol,
                                    std::min(1e-4, std::pow(10.0, -o.inner_relax) * o.tol / r));
         }
-        // expand with the last block
-        const int64_t bs = P->blk_start, bsz = P->blk_size;
+        // expand with the last block (the provisional one if there is one)
+        const int64_t bs = P->prov > 0 ? P->k : P->blk_start;
+        const int64_t bsz = P->prov > 0 ? P->prov : P->blk_size;
         int ops[kMaxCols];
         const double* b[kMaxCols];
         int n = 0;
@@ -2050,12 +2244,19 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
         std::vector<int> src_tag(n);
         for (int j = 0; j < n; ++j) src_tag[j] = P->tags[bs + perm[j]];
         int idx[16];
+        // lagged: the provisional block becomes final here (P->k moves past
+        // it) and the new block stays provisional unless a check follows
+        const int kept = lag ? append_lagged(P, n, o.defl_tol, due, idx)
+                             : append_block(P, n, o.defl_tol, idx);
         const int64_t kprev = P->k;
-        const int kept = append_block(P, n, o.defl_tol, idx);
         for (int j = 0; j < kept; ++j) P->tags.push_back(src_tag[idx[j]]);
-        P->blk_start = kprev;
-        P->blk_size = kept;
-        P->k = kprev + kept;
+        if (!lag || due) {
+          P->blk_start = kprev;
+          P->blk_size = kept;
+          P->k = kprev + kept;
+        } else {
+          P->prov = kept;
+        }
         if (kept == 0) {
           // every new column lies in the space: it is invariant under A and
           // A^{-1}, so the Galerkin solution is exact in exact arithmetic.  A
@@ -2079,8 +2280,6 @@ sts_status sts_solve(sts_problem* P, const sts_opts* opts_in, sts_info* info) {
           result = STS_OK;
           break;
         }
-        const bool due = o.check_every > 0 ? (outer % o.check_every == 0 || outer == o.max_outer)
-                                           : (outer >= next_check || outer == o.max_outer);
         if (!due) continue;
         if (o.rational) {
           // no projected-residual formula for this space: the exact residual

@@ -403,7 +403,7 @@ struct OrthScratch {
 int orthonormalize_block(const Grid& g, const Stencil& K, const Stencil& M, const double* V,
                          const double* MV, int64_t ldv, int64_t k, double* W, double* MW,
                          int64_t ldw, int ncols, double defl, OrthScratch& s, int* idx,
-                         hipStream_t st, double* KW = nullptr);
+                         hipStream_t st, double* KW = nullptr, bool first_done = false);
 // W[:, 0:kept] = W[:, idx] * Rinv (kept x kept upper triangular), also for MW.
 void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, double* W,
                 double* MW, int64_t ldw, double* tmp, hipStream_t st);
