@@ -371,7 +371,7 @@ def bench_serve(args) -> int:
         # (3-D grids with n > 63)
         o = dict(opts, inner_relax=2 if w.dim == 3 else 1)
         if args.serve_mixed:
-            o["mixed"] = 1
+            o["mixed"] = args.mixed_mode
         return o
 
     budget = 200 << 30
@@ -521,6 +521,10 @@ def main() -> int:
                     help="heat3d: FP32 bulk with FP64 refinement (sts_opts.mixed): FP32 multigrid "
                          "PCG inside FP64 defect correction for the Kx solves and an FP32 first "
                          "Gram-Schmidt pass; reduced solve and exact residual FP64")
+    ap.add_argument("--mixed-mode", type=int, default=2, choices=(1, 2, 3),
+                    help="sts_opts.mixed of the mixed-precision runs: 1 = FP32 Kx solves and the FP32 "
+                         "first Gram-Schmidt pass, 2 = FP32 Kx solves with the lagged FP64 "
+                         "Gram-Schmidt (two reads of V per block), 3 = the FP32 pass only")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="heat3d (FP64 run): timed solves of the same problem with sts_opts.mixed, "
                          "reported as mixed_precision with their error against the FP64 run "
@@ -601,7 +605,7 @@ def main() -> int:
         # inside FP64 CG (sts_opts.precond_fp32); everything else stays FP64
         opts["precond_fp32"] = 1
     if args.mixed:
-        opts["mixed"] = 1
+        opts["mixed"] = args.mixed_mode
     for i in range(args.warmup):
         info = prob.solve(**opts)
         _log(f"warmup {i}: {info['status']} outer={info['outer_its']} k={info['k']} "
@@ -692,7 +696,7 @@ def main() -> int:
         # the same problem with FP32 bulk work and FP64 refinement
         # (sts_opts.mixed), gated at relative error 1e-8 against this FP64 run
         # on sampled time columns
-        mopts = dict(opts, mixed=1)
+        mopts = dict(opts, mixed=args.mixed_mode)
         minfo = prob.solve(**mopts)   # first mixed solve: the FP32 copy of V is allocated
         torch.cuda.synchronize()
         mlat = []
@@ -706,7 +710,8 @@ def main() -> int:
         Um = prob.solution_columns(cols, device=True)
         merr = float(torch.linalg.norm(Um - Uf) / torch.linalg.norm(Uf))
         mt = sum(mlat) / len(mlat)
-        mixed = {"dtype": "f32+f64_refine", "value": w.nh * w.nt / mt, "unit": "dof/s",
+        mixed = {"dtype": "f32+f64_refine", "sts_opts_mixed": args.mixed_mode,
+                 "value": w.nh * w.nt / mt, "unit": "dof/s",
                  "ms_per_step": 1e3 * mt, "steps": len(mlat),
                  "rel_error_vs_fp64_run": merr, "error_columns": len(cols),
                  "res_true": minfo["res_true"], "outer_its": minfo["outer_its"], "k": minfo["k"],
