@@ -265,11 +265,15 @@ sts_status sts_create(const sts_space* space, const sts_bidiag* Dt, const sts_bi
  * exact solution has a smaller residual).  When the projected residual meets
  * tol but the exact one does not, the library estimates that floor
  * (info->res_floor); if it is at least tol / 2 and the exact residual lies
- * within tol + floor, the solve is accepted (info->floor_limited = 1).  Where
- * the floor is at least tol / 2 the inner solves carry the same rounding, and
- * the projected residual itself can stall above tol: a solve whose projected
- * residual has not halved over three checks is accepted with an exact
- * residual within tol + 4 floor (floor_limited = 1), else it continues.
+ * within tol + floor, the solve is accepted (info->floor_limited = 1).  The
+ * floor grows like sqrt(k / 64) beyond 64 basis columns (the backward error
+ * of the order-k reduced eigendecomposition).  Where the estimated floor
+ * alone exceeds tol, the projected residual is driven to tol + floor instead
+ * of tol.  Where the floor is at least tol / 2 the inner solves carry the
+ * same rounding, and the projected residual itself can stall above tol: a
+ * solve whose projected residual has not halved over three checks is
+ * accepted with an exact residual within tol + 4 floor (floor_limited = 1),
+ * else it continues.
  *
  * Returns STS_OK; STS_E_NOT_CONVERGED when max_outer blocks did not reach tol
  * (the factors of the last iterate are kept and fetchable); STS_E_NUMERIC on a
@@ -284,12 +288,6 @@ sts_status sts_solve(sts_problem* prob, const sts_opts* opts, sts_info* info);
  * the basis size mu_mem that Sec. 5, Table 1 reports. */
 sts_status sts_rank(const sts_problem* prob, int64_t* k);
 
-/* Copy the factors of the low-rank solution U ~= V Y of Sec. 4 (V the
- * Mx-orthonormal spatial basis, Y the reduced solution) into caller buffers:
- * V (Nh x k, ld ldv >= Nh) and Y (k x nt, ld ldy >= k), either may be NULL;
- * `mem` says whether the buffers are host or device memory.  The library
- * keeps its copies.  STS_E_STATE before a successful or not-converged solve.
- * Synchronous. */
 /* Columns of the low-rank solution U ~= V Y of Sec. 4 at chosen time steps
  * without copying V: U[:, j] = V Y[:, cols[j]] for j < ncols, computed on the
  * device (the nodal values at time t^{cols[j] + 1}).  cols (host, ncols >= 1
@@ -299,6 +297,12 @@ sts_status sts_rank(const sts_problem* prob, int64_t* k);
 sts_status sts_solution_columns(const sts_problem* prob, const int64_t* cols, int32_t ncols,
                                 double* U, int64_t ldu, int32_t mem, void* stream);
 
+/* Copy the factors of the low-rank solution U ~= V Y of Sec. 4 (V the
+ * Mx-orthonormal spatial basis, Y the reduced solution) into caller buffers:
+ * V (Nh x k, ld ldv >= Nh) and Y (k x nt, ld ldy >= k), either may be NULL;
+ * `mem` says whether the buffers are host or device memory.  The library
+ * keeps its copies.  STS_E_STATE before a successful or not-converged solve.
+ * Synchronous. */
 sts_status sts_get_factors(const sts_problem* prob, double* V, int64_t ldv, double* Y,
                            int64_t ldy, int32_t mem, void* stream);
 
@@ -323,8 +327,17 @@ sts_status sts_kernel_profile(sts_problem* prob, int32_t kernel, double* seconds
 /* Short name of an sts_kernel ("" if out of range). */
 const char* sts_kernel_name(int32_t kernel);
 
-/* Free everything the problem holds.  NULL-safe. */
+/* Free everything the problem holds.  NULL-safe.  Device blocks of 16 MiB and
+ * more go to the library's block cache (kept per device, up to 32 GiB idle,
+ * for later problems of similar size; reusing a block avoids seconds of
+ * driver work at gigabyte sizes), the rest back to the driver. */
 void sts_destroy(sts_problem* prob);
+
+/* Return every idle block of the library's cache to the driver (e.g. before
+ * another allocator on the same GPU needs the memory); blocks held by live
+ * problems are not affected.  A failed allocation inside the library does
+ * this by itself before it reports STS_E_NOMEM.  Thread-safe. */
+void sts_release_cached_memory(void);
 
 /* Description of the last error on this thread ("" if none). */
 const char* sts_last_error(void);

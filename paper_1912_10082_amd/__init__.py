@@ -10,5 +10,6 @@ from .binding import (  # noqa: F401
     EXPORTED, STS_FE_P1_1D, STS_FE_P1_2D, STS_FE_Q1_3D_7PT, STS_OP_K, STS_OP_M, Pool, Problem,
     Server, adaptive_shift, footprint, shifted_solve,
     STSError, apply_op, basis_update, cg, default_opts, gram, load, m_orthonormalize, make_space,
-    mass_solve, mg_vcycle, pcg_mg, pcg_mg_mixed, pcg_mg_refined, sym_eig, time_matrices, time_sweep, tridiag_solve,
+    mass_solve, mg_vcycle, pcg_mg, pcg_mg_mixed, pcg_mg_refined, release_cached_memory, sym_eig,
+    time_matrices, time_sweep, tridiag_solve,
 )

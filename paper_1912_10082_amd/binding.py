@@ -98,6 +98,7 @@ _SIGS = {
     "sts_true_residual": (C.c_int, [_P, _D]),
     "sts_numerical_rank": (C.c_int, [_P, C.POINTER(_I64)]),
     "sts_destroy": (None, [_P]),
+    "sts_release_cached_memory": (None, []),
     "sts_kernel_profile": (C.c_int, [_P, _I32, C.POINTER(_F64), C.POINTER(_I64), C.POINTER(_F64)]),
     "sts_kernel_name": (C.c_char_p, [_I32]),
     "sts_apply_op": (C.c_int, [C.POINTER(Space), _I32, _P, _I64, _P, _I64, _I32, _P]),
@@ -244,6 +245,12 @@ def _bidiag(diag: np.ndarray, sub: np.ndarray):
 # ----------------------------------------------------------------------------
 # API
 # ----------------------------------------------------------------------------
+
+def release_cached_memory() -> None:
+    """Return the library's idle cached device blocks to the driver
+    (sts_release_cached_memory)."""
+    load().sts_release_cached_memory()
+
 
 def default_opts(**kw) -> Opts:
     o = Opts()

@@ -956,6 +956,12 @@ int append_block(sts_problem* P, int ncols, double defl, int* keep_idx) {
   return kept;
 }
 
+// dst[j] = src[idx[j]] for the columns a Cholesky-QR kept (their entry norms)
+__global__ void gather_kept_kernel(const double* src, const CholInfo* info, double* dst) {
+  const int j = threadIdx.x;
+  if (j < info->kept) dst[j] = src[info->idx[j]];
+}
+
 // Lagged re-orthogonalisation (the delayed second pass of classical
 // Gram-Schmidt run twice, after Swirydowicz et al., "Low synchronization
 // Gram-Schmidt and GMRES algorithms", 2020, in block form and the Mx inner
@@ -1087,13 +1093,8 @@ int append_lagged(sts_problem* P, int nw, double defl, bool final_now, int* idx)
   if (kept == 0) return 0;
   stencil_apply_km(g, P->K, P->M, kept, W, ld, P->KV.d() + k * ld, ld, MW, ld, st);
   // entry norms of the kept columns, the reference of the lagged pass
-  double n0[16];
-  STS_HIP(hipMemcpyAsync(n0, s.norm0, nw * 8, hipMemcpyDeviceToHost, st));
-  STS_HIP(hipStreamSynchronize(st));
-  double n1[16];
-  for (int j = 0; j < kept; ++j) n1[j] = n0[idx[j]];
-  STS_HIP(hipMemcpyAsync(P->prov_norm0.p, n1, kept * 8, hipMemcpyHostToDevice, st));
-  STS_HIP(hipStreamSynchronize(st));
+  gather_kept_kernel<<<1, 16, 0, st>>>(s.norm0, s.info, P->prov_norm0.d());
+  STS_HIP(hipGetLastError());
   P->alg_bytes += 8.0 * nh * (6 * nw + 4 * kept);
   (void)kc;
   return kept;
@@ -2545,6 +2546,8 @@ const char* sts_kernel_name(int32_t kernel) {
       "mg_restrict", "pcg_reduce", "residual_qr", "gram_reduce"};
   return (kernel >= 0 && kernel < STS_K_COUNT) ? names[kernel] : "";
 }
+
+void sts_release_cached_memory(void) { cache_trim(-1); }
 
 void sts_destroy(sts_problem* P) {
   if (!P) return;
