@@ -16,11 +16,15 @@
 
 #include <cmath>
 
+#include "mg_common.h"
 #include "sts_internal.h"
 
 namespace sts {
 
 namespace {
+
+using mgc::ld_or_zero;
+using mgc::StagedN;
 
 constexpr int kT = 256;
 constexpr int TX = 64, TY = 16;      // owned nodes per tile
@@ -71,15 +75,30 @@ __global__ __launch_bounds__(kT) void mass_cheb_kernel(MassArgs a) {
   const bool fresh = a.k0 == 0;
   const double* xg = fresh ? nullptr : a.xin + (size_t)col * a.ld;
   const double* dg = fresh ? nullptr : a.din + (size_t)col * a.ld;
-  for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int gx = x0 + i % W, gy = y0 + i / W;
-    const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n;
-    const size_t g = (size_t)gy * n + gx;
-    bs[i] = in ? bg[g] : 0.0;
-    const double xv = (in && !fresh) ? xg[g] : 0.0;
-    xs[0][i] = xv;
-    xs[1][i] = xv;
-    ds[i] = (in && !fresh) ? dg[g] : 0.0;
+  {
+    // all of a thread's loads in flight before the first LDS store
+    auto at = [&](const double* v, int i) {
+      const int gx = x0 + i % W, gy = y0 + i / W;
+      return ld_or_zero(v, gx >= 0 && gx < n && gy >= 0 && gy < n, (size_t)gy * n + gx);
+    };
+    StagedN<W * H, double, kT> hb, hx, hd;
+    hb.load([&](int i) { return at(bg, i); });
+    if (!fresh) {
+      hx.load([&](int i) { return at(xg, i); });
+      hd.load([&](int i) { return at(dg, i); });
+    }
+    hb.store(bs);
+    if (fresh) {
+      for (int i = threadIdx.x; i < W * H; i += kT) {
+        xs[0][i] = 0.0;
+        xs[1][i] = 0.0;
+        ds[i] = 0.0;
+      }
+    } else {
+      hx.store(xs[0]);
+      hx.store(xs[1]);
+      hd.store(ds);
+    }
   }
   __syncthreads();
   int cur = 0;

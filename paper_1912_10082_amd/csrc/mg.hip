@@ -183,9 +183,13 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
   const Op op = a.op;
   const double inv_d = 1.0 / op_diag<SH>(op);
   const double* bf = a.bf + (size_t)col * a.ldf;
-  for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int gx = R.ox + i % W, gy = R.oy + i / W;
-    bs[i] = (gx >= 0 && gx < nf && gy >= 0 && gy < nf) ? bf[(size_t)gy * nf + gx] : 0.0;
+  {
+    StagedN<W * H, double, kT> hb;
+    hb.load([&](int i) {
+      const int gx = R.ox + i % W, gy = R.oy + i / W;
+      return ld_or_zero(bf, gx >= 0 && gx < nf && gy >= 0 && gy < nf, (size_t)gy * nf + gx);
+    });
+    hb.store(bs);
   }
   __syncthreads();
   const int cur = presmooth<SH, W, H>(R, a.sm, inv_d, bs, us, ds, op);
@@ -249,18 +253,27 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   const double* ecg = a.ec + (size_t)col * a.ldc;
   // b and the pre-smoothed iterate of the down launch (zero outside the
   // domain in both buffers: the Dirichlet values the stencil reads)
-  for (int i = threadIdx.x; i < W * H; i += kT) {
-    const int gx = R.ox + i % W, gy = R.oy + i / W;
-    const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf;
-    const size_t g = (size_t)gy * nf + gx;
-    bs[i] = in ? bf[g] : 0.0;
-    us[0][i] = in ? xpg[g] : 0.0;
-    us[1][i] = 0.0;
-    ds[i] = 0.0;
-  }
-  for (int i = threadIdx.x; i < EW * EH; i += kT) {
-    const int I = cox + i % EW, J = coy + i / EW;
-    es[i] = (I >= 0 && I < nc && J >= 0 && J < nc) ? ecg[(size_t)J * nc + I] : 0.0;
+  // (all of a thread's loads in flight before the first LDS store)
+  {
+    StagedN<W * H, double, kT> hb, hu;
+    StagedN<EW * EH, double, kT> he;
+    auto at = [&](const double* g, int i) {
+      const int gx = R.ox + i % W, gy = R.oy + i / W;
+      return ld_or_zero(g, gx >= 0 && gx < nf && gy >= 0 && gy < nf, (size_t)gy * nf + gx);
+    };
+    hb.load([&](int i) { return at(bf, i); });
+    hu.load([&](int i) { return at(xpg, i); });
+    he.load([&](int i) {
+      const int I = cox + i % EW, J = coy + i / EW;
+      return ld_or_zero(ecg, I >= 0 && I < nc && J >= 0 && J < nc, (size_t)J * nc + I);
+    });
+    hb.store(bs);
+    hu.store(us[0]);
+    he.store(es);
+    for (int i = threadIdx.x; i < W * H; i += kT) {
+      us[1][i] = 0.0;
+      ds[i] = 0.0;
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < W * H; i += kT) {
@@ -631,14 +644,15 @@ __global__ __launch_bounds__(kT) void pcg_a_kernel(PCGArgs a) {
   const double* pin = a.pin + (size_t)col * a.ld;
   double* pout = a.pout + (size_t)col * a.ld;
   double* qg = a.q + (size_t)col * a.ld;
-  for (int i = threadIdx.x; i < RW * RH; i += kT) {
-    const int gx = x0 - 1 + i % RW, gy = y0 - 1 + i / RW;
-    double v = 0.0;
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
+  {
+    StagedN<RW * RH, double, kT> hp;
+    hp.load([&](int i) {
+      const int gx = x0 - 1 + i % RW, gy = y0 - 1 + i / RW;
+      const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n;
       const size_t g = (size_t)gy * n + gx;
-      v = zg[g] + beta * pin[g];
-    }
-    ps[i] = v;
+      return ld_or_zero(zg, in, g) + beta * ld_or_zero(pin, in, g);
+    });
+    hp.store(ps);
   }
   __syncthreads();
   double part = 0.0;
@@ -680,16 +694,32 @@ __global__ __launch_bounds__(kT) void pcg_b_kernel(PCGArgs a) {
   double* rg = a.r + (size_t)col * a.ld;
   const double* pg = a.pout + (size_t)col * a.ld;
   const double* qg = a.q + (size_t)col * a.ld;
-  double part = 0.0;
-  for (int i = threadIdx.x; i < TX * TY; i += kT) {
+  // every load of the thread's nodes before the first store (outside the
+  // domain the loads read node 0 and nothing is stored)
+  constexpr int NN = TX * TY / kT;
+  static_assert(NN * kT == TX * TY, "whole tile nodes per thread");
+  size_t g[NN];
+  bool in[NN];
+  double xv[NN], pv[NN], rv[NN], qv[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    const int i = threadIdx.x + k * kT;
     const int gx = x0 + i % TX, gy = y0 + i / TX;
-    if (gx < n && gy < n) {
-      const size_t g = (size_t)gy * n + gx;
-      xg[g] += alpha * pg[g];
-      const double rv = rg[g] - alpha * qg[g];
-      rg[g] = rv;
-      part += rv * rv;
-    }
+    in[k] = gx < n && gy < n;
+    g[k] = in[k] ? (size_t)gy * n + gx : 0;
+    xv[k] = xg[g[k]];
+    pv[k] = pg[g[k]];
+    rv[k] = rg[g[k]];
+    qv[k] = qg[g[k]];
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    if (!in[k]) continue;
+    xg[g[k]] = xv[k] + alpha * pv[k];
+    const double r = rv[k] - alpha * qv[k];
+    rg[g[k]] = r;
+    part += r * r;
   }
   part = block_sum<kT>(part, red);
   if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = part;

@@ -116,15 +116,48 @@ __device__ __forceinline__ double k7_diag(double c, double sm) {
   return SH ? 6.0 * c + 64.0 * sm : 6.0 * c;
 }
 
-// The tile of g (n^3 nodes, x fastest) with a one-node halo into s; zero
+template <int N, class S>
+using Staged = StagedN<N, S, kT>;
+
+// Slot i of the tile of g (n^3 nodes, x fastest) with a one-node halo; zero
 // outside the domain (the Dirichlet values).
 template <class S>
+__device__ __forceinline__ S halo_at(const S* g, int n, const Tile3& T, int i) {
+  const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
+  const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
+  return ld_or_zero(g, in, ((size_t)gz * n + gy) * n + gx);
+}
+
+template <class S>
 __device__ __forceinline__ void load_halo(const S* g, int n, const Tile3& T, S* s) {
-  for (int i = threadIdx.x; i < NR; i += kT) {
-    const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
-    const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n;
-    s[i] = in ? g[((size_t)gz * n + gy) * n + gx] : (S)0;
+  Staged<NR, S> h;
+  h.load([&](int i) { return halo_at(g, n, T, i); });
+  h.store(s);
+}
+
+// The tile nodes of a thread (tile node threadIdx.x + k kT): global index g
+// (0 outside the domain, so that loads at g stay branch-free), LDS index q in
+// the one-node-halo array, and whether the node is inside.
+constexpr int NC = TX * TY * TZ / kT;
+static_assert(NC * kT == TX * TY * TZ, "whole tile nodes per thread");
+struct Core {
+  size_t g[NC];
+  int q[NC];
+  bool in[NC];
+};
+
+__device__ __forceinline__ Core core_nodes(int n, const Tile3& T) {
+  Core c;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int i = threadIdx.x + k * kT;
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int gx = T.x0 + lx, gy = T.y0 + ly, gz = T.z0 + lz;
+    c.in[k] = gx < n && gy < n && gz < n;
+    c.g[k] = c.in[k] ? ((size_t)gz * n + gy) * n + gx : 0;
+    c.q[k] = ((lz + 1) * RY + ly + 1) * RX + lx + 1;
   }
+  return c;
 }
 
 // Visit the tile's own nodes: f(global index, LDS index in the halo array).
@@ -180,17 +213,20 @@ template <bool SH, class B, class S>
 __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
   constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
-  constexpr int NC = TX * TY * TZ / kT;                  // tile nodes per thread
   static_assert(NR <= BX * BY * BZ, "u_2 fits where b was");
   __shared__ S sh[BX * BY * BZ];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf;
   const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
-  for (int i = threadIdx.x; i < BX * BY * BZ; i += kT) {
-    const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
-    const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
-    sh[i] = in ? (S)bf[((size_t)gz * nf + gy) * nf + gx] : (S)0;
+  {
+    Staged<BX * BY * BZ, S> hb;
+    hb.load([&](int i) {
+      const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
+      const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
+      return (S)ld_or_zero(bf, in, ((size_t)gz * nf + gy) * nf + gx);
+    });
+    hb.store(sh);
   }
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
@@ -254,11 +290,15 @@ __global__ __launch_bounds__(kT) void mg3_restrict_kernel(Level3Args a) {
   const int nf = a.nf, nc = a.nc;
   const int fx0 = 2 * C.x0, fy0 = 2 * C.y0, fz0 = 2 * C.z0;
   const S* r = static_cast<const S*>(a.d0) + (size_t)col * a.ldf;
-  for (int i = threadIdx.x; i < SX * SY * SZ; i += kT) {
-    const int gx = fx0 + i % SX, gy = fy0 + (i / SX) % SY, gz = fz0 + i / (SX * SY);
-    // fine nodes beyond the domain are never gathered (every coarse node's
-    // neighbours lie inside); read them as zero
-    rs[i] = (gx < nf && gy < nf && gz < nf) ? r[((size_t)gz * nf + gy) * nf + gx] : (S)0;
+  {
+    Staged<SX * SY * SZ, S> hr;
+    hr.load([&](int i) {
+      const int gx = fx0 + i % SX, gy = fy0 + (i / SX) % SY, gz = fz0 + i / (SX * SY);
+      // fine nodes beyond the domain are never gathered (every coarse node's
+      // neighbours lie inside); read them as zero
+      return ld_or_zero(r, gx < nf && gy < nf && gz < nf, ((size_t)gz * nf + gy) * nf + gx);
+    });
+    hr.store(rs);
   }
   __syncthreads();
   S* bc = static_cast<S*>(a.bc) + (size_t)col * a.ldc;
@@ -302,14 +342,25 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf, nc = a.nc;
-  load_halo(static_cast<const S*>(a.xp) + (size_t)col * a.ldf, nf, T, us);
   const int ox = T.x0 / 2 - 1, oy = T.y0 / 2 - 1, oz = T.z0 / 2 - 1;
+  const S* xp = static_cast<const S*>(a.xp) + (size_t)col * a.ldf;
   const S* ec = static_cast<const S*>(a.ec) + (size_t)col * a.ldc;
-  for (int i = threadIdx.x; i < EX * EY * EZ; i += kT) {
+  const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
+  // every global read of the launch in flight before the first wait
+  Staged<NR, S> hu;
+  Staged<EX * EY * EZ, S> he;
+  hu.load([&](int i) { return halo_at(xp, nf, T, i); });
+  he.load([&](int i) {
     const int I = ox + i % EX, J = oy + (i / EX) % EY, K = oz + i / (EX * EY);
     const bool in = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
-    es[i] = in ? ec[((size_t)K * nc + J) * nc + I] : (S)0;
-  }
+    return ld_or_zero(ec, in, ((size_t)K * nc + J) * nc + I);
+  });
+  const Core C = core_nodes(nf, T);
+  B bv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) bv[k] = bf[C.g[k]];
+  hu.store(us);
+  he.store(es);
   __syncthreads();
   for (int i = threadIdx.x; i < NR; i += kT) {
     const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
@@ -318,14 +369,16 @@ __global__ __launch_bounds__(kT) void mg3_post1_kernel(Level3Args a) {
   }
   __syncthreads();
   const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
-  const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
   S* u1 = static_cast<S*>(a.u1) + (size_t)col * a.ldf;
   S* d0 = static_cast<S*>(a.d0) + (size_t)col * a.ldf;
-  for_core(nf, T, [&](size_t g, int q) {
-    const double d = a.c0 * inv_d * ((double)bf[g] - k7<SH, RX, RY>(us, q, a.c, a.sm));
-    d0[g] = (S)d;
-    u1[g] = (S)((double)us[q] + d);
-  });
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (!C.in[k]) continue;
+    const int q = C.q[k];
+    const double d = a.c0 * inv_d * ((double)bv[k] - k7<SH, RX, RY>(us, q, a.c, a.sm));
+    d0[C.g[k]] = (S)d;
+    u1[C.g[k]] = (S)((double)us[q] + d);
+  }
 }
 
 // post2: d_1 = a_1 d_0 + c_1 (b - K u_1) / D, e = u_1 + d_1; per-tile (b, e).
@@ -336,20 +389,35 @@ __global__ __launch_bounds__(kT) void mg3_post2_kernel(Level3Args a) {
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf;
-  load_halo(static_cast<const S*>(a.u1) + (size_t)col * a.ldf, nf, T, us);
-  __syncthreads();
-  const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
+  const S* u1 = static_cast<const S*>(a.u1) + (size_t)col * a.ldf;
   const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
   const S* d0 = static_cast<const S*>(a.d0) + (size_t)col * a.ldf;
+  // every global read of the launch in flight before the first wait
+  Staged<NR, S> hu;
+  hu.load([&](int i) { return halo_at(u1, nf, T, i); });
+  const Core C = core_nodes(nf, T);
+  B bv[NC];
+  S dv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    bv[k] = bf[C.g[k]];
+    dv[k] = d0[C.g[k]];
+  }
+  hu.store(us);
+  __syncthreads();
+  const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
   B* ef = static_cast<B*>(a.ef) + (size_t)col * a.ldf;
   double part = 0.0;
-  for_core(nf, T, [&](size_t g, int q) {
-    const double b = bf[g];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (!C.in[k]) continue;
+    const int q = C.q[k];
+    const double b = bv[k];
     const double e =
-        (double)us[q] + (a.a1 * (double)d0[g] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
-    ef[g] = (B)e;
+        (double)us[q] + (a.a1 * (double)dv[k] + a.c1 * inv_d * (b - k7<SH, RX, RY>(us, q, a.c, a.sm)));
+    ef[C.g[k]] = (B)e;
     part += b * (double)(B)e;   // (b, e) of the stored result
-  });
+  }
   if (a.part) {
     part = block_sum<kT>(part, red);
     if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
@@ -631,14 +699,10 @@ __global__ __launch_bounds__(kT) void pcg3_a_kernel(PCG3Args a) {
   const V* zg = static_cast<const V*>(a.z) + (size_t)col * a.ld;
   const V* pin = static_cast<const V*>(a.pin) + (size_t)col * a.ld;
   const V bv = (V)beta;
-  for (int i = threadIdx.x; i < NR; i += kT) {
-    const int gx = T.x0 - 1 + i % RX, gy = T.y0 - 1 + (i / RX) % RY, gz = T.z0 - 1 + i / (RX * RY);
-    V v = (V)0;
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n && gz >= 0 && gz < n) {
-      const size_t g = ((size_t)gz * n + gy) * n + gx;
-      v = zg[g] + bv * pin[g];
-    }
-    ps[i] = v;
+  {
+    Staged<NR, V> hp;
+    hp.load([&](int i) { return halo_at(zg, n, T, i) + bv * halo_at(pin, n, T, i); });
+    hp.store(ps);
   }
   __syncthreads();
   V* pout = static_cast<V*>(a.pout) + (size_t)col * a.ld;
@@ -681,13 +745,25 @@ __global__ __launch_bounds__(kT) void pcg3_b_kernel(PCG3Args a) {
   const V* pg = static_cast<const V*>(a.pout) + (size_t)col * a.ld;
   const V* qg = static_cast<const V*>(a.q) + (size_t)col * a.ld;
   const V av = (V)alpha;
+  const Core C = core_nodes(a.n, T);
+  XT xv[NC];
+  V pv[NC], rv[NC], qv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    xv[k] = xg[C.g[k]];
+    pv[k] = pg[C.g[k]];
+    rv[k] = rg[C.g[k]];
+    qv[k] = qg[C.g[k]];
+  }
   V part = (V)0;
-  for_core(a.n, T, [&](size_t g, int) {
-    xg[g] += (XT)alpha * (XT)pg[g];
-    const V rv = rg[g] - av * qg[g];
-    rg[g] = rv;
-    part += rv * rv;
-  });
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (!C.in[k]) continue;
+    xg[C.g[k]] = xv[k] + (XT)alpha * (XT)pv[k];
+    const V r = rv[k] - av * qv[k];
+    rg[C.g[k]] = r;
+    part += r * r;
+  }
   const double tot = block_sum_v<V>(part, redv);
   if (threadIdx.x == 0) a.part_rr[(size_t)col * a.max_tiles + t] = tot;
 }
@@ -769,11 +845,14 @@ __global__ __launch_bounds__(kT) void defect3_kernel(Defect3Args a) {
   const double* bg = a.b[jb];
   double* rg = a.r[jb];
   double part = 0.0;
-  for_core(a.n, T, [&](size_t g, int q) {
-    const double rv = bg[g] - k7<SH, RX, RY>(us, q, a.c, a.sm);
-    rg[g] = rv;
+  const Core C = core_nodes(a.n, T);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (!C.in[k]) continue;
+    const double rv = bg[C.g[k]] - k7<SH, RX, RY>(us, C.q[k], a.c, a.sm);
+    rg[C.g[k]] = rv;
     part += rv * rv;
-  });
+  }
   part = block_sum<kT>(part, red);
   if (threadIdx.x == 0) a.part[(size_t)jb * a.max_tiles + t] = part;
 }
@@ -807,11 +886,14 @@ __global__ __launch_bounds__(kT) void replace3_kernel(Replace3Args a) {
   const double* bg = a.b[col];
   float* rg = a.r + (size_t)col * a.ld;
   double part = 0.0;
-  for_core(a.n, T, [&](size_t g, int q) {
-    const double rv = bg[g] - k7<SH, RX, RY>(us, q, a.c, a.sm);
-    rg[g] = (float)rv;
+  const Core C = core_nodes(a.n, T);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (!C.in[k]) continue;
+    const double rv = bg[C.g[k]] - k7<SH, RX, RY>(us, C.q[k], a.c, a.sm);
+    rg[C.g[k]] = (float)rv;
     part += rv * rv;
-  });
+  }
   part = block_sum<kT>(part, red);
   if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
 }

@@ -27,6 +27,40 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// g[idx] if `in`, else zero, without a branch: outside, the load reads the
+// column's first element instead and the value is dropped.  A load under a
+// branch sits in a basic block of its own and waits for its data before the
+// next one is issued; branch-free loads of a fully unrolled loop are all in
+// flight together, which is what a latency-bound tile fill needs.
+template <class T>
+__device__ __forceinline__ T ld_or_zero(const T* g, bool in, size_t idx) {
+  const T v = g[in ? idx : 0];
+  return in ? v : (T)0;
+}
+
+// A thread's share of an LDS fill of N slots by NT threads (slots
+// threadIdx.x + k NT): load() issues every load into registers, store()
+// writes them, so a kernel can put several fills (and its other global
+// reads) in flight before the first wait.  get(i) must be branch-free (ld_or_zero); the last partial
+// round re-reads slot N - 1 and drops it.
+template <int N, class S, int NT>
+struct StagedN {
+  static constexpr int NI = (N + NT - 1) / NT;
+  S v[NI];
+  template <class F>
+  __device__ __forceinline__ void load(F&& get) {
+#pragma unroll
+    for (int k = 0; k < NI; ++k) v[k] = get(min((int)threadIdx.x + k * NT, N - 1));
+  }
+  __device__ __forceinline__ void store(S* s) const {
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int i = threadIdx.x + k * NT;
+      if (i < N) s[i] = v[k];
+    }
+  }
+};
+
 // Consecutive block ids go round-robin over the 8 XCDs; give each XCD a
 // contiguous range of tiles so that halo neighbours share an L2.
 __device__ __forceinline__ int xcd_remap(int bid, int n) {

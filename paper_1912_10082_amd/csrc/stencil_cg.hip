@@ -571,15 +571,28 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(ApplyArgs a) {
   double* yg = a.Y + (size_t)c * a.ldy;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t sxy = (size_t)nx * ny;
-  for (int i = threadIdx.x; i < NR; i += kThreads) {
-    const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
-    const int gx = x0 - H + lx;
-    const int gy = DIM >= 2 ? y0 - H + ly : 0;
-    const int gz = DIM >= 3 ? z0 - H + lz : 0;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
-      v = xg[(size_t)gz * sxy + (size_t)gy * nx + gx];
-    xs[i] = v;
+  {
+    // all of a thread's halo loads in flight together: branch-free (outside
+    // the domain the load reads the column's first node and the value is
+    // dropped), fully unrolled, stored to LDS after the last one is issued
+    constexpr int NL = (NR + kThreads - 1) / kThreads;
+    double v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = min((int)threadIdx.x + k * kThreads, NR - 1);
+      const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+      const int gx = x0 - H + lx;
+      const int gy = DIM >= 2 ? y0 - H + ly : 0;
+      const int gz = DIM >= 3 ? z0 - H + lz : 0;
+      const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+      const double x = xg[in ? (size_t)gz * sxy + (size_t)gy * nx + gx : 0];
+      v[k] = in ? x : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * kThreads;
+      if (i < NR) xs[i] = v[k];
+    }
   }
   __syncthreads();
   if (a.Y2) {

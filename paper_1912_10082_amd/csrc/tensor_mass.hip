@@ -40,6 +40,7 @@ struct TensorArgs {
   double scale;          // 6 / h, applied once per pass
 };
 
+constexpr int kLine = 8;
 __global__ __launch_bounds__(256) void tensor_mass_kernel(TensorArgs a) {
   const int n = a.n;
   const int64_t lines = (int64_t)n * n;
@@ -62,15 +63,43 @@ __global__ __launch_bounds__(256) void tensor_mass_kernel(TensorArgs a) {
   double* out = a.out[c] + base;
   const double* cf = a.fac;
   const double* mf = a.fac + n;
+  // The recurrences are serial but their loads are not: each chunk of
+  // kLine elements is loaded into registers before its steps run, so a
+  // thread has kLine loads in flight instead of one.  (In place, in == out:
+  // every element is read before the same thread writes it.)
   double y = 0.0;
-  for (int i = 0; i < n; ++i) {
-    y = (a.scale * in[i * stride] - y) * mf[i];
-    out[i * stride] = y;
+  for (int i0 = 0; i0 < n; i0 += kLine) {
+    double v[kLine], m[kLine];
+#pragma unroll
+    for (int u = 0; u < kLine; ++u) {
+      v[u] = in[min(i0 + u, n - 1) * stride];
+      m[u] = mf[min(i0 + u, n - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kLine; ++u) {
+      const int i = i0 + u;
+      if (i < n) {
+        y = (a.scale * v[u] - y) * m[u];
+        out[i * stride] = y;
+      }
+    }
   }
   double z = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    z = out[i * stride] - cf[i] * z;
-    out[i * stride] = z;
+  for (int i1 = n - 1; i1 >= 0; i1 -= kLine) {
+    double v[kLine], f[kLine];
+#pragma unroll
+    for (int u = 0; u < kLine; ++u) {
+      v[u] = out[max(i1 - u, 0) * stride];
+      f[u] = cf[max(i1 - u, 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < kLine; ++u) {
+      const int i = i1 - u;
+      if (i >= 0) {
+        z = v[u] - f[u] * z;
+        out[i * stride] = z;
+      }
+    }
   }
 }
 
@@ -81,6 +110,29 @@ __global__ __launch_bounds__(256) void tensor_mass_kernel(TensorArgs a) {
 // the staged chunk.  Forward sweep left to right (y written out), then the
 // backward sweep right to left over y.
 constexpr int kChunk = 16;
+
+// Elements x0 .. x0 + kChunk - 1 of the wave's 64 lines into T (zero past the
+// grid): branch-free loads (outside, the column's first element is read and
+// dropped), all kChunk of a lane issued before the first LDS store.
+__device__ __forceinline__ void stage_chunk(double (*T)[kChunk + 1], const double* g, int64_t line0,
+                                            int64_t lines, int n, int x0, int lane) {
+  double v[kChunk];
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int e = lane + 64 * k;
+    const int l = e / kChunk, x = e % kChunk;
+    const int64_t line = line0 + l;
+    const bool in = line < lines && x0 + x < n;
+    const double w = g[in ? line * n + x0 + x : 0];
+    v[k] = in ? w : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int e = lane + 64 * k;
+    T[e / kChunk][e % kChunk] = v[k];
+  }
+}
+
 __global__ __launch_bounds__(256) void tensor_mass_x_kernel(TensorArgs a) {
   __shared__ double tile[4][64][kChunk + 1];
   const int n = a.n;
@@ -97,15 +149,17 @@ __global__ __launch_bounds__(256) void tensor_mass_x_kernel(TensorArgs a) {
   double y = 0.0;
   for (int ch = 0; ch < nch; ++ch) {
     const int x0 = ch * kChunk;
-    for (int e = lane; e < 64 * kChunk; e += 64) {
-      const int l = e / kChunk, x = e % kChunk;
-      const int64_t line = line0 + l;
-      T[l][x] = (line < lines && x0 + x < n) ? in[line * n + x0 + x] : 0.0;
-    }
+    stage_chunk(T, in, line0, lines, n, x0, lane);
+    double m[kChunk];
+#pragma unroll
+    for (int x = 0; x < kChunk; ++x) m[x] = mf[min(x0 + x, n - 1)];
     __syncthreads();
-    for (int x = 0; x < kChunk && x0 + x < n; ++x) {
-      y = (a.scale * T[lane][x] - y) * mf[x0 + x];
-      T[lane][x] = y;
+#pragma unroll
+    for (int x = 0; x < kChunk; ++x) {
+      if (x0 + x < n) {
+        y = (a.scale * T[lane][x] - y) * m[x];
+        T[lane][x] = y;
+      }
     }
     __syncthreads();
     for (int e = lane; e < 64 * kChunk; e += 64) {
@@ -118,15 +172,15 @@ __global__ __launch_bounds__(256) void tensor_mass_x_kernel(TensorArgs a) {
   double z = 0.0;
   for (int ch = nch - 1; ch >= 0; --ch) {
     const int x0 = ch * kChunk;
-    for (int e = lane; e < 64 * kChunk; e += 64) {
-      const int l = e / kChunk, x = e % kChunk;
-      const int64_t line = line0 + l;
-      T[l][x] = (line < lines && x0 + x < n) ? out[line * n + x0 + x] : 0.0;
-    }
+    stage_chunk(T, out, line0, lines, n, x0, lane);
+    double f[kChunk];
+#pragma unroll
+    for (int x = 0; x < kChunk; ++x) f[x] = cf[min(x0 + x, n - 1)];
     __syncthreads();
+#pragma unroll
     for (int x = kChunk - 1; x >= 0; --x) {
       if (x0 + x < n) {
-        z = T[lane][x] - cf[x0 + x] * z;
+        z = T[lane][x] - f[x] * z;
         T[lane][x] = z;
       }
     }
