@@ -565,29 +565,41 @@ __global__ __launch_bounds__(256) void gemm_nn_sub4_kernel(int64_t rows, int m, 
     const int kk = k0 + g;
     const bool kok = kk < m;
     const double* ap = A + ra + (int64_t)(kok ? kk : 0) * lda;
+    // loads without a branch (ap and the C index stay in bounds when the
+    // step is past m), so that they do not wait on each other
     double a[4];
     if (VEC && full) {
-      const double2 x = kok ? *(const double2*)ap : double2{0.0, 0.0};
-      const double2 y = kok ? *(const double2*)(ap + 2) : double2{0.0, 0.0};
-      a[0] = x.x;
-      a[1] = x.y;
-      a[2] = y.x;
-      a[3] = y.y;
+      const double2 x = *(const double2*)ap;
+      const double2 y = *(const double2*)(ap + 2);
+      a[0] = kok ? x.x : 0.0;
+      a[1] = kok ? x.y : 0.0;
+      a[2] = kok ? y.x : 0.0;
+      a[3] = kok ? y.y : 0.0;
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) a[s] = (kok && ra + s < rows) ? ap[s] : 0.0;
     }
-    const double b = (cok && kok) ? C[kk + (int64_t)i * ldc] : 0.0;
+    const double c = C[(kok ? kk : 0) + (int64_t)(cok ? i : 0) * ldc];
+    const double b = (cok && kok) ? c : 0.0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[s] = mfma(a[s], b, acc[s]);
   }
   if (cok) {
+    // the old values of the lane's outputs, four in flight together (rows
+    // past the end read row r0 and are not written back; four at a time
+    // keeps the register count, and so the occupancy, of the main loop)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      double w[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int64_t row = r0 + 4 * (4 * q + g) + s;
-        if (row < rows) W[row + (int64_t)i * ldw] -= acc[s][q];
+        w[s] = W[(row < rows ? row : r0) + (int64_t)i * ldw];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t row = r0 + 4 * (4 * q + g) + s;
+        if (row < rows) W[row + (int64_t)i * ldw] = w[s] - acc[s][q];
       }
     }
   }

@@ -44,15 +44,17 @@
 // FP32 in the LDS tile while the post-smoothing launches read b in FP64, so
 // the variant is linear and symmetric only up to single-precision rounding.
 // The rounding perturbs the preconditioner only, so the FP64 CG around it
-// reaches the same tolerances, and the finest level moves 64 instead of 96
-// bytes per node and column.
+// reaches the same tolerances.  The finest level moves 64 bytes per node and
+// column (96 with FP64 vectors in the same launches, 58 with the FP64
+// V-cycle's fused post-smoothing launch).
 //
 // Launches per smoothed level: "pre" (both pre-smoothing steps from zero,
 // which need b on a one-node halo only, on the tile and its halo, then the
 // residual; the iterate and the residual are stored), "restrict" (P^T of the
-// residual), "post1" (iterate + P e_c on a halo, first post-smoothing step)
-// and "post2" (second step, the result).  Fine-level launches work on
-// 32 x 8 x 4 tiles staged in LDS with a one- or two-node halo.
+// residual), "post" (iterate + P e_c on a two-node halo, both
+// post-smoothing steps, the result; in the FP32-storage V-cycle two launches,
+// "post1" and "post2", one per step).  Fine-level launches work on 32 x 8 x 4
+// tiles staged in LDS with a one- or two-node halo.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -179,12 +181,12 @@ struct Level3Args {
   int nf, nc;           // fine / coarse nodes per direction (nf = 2 nc + 1)
   int64_t ldf, ldc;     // column strides, in elements
   const void* bf;       // fine right-hand side (B)
-  void* xp;             // pre-smoothed iterate: written by pre, read by post1 (S)
+  void* xp;             // pre-smoothed iterate: written by pre, read by post (S)
   void* bc;             // restrict: coarse right-hand side (S)
-  const void* ec;       // post1: coarse correction (S)
+  const void* ec;       // post, post1: coarse correction (S)
   void* u1;             // post1 -> post2: iterate after the first step (S)
   void* d0;             // pre -> restrict: the residual; post1 -> post2: first Chebyshev direction (S)
-  void* ef;             // post2: result on the fine level (B)
+  void* ef;             // post, post2: result on the fine level (B)
   int ntx, nty, ntz;    // tiles of the launch
   int nlaunch;
   int cols[kMaxCols];
@@ -192,7 +194,7 @@ struct Level3Args {
   double c;             // stencil coefficient of the fine level
   double sm;            // shifted mass scale s (h/6)^3 of the fine level (0: Kx alone)
   double a1, c0, c1;    // Chebyshev coefficients of steps 0 and 1
-  double* part;         // post2: per-tile (b, e), may be null
+  double* part;         // post, post2: per-tile (b, e), may be null
   int max_tiles;
 };
 
@@ -204,7 +206,7 @@ struct Level3Args {
 
 // pre: u_1 = c_0 b / D, d_1 = a_1 u_1 + c_1 (b - K u_1) / D, u_2 = u_1 + d_1
 // on the tile and a one-node halo (from b on a two-node halo), then the
-// residual r = b - K u_2 on the tile.  Stores u_2 (for post1) and r.  One LDS
+// residual r = b - K u_2 on the tile.  Stores u_2 (for post) and r.  One LDS
 // array holds b first and u_2 after it (the values pass through registers),
 // which keeps five work-groups per compute unit.  LDS arrays hold the storage
 // type S (b rounded to it in the mixed-precision V-cycle); every value is
@@ -332,6 +334,125 @@ __device__ __forceinline__ double interp3(const S* es, int ox, int oy, int oz, i
   return 0.5 * ((double)c[0] + (double)c[ex + ey * EX + ez * EX * EY]);
 }
 
+// post: u = u_2 + P e_c on the tile and a two-node halo; the first step
+// d_0 = c_0 (b - K u) / D, u_1 = u + d_0 on the tile and a one-node halo;
+// the second step d_1 = a_1 d_0 + c_1 (b - K u_1) / D, e = u_1 + d_1 on the
+// tile; per-tile (b, e).  Every work-group computes the first step on its
+// halo itself (the same arithmetic its neighbour does for those nodes), so
+// u_1 and d_0 never go through global memory.  One LDS array holds u first,
+// then u_1 on the one-node halo followed by d_0 on the tile (the values pass
+// through registers).  u_1 and d_0 are rounded to the storage type S, as
+// stored vectors would be.
+template <bool SH, class B, class S>
+__global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
+  constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // u with a two-node halo
+  constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3, EZ = TZ / 2 + 3;
+  constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
+  static_assert(NR + TX * TY * TZ <= BX * BY * BZ, "u_1 and d_0 fit where u was");
+  __shared__ S sh[BX * BY * BZ];
+  __shared__ S es[EX * EY * EZ];
+  __shared__ double red[kT / 64];
+  STS_MG3_PROLOGUE(a)
+  const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
+  const int nf = a.nf, nc = a.nc;
+  // coarse nodes under the two-node halo: fine x0 - 2 interpolates from
+  // coarse x0 / 2 - 2, fine x0 + TX + 1 from coarse x0 / 2 + TX / 2
+  const int ox = T.x0 / 2 - 2, oy = T.y0 / 2 - 2, oz = T.z0 / 2 - 2;
+  const S* xp = static_cast<const S*>(a.xp) + (size_t)col * a.ldf;
+  const S* ec = static_cast<const S*>(a.ec) + (size_t)col * a.ldc;
+  const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
+  auto inside = [&](int gx, int gy, int gz) {
+    return gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
+  };
+  // every global read of the launch in flight before the first wait:
+  // u_2 on the two-node halo, e_c, b on the one-node halo and on the tile
+  Staged<BX * BY * BZ, S> hx;
+  Staged<EX * EY * EZ, S> he;
+  hx.load([&](int i) {
+    const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
+    return ld_or_zero(xp, inside(gx, gy, gz), ((size_t)gz * nf + gy) * nf + gx);
+  });
+  he.load([&](int i) {
+    const int I = ox + i % EX, J = oy + (i / EX) % EY, K = oz + i / (EX * EY);
+    const bool in = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
+    return ld_or_zero(ec, in, ((size_t)K * nc + J) * nc + I);
+  });
+  Staged<NR, B> hb;
+  hb.load([&](int i) { return halo_at(bf, nf, T, i); });
+  const Core C = core_nodes(nf, T);
+  B bv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) bv[k] = bf[C.g[k]];
+  hx.store(sh);
+  he.store(es);
+  __syncthreads();
+  // u = u_2 + P e_c (each thread updates its own slots)
+#pragma unroll
+  for (int k = 0; k < Staged<BX * BY * BZ, S>::NI; ++k) {
+    const int i = threadIdx.x + k * kT;
+    if (i < BX * BY * BZ) {
+      const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
+      if (inside(gx, gy, gz))
+        sh[i] = (S)((double)sh[i] + interp3<EX, EY>(es, ox, oy, oz, gx, gy, gz));
+    }
+  }
+  __syncthreads();
+  // first step on the tile and its one-node halo (zero outside the domain)
+  const double inv_d = 1.0 / k7_diag<SH>(a.c, a.sm);
+  S u1r[NU], d0r[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int i = threadIdx.x + k * kT;
+    S u1 = (S)0, d0 = (S)0;
+    if (i < NR) {
+      const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+      if (inside(T.x0 - 1 + lx, T.y0 - 1 + ly, T.z0 - 1 + lz)) {
+        const int q = ((lz + 1) * BY + ly + 1) * BX + lx + 1;
+        const double d = a.c0 * inv_d * ((double)hb.v[k] - k7<SH, BX, BY>(sh, q, a.c, a.sm));
+        d0 = (S)d;
+        u1 = (S)((double)sh[q] + d);
+      }
+    }
+    u1r[k] = u1;
+    d0r[k] = d0;
+  }
+  __syncthreads();
+  S* d0s = sh + NR;   // d_0 on the tile, x fastest
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int i = threadIdx.x + k * kT;
+    if (i < NR) {
+      sh[i] = u1r[k];
+      const int lx = i % RX - 1, ly = (i / RX) % RY - 1, lz = i / (RX * RY) - 1;
+      if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && lz >= 0 && lz < TZ)
+        d0s[(lz * TY + ly) * TX + lx] = d0r[k];
+    }
+  }
+  __syncthreads();
+  // second step on the tile
+  B* ef = static_cast<B*>(a.ef) + (size_t)col * a.ldf;
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (!C.in[k]) continue;
+    const int q = C.q[k];
+    const double b = bv[k];
+    const double d0 = d0s[threadIdx.x + k * kT];
+    const double e =
+        (double)sh[q] + (a.a1 * d0 + a.c1 * inv_d * (b - k7<SH, RX, RY>(sh, q, a.c, a.sm)));
+    ef[C.g[k]] = (B)e;
+    part += b * (double)(B)e;   // (b, e) of the stored result
+  }
+  if (a.part) {
+    part = block_sum<kT>(part, red);
+    if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
+  }
+}
+
+// The same two post-smoothing steps as two launches, for the FP32-storage
+// V-cycle: there the recomputation on the halo that the fused launch does
+// costs more than the stored u_1 and d_0 it saves (all arithmetic is FP64
+// while the vectors move half the bytes).
 // post1: u = u_2 + P e_c on the tile and its halo; d_0 = c_0 (b - K u) / D,
 // u_1 = u + d_0 on the tile.
 template <bool SH, class B, class S>
@@ -980,10 +1101,12 @@ double mg3_bytes_per_node(const MGPlan& p) {
   for (int l = 0; l < p.nlev; ++l) {
     const double nf = std::pow((double)p.n[l], 3), nc = std::pow((double)p.n[l + 1], 3);
     const double sb = (f32 && (l > 0 || all32)) ? 4.0 : 8.0, ss = f32 ? 4.0 : 8.0;
-    // pre: b -> xp, r; restrict: r -> b_c; post1: xp, b, e_c -> d0, u1;
-    // post2: u1, b, d0 -> e
-    b += (sb + 2.0 * ss) * nf + ss * (nf + nc) + ((sb + 3.0 * ss) * nf + ss * nc) +
-         (2.0 * sb + 2.0 * ss) * nf;
+    // pre: b -> xp, r; restrict: r -> b_c; then with FP64 vectors post: xp,
+    // b, e_c -> e, with FP32 ones post1: xp, b, e_c -> d0, u1 and post2: u1,
+    // b, d0 -> e
+    b += (sb + 2.0 * ss) * nf + ss * (nf + nc);
+    b += f32 ? ((sb + 3.0 * ss) * nf + ss * nc) + (2.0 * sb + 2.0 * ss) * nf
+             : (2.0 * sb + ss) * nf + ss * nc;
   }
   b += (f32 ? 24.0 : 48.0) * std::pow((double)p.exact, 3);
   return b / n0;
@@ -1023,18 +1146,27 @@ void level_up(Level3Args a, bool shifted, int nlaunch, hipStream_t st) {
   a.nty = (a.nf + TY - 1) / TY;
   a.ntz = (a.nf + TZ - 1) / TZ;
   const int blocks = a.ntx * a.nty * a.ntz * nlaunch;
-  const double post1 = ((sb + 3.0 * ss) * nf + ss * nc) * nlaunch;
-  const double post2 = (2.0 * sb + 2.0 * ss) * nf * nlaunch;
-  if (shifted)
-    launch(STS_K_MG_UP, post1, mg3_post1_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
-  else
-    launch(STS_K_MG_UP, post1, mg3_post1_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
-  STS_HIP(hipGetLastError());
-  if (shifted)
-    launch(STS_K_MG_UP, post2, mg3_post2_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
-  else
-    launch(STS_K_MG_UP, post2, mg3_post2_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
-  STS_HIP(hipGetLastError());
+  if constexpr (sizeof(S) == 8) {
+    const double post = ((2.0 * sb + ss) * nf + ss * nc) * nlaunch;
+    if (shifted)
+      launch(STS_K_MG_UP, post, mg3_post_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    else
+      launch(STS_K_MG_UP, post, mg3_post_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    STS_HIP(hipGetLastError());
+  } else {
+    const double post1 = ((sb + 3.0 * ss) * nf + ss * nc) * nlaunch;
+    const double post2 = (2.0 * sb + 2.0 * ss) * nf * nlaunch;
+    if (shifted)
+      launch(STS_K_MG_UP, post1, mg3_post1_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    else
+      launch(STS_K_MG_UP, post1, mg3_post1_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    STS_HIP(hipGetLastError());
+    if (shifted)
+      launch(STS_K_MG_UP, post2, mg3_post2_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    else
+      launch(STS_K_MG_UP, post2, mg3_post2_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    STS_HIP(hipGetLastError());
+  }
 }
 
 template <class T>
