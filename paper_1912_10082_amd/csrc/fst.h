@@ -47,8 +47,10 @@ __device__ __forceinline__ int bitrev(int j) {
 
 // Load the odd extensions of two length-m vectors (x1[j - 1], x2[j - 1] read
 // through `get`) in bit-reversed order: thread t places entries t and t + L.
-template <int L, class Get>
-__device__ __forceinline__ void fst_load(double2* z, int m, Get get) {
+// `also` runs after the stores and before the barrier (LDS stores of values
+// the caller loaded earlier, so that their loads overlap with these).
+template <int L, class Get, class Also>
+__device__ __forceinline__ void fst_load(double2* z, int m, Get get, Also also) {
   const int t = threadIdx.x;
   double2 v = double2{0.0, 0.0}, w = double2{0.0, 0.0};
   if (t >= 1 && t <= m) v = get(t - 1);                         // z_t = x_t
@@ -58,7 +60,13 @@ __device__ __forceinline__ void fst_load(double2* z, int m, Get get) {
   }
   z[bitrev<L>(t)] = v;
   z[bitrev<L>(t + L)] = w;
+  also();
   __syncthreads();
+}
+
+template <int L, class Get>
+__device__ __forceinline__ void fst_load(double2* z, int m, Get get) {
+  fst_load<L>(z, m, get, [] {});
 }
 
 }  // namespace sts

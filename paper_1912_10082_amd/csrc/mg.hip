@@ -509,13 +509,19 @@ __global__ __launch_bounds__(L) void fst_row_kernel(FstArgs a) {
   const int col = a.cols[blockIdx.y];
   if (a.st && !a.st[col].active) return;
   const int m = a.m;
-  for (int i = threadIdx.x; i < 2 * L; i += L) tw[i] = a.tw[i];
+  const double tw0 = a.tw[threadIdx.x], tw1 = a.tw[threadIdx.x + L];   // stored with z
   const int r1 = 2 * blockIdx.x, r2 = r1 + 1;
   const double* in = a.in + (size_t)col * a.in_ld;
   double* out = a.out + (size_t)col * a.out_ld;
-  fst_load<L>(z, m, [&](int j) {
-    return double2{in[(size_t)r1 * m + j], r2 < m ? in[(size_t)r2 * m + j] : 0.0};
-  });
+  fst_load<L>(
+      z, m,
+      [&](int j) {
+        return double2{in[(size_t)r1 * m + j], r2 < m ? in[(size_t)r2 * m + j] : 0.0};
+      },
+      [&] {
+        tw[threadIdx.x] = tw0;
+        tw[threadIdx.x + L] = tw1;
+      });
   fft_lds<L>(z, tw);
   const double sc = 0.5 * sqrt(2.0 / L);
   const int k = threadIdx.x + 1;   // frequency 1 .. m
@@ -534,25 +540,32 @@ __global__ __launch_bounds__(L) void fst_col_kernel(FstArgs a) {
   const int col = a.cols[blockIdx.y];
   if (a.st && !a.st[col].active) return;
   const int m = a.m;
-  for (int i = threadIdx.x; i < 2 * L; i += L) tw[i] = a.tw[i];
+  const double tw0 = a.tw[threadIdx.x], tw1 = a.tw[threadIdx.x + L];   // stored with z
   // a work-group reads 16 bytes of each row; the eight groups that share a
   // 128-byte line run on one XCD (consecutive block ids go round-robin over
   // the XCDs), so the line is fetched into one L2 instead of eight
   const int c1 = 2 * xcd_remap(blockIdx.x, gridDim.x), c2 = c1 + 1;
   const double* in = a.in + (size_t)col * a.in_ld;
   double* out = a.out + (size_t)col * a.out_ld;
-  fst_load<L>(z, m, [&](int j) {
-    return double2{in[(size_t)j * m + c1], c2 < m ? in[(size_t)j * m + c2] : 0.0};
-  });
+  const int t = threadIdx.x;
+  // eigenvalues of the divisor, loaded with the data (indices clamped to m - 1)
+  const double lr = a.lv[min(t, m - 1)], l1 = a.lv[c1], l2 = a.lv[min(c2, m - 1)];
+  fst_load<L>(
+      z, m,
+      [&](int j) {
+        return double2{in[(size_t)j * m + c1], c2 < m ? in[(size_t)j * m + c2] : 0.0};
+      },
+      [&] {
+        tw[threadIdx.x] = tw0;
+        tw[threadIdx.x + L] = tw1;
+      });
   fft_lds<L>(z, tw);
   const double sc = 0.5 * sqrt(2.0 / L);
-  const int t = threadIdx.x;
   if (t < m) {
     // frequency t + 1 along the rows; the columns already hold frequencies c1, c2
     const double2 Z = z[t + 1];
-    const double lr = a.lv[t];
-    const double d1 = a.mu * (lr + a.lv[c1]) + a.sw * (10.0 - lr - a.lv[c1]);
-    const double d2 = c2 < m ? a.mu * (lr + a.lv[c2]) + a.sw * (10.0 - lr - a.lv[c2]) : 1.0;
+    const double d1 = a.mu * (lr + l1) + a.sw * (10.0 - lr - l1);
+    const double d2 = c2 < m ? a.mu * (lr + l2) + a.sw * (10.0 - lr - l2) : 1.0;
     v[t] = double2{-Z.y * sc / d1, c2 < m ? Z.x * sc / d2 : 0.0};
   }
   __syncthreads();
