@@ -89,7 +89,7 @@ HIP_KERNELS = {
     "gram_reduce": ["gemm_tn_reduce", "gemm_tnw_reduce", "gemm_tn32_reduce"],
     "residual": ["residual_kernel"],
     "basis_update": ["gemm_nn_sub_kernel", "gemm_nn_sub4_kernel"],
-    "mg_up": ["mg_up_kernel", "mg3_post1_kernel", "mg3_post2_kernel"],
+    "mg_up": ["mg_up_kernel", "mg3_post_kernel", "mg3_post1_kernel", "mg3_post2_kernel"],
     "mg_down": ["mg_down_kernel", "mg3_pre_kernel"],
     "mg_restrict": ["mg3_restrict_kernel"],
     "mass_cheb": ["mass_cheb_kernel", "tensor_mass_kernel", "tensor_mass_x_kernel"],

@@ -10,6 +10,8 @@
 // accumulator element).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 
 #include "sts_internal.h"
@@ -556,34 +558,41 @@ __global__ __launch_bounds__(256) void gemm_nn_sub4_kernel(int64_t rows, int m, 
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
   if (r0 >= rows) return;
   const int64_t ra = r0 + 4 * i;
-  const bool full = ra + 3 < rows;
   const bool cok = i < n;
   d4 acc[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc[s] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < m; k0 += 4) {
-    const int kk = k0 + g;
-    const bool kok = kk < m;
-    const double* ap = A + ra + (int64_t)(kok ? kk : 0) * lda;
-    // loads without a branch (ap and the C index stay in bounds when the
-    // step is past m), so that they do not wait on each other
-    double a[4];
-    if (VEC && full) {
-      const double2 x = *(const double2*)ap;
-      const double2 y = *(const double2*)(ap + 2);
-      a[0] = kok ? x.x : 0.0;
-      a[1] = kok ? x.y : 0.0;
-      a[2] = kok ? y.x : 0.0;
-      a[3] = kok ? y.y : 0.0;
-    } else {
+  // Two copies of the k loop: 32-byte loads for waves whose 64 rows all
+  // exist, guarded scalar loads for the last one.  Every load is
+  // branch-free (ap and the C index stay in bounds past m), so a step's
+  // loads are in flight together.
+  auto k_loop = [&](auto wide) {
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      const int kk = k0 + g;
+      const bool kok = kk < m;
+      const double* ap = A + ra + (int64_t)(kok ? kk : 0) * lda;
+      const double c = C[(kok ? kk : 0) + (int64_t)(cok ? i : 0) * ldc];
+      double a[4];
+      if constexpr (decltype(wide)::value) {
+        const double2 x = *(const double2*)ap;
+        const double2 y = *(const double2*)(ap + 2);
+        a[0] = kok ? x.x : 0.0;
+        a[1] = kok ? x.y : 0.0;
+        a[2] = kok ? y.x : 0.0;
+        a[3] = kok ? y.y : 0.0;
+      } else {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) a[s] = (kok && ra + s < rows) ? ap[s] : 0.0;
+        for (int s = 0; s < 4; ++s) a[s] = (kok && ra + s < rows) ? ap[s] : 0.0;
+      }
+      const double b = (cok && kok) ? c : 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = mfma(a[s], b, acc[s]);
     }
-    const double c = C[(kok ? kk : 0) + (int64_t)(cok ? i : 0) * ldc];
-    const double b = (cok && kok) ? c : 0.0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] = mfma(a[s], b, acc[s]);
-  }
+  };
+  if (VEC && r0 + 63 < rows)
+    k_loop(std::true_type{});
+  else
+    k_loop(std::false_type{});
   if (cok) {
     // the old values of the lane's outputs, four in flight together (rows
     // past the end read row r0 and are not written back; four at a time
