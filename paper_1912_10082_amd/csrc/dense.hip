@@ -176,6 +176,8 @@ __global__ __launch_bounds__(256) void gemm_tn_reduce(int m, int n, int64_t nchu
   if (idx >= m * n) return;
   const int i = idx % m, j = idx / m;
   double s = 0.0;
+  // unrolled so that eight loads are in flight per trip (same summation order)
+#pragma unroll 8
   for (int64_t c = lane; c < nchunks; c += 64) s += partial[(c * m16 + i) * 16 + j];
   s = wave_sum(s);
   if (lane == 0) {
@@ -508,6 +510,8 @@ __global__ __launch_bounds__(256) void gemm_tnw_reduce(int m, int n, int64_t nch
   if (idx >= m * n) return;
   const int i = idx % m, j = idx / m;
   double s = 0.0;
+  // unrolled so that eight loads are in flight per trip (same summation order)
+#pragma unroll 8
   for (int64_t c = lane; c < nchunks; c += 64) s += partial[(c * m16 + i) * width + j];
   s = wave_sum(s);
   if (lane == 0) {
@@ -854,8 +858,14 @@ __global__ __launch_bounds__(64) void chol_deflate_kernel(int b, const double* G
   if (j < b)
     for (int i = 0; i < b; ++i) Rinv[i + j * b] = (j < kept && i <= j) ? X[i][j] : 0.0;
 }
-__global__ void apply_rinv_kernel(int64_t rows, int b, const CholInfo* info, const double* Rinv,
-                                  double* W, double* MW, int64_t ldw) {
+__global__ __launch_bounds__(256) void apply_rinv_kernel(int64_t rows, int b, const CholInfo* info,
+                                                         const double* Rinv, double* W, double* MW,
+                                                         int64_t ldw) {
+  // R^-1 (b <= 16) in LDS: every row uses all of it, and read from global
+  // memory inside the triangular loop below each product waited on a load
+  __shared__ double R[16 * 16];
+  if ((int)threadIdx.x < b * b) R[threadIdx.x] = Rinv[threadIdx.x];
+  __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   const int kept = info->kept;
@@ -868,7 +878,7 @@ __global__ void apply_rinv_kernel(int64_t rows, int b, const CholInfo* info, con
   for (int j = 0; j < kept; ++j) {
     double s = 0.0, t = 0.0;
     for (int i = 0; i <= j; ++i) {
-      const double q = Rinv[i + j * b];
+      const double q = R[i + j * b];
       s += w[i] * q;
       t += mw[i] * q;
     }
@@ -1146,6 +1156,7 @@ void chol_deflate(int b, const double* G, int64_t ldg, const double* norm0, doub
 void apply_rinv(int64_t rows, int b, const CholInfo* info, const double* Rinv, double* W,
                 double* MW, int64_t ldw, double* /*tmp*/, hipStream_t st) {
   if (rows <= 0 || b <= 0) return;
+  STS_REQUIRE(b <= 16, STS_E_INVALID, "apply_rinv: b > 16");
   apply_rinv_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(rows, b, info, Rinv, W, MW,
                                                                      ldw);
   STS_HIP(hipGetLastError());
