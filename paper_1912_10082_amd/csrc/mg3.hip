@@ -69,6 +69,13 @@ namespace {
 using namespace mgc;
 
 constexpr int kT = 256;
+// The pre- and post-smoothing launches run 512 threads on the 32 x 8 x 4
+// tile: their LDS tiles allow four work-groups per CU, and with 256 threads
+// that was 16 waves to hide the serial fill, smoothing and store phases of
+// each work-group (measured on the 255^3 grid: pre 223 -> 211 ms, post
+// 386 -> 367 ms per solve).
+constexpr int kPreT = 512;                             // threads of the pre-smoothing launch
+constexpr int kPostT = 512;                            // threads of the fused post-smoothing launch
 constexpr int TX = 32, TY = 8, TZ = 4;                 // fine tile
 constexpr int RX = TX + 2, RY = TY + 2, RZ = TZ + 2;   // with a one-node halo
 constexpr int NR = RX * RY * RZ;
@@ -211,10 +218,12 @@ struct Level3Args {
 // which keeps five work-groups per compute unit.  LDS arrays hold the storage
 // type S (b rounded to it in the mixed-precision V-cycle); every value is
 // widened to FP64 before it is used.
-template <bool SH, class B, class S>
-__global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
+template <bool SH, class B, class S, int NT>
+__global__ __launch_bounds__(NT) void mg3_pre_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
-  constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
+  constexpr int NU = (NR + NT - 1) / NT;                 // halo-1 nodes per thread
+  constexpr int NK = TX * TY * TZ / NT;                  // tile nodes per thread
+  static_assert(NK * NT == TX * TY * TZ, "whole tile nodes per thread");
   static_assert(NR <= BX * BY * BZ, "u_2 fits where b was");
   __shared__ S sh[BX * BY * BZ];
   STS_MG3_PROLOGUE(a)
@@ -222,7 +231,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   const int nf = a.nf;
   const B* bf = static_cast<const B*>(a.bf) + (size_t)col * a.ldf;
   {
-    Staged<BX * BY * BZ, S> hb;
+    StagedN<BX * BY * BZ, S, NT> hb;
     hb.load([&](int i) {
       const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
       const bool in = gx >= 0 && gx < nf && gy >= 0 && gy < nf && gz >= 0 && gz < nf;
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
   double u2r[NU];
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
-    const int i = threadIdx.x + k * kT;
+    const int i = threadIdx.x + k * NT;
     double u2 = 0.0;   // zero outside the domain (the Dirichlet values)
     if (i < NR) {
       const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
@@ -250,25 +259,25 @@ __global__ __launch_bounds__(kT) void mg3_pre_kernel(Level3Args a) {
     }
     u2r[k] = u2;
   }
-  double bc[NC];
+  double bc[NK];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    const int i = threadIdx.x + k * kT;
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + k * NT;
     const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
     bc[k] = sh[((lz + 2) * BY + ly + 2) * BX + lx + 2];
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
-    const int i = threadIdx.x + k * kT;
+    const int i = threadIdx.x + k * NT;
     if (i < NR) sh[i] = (S)u2r[k];
   }
   __syncthreads();
   S* xp = static_cast<S*>(a.xp) + (size_t)col * a.ldf;
   S* r = static_cast<S*>(a.d0) + (size_t)col * a.ldf;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    const int i = threadIdx.x + k * kT;
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + k * NT;
     const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
     const int gx = T.x0 + lx, gy = T.y0 + ly, gz = T.z0 + lz;
     if (gx < nf && gy < nf && gz < nf) {
@@ -343,15 +352,17 @@ __device__ __forceinline__ double interp3(const S* es, int ox, int oy, int oz, i
 // then u_1 on the one-node halo followed by d_0 on the tile (the values pass
 // through registers).  u_1 and d_0 are rounded to the storage type S, as
 // stored vectors would be.
-template <bool SH, class B, class S>
-__global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
+template <bool SH, class B, class S, int NT>
+__global__ __launch_bounds__(NT) void mg3_post_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // u with a two-node halo
   constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3, EZ = TZ / 2 + 3;
-  constexpr int NU = (NR + kT - 1) / kT;                 // halo-1 nodes per thread
+  constexpr int NU = (NR + NT - 1) / NT;                 // halo-1 nodes per thread
+  constexpr int NK = TX * TY * TZ / NT;                  // tile nodes per thread
+  static_assert(NK * NT == TX * TY * TZ, "whole tile nodes per thread");
   static_assert(NR + TX * TY * TZ <= BX * BY * BZ, "u_1 and d_0 fit where u was");
   __shared__ S sh[BX * BY * BZ];
   __shared__ S es[EX * EY * EZ];
-  __shared__ double red[kT / 64];
+  __shared__ double red[NT / 64];
   STS_MG3_PROLOGUE(a)
   const Tile3 T = tile_of(t, a.ntx, a.nty, TX, TY, TZ);
   const int nf = a.nf, nc = a.nc;
@@ -366,8 +377,8 @@ __global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
   };
   // every global read of the launch in flight before the first wait:
   // u_2 on the two-node halo, e_c, b on the one-node halo and on the tile
-  Staged<BX * BY * BZ, S> hx;
-  Staged<EX * EY * EZ, S> he;
+  StagedN<BX * BY * BZ, S, NT> hx;
+  StagedN<EX * EY * EZ, S, NT> he;
   hx.load([&](int i) {
     const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
     return ld_or_zero(xp, inside(gx, gy, gz), ((size_t)gz * nf + gy) * nf + gx);
@@ -377,19 +388,29 @@ __global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
     const bool in = I >= 0 && I < nc && J >= 0 && J < nc && K >= 0 && K < nc;
     return ld_or_zero(ec, in, ((size_t)K * nc + J) * nc + I);
   });
-  Staged<NR, B> hb;
+  StagedN<NR, B, NT> hb;
   hb.load([&](int i) { return halo_at(bf, nf, T, i); });
-  const Core C = core_nodes(nf, T);
-  B bv[NC];
+  size_t cg[NK];
+  int cq[NK];
+  bool cin[NK];
+  B bv[NK];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) bv[k] = bf[C.g[k]];
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + k * NT;
+    const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+    const int gx = T.x0 + lx, gy = T.y0 + ly, gz = T.z0 + lz;
+    cin[k] = gx < nf && gy < nf && gz < nf;
+    cg[k] = cin[k] ? ((size_t)gz * nf + gy) * nf + gx : 0;
+    cq[k] = ((lz + 1) * RY + ly + 1) * RX + lx + 1;
+    bv[k] = bf[cg[k]];
+  }
   hx.store(sh);
   he.store(es);
   __syncthreads();
   // u = u_2 + P e_c (each thread updates its own slots)
 #pragma unroll
-  for (int k = 0; k < Staged<BX * BY * BZ, S>::NI; ++k) {
-    const int i = threadIdx.x + k * kT;
+  for (int k = 0; k < StagedN<BX * BY * BZ, S, NT>::NI; ++k) {
+    const int i = threadIdx.x + k * NT;
     if (i < BX * BY * BZ) {
       const int gx = T.x0 - 2 + i % BX, gy = T.y0 - 2 + (i / BX) % BY, gz = T.z0 - 2 + i / (BX * BY);
       if (inside(gx, gy, gz))
@@ -402,7 +423,7 @@ __global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
   S u1r[NU], d0r[NU];
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
-    const int i = threadIdx.x + k * kT;
+    const int i = threadIdx.x + k * NT;
     S u1 = (S)0, d0 = (S)0;
     if (i < NR) {
       const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
@@ -420,7 +441,7 @@ __global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
   S* d0s = sh + NR;   // d_0 on the tile, x fastest
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
-    const int i = threadIdx.x + k * kT;
+    const int i = threadIdx.x + k * NT;
     if (i < NR) {
       sh[i] = u1r[k];
       const int lx = i % RX - 1, ly = (i / RX) % RY - 1, lz = i / (RX * RY) - 1;
@@ -433,18 +454,18 @@ __global__ __launch_bounds__(kT) void mg3_post_kernel(Level3Args a) {
   B* ef = static_cast<B*>(a.ef) + (size_t)col * a.ldf;
   double part = 0.0;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    if (!C.in[k]) continue;
-    const int q = C.q[k];
+  for (int k = 0; k < NK; ++k) {
+    if (!cin[k]) continue;
+    const int q = cq[k];
     const double b = bv[k];
-    const double d0 = d0s[threadIdx.x + k * kT];
+    const double d0 = d0s[threadIdx.x + k * NT];
     const double e =
         (double)sh[q] + (a.a1 * d0 + a.c1 * inv_d * (b - k7<SH, RX, RY>(sh, q, a.c, a.sm)));
-    ef[C.g[k]] = (B)e;
+    ef[cg[k]] = (B)e;
     part += b * (double)(B)e;   // (b, e) of the stored result
   }
   if (a.part) {
-    part = block_sum<kT>(part, red);
+    part = block_sum<NT>(part, red);
     if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
   }
 }
@@ -1127,9 +1148,11 @@ void level_down(Level3Args a, bool shifted, int nlaunch, hipStream_t st) {
   int blocks = a.ntx * a.nty * a.ntz * nlaunch;
   const double pre = (sb + 2.0 * ss) * nf * nlaunch;
   if (shifted)
-    launch(STS_K_MG_DOWN, pre, mg3_pre_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    launch(STS_K_MG_DOWN, pre, mg3_pre_kernel<true, B, S, kPreT>, dim3(blocks), dim3(kPreT), 0, st,
+           a);
   else
-    launch(STS_K_MG_DOWN, pre, mg3_pre_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+    launch(STS_K_MG_DOWN, pre, mg3_pre_kernel<false, B, S, kPreT>, dim3(blocks), dim3(kPreT), 0, st,
+           a);
   STS_HIP(hipGetLastError());
   a.ntx = (a.nc + CX - 1) / CX;
   a.nty = (a.nc + CY - 1) / CY;
@@ -1151,9 +1174,11 @@ void level_up(Level3Args a, bool shifted, int nlaunch, hipStream_t st) {
   if constexpr (sizeof(S) == 8) {
     const double post = ((2.0 * sb + ss) * nf + ss * nc) * nlaunch;
     if (shifted)
-      launch(STS_K_MG_UP, post, mg3_post_kernel<true, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+      launch(STS_K_MG_UP, post, mg3_post_kernel<true, B, S, kPostT>, dim3(blocks), dim3(kPostT), 0,
+             st, a);
     else
-      launch(STS_K_MG_UP, post, mg3_post_kernel<false, B, S>, dim3(blocks), dim3(kT), 0, st, a);
+      launch(STS_K_MG_UP, post, mg3_post_kernel<false, B, S, kPostT>, dim3(blocks), dim3(kPostT), 0,
+             st, a);
     STS_HIP(hipGetLastError());
   } else {
     const double post1 = ((sb + 3.0 * ss) * nf + ss * nc) * nlaunch;
