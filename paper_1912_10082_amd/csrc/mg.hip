@@ -50,7 +50,11 @@ namespace {
 
 using namespace mgc;
 
-constexpr int kT = 256;          // threads per work-group of the level and PCG kernels
+constexpr int kT = 256;          // threads per work-group of the PCG kernels
+// Threads per work-group of the level (smoothing) kernels: their LDS regions
+// allow three work-groups per CU, and 512 threads double the waves that hide
+// each work-group's serial smoothing steps.
+constexpr int kLT = 512;
 constexpr int CX = 32, CY = 8;   // coarse nodes per level-kernel tile (fine footprint 64 x 16)
 constexpr int TX = 64, TY = 16;  // fine nodes per PCG-kernel tile
 constexpr int kNu = kMGNu;       // smoothing steps
@@ -114,7 +118,7 @@ template <bool SH, int W, int H>
 __device__ __forceinline__ void cheb_step(const Region<W, H>& R, int shrink, double ak, double ck,
                                           double inv_d, const double* bs, const double* u,
                                           double* un, double* ds, const Op& op) {
-  for (int i = threadIdx.x; i < W * H; i += kT) {
+  for (int i = threadIdx.x; i < W * H; i += kLT) {
     if (R.inside(i, shrink)) {
       const double d = ak * ds[i] + ck * inv_d * (bs[i] - aop<SH>(u, i, W, op));
       ds[i] = d;
@@ -130,7 +134,7 @@ template <bool SH, int W, int H>
 __device__ __forceinline__ int presmooth(const Region<W, H>& R, const Smooth& sm, double inv_d,
                                          const double* bs, double (*us)[W * H], double* ds,
                                          const Op& op) {
-  for (int i = threadIdx.x; i < W * H; i += kT) {
+  for (int i = threadIdx.x; i < W * H; i += kLT) {
     const double v = R.inside(i, 0) ? sm.c[0] * inv_d * bs[i] : 0.0;
     ds[i] = v;
     us[0][i] = v;
@@ -168,7 +172,7 @@ struct LevelArgs {
 // coarse nodes.  Fine region [2 cx0 - kNu, 2 cx0 + 2 CX + kNu] per direction.
 // ---------------------------------------------------------------------------
 template <bool SH>
-__global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
+__global__ __launch_bounds__(kLT) void mg_down_kernel(LevelArgs a) {
   constexpr int W = 2 * CX + 1 + 2 * kNu, H = 2 * CY + 1 + 2 * kNu;
   __shared__ double bs[W * H];
   __shared__ double us[2][W * H];
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
   const double inv_d = 1.0 / op_diag<SH>(op);
   const double* bf = a.bf + (size_t)col * a.ldf;
   {
-    StagedN<W * H, double, kT> hb;
+    StagedN<W * H, double, kLT> hb;
     hb.load([&](int i) {
       const int gx = R.ox + i % W, gy = R.oy + i / W;
       return ld_or_zero(bf, gx >= 0 && gx < nf && gy >= 0 && gy < nf, (size_t)gy * nf + gx);
@@ -199,20 +203,20 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
     const int y1 = (cy0 + CY >= nc) ? nf : 2 * (cy0 + CY);
     const int ow = x1 - 2 * cx0, oh = y1 - 2 * cy0;
     double* xpg = a.xp + (size_t)col * a.ldf;
-    for (int i = threadIdx.x; i < ow * oh; i += kT) {
+    for (int i = threadIdx.x; i < ow * oh; i += kLT) {
       const int gx = 2 * cx0 + i % ow, gy = 2 * cy0 + i / ow;
       xpg[(size_t)gy * nf + gx] = us[cur][(gy - R.oy) * W + (gx - R.ox)];
     }
   }
   // residual on shrink kNu into ds
-  for (int i = threadIdx.x; i < W * H; i += kT) {
+  for (int i = threadIdx.x; i < W * H; i += kLT) {
     const int lx = i % W, ly = i / W;
     if (lx >= kNu && lx < W - kNu && ly >= kNu && ly < H - kNu)
       ds[i] = bs[i] - aop<SH>(us[cur], i, W, op);
   }
   __syncthreads();
   double* bc = a.bc + (size_t)col * a.ldc;
-  for (int i = threadIdx.x; i < CX * CY; i += kT) {
+  for (int i = threadIdx.x; i < CX * CY; i += kLT) {
     const int I = cx0 + i % CX, J = cy0 + i / CX;
     if (I < nc && J < nc) {
       const int q = (2 * (J - cy0) + 1 + kNu) * W + (2 * (I - cx0) + 1 + kNu);
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(kT) void mg_down_kernel(LevelArgs a) {
 // nf).  Fine region [2 cx0 - (2 kNu - 1), ...), coarse [cx0 - kNu, ...).
 // ---------------------------------------------------------------------------
 template <bool SH>
-__global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
+__global__ __launch_bounds__(kLT) void mg_up_kernel(LevelArgs a) {
   constexpr int HL = kNu;   // halo of the kNu post-smoothing steps
   constexpr int W = 2 * CX + 1 + 2 * HL, H = 2 * CY + 1 + 2 * HL;
   constexpr int EW = CX + 2 * kNu, EH = CY + 2 * kNu;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   __shared__ double us[2][W * H];
   __shared__ double ds[W * H];
   __shared__ double es[EW * EH];
-  __shared__ double red[kT / 64];
+  __shared__ double red[kLT / 64];
   const int ntiles = a.ntx * a.nty;
   const int lin = xcd_remap(blockIdx.x, a.nlaunch * ntiles);
   const int t = lin / a.nlaunch, col = a.cols[lin % a.nlaunch];
@@ -255,8 +259,8 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   // domain in both buffers: the Dirichlet values the stencil reads)
   // (all of a thread's loads in flight before the first LDS store)
   {
-    StagedN<W * H, double, kT> hb, hu;
-    StagedN<EW * EH, double, kT> he;
+    StagedN<W * H, double, kLT> hb, hu;
+    StagedN<EW * EH, double, kLT> he;
     auto at = [&](const double* g, int i) {
       const int gx = R.ox + i % W, gy = R.oy + i / W;
       return ld_or_zero(g, gx >= 0 && gx < nf && gy >= 0 && gy < nf, (size_t)gy * nf + gx);
@@ -270,13 +274,13 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
     hb.store(bs);
     hu.store(us[0]);
     he.store(es);
-    for (int i = threadIdx.x; i < W * H; i += kT) {
+    for (int i = threadIdx.x; i < W * H; i += kLT) {
       us[1][i] = 0.0;
       ds[i] = 0.0;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < W * H; i += kT) {
+  for (int i = threadIdx.x; i < W * H; i += kLT) {
     if (R.inside(i, 0)) {
       const int gx = R.ox + i % W, gy = R.oy + i / W;
       us[0][i] += interp(es, EW, cox, coy, gx, gy);
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
   const double* u = us[cur];
   double* ef = a.ef + (size_t)col * a.ldf;
   double part = 0.0;
-  for (int i = threadIdx.x; i < ow * oh; i += kT) {
+  for (int i = threadIdx.x; i < ow * oh; i += kLT) {
     const int gx = 2 * cx0 + i % ow, gy = 2 * cy0 + i / ow;
     const int q = (gy - R.oy) * W + (gx - R.ox);
     const double d = ak * ds[q] + ck * inv_d * (bs[q] - aop<SH>(u, q, W, op));
@@ -306,7 +310,7 @@ __global__ __launch_bounds__(kT) void mg_up_kernel(LevelArgs a) {
     part += bs[q] * e;
   }
   if (a.part) {
-    part = block_sum<kT>(part, red);
+    part = block_sum<kLT>(part, red);
     if (threadIdx.x == 0) a.part[(size_t)col * a.max_tiles + t] = part;
   }
 }
@@ -908,10 +912,10 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.sm = sm;
     const double by = 8.0 * (2.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch;
     if (sh)
-      launch(STS_K_MG_DOWN, by, mg_down_kernel<true>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0,
+      launch(STS_K_MG_DOWN, by, mg_down_kernel<true>, dim3(a.ntx * a.nty * nlaunch), dim3(kLT), 0,
              st, a);
     else
-      launch(STS_K_MG_DOWN, by, mg_down_kernel<false>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0,
+      launch(STS_K_MG_DOWN, by, mg_down_kernel<false>, dim3(a.ntx * a.nty * nlaunch), dim3(kLT), 0,
              st, a);
     STS_HIP(hipGetLastError());
   }
@@ -1016,10 +1020,10 @@ void mg_vcycle(const MGWork& w, const CGScal* act, const int* cols, int nlaunch,
     a.max_tiles = w.max_tiles;
     const double by = 8.0 * (3.0 * a.nf * a.nf + (double)a.nc * a.nc) * nlaunch;
     if (sh)
-      launch(STS_K_MG_UP, by, mg_up_kernel<true>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st,
+      launch(STS_K_MG_UP, by, mg_up_kernel<true>, dim3(a.ntx * a.nty * nlaunch), dim3(kLT), 0, st,
              a);
     else
-      launch(STS_K_MG_UP, by, mg_up_kernel<false>, dim3(a.ntx * a.nty * nlaunch), dim3(kT), 0, st,
+      launch(STS_K_MG_UP, by, mg_up_kernel<false>, dim3(a.ntx * a.nty * nlaunch), dim3(kLT), 0, st,
              a);
     STS_HIP(hipGetLastError());
   }
