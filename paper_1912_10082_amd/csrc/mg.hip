@@ -52,8 +52,8 @@ using namespace mgc;
 
 constexpr int kT = 256;          // threads per work-group of the PCG kernels
 // Threads per work-group of the level (smoothing) kernels: their LDS regions
-// allow three work-groups per CU, and 512 threads double the waves that hide
-// each work-group's serial smoothing steps.
+// allow two (up) or three (down) work-groups per CU, and 512 threads double
+// the waves that hide each work-group's serial smoothing steps.
 constexpr int kLT = 512;
 constexpr int CX = 32, CY = 8;   // coarse nodes per level-kernel tile (fine footprint 64 x 16)
 constexpr int TX = 64, TY = 16;  // fine nodes per PCG-kernel tile

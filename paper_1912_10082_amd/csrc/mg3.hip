@@ -70,10 +70,10 @@ using namespace mgc;
 
 constexpr int kT = 256;
 // The pre- and post-smoothing launches run 512 threads on the 32 x 8 x 4
-// tile: their LDS tiles allow four work-groups per CU, and with 256 threads
-// that was 16 waves to hide the serial fill, smoothing and store phases of
-// each work-group (measured on the 255^3 grid: pre 223 -> 211 ms, post
-// 386 -> 367 ms per solve).
+// tile: their FP64 LDS tiles allow five (pre) or four (post) work-groups per
+// CU, and with 256 threads that was 20 or 16 waves to hide the serial fill,
+// smoothing and store phases of each work-group (measured on the 255^3 grid:
+// pre 223 -> 211 ms, post 386 -> 367 ms per solve).
 constexpr int kPreT = 512;                             // threads of the pre-smoothing launch
 constexpr int kPostT = 512;                            // threads of the fused post-smoothing launch
 constexpr int TX = 32, TY = 8, TZ = 4;                 // fine tile
@@ -215,9 +215,9 @@ struct Level3Args {
 // on the tile and a one-node halo (from b on a two-node halo), then the
 // residual r = b - K u_2 on the tile.  Stores u_2 (for post) and r.  One LDS
 // array holds b first and u_2 after it (the values pass through registers),
-// which keeps five work-groups per compute unit.  LDS arrays hold the storage
-// type S (b rounded to it in the mixed-precision V-cycle); every value is
-// widened to FP64 before it is used.
+// so the launch needs one b tile of LDS (27 KB in FP64).  LDS arrays hold
+// the storage type S (b rounded to it in the mixed-precision V-cycle); every
+// value is widened to FP64 before it is used.
 template <bool SH, class B, class S, int NT>
 __global__ __launch_bounds__(NT) void mg3_pre_kernel(Level3Args a) {
   constexpr int BX = TX + 4, BY = TY + 4, BZ = TZ + 4;   // b with a two-node halo
