@@ -41,3 +41,20 @@ def test_kernel_sources_name_the_defining_file_and_headers():
     src = bench._kernel_sources("mg3_pre_kernel")
     assert "mg3.hip" in src and "sts_internal.h" in src and "include/sts.h" in src
     assert "dense.hip" not in src
+
+
+def test_profiler_ids_name_kernels_that_exist():
+    """Every HIP kernel bench.py maps to a profiler id is defined in the
+    library sources, so a renamed kernel cannot silently drop its traffic
+    and time from the report."""
+    import re
+    defined = set()
+    for fn in os.listdir(bench.CSRC):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(bench.CSRC, fn)) as fh:
+                text = fh.read()
+            defined |= set(re.findall(
+                r"__global__\s+(?:__launch_bounds__\([^)]*\)\s+)?void\s+(\w+)\s*\(", text))
+    assert "gemm_nn_sub4_kernel" in defined and "mg3_post_kernel" in defined
+    missing = {pid: [k for k in ks if k not in defined] for pid, ks in bench.HIP_KERNELS.items()}
+    assert not any(missing.values()), missing
