@@ -570,7 +570,7 @@ def main() -> int:
     if args.gpus == 1 and args.workload == "serve":
         return bench_serve(args)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "the solver has no multi-GPU path", file=sys.stderr)
         return 2
 
